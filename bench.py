@@ -1,0 +1,222 @@
+"""Benchmark of the counter-guided search sweep on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu-baseline]
+
+Workload: the 12-parameter tuning space (value-set sizes 8,4,2,8,4,2,8,4,2,4,
+4,4: 16,777,216 raw configurations, 6 constraints keep 4,813,824), a forest of
+16 depth-12 trees predicting 24 counters per configuration, and 100
+sequential search steps.  Each step profiles the previous pick: seeded
+synthetic Table 1 counters go through the expert system to the counter
+changes, every unexplored configuration is scored and weighted, and one
+configuration is drawn (Alg. 1 with one draw per scoring pass).
+
+Timed region (after warm-up): one full model evaluation (forest -> predicted
+counters of every valid configuration), the uniform starting draw, and K
+scored steps, each synchronised on its pick.  value = configurations scored
+in the K steps / wall time of the region.  The picks of the timed run are
+compared with the oracle's stored trajectory of the same inputs.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CORES_PROFILED = 1920.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload_inputs(n_steps: int):
+    import synth
+    g = synth.rng(2, 3)
+    U = synth.uniforms_u64(g, n_steps + 1)
+    pcs = synth.profiler_counters(synth.rng(2, 4), n_steps)
+    thr = synth.threads_launched(synth.rng(2, 5), n_steps)
+    return U, pcs, thr
+
+
+def run_search(cgs, sp, model, U, pcs, thr, n_steps, timing):
+    """Uniform start + n_steps scored steps; returns (picks, session)."""
+    params = cgs.cgs_default_params()
+    params.timing = 1 if timing else 0
+    sess = cgs.Session(sp, params)
+    picks = []
+    sess.search_step(model, cgs.NO_PROFILE)
+    raw, l = sess.sample_next(int(U[0]))
+    picks.append(l)
+    for i in range(n_steps):
+        ep = cgs.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=CORES_PROFILED,
+                                   threads=float(thr[i]))
+        sess.search_step(model, raw, measured=pcs[i], expert=ep)
+        raw, l = sess.sample_next(int(U[i + 1]))
+        picks.append(l)
+    return picks, sess
+
+
+def cpu_baseline(spec, forest, n_steps):
+    """The oracle, untouched, on a bounded sample of the workload: the
+    configurations with raw index below 2^21 (1/8 of the raw space).  Its
+    rate for the same job: sample x K / (model evaluation + K x one step)."""
+    from oracle import expert as E
+    from oracle import search as SR
+    from oracle import space as SP
+    t0 = time.perf_counter()
+    mask = SP.valid_mask(spec.radix, spec.values, spec.constraints, chunk=1 << 21)
+    sample = np.flatnonzero(mask[: 1 << 21]).astype(np.uint32)
+    del mask
+    t1 = time.perf_counter()
+    prep = SR.prepare(spec, forest, valid=sample)
+    t2 = time.perf_counter()
+    U, pcs, thr = workload_inputs(2)
+    _, _, d32, _ = E.expert_system(pcs[0], False, CORES_PROFILED, float(thr[0]), 0.7)
+    explored = np.zeros(len(sample), dtype=bool)
+    SR.step(prep, explored, 0, d32, [int(U[1])])
+    t3 = time.perf_counter()
+    t_eval, t_step = t2 - t1, t3 - t2
+    rate = len(sample) * n_steps / (t_eval + n_steps * t_step)
+    return {
+        "value": rate, "unit": "configs/s", "cores": 1, "kind": "oracle",
+        "sample": (f"raw indices < 2^21 of the same space ({len(sample)} valid configs): oracle "
+                   f"model evaluation {t_eval:.2f} s once + one scored step {t_step:.2f} s, "
+                   f"scaled to {n_steps} steps; NumPy float64/float32, single thread "
+                   f"(enumeration {t1 - t0:.2f} s not counted)"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the sweep runs on a single MI355X "
+              "(multi-GPU sharding is design-only); run with --gpus 1", file=sys.stderr)
+        return 2
+    K, W = args.steps, args.warmup
+    if K < 1:
+        print("--steps must be >= 1", file=sys.stderr)
+        return 2
+
+    import synth
+    from paper_2102_05297_amd import cgs   # fails loudly without the HIP library
+
+    spec = synth.space_c2()
+    forest = synth.forest_c2(spec)
+    t0 = time.perf_counter()
+    sp = cgs.Space.from_spec(spec)
+    t_enum = time.perf_counter() - t0
+    model = cgs.ForestModel.from_spec(sp, forest)
+    log(f"space: {sp.n_raw} raw, {sp.n_valid} valid (create {t_enum * 1e3:.1f} ms); "
+        f"forest eval {model.eval_ms():.3f} ms")
+    U, pcs, thr = workload_inputs(max(K, W))
+
+    # counters entering each step's score (for the algorithmic byte count)
+    n_active = []
+    for i in range(K):
+        ep = cgs.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=CORES_PROFILED,
+                                   threads=float(thr[i]))
+        _, d, _ = cgs.cgs_expert_system(pcs[i], ep)
+        n_active.append(int((d.astype(np.float32) != 0).sum()))
+
+    if W > 0:
+        run_search(cgs, sp, model, U, pcs, thr, W, timing=False)
+        sp.synchronize()
+        log(f"warmup: {W} steps done")
+
+    sp.synchronize()
+    t_start = time.perf_counter()
+    model.refresh()                       # model evaluation inside the timed region
+    picks, sess = run_search(cgs, sp, model, U, pcs, thr, K, timing=True)
+    sp.synchronize()
+    t_total = time.perf_counter() - t_start
+    log(f"timed: {K} steps in {t_total * 1e3:.2f} ms")
+
+    n_valid = sp.n_valid
+    # step i (1-based) scores every valid configuration except the profile
+    # and the i picks so far: n_valid - i
+    scored = sum(n_valid - i for i in range(1, K + 1))
+    value = scored / t_total
+
+    ms, launches = sess.kernel_times()
+    # score pass: reads the rows of P of the active counters, writes s, reads
+    # the explored bits; launch 0 is the uniform start (no active counter)
+    bytes_score = n_valid * (4 + 0.125) * (K + 1) + n_valid * 4.0 * sum(n_active)
+    score_s = ms[0] / 1e3
+    achieved = bytes_score / score_s / 1e9 if score_s > 0 else 0.0
+
+    # oracle-exact picks: stored oracle trajectory for the same inputs
+    golden_path = os.path.join(ROOT, "tests", "golden", "c2_search.json")
+    exact = None
+    if os.path.exists(golden_path):
+        ref = json.load(open(golden_path))["steps"]
+        n_chk = min(len(ref), len(picks))
+        exact = {"checked": n_chk,
+                 "equal": int(sum(ref[i]["pick"] == picks[i] for i in range(n_chk)))}
+        log(f"picks equal to the oracle trajectory: {exact['equal']}/{exact['checked']}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample) ...")
+        cpu = cpu_baseline(spec, forest, K)
+
+    out = {
+        "metric": "configs scored/sec per search step (tree vs MLP surrogate) at oracle-exact pick",
+        "value": value,
+        "unit": "configs/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": t_total * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("12-param space, 16,777,216 raw / %d valid configs, forest 16 trees depth 12, "
+                         "24 counters, %d sequential steps, 1 draw per step, tree model" % (n_valid, K)),
+            "n_raw": sp.n_raw, "n_valid": n_valid, "trees": 16, "depth": 12, "counters": 24,
+            "model": "forest (predictions evaluated once per timed run, inside the timed region)",
+        },
+        "roofline": {
+            "kernel": "score_pass",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "launches": int(launches[0]),
+            "avg_us": ms[0] / max(1, launches[0]) * 1e3,
+        },
+        "kernel_avg_us": {
+            "score_pass": ms[0] / max(1, launches[0]) * 1e3,
+            "weight_draw": ms[1] / max(1, launches[1]) * 1e3,
+        },
+        "model_eval_ms": model.eval_ms(),
+        "space_create_ms": t_enum * 1e3,
+        "mean_active_counters": float(np.mean(n_active)),
+        "oracle_exact_picks": exact,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

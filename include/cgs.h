@@ -1,0 +1,269 @@
+/*
+ * cgs.h - counter-guided search sweep on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the data-parallel hot path of the profile-based autotuning
+ * searcher of Filipovic et al., "Using hardware performance counters to
+ * speed up autotuning convergence on GPUs":
+ *
+ *   space    the tuning space: cross product of per-parameter value sets,
+ *            pruned by a-priori constraints (Sect. 1; the array TS of Alg. 1)
+ *   model    a problem-specific model predicting each configuration's
+ *            counter vector (Sect. 3.4: decision tree; here also a forest and
+ *            a multilayer-perceptron surrogate)
+ *   session  the state of one search: explored configurations, scores,
+ *            weights (Sect. 3.6 and Alg. 1)
+ *   step     score every unexplored configuration against the profiled one
+ *            (Sect. 3.6, score and score-normalisation equations)
+ *   sample   draw the next configuration with probability proportional to
+ *            its normalised score, then zero that score (Sect. 3.7, Alg. 1)
+ *
+ * Conventions, for every entry point:
+ *   - Pointers named *_host are caller-owned host arrays, read (or written)
+ *     before the call returns; the library keeps no reference to them.
+ *   - Handles own their device memory (hipMalloc on the current device) and
+ *     free it in *_destroy.  *_destroy accepts NULL.  Models and sessions
+ *     hold a reference to their space, so handles may be destroyed in any
+ *     order.
+ *   - Work runs on the HIP stream given at space creation (NULL: the library
+ *     creates one, default priority).  Every handle derived from a space uses
+ *     that stream.  Calls that return device results to the host
+ *     synchronise that stream; others only enqueue.
+ *   - A handle is not thread-safe: one host thread at a time.
+ *   - No C++ exception crosses this ABI.  A non-zero status comes with a
+ *     message from cgs_last_error() (thread-local, valid until the next call
+ *     on that thread).
+ *   - Configurations are named by their raw index k in the mixed-radix
+ *     numbering of the cross product, parameter 0 most significant, or by
+ *     their valid index l: the position of k in the ascending list of valid
+ *     raw indices.
+ */
+#ifndef CGS_H
+#define CGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cgs_space_s *cgs_space;
+typedef struct cgs_model_s *cgs_model;
+typedef struct cgs_session_s *cgs_session;
+
+typedef enum {
+  CGS_OK = 0,
+  CGS_EINVAL = -1,  /* malformed argument                                 */
+  CGS_ENOMEM = -2,  /* device or host allocation failed                   */
+  CGS_EDEVICE = -3, /* HIP runtime error (message names the call)         */
+  CGS_EEMPTY = -4,  /* no unexplored valid configuration is left          */
+  CGS_ESTATE = -5,  /* call out of order (e.g. sample before any step)    */
+  CGS_ERANGE = -6   /* a size exceeds a documented limit                  */
+} cgs_status;
+
+/* Limits (CGS_ERANGE beyond them). */
+#define CGS_MAX_PARAMS 32           /* tuning parameters per space             */
+#define CGS_MAX_RADIX 16            /* values per parameter                    */
+#define CGS_MAX_ABS_VALUE (1 << 20) /* |parameter value| must stay below this  */
+#define CGS_MAX_CONSTRAINTS 32
+#define CGS_MAX_COUNTERS 64         /* counters per model                      */
+#define CGS_MAX_TREES 64
+#define CGS_MAX_DEPTH 14
+/* raw space size: at most 2^32 - 1 configurations */
+
+/* Constraint kinds, over parameter values v[] of one configuration.
+ * A divisibility test by a zero value fails. */
+enum {
+  CGS_DIV = 0,      /* v[a] % v[b] == 0          */
+  CGS_DIV2 = 1,     /* v[a] % (v[b] * v[c]) == 0 */
+  CGS_PROD_LE = 2,  /* v[a] * v[b] <= bound      */
+  CGS_PROD3_LE = 3, /* v[a] * v[b] * v[c] <= bound */
+  CGS_PROD_GE = 4,  /* v[a] * v[b] >= bound      */
+  CGS_LE = 5        /* v[a] <= v[b]              */
+};
+
+typedef struct {
+  int32_t kind;  /* CGS_DIV ... CGS_LE                     */
+  int32_t a, b, c; /* parameter indices (unused ones: 0)  */
+  int64_t bound;
+} cgs_constraint;
+
+/* Search constants; cgs_default_params() gives the paper's values
+ * (Sect. 3.6: cut-off gamma = -0.25, weights in [1e-4, 256]). */
+typedef struct {
+  float gamma;       /* scores <= gamma get weight w_min                    */
+  float w_min;       /* smallest weight of an unexplored configuration      */
+  int32_t block_log2; /* configurations per weight block = 2^block_log2,
+                          12..20; 0 = automatic                              */
+  int32_t timing;     /* non-zero: time every kernel of every step with HIP
+                         events (cgs_session_kernel_times)                  */
+} cgs_params;
+
+/* Expert-system settings (Sect. 3.5). */
+typedef struct {
+  double inst_reaction; /* 0.7, or 0.5 for problems known to be compute-bound */
+  int32_t volta;        /* counters from a Volta-or-newer GPU: L2_U is a
+                           percentage and issue utilisation saturates at 50  */
+  int32_t reserved;
+  double cores;         /* CUDA cores of the profiled GPU                     */
+  double threads;       /* threads of the profiled launch                     */
+} cgs_expert_params;
+
+/* Results of the last search step.  Filled by cgs_session_step_info(). */
+typedef struct {
+  uint64_t n_unexplored; /* valid configurations not yet explored          */
+  uint64_t total_weight; /* Q: sum of quantised weights at the last draw   */
+  float s_min, s_max;    /* extreme scores over unexplored configurations */
+  float device_ms;       /* device time of the step's kernels (hipEvents) */
+  int32_t n_active;      /* counters that entered the score               */
+} cgs_step_info;
+
+/* ---------------------------------------------------------------- misc */
+const char *cgs_last_error(void);
+int cgs_version(void);
+void cgs_default_params(cgs_params *out);
+void cgs_default_expert_params(cgs_expert_params *out);
+/* Wait for all work enqueued on the space's stream. */
+cgs_status cgs_synchronize(cgs_space space);
+
+/* ------------------------------------------------------------- space */
+/* Enumerate the tuning space (Sect. 1; TS of Alg. 1): decode every raw index
+ * k < prod(radix) to digits, look the digits up in the value tables,
+ * evaluate every constraint, and keep the valid ones in ascending k.
+ *   radix[n_params]   values per parameter, 1..CGS_MAX_RADIX
+ *   values[sum radix] value tables, concatenated in parameter order, each
+ *                     strictly ascending, |v| < CGS_MAX_ABS_VALUE
+ *   cons[n_cons]      constraints (may be NULL when n_cons == 0)
+ *   hip_stream        hipStream_t to use, or NULL
+ * Synchronises once (to size the valid list).  An empty valid set is not an
+ * error (n_valid = 0; every later step reports CGS_EEMPTY). */
+cgs_status cgs_space_create(int n_params, const int32_t *radix, const int64_t *values,
+                            int n_cons, const cgs_constraint *cons, void *hip_stream,
+                            cgs_space *out);
+cgs_status cgs_space_info(cgs_space space, uint64_t *n_raw, uint64_t *n_valid);
+/* Digits of raw index k (host arithmetic).  digits_host[n_params]. */
+cgs_status cgs_space_decode(cgs_space space, uint64_t raw_index, int32_t *digits_host);
+/* Valid index of raw index k, or -1 when k is not a valid configuration. */
+cgs_status cgs_space_valid_index(cgs_space space, uint64_t raw_index, int64_t *valid_index);
+/* Copy valid raw indices [first, first+count) (uint32, ascending). */
+cgs_status cgs_space_copy_valid(cgs_space space, uint64_t first, uint64_t count,
+                                uint32_t *dst_host);
+/* Copy the validity bitmask: bit (k % 32) of word k / 32 is set when raw
+ * index k is valid; ceil(n_raw / 32) words. */
+cgs_status cgs_space_copy_mask(cgs_space space, uint32_t *dst_host, uint64_t n_words);
+void cgs_space_destroy(cgs_space space);
+
+/* ------------------------------------------------------------- model */
+/* Load a regression forest and predict every valid configuration
+ * (Sect. 3.4.2).  Trees are complete binary trees of depth `depth` in heap
+ * order (children of node i: 2i+1, 2i+2); internal node i of tree t goes left
+ * when digit[feat[t][i]] <= thr[t][i].  The prediction is the mean of the
+ * trees' leaf vectors: sum over t ascending in float32, then one division by
+ * n_trees.
+ *   feat, thr [n_trees][2^depth - 1]   uint8
+ *   leaves    [n_trees][2^depth][n_counters]  float32
+ * The predictions of all valid configurations are kept on the device
+ * (n_counters * n_valid floats) and reused by every search step. */
+cgs_status cgs_model_load_forest(cgs_space space, int n_trees, int depth, int n_counters,
+                                 const uint8_t *feat, const uint8_t *thr, const float *leaves,
+                                 cgs_model *out);
+/* n_counters and the device time of the last full model evaluation. */
+cgs_status cgs_model_info(cgs_model model, int *n_counters, float *eval_ms);
+/* Re-run the full-space model evaluation (same result; for timing). */
+cgs_status cgs_model_refresh(cgs_model model);
+/* Predictions of valid configurations [first, first+count): dst[count][C]. */
+cgs_status cgs_model_copy_predictions(cgs_model model, uint64_t first, uint64_t count,
+                                      float *dst_host);
+/* Forest only: leaf reached in each tree by valid configurations
+ * [first, first+count): dst[n_trees][count] uint16. */
+cgs_status cgs_model_copy_leaf_ids(cgs_model model, uint64_t first, uint64_t count,
+                                   uint16_t *dst_host);
+void cgs_model_destroy(cgs_model model);
+
+/* ----------------------------------------------------------- session */
+/* profile_raw value meaning "nothing profiled yet": the step gives every
+ * unexplored configuration score 0 (weight 1), so the next draw is the
+ * uniform random start of Alg. 1. */
+#define CGS_NO_PROFILE UINT64_MAX
+
+/* A search over `space` with nothing explored.  params: NULL = defaults. */
+cgs_status cgs_session_create(cgs_space space, const cgs_params *params, cgs_session *out);
+
+/* One scoring pass of Alg. 1 (Sect. 3.6): mark the profiled configuration
+ * explored, score every unexplored valid configuration c against it with
+ *   s(c) = sum_{p: dpc_p != 0, a_p != 0, x_p != 0} dpc_p (x_p - a_p) / (a_p + x_p)
+ * (x = model prediction of c, a = model prediction of the profiled
+ * configuration; float32, counters ascending, every operation rounded), find
+ * s_min / s_max over unexplored configurations, normalise
+ *   s > 0: (1 + s/s_max)^8;  gamma < s <= 0: max(w_min, (1 - s/s_min)^8)
+ *   (1 when s == 0);  s <= gamma: w_min;  explored: 0
+ * and quantise to integer weights q = rint(w * 2^23).
+ *   profile_raw   raw index of the profiled configuration (must be valid),
+ *                 or CGS_NO_PROFILE (delta and measured are then ignored)
+ *   delta_host    [n_counters] required counter changes in [-1, 1], or NULL
+ *   measured_host [24] Table 1 counters of the profiled run, used when
+ *                 delta_host is NULL: the expert system derives the changes
+ *                 (cgs_expert_system); the model must have 24 counters
+ *   expert        NULL = defaults
+ * Records the step; its kernels are enqueued together with its first draw
+ * (cgs_sample_next), or when one of its results is read.  Recording a new
+ * step before drawing from the previous one still executes the previous one
+ * (its profile is marked explored). */
+cgs_status cgs_search_step(cgs_session session, cgs_model model, uint64_t profile_raw,
+                           const float *delta_host, const double *measured_host,
+                           const cgs_expert_params *expert);
+
+/* Draw one configuration (Alg. 1): r = floor(u64 * Q / 2^64) with Q the sum
+ * of weights; pick l with sum_{i<l} q_i <= r < sum_{i<=l} q_i (valid-index
+ * order); mark it explored and zero its weight for further draws of this
+ * step.  Synchronises.  CGS_EEMPTY when Q == 0.
+ *   raw_out / valid_out may be NULL. */
+cgs_status cgs_sample_next(cgs_session session, uint64_t u64, uint64_t *raw_out,
+                           uint64_t *valid_out);
+
+/* Statistics of the last step (synchronises). */
+cgs_status cgs_session_step_info(cgs_session session, cgs_step_info *out);
+
+/* Device time per kernel kind, summed since session creation (sessions
+ * created with params.timing != 0; zeros otherwise):
+ *   total_ms[4] / launches[4]: [0] score pass, [1] weight pass with the
+ *   step's first draw, [2] further draws, [3] reserved (0).  Synchronises. */
+cgs_status cgs_session_kernel_times(cgs_session session, double *total_ms, uint64_t *launches);
+
+/* Mark raw index k explored (must be valid). */
+cgs_status cgs_mark_explored(cgs_session session, uint64_t raw_index);
+/* Copy scores of valid configurations [first, first+count) from the last step. */
+cgs_status cgs_session_copy_scores(cgs_session session, uint64_t first, uint64_t count,
+                                   float *dst_host);
+/* Copy quantised weights q of valid configurations [first, first+count) as
+ * the last step left them (explored: 0). */
+cgs_status cgs_session_copy_weights(cgs_session session, uint64_t first, uint64_t count,
+                                    uint32_t *dst_host);
+/* Copy the explored bitmask over valid indices: ceil(n_valid / 32) words. */
+cgs_status cgs_session_copy_explored(cgs_session session, uint32_t *dst_host, uint64_t n_words);
+void cgs_session_destroy(cgs_session session);
+
+/* ------------------------------------------------ standalone sampler */
+/* The draw of Alg. 1 on caller-given integer weights: n_draws consecutive
+ * draws with removal over q_host[n] (each < 2^32), uniforms u64_host[n_draws].
+ * picks_host[i] = chosen index, or -1 once every weight is 0.  Uses the same
+ * device scan and search as cgs_sample_next.  Synchronises. */
+cgs_status cgs_sample_weights(cgs_space stream_owner, const uint32_t *q_host, uint64_t n,
+                              const uint64_t *u64_host, int n_draws, int64_t *picks_host);
+
+/* -------------------------------------------------- expert system */
+/* Bottleneck analysis and counter changes (Sect. 3.5), host float64.
+ *   pc_host[24]       measured counters in Table 1 order
+ *   b_host[18]        out: bottlenecks dram_read, dram_write, l2_read,
+ *                     l2_write, tex, local, shr_load, shr_store, fp32, fp64,
+ *                     int, misc, ldst, cont, bconv, issue, sm, paral
+ *   delta_host[24]    out: required change per Table 1 counter
+ *   delta_threads     out: required change of the thread count (may be NULL)
+ * A ratio with a zero denominator is 0; bottlenecks are clipped to [0, 1]. */
+cgs_status cgs_expert_system(const double *pc_host, const cgs_expert_params *expert,
+                             double *b_host, double *delta_host, double *delta_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGS_H */

@@ -56,11 +56,18 @@ class StepResult:
 def step(prep: Prepared, explored: np.ndarray, profile: int, delta: np.ndarray,
          uniforms, with_fp64: bool = True) -> StepResult:
     """Score all unexplored configurations against ``profile`` (a valid
-    index) and draw ``len(uniforms)`` configurations.  ``explored`` is updated
-    in place with the picks."""
+    index, marked explored) and draw ``len(uniforms)`` configurations.
+    ``profile=None`` is the start of Alg. 1 (nothing profiled): every score
+    is 0.  ``explored`` is updated in place with the profile and the picks."""
     delta = np.asarray(delta, dtype=np.float32)
-    s32 = SC.score_fp32(prep.P32[profile], prep.P32, delta)
-    s64 = SC.score_fp64(prep.P64[profile], prep.P64, delta.astype(np.float64)) if with_fp64 else None
+    if profile is None:
+        s32 = np.zeros(len(prep.valid), dtype=np.float32)
+        s64 = np.zeros(len(prep.valid)) if with_fp64 else None
+    else:
+        explored[profile] = True
+        s32 = SC.score_fp32(prep.P32[profile], prep.P32, delta)
+        s64 = (SC.score_fp64(prep.P64[profile], prep.P64, delta.astype(np.float64))
+               if with_fp64 else None)
     w32, s_min, s_max = SC.weights_fp32(s32, explored)
     q = SC.quantize(w32)
     total = int(q.sum(dtype=np.uint64))

@@ -1,0 +1,346 @@
+"""Thin ctypes binding of libcgs (include/cgs.h).
+
+Argument marshalling only: every function here converts NumPy arrays to
+pointers, calls the C entry point of the same name and turns a non-zero
+status into :class:`CgsError`.  All computation runs in the HIP library.
+The library must have been built (``python -m paper_2102_05297_amd.build``);
+importing this module without it raises ``ImportError``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcgs.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2102_05297_amd.build`")
+_lib = C.CDLL(_LIB_PATH)
+
+# ----------------------------------------------------------------- constants
+OK, EINVAL, ENOMEM, EDEVICE, EEMPTY, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5, -6
+KIND_CODES = {"DIV": 0, "DIV2": 1, "PROD_LE": 2, "PROD3_LE": 3, "PROD_GE": 4, "LE": 5}
+MAX_PARAMS, MAX_RADIX, MAX_COUNTERS, MAX_TREES, MAX_DEPTH = 32, 16, 64, 64, 14
+NO_PROFILE = (1 << 64) - 1
+
+# The C-ABI function names, for symbol checks.
+EXPORTS = (
+    "cgs_last_error", "cgs_version", "cgs_default_params", "cgs_default_expert_params",
+    "cgs_synchronize", "cgs_space_create", "cgs_space_info", "cgs_space_decode",
+    "cgs_space_valid_index", "cgs_space_copy_valid", "cgs_space_copy_mask", "cgs_space_destroy",
+    "cgs_model_load_forest", "cgs_model_info", "cgs_model_refresh", "cgs_model_copy_predictions",
+    "cgs_model_copy_leaf_ids", "cgs_model_destroy", "cgs_session_create", "cgs_search_step",
+    "cgs_sample_next", "cgs_session_step_info", "cgs_session_kernel_times", "cgs_mark_explored", "cgs_session_copy_scores",
+    "cgs_session_copy_weights", "cgs_session_copy_explored", "cgs_session_destroy",
+    "cgs_sample_weights", "cgs_expert_system",
+)
+
+
+class CgsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.cgs_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with status {status}: {msg}")
+
+
+# ----------------------------------------------------------------- structs
+class cgs_constraint(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("a", C.c_int32), ("b", C.c_int32), ("c", C.c_int32),
+                ("bound", C.c_int64)]
+
+
+class cgs_params(C.Structure):
+    _fields_ = [("gamma", C.c_float), ("w_min", C.c_float), ("block_log2", C.c_int32),
+                ("timing", C.c_int32)]
+
+
+class cgs_expert_params(C.Structure):
+    _fields_ = [("inst_reaction", C.c_double), ("volta", C.c_int32), ("reserved", C.c_int32),
+                ("cores", C.c_double), ("threads", C.c_double)]
+
+
+class cgs_step_info(C.Structure):
+    _fields_ = [("n_unexplored", C.c_uint64), ("total_weight", C.c_uint64), ("s_min", C.c_float),
+                ("s_max", C.c_float), ("device_ms", C.c_float), ("n_active", C.c_int32)]
+
+
+_p = C.c_void_p
+_u64 = C.c_uint64
+_i32 = C.c_int32
+_ptr = C.POINTER
+
+
+def _sig(name, args, res=C.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_lib.cgs_last_error.argtypes = []
+_lib.cgs_last_error.restype = C.c_char_p
+_sig("cgs_version", [])
+_sig("cgs_default_params", [_ptr(cgs_params)], None)
+_sig("cgs_default_expert_params", [_ptr(cgs_expert_params)], None)
+_sig("cgs_synchronize", [_p])
+_sig("cgs_space_create", [C.c_int, _p, _p, C.c_int, _p, _p, _ptr(_p)])
+_sig("cgs_space_info", [_p, _ptr(_u64), _ptr(_u64)])
+_sig("cgs_space_decode", [_p, _u64, _p])
+_sig("cgs_space_valid_index", [_p, _u64, _ptr(C.c_int64)])
+_sig("cgs_space_copy_valid", [_p, _u64, _u64, _p])
+_sig("cgs_space_copy_mask", [_p, _p, _u64])
+_sig("cgs_space_destroy", [_p], None)
+_sig("cgs_model_load_forest", [_p, C.c_int, C.c_int, C.c_int, _p, _p, _p, _ptr(_p)])
+_sig("cgs_model_info", [_p, _ptr(C.c_int), _ptr(C.c_float)])
+_sig("cgs_model_refresh", [_p])
+_sig("cgs_model_copy_predictions", [_p, _u64, _u64, _p])
+_sig("cgs_model_copy_leaf_ids", [_p, _u64, _u64, _p])
+_sig("cgs_model_destroy", [_p], None)
+_sig("cgs_session_create", [_p, _ptr(cgs_params), _ptr(_p)])
+_sig("cgs_search_step", [_p, _p, _u64, _p, _p, _ptr(cgs_expert_params)])
+_sig("cgs_sample_next", [_p, _u64, _ptr(_u64), _ptr(_u64)])
+_sig("cgs_session_step_info", [_p, _ptr(cgs_step_info)])
+_sig("cgs_session_kernel_times", [_p, _p, _p])
+_sig("cgs_mark_explored", [_p, _u64])
+_sig("cgs_session_copy_scores", [_p, _u64, _u64, _p])
+_sig("cgs_session_copy_weights", [_p, _u64, _u64, _p])
+_sig("cgs_session_copy_explored", [_p, _p, _u64])
+_sig("cgs_session_destroy", [_p], None)
+_sig("cgs_sample_weights", [_p, _p, _u64, _p, C.c_int, _p])
+_sig("cgs_expert_system", [_p, _ptr(cgs_expert_params), _p, _p, _ptr(C.c_double)])
+
+
+def _check(st: int, where: str) -> None:
+    if st != OK:
+        raise CgsError(st, where)
+
+
+def _arr(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _ptrof(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def cgs_version() -> int:
+    return int(_lib.cgs_version())
+
+
+def cgs_default_params() -> cgs_params:
+    p = cgs_params()
+    _lib.cgs_default_params(C.byref(p))
+    return p
+
+
+def cgs_default_expert_params() -> cgs_expert_params:
+    p = cgs_expert_params()
+    _lib.cgs_default_expert_params(C.byref(p))
+    return p
+
+
+def cgs_expert_system(pc, expert: Optional[cgs_expert_params] = None):
+    """Returns (B[18], delta[24], delta_threads), float64."""
+    pc = _arr(pc, np.float64)
+    B = np.zeros(18)
+    d = np.zeros(24)
+    dt = C.c_double(0.0)
+    _check(_lib.cgs_expert_system(_ptrof(pc), C.byref(expert) if expert else None, _ptrof(B),
+                                  _ptrof(d), C.byref(dt)), "cgs_expert_system")
+    return B, d, dt.value
+
+
+# ----------------------------------------------------------------- handles
+class Space:
+    """A tuning space on the device (cgs_space)."""
+
+    def __init__(self, radix: Sequence[int], values: Sequence[Sequence[int]],
+                 constraints: Sequence = (), stream: Optional[int] = None):
+        r = _arr(radix, np.int32)
+        v = _arr([x for tab in values for x in tab], np.int64)
+        cons = (cgs_constraint * max(1, len(constraints)))()
+        for i, (kind, a, b, c, bound) in enumerate(constraints):
+            cons[i] = cgs_constraint(KIND_CODES[kind] if isinstance(kind, str) else int(kind),
+                                     int(a), int(b), int(c), int(bound))
+        h = C.c_void_p()
+        _check(_lib.cgs_space_create(len(r), _ptrof(r), _ptrof(v), len(constraints), cons,
+                                     C.c_void_p(stream) if stream else None, C.byref(h)),
+               "cgs_space_create")
+        self.h = h
+        self.radix = [int(x) for x in r]
+        n_raw, n_valid = _u64(), _u64()
+        _check(_lib.cgs_space_info(h, C.byref(n_raw), C.byref(n_valid)), "cgs_space_info")
+        self.n_raw, self.n_valid = int(n_raw.value), int(n_valid.value)
+
+    @classmethod
+    def from_spec(cls, spec, stream=None) -> "Space":
+        return cls(spec.radix, spec.values, spec.constraints, stream)
+
+    def decode(self, raw: int) -> np.ndarray:
+        out = np.zeros(len(self.radix), dtype=np.int32)
+        _check(_lib.cgs_space_decode(self.h, int(raw), _ptrof(out)), "cgs_space_decode")
+        return out
+
+    def valid_index(self, raw: int) -> int:
+        out = C.c_int64()
+        _check(_lib.cgs_space_valid_index(self.h, int(raw), C.byref(out)), "cgs_space_valid_index")
+        return int(out.value)
+
+    def copy_valid(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        count = self.n_valid - first if count is None else count
+        out = np.zeros(count, dtype=np.uint32)
+        _check(_lib.cgs_space_copy_valid(self.h, first, count, _ptrof(out)), "cgs_space_copy_valid")
+        return out
+
+    def copy_mask(self) -> np.ndarray:
+        n = (self.n_raw + 31) // 32
+        out = np.zeros(n, dtype=np.uint32)
+        _check(_lib.cgs_space_copy_mask(self.h, _ptrof(out), n), "cgs_space_copy_mask")
+        return out
+
+    def synchronize(self) -> None:
+        _check(_lib.cgs_synchronize(self.h), "cgs_synchronize")
+
+    def sample_weights(self, q, uniforms) -> np.ndarray:
+        q = _arr(q, np.uint32)
+        u = _arr(uniforms, np.uint64)
+        picks = np.full(len(u), -1, dtype=np.int64)
+        _check(_lib.cgs_sample_weights(self.h, _ptrof(q), len(q), _ptrof(u), len(u),
+                                       _ptrof(picks)), "cgs_sample_weights")
+        return picks
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _lib.cgs_space_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class ForestModel:
+    """A regression forest and its cached predictions (cgs_model)."""
+
+    def __init__(self, space: Space, feat, thr, leaves):
+        leaves = _arr(leaves, np.float32)
+        T, L, Cn = leaves.shape
+        depth = int(L).bit_length() - 1
+        feat = _arr(feat, np.uint8)
+        thr = _arr(thr, np.uint8)
+        h = C.c_void_p()
+        _check(_lib.cgs_model_load_forest(space.h, T, depth, Cn, _ptrof(feat), _ptrof(thr),
+                                          _ptrof(leaves), C.byref(h)), "cgs_model_load_forest")
+        self.h, self.space = h, space
+        self.n_trees, self.depth, self.n_counters = T, depth, Cn
+
+    @classmethod
+    def from_spec(cls, space: Space, forest) -> "ForestModel":
+        return cls(space, forest.feat, forest.thr, forest.leaves)
+
+    def eval_ms(self) -> float:
+        n = C.c_int()
+        ms = C.c_float()
+        _check(_lib.cgs_model_info(self.h, C.byref(n), C.byref(ms)), "cgs_model_info")
+        return float(ms.value)
+
+    def refresh(self) -> None:
+        _check(_lib.cgs_model_refresh(self.h), "cgs_model_refresh")
+
+    def copy_predictions(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        count = self.space.n_valid - first if count is None else count
+        out = np.zeros((count, self.n_counters), dtype=np.float32)
+        _check(_lib.cgs_model_copy_predictions(self.h, first, count, _ptrof(out)),
+               "cgs_model_copy_predictions")
+        return out
+
+    def copy_leaf_ids(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        count = self.space.n_valid - first if count is None else count
+        out = np.zeros((self.n_trees, count), dtype=np.uint16)
+        _check(_lib.cgs_model_copy_leaf_ids(self.h, first, count, _ptrof(out)),
+               "cgs_model_copy_leaf_ids")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _lib.cgs_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Session:
+    """One search over a space (cgs_session)."""
+
+    def __init__(self, space: Space, params: Optional[cgs_params] = None):
+        h = C.c_void_p()
+        _check(_lib.cgs_session_create(space.h, C.byref(params) if params else None, C.byref(h)),
+               "cgs_session_create")
+        self.h, self.space = h, space
+
+    def search_step(self, model, profile_raw: int, delta=None, measured=None,
+                    expert: Optional[cgs_expert_params] = None) -> None:
+        d = None if delta is None else _arr(delta, np.float32)
+        m = None if measured is None else _arr(measured, np.float64)
+        _check(_lib.cgs_search_step(self.h, model.h, int(profile_raw), _ptrof(d), _ptrof(m),
+                                    C.byref(expert) if expert else None), "cgs_search_step")
+
+    def sample_next(self, u64: int):
+        """(raw index, valid index) of the drawn configuration; None when exhausted."""
+        raw, valid = _u64(), _u64()
+        st = _lib.cgs_sample_next(self.h, int(u64), C.byref(raw), C.byref(valid))
+        if st == EEMPTY:
+            return None
+        _check(st, "cgs_sample_next")
+        return int(raw.value), int(valid.value)
+
+    def step_info(self) -> cgs_step_info:
+        info = cgs_step_info()
+        _check(_lib.cgs_session_step_info(self.h, C.byref(info)), "cgs_session_step_info")
+        return info
+
+    def kernel_times(self):
+        """(total ms[4], launches[4]): score pass, weight pass + first draw,
+        further draws, reserved."""
+        ms = np.zeros(4, dtype=np.float64)
+        n = np.zeros(4, dtype=np.uint64)
+        _check(_lib.cgs_session_kernel_times(self.h, _ptrof(ms), _ptrof(n)),
+               "cgs_session_kernel_times")
+        return ms, n
+
+    def mark_explored(self, raw: int) -> None:
+        _check(_lib.cgs_mark_explored(self.h, int(raw)), "cgs_mark_explored")
+
+    def copy_scores(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        count = self.space.n_valid - first if count is None else count
+        out = np.zeros(count, dtype=np.float32)
+        _check(_lib.cgs_session_copy_scores(self.h, first, count, _ptrof(out)),
+               "cgs_session_copy_scores")
+        return out
+
+    def copy_weights(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        count = self.space.n_valid - first if count is None else count
+        out = np.zeros(count, dtype=np.uint32)
+        _check(_lib.cgs_session_copy_weights(self.h, first, count, _ptrof(out)),
+               "cgs_session_copy_weights")
+        return out
+
+    def copy_explored(self) -> np.ndarray:
+        n = (self.space.n_valid + 31) // 32
+        out = np.zeros(n, dtype=np.uint32)
+        _check(_lib.cgs_session_copy_explored(self.h, _ptrof(out), n), "cgs_session_copy_explored")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _lib.cgs_session_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,109 @@
+// Regression-forest evaluation over every valid configuration (Sect. 3.4.2:
+// internal nodes test a tuning parameter, leaves hold predicted counters).
+//
+// One thread per valid configuration, 256 per workgroup.  Each thread decodes
+// its raw index once into packed 4-bit digits.  Trees are processed one at a
+// time: the workgroup stages tree t's internal nodes (uint16: feature |
+// threshold << 8) in LDS, every thread walks depth D levels out of LDS and
+// parks its leaf id in LDS.  Then each thread gathers its T leaf vectors
+// (float4 loads from the L2-resident leaf array), sums them in ascending t
+// starting from tree 0, divides once by T, and writes the counters
+// structure-of-arrays: P[c][l], so a row of P is contiguous over
+// configurations and the sweep reads it coalesced.
+#include "device_common.h"
+
+namespace cgs {
+
+namespace {
+
+constexpr int kForestThreads = 256;
+
+__global__ __launch_bounds__(kForestThreads) void forest_eval(
+    const SpaceDev *__restrict__ sp, const uint32_t *__restrict__ idx, uint32_t first,
+    uint32_t count, const uint16_t *__restrict__ nodes, const float *__restrict__ leaves,
+    int n_trees, int depth, int n_counters, float *__restrict__ P, uint64_t stride,
+    uint16_t *__restrict__ leaf_out) {
+  extern __shared__ uint16_t smem[];
+  const uint32_t n_int = (1u << depth) - 1u;
+  const uint32_t n_int_pad = (n_int + 8u) & ~7u; // keep the leaf-id area 16-byte aligned
+  uint16_t *lnodes = smem;
+  uint16_t *lleaf = smem + n_int_pad; // [T][256]
+
+  const uint32_t i = blockIdx.x * kForestThreads + threadIdx.x;
+  const bool active = i < count;
+  const uint32_t l = first + i;
+  uint64_t lo = 0, hi = 0;
+  if (active) decode_packed(idx[l], sp, lo, hi);
+
+  for (int t = 0; t < n_trees; ++t) {
+    __syncthreads();
+    const uint16_t *tn = nodes + (size_t)t * n_int;
+    for (uint32_t j = threadIdx.x; j < n_int; j += kForestThreads) lnodes[j] = tn[j];
+    __syncthreads();
+    uint32_t node = 0;
+    for (int lev = 0; lev < depth; ++lev) {
+      const uint32_t nd = lnodes[node];
+      const uint32_t dig = digit_of(lo, hi, nd & 0xffu);
+      node = 2u * node + 1u + (dig > (nd >> 8) ? 1u : 0u);
+    }
+    const uint32_t leaf = node - n_int;
+    lleaf[t * kForestThreads + threadIdx.x] = (uint16_t)leaf;
+    if (leaf_out != nullptr && active) leaf_out[(size_t)t * count + i] = (uint16_t)leaf;
+  }
+  if (!active) return;
+
+  const uint32_t n_leaf = 1u << depth;
+  const float t_div = (float)n_trees;
+  if ((n_counters & 3) == 0) {
+    for (int c = 0; c < n_counters; c += 4) {
+      const uint32_t leaf0 = lleaf[threadIdx.x];
+      float4 acc = *reinterpret_cast<const float4 *>(leaves + (size_t)leaf0 * n_counters + c);
+      for (int t = 1; t < n_trees; ++t) {
+        const uint32_t lf = lleaf[t * kForestThreads + threadIdx.x];
+        const float4 v = *reinterpret_cast<const float4 *>(
+            leaves + ((size_t)t * n_leaf + lf) * n_counters + c);
+        acc.x = acc.x + v.x;
+        acc.y = acc.y + v.y;
+        acc.z = acc.z + v.z;
+        acc.w = acc.w + v.w;
+      }
+      P[(size_t)(c + 0) * stride + l] = acc.x / t_div;
+      P[(size_t)(c + 1) * stride + l] = acc.y / t_div;
+      P[(size_t)(c + 2) * stride + l] = acc.z / t_div;
+      P[(size_t)(c + 3) * stride + l] = acc.w / t_div;
+    }
+  } else {
+    for (int c = 0; c < n_counters; ++c) {
+      float acc = leaves[(size_t)lleaf[threadIdx.x] * n_counters + c];
+      for (int t = 1; t < n_trees; ++t) {
+        const uint32_t lf = lleaf[t * kForestThreads + threadIdx.x];
+        acc = acc + leaves[((size_t)t * n_leaf + lf) * n_counters + c];
+      }
+      P[(size_t)c * stride + l] = acc / t_div;
+    }
+  }
+}
+
+} // namespace
+
+// Evaluates valid configurations [first, first + count).  With d_leaf_out
+// set, also writes leaf ids [T][count] and skips nothing else.
+hipError_t launch_forest_eval(const SpaceDev *d_space, const uint32_t *d_idx, uint32_t n_valid,
+                              const uint16_t *d_nodes, const float *d_leaves, int n_trees,
+                              int depth, int n_counters, float *d_P, uint64_t stride,
+                              uint16_t *d_leaf_out, uint32_t leaf_first, uint32_t leaf_count,
+                              hipStream_t stream) {
+  const uint32_t first = d_leaf_out ? leaf_first : 0u;
+  const uint32_t count = d_leaf_out ? leaf_count : n_valid;
+  if (count == 0) return hipSuccess;
+  const uint32_t n_int = (1u << depth) - 1u;
+  const uint32_t n_int_pad = (n_int + 8u) & ~7u;
+  const size_t lds = (size_t)(n_int_pad + (uint32_t)n_trees * kForestThreads) * sizeof(uint16_t);
+  const uint32_t grid = (count + kForestThreads - 1) / kForestThreads;
+  hipLaunchKernelGGL(forest_eval, dim3(grid), dim3(kForestThreads), lds, stream, d_space, d_idx,
+                     first, count, d_nodes, d_leaves, n_trees, depth, n_counters, d_P, stride,
+                     d_leaf_out);
+  return hipGetLastError();
+}
+
+} // namespace cgs

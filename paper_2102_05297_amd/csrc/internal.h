@@ -1,0 +1,103 @@
+// Internal types shared by the host runtime and the kernels of libcgs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cgs.h"
+
+namespace cgs {
+
+// Division by a run-time invariant 32-bit divisor d, exact for every 32-bit
+// dividend: Granlund & Montgomery, "Division by invariant integers using
+// multiplication" (PLDI 1994), Fig. 4.1.  With l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1, sh1 = min(l, 1), sh2 = max(l - 1, 0):
+//   t = mulhi(m, n);  q = (t + ((n - t) >> sh1)) >> sh2.
+struct FastDiv {
+  uint32_t m;
+  uint32_t sh; // sh1 | sh2 << 8
+};
+
+// Space description, resident in device memory (one per space).
+// Parameter j's value for digit d is table[j * CGS_MAX_RADIX + d].
+struct SpaceDev {
+  int32_t n_params;
+  int32_t n_cons;
+  uint32_t n_raw;
+  uint32_t n_words; // ceil(n_raw / 32)
+  uint32_t radix[CGS_MAX_PARAMS];
+  FastDiv div[CGS_MAX_PARAMS];
+  uint32_t cons_code[CGS_MAX_CONSTRAINTS]; // kind | a << 8 | b << 16 | c << 24
+  int64_t cons_bound[CGS_MAX_CONSTRAINTS];
+  int32_t table[CGS_MAX_PARAMS * CGS_MAX_RADIX];
+};
+
+// Counters that enter one step's score: Table positions with dpc != 0,
+// ascending.  Passed by value to the score kernel.
+struct ActiveCounters {
+  int32_t n;
+  int32_t pad;
+  uint32_t ctr[CGS_MAX_COUNTERS];
+  float delta[CGS_MAX_COUNTERS];
+};
+
+// Per-step accumulators written by the kernels (device memory): one of
+// kAccSlots slots per score workgroup, combined by the readers.
+struct StepAcc {
+  uint32_t min_key;    // order-preserving key of s_min over unexplored
+  uint32_t max_key;    // ... of s_max
+  uint32_t n_unexplored;
+  uint32_t pad;
+};
+struct StepAccSums {
+  uint32_t min_key, max_key, n_unexplored;
+};
+constexpr int kAccSlots = 64;
+
+// Result of one draw (device memory, copied to pinned host memory).
+struct DrawResult {
+  uint64_t valid;  // picked valid index, or ~0 when the total weight is 0
+  uint64_t raw;    // its raw index
+  uint64_t total;  // Q at this draw
+  uint64_t r;      // floor(U * Q / 2^64)
+};
+
+constexpr uint64_t kNoPick = ~0ull;
+constexpr uint32_t kNoProfile = ~0u; // step prologue: no configuration to mark
+
+// ---- launchers (each enqueues on `stream`; return hipSuccess or an error)
+hipError_t launch_enumeration(const SpaceDev *d_space, uint32_t n_raw, uint32_t *d_mask,
+                              uint32_t *d_tile_count, uint32_t *d_tile_off, uint64_t *d_total,
+                              uint32_t *d_idx, int phase, hipStream_t stream);
+uint32_t enumeration_tiles(uint32_t n_raw);
+
+hipError_t launch_forest_eval(const SpaceDev *d_space, const uint32_t *d_idx, uint32_t n_valid,
+                              const uint16_t *d_nodes, const float *d_leaves, int n_trees,
+                              int depth, int n_counters, float *d_P, uint64_t stride,
+                              uint16_t *d_leaf_out, uint32_t leaf_first, uint32_t leaf_count,
+                              hipStream_t stream);
+
+hipError_t launch_reset_acc(StepAcc *d_acc, int n, hipStream_t stream);
+hipError_t launch_score_pass(const float *d_P, uint64_t stride, uint32_t profile,
+                             const ActiveCounters &act, const uint32_t *d_explored,
+                             uint32_t n_valid, float *d_s, StepAcc *d_acc, hipStream_t stream);
+hipError_t launch_weight_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
+                              uint32_t profile, const StepAcc *d_acc, StepAcc *d_acc_next,
+                              float gamma, float w_min, int block_log2, uint64_t *d_bsum,
+                              uint32_t n_blocks, uint32_t *d_done, bool do_draw, uint64_t u64,
+                              const uint32_t *d_idx, DrawResult *d_res, hipStream_t stream);
+hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
+                       const StepAcc *d_acc, float gamma, float w_min, int block_log2,
+                       uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64, const uint32_t *d_idx,
+                       DrawResult *d_res, hipStream_t stream);
+hipError_t launch_copy_weights(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
+                               const StepAcc *d_acc, float gamma, float w_min, uint32_t first,
+                               uint32_t count, uint32_t *d_q, hipStream_t stream);
+// Standalone sampler over an integer weight array.
+hipError_t launch_array_block_sums(const uint32_t *d_q, uint32_t n, int block_log2,
+                                   uint64_t *d_bsum, hipStream_t stream);
+hipError_t launch_array_draw(uint32_t *d_q, uint32_t n, int block_log2, uint64_t *d_bsum,
+                             uint32_t n_blocks, uint64_t u64, DrawResult *d_res,
+                             hipStream_t stream);
+
+} // namespace cgs
