@@ -66,6 +66,36 @@ def run_search(cgs, sp, model, U, pcs, thr, n_steps, timing):
     return picks, sess
 
 
+def copy_probe(n_bytes: int = 1 << 30, reps: int = 5) -> dict:
+    """Achievable HBM bandwidth of a plain device-to-device copy of n_bytes
+    (the HIP runtime's copy kernel), timed with HIP events; reads + writes."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so.7")
+    src, dst = C.c_void_p(), C.c_void_p()
+    e0, e1 = C.c_void_p(), C.c_void_p()
+    ok = (hip.hipMalloc(C.byref(src), C.c_size_t(n_bytes)) == 0 and
+          hip.hipMalloc(C.byref(dst), C.c_size_t(n_bytes)) == 0 and
+          hip.hipEventCreate(C.byref(e0)) == 0 and hip.hipEventCreate(C.byref(e1)) == 0)
+    if not ok:
+        return {"error": "allocation failed"}
+    hip.hipMemset(src, 1, C.c_size_t(n_bytes))
+    hip.hipMemcpy(dst, src, C.c_size_t(n_bytes), 3)     # warm-up, hipMemcpyDeviceToDevice
+    hip.hipDeviceSynchronize()
+    hip.hipEventRecord(e0, None)
+    for _ in range(reps):
+        hip.hipMemcpyAsync(dst, src, C.c_size_t(n_bytes), 3, None)
+    hip.hipEventRecord(e1, None)
+    hip.hipEventSynchronize(e1)
+    ms = C.c_float()
+    hip.hipEventElapsedTime(C.byref(ms), e0, e1)
+    hip.hipFree(src)
+    hip.hipFree(dst)
+    hip.hipEventDestroy(e0)
+    hip.hipEventDestroy(e1)
+    gbs = 2.0 * n_bytes * reps / (ms.value / 1e3) / 1e9
+    return {"copy_gbs": gbs, "bytes": n_bytes, "reps": reps, "avg_ms": ms.value / reps}
+
+
 def cpu_baseline(spec, forest, n_steps):
     """The oracle, untouched, on a bounded sample of the workload: the
     configurations with raw index below 2^21 (1/8 of the raw space).  Its
@@ -169,6 +199,9 @@ def main() -> int:
                  "equal": int(sum(ref[i]["pick"] == picks[i] for i in range(n_chk)))}
         log(f"picks equal to the oracle trajectory: {exact['equal']}/{exact['checked']}")
 
+    probe = copy_probe()
+    log(f"copy probe: {probe}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")
@@ -206,8 +239,10 @@ def main() -> int:
         },
         "kernel_avg_us": {
             "score_pass": ms[0] / max(1, launches[0]) * 1e3,
-            "weight_draw": ms[1] / max(1, launches[1]) * 1e3,
+            "weight_pass": ms[1] / max(1, launches[1]) * 1e3,
+            "draw": ms[2] / max(1, launches[2]) * 1e3,
         },
+        "hbm_copy_probe": probe,
         "model_eval_ms": model.eval_ms(),
         "space_create_ms": t_enum * 1e3,
         "mean_active_counters": float(np.mean(n_active)),

@@ -226,8 +226,8 @@ cgs_status cgs_session_step_info(cgs_session session, cgs_step_info *out);
 
 /* Device time per kernel kind, summed since session creation (sessions
  * created with params.timing != 0; zeros otherwise):
- *   total_ms[4] / launches[4]: [0] score pass, [1] weight pass with the
- *   step's first draw, [2] further draws, [3] reserved (0).  Synchronises. */
+ *   total_ms[4] / launches[4]: [0] score pass, [1] weight pass, [2] draws,
+ *   [3] reserved (0).  Synchronises. */
 cgs_status cgs_session_kernel_times(cgs_session session, double *total_ms, uint64_t *launches);
 
 /* Mark raw index k explored (must be valid). */

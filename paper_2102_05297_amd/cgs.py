@@ -306,8 +306,7 @@ class Session:
         return info
 
     def kernel_times(self):
-        """(total ms[4], launches[4]): score pass, weight pass + first draw,
-        further draws, reserved."""
+        """(total ms[4], launches[4]): score pass, weight pass, draws, reserved."""
         ms = np.zeros(4, dtype=np.float64)
         n = np.zeros(4, dtype=np.uint64)
         _check(_lib.cgs_session_kernel_times(self.h, _ptrof(ms), _ptrof(n)),

@@ -95,7 +95,6 @@ struct cgs_session_s {
   float *d_s = nullptr;
   uint64_t *d_bsum = nullptr;
   StepAcc *d_acc = nullptr; // [2][kAccSlots]
-  uint32_t *d_done = nullptr;
   DrawResult *d_res = nullptr;
   DrawResult *h_res = nullptr; // pinned
   StepAcc *h_acc = nullptr;    // pinned, [kAccSlots]
@@ -163,7 +162,6 @@ void destroy_space(cgs_space sp) {
   dfree(sp->d_desc);
   dfree(sp->d_mask);
   dfree(sp->d_idx);
-  dfree(sp->d_res);
   if (sp->h_res) (void)hipHostFree(sp->h_res);
   if (sp->own_stream && sp->stream) (void)hipStreamDestroy(sp->stream);
   delete sp;
@@ -248,8 +246,9 @@ extern "C" cgs_status cgs_space_create(int n_params, const int32_t *radix, const
   }
   SP_TRY(dalloc(&sp->d_desc, 1));
   SP_TRY(dalloc(&sp->d_mask, desc.n_words));
-  SP_TRY(dalloc(&sp->d_res, 1));
-  SP_TRY(hipHostMalloc(reinterpret_cast<void **>(&sp->h_res), sizeof(DrawResult), 0));
+  SP_TRY(hipHostMalloc(reinterpret_cast<void **>(&sp->h_res), sizeof(DrawResult),
+                       hipHostMallocMapped));
+  SP_TRY(hipHostGetDevicePointer(reinterpret_cast<void **>(&sp->d_res), sp->h_res, 0));
   const uint32_t n_tiles = enumeration_tiles((uint32_t)n_raw);
   uint32_t *d_tile_count = nullptr, *d_tile_off = nullptr;
   uint64_t *d_total = nullptr;
@@ -511,8 +510,6 @@ void destroy_session(cgs_session s) {
   dfree(s->d_s);
   dfree(s->d_bsum);
   dfree(s->d_acc);
-  dfree(s->d_done);
-  dfree(s->d_res);
   if (s->h_res) (void)hipHostFree(s->h_res);
   if (s->h_acc) (void)hipHostFree(s->h_acc);
   if (s->ev_begin) (void)hipEventDestroy(s->ev_begin);
@@ -545,8 +542,8 @@ hipError_t collect_step_times(cgs_session s) {
   return hipSuccess;
 }
 
-// Enqueues the recorded step: score pass, then weights + block sums with the
-// first draw (when do_draw) in the last workgroup.
+// Enqueues the recorded step: score pass, weight pass, and either its first
+// draw (do_draw) or just the marking of its profiled configuration.
 hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
   cgs_space sp = s->space;
   cgs_model m = s->pending_model;
@@ -556,17 +553,27 @@ hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
   if (timing && s->step_times_pending) e = collect_step_times(s);
   StepAcc *acc = s->d_acc + s->parity * kAccSlots;
   StepAcc *acc_next = s->d_acc + (s->parity ^ 1) * kAccSlots;
+  const uint32_t prof = s->pending_profile;
   if (e == hipSuccess) e = hipEventRecord(s->ev_begin, sp->stream);
   if (e == hipSuccess && timing) e = hipEventRecord(s->ev_k[0], sp->stream);
   if (e == hipSuccess)
-    e = launch_score_pass(m->d_P, m->stride, s->pending_profile, s->pending_act, s->d_explored, nv,
-                          s->d_s, acc, sp->stream);
+    e = launch_score_pass(m->d_P, m->stride, prof, s->pending_act, s->d_explored, nv, s->d_s, acc,
+                          sp->stream);
   if (e == hipSuccess && timing) e = hipEventRecord(s->ev_k[1], sp->stream);
   if (e == hipSuccess)
-    e = launch_weight_draw(s->d_s, s->d_explored, nv, s->pending_profile, acc, acc_next,
-                           s->params.gamma, s->params.w_min, s->block_log2, s->d_bsum,
-                           s->n_blocks, s->d_done, do_draw, u64, sp->d_idx, s->d_res, sp->stream);
+    e = launch_weight_pass(s->d_s, s->d_explored, nv, prof, acc, acc_next, s->params.gamma,
+                           s->params.w_min, s->block_log2, s->d_bsum, s->n_blocks, sp->stream);
   if (e == hipSuccess && timing) e = hipEventRecord(s->ev_k[2], sp->stream);
+  if (e == hipSuccess && do_draw && timing) e = hipEventRecord(s->ev_k[3], sp->stream);
+  if (e == hipSuccess) {
+    if (do_draw)
+      e = launch_draw(s->d_s, s->d_explored, nv, prof, true, acc, s->params.gamma, s->params.w_min,
+                      s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, s->d_res,
+                      sp->stream);
+    else
+      e = launch_mark_one(s->d_explored, prof, nv, sp->stream);
+  }
+  if (e == hipSuccess && do_draw && timing) e = hipEventRecord(s->ev_k[4], sp->stream);
   if (e == hipSuccess) e = hipEventRecord(s->ev_end, sp->stream);
   if (e != hipSuccess) return e;
   s->step_times_pending = timing;
@@ -622,9 +629,9 @@ extern "C" cgs_status cgs_session_create(cgs_space sp, const cgs_params *params,
   if (e == hipSuccess) e = dalloc(&s->d_s, stride);
   if (e == hipSuccess) e = dalloc(&s->d_bsum, s->n_blocks);
   if (e == hipSuccess) e = dalloc(&s->d_acc, 2 * kAccSlots);
-  if (e == hipSuccess) e = dalloc(&s->d_done, 1);
-  if (e == hipSuccess) e = dalloc(&s->d_res, 1);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->h_res), sizeof(DrawResult), 0);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void **>(&s->h_res), sizeof(DrawResult), hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->d_res), s->h_res, 0);
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void **>(&s->h_acc), kAccSlots * sizeof(StepAcc), 0);
   if (e == hipSuccess) e = hipEventCreate(&s->ev_begin);
@@ -634,7 +641,6 @@ extern "C" cgs_status cgs_session_create(cgs_space sp, const cgs_params *params,
     e = hipMemsetAsync(s->d_explored, 0, std::max<uint64_t>(n_words, 1) * sizeof(uint32_t),
                        sp->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->d_s, 0, stride * sizeof(float), sp->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(s->d_done, 0, sizeof(uint32_t), sp->stream);
   if (e == hipSuccess) e = launch_reset_acc(s->d_acc, 2 * kAccSlots, sp->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
   if (e != hipSuccess) {
@@ -704,32 +710,28 @@ extern "C" cgs_status cgs_sample_next(cgs_session s, uint64_t u64, uint64_t *raw
   cgs_space sp = s->space;
   if (sp->n_valid == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
   const bool timing = s->params.timing != 0;
-  bool further = false;
   if (s->pending) {
     HIP_TRY(launch_pending(s, true, u64));
   } else {
-    further = true;
     if (timing) HIP_TRY(hipEventRecord(s->ev_k[3], sp->stream));
-    HIP_TRY(launch_draw(s->d_s, s->d_explored, (uint32_t)sp->n_valid,
+    HIP_TRY(launch_draw(s->d_s, s->d_explored, (uint32_t)sp->n_valid, kNoProfile, false,
                         s->d_acc + s->cur_acc * kAccSlots, s->params.gamma, s->params.w_min,
                         s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, s->d_res,
                         sp->stream));
     if (timing) HIP_TRY(hipEventRecord(s->ev_k[4], sp->stream));
     HIP_TRY(hipEventRecord(s->ev_end, sp->stream));
   }
-  HIP_TRY(hipMemcpyAsync(s->h_res, s->d_res, sizeof(DrawResult), hipMemcpyDeviceToHost,
-                         sp->stream));
   HIP_TRY(hipStreamSynchronize(sp->stream));
   if (timing) {
     if (s->step_times_pending) HIP_TRY(collect_step_times(s));
-    if (further) {
-      float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, s->ev_k[3], s->ev_k[4]));
-      s->kernel_ms[2] += ms;
-      s->kernel_n[2] += 1;
-    }
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, s->ev_k[3], s->ev_k[4]));
+    s->kernel_ms[2] += ms;
+    s->kernel_n[2] += 1;
   }
-  const DrawResult r = *s->h_res;
+  DrawResult r;
+  std::memcpy(&r, const_cast<const DrawResult *>(static_cast<volatile DrawResult *>(s->h_res)),
+              sizeof r);
   s->last_total = r.total;
   if (r.total == 0) return fail(CGS_EEMPTY, "no unexplored valid configuration is left");
   if (r.valid == kNoPick)
@@ -864,9 +866,6 @@ extern "C" cgs_status cgs_sample_weights(cgs_space sp, const uint32_t *q, uint64
   if (e == hipSuccess) e = launch_array_block_sums(d_q, (uint32_t)n, lg, d_bsum, sp->stream);
   for (int i = 0; i < n_draws && e == hipSuccess; ++i) {
     e = launch_array_draw(d_q, (uint32_t)n, lg, d_bsum, n_blocks, u64[i], sp->d_res, sp->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(sp->h_res, sp->d_res, sizeof(DrawResult), hipMemcpyDeviceToHost,
-                         sp->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
     if (e == hipSuccess) {
       if (sp->h_res->total == 0) break;

@@ -81,15 +81,15 @@ hipError_t launch_reset_acc(StepAcc *d_acc, int n, hipStream_t stream);
 hipError_t launch_score_pass(const float *d_P, uint64_t stride, uint32_t profile,
                              const ActiveCounters &act, const uint32_t *d_explored,
                              uint32_t n_valid, float *d_s, StepAcc *d_acc, hipStream_t stream);
-hipError_t launch_weight_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
+hipError_t launch_weight_pass(const float *d_s, const uint32_t *d_explored, uint32_t n_valid,
                               uint32_t profile, const StepAcc *d_acc, StepAcc *d_acc_next,
                               float gamma, float w_min, int block_log2, uint64_t *d_bsum,
-                              uint32_t n_blocks, uint32_t *d_done, bool do_draw, uint64_t u64,
-                              const uint32_t *d_idx, DrawResult *d_res, hipStream_t stream);
-hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
-                       const StepAcc *d_acc, float gamma, float w_min, int block_log2,
-                       uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64, const uint32_t *d_idx,
-                       DrawResult *d_res, hipStream_t stream);
+                              uint32_t n_blocks, hipStream_t stream);
+hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid, uint32_t profile,
+                       bool mark_profile, const StepAcc *d_acc, float gamma, float w_min,
+                       int block_log2, uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64,
+                       const uint32_t *d_idx, DrawResult *d_res, hipStream_t stream);
+hipError_t launch_mark_one(uint32_t *d_explored, uint32_t l, uint32_t n_valid, hipStream_t stream);
 hipError_t launch_copy_weights(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
                                const StepAcc *d_acc, float gamma, float w_min, uint32_t first,
                                uint32_t count, uint32_t *d_q, hipStream_t stream);

@@ -12,7 +12,7 @@
 //   acc[2][64]     per-step min / max / count accumulators, two sets used by
 //                  alternate steps (the step using one set clears the other)
 //
-// Kernels per step (two launches up to the first draw):
+// Kernels per step (three launches up to the first draw):
 //   score_pass    4 configurations per thread, float4 loads of up to 8
 //                 counter rows issued before any arithmetic; float32 with
 //                 every operation rounded (this file is built without
@@ -21,15 +21,18 @@
 //                 explored.  Per-workgroup min / max of s over unexplored
 //                 configurations go to one of 64 accumulator slots with
 //                 order-preserving uint32 atomics.
-//   weight_draw   one workgroup per block: q = rint(w * 2^23) and the block
-//                 sum.  The last workgroup to finish (device-scope counter)
-//                 performs the first draw of the step and marks the
+//   weight_pass   one workgroup per block: q = rint(w * 2^23) and the block
+//                 sum (plain stores; the kernel boundary publishes them to
+//                 every XCD, which a device-scope handoff inside one launch
+//                 would pay for with an L2 write-back per workgroup)
+//   draw          one workgroup per draw; the step's first draw also marks the
 //                 profiled configuration explored.
-//   draw          further draws of the same step: one workgroup.
 // A draw: Q = sum of block sums, r = mulhi64(U, Q), scan of the block sums
 // to the block holding r, recompute that block's q and scan it to l with
 // prefix_l <= r < prefix_l + q_l; mark l explored and subtract q_l from its
 // block sum (Alg. 1 zeroes S_l before the next draw of the iteration).
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace cgs {
@@ -40,35 +43,45 @@ constexpr int kScoreThreads = 256;
 constexpr int kWeightThreads = 256;
 constexpr int kDrawThreads = 1024;
 constexpr int kRowsInFlight = 8;
+constexpr uint32_t kScoreGrid = 2048; // 8 workgroups of 256 threads per CU
 
+// Combines the kAccSlots accumulator slots: wave 0 loads one slot per lane
+// and reduces across the wave; the result is broadcast through LDS.  Every
+// thread of the block must call it (it contains a barrier).
 __device__ __forceinline__ StepAccSums reduce_slots(const StepAcc *__restrict__ slots) {
-  StepAccSums r{0xffffffffu, 0u, 0u};
-  for (int i = 0; i < kAccSlots; ++i) {
-    r.min_key = min(r.min_key, slots[i].min_key);
-    r.max_key = max(r.max_key, slots[i].max_key);
-    r.n_unexplored += slots[i].n_unexplored;
+  static_assert(kAccSlots == kWave, "one slot per lane");
+  __shared__ StepAccSums shared_sums;
+  if (threadIdx.x < kWave) {
+    const StepAcc a = slots[threadIdx.x];
+    const uint32_t mn = wave_umin(a.min_key), mx = wave_umax(a.max_key);
+    const uint32_t n = wave_sum(a.n_unexplored);
+    if (threadIdx.x == 0) shared_sums = StepAccSums{mn, mx, n};
   }
-  return r;
+  __syncthreads();
+  return shared_sums;
 }
 
+// Scores 4 configurations per thread over tiles of 4 * kScoreThreads
+// configurations, grid-stride, so few workgroups update the accumulators.
 __global__ __launch_bounds__(kScoreThreads) void score_pass(
     const float *__restrict__ P, uint64_t stride, uint32_t profile, ActiveCounters act,
     const uint32_t *__restrict__ explored, uint32_t n_valid, float *__restrict__ s_out,
     StepAcc *__restrict__ acc) {
   __shared__ uint32_t red[3][kScoreThreads / kWave];
-  const uint32_t g = blockIdx.x * kScoreThreads + threadIdx.x; // group of 4 configs
-  const uint32_t l0 = 4u * g;
-  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-  uint32_t ex4 = 0xfu;
-  if (l0 < n_valid) {
+  uint32_t kmin = 0xffffffffu, kmax = 0u, cnt = 0u;
+  const int n = profile < n_valid ? act.n : 0;
+  const uint32_t n_tiles = (n_valid + 4u * kScoreThreads - 1) / (4u * kScoreThreads);
+  for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const uint32_t l0 = 4u * (tile * kScoreThreads + threadIdx.x);
+    if (l0 >= n_valid) continue;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
     const uint32_t word = explored[l0 >> 5];
-    ex4 = (word >> (l0 & 31u)) & 0xfu;
+    uint32_t ex4 = (word >> (l0 & 31u)) & 0xfu;
     // configurations past the end and the profiled one count as explored
     const uint32_t tail = n_valid - l0;
     if (tail < 4u) ex4 |= (0xfu << tail) & 0xfu;
     if (profile - l0 < 4u) ex4 |= 1u << (profile - l0);
     const float *__restrict__ col = P + l0;
-    const int n = profile < n_valid ? act.n : 0;
     for (int j0 = 0; j0 < n; j0 += kRowsInFlight) {
       float4 x[kRowsInFlight];
       float av[kRowsInFlight];
@@ -105,16 +118,15 @@ __global__ __launch_bounds__(kScoreThreads) void score_pass(
       }
     }
     *reinterpret_cast<float4 *>(s_out + l0) = make_float4(s0, s1, s2, s3);
-  }
-  uint32_t kmin = 0xffffffffu, kmax = 0u, cnt = 0u;
-  const float sv[4] = {s0, s1, s2, s3};
+    const float sv[4] = {s0, s1, s2, s3};
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    if (!((ex4 >> e) & 1u)) {
-      const uint32_t k = float_key(sv[e]);
-      kmin = min(kmin, k);
-      kmax = max(kmax, k);
-      ++cnt;
+    for (int e = 0; e < 4; ++e) {
+      if (!((ex4 >> e) & 1u)) {
+        const uint32_t k = float_key(sv[e]);
+        kmin = min(kmin, k);
+        kmax = max(kmax, k);
+        ++cnt;
+      }
     }
   }
   kmin = wave_umin(kmin);
@@ -164,10 +176,12 @@ struct ArrayWeights {
   __device__ void remove(uint32_t l) const { q[l] = 0u; }
 };
 
-// Block sums are read with device-coherent loads: in the fused kernel they
-// were written by other workgroups of the same launch.
-__device__ __forceinline__ uint64_t load_coherent(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t load_coherent(const uint64_t *p) { return *p; }
+
+// The draw result lives in mapped pinned host memory: system-scope stores, so
+// the host reads it right after the stream synchronises (no copy kernel).
+__device__ __forceinline__ void put(uint64_t *field, uint64_t v) {
+  __hip_atomic_store(field, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 template <int NT, typename W>
@@ -185,10 +199,10 @@ __device__ void draw_body(const W &wsrc, int block_log2, uint64_t *__restrict__ 
   const uint64_t Q = block_sum<NT>(part, scratch);
   if (Q == 0) {
     if (tid == 0) {
-      res->valid = kNoPick;
-      res->raw = kNoPick;
-      res->total = 0;
-      res->r = 0;
+      put(&res->valid, kNoPick);
+      put(&res->raw, kNoPick);
+      put(&res->total, 0);
+      put(&res->r, 0);
     }
     return;
   }
@@ -196,10 +210,10 @@ __device__ void draw_body(const W &wsrc, int block_log2, uint64_t *__restrict__ 
   if (tid == 0) {
     // overwritten by the thread that finds the pick; stays "no pick" only if
     // the block sums disagree with the weights (reported as an error)
-    res->valid = kNoPick;
-    res->raw = kNoPick;
-    res->total = Q;
-    res->r = r;
+    put(&res->valid, kNoPick);
+    put(&res->raw, kNoPick);
+    put(&res->total, Q);
+    put(&res->r, r);
     found = 0;
     found_block = 0;
     found_rem = 0;
@@ -240,8 +254,8 @@ __device__ void draw_body(const W &wsrc, int block_log2, uint64_t *__restrict__ 
         const uint32_t l = first + e;
         wsrc.remove(l);
         bsum[blk] = load_coherent(bsum + blk) - q;
-        res->valid = l;
-        res->raw = idx ? idx[l] : l;
+        put(&res->valid, l);
+        put(&res->raw, idx ? idx[l] : l);
         break;
       }
       pre += q;
@@ -249,15 +263,12 @@ __device__ void draw_body(const W &wsrc, int block_log2, uint64_t *__restrict__ 
   }
 }
 
-// One workgroup per block of 2^block_log2 configurations.
-__global__ __launch_bounds__(kWeightThreads) void weight_draw(
-    const float *__restrict__ s, uint32_t *__restrict__ explored, uint32_t n_valid,
+// One workgroup per block of 2^block_log2 configurations: block sums of q.
+__global__ __launch_bounds__(kWeightThreads) void weight_pass(
+    const float *__restrict__ s, const uint32_t *__restrict__ explored, uint32_t n_valid,
     uint32_t profile, const StepAcc *__restrict__ acc, StepAcc *__restrict__ acc_next,
-    float gamma, float w_min, int block_log2, uint64_t *__restrict__ bsum, uint32_t n_blocks,
-    uint32_t *__restrict__ done, int do_draw, uint64_t u64, const uint32_t *__restrict__ idx,
-    DrawResult *__restrict__ res) {
+    float gamma, float w_min, int block_log2, uint64_t *__restrict__ bsum) {
   __shared__ uint64_t scratch[kWeightThreads / kWave];
-  __shared__ int is_last;
   const StepAccSums a = reduce_slots(acc);
   const float s_min = key_float(a.min_key), s_max = key_float(a.max_key);
   if (blockIdx.x == 0 && threadIdx.x < kAccSlots) {
@@ -296,36 +307,29 @@ __global__ __launch_bounds__(kWeightThreads) void weight_draw(
     }
   }
   const uint64_t total = block_sum<kWeightThreads>(sum, scratch);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(bsum + blockIdx.x, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t prev =
-        __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = prev == n_blocks - 1;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  // last workgroup: every block sum of this launch is visible
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  if (do_draw) {
-    ScoreWeights w{s, explored, n_valid, profile, s_min, s_max, gamma, w_min};
-    draw_body<kWeightThreads>(w, block_log2, bsum, n_blocks, u64, idx, res);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (profile < n_valid) atomicOr(&explored[profile >> 5], 1u << (profile & 31u));
-    *done = 0u;
-  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
+// One draw.  `profile` (or kNoProfile) is excluded and, when `mark_profile`,
+// marked explored once the draw is done.
 __global__ __launch_bounds__(kDrawThreads) void draw_scores(
     const float *__restrict__ s, uint32_t *__restrict__ explored, uint32_t n_valid,
-    const StepAcc *__restrict__ acc, float gamma, float w_min, int block_log2,
-    uint64_t *__restrict__ bsum, uint32_t n_blocks, uint64_t u64,
+    uint32_t profile, int mark_profile, const StepAcc *__restrict__ acc, float gamma,
+    float w_min, int block_log2, uint64_t *__restrict__ bsum, uint32_t n_blocks, uint64_t u64,
     const uint32_t *__restrict__ idx, DrawResult *__restrict__ res) {
   const StepAccSums a = reduce_slots(acc);
-  ScoreWeights w{s, explored, n_valid, kNoProfile, key_float(a.min_key), key_float(a.max_key),
+  ScoreWeights w{s, explored, n_valid, profile, key_float(a.min_key), key_float(a.max_key),
                  gamma, w_min};
   draw_body<kDrawThreads>(w, block_log2, bsum, n_blocks, u64, idx, res);
+  __syncthreads();
+  if (threadIdx.x == 0 && mark_profile && profile < n_valid)
+    atomicOr(&explored[profile >> 5], 1u << (profile & 31u));
+}
+
+// Marks the profiled configuration explored (a step read without a draw).
+__global__ __launch_bounds__(64) void mark_one(uint32_t *__restrict__ explored, uint32_t l,
+                                               uint32_t n_valid) {
+  if (threadIdx.x == 0 && l < n_valid) atomicOr(&explored[l >> 5], 1u << (l & 31u));
 }
 
 __global__ __launch_bounds__(kDrawThreads) void draw_array(uint32_t *__restrict__ q, uint32_t n,
@@ -358,9 +362,9 @@ __global__ __launch_bounds__(256) void copy_weights(const float *__restrict__ s,
                                                     const StepAcc *__restrict__ acc, float gamma,
                                                     float w_min, uint32_t first, uint32_t count,
                                                     uint32_t *__restrict__ q) {
+  const StepAccSums a = reduce_slots(acc);
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
-  const StepAccSums a = reduce_slots(acc);
   ScoreWeights w{s, explored, n_valid, kNoProfile, key_float(a.min_key), key_float(a.max_key),
                  gamma, w_min};
   q[i] = w(first + i);
@@ -385,32 +389,37 @@ hipError_t launch_reset_acc(StepAcc *d_acc, int n, hipStream_t stream) {
 hipError_t launch_score_pass(const float *d_P, uint64_t stride, uint32_t profile,
                              const ActiveCounters &act, const uint32_t *d_explored,
                              uint32_t n_valid, float *d_s, StepAcc *d_acc, hipStream_t stream) {
-  const uint32_t groups = (n_valid + 3u) / 4u;
-  const uint32_t grid = (groups + kScoreThreads - 1) / kScoreThreads;
+  const uint32_t n_tiles = (n_valid + 4u * kScoreThreads - 1) / (4u * kScoreThreads);
+  const uint32_t grid = std::min<uint32_t>(n_tiles, kScoreGrid);
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL(score_pass, dim3(grid), dim3(kScoreThreads), 0, stream, d_P, stride, profile,
                      act, d_explored, n_valid, d_s, d_acc);
   return hipGetLastError();
 }
 
-hipError_t launch_weight_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
+hipError_t launch_weight_pass(const float *d_s, const uint32_t *d_explored, uint32_t n_valid,
                               uint32_t profile, const StepAcc *d_acc, StepAcc *d_acc_next,
                               float gamma, float w_min, int block_log2, uint64_t *d_bsum,
-                              uint32_t n_blocks, uint32_t *d_done, bool do_draw, uint64_t u64,
-                              const uint32_t *d_idx, DrawResult *d_res, hipStream_t stream) {
+                              uint32_t n_blocks, hipStream_t stream) {
   if (n_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(weight_draw, dim3(n_blocks), dim3(kWeightThreads), 0, stream, d_s, d_explored,
-                     n_valid, profile, d_acc, d_acc_next, gamma, w_min, block_log2, d_bsum,
-                     n_blocks, d_done, do_draw ? 1 : 0, u64, d_idx, d_res);
+  hipLaunchKernelGGL(weight_pass, dim3(n_blocks), dim3(kWeightThreads), 0, stream, d_s, d_explored,
+                     n_valid, profile, d_acc, d_acc_next, gamma, w_min, block_log2, d_bsum);
   return hipGetLastError();
 }
 
-hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
-                       const StepAcc *d_acc, float gamma, float w_min, int block_log2,
-                       uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64, const uint32_t *d_idx,
-                       DrawResult *d_res, hipStream_t stream) {
+hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid, uint32_t profile,
+                       bool mark_profile, const StepAcc *d_acc, float gamma, float w_min,
+                       int block_log2, uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64,
+                       const uint32_t *d_idx, DrawResult *d_res, hipStream_t stream) {
   hipLaunchKernelGGL(draw_scores, dim3(1), dim3(kDrawThreads), 0, stream, d_s, d_explored, n_valid,
-                     d_acc, gamma, w_min, block_log2, d_bsum, n_blocks, u64, d_idx, d_res);
+                     profile, mark_profile ? 1 : 0, d_acc, gamma, w_min, block_log2, d_bsum,
+                     n_blocks, u64, d_idx, d_res);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_one(uint32_t *d_explored, uint32_t l, uint32_t n_valid,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(mark_one, dim3(1), dim3(64), 0, stream, d_explored, l, n_valid);
   return hipGetLastError();
 }
 
