@@ -1,0 +1,124 @@
+"""Multilayer-perceptron surrogate of the counter model (oracle).
+
+An extension of the method: the model of Sect. 3.4 maps tuning parameters to
+predicted counters; here a three-layer perceptron plays that role next to
+the decision trees.  Everything is plain float64 NumPy:
+
+  features   x_j = digit_j / 8 (digit = index of parameter j's value)
+  layers     z1 = W1 x + b1, h1 = gelu(z1); z2 = W2 h1 + b2, h2 = gelu(z2);
+             y = W3 h2 + b3
+  gelu       0.5 z (1 + erf(z / sqrt 2))                  (exact form)
+  loss       mean over batch and counters of (y - target)^2
+  backward   hand-written chain rule (no autodiff)
+  optimiser  Adam (Kingma & Ba, "Adam: a method for stochastic optimization",
+             ICLR 2015, Algorithm 1) with bias correction
+  inference  predictions max(y, 0): the score equation needs non-negative
+             counters (a prediction of exactly 0 drops the counter from
+             PC_used)
+
+``bf16`` rounds to bfloat16 (round to nearest even), used to feed the oracle
+the same weights the device computes with.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erf
+
+SQRT2 = math.sqrt(2.0)
+INV_SQRT_2PI = 1.0 / math.sqrt(2.0 * math.pi)
+
+
+def features(digits: np.ndarray) -> np.ndarray:
+    return np.asarray(digits, dtype=np.float64) / 8.0
+
+
+def gelu(z):
+    return 0.5 * z * (1.0 + erf(z / SQRT2))
+
+
+def gelu_grad(z):
+    """d/dz gelu(z) = Phi(z) + z phi(z)."""
+    return 0.5 * (1.0 + erf(z / SQRT2)) + z * INV_SQRT_2PI * np.exp(-0.5 * z * z)
+
+
+def bf16(x) -> np.ndarray:
+    """Round float32 values to the nearest bfloat16 (ties to even); returns float32."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return r.astype(np.uint32).view(np.float32).reshape(f.shape)
+
+
+def forward(params, X):
+    """params = [W1, b1, W2, b2, W3, b3]; X [n][F].  Returns (y, cache)."""
+    W1, b1, W2, b2, W3, b3 = params
+    z1 = X @ W1.T + b1
+    h1 = gelu(z1)
+    z2 = h1 @ W2.T + b2
+    h2 = gelu(z2)
+    y = h2 @ W3.T + b3
+    return y, (X, z1, h1, z2, h2)
+
+
+def predict(params, X) -> np.ndarray:
+    return np.maximum(forward(params, X)[0], 0.0)
+
+
+def loss_and_grads(params, X, T):
+    """MSE loss and its gradients for every parameter (same order as params)."""
+    W1, b1, W2, b2, W3, b3 = params
+    y, (X, z1, h1, z2, h2) = forward(params, X)
+    n, C = y.shape
+    diff = y - T
+    loss = float((diff * diff).sum() / (n * C))
+    dy = 2.0 * diff / (n * C)
+    dW3 = dy.T @ h2
+    db3 = dy.sum(axis=0)
+    dz2 = (dy @ W3) * gelu_grad(z2)
+    dW2 = dz2.T @ h1
+    db2 = dz2.sum(axis=0)
+    dz1 = (dz2 @ W2) * gelu_grad(z1)
+    dW1 = dz1.T @ X
+    db1 = dz1.sum(axis=0)
+    return loss, [dW1, db1, dW2, db2, dW3, db3]
+
+
+class Adam:
+    """Kingma & Ba, Algorithm 1."""
+
+    def __init__(self, params, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.lr, self.b1, self.b2, self.eps = lr, beta1, beta2, eps
+        self.m = [np.zeros_like(p) for p in params]
+        self.v = [np.zeros_like(p) for p in params]
+        self.t = 0
+
+    def step(self, params, grads):
+        self.t += 1
+        out = []
+        for i, (p, g) in enumerate(zip(params, grads)):
+            self.m[i] = self.b1 * self.m[i] + (1.0 - self.b1) * g
+            self.v[i] = self.b2 * self.v[i] + (1.0 - self.b2) * g * g
+            mhat = self.m[i] / (1.0 - self.b1 ** self.t)
+            vhat = self.v[i] / (1.0 - self.b2 ** self.t)
+            out.append(p - self.lr * mhat / (np.sqrt(vhat) + self.eps))
+        return out
+
+
+def init_params(init) -> list:
+    """float64 copies of a synth.MLPInit."""
+    return [init.w[0].astype(np.float64), init.b[0].astype(np.float64),
+            init.w[1].astype(np.float64), init.b[1].astype(np.float64),
+            init.w[2].astype(np.float64), init.b[2].astype(np.float64)]
+
+
+def train(params, X_all, T_all, batches, lr=1e-3):
+    """Adam over the given minibatch index rows; returns (params, losses)."""
+    opt = Adam(params, lr=lr)
+    losses = []
+    for idx in batches:
+        loss, g = loss_and_grads(params, X_all[idx], T_all[idx])
+        losses.append(loss)
+        params = opt.step(params, g)
+    return params, losses

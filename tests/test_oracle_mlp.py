@@ -1,0 +1,89 @@
+"""Oracle pins: the perceptron surrogate's forward, backward, Adam and bf16
+rounding (plain float64; see oracle/mlp.py)."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+
+
+def _toy(seed, F=5, H=7, C=3, n=16):
+    g = np.random.default_rng(seed)
+    params = [g.normal(0, 0.5, (H, F)), g.normal(0, 0.1, H), g.normal(0, 0.5, (H, H)),
+              g.normal(0, 0.1, H), g.normal(0, 0.5, (C, H)), g.normal(0, 0.1, C)]
+    X = g.random((n, F))
+    T = g.random((n, C))
+    return params, X, T
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_backprop_matches_central_differences(seed):
+    params, X, T = _toy(seed)
+    _, grads = M.loss_and_grads(params, X, T)
+    h = 1e-6
+    for i, p in enumerate(params):
+        num = np.zeros_like(p)
+        flat = p.reshape(-1)
+        for j in range(flat.size):
+            old = flat[j]
+            flat[j] = old + h
+            lp, _ = M.loss_and_grads(params, X, T)
+            flat[j] = old - h
+            lm, _ = M.loss_and_grads(params, X, T)
+            flat[j] = old
+            num.reshape(-1)[j] = (lp - lm) / (2 * h)
+        err = np.abs(num - grads[i]).max() / max(1e-12, np.abs(num).max())
+        assert err < 1e-6, (i, err)
+
+
+def test_gelu_closed_forms():
+    x = np.linspace(-6, 6, 241)
+    assert M.gelu(0.0) == 0.0
+    # Phi(x) + Phi(-x) = 1  =>  gelu(x) - gelu(-x) = x
+    assert np.allclose(M.gelu(x) - M.gelu(-x), x, atol=1e-15)
+    assert M.gelu_grad(0.0) == 0.5
+    assert abs(M.gelu(40.0) - 40.0) < 1e-12 and abs(M.gelu(-40.0)) < 1e-12
+    # known value: gelu(1) = Phi(1) = 0.8413447460685429
+    assert abs(M.gelu(1.0) - 0.8413447460685429) < 1e-15
+    h = 1e-6
+    assert np.allclose((M.gelu(x + h) - M.gelu(x - h)) / (2 * h), M.gelu_grad(x), atol=1e-8)
+
+
+def test_adam_first_and_second_step_closed_form():
+    p0 = [np.array([0.5, -1.0, 2.0])]
+    g1 = np.array([0.2, -3.0, 1e-9])
+    g2 = np.array([-0.1, 1.0, 4.0])
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    opt = M.Adam(p0, lr, b1, b2, eps)
+    p1 = opt.step(p0, [g1])[0]
+    # t = 1: mhat = g, vhat = g^2  ->  step = lr * g / (|g| + eps)
+    assert np.allclose(p1, p0[0] - lr * g1 / (np.abs(g1) + eps), rtol=0, atol=1e-15)
+    p2 = opt.step([p1], [g2])[0]
+    m = b1 * (1 - b1) * g1 + (1 - b1) * g2
+    v = b2 * (1 - b2) * g1 ** 2 + (1 - b2) * g2 ** 2
+    mhat, vhat = m / (1 - b1 ** 2), v / (1 - b2 ** 2)
+    assert np.allclose(p2, p1 - lr * mhat / (np.sqrt(vhat) + eps), rtol=0, atol=1e-15)
+
+
+def test_bf16_rounding():
+    vals = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 3.14159265, -2.5, 0.0, 1 + 2.0 ** -7],
+                    dtype=np.float32)
+    # ties to even at 1 + 2^-8; 1 + 3*2^-8 rounds up to 1 + 2^-6; pi -> 3.140625
+    assert M.bf16(vals).tolist() == [1.0, 1.0, 1 + 2.0 ** -6, 3.140625, -2.5, 0.0, 1 + 2.0 ** -7]
+
+
+def test_features_are_exact_eighths():
+    d = np.array([[0, 1, 7, 15]])
+    assert M.features(d).tolist() == [[0.0, 0.125, 0.875, 1.875]]
+    assert (M.bf16(M.features(d).astype(np.float32)) == M.features(d)).all()
+
+
+def test_training_reduces_loss_on_a_smooth_target():
+    g = np.random.default_rng(4)
+    F, H, C = 4, 16, 2
+    X = g.random((512, F))
+    T = np.stack([X @ np.array([1.0, -0.5, 0.25, 0.0]), np.sin(X[:, 0] * 3)], axis=1)
+    params = [g.normal(0, (1 / F) ** 0.5, (H, F)), np.zeros(H), g.normal(0, (1 / H) ** 0.5, (H, H)),
+              np.zeros(H), g.normal(0, (1 / H) ** 0.5, (C, H)), np.zeros(C)]
+    batches = g.integers(0, 512, (300, 64))
+    _, losses = M.train(params, X, T, batches, lr=1e-2)
+    assert np.mean(losses[-20:]) < 0.1 * np.mean(losses[:5])
