@@ -180,6 +180,53 @@ cgs_status cgs_model_copy_leaf_ids(cgs_model model, uint64_t first, uint64_t cou
                                    uint16_t *dst_host);
 void cgs_model_destroy(cgs_model model);
 
+/* Multilayer-perceptron surrogate of the counter model (an extension: it
+ * stands in for the trees of Sect. 3.4).  Features x_j = digit_j / 8 of
+ * every parameter; z1 = W1 x + b1, h1 = gelu(z1), z2 = W2 h1 + b2,
+ * h2 = gelu(z2), y = W3 h2 + b3; predictions max(y, 0).  bf16 weights and
+ * activations, fp32 accumulation (MFMA), fp32 master weights.
+ *   n_in    must equal the space's n_params (<= 32)
+ *   hidden  64, 128, 256 or 512
+ *   n_out   1..64 counters */
+typedef struct {
+  int32_t n_in, hidden, n_out, reserved;
+} cgs_mlp_desc;
+
+/* Adam settings (Kingma & Ba): lr, beta1, beta2, eps; batch rows per step
+ * (1..4096) and number of steps. */
+typedef struct {
+  float lr, beta1, beta2, eps;
+  int32_t batch, steps;
+} cgs_train_opts;
+
+/* Number of fp32 parameters: H*F + H + H*H + H + C*H + C, stored in that
+ * order: W1 [H][F], b1 [H], W2 [H][H], b2 [H], W3 [C][H], b3 [C]. */
+uint64_t cgs_mlp_param_count(const cgs_mlp_desc *desc);
+
+/* Load a perceptron with the given fp32 parameters (layout above) and
+ * predict every valid configuration; Adam moments start at zero. */
+cgs_status cgs_model_load_mlp(cgs_space space, const cgs_mlp_desc *desc, const float *params_host,
+                              cgs_model *out);
+/* opts.steps Adam steps on (configuration, counter) pairs: cfg_raw_host[n]
+ * raw indices (< n_raw), targets_host[n][n_out]; batch_idx_host
+ * [steps][batch] rows of the pairs used by each step.  Loss: mean squared
+ * error over the batch and the counters; loss_host[steps] receives it (may be
+ * NULL).  Afterwards the predictions of every valid configuration are
+ * recomputed.  Synchronises. */
+cgs_status cgs_mlp_train(cgs_model model, const uint32_t *cfg_raw_host, const float *targets_host,
+                         uint64_t n, const int32_t *batch_idx_host, const cgs_train_opts *opts,
+                         float *loss_host);
+/* Loss gradient of every parameter (layout above) on n <= 4096 pairs, without
+ * updating; grads_host[cgs_mlp_param_count], loss_host (may be NULL). */
+cgs_status cgs_mlp_gradients(cgs_model model, const uint32_t *cfg_raw_host,
+                             const float *targets_host, uint32_t n, float *grads_host,
+                             float *loss_host);
+/* Unclamped outputs y of n <= 4096 raw configurations: y_host[n][n_out]. */
+cgs_status cgs_mlp_forward(cgs_model model, const uint32_t *cfg_raw_host, uint32_t n,
+                           float *y_host);
+/* fp32 master parameters (layout above). */
+cgs_status cgs_mlp_copy_params(cgs_model model, float *params_host, uint64_t n);
+
 /* ----------------------------------------------------------- session */
 /* profile_raw value meaning "nothing profiled yet": the step gives every
  * unexplored configuration score 0 (weight 1), so the next draw is the

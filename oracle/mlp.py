@@ -62,6 +62,19 @@ def forward(params, X):
     return y, (X, z1, h1, z2, h2)
 
 
+def forward_bf16(params, X, round_activations: bool = True):
+    """The forward pass with the device's precision choices: weights and the
+    inputs rounded to bf16, biases kept, the hidden activations h1 and h2
+    rounded to bf16; every sum in float64.  Returns y (float64)."""
+    W1, b1, W2, b2, W3, b3 = params
+    w1, w2, w3 = (bf16(w).astype(np.float64) for w in (W1, W2, W3))
+    r = (lambda a: bf16(a).astype(np.float64)) if round_activations else (lambda a: a)
+    x = bf16(X).astype(np.float64)
+    h1 = r(gelu(x @ w1.T + b1))
+    h2 = r(gelu(h1 @ w2.T + b2))
+    return h2 @ w3.T + b3
+
+
 def predict(params, X) -> np.ndarray:
     return np.maximum(forward(params, X)[0], 0.0)
 

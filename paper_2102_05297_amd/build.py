@@ -35,6 +35,7 @@ SOURCES = {
     "enumerate.hip": ["-ffp-contract=off"],
     "forest.hip": ["-ffp-contract=off"],
     "sweep.hip": ["-ffp-contract=off"],
+    "mlp.hip": ["-ffp-contract=fast"],
 }
 
 

@@ -34,7 +34,8 @@ EXPORTS = (
     "cgs_model_copy_leaf_ids", "cgs_model_destroy", "cgs_session_create", "cgs_search_step",
     "cgs_sample_next", "cgs_session_step_info", "cgs_session_kernel_times", "cgs_mark_explored", "cgs_session_copy_scores",
     "cgs_session_copy_weights", "cgs_session_copy_explored", "cgs_session_destroy",
-    "cgs_sample_weights", "cgs_expert_system",
+    "cgs_sample_weights", "cgs_expert_system", "cgs_mlp_param_count", "cgs_model_load_mlp",
+    "cgs_mlp_train", "cgs_mlp_gradients", "cgs_mlp_forward", "cgs_mlp_copy_params",
 )
 
 
@@ -64,6 +65,16 @@ class cgs_expert_params(C.Structure):
 class cgs_step_info(C.Structure):
     _fields_ = [("n_unexplored", C.c_uint64), ("total_weight", C.c_uint64), ("s_min", C.c_float),
                 ("s_max", C.c_float), ("device_ms", C.c_float), ("n_active", C.c_int32)]
+
+
+class cgs_mlp_desc(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("hidden", C.c_int32), ("n_out", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class cgs_train_opts(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("batch", C.c_int32), ("steps", C.c_int32)]
 
 
 _p = C.c_void_p
@@ -110,6 +121,12 @@ _sig("cgs_session_copy_explored", [_p, _p, _u64])
 _sig("cgs_session_destroy", [_p], None)
 _sig("cgs_sample_weights", [_p, _p, _u64, _p, C.c_int, _p])
 _sig("cgs_expert_system", [_p, _ptr(cgs_expert_params), _p, _p, _ptr(C.c_double)])
+_sig("cgs_mlp_param_count", [_ptr(cgs_mlp_desc)], C.c_uint64)
+_sig("cgs_model_load_mlp", [_p, _ptr(cgs_mlp_desc), _p, _ptr(_p)])
+_sig("cgs_mlp_train", [_p, _p, _p, _u64, _p, _ptr(cgs_train_opts), _p])
+_sig("cgs_mlp_gradients", [_p, _p, _p, C.c_uint32, _p, _p])
+_sig("cgs_mlp_forward", [_p, _p, C.c_uint32, _p])
+_sig("cgs_mlp_copy_params", [_p, _p, _u64])
 
 
 def _check(st: int, where: str) -> None:
@@ -224,7 +241,38 @@ class Space:
         self.close()
 
 
-class ForestModel:
+class _Model:
+    """Common part of the model handles (cgs_model)."""
+    h = None
+    space: "Space"
+    n_counters: int
+
+    def eval_ms(self) -> float:
+        n = C.c_int()
+        ms = C.c_float()
+        _check(_lib.cgs_model_info(self.h, C.byref(n), C.byref(ms)), "cgs_model_info")
+        return float(ms.value)
+
+    def refresh(self) -> None:
+        _check(_lib.cgs_model_refresh(self.h), "cgs_model_refresh")
+
+    def copy_predictions(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        count = self.space.n_valid - first if count is None else count
+        out = np.zeros((count, self.n_counters), dtype=np.float32)
+        _check(_lib.cgs_model_copy_predictions(self.h, first, count, _ptrof(out)),
+               "cgs_model_copy_predictions")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _lib.cgs_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class ForestModel(_Model):
     """A regression forest and its cached predictions (cgs_model)."""
 
     def __init__(self, space: Space, feat, thr, leaves):
@@ -243,22 +291,6 @@ class ForestModel:
     def from_spec(cls, space: Space, forest) -> "ForestModel":
         return cls(space, forest.feat, forest.thr, forest.leaves)
 
-    def eval_ms(self) -> float:
-        n = C.c_int()
-        ms = C.c_float()
-        _check(_lib.cgs_model_info(self.h, C.byref(n), C.byref(ms)), "cgs_model_info")
-        return float(ms.value)
-
-    def refresh(self) -> None:
-        _check(_lib.cgs_model_refresh(self.h), "cgs_model_refresh")
-
-    def copy_predictions(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
-        count = self.space.n_valid - first if count is None else count
-        out = np.zeros((count, self.n_counters), dtype=np.float32)
-        _check(_lib.cgs_model_copy_predictions(self.h, first, count, _ptrof(out)),
-               "cgs_model_copy_predictions")
-        return out
-
     def copy_leaf_ids(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         count = self.space.n_valid - first if count is None else count
         out = np.zeros((self.n_trees, count), dtype=np.uint16)
@@ -266,13 +298,72 @@ class ForestModel:
                "cgs_model_copy_leaf_ids")
         return out
 
-    def close(self) -> None:
-        if getattr(self, "h", None):
-            _lib.cgs_model_destroy(self.h)
-            self.h = None
 
-    def __del__(self):
-        self.close()
+def mlp_flatten(params) -> np.ndarray:
+    """[W1, b1, W2, b2, W3, b3] -> the library's fp32 parameter vector."""
+    return np.concatenate([np.asarray(p, dtype=np.float32).ravel() for p in params])
+
+
+class MLPModel(_Model):
+    """The perceptron surrogate (cgs_model): F -> H -> H -> C."""
+
+    def __init__(self, space: Space, params):
+        W1, b1, W2, b2, W3, b3 = params
+        H, F = np.shape(W1)
+        Cn = np.shape(W3)[0]
+        self.desc = cgs_mlp_desc(int(F), int(H), int(Cn), 0)
+        flat = mlp_flatten(params)
+        if flat.size != int(_lib.cgs_mlp_param_count(C.byref(self.desc))):
+            raise ValueError("parameter shapes do not match the perceptron layout")
+        h = C.c_void_p()
+        _check(_lib.cgs_model_load_mlp(space.h, C.byref(self.desc), _ptrof(flat), C.byref(h)),
+               "cgs_model_load_mlp")
+        self.h, self.space = h, space
+        self.F, self.H, self.n_counters = int(F), int(H), int(Cn)
+        self.n_params = flat.size
+
+    def train(self, cfg_raw, targets, batch_idx, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """Adam steps over the rows of batch_idx [steps][batch]; returns the losses."""
+        cfg = _arr(cfg_raw, np.uint32)
+        tg = _arr(targets, np.float32)
+        bi = _arr(batch_idx, np.int32)
+        steps, batch = bi.shape
+        opts = cgs_train_opts(lr, beta1, beta2, eps, batch, steps)
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        _check(_lib.cgs_mlp_train(self.h, _ptrof(cfg), _ptrof(tg), len(cfg), _ptrof(bi),
+                                  C.byref(opts), _ptrof(losses)), "cgs_mlp_train")
+        return losses[:steps]
+
+    def gradients(self, cfg_raw, targets):
+        cfg = _arr(cfg_raw, np.uint32)
+        tg = _arr(targets, np.float32)
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_float()
+        _check(_lib.cgs_mlp_gradients(self.h, _ptrof(cfg), _ptrof(tg), len(cfg), _ptrof(g),
+                                      C.byref(loss)), "cgs_mlp_gradients")
+        return g, float(loss.value)
+
+    def forward(self, cfg_raw) -> np.ndarray:
+        cfg = _arr(cfg_raw, np.uint32)
+        y = np.zeros((len(cfg), self.n_counters), dtype=np.float32)
+        _check(_lib.cgs_mlp_forward(self.h, _ptrof(cfg), len(cfg), _ptrof(y)), "cgs_mlp_forward")
+        return y
+
+    def copy_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(_lib.cgs_mlp_copy_params(self.h, _ptrof(out), self.n_params),
+               "cgs_mlp_copy_params")
+        return out
+
+    def unflatten(self, flat):
+        F, H, Cn = self.F, self.H, self.n_counters
+        sizes = [(H, F), (H,), (H, H), (H,), (Cn, H), (Cn,)]
+        out, o = [], 0
+        for shp in sizes:
+            n = int(np.prod(shp))
+            out.append(np.asarray(flat[o:o + n]).reshape(shp))
+            o += n
+        return out
 
 
 class Session:

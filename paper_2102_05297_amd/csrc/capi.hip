@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -76,14 +77,30 @@ struct cgs_space_s {
 
 struct cgs_model_s {
   cgs_space space = nullptr;
-  int kind = 0; // 0 = forest
+  int kind = 0; // 0 = forest, 1 = perceptron
   int n_counters = 0;
+  float *d_P = nullptr; // predictions [C][stride] of every valid configuration
+  uint64_t stride = 0;
+  float eval_ms = 0.0f;
+  // forest
   int n_trees = 0, depth = 0;
   uint16_t *d_nodes = nullptr;
   float *d_leaves = nullptr;
-  float *d_P = nullptr;
-  uint64_t stride = 0;
-  float eval_ms = 0.0f;
+  // perceptron: fp32 master parameters, Adam moments, gradient, packed bf16
+  MlpShape sh{};
+  uint64_t n_theta = 0;
+  size_t off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
+  float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
+  __bf16 *d_w1p = nullptr, *d_w2p = nullptr, *d_w3p = nullptr;
+  size_t n_w1p = 0, n_w2p = 0, n_w3p = 0;
+  uint64_t adam_t = 0;
+  int n_cu = 256;
+  // training activations for up to scratch_rows rows
+  uint32_t scratch_rows = 0;
+  __bf16 *d_x = nullptr, *d_h1 = nullptr, *d_h2 = nullptr, *d_dyb = nullptr, *d_dz1b = nullptr,
+         *d_dz2b = nullptr;
+  float *d_z1 = nullptr, *d_z2 = nullptr, *d_y = nullptr, *d_dyf = nullptr, *d_dz1f = nullptr,
+        *d_dz2f = nullptr;
 };
 
 struct cgs_session_s {
@@ -355,14 +372,59 @@ extern "C" void cgs_space_destroy(cgs_space sp) { destroy_space(sp); }
 // ------------------------------------------------------------------ model
 namespace {
 
+void free_mlp_scratch(cgs_model m) {
+  dfree(m->d_x);
+  dfree(m->d_h1);
+  dfree(m->d_h2);
+  dfree(m->d_dyb);
+  dfree(m->d_dz1b);
+  dfree(m->d_dz2b);
+  dfree(m->d_z1);
+  dfree(m->d_z2);
+  dfree(m->d_y);
+  dfree(m->d_dyf);
+  dfree(m->d_dz1f);
+  dfree(m->d_dz2f);
+  m->scratch_rows = 0;
+}
+
 void destroy_model(cgs_model m) {
   if (!m) return;
   if (m->space && m->space->stream) (void)hipStreamSynchronize(m->space->stream);
   dfree(m->d_nodes);
   dfree(m->d_leaves);
   dfree(m->d_P);
+  dfree(m->d_theta);
+  dfree(m->d_m);
+  dfree(m->d_v);
+  dfree(m->d_grad);
+  dfree(m->d_w1p);
+  dfree(m->d_w2p);
+  dfree(m->d_w3p);
+  free_mlp_scratch(m);
   destroy_space(m->space);
   delete m;
+}
+
+MlpFwdArgs mlp_args(cgs_model m) {
+  cgs_space sp = m->space;
+  MlpFwdArgs a{};
+  a.sp = sp->d_desc;
+  a.idx = sp->d_idx;
+  a.F = m->sh.F;
+  a.H = m->sh.H;
+  a.C = m->sh.C;
+  a.K1 = m->sh.K1;
+  a.n_cu = m->n_cu;
+  a.w1p = reinterpret_cast<const bf16x8 *>(m->d_w1p);
+  a.w2p = reinterpret_cast<const bf16x8 *>(m->d_w2p);
+  a.w3p = reinterpret_cast<const bf16x8 *>(m->d_w3p);
+  a.b1 = m->d_theta + m->off_b1;
+  a.b2 = m->d_theta + m->off_b2;
+  a.b3 = m->d_theta + m->off_b3;
+  a.P = m->d_P;
+  a.stride = m->stride;
+  return a;
 }
 
 cgs_status evaluate_model(cgs_model m) {
@@ -371,16 +433,23 @@ cgs_status evaluate_model(cgs_model m) {
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, sp->stream));
-  hipError_t e = launch_forest_eval(sp->d_desc, sp->d_idx, (uint32_t)sp->n_valid, m->d_nodes,
-                                    m->d_leaves, m->n_trees, m->depth, m->n_counters, m->d_P,
-                                    m->stride, nullptr, 0, 0, sp->stream);
+  hipError_t e = hipSuccess;
+  if (m->kind == 0) {
+    e = launch_forest_eval(sp->d_desc, sp->d_idx, (uint32_t)sp->n_valid, m->d_nodes, m->d_leaves,
+                           m->n_trees, m->depth, m->n_counters, m->d_P, m->stride, nullptr, 0, 0,
+                           sp->stream);
+  } else {
+    MlpFwdArgs a = mlp_args(m);
+    a.n = (uint32_t)sp->n_valid;
+    e = launch_mlp_forward(a, false, sp->stream);
+  }
   if (e == hipSuccess) e = hipEventRecord(e1, sp->stream);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.0f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (e != hipSuccess) return fail(CGS_EDEVICE, "forest evaluation: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return fail(CGS_EDEVICE, "model evaluation: %s", hipGetErrorString(e));
   m->eval_ms = ms;
   return CGS_OK;
 }
@@ -495,6 +564,310 @@ extern "C" cgs_status cgs_model_copy_leaf_ids(cgs_model m, uint64_t first, uint6
   if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
   dfree(d_out);
   if (e != hipSuccess) return fail(CGS_EDEVICE, "leaf ids: %s", hipGetErrorString(e));
+  return CGS_OK;
+}
+
+// ------------------------------------------------------------ perceptron
+namespace {
+
+bool mlp_desc_ok(const cgs_mlp_desc *d) {
+  return d && d->n_in >= 1 && d->n_in <= 32 &&
+         (d->hidden == 64 || d->hidden == 128 || d->hidden == 256 || d->hidden == 512) &&
+         d->n_out >= 1 && d->n_out <= CGS_MAX_COUNTERS;
+}
+
+uint64_t mlp_count(int F, int H, int C) {
+  return (uint64_t)H * F + H + (uint64_t)H * H + H + (uint64_t)C * H + C;
+}
+
+hipError_t ensure_mlp_scratch(cgs_model m, uint32_t rows) {
+  if (m->scratch_rows >= rows) return hipSuccess;
+  free_mlp_scratch(m);
+  const size_t H = m->sh.H, K1 = m->sh.K1, Cp = (size_t)32 * ((m->sh.C + 31) / 32);
+  hipError_t e = dalloc(&m->d_x, rows * K1);
+  if (e == hipSuccess) e = dalloc(&m->d_h1, rows * H);
+  if (e == hipSuccess) e = dalloc(&m->d_h2, rows * H);
+  if (e == hipSuccess) e = dalloc(&m->d_dyb, rows * Cp);
+  if (e == hipSuccess) e = dalloc(&m->d_dz1b, rows * H);
+  if (e == hipSuccess) e = dalloc(&m->d_dz2b, rows * H);
+  if (e == hipSuccess) e = dalloc(&m->d_z1, rows * H);
+  if (e == hipSuccess) e = dalloc(&m->d_z2, rows * H);
+  if (e == hipSuccess) e = dalloc(&m->d_y, rows * Cp);
+  if (e == hipSuccess) e = dalloc(&m->d_dyf, rows * Cp);
+  if (e == hipSuccess) e = dalloc(&m->d_dz1f, rows * H);
+  if (e == hipSuccess) e = dalloc(&m->d_dz2f, rows * H);
+  if (e != hipSuccess) {
+    free_mlp_scratch(m);
+    return e;
+  }
+  m->scratch_rows = rows;
+  return hipSuccess;
+}
+
+// Forward of n rows (cfg_raw[batch[i]]) storing the activations.
+hipError_t mlp_forward_rows(cgs_model m, const uint32_t *d_cfg, const int32_t *d_batch, uint32_t n) {
+  MlpFwdArgs a = mlp_args(m);
+  a.cfg_raw = d_cfg;
+  a.batch = d_batch;
+  a.n = n;
+  a.xout = m->d_x;
+  a.z1out = m->d_z1;
+  a.z2out = m->d_z2;
+  a.h1out = m->d_h1;
+  a.h2out = m->d_h2;
+  a.yout = m->d_y;
+  return launch_mlp_forward(a, true, m->space->stream);
+}
+
+// Forward + loss + backward of n rows into m->d_grad; loss to *d_loss.
+hipError_t mlp_backward_rows(cgs_model m, const uint32_t *d_cfg, const float *d_targets,
+                             const int32_t *d_batch, uint32_t n, float *d_loss) {
+  hipStream_t st = m->space->stream;
+  const int H = m->sh.H, F = m->sh.F, C = m->sh.C, K1 = m->sh.K1, Cp = 32 * ((C + 31) / 32);
+  hipError_t e = mlp_forward_rows(m, d_cfg, d_batch, n);
+  if (e == hipSuccess)
+    e = launch_mse_grad(m->d_y, Cp, C, (int)n, d_targets, d_batch, m->d_dyf, m->d_dyb, d_loss, st);
+  float *g = m->d_grad;
+  GemmArgs ga{};
+  // dW3 = dY^T H2
+  if (e == hipSuccess) {
+    ga = GemmArgs{C, H, (int)n, m->d_dyb, 1, Cp, m->d_h2, H, 1, g + m->off_w3, nullptr, nullptr, H};
+    e = launch_gemm(ga, 1, 1, 0, st);
+  }
+  // dZ2 = (dY W3) * gelu'(Z2)
+  if (e == hipSuccess) {
+    ga = GemmArgs{(int)n, H, C, m->d_dyb, Cp, 1, m->d_theta + m->off_w3, H, 1, m->d_dz2f,
+                  m->d_dz2b, m->d_z2, H};
+    e = launch_gemm(ga, 1, 0, 1, st);
+  }
+  // dW2 = dZ2^T H1
+  if (e == hipSuccess) {
+    ga = GemmArgs{H, H, (int)n, m->d_dz2b, 1, H, m->d_h1, H, 1, g + m->off_w2, nullptr, nullptr, H};
+    e = launch_gemm(ga, 1, 1, 0, st);
+  }
+  // dZ1 = (dZ2 W2) * gelu'(Z1)
+  if (e == hipSuccess) {
+    ga = GemmArgs{(int)n, H, H, m->d_dz2b, H, 1, m->d_theta + m->off_w2, H, 1, m->d_dz1f,
+                  m->d_dz1b, m->d_z1, H};
+    e = launch_gemm(ga, 1, 0, 1, st);
+  }
+  // dW1 = dZ1^T X
+  if (e == hipSuccess) {
+    ga = GemmArgs{H, F, (int)n, m->d_dz1b, 1, H, m->d_x, K1, 1, g, nullptr, nullptr, F};
+    e = launch_gemm(ga, 1, 1, 0, st);
+  }
+  if (e == hipSuccess)
+    e = launch_bias_grads(m->d_dz1f, m->d_dz2f, m->d_dyf, (int)n, H, C, Cp, g + m->off_b1,
+                          g + m->off_b2, g + m->off_b3, st);
+  return e;
+}
+
+// Uploads host pairs; returns device copies (caller frees).
+hipError_t upload_pairs(cgs_model m, const uint32_t *cfg, const float *targets, uint64_t n,
+                        uint32_t **d_cfg, float **d_t) {
+  hipStream_t st = m->space->stream;
+  hipError_t e = dalloc(d_cfg, n);
+  if (e == hipSuccess && targets) e = dalloc(d_t, n * (size_t)m->sh.C);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(*d_cfg, cfg, n * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && targets)
+    e = hipMemcpyAsync(*d_t, targets, n * (size_t)m->sh.C * sizeof(float), hipMemcpyHostToDevice,
+                       st);
+  return e;
+}
+
+cgs_status check_pairs(cgs_model m, const uint32_t *cfg, const float *targets, uint64_t n) {
+  for (uint64_t i = 0; i < n; ++i)
+    if (cfg[i] >= m->space->n_raw)
+      return fail(CGS_EINVAL, "pair %llu: raw index %u >= n_raw", (unsigned long long)i, cfg[i]);
+  if (targets)
+    for (uint64_t i = 0; i < n * (uint64_t)m->sh.C; ++i)
+      if (!std::isfinite(targets[i])) return fail(CGS_EINVAL, "target %llu not finite",
+                                                  (unsigned long long)i);
+  return CGS_OK;
+}
+
+} // namespace
+
+extern "C" uint64_t cgs_mlp_param_count(const cgs_mlp_desc *d) {
+  return mlp_desc_ok(d) ? mlp_count(d->n_in, d->hidden, d->n_out) : 0;
+}
+
+extern "C" cgs_status cgs_model_load_mlp(cgs_space sp, const cgs_mlp_desc *desc,
+                                         const float *params, cgs_model *out) {
+  if (!out) return fail(CGS_EINVAL, "NULL out");
+  *out = nullptr;
+  if (!sp || !params) return fail(CGS_EINVAL, "NULL argument");
+  if (!mlp_desc_ok(desc))
+    return fail(CGS_ERANGE, "perceptron shape: n_in 1..32, hidden 64/128/256/512, n_out 1..64");
+  if (desc->n_in != sp->n_params)
+    return fail(CGS_EINVAL, "n_in %d must equal the space's %d parameters", desc->n_in,
+                sp->n_params);
+  const uint64_t n = mlp_count(desc->n_in, desc->hidden, desc->n_out);
+  for (uint64_t i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return fail(CGS_EINVAL, "parameter %llu not finite",
+                                               (unsigned long long)i);
+  cgs_model m = new (std::nothrow) cgs_model_s();
+  if (!m) return fail(CGS_ENOMEM, "host allocation");
+  m->space = sp;
+  ++sp->refs;
+  m->kind = 1;
+  m->n_counters = desc->n_out;
+  m->sh = MlpShape{desc->n_in, desc->hidden, desc->n_out, desc->n_in <= 16 ? 16 : 32};
+  m->n_theta = n;
+  const size_t H = desc->hidden, F = desc->n_in, C = desc->n_out;
+  m->off_b1 = H * F;
+  m->off_w2 = m->off_b1 + H;
+  m->off_b2 = m->off_w2 + H * H;
+  m->off_w3 = m->off_b2 + H;
+  m->off_b3 = m->off_w3 + C * H;
+  m->n_w1p = H * m->sh.K1;
+  m->n_w2p = H * H;
+  m->n_w3p = (size_t)32 * ((C + 31) / 32) * H;
+  m->stride = (sp->n_valid + 63) & ~(uint64_t)63;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    m->n_cu = prop.multiProcessorCount;
+  hipStream_t st = sp->stream;
+  hipError_t e = dalloc(&m->d_theta, n);
+  if (e == hipSuccess) e = dalloc(&m->d_m, n);
+  if (e == hipSuccess) e = dalloc(&m->d_v, n);
+  if (e == hipSuccess) e = dalloc(&m->d_grad, n);
+  if (e == hipSuccess) e = dalloc(&m->d_w1p, m->n_w1p);
+  if (e == hipSuccess) e = dalloc(&m->d_w2p, m->n_w2p);
+  if (e == hipSuccess) e = dalloc(&m->d_w3p, m->n_w3p);
+  if (e == hipSuccess) e = dalloc(&m->d_P, (size_t)C * m->stride);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->d_theta, params, n * sizeof(float), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(m->d_m, 0, n * sizeof(float), st);
+  if (e == hipSuccess) e = hipMemsetAsync(m->d_v, 0, n * sizeof(float), st);
+  if (e == hipSuccess) e = hipMemsetAsync(m->d_w1p, 0, m->n_w1p * sizeof(__bf16), st);
+  if (e == hipSuccess) e = hipMemsetAsync(m->d_w3p, 0, m->n_w3p * sizeof(__bf16), st);
+  if (e == hipSuccess) e = hipMemsetAsync(m->d_P, 0, (size_t)C * m->stride * sizeof(float), st);
+  if (e == hipSuccess) e = launch_pack_weights(m->sh, m->d_theta, n, m->d_w1p, m->d_w2p, m->d_w3p, st);
+  if (e != hipSuccess) {
+    destroy_model(m);
+    return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "perceptron buffers: %s",
+                hipGetErrorString(e));
+  }
+  const cgs_status stt = evaluate_model(m);
+  if (stt != CGS_OK) {
+    destroy_model(m);
+    return stt;
+  }
+  *out = m;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_mlp_train(cgs_model m, const uint32_t *cfg, const float *targets,
+                                    uint64_t n, const int32_t *batch_idx,
+                                    const cgs_train_opts *o, float *loss_host) {
+  if (!m || !cfg || !targets || !batch_idx || !o) return fail(CGS_EINVAL, "NULL argument");
+  if (m->kind != 1) return fail(CGS_EINVAL, "not a perceptron model");
+  if (n == 0 || n > 0xffffffffull) return fail(CGS_ERANGE, "need 1 .. 2^32-1 pairs");
+  if (o->batch < 1 || o->batch > 4096 || o->steps < 0)
+    return fail(CGS_ERANGE, "batch must be 1..4096 and steps >= 0");
+  if (!(o->lr > 0.0f) || !(o->beta1 >= 0.0f && o->beta1 < 1.0f) ||
+      !(o->beta2 >= 0.0f && o->beta2 < 1.0f) || !(o->eps > 0.0f))
+    return fail(CGS_EINVAL, "Adam settings out of range");
+  cgs_status cs = check_pairs(m, cfg, targets, n);
+  if (cs != CGS_OK) return cs;
+  const size_t nb = (size_t)o->steps * o->batch;
+  for (size_t i = 0; i < nb; ++i)
+    if (batch_idx[i] < 0 || (uint64_t)batch_idx[i] >= n)
+      return fail(CGS_EINVAL, "batch entry %zu = %d outside the pairs", i, batch_idx[i]);
+  hipStream_t st = m->space->stream;
+  uint32_t *d_cfg = nullptr;
+  float *d_t = nullptr, *d_loss = nullptr;
+  int32_t *d_batch = nullptr;
+  hipError_t e = ensure_mlp_scratch(m, (uint32_t)o->batch);
+  if (e == hipSuccess) e = upload_pairs(m, cfg, targets, n, &d_cfg, &d_t);
+  if (e == hipSuccess) e = dalloc(&d_batch, std::max<size_t>(nb, 1));
+  if (e == hipSuccess) e = dalloc(&d_loss, std::max<int>(o->steps, 1));
+  if (e == hipSuccess && nb)
+    e = hipMemcpyAsync(d_batch, batch_idx, nb * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  for (int s = 0; s < o->steps && e == hipSuccess; ++s) {
+    e = mlp_backward_rows(m, d_cfg, d_t, d_batch + (size_t)s * o->batch, (uint32_t)o->batch,
+                          d_loss + s);
+    if (e != hipSuccess) break;
+    m->adam_t += 1;
+    const double c1 = 1.0 / (1.0 - std::pow((double)o->beta1, (double)m->adam_t));
+    const double c2 = 1.0 / (1.0 - std::pow((double)o->beta2, (double)m->adam_t));
+    e = launch_adam_pack(m->sh, m->d_theta, m->d_m, m->d_v, m->d_grad, m->n_theta, o->lr,
+                         o->beta1, o->beta2, o->eps, (float)c1, (float)c2, m->d_w1p, m->d_w2p,
+                         m->d_w3p, st);
+  }
+  if (e == hipSuccess && loss_host && o->steps > 0)
+    e = hipMemcpyAsync(loss_host, d_loss, o->steps * sizeof(float), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dfree(d_cfg);
+  dfree(d_t);
+  dfree(d_batch);
+  dfree(d_loss);
+  if (e != hipSuccess) return fail(CGS_EDEVICE, "training: %s", hipGetErrorString(e));
+  return evaluate_model(m);
+}
+
+extern "C" cgs_status cgs_mlp_gradients(cgs_model m, const uint32_t *cfg, const float *targets,
+                                        uint32_t n, float *grads, float *loss_host) {
+  if (!m || !cfg || !targets || !grads) return fail(CGS_EINVAL, "NULL argument");
+  if (m->kind != 1) return fail(CGS_EINVAL, "not a perceptron model");
+  if (n < 1 || n > 4096) return fail(CGS_ERANGE, "n must be 1..4096");
+  cgs_status cs = check_pairs(m, cfg, targets, n);
+  if (cs != CGS_OK) return cs;
+  hipStream_t st = m->space->stream;
+  uint32_t *d_cfg = nullptr;
+  float *d_t = nullptr, *d_loss = nullptr;
+  hipError_t e = ensure_mlp_scratch(m, n);
+  if (e == hipSuccess) e = upload_pairs(m, cfg, targets, n, &d_cfg, &d_t);
+  if (e == hipSuccess) e = dalloc(&d_loss, 1);
+  if (e == hipSuccess) e = mlp_backward_rows(m, d_cfg, d_t, nullptr, n, d_loss);
+  float loss = 0.0f;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(grads, m->d_grad, m->n_theta * sizeof(float), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&loss, d_loss, sizeof(float), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dfree(d_cfg);
+  dfree(d_t);
+  dfree(d_loss);
+  if (e != hipSuccess) return fail(CGS_EDEVICE, "gradients: %s", hipGetErrorString(e));
+  if (loss_host) *loss_host = loss;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_mlp_forward(cgs_model m, const uint32_t *cfg, uint32_t n, float *y) {
+  if (!m || !cfg || !y) return fail(CGS_EINVAL, "NULL argument");
+  if (m->kind != 1) return fail(CGS_EINVAL, "not a perceptron model");
+  if (n < 1 || n > 4096) return fail(CGS_ERANGE, "n must be 1..4096");
+  cgs_status cs = check_pairs(m, cfg, nullptr, n);
+  if (cs != CGS_OK) return cs;
+  hipStream_t st = m->space->stream;
+  uint32_t *d_cfg = nullptr;
+  float *d_unused = nullptr;
+  const int Cp = 32 * ((m->sh.C + 31) / 32);
+  std::vector<float> rows((size_t)n * Cp);
+  hipError_t e = ensure_mlp_scratch(m, n);
+  if (e == hipSuccess) e = upload_pairs(m, cfg, nullptr, n, &d_cfg, &d_unused);
+  if (e == hipSuccess) e = mlp_forward_rows(m, d_cfg, nullptr, n);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rows.data(), m->d_y, rows.size() * sizeof(float), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dfree(d_cfg);
+  if (e != hipSuccess) return fail(CGS_EDEVICE, "forward: %s", hipGetErrorString(e));
+  for (uint32_t i = 0; i < n; ++i)
+    for (int c = 0; c < m->sh.C; ++c) y[(size_t)i * m->sh.C + c] = rows[(size_t)i * Cp + c];
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_mlp_copy_params(cgs_model m, float *dst, uint64_t n) {
+  if (!m || !dst) return fail(CGS_EINVAL, "NULL argument");
+  if (m->kind != 1) return fail(CGS_EINVAL, "not a perceptron model");
+  if (n != m->n_theta) return fail(CGS_EINVAL, "model has %llu parameters",
+                                   (unsigned long long)m->n_theta);
+  HIP_TRY(hipMemcpyAsync(dst, m->d_theta, n * sizeof(float), hipMemcpyDeviceToHost,
+                         m->space->stream));
+  HIP_TRY(hipStreamSynchronize(m->space->stream));
   return CGS_OK;
 }
 

@@ -65,6 +65,59 @@ struct DrawResult {
 constexpr uint64_t kNoPick = ~0ull;
 constexpr uint32_t kNoProfile = ~0u; // step prologue: no configuration to mark
 
+// ---- perceptron surrogate
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+// F inputs (one per parameter, padded to K1 = 16 or 32), H hidden units per
+// layer (64, 128, 256 or 512), C outputs (padded to 32 or 64).
+struct MlpShape {
+  int F, H, C, K1;
+};
+
+struct MlpFwdArgs {
+  const SpaceDev *sp;
+  const uint32_t *idx;     // inference: valid raw indices
+  const uint32_t *cfg_raw; // training: raw indices of the pairs
+  const int32_t *batch;    // training: rows of this step (or null: 0..n-1)
+  uint32_t n;
+  int F, H, C, K1, n_cu;
+  const bf16x8 *w1p, *w2p, *w3p;
+  const float *b1, *b2, *b3;
+  float *P;
+  uint64_t stride;
+  __bf16 *xout;
+  float *z1out, *z2out;
+  __bf16 *h1out, *h2out;
+  float *yout;
+};
+
+struct GemmArgs {
+  int M, N, K;
+  const void *A;
+  long a_sm, a_sk;
+  const void *B;
+  long b_sk, b_sn;
+  float *Cf;
+  __bf16 *Cb;
+  const float *Z;
+  long ldc;
+};
+
+hipError_t launch_mlp_forward(const MlpFwdArgs &a, bool train, hipStream_t stream);
+hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipStream_t stream);
+hipError_t launch_mse_grad(const float *Y, int Cp, int C, int n, const float *targets,
+                           const int32_t *batch, float *dYf, __bf16 *dYb, float *loss_out,
+                           hipStream_t stream);
+hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dyf, int n, int H,
+                             int C, int Cp, float *gb1, float *gb2, float *gb3,
+                             hipStream_t stream);
+hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
+                               __bf16 *w2p, __bf16 *w3p, hipStream_t stream);
+hipError_t launch_adam_pack(const MlpShape &sh, float *theta, float *m, float *v,
+                            const float *grad, size_t n, float lr, float b1, float b2, float eps,
+                            float c1, float c2, __bf16 *w1p, __bf16 *w2p, __bf16 *w3p,
+                            hipStream_t stream);
+
 // ---- launchers (each enqueues on `stream`; return hipSuccess or an error)
 hipError_t launch_enumeration(const SpaceDev *d_space, uint32_t n_raw, uint32_t *d_mask,
                               uint32_t *d_tile_count, uint32_t *d_tile_off, uint64_t *d_total,

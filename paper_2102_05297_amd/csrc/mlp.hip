@@ -1,0 +1,546 @@
+// Perceptron surrogate of the counter model: F -> H -> H -> C with GELU,
+// bf16 weights and activations, fp32 accumulation on gfx950 MFMA
+// (v_mfma_f32_32x32x16_bf16), fp32 master weights and Adam moments.
+//
+// Transposed formulation: every layer computes Z^T = W X^T, so weights are
+// the MFMA A operand (rows = output features) and activations the B operand
+// (columns = 32 configurations per wave).  The accumulator of a 32x32 block
+// holds, in lane l and register i, row 8(i/4) + 4(l/32) + (i%4) of column
+// l%32.  Registers 8s'..8s'+7 of a block are therefore exactly the B operand
+// of one 16-deep K step whose k slots 8(l/32) + j map to rows
+// 16s' + 8(j/4) + 4(l/32) + (j%4): the hidden activations never leave
+// registers, provided the next layer's weight columns are stored in that
+// order.  The packed weight arrays hold each A fragment as 64 lanes x 8 bf16:
+//   W1p[r][s][lane][j] = W1[32r + lane%32][16s + 8(lane/32) + j]   (natural)
+//   W2p[r][s][lane][j] = W2[32r + lane%32][kperm(s, lane/32, j)]
+//   W3p[r][s][lane][j] = W3[32r + lane%32][kperm(s, lane/32, j)]
+//   kperm(s, h, j) = 32(s/2) + 16(s%2) + 8(j/4) + 4h + (j%4)
+// GELU uses erf from Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7), far
+// below the bf16 rounding of the activations.
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace cgs {
+
+namespace {
+
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr int kGemmThreads = 256;
+
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Phi(z) and phi(z) = exp(-z^2/2) / sqrt(2 pi); erf by A&S 7.1.26.
+__device__ __forceinline__ void normal_cdf_pdf(float z, float &cdf, float &pdf) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+  const float poly =
+      t * (0.254829592f +
+           t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float e = __expf(-x * x);
+  const float erf_abs = 1.0f - poly * e;
+  cdf = 0.5f * (1.0f + (z >= 0.0f ? erf_abs : -erf_abs));
+  pdf = e * 0.3989422804014327f;
+}
+__device__ __forceinline__ float gelu(float z) {
+  float c, p;
+  normal_cdf_pdf(z, c, p);
+  return z * c;
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+  float c, p;
+  normal_cdf_pdf(z, c, p);
+  return c + z * p;
+}
+
+// ---------------------------------------------------------------- forward
+// TRAIN: configurations cfg_raw[batch[i]] (batch may be null: i), writes
+// X (bf16 [n][K1]), Z1, Z2 (fp32 [n][H]), H1, H2 (bf16 [n][H]) and the
+// unclamped output Y (fp32 [n][Cp]).  Otherwise: the valid configurations
+// idx[0..n) and P[c][l] = max(y_c, 0).
+//
+// H <= 256: layer-1 block r is computed right before layer 2 consumes its
+// two K steps, accumulating all H/32 layer-2 blocks at once.
+// H = 512: each wave first parks its layer-1 output in a private LDS region
+// in fragment order ([r][s'][lane][8] bf16, conflict-free 16-byte reads),
+// then accumulates layer 2 in groups of 8 output blocks.
+// LDSW: packed weights staged in LDS once per workgroup (H <= 256).
+template <int H, int NB3, int S1, bool TRAIN, bool LDSW>
+__global__ __launch_bounds__(LDSW ? 512 : 256) void mlp_forward(MlpFwdArgs a) {
+  constexpr int NB = H / 32;
+  constexpr int S2 = H / 16;
+  constexpr int K1 = 16 * S1;
+  constexpr bool H1_IN_LDS = H > 256;
+  constexpr int G = H1_IN_LDS ? 8 : NB; // layer-2 output blocks per group
+  static_assert(!(LDSW && H1_IN_LDS), "weights and hidden activations cannot both use LDS");
+  extern __shared__ bf16x8 lds[];
+  constexpr int N2 = H * H / 8, N3 = NB3 * 32 * H / 8, N1 = H * K1 / 8;
+  if constexpr (LDSW) {
+    for (int i = threadIdx.x; i < N2; i += blockDim.x) lds[i] = a.w2p[i];
+    for (int i = threadIdx.x; i < N3; i += blockDim.x) lds[N2 + i] = a.w3p[i];
+    for (int i = threadIdx.x; i < N1; i += blockDim.x) lds[N2 + N3 + i] = a.w1p[i];
+    __syncthreads();
+  }
+#define W2F(ix) (LDSW ? lds[(ix)] : a.w2p[(ix)])
+#define W3F(ix) (LDSW ? lds[N2 + (ix)] : a.w3p[(ix)])
+#define W1F(ix) (LDSW ? lds[N2 + N3 + (ix)] : a.w1p[(ix)])
+  const int lane = threadIdx.x & 63, hh = lane >> 5, col = lane & 31;
+  const uint32_t wave_in_block = threadIdx.x / 64;
+  // private hidden-activation region of this wave (H1_IN_LDS): NB * 2 * 64 fragments
+  bf16x8 *h1lds = lds + (size_t)wave_in_block * NB * 2 * 64;
+  const uint32_t waves_per_block = blockDim.x / 64;
+  const uint32_t n_waves = gridDim.x * waves_per_block;
+  const uint32_t n_tiles = (a.n + 31) / 32;
+  for (uint32_t tile = blockIdx.x * waves_per_block + wave_in_block; tile < n_tiles;
+       tile += n_waves) {
+    const uint32_t i = tile * 32 + col;
+    const bool ok = i < a.n;
+    uint32_t raw = 0;
+    if (ok) raw = TRAIN ? a.cfg_raw[a.batch ? (uint32_t)a.batch[i] : i] : a.idx[i];
+    uint64_t lo = 0, hi = 0;
+    if (ok) decode_packed(raw, a.sp, lo, hi);
+    bf16x8 xb[S1];
+#pragma unroll
+    for (int s = 0; s < S1; ++s)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = 16 * s + 8 * hh + j;
+        const float f = (ok && k < a.F) ? (float)digit_of(lo, hi, (uint32_t)k) * 0.125f : 0.0f;
+        xb[s][j] = (__bf16)f;
+        if (TRAIN && ok) a.xout[(size_t)i * K1 + k] = xb[s][j];
+      }
+
+    // layer-1 block r -> its two B fragments for layer 2
+    auto layer1 = [&](int r, bf16x8 &f0, bf16x8 &f1) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int s = 0; s < S1; ++s) acc = mfma(W1F((r * S1 + s) * 64 + lane), xb[s], acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row0 = 32 * r + 8 * q + 4 * hh;
+        const float4 bb = *reinterpret_cast<const float4 *>(a.b1 + row0);
+        const float z[4] = {acc[4 * q] + bb.x, acc[4 * q + 1] + bb.y, acc[4 * q + 2] + bb.z,
+                            acc[4 * q + 3] + bb.w};
+        if (TRAIN && ok)
+          *reinterpret_cast<float4 *>(a.z1out + (size_t)i * H + row0) =
+              make_float4(z[0], z[1], z[2], z[3]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const __bf16 v = (__bf16)gelu(z[t]);
+          if (q < 2) f0[q * 4 + t] = v;
+          else f1[(q - 2) * 4 + t] = v;
+          if (TRAIN && ok) a.h1out[(size_t)i * H + row0 + t] = v;
+        }
+      }
+    };
+
+    if constexpr (H1_IN_LDS) {
+#pragma unroll 2
+      for (int r = 0; r < NB; ++r) {
+        bf16x8 f0, f1;
+        layer1(r, f0, f1);
+        h1lds[(r * 2 + 0) * 64 + lane] = f0;
+        h1lds[(r * 2 + 1) * 64 + lane] = f1;
+      }
+    }
+
+    f32x16 accy[NB3];
+#pragma unroll
+    for (int r3 = 0; r3 < NB3; ++r3) accy[r3] = f32x16{};
+#pragma unroll
+    for (int g = 0; g < NB / G; ++g) {
+      f32x16 acc2[G];
+#pragma unroll
+      for (int gi = 0; gi < G; ++gi) acc2[gi] = f32x16{};
+      // B fragments of layer-2 K steps 2r, 2r+1
+      auto hidden = [&](int r, bf16x8 (&f)[2]) {
+        if constexpr (H1_IN_LDS) {
+          f[0] = h1lds[(r * 2 + 0) * 64 + lane];
+          f[1] = h1lds[(r * 2 + 1) * 64 + lane];
+        } else {
+          layer1(r, f[0], f[1]);
+        }
+      };
+      auto load_w = [&](int r, bf16x8 (&w)[2][G]) {
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int gi = 0; gi < G; ++gi) w[sp][gi] = W2F(((g * G + gi) * S2 + 2 * r + sp) * 64 + lane);
+      };
+      auto multiply = [&](const bf16x8 (&w)[2][G], const bf16x8 (&f)[2]) {
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int gi = 0; gi < G; ++gi) acc2[gi] = mfma(w[sp][gi], f[sp], acc2[gi]);
+      };
+      if constexpr (LDSW) {
+        // LDS fragments: short latency, one K step's fragments at a time
+#pragma unroll 1
+        for (int r = 0; r < NB; ++r) {
+          bf16x8 f[2];
+          hidden(r, f);
+#pragma unroll
+          for (int sp = 0; sp < 2; ++sp) {
+            bf16x8 w[G];
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) w[gi] = W2F(((g * G + gi) * S2 + 2 * r + sp) * 64 + lane);
+#pragma unroll
+            for (int gi = 0; gi < G; ++gi) acc2[gi] = mfma(w[gi], f[sp], acc2[gi]);
+          }
+        }
+      } else {
+        // global fragments: the next K step's loads overlap this step's MFMAs
+        bf16x8 wa[2][G], wb[2][G];
+        load_w(0, wa);
+#pragma unroll 1
+        for (int r = 0; r < NB; r += 2) {
+          bf16x8 f[2];
+          load_w(r + 1, wb);
+          hidden(r, f);
+          multiply(wa, f);
+          if (r + 2 < NB) load_w(r + 2, wa);
+          hidden(r + 1, f);
+          multiply(wb, f);
+        }
+      }
+#pragma unroll
+      for (int gi = 0; gi < G; ++gi) {
+        bf16x8 h2[2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row0 = 32 * (g * G + gi) + 8 * q + 4 * hh;
+          const float4 bb = *reinterpret_cast<const float4 *>(a.b2 + row0);
+          const float z[4] = {acc2[gi][4 * q] + bb.x, acc2[gi][4 * q + 1] + bb.y,
+                              acc2[gi][4 * q + 2] + bb.z, acc2[gi][4 * q + 3] + bb.w};
+          if (TRAIN && ok)
+            *reinterpret_cast<float4 *>(a.z2out + (size_t)i * H + row0) =
+                make_float4(z[0], z[1], z[2], z[3]);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const __bf16 v = (__bf16)gelu(z[t]);
+            h2[q >> 1][(q & 1) * 4 + t] = v;
+            if (TRAIN && ok) a.h2out[(size_t)i * H + row0 + t] = v;
+          }
+        }
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int r3 = 0; r3 < NB3; ++r3)
+            accy[r3] = mfma(W3F((r3 * S2 + 2 * (g * G + gi) + sp) * 64 + lane), h2[sp], accy[r3]);
+      }
+    }
+
+    // output
+#pragma unroll
+    for (int r3 = 0; r3 < NB3; ++r3)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int c = 32 * r3 + 8 * q + 4 * hh + t;
+          if (ok && c < a.C) {
+            const float y = accy[r3][4 * q + t] + a.b3[c];
+            if (TRAIN)
+              a.yout[(size_t)i * (32 * NB3) + c] = y;
+            else
+              a.P[(size_t)c * a.stride + i] = fmaxf(y, 0.0f);
+          }
+        }
+  }
+#undef W2F
+#undef W3F
+#undef W1F
+}
+
+// ------------------------------------------------------------------ GEMM
+// C[M][N] = sum_k A(m, k) B(k, n), bf16 operands (converted on load), fp32
+// accumulation; one 32x32 output tile per wave.  Operands are addressed with
+// arbitrary strides so transposed products need no copies.
+template <typename T> __device__ __forceinline__ __bf16 to_bf16(T v);
+template <> __device__ __forceinline__ __bf16 to_bf16<float>(float v) { return (__bf16)v; }
+template <> __device__ __forceinline__ __bf16 to_bf16<__bf16>(__bf16 v) { return v; }
+
+template <typename TA, typename TB, int EPI>
+__global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g) {
+  const TA *A = static_cast<const TA *>(g.A);
+  const TB *B = static_cast<const TB *>(g.B);
+  const int tiles_n = (g.N + 31) / 32, tiles_m = (g.M + 31) / 32;
+  const int wave = blockIdx.x * (kGemmThreads / 64) + threadIdx.x / 64;
+  if (wave >= tiles_m * tiles_n) return;
+  const int m0 = (wave / tiles_n) * 32, n0 = (wave % tiles_n) * 32;
+  const int lane = threadIdx.x & 63, hh = lane >> 5, c = lane & 31;
+  const int m = m0 + c, n = n0 + c;
+  f32x16 acc = {};
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    bf16x8 af, bf;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + 8 * hh + j;
+      af[j] = (m < g.M && k < g.K) ? to_bf16(A[(size_t)m * g.a_sm + (size_t)k * g.a_sk])
+                                   : (__bf16)0.0f;
+      bf[j] = (n < g.N && k < g.K) ? to_bf16(B[(size_t)k * g.b_sk + (size_t)n * g.b_sn])
+                                   : (__bf16)0.0f;
+    }
+    acc = mfma(af, bf, acc);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = m0 + 8 * (i / 4) + 4 * hh + (i % 4), cl = n0 + c;
+    if (row >= g.M || cl >= g.N) continue;
+    const size_t o = (size_t)row * g.ldc + cl;
+    if (EPI == 0) {
+      g.Cf[o] = acc[i];
+    } else { // dZ = dH * gelu'(Z)
+      const float v = acc[i] * gelu_grad(g.Z[o]);
+      g.Cf[o] = v;
+      g.Cb[o] = (__bf16)v;
+    }
+  }
+}
+
+// ------------------------------------------------------ loss, biases, Adam
+// dY = 2 (Y - T) / (n C) in fp32 and bf16, and the mean squared error.
+__global__ __launch_bounds__(1024) void mse_grad(const float *__restrict__ Y, int Cp, int C, int n,
+                                                 const float *__restrict__ targets,
+                                                 const int32_t *__restrict__ batch,
+                                                 float *__restrict__ dYf, __bf16 *__restrict__ dYb,
+                                                 float *__restrict__ loss_out) {
+  __shared__ float red[16];
+  const float scale = 2.0f / (float)(n * C);
+  float sum = 0.0f;
+  for (int e = threadIdx.x; e < n * Cp; e += 1024) {
+    const int b = e / Cp, cc = e % Cp;
+    float d = 0.0f;
+    if (cc < C) {
+      const int src = batch ? batch[b] : b;
+      d = Y[(size_t)b * Cp + cc] - targets[(size_t)src * C + cc];
+      sum += d * d;
+    }
+    dYf[e] = scale * d;
+    dYb[e] = (__bf16)(scale * d);
+  }
+  sum = wave_sum(sum);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    *loss_out = t / (float)(n * C);
+  }
+}
+
+// Bias gradients: column sums over the batch.
+__global__ __launch_bounds__(256) void bias_grads(const float *__restrict__ dz1,
+                                                  const float *__restrict__ dz2,
+                                                  const float *__restrict__ dyf, int n, int H,
+                                                  int C, int Cp, float *__restrict__ gb1,
+                                                  float *__restrict__ gb2,
+                                                  float *__restrict__ gb3) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < H) {
+    float s = 0.0f;
+    for (int b = 0; b < n; ++b) s += dz1[(size_t)b * H + t];
+    gb1[t] = s;
+  } else if (t < 2 * H) {
+    const int h = t - H;
+    float s = 0.0f;
+    for (int b = 0; b < n; ++b) s += dz2[(size_t)b * H + h];
+    gb2[h] = s;
+  } else if (t < 2 * H + C) {
+    const int c = t - 2 * H;
+    float s = 0.0f;
+    for (int b = 0; b < n; ++b) s += dyf[(size_t)b * Cp + c];
+    gb3[c] = s;
+  }
+}
+
+// Position of master parameter p in the packed bf16 weight arrays, or -1
+// for biases.  which: 1, 2, 3 = W1p, W2p, W3p.
+__device__ __forceinline__ long packed_position(const MlpShape &sh, size_t p, int &which) {
+  const size_t w1 = (size_t)sh.H * sh.F, b1 = sh.H, w2 = (size_t)sh.H * sh.H, b2 = sh.H;
+  const size_t w3 = (size_t)sh.C * sh.H;
+  const int S1 = sh.K1 / 16, S2 = sh.H / 16;
+  if (p < w1) {
+    const int o = (int)(p / sh.F), f = (int)(p % sh.F);
+    const int s = f / 16, kk = f % 16, hh = kk / 8, j = kk % 8;
+    const int lane = hh * 32 + o % 32;
+    which = 1;
+    return ((long)((o / 32) * S1 + s) * 64 + lane) * 8 + j;
+  }
+  p -= w1;
+  if (p < b1) return which = 0, -1;
+  p -= b1;
+  size_t o, k;
+  if (p < w2) {
+    o = p / sh.H;
+    k = p % sh.H;
+    which = 2;
+  } else {
+    p -= w2;
+    if (p < b2) return which = 0, -1;
+    p -= b2;
+    if (p >= w3) return which = 0, -1;
+    o = p / sh.H;
+    k = p % sh.H;
+    which = 3;
+  }
+  const int r = (int)(k / 32), kk = (int)(k % 32), sp = kk / 16, rem = kk % 16;
+  const int hh = (rem % 8) / 4, j = 4 * (rem / 8) + rem % 4;
+  const int lane = hh * 32 + (int)(o % 32);
+  return ((long)((o / 32) * S2 + 2 * r + sp) * 64 + lane) * 8 + j;
+}
+
+__device__ __forceinline__ void pack_one(const MlpShape &sh, size_t p, float v, __bf16 *w1p,
+                                         __bf16 *w2p, __bf16 *w3p) {
+  int which = 0;
+  const long pos = packed_position(sh, p, which);
+  if (which == 1) w1p[pos] = (__bf16)v;
+  else if (which == 2) w2p[pos] = (__bf16)v;
+  else if (which == 3) w3p[pos] = (__bf16)v;
+}
+
+__global__ __launch_bounds__(256) void pack_weights(MlpShape sh, const float *__restrict__ theta,
+                                                    size_t n, __bf16 *w1p, __bf16 *w2p,
+                                                    __bf16 *w3p) {
+  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (p < n) pack_one(sh, p, theta[p], w1p, w2p, w3p);
+}
+
+// Adam (Kingma & Ba, Algorithm 1); c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t).
+__global__ __launch_bounds__(256) void adam_pack(MlpShape sh, float *__restrict__ theta,
+                                                 float *__restrict__ m, float *__restrict__ v,
+                                                 const float *__restrict__ grad, size_t n,
+                                                 float lr, float b1, float b2, float eps, float c1,
+                                                 float c2, __bf16 *w1p, __bf16 *w2p,
+                                                 __bf16 *w3p) {
+  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
+  const float g = grad[p];
+  const float mm = b1 * m[p] + (1.0f - b1) * g;
+  const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+  m[p] = mm;
+  v[p] = vv;
+  const float th = theta[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+  theta[p] = th;
+  pack_one(sh, p, th, w1p, w2p, w3p);
+}
+
+template <int H, int NB3, int S1, bool TRAIN, bool LDSW>
+hipError_t launch_fwd_t(const MlpFwdArgs &a, hipStream_t stream) {
+  const uint32_t n_tiles = (a.n + 31) / 32;
+  if (n_tiles == 0) return hipSuccess;
+  if (LDSW) {
+    const size_t lds = (size_t)(H * H + NB3 * 32 * H + H * 16 * S1) * sizeof(__bf16);
+    static bool attr_set = false;
+    if (!attr_set) {
+      hipError_t e = hipFuncSetAttribute(
+          reinterpret_cast<const void *>(&mlp_forward<H, NB3, S1, TRAIN, LDSW>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    const uint32_t grid = std::min<uint32_t>((n_tiles + 7) / 8, (uint32_t)a.n_cu);
+    hipLaunchKernelGGL((mlp_forward<H, NB3, S1, TRAIN, LDSW>), dim3(grid), dim3(512), lds, stream,
+                       a);
+  } else {
+    // H = 512: each of the 4 waves keeps its layer-1 output in LDS
+    const size_t lds = H > 256 ? (size_t)4 * (H / 32) * 2 * 64 * sizeof(bf16x8) : 0;
+    if (lds > 64 * 1024) {
+      static bool attr_set = false;
+      if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&mlp_forward<H, NB3, S1, TRAIN, LDSW>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+      }
+    }
+    const uint32_t grid = std::min<uint32_t>((n_tiles + 3) / 4, (uint32_t)a.n_cu * 8);
+    hipLaunchKernelGGL((mlp_forward<H, NB3, S1, TRAIN, LDSW>), dim3(grid), dim3(256), lds, stream,
+                       a);
+  }
+  return hipGetLastError();
+}
+
+template <int H, int NB3, int S1>
+hipError_t launch_fwd_h(const MlpFwdArgs &a, bool train, hipStream_t stream) {
+  constexpr size_t lds = (size_t)(H * H + NB3 * 32 * H + H * 16 * S1) * 2;
+  constexpr bool fits = H <= 256 && lds <= 160 * 1024;
+  if (train) return launch_fwd_t<H, NB3, S1, true, false>(a, stream);
+  if (fits) return launch_fwd_t<H, NB3, S1, false, fits>(a, stream);
+  return launch_fwd_t<H, NB3, S1, false, false>(a, stream);
+}
+
+template <int H> hipError_t launch_fwd_nb(const MlpFwdArgs &a, bool train, hipStream_t s) {
+  const int nb3 = (a.C + 31) / 32, s1 = a.K1 / 16;
+  if (nb3 == 1 && s1 == 1) return launch_fwd_h<H, 1, 1>(a, train, s);
+  if (nb3 == 1 && s1 == 2) return launch_fwd_h<H, 1, 2>(a, train, s);
+  if (nb3 == 2 && s1 == 1) return launch_fwd_h<H, 2, 1>(a, train, s);
+  if (nb3 == 2 && s1 == 2) return launch_fwd_h<H, 2, 2>(a, train, s);
+  return hipErrorInvalidValue;
+}
+
+} // namespace
+
+hipError_t launch_mlp_forward(const MlpFwdArgs &a, bool train, hipStream_t stream) {
+  switch (a.H) {
+  case 64: return launch_fwd_nb<64>(a, train, stream);
+  case 128: return launch_fwd_nb<128>(a, train, stream);
+  case 256: return launch_fwd_nb<256>(a, train, stream);
+  case 512: return launch_fwd_nb<512>(a, train, stream);
+  default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipStream_t stream) {
+  const int waves = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+  if (waves == 0) return hipSuccess;
+  const dim3 grid((waves + 3) / 4), block(kGemmThreads);
+#define GEMM_CASE(TA, TB, E)                                                                   \
+  hipLaunchKernelGGL((gemm_bf16<TA, TB, E>), grid, block, 0, stream, g)
+  if (a_bf16 && b_bf16 && epi == 0) GEMM_CASE(__bf16, __bf16, 0);
+  else if (a_bf16 && !b_bf16 && epi == 1) GEMM_CASE(__bf16, float, 1);
+  else if (a_bf16 && !b_bf16 && epi == 0) GEMM_CASE(__bf16, float, 0);
+  else if (a_bf16 && b_bf16 && epi == 1) GEMM_CASE(__bf16, __bf16, 1);
+  else return hipErrorInvalidValue;
+#undef GEMM_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_mse_grad(const float *Y, int Cp, int C, int n, const float *targets,
+                           const int32_t *batch, float *dYf, __bf16 *dYb, float *loss_out,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(mse_grad, dim3(1), dim3(1024), 0, stream, Y, Cp, C, n, targets, batch, dYf,
+                     dYb, loss_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dyf, int n, int H,
+                             int C, int Cp, float *gb1, float *gb2, float *gb3,
+                             hipStream_t stream) {
+  const int total = 2 * H + C;
+  hipLaunchKernelGGL(bias_grads, dim3((total + 255) / 256), dim3(256), 0, stream, dz1, dz2, dyf, n,
+                     H, C, Cp, gb1, gb2, gb3);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
+                               __bf16 *w2p, __bf16 *w3p, hipStream_t stream) {
+  hipLaunchKernelGGL(pack_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh,
+                     theta, n, w1p, w2p, w3p);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_pack(const MlpShape &sh, float *theta, float *m, float *v,
+                            const float *grad, size_t n, float lr, float b1, float b2, float eps,
+                            float c1, float c2, __bf16 *w1p, __bf16 *w2p, __bf16 *w3p,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh, theta,
+                     m, v, grad, n, lr, b1, b2, eps, c1, c2, w1p, w2p, w3p);
+  return hipGetLastError();
+}
+
+} // namespace cgs

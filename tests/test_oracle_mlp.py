@@ -87,3 +87,20 @@ def test_training_reduces_loss_on_a_smooth_target():
     batches = g.integers(0, 512, (300, 64))
     _, losses = M.train(params, X, T, batches, lr=1e-2)
     assert np.mean(losses[-20:]) < 0.1 * np.mean(losses[:5])
+
+
+def test_bf16_forward_reduces_to_plain_forward():
+    params, X, T = _toy(7, F=6, H=16, C=4, n=32)
+    X = M.features(np.random.default_rng(1).integers(0, 8, (32, 6)))
+    pb = [M.bf16(p.astype(np.float32)).astype(np.float64) if i % 2 == 0 else p
+          for i, p in enumerate(params)]
+    # without activation rounding it is the float64 forward of the rounded weights
+    assert np.array_equal(M.forward_bf16(params, X, round_activations=False), M.forward(pb, X)[0])
+    # with it, the output moves by at most the bf16 relative rounding (2^-9) of
+    # each hidden value, propagated through |W3| and |W2|
+    y = M.forward(pb, X)[0]
+    yb = M.forward_bf16(params, X)
+    _, (_, _, h1, _, h2) = M.forward(pb, X)
+    w2, w3 = np.abs(pb[2]), np.abs(pb[4])
+    bound = (np.abs(h2) @ w3.T + (np.abs(h1) @ w2.T) @ w3.T * 1.2) * 2.0 ** -8
+    assert (np.abs(yb - y) <= bound + 1e-12).all()
