@@ -96,6 +96,236 @@ def copy_probe(n_bytes: int = 1 << 30, reps: int = 5) -> dict:
     return {"copy_gbs": gbs, "bytes": n_bytes, "reps": reps, "avg_ms": ms.value / reps}
 
 
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_path(cgs, sp, tree, U, pcs, thr, n_pairs=8192, steps=2000, batch=256, top_pairs=10):
+    """Learned surrogate: train on forest samples + N(0, 0.02) noise, predict
+    every valid configuration, compare with the tree and time both uses."""
+    import synth
+    F_, H, Cn = len(sp.radix), 256, tree.n_counters
+    valid = sp.copy_valid()
+    g = synth.rng(3, 1)
+    pos = synth.uniform_indices(g, n_pairs, sp.n_valid)
+    # targets: tree predictions of the sampled configurations plus noise
+    P_tree_all = tree.copy_predictions()
+    tgt = (P_tree_all[pos] + synth.normal_noise(g, (n_pairs, Cn), 0.02)).astype(np.float32)
+    cfg = valid[pos]
+    init = synth.mlp_init((3, 2), F_, H, Cn)
+    model = cgs.MLPModel(sp, [init.w[0], init.b[0], init.w[1], init.b[1], init.w[2], init.b[2]])
+    batches = synth.minibatches(synth.rng(3, 3), steps, batch, n_pairs)
+    sp.synchronize()
+    t0 = time.perf_counter()
+    losses = model.train(cfg, tgt, batches, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    log(f"mlp: trained {steps} steps in {t_train * 1e3:.1f} ms, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    # inference over every valid configuration (timed over a few refreshes)
+    reps = 5
+    ms = []
+    for _ in range(reps):
+        model.refresh()
+        ms.append(model.eval_ms())
+    inf_ms = float(np.median(ms))
+    flop = 2.0 * (F_ * H + H * H + H * Cn) * sp.n_valid
+    tflops = flop / (inf_ms / 1e3) / 1e12
+    P_mlp = model.copy_predictions()
+    sample = synth.uniform_indices(synth.rng(3, 4), 65536, sp.n_valid)
+    rmse = float(np.sqrt(np.mean((P_mlp[sample].astype(np.float64) - P_tree_all[sample]) ** 2)))
+    # top-10 agreement on the first scoring pairs of the search trajectory
+    agree = []
+    sess_t = cgs.Session(sp)
+    sess_m = cgs.Session(sp)
+    sess_t.search_step(tree, cgs.NO_PROFILE)
+    raw, _ = sess_t.sample_next(int(U[0]))
+    for i in range(top_pairs):
+        ep = cgs.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=CORES_PROFILED,
+                                   threads=float(thr[i]))
+        sess_t.search_step(tree, raw, measured=pcs[i], expert=ep)
+        sess_m.search_step(model, raw, measured=pcs[i], expert=ep)
+        st, sm = sess_t.copy_scores(), sess_m.copy_scores()
+        ex = np.unpackbits(sess_t.copy_explored().view(np.uint8), bitorder="little")[: sp.n_valid]
+        st[ex.astype(bool)] = -np.inf
+        sm[ex.astype(bool)] = -np.inf
+        top_t = set(np.argpartition(-st, 10)[:10].tolist())
+        top_m = set(np.argpartition(-sm, 10)[:10].tolist())
+        agree.append(len(top_t & top_m) / 10.0)
+        raw, _ = sess_t.sample_next(int(U[i + 1]))
+        sess_m.mark_explored(raw)
+    # search throughput with the surrogate's cached predictions
+    K = 20
+    picks, sess = run_search(cgs, sp, model, U, pcs, thr, 2, timing=False)
+    sp.synchronize()
+    t0 = time.perf_counter()
+    picks, sess = run_search(cgs, sp, model, U, pcs, thr, K, timing=False)
+    sp.synchronize()
+    t_steps = time.perf_counter() - t0
+    step_ms = t_steps * 1e3 / K
+    scored = sum(sp.n_valid - i for i in range(1, K + 1)) / K
+    return {
+        "shape": f"{F_}->{H}->{H}->{Cn}",
+        "pairs": n_pairs, "train_steps": steps, "batch": batch,
+        "train_ms": t_train * 1e3, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+        "inference_ms": inf_ms, "inference_configs": sp.n_valid,
+        "inference_tflops": tflops,
+        "mfma_roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_PEAK_TFLOPS,
+                          "unit": "TFLOP/s", "frac": tflops / BF16_PEAK_TFLOPS},
+        "rmse_vs_tree": rmse, "rmse_sample": 65536,
+        "top10_agreement": float(np.mean(agree)), "top10_pairs": top_pairs,
+        "scored_per_s_cached": scored / (step_ms / 1e3),
+        "scored_per_s_eval_in_step": sp.n_valid / ((inf_ms + step_ms) / 1e3),
+    }
+
+
+def batch_path(cgs, n_sess=64, n_steps=10):
+    """64 independent searches (log-uniform 10^4..10^7 raw configurations,
+    8-14 parameters, forests of 8 depth-10 trees over 16 counters) stepped
+    together; compared with stepping the same sessions one by one."""
+    import synth
+    specs = [synth.space_batch(s) for s in range(n_sess)]
+    spaces = [cgs.Space.from_spec(sp) for sp in specs]
+    models = [cgs.ForestModel.from_spec(spc, synth.forest_batch(s, sp))
+              for s, (sp, spc) in enumerate(zip(specs, spaces))]
+    g = synth.rng(4, 3, 0)
+    D = synth.deltas(g, n_steps * n_sess, 16).reshape(n_steps, n_sess, 16)
+    U = synth.uniforms_u64(g, (n_steps + 1) * n_sess).reshape(n_steps + 1, n_sess)
+    n_valid = np.array([spc.n_valid for spc in spaces], dtype=np.int64)
+
+    def run_batch(batch, sessions, timed):
+        prof = [cgs.NO_PROFILE] * n_sess
+        raw, _, _ = batch.step(prof, None, U[0])
+        prof = [int(x) for x in raw]
+        dev = []
+        t0 = time.perf_counter()
+        for k in range(n_steps):
+            raw, _, st = batch.step(prof, D[k], U[k + 1])
+            dev.append(batch.step_ms())
+            prof = [int(x) for x in raw]
+        return time.perf_counter() - t0, dev
+
+    sessions = [cgs.Session(spc) for spc in spaces]
+    batch = cgs.Batch(sessions, models)
+    t_tune = time.perf_counter()
+    sched = batch.autotune(None)
+    t_tune = time.perf_counter() - t_tune
+    run_batch(batch, sessions, False)                       # warm-up run
+    sessions = [cgs.Session(spc) for spc in spaces]
+    batch = cgs.Batch(sessions, models, sched)
+    wall, dev = run_batch(batch, sessions, True)
+    # step k scores every valid configuration but the profile and k earlier picks
+    scored = sum(int((n_valid - np.minimum(n_valid, k + 1)).sum()) for k in range(1, n_steps + 1))
+    # the same steps through the single-session calls, one session after another
+    singles = [cgs.Session(spc) for spc in spaces]
+    prof = []
+    for i in range(n_sess):
+        singles[i].search_step(models[i], cgs.NO_PROFILE)
+        prof.append(singles[i].sample_next(int(U[0][i]))[0])
+    t0 = time.perf_counter()
+    for k in range(n_steps):
+        for i in range(n_sess):
+            singles[i].search_step(models[i], prof[i], delta=D[k][i])
+            prof[i] = singles[i].sample_next(int(U[k + 1][i]))[0]
+    wall_single = time.perf_counter() - t0
+    return {
+        "sessions": n_sess, "steps": n_steps,
+        "raw_total": int(sum(sp.n_raw for sp in specs)), "valid_total": int(n_valid.sum()),
+        "schedule": {"score_grid": sched.score_grid, "weight_grid": sched.weight_grid,
+                     "use_graph": sched.use_graph},
+        "autotune_ms": t_tune * 1e3,
+        "ms_per_batch_step": wall * 1e3 / n_steps,
+        "device_ms_per_batch_step": float(np.median(dev)),
+        "scored_per_s": scored / wall,
+        "ms_per_step_sessions_one_by_one": wall_single * 1e3 / n_steps,
+        "scored_per_s_one_by_one": scored / wall_single,
+    }
+
+
+def online_search(cgs, sp, tree, mlp, n_steps, deltas, U, noise, seed_cfg, seed_tgt, val_sample,
+                  retrain_every=20, threshold=0.05, train_steps=500, batch=256, lr=1e-3,
+                  batch_rng=None):
+    """Search with the surrogate retrained online (an extension): every
+    `retrain_every` steps the perceptron is trained further on the seed pairs
+    plus the pairs the search collected (configuration, counters measured by
+    the synthetic profiler = tree prediction + noise); for the next window the
+    surrogate scores only if its RMSE against the tree over `val_sample` is at
+    most `threshold`, else the tree does.  Returns the per-step log."""
+    import synth
+    cfg = list(np.asarray(seed_cfg, dtype=np.uint32))
+    tgt = list(np.asarray(seed_tgt, dtype=np.float32))
+    rng = batch_rng if batch_rng is not None else synth.rng(5, 9)
+    rmse = mlp.rmse(tree, val_sample)
+    use_mlp = rmse <= threshold
+    log = {"windows": [], "picks": [], "step_ms": [], "retrain_ms": []}
+    log["windows"].append({"step": 0, "rmse": rmse, "model": "mlp" if use_mlp else "tree"})
+    sess = cgs.Session(sp)
+    sess.search_step(tree, cgs.NO_PROFILE)
+    raw, l = sess.sample_next(int(U[0]))
+    log["picks"].append(l)
+    cfg.append(raw)
+    tgt.append(tree.copy_predictions(l, 1)[0] + noise[0])
+    for i in range(1, n_steps + 1):
+        if i % retrain_every == 0:
+            t0 = time.perf_counter()
+            idx = synth.minibatches(rng, train_steps, batch, len(cfg))
+            mlp.train(np.array(cfg, np.uint32), np.array(tgt, np.float32), idx, lr=lr)
+            rmse = mlp.rmse(tree, val_sample)
+            log["retrain_ms"].append((time.perf_counter() - t0) * 1e3)
+            use_mlp = rmse <= threshold
+            log["windows"].append({"step": i, "rmse": rmse, "model": "mlp" if use_mlp else "tree"})
+        t0 = time.perf_counter()
+        sess.search_step(mlp if use_mlp else tree, raw, delta=deltas[i - 1])
+        r = sess.sample_next(int(U[i]))
+        log["step_ms"].append((time.perf_counter() - t0) * 1e3)
+        if r is None:
+            break
+        raw, l = r
+        log["picks"].append(l)
+        cfg.append(raw)
+        tgt.append(tree.copy_predictions(l, 1)[0] + noise[i])
+    return log
+
+
+def online_path(cgs, n_steps=200):
+    """The 16-parameter space (2^14 * 3^8 = 107,495,424 raw configurations),
+    forest of 16 depth-12 trees over 32 counters as the tree model and the
+    synthetic profiler, perceptron 16 -> 512 -> 512 -> 32 retrained online."""
+    import synth
+    spec = synth.space_c5()
+    t0 = time.perf_counter()
+    sp = cgs.Space.from_spec(spec)
+    t_space = time.perf_counter() - t0
+    tree = cgs.ForestModel.from_spec(sp, synth.forest_c5(spec))
+    g = synth.rng(5, 3)
+    C = 32
+    deltas = synth.deltas(g, n_steps, C)
+    U = synth.uniforms_u64(g, n_steps + 1)
+    noise = synth.normal_noise(g, (n_steps + 1, C), 0.02)
+    valid = sp.copy_valid()
+    seed_pos = synth.uniform_indices(synth.rng(5, 4), 8192, sp.n_valid)
+    seed_tgt = np.empty((8192, C), dtype=np.float32)
+    for k in range(0, 8192, 1024):
+        sel = seed_pos[k:k + 1024]
+        seed_tgt[k:k + 1024] = np.stack([tree.copy_predictions(int(l), 1)[0] for l in sel])
+    seed_tgt += synth.normal_noise(synth.rng(5, 5), (8192, C), 0.02)
+    init = synth.mlp_init((5, 6), len(spec.radix), 512, C)
+    mlp = cgs.MLPModel(sp, [init.w[0], init.b[0], init.w[1], init.b[1], init.w[2], init.b[2]])
+    t0 = time.perf_counter()
+    mlp.train(valid[seed_pos], seed_tgt, synth.minibatches(synth.rng(5, 7), 2000, 256, 8192))
+    t_first = time.perf_counter() - t0
+    val_sample = synth.uniform_indices(synth.rng(5, 8), 65536, sp.n_valid)
+    log = online_search(cgs, sp, tree, mlp, n_steps, deltas, U, noise, valid[seed_pos], seed_tgt,
+                        val_sample)
+    inf_ms = mlp.eval_ms()
+    flop = 2.0 * (16 * 512 + 512 * 512 + 512 * C) * sp.n_valid
+    return {
+        "n_raw": sp.n_raw, "n_valid": sp.n_valid, "space_create_ms": t_space * 1e3,
+        "tree_eval_ms": tree.eval_ms(), "mlp_first_train_ms": t_first * 1e3,
+        "mlp_inference_ms": inf_ms, "mlp_inference_tflops": flop / (inf_ms / 1e3) / 1e12,
+        "windows": log["windows"], "retrain_ms_mean": float(np.mean(log["retrain_ms"])),
+        "step_ms_median": float(np.median(log["step_ms"])), "steps": len(log["step_ms"]),
+        "scored_per_s": float(sp.n_valid / (np.median(log["step_ms"]) / 1e3)),
+    }
+
+
 def cpu_baseline(spec, forest, n_steps):
     """The oracle, untouched, on a bounded sample of the workload: the
     configurations with raw index below 2^21 (1/8 of the raw space).  Its
@@ -132,6 +362,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-online", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the sweep runs on a single MI355X "
@@ -202,6 +435,21 @@ def main() -> int:
     probe = copy_probe()
     log(f"copy probe: {probe}")
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_path(cgs)
+        log(f"batch: {batch}")
+
+    online = None
+    if not args.no_online:
+        online = online_path(cgs)
+        log(f"online: {online}")
+
+    mlp = None
+    if not args.no_mlp:
+        mlp = mlp_path(cgs, sp, model, U, pcs, thr)
+        log(f"mlp: {mlp}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")
@@ -242,6 +490,10 @@ def main() -> int:
             "weight_pass": ms[1] / max(1, launches[1]) * 1e3,
             "draw": ms[2] / max(1, launches[2]) * 1e3,
         },
+        "tree_eval_in_step_per_s": n_valid / ((model.eval_ms() + t_total * 1e3 / K) / 1e3),
+        "mlp": mlp,
+        "batch": batch,
+        "online": online,
         "hbm_copy_probe": probe,
         "model_eval_ms": model.eval_ms(),
         "space_create_ms": t_enum * 1e3,

@@ -174,6 +174,11 @@ cgs_status cgs_model_refresh(cgs_model model);
 /* Predictions of valid configurations [first, first+count): dst[count][C]. */
 cgs_status cgs_model_copy_predictions(cgs_model model, uint64_t first, uint64_t count,
                                       float *dst_host);
+/* Root-mean-square difference of two models' predictions (same space, same
+ * counters) over valid indices sample_host[n]: sqrt(mean over the sampled
+ * configurations and the counters of (Pa - Pb)^2), summed in float64. */
+cgs_status cgs_model_rmse(cgs_model a, cgs_model b, const uint32_t *sample_host, uint64_t n,
+                          double *rmse);
 /* Forest only: leaf reached in each tree by valid configurations
  * [first, first+count): dst[n_trees][count] uint16. */
 cgs_status cgs_model_copy_leaf_ids(cgs_model model, uint64_t first, uint64_t count,
@@ -289,6 +294,49 @@ cgs_status cgs_session_copy_weights(cgs_session session, uint64_t first, uint64_
 /* Copy the explored bitmask over valid indices: ceil(n_valid / 32) words. */
 cgs_status cgs_session_copy_explored(cgs_session session, uint32_t *dst_host, uint64_t n_words);
 void cgs_session_destroy(cgs_session session);
+
+/* ---------------------------------------------------------- batches */
+/* Many independent searches stepped together (an extension: the paper tunes
+ * one kernel at a time).  Each step scores, weighs and draws in every member
+ * session with three launches that run over the concatenated per-session
+ * tile lists, replayed from one captured hipGraph. */
+typedef struct cgs_batch_s *cgs_batch;
+
+typedef struct {
+  int32_t score_grid;  /* workgroups of the score pass                     */
+  int32_t weight_grid; /* workgroups of the weight pass                    */
+  int32_t use_graph;   /* 1: replay the step from a captured hipGraph      */
+  int32_t reserved;
+} cgs_batch_schedule;
+
+/* sessions[i] searches its own space with models[i] (same space).  The batch
+ * keeps pointers to both: destroy the batch first.  While stepping through
+ * the batch, the sessions may still be read (copy_scores, step_info, ...) and
+ * drawn from between batch steps.  sched NULL: defaults (grids capped at
+ * 2048 workgroups, graph on). */
+cgs_status cgs_batch_create(int n, const cgs_session *sessions, const cgs_model *models,
+                            const cgs_batch_schedule *sched, cgs_batch *out);
+/* One step in every session: profile_raw_host[n] (CGS_NO_PROFILE allowed),
+ * deltas_host: session i's n_counters changes, concatenated in session
+ * order (may be NULL when no session has a profile), u64_host[n] uniforms.
+ * Outputs per session (may be NULL): raw / valid index of the pick and
+ * CGS_OK or CGS_EEMPTY.  Synchronises. */
+cgs_status cgs_batch_step(cgs_batch batch, const uint64_t *profile_raw_host,
+                          const float *deltas_host, const uint64_t *u64_host,
+                          uint64_t *raw_out_host, uint64_t *valid_out_host,
+                          int32_t *status_out_host);
+/* Device time of the last batch step (ms, HIP events around the launch). */
+cgs_status cgs_batch_step_time(cgs_batch batch, float *ms);
+/* Picks the score and weight grid sizes by timing candidates with HIP events
+ * (score records with every counter active; no draw, the explored sets are
+ * untouched; the sessions' last-step results become unavailable until their
+ * next step).  cache_path (may be NULL): a text file of
+ * "<shape key> -> score_grid weight_grid use_graph" lines, read first and
+ * appended to. */
+cgs_status cgs_batch_autotune(cgs_batch batch, const char *cache_path,
+                              cgs_batch_schedule *chosen);
+cgs_status cgs_batch_set_schedule(cgs_batch batch, const cgs_batch_schedule *sched);
+void cgs_batch_destroy(cgs_batch batch);
 
 /* ------------------------------------------------ standalone sampler */
 /* The draw of Alg. 1 on caller-given integer weights: n_draws consecutive

@@ -36,6 +36,8 @@ EXPORTS = (
     "cgs_session_copy_weights", "cgs_session_copy_explored", "cgs_session_destroy",
     "cgs_sample_weights", "cgs_expert_system", "cgs_mlp_param_count", "cgs_model_load_mlp",
     "cgs_mlp_train", "cgs_mlp_gradients", "cgs_mlp_forward", "cgs_mlp_copy_params",
+    "cgs_batch_create", "cgs_batch_step", "cgs_batch_step_time", "cgs_batch_autotune",
+    "cgs_batch_set_schedule", "cgs_batch_destroy", "cgs_model_rmse",
 )
 
 
@@ -77,6 +79,11 @@ class cgs_train_opts(C.Structure):
                 ("batch", C.c_int32), ("steps", C.c_int32)]
 
 
+class cgs_batch_schedule(C.Structure):
+    _fields_ = [("score_grid", C.c_int32), ("weight_grid", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 _p = C.c_void_p
 _u64 = C.c_uint64
 _i32 = C.c_int32
@@ -108,6 +115,7 @@ _sig("cgs_model_info", [_p, _ptr(C.c_int), _ptr(C.c_float)])
 _sig("cgs_model_refresh", [_p])
 _sig("cgs_model_copy_predictions", [_p, _u64, _u64, _p])
 _sig("cgs_model_copy_leaf_ids", [_p, _u64, _u64, _p])
+_sig("cgs_model_rmse", [_p, _p, _p, _u64, _ptr(C.c_double)])
 _sig("cgs_model_destroy", [_p], None)
 _sig("cgs_session_create", [_p, _ptr(cgs_params), _ptr(_p)])
 _sig("cgs_search_step", [_p, _p, _u64, _p, _p, _ptr(cgs_expert_params)])
@@ -127,6 +135,12 @@ _sig("cgs_mlp_train", [_p, _p, _p, _u64, _p, _ptr(cgs_train_opts), _p])
 _sig("cgs_mlp_gradients", [_p, _p, _p, C.c_uint32, _p, _p])
 _sig("cgs_mlp_forward", [_p, _p, C.c_uint32, _p])
 _sig("cgs_mlp_copy_params", [_p, _p, _u64])
+_sig("cgs_batch_create", [C.c_int, _p, _p, _ptr(cgs_batch_schedule), _ptr(_p)])
+_sig("cgs_batch_step", [_p, _p, _p, _p, _p, _p, _p])
+_sig("cgs_batch_step_time", [_p, _ptr(C.c_float)])
+_sig("cgs_batch_autotune", [_p, C.c_char_p, _ptr(cgs_batch_schedule)])
+_sig("cgs_batch_set_schedule", [_p, _ptr(cgs_batch_schedule)])
+_sig("cgs_batch_destroy", [_p], None)
 
 
 def _check(st: int, where: str) -> None:
@@ -262,6 +276,14 @@ class _Model:
         _check(_lib.cgs_model_copy_predictions(self.h, first, count, _ptrof(out)),
                "cgs_model_copy_predictions")
         return out
+
+    def rmse(self, other: "_Model", sample) -> float:
+        """RMS difference of the two models' predictions over valid indices."""
+        smp = _arr(sample, np.uint32)
+        out = C.c_double()
+        _check(_lib.cgs_model_rmse(self.h, other.h, _ptrof(smp), len(smp), C.byref(out)),
+               "cgs_model_rmse")
+        return float(out.value)
 
     def close(self) -> None:
         if getattr(self, "h", None):
@@ -430,6 +452,53 @@ class Session:
     def close(self) -> None:
         if getattr(self, "h", None):
             _lib.cgs_session_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Batch:
+    """Independent sessions stepped together (cgs_batch)."""
+
+    def __init__(self, sessions, models, schedule: Optional[cgs_batch_schedule] = None):
+        n = len(sessions)
+        hs = (C.c_void_p * n)(*[x.h for x in sessions])
+        hm = (C.c_void_p * n)(*[x.h for x in models])
+        h = C.c_void_p()
+        _check(_lib.cgs_batch_create(n, hs, hm, C.byref(schedule) if schedule else None,
+                                     C.byref(h)), "cgs_batch_create")
+        self.h, self.sessions, self.models, self.n = h, list(sessions), list(models), n
+
+    def step(self, profiles, deltas, uniforms):
+        """(raw[n], valid[n], status[n]); raw/valid are 2^64-1 where status != 0."""
+        pr = _arr([int(p) for p in profiles], np.uint64)
+        d = None if deltas is None else _arr(np.concatenate([np.ravel(x) for x in deltas]), np.float32)
+        u = _arr(uniforms, np.uint64)
+        raw = np.zeros(self.n, dtype=np.uint64)
+        val = np.zeros(self.n, dtype=np.uint64)
+        st = np.zeros(self.n, dtype=np.int32)
+        _check(_lib.cgs_batch_step(self.h, _ptrof(pr), _ptrof(d), _ptrof(u), _ptrof(raw),
+                                   _ptrof(val), _ptrof(st)), "cgs_batch_step")
+        return raw, val, st
+
+    def step_ms(self) -> float:
+        ms = C.c_float()
+        _check(_lib.cgs_batch_step_time(self.h, C.byref(ms)), "cgs_batch_step_time")
+        return float(ms.value)
+
+    def autotune(self, cache_path: Optional[str] = None) -> cgs_batch_schedule:
+        sched = cgs_batch_schedule()
+        _check(_lib.cgs_batch_autotune(self.h, cache_path.encode() if cache_path else None,
+                                       C.byref(sched)), "cgs_batch_autotune")
+        return sched
+
+    def set_schedule(self, sched: cgs_batch_schedule) -> None:
+        _check(_lib.cgs_batch_set_schedule(self.h, C.byref(sched)), "cgs_batch_set_schedule")
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _lib.cgs_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

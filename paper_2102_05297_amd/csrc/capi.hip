@@ -130,6 +130,8 @@ struct cgs_session_s {
   int parity = 0;     // accumulator set of the next launched step
   int cur_acc = 0;    // accumulator set of the last launched step
   bool stepped = false;
+  bool events_valid = false; // ev_begin / ev_end bracket the last step
+  float batch_ms = 0.0f;     // device time of the batch step that ran it, if any
   int n_active = 0;
   uint64_t last_total = 0;
 };
@@ -545,6 +547,40 @@ extern "C" cgs_status cgs_model_copy_predictions(cgs_model m, uint64_t first, ui
   return CGS_OK;
 }
 
+extern "C" cgs_status cgs_model_rmse(cgs_model a, cgs_model b, const uint32_t *sample,
+                                     uint64_t n, double *rmse) {
+  if (!a || !b || !rmse || (!sample && n)) return fail(CGS_EINVAL, "NULL argument");
+  if (a->space != b->space) return fail(CGS_EINVAL, "models predict different spaces");
+  if (a->n_counters != b->n_counters) return fail(CGS_EINVAL, "models differ in counters");
+  if (n == 0 || n > 0xffffffffull) return fail(CGS_ERANGE, "need 1 .. 2^32-1 samples");
+  cgs_space sp = a->space;
+  for (uint64_t i = 0; i < n; ++i)
+    if (sample[i] >= sp->n_valid) return fail(CGS_EINVAL, "sample %llu outside the valid list",
+                                              (unsigned long long)i);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 1024);
+  uint32_t *d_s = nullptr;
+  double *d_part = nullptr;
+  std::vector<double> part(grid);
+  hipError_t e = dalloc(&d_s, n);
+  if (e == hipSuccess) e = dalloc(&d_part, grid);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_s, sample, n * sizeof(uint32_t), hipMemcpyHostToDevice, sp->stream);
+  if (e == hipSuccess)
+    e = launch_sq_diff(a->d_P, b->d_P, a->stride, b->stride, a->n_counters, d_s, (uint32_t)n,
+                       d_part, grid, sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(part.data(), d_part, grid * sizeof(double), hipMemcpyDeviceToHost,
+                       sp->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
+  dfree(d_s);
+  dfree(d_part);
+  if (e != hipSuccess) return fail(CGS_EDEVICE, "rmse: %s", hipGetErrorString(e));
+  double sum = 0.0;
+  for (double v : part) sum += v;
+  *rmse = std::sqrt(sum / ((double)n * a->n_counters));
+  return CGS_OK;
+}
+
 extern "C" cgs_status cgs_model_copy_leaf_ids(cgs_model m, uint64_t first, uint64_t count,
                                               uint16_t *dst) {
   if (!m || (!dst && count)) return fail(CGS_EINVAL, "NULL argument");
@@ -949,6 +985,7 @@ hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
   if (e == hipSuccess && do_draw && timing) e = hipEventRecord(s->ev_k[4], sp->stream);
   if (e == hipSuccess) e = hipEventRecord(s->ev_end, sp->stream);
   if (e != hipSuccess) return e;
+  s->events_valid = true;
   s->step_times_pending = timing;
   s->cur_acc = s->parity;
   s->parity ^= 1;
@@ -1140,8 +1177,8 @@ extern "C" cgs_status cgs_session_step_info(cgs_session s, cgs_step_info *out) {
   out->total_weight = s->last_total;
   out->s_min = a.n_unexplored ? key_to_float(a.min_key) : 0.0f;
   out->s_max = a.n_unexplored ? key_to_float(a.max_key) : 0.0f;
-  float ms = 0.0f;
-  HIP_TRY(hipEventElapsedTime(&ms, s->ev_begin, s->ev_end));
+  float ms = s->batch_ms;
+  if (s->events_valid) HIP_TRY(hipEventElapsedTime(&ms, s->ev_begin, s->ev_end));
   out->device_ms = ms;
   out->n_active = s->n_active;
   return CGS_OK;
@@ -1218,6 +1255,371 @@ extern "C" cgs_status cgs_session_copy_explored(cgs_session s, uint32_t *dst, ui
 }
 
 extern "C" void cgs_session_destroy(cgs_session s) { destroy_session(s); }
+
+// ------------------------------------------------------------------ batch
+struct cgs_batch_s {
+  int n = 0;
+  std::vector<cgs_session> sess;
+  std::vector<cgs_model> models;
+  hipStream_t stream = nullptr;
+  BatchSess *d_sess = nullptr;
+  BatchStep *d_step = nullptr;
+  BatchStep *h_step = nullptr;  // pinned
+  DrawResult *h_res = nullptr;  // pinned, mapped
+  DrawResult *d_res = nullptr;  // device view of h_res
+  uint16_t *d_tile_sess = nullptr, *d_blk_sess = nullptr;
+  uint32_t total_tiles = 0, total_blocks = 0;
+  uint64_t total_valid = 0;
+  int total_counters = 0;
+  cgs_batch_schedule sched{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float last_ms = 0.0f;
+};
+
+namespace {
+
+void drop_graph(cgs_batch b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+void destroy_batch(cgs_batch b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  dfree(b->d_sess);
+  dfree(b->d_step);
+  dfree(b->d_tile_sess);
+  dfree(b->d_blk_sess);
+  if (b->h_step) (void)hipHostFree(b->h_step);
+  if (b->h_res) (void)hipHostFree(b->h_res);
+  if (b->e0) (void)hipEventDestroy(b->e0);
+  if (b->e1) (void)hipEventDestroy(b->e1);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+// Enqueues one batched step (copy of the step records, score, weight, draw).
+hipError_t enqueue_batch(cgs_batch b, bool draw) {
+  hipError_t e = hipMemcpyAsync(b->d_step, b->h_step, (size_t)b->n * sizeof(BatchStep),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = launch_batch_score(b->d_sess, b->d_step, b->d_tile_sess, b->total_tiles,
+                           (uint32_t)b->sched.score_grid, b->stream);
+  if (e == hipSuccess)
+    e = launch_batch_weight(b->d_sess, b->d_step, b->d_blk_sess, b->total_blocks,
+                            (uint32_t)b->sched.weight_grid, b->stream);
+  if (e == hipSuccess && draw) e = launch_batch_draw(b->d_sess, b->d_step, (uint32_t)b->n, b->stream);
+  return e;
+}
+
+hipError_t capture_graph(cgs_batch b) {
+  drop_graph(b);
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const hipError_t ek = enqueue_batch(b, true);
+  e = hipStreamEndCapture(b->stream, &b->graph);
+  if (ek != hipSuccess) return ek;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  return e;
+}
+
+cgs_batch_schedule default_schedule(cgs_batch b) {
+  cgs_batch_schedule s{};
+  s.score_grid = (int32_t)std::min<uint32_t>(std::max<uint32_t>(b->total_tiles, 1), 2048);
+  s.weight_grid = (int32_t)std::min<uint32_t>(std::max<uint32_t>(b->total_blocks, 1), 2048);
+  s.use_graph = 1;
+  return s;
+}
+
+std::string batch_key(cgs_batch b) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "gfx950 n=%d tiles=%u blocks=%u counters=%d", b->n, b->total_tiles,
+           b->total_blocks, b->total_counters);
+  return buf;
+}
+
+} // namespace
+
+extern "C" cgs_status cgs_batch_create(int n, const cgs_session *sessions, const cgs_model *models,
+                                       const cgs_batch_schedule *sched, cgs_batch *out) {
+  if (!out) return fail(CGS_EINVAL, "NULL out");
+  *out = nullptr;
+  if (n < 1 || n > 65535 || !sessions || !models) return fail(CGS_EINVAL, "need 1..65535 sessions");
+  std::vector<BatchSess> desc(n);
+  uint64_t tiles = 0, blocks = 0, valid = 0;
+  int counters = 0;
+  for (int i = 0; i < n; ++i) {
+    cgs_session s = sessions[i];
+    cgs_model m = models[i];
+    if (!s || !m) return fail(CGS_EINVAL, "NULL session or model %d", i);
+    if (m->space != s->space) return fail(CGS_EINVAL, "model %d predicts another space", i);
+    const cgs_status st = flush_pending(s);
+    if (st != CGS_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s->space->stream));
+    BatchSess &d = desc[i];
+    d.P = m->d_P;
+    d.stride = m->stride;
+    d.explored = s->d_explored;
+    d.s = s->d_s;
+    d.bsum = s->d_bsum;
+    d.acc = s->d_acc;
+    d.idx = s->space->d_idx;
+    d.n_valid = (uint32_t)s->space->n_valid;
+    d.n_blocks = s->n_blocks;
+    d.block_log2 = s->block_log2;
+    d.tile0 = (uint32_t)tiles;
+    d.blk0 = (uint32_t)blocks;
+    d.gamma = s->params.gamma;
+    d.w_min = s->params.w_min;
+    tiles += (d.n_valid + kBatchTile - 1) / kBatchTile;
+    blocks += d.n_blocks;
+    valid += d.n_valid;
+    counters += m->n_counters;
+  }
+  if (tiles > 0xffffffffull || blocks > 0xffffffffull)
+    return fail(CGS_ERANGE, "batch too large");
+  cgs_batch b = new (std::nothrow) cgs_batch_s();
+  if (!b) return fail(CGS_ENOMEM, "host allocation");
+  b->n = n;
+  b->sess.assign(sessions, sessions + n);
+  b->models.assign(models, models + n);
+  b->total_tiles = (uint32_t)tiles;
+  b->total_blocks = (uint32_t)blocks;
+  b->total_valid = valid;
+  b->total_counters = counters;
+  std::vector<uint16_t> tile_sess(std::max<uint64_t>(tiles, 1)), blk_sess(std::max<uint64_t>(blocks, 1));
+  for (int i = 0; i < n; ++i) {
+    const uint32_t nt = (desc[i].n_valid + kBatchTile - 1) / kBatchTile;
+    for (uint32_t t = 0; t < nt; ++t) tile_sess[desc[i].tile0 + t] = (uint16_t)i;
+    for (uint32_t t = 0; t < desc[i].n_blocks; ++t) blk_sess[desc[i].blk0 + t] = (uint16_t)i;
+  }
+  hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = dalloc(&b->d_sess, n);
+  if (e == hipSuccess) e = dalloc(&b->d_step, n);
+  if (e == hipSuccess) e = dalloc(&b->d_tile_sess, tile_sess.size());
+  if (e == hipSuccess) e = dalloc(&b->d_blk_sess, blk_sess.size());
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void **>(&b->h_step), (size_t)n * sizeof(BatchStep), 0);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void **>(&b->h_res), (size_t)n * sizeof(DrawResult),
+                      hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&b->d_res), b->h_res, 0);
+  if (e == hipSuccess) e = hipEventCreate(&b->e0);
+  if (e == hipSuccess) e = hipEventCreate(&b->e1);
+  if (e == hipSuccess) {
+    for (int i = 0; i < n; ++i) desc[i].res = b->d_res + i;
+    e = hipMemcpyAsync(b->d_sess, desc.data(), (size_t)n * sizeof(BatchSess), hipMemcpyHostToDevice,
+                       b->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_tile_sess, tile_sess.data(), tile_sess.size() * sizeof(uint16_t),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_blk_sess, blk_sess.data(), blk_sess.size() * sizeof(uint16_t),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    destroy_batch(b);
+    return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "batch buffers: %s",
+                hipGetErrorString(e));
+  }
+  b->sched = sched ? *sched : default_schedule(b);
+  if (b->sched.score_grid < 1 || b->sched.weight_grid < 1) {
+    const cgs_batch_schedule d = default_schedule(b);
+    if (b->sched.score_grid < 1) b->sched.score_grid = d.score_grid;
+    if (b->sched.weight_grid < 1) b->sched.weight_grid = d.weight_grid;
+  }
+  *out = b;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_batch_set_schedule(cgs_batch b, const cgs_batch_schedule *s) {
+  if (!b || !s) return fail(CGS_EINVAL, "NULL argument");
+  if (s->score_grid < 1 || s->weight_grid < 1) return fail(CGS_EINVAL, "grids must be >= 1");
+  b->sched = *s;
+  drop_graph(b);
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_batch_step(cgs_batch b, const uint64_t *profile_raw, const float *deltas,
+                                     const uint64_t *u64, uint64_t *raw_out, uint64_t *valid_out,
+                                     int32_t *status_out) {
+  if (!b || !profile_raw || !u64) return fail(CGS_EINVAL, "NULL argument");
+  size_t doff = 0;
+  for (int i = 0; i < b->n; ++i) {
+    cgs_session s = b->sess[i];
+    cgs_model m = b->models[i];
+    if (s->pending) {
+      const cgs_status st = flush_pending(s);
+      if (st != CGS_OK) return st;
+      HIP_TRY(hipStreamSynchronize(s->space->stream));
+    }
+    BatchStep &st = b->h_step[i];
+    const int C = m->n_counters;
+    st.n_act = 0;
+    if (profile_raw[i] == CGS_NO_PROFILE || s->space->n_valid == 0) {
+      st.profile = kNoProfile;
+    } else {
+      const int64_t l = valid_index_of(s->space, profile_raw[i]);
+      if (l < 0) return fail(CGS_EINVAL, "session %d: profile is not a valid configuration", i);
+      st.profile = (uint32_t)l;
+      if (!deltas) return fail(CGS_EINVAL, "deltas needed for profiled sessions");
+      for (int c = 0; c < C; ++c) {
+        const float d = deltas[doff + c];
+        if (!(d >= -1.0f && d <= 1.0f))
+          return fail(CGS_EINVAL, "session %d: delta[%d] outside [-1, 1]", i, c);
+        if (d != 0.0f) {
+          st.ctr[st.n_act] = (uint32_t)c;
+          st.delta[st.n_act] = d;
+          ++st.n_act;
+        }
+      }
+    }
+    doff += (size_t)C;
+    st.parity = s->parity;
+    st.draw = 1;
+    st.u64 = u64[i];
+  }
+  HIP_TRY(hipEventRecord(b->e0, b->stream));
+  if (b->sched.use_graph) {
+    if (!b->exec) HIP_TRY(capture_graph(b));
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  } else {
+    HIP_TRY(enqueue_batch(b, true));
+  }
+  HIP_TRY(hipEventRecord(b->e1, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipEventElapsedTime(&b->last_ms, b->e0, b->e1));
+  for (int i = 0; i < b->n; ++i) {
+    cgs_session s = b->sess[i];
+    // the session now looks as if it had run this step itself
+    s->cur_acc = s->parity;
+    s->parity ^= 1;
+    s->stepped = true;
+    s->pending = false;
+    s->events_valid = false;
+    s->batch_ms = b->last_ms;
+    s->n_active = b->h_step[i].n_act;
+    DrawResult r;
+    std::memcpy(&r, const_cast<const DrawResult *>(static_cast<volatile DrawResult *>(b->h_res + i)),
+                sizeof r);
+    s->last_total = r.total;
+    int32_t status = CGS_OK;
+    if (r.total == 0) status = CGS_EEMPTY;
+    else if (r.valid == kNoPick) return fail(CGS_EDEVICE, "session %d: no pick although Q > 0", i);
+    if (status_out) status_out[i] = status;
+    if (raw_out) raw_out[i] = status == CGS_OK ? r.raw : kNoPick;
+    if (valid_out) valid_out[i] = status == CGS_OK ? r.valid : kNoPick;
+  }
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_batch_step_time(cgs_batch b, float *ms) {
+  if (!b || !ms) return fail(CGS_EINVAL, "NULL argument");
+  *ms = b->last_ms;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_batch_autotune(cgs_batch b, const char *cache_path,
+                                         cgs_batch_schedule *chosen) {
+  if (!b) return fail(CGS_EINVAL, "NULL batch");
+  const std::string key = batch_key(b);
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "r")) {
+      char line[256];
+      while (fgets(line, sizeof line, f)) {
+        const char *sep = strstr(line, " -> ");
+        if (!sep || std::string(line, sep - line) != key) continue;
+        int sg = 0, wg = 0, ug = 1;
+        if (sscanf(sep + 4, "%d %d %d", &sg, &wg, &ug) == 3 && sg > 0 && wg > 0) {
+          b->sched = cgs_batch_schedule{sg, wg, ug, 0};
+          drop_graph(b);
+          fclose(f);
+          if (chosen) *chosen = b->sched;
+          return CGS_OK;
+        }
+      }
+      fclose(f);
+    }
+  }
+  // timing records: profile 0, every counter active, no draw; accumulator
+  // set = the one the sessions' next step will not use
+  for (int i = 0; i < b->n; ++i) {
+    cgs_session s = b->sess[i];
+    BatchStep &st = b->h_step[i];
+    st.profile = s->space->n_valid > 0 ? 0u : kNoProfile;
+    st.n_act = b->models[i]->n_counters;
+    for (int c = 0; c < st.n_act; ++c) {
+      st.ctr[c] = (uint32_t)c;
+      st.delta[c] = (c & 1) ? -0.5f : 0.5f;
+    }
+    st.parity = s->parity ^ 1;
+    st.draw = 0;
+    st.u64 = 0;
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_step, b->h_step, (size_t)b->n * sizeof(BatchStep),
+                         hipMemcpyHostToDevice, b->stream));
+  auto time_it = [&](bool score, int grid, float &best) -> hipError_t {
+    float total = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+      hipError_t e = hipEventRecord(b->e0, b->stream);
+      if (e == hipSuccess)
+        e = score ? launch_batch_score(b->d_sess, b->d_step, b->d_tile_sess, b->total_tiles,
+                                       (uint32_t)grid, b->stream)
+                  : launch_batch_weight(b->d_sess, b->d_step, b->d_blk_sess, b->total_blocks,
+                                        (uint32_t)grid, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(b->e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b->e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->e0, b->e1);
+      if (e != hipSuccess) return e;
+      if (rep > 0) total = std::min(total, ms); // first run warms caches
+    }
+    best = total;
+    return hipSuccess;
+  };
+  const int cand[] = {128, 256, 512, 1024, 2048, 4096, 8192};
+  cgs_batch_schedule best = default_schedule(b);
+  float best_s = 1e30f, best_w = 1e30f;
+  for (int g : cand) {
+    if ((uint32_t)g > std::max<uint32_t>(b->total_tiles, 1) && g != cand[0]) break;
+    float t;
+    HIP_TRY(time_it(true, g, t));
+    if (t < best_s) {
+      best_s = t;
+      best.score_grid = g;
+    }
+  }
+  for (int g : cand) {
+    if ((uint32_t)g > std::max<uint32_t>(b->total_blocks, 1) && g != cand[0]) break;
+    float t;
+    HIP_TRY(time_it(false, g, t));
+    if (t < best_w) {
+      best_w = t;
+      best.weight_grid = g;
+    }
+  }
+  best.use_graph = 1;
+  b->sched = best;
+  drop_graph(b);
+  // the sessions' last-step results were overwritten
+  for (cgs_session s : b->sess) s->stepped = false;
+  if (cache_path) {
+    if (FILE *f = fopen(cache_path, "a")) {
+      fprintf(f, "%s -> %d %d %d\n", key.c_str(), best.score_grid, best.weight_grid, best.use_graph);
+      fclose(f);
+    }
+  }
+  if (chosen) *chosen = best;
+  return CGS_OK;
+}
+
+extern "C" void cgs_batch_destroy(cgs_batch b) { destroy_batch(b); }
 
 // ------------------------------------------------------- standalone sampler
 extern "C" cgs_status cgs_sample_weights(cgs_space sp, const uint32_t *q, uint64_t n,

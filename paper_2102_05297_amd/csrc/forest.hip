@@ -84,7 +84,37 @@ __global__ __launch_bounds__(kForestThreads) void forest_eval(
   }
 }
 
+// Partial sums of squared prediction differences over sampled valid
+// configurations: one double per workgroup.
+__global__ __launch_bounds__(256) void sq_diff(const float *__restrict__ Pa,
+                                               const float *__restrict__ Pb, uint64_t stride_a,
+                                               uint64_t stride_b, int n_counters,
+                                               const uint32_t *__restrict__ sample, uint32_t n,
+                                               double *__restrict__ partial) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const uint32_t l = sample[i];
+    for (int c = 0; c < n_counters; ++c) {
+      const double d = (double)Pa[(size_t)c * stride_a + l] - (double)Pb[(size_t)c * stride_b + l];
+      acc += d * d;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 } // namespace
+
+hipError_t launch_sq_diff(const float *Pa, const float *Pb, uint64_t stride_a, uint64_t stride_b,
+                          int n_counters, const uint32_t *sample, uint32_t n, double *partial,
+                          uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(sq_diff, dim3(grid), dim3(256), 0, stream, Pa, Pb, stride_a, stride_b,
+                     n_counters, sample, n, partial);
+  return hipGetLastError();
+}
 
 // Evaluates valid configurations [first, first + count).  With d_leaf_out
 // set, also writes leaf ids [T][count] and skips nothing else.

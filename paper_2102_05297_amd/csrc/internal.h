@@ -65,6 +65,43 @@ struct DrawResult {
 constexpr uint64_t kNoPick = ~0ull;
 constexpr uint32_t kNoProfile = ~0u; // step prologue: no configuration to mark
 
+// ---- batched sessions: one descriptor per session (device memory) and one
+// step record per session (refreshed from pinned memory before each step)
+struct BatchSess {
+  const float *P;
+  uint64_t stride;
+  uint32_t *explored;
+  float *s;
+  uint64_t *bsum;
+  StepAcc *acc; // 2 sets of kAccSlots
+  const uint32_t *idx;
+  DrawResult *res;
+  uint32_t n_valid, n_blocks;
+  int32_t block_log2;
+  uint32_t tile0, blk0; // first global score tile / weight block of the session
+  float gamma, w_min;
+  uint32_t pad;
+};
+struct BatchStep {
+  uint32_t profile; // valid index, kNoProfile for none
+  int32_t n_act;
+  int32_t parity;   // accumulator set of this step
+  int32_t draw;     // 0: score and weigh only (timing)
+  uint64_t u64;
+  uint32_t ctr[CGS_MAX_COUNTERS];
+  float delta[CGS_MAX_COUNTERS];
+};
+constexpr uint32_t kBatchTile = 1024; // configurations per score tile
+
+hipError_t launch_batch_score(const BatchSess *d_sess, const BatchStep *d_step,
+                              const uint16_t *d_tile_sess, uint32_t total_tiles, uint32_t grid,
+                              hipStream_t stream);
+hipError_t launch_batch_weight(const BatchSess *d_sess, const BatchStep *d_step,
+                               const uint16_t *d_blk_sess, uint32_t total_blocks, uint32_t grid,
+                               hipStream_t stream);
+hipError_t launch_batch_draw(const BatchSess *d_sess, const BatchStep *d_step, uint32_t n_sess,
+                             hipStream_t stream);
+
 // ---- perceptron surrogate
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 
@@ -130,6 +167,9 @@ hipError_t launch_forest_eval(const SpaceDev *d_space, const uint32_t *d_idx, ui
                               uint16_t *d_leaf_out, uint32_t leaf_first, uint32_t leaf_count,
                               hipStream_t stream);
 
+hipError_t launch_sq_diff(const float *Pa, const float *Pb, uint64_t stride_a, uint64_t stride_b,
+                          int n_counters, const uint32_t *sample, uint32_t n, double *partial,
+                          uint32_t grid, hipStream_t stream);
 hipError_t launch_reset_acc(StepAcc *d_acc, int n, hipStream_t stream);
 hipError_t launch_score_pass(const float *d_P, uint64_t stride, uint32_t profile,
                              const ActiveCounters &act, const uint32_t *d_explored,

@@ -61,78 +61,84 @@ __device__ __forceinline__ StepAccSums reduce_slots(const StepAcc *__restrict__ 
   return shared_sums;
 }
 
-// Scores 4 configurations per thread over tiles of 4 * kScoreThreads
-// configurations, grid-stride, so few workgroups update the accumulators.
-__global__ __launch_bounds__(kScoreThreads) void score_pass(
-    const float *__restrict__ P, uint64_t stride, uint32_t profile, ActiveCounters act,
-    const uint32_t *__restrict__ explored, uint32_t n_valid, float *__restrict__ s_out,
-    StepAcc *__restrict__ acc) {
-  __shared__ uint32_t red[3][kScoreThreads / kWave];
-  uint32_t kmin = 0xffffffffu, kmax = 0u, cnt = 0u;
-  const int n = profile < n_valid ? act.n : 0;
-  const uint32_t n_tiles = (n_valid + 4u * kScoreThreads - 1) / (4u * kScoreThreads);
-  for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const uint32_t l0 = 4u * (tile * kScoreThreads + threadIdx.x);
-    if (l0 >= n_valid) continue;
-    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-    const uint32_t word = explored[l0 >> 5];
-    uint32_t ex4 = (word >> (l0 & 31u)) & 0xfu;
-    // configurations past the end and the profiled one count as explored
-    const uint32_t tail = n_valid - l0;
-    if (tail < 4u) ex4 |= (0xfu << tail) & 0xfu;
-    if (profile - l0 < 4u) ex4 |= 1u << (profile - l0);
-    const float *__restrict__ col = P + l0;
-    for (int j0 = 0; j0 < n; j0 += kRowsInFlight) {
-      float4 x[kRowsInFlight];
-      float av[kRowsInFlight];
+// Scores the 4 configurations of this thread in `tile` (4 * kScoreThreads
+// configurations per tile) and folds the unexplored ones into the running
+// min / max keys and count.  Counters ctr[0..n) with changes delta[].
+__device__ __forceinline__ void score_tile(const float *__restrict__ P, uint64_t stride,
+                                           uint32_t profile, int n, const uint32_t *ctr,
+                                           const float *delta,
+                                           const uint32_t *__restrict__ explored,
+                                           uint32_t n_valid, float *__restrict__ s_out,
+                                           uint32_t tile, uint32_t &kmin, uint32_t &kmax,
+                                           uint32_t &cnt) {
+  const uint32_t l0 = 4u * (tile * kScoreThreads + threadIdx.x);
+  if (l0 >= n_valid) return;
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  const uint32_t word = explored[l0 >> 5];
+  uint32_t ex4 = (word >> (l0 & 31u)) & 0xfu;
+  // configurations past the end and the profiled one count as explored
+  const uint32_t tail = n_valid - l0;
+  if (tail < 4u) ex4 |= (0xfu << tail) & 0xfu;
+  if (profile - l0 < 4u) ex4 |= 1u << (profile - l0);
+  const float *__restrict__ col = P + l0;
+  for (int j0 = 0; j0 < n; j0 += kRowsInFlight) {
+    float4 x[kRowsInFlight];
+    float av[kRowsInFlight];
 #pragma unroll
-      for (int u = 0; u < kRowsInFlight; ++u) {
-        if (j0 + u < n) {
-          const size_t row = (size_t)act.ctr[j0 + u] * stride;
-          x[u] = *reinterpret_cast<const float4 *>(col + row);
-          av[u] = P[row + profile];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kRowsInFlight; ++u) {
-        if (j0 + u < n && av[u] != 0.0f) { // a_p == 0: counter not in PC_used
-          const float ap = av[u];
-          const float d = act.delta[j0 + u];
-          {
-            const float t = (x[u].x - ap) / (ap + x[u].x);
-            s0 = (x[u].x != 0.0f) ? s0 + d * t : s0;
-          }
-          {
-            const float t = (x[u].y - ap) / (ap + x[u].y);
-            s1 = (x[u].y != 0.0f) ? s1 + d * t : s1;
-          }
-          {
-            const float t = (x[u].z - ap) / (ap + x[u].z);
-            s2 = (x[u].z != 0.0f) ? s2 + d * t : s2;
-          }
-          {
-            const float t = (x[u].w - ap) / (ap + x[u].w);
-            s3 = (x[u].w != 0.0f) ? s3 + d * t : s3;
-          }
-        }
+    for (int u = 0; u < kRowsInFlight; ++u) {
+      if (j0 + u < n) {
+        const size_t row = (size_t)ctr[j0 + u] * stride;
+        x[u] = *reinterpret_cast<const float4 *>(col + row);
+        av[u] = P[row + profile];
       }
     }
-    *reinterpret_cast<float4 *>(s_out + l0) = make_float4(s0, s1, s2, s3);
-    const float sv[4] = {s0, s1, s2, s3};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (!((ex4 >> e) & 1u)) {
-        const uint32_t k = float_key(sv[e]);
-        kmin = min(kmin, k);
-        kmax = max(kmax, k);
-        ++cnt;
+    for (int u = 0; u < kRowsInFlight; ++u) {
+      if (j0 + u < n && av[u] != 0.0f) { // a_p == 0: counter not in PC_used
+        const float ap = av[u];
+        const float d = delta[j0 + u];
+        {
+          const float t = (x[u].x - ap) / (ap + x[u].x);
+          s0 = (x[u].x != 0.0f) ? s0 + d * t : s0;
+        }
+        {
+          const float t = (x[u].y - ap) / (ap + x[u].y);
+          s1 = (x[u].y != 0.0f) ? s1 + d * t : s1;
+        }
+        {
+          const float t = (x[u].z - ap) / (ap + x[u].z);
+          s2 = (x[u].z != 0.0f) ? s2 + d * t : s2;
+        }
+        {
+          const float t = (x[u].w - ap) / (ap + x[u].w);
+          s3 = (x[u].w != 0.0f) ? s3 + d * t : s3;
+        }
       }
     }
   }
+  *reinterpret_cast<float4 *>(s_out + l0) = make_float4(s0, s1, s2, s3);
+  const float sv[4] = {s0, s1, s2, s3};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (!((ex4 >> e) & 1u)) {
+      const uint32_t k = float_key(sv[e]);
+      kmin = min(kmin, k);
+      kmax = max(kmax, k);
+      ++cnt;
+    }
+  }
+}
+
+// Block-wide reduction of the min / max keys and count; thread 0 adds them
+// to accumulator slot `slot` (skipped when nothing was unexplored).
+__device__ __forceinline__ void flush_acc(uint32_t kmin, uint32_t kmax, uint32_t cnt,
+                                          StepAcc *slot) {
+  __shared__ uint32_t red[3][kScoreThreads / kWave];
   kmin = wave_umin(kmin);
   kmax = wave_umax(kmax);
   cnt = wave_sum(cnt);
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  __syncthreads();
   if (lane == 0) {
     red[0][wave] = kmin;
     red[1][wave] = kmax;
@@ -146,12 +152,26 @@ __global__ __launch_bounds__(kScoreThreads) void score_pass(
       cnt += red[2][w];
     }
     if (cnt != 0u) {
-      StepAcc *slot = acc + (blockIdx.x & (kAccSlots - 1));
       atomicMin(&slot->min_key, kmin);
       atomicMax(&slot->max_key, kmax);
       atomicAdd(&slot->n_unexplored, cnt);
     }
   }
+}
+
+// Scores 4 configurations per thread over tiles of 4 * kScoreThreads
+// configurations, grid-stride, so few workgroups update the accumulators.
+__global__ __launch_bounds__(kScoreThreads) void score_pass(
+    const float *__restrict__ P, uint64_t stride, uint32_t profile, ActiveCounters act,
+    const uint32_t *__restrict__ explored, uint32_t n_valid, float *__restrict__ s_out,
+    StepAcc *__restrict__ acc) {
+  uint32_t kmin = 0xffffffffu, kmax = 0u, cnt = 0u;
+  const int n = profile < n_valid ? act.n : 0;
+  const uint32_t n_tiles = (n_valid + 4u * kScoreThreads - 1) / (4u * kScoreThreads);
+  for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
+    score_tile(P, stride, profile, n, act.ctr, act.delta, explored, n_valid, s_out, tile, kmin,
+               kmax, cnt);
+  flush_acc(kmin, kmax, cnt, acc + (blockIdx.x & (kAccSlots - 1)));
 }
 
 // Quantised weight of valid index l (0 past the end, for explored
@@ -263,21 +283,15 @@ __device__ void draw_body(const W &wsrc, int block_log2, uint64_t *__restrict__ 
   }
 }
 
-// One workgroup per block of 2^block_log2 configurations: block sums of q.
-__global__ __launch_bounds__(kWeightThreads) void weight_pass(
-    const float *__restrict__ s, const uint32_t *__restrict__ explored, uint32_t n_valid,
-    uint32_t profile, const StepAcc *__restrict__ acc, StepAcc *__restrict__ acc_next,
-    float gamma, float w_min, int block_log2, uint64_t *__restrict__ bsum) {
+// Sum of the quantised weights of block `blk` (2^block_log2 configurations),
+// returned to every thread.
+__device__ __forceinline__ uint64_t weight_block_sum(const float *__restrict__ s,
+                                                     const uint32_t *__restrict__ explored,
+                                                     uint32_t n_valid, uint32_t profile,
+                                                     float s_min, float s_max, float gamma,
+                                                     float w_min, int block_log2, uint32_t blk) {
   __shared__ uint64_t scratch[kWeightThreads / kWave];
-  const StepAccSums a = reduce_slots(acc);
-  const float s_min = key_float(a.min_key), s_max = key_float(a.max_key);
-  if (blockIdx.x == 0 && threadIdx.x < kAccSlots) {
-    // clear the accumulators of the next step
-    acc_next[threadIdx.x].min_key = 0xffffffffu;
-    acc_next[threadIdx.x].max_key = 0u;
-    acc_next[threadIdx.x].n_unexplored = 0u;
-  }
-  const uint32_t base = blockIdx.x << block_log2;
+  const uint32_t base = blk << block_log2;
   const uint32_t end = min(n_valid, base + (1u << block_log2));
   uint64_t sum = 0;
   // 4096 configurations per round: 4 float4 of scores per thread, loaded first
@@ -306,7 +320,27 @@ __global__ __launch_bounds__(kWeightThreads) void weight_pass(
       }
     }
   }
-  const uint64_t total = block_sum<kWeightThreads>(sum, scratch);
+  return block_sum<kWeightThreads>(sum, scratch);
+}
+
+__device__ __forceinline__ void clear_acc(StepAcc *acc_next) {
+  if (threadIdx.x < kAccSlots) {
+    acc_next[threadIdx.x].min_key = 0xffffffffu;
+    acc_next[threadIdx.x].max_key = 0u;
+    acc_next[threadIdx.x].n_unexplored = 0u;
+  }
+}
+
+// One workgroup per block of 2^block_log2 configurations: block sums of q.
+__global__ __launch_bounds__(kWeightThreads) void weight_pass(
+    const float *__restrict__ s, const uint32_t *__restrict__ explored, uint32_t n_valid,
+    uint32_t profile, const StepAcc *__restrict__ acc, StepAcc *__restrict__ acc_next,
+    float gamma, float w_min, int block_log2, uint64_t *__restrict__ bsum) {
+  const StepAccSums a = reduce_slots(acc);
+  const float s_min = key_float(a.min_key), s_max = key_float(a.max_key);
+  if (blockIdx.x == 0) clear_acc(acc_next); // the next step's accumulators
+  const uint64_t total = weight_block_sum(s, explored, n_valid, profile, s_min, s_max, gamma,
+                                          w_min, block_log2, blockIdx.x);
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
@@ -324,6 +358,70 @@ __global__ __launch_bounds__(kDrawThreads) void draw_scores(
   __syncthreads();
   if (threadIdx.x == 0 && mark_profile && profile < n_valid)
     atomicOr(&explored[profile >> 5], 1u << (profile & 31u));
+}
+
+// ------------------------------------------------------------ batched
+// Score tiles of every session, grid-stride over the concatenated tile list;
+// a workgroup flushes its accumulators whenever the session changes.
+__global__ __launch_bounds__(kScoreThreads) void batch_score(const BatchSess *__restrict__ sess,
+                                                             const BatchStep *__restrict__ step,
+                                                             const uint16_t *__restrict__ tile_sess,
+                                                             uint32_t total_tiles) {
+  uint32_t kmin = 0xffffffffu, kmax = 0u, cnt = 0u;
+  uint32_t cur = 0xffffffffu;
+  for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+    const uint32_t si = tile_sess[t];
+    if (si != cur) {
+      if (cur != 0xffffffffu)
+        flush_acc(kmin, kmax, cnt,
+                  sess[cur].acc + step[cur].parity * kAccSlots + (blockIdx.x & (kAccSlots - 1)));
+      kmin = 0xffffffffu;
+      kmax = 0u;
+      cnt = 0u;
+      cur = si;
+    }
+    const BatchSess &d = sess[si];
+    const BatchStep &st = step[si];
+    const int n = st.profile < d.n_valid ? st.n_act : 0;
+    score_tile(d.P, d.stride, st.profile, n, st.ctr, st.delta, d.explored, d.n_valid, d.s,
+               t - d.tile0, kmin, kmax, cnt);
+  }
+  if (cur != 0xffffffffu)
+    flush_acc(kmin, kmax, cnt,
+              sess[cur].acc + step[cur].parity * kAccSlots + (blockIdx.x & (kAccSlots - 1)));
+}
+
+// Weight blocks of every session, grid-stride over the concatenated block list.
+__global__ __launch_bounds__(kWeightThreads) void batch_weight(
+    const BatchSess *__restrict__ sess, const BatchStep *__restrict__ step,
+    const uint16_t *__restrict__ blk_sess, uint32_t total_blocks) {
+  for (uint32_t b = blockIdx.x; b < total_blocks; b += gridDim.x) {
+    const uint32_t si = blk_sess[b];
+    const BatchSess &d = sess[si];
+    const BatchStep &st = step[si];
+    const uint32_t lb = b - d.blk0;
+    const StepAccSums a = reduce_slots(d.acc + st.parity * kAccSlots);
+    if (lb == 0) clear_acc(d.acc + (st.parity ^ 1) * kAccSlots);
+    const uint64_t total =
+        weight_block_sum(d.s, d.explored, d.n_valid, st.profile, key_float(a.min_key),
+                         key_float(a.max_key), d.gamma, d.w_min, d.block_log2, lb);
+    if (threadIdx.x == 0) d.bsum[lb] = total;
+  }
+}
+
+// One workgroup per session: its draw, then its profile is marked explored.
+__global__ __launch_bounds__(kDrawThreads) void batch_draw(const BatchSess *__restrict__ sess,
+                                                           const BatchStep *__restrict__ step) {
+  const BatchSess &d = sess[blockIdx.x];
+  const BatchStep &st = step[blockIdx.x];
+  if (!st.draw) return;
+  const StepAccSums a = reduce_slots(d.acc + st.parity * kAccSlots);
+  ScoreWeights w{d.s, d.explored, d.n_valid, st.profile, key_float(a.min_key),
+                 key_float(a.max_key), d.gamma, d.w_min};
+  draw_body<kDrawThreads>(w, d.block_log2, d.bsum, d.n_blocks, st.u64, d.idx, d.res);
+  __syncthreads();
+  if (threadIdx.x == 0 && st.profile < d.n_valid)
+    atomicOr(&d.explored[st.profile >> 5], 1u << (st.profile & 31u));
 }
 
 // Marks the profiled configuration explored (a step read without a draw).
@@ -414,6 +512,31 @@ hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
   hipLaunchKernelGGL(draw_scores, dim3(1), dim3(kDrawThreads), 0, stream, d_s, d_explored, n_valid,
                      profile, mark_profile ? 1 : 0, d_acc, gamma, w_min, block_log2, d_bsum,
                      n_blocks, u64, d_idx, d_res);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_score(const BatchSess *d_sess, const BatchStep *d_step,
+                              const uint16_t *d_tile_sess, uint32_t total_tiles, uint32_t grid,
+                              hipStream_t stream) {
+  if (total_tiles == 0 || grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_score, dim3(grid), dim3(kScoreThreads), 0, stream, d_sess, d_step,
+                     d_tile_sess, total_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_weight(const BatchSess *d_sess, const BatchStep *d_step,
+                               const uint16_t *d_blk_sess, uint32_t total_blocks, uint32_t grid,
+                               hipStream_t stream) {
+  if (total_blocks == 0 || grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_weight, dim3(grid), dim3(kWeightThreads), 0, stream, d_sess, d_step,
+                     d_blk_sess, total_blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_draw(const BatchSess *d_sess, const BatchStep *d_step, uint32_t n_sess,
+                             hipStream_t stream) {
+  if (n_sess == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_draw, dim3(n_sess), dim3(kDrawThreads), 0, stream, d_sess, d_step);
   return hipGetLastError();
 }
 
