@@ -95,8 +95,11 @@ typedef struct {
   float w_min;       /* smallest weight of an unexplored configuration      */
   int32_t block_log2; /* configurations per weight block = 2^block_log2,
                           12..20; 0 = automatic                              */
-  int32_t timing;     /* non-zero: time every kernel of every step with HIP
-                         events (cgs_session_kernel_times)                  */
+  int32_t timing;     /* k > 0: time the kernels of every k-th step (steps
+                         0, k, 2k, ... in launch order, with any further
+                         draws of those steps) with HIP events; each timed
+                         step pays a few microseconds for its event markers
+                         (cgs_session_kernel_times); 0: no timing           */
 } cgs_params;
 
 /* Expert-system settings (Sect. 3.5). */
@@ -114,7 +117,10 @@ typedef struct {
   uint64_t n_unexplored; /* valid configurations not yet explored          */
   uint64_t total_weight; /* Q: sum of quantised weights at the last draw   */
   float s_min, s_max;    /* extreme scores over unexplored configurations */
-  float device_ms;       /* device time of the step's kernels (hipEvents) */
+  float device_ms;       /* device time from the score pass to the end of the
+                            first draw of the last timed step (hipEvents); the
+                            batch step's time for a step run in a batch; 0
+                            without timing                                  */
   int32_t n_active;      /* counters that entered the score               */
 } cgs_step_info;
 
@@ -276,8 +282,8 @@ cgs_status cgs_sample_next(cgs_session session, uint64_t u64, uint64_t *raw_out,
 /* Statistics of the last step (synchronises). */
 cgs_status cgs_session_step_info(cgs_session session, cgs_step_info *out);
 
-/* Device time per kernel kind, summed since session creation (sessions
- * created with params.timing != 0; zeros otherwise):
+/* Device time per kernel kind, summed over the timed launches since session
+ * creation (sessions created with params.timing > 0; zeros otherwise):
  *   total_ms[4] / launches[4]: [0] score pass, [1] weight pass, [2] draws,
  *   [3] reserved (0).  Synchronises. */
 cgs_status cgs_session_kernel_times(cgs_session session, double *total_ms, uint64_t *launches);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstdarg>
@@ -103,6 +104,16 @@ struct cgs_model_s {
         *d_dz2f = nullptr;
 };
 
+constexpr uint32_t kTimeEvents = 512; // event markers of 128 timed steps
+
+// Launches between consecutive markers t_ev[ev .. ev + n]: kernel k runs
+// between markers ev + k and ev + k + 1.
+struct TimedSpan {
+  uint32_t ev;
+  int n;
+  int kind[3]; // 0 score, 1 weight, 2 draw, 3 profile mark
+};
+
 struct cgs_session_s {
   cgs_space space = nullptr;
   cgs_params params{};
@@ -115,11 +126,16 @@ struct cgs_session_s {
   DrawResult *d_res = nullptr;
   DrawResult *h_res = nullptr; // pinned
   StepAcc *h_acc = nullptr;    // pinned, [kAccSlots]
-  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
-  // timing mode: [0] before score, [1] after score, [2] after weights + first
-  // draw, [3] before a further draw, [4] after it
-  hipEvent_t ev_k[5] = {};
-  bool step_times_pending = false;
+  // timing mode: event markers (timing only, no system-scope fence) around
+  // the kernels of every params.timing-th step, summed when the pool is
+  // full or when times are read, so reading them costs the step loop nothing
+  std::vector<hipEvent_t> t_ev; // kTimeEvents markers
+  uint32_t t_ev_used = 0;
+  std::vector<TimedSpan> t_spans;
+  int32_t t_step = -1;  // span of the last timed step, -1 once summed
+  float step_ms = 0.0f; // score start to first draw end of the last timed step
+  uint64_t n_launched = 0; // steps launched so far
+  bool step_timed = false; // the last launched step is timed
   double kernel_ms[4] = {0, 0, 0, 0};
   uint64_t kernel_n[4] = {0, 0, 0, 0};
   // the recorded step, launched with its first draw (or when results are read)
@@ -130,8 +146,9 @@ struct cgs_session_s {
   int parity = 0;     // accumulator set of the next launched step
   int cur_acc = 0;    // accumulator set of the last launched step
   bool stepped = false;
-  bool events_valid = false; // ev_begin / ev_end bracket the last step
-  float batch_ms = 0.0f;     // device time of the batch step that ran it, if any
+  bool ran_in_batch = false; // the last step ran inside a batch step
+  float batch_ms = 0.0f;     // device time of that batch step
+  uint64_t seq = 0;          // sequence number of the last launched draw
   int n_active = 0;
   uint64_t last_total = 0;
 };
@@ -921,9 +938,7 @@ void destroy_session(cgs_session s) {
   dfree(s->d_acc);
   if (s->h_res) (void)hipHostFree(s->h_res);
   if (s->h_acc) (void)hipHostFree(s->h_acc);
-  if (s->ev_begin) (void)hipEventDestroy(s->ev_begin);
-  if (s->ev_end) (void)hipEventDestroy(s->ev_end);
-  for (hipEvent_t &ev : s->ev_k)
+  for (hipEvent_t ev : s->t_ev)
     if (ev) (void)hipEventDestroy(ev);
   destroy_space(s->space);
   delete s;
@@ -936,19 +951,70 @@ int auto_block_log2(uint64_t n_valid) {
   return lg;
 }
 
-// Adds the score / weight times of the last launched step.
-hipError_t collect_step_times(cgs_session s) {
-  hipError_t e = hipEventSynchronize(s->ev_k[2]);
-  float ms[2] = {0, 0};
-  for (int i = 0; i < 2 && e == hipSuccess; ++i)
-    e = hipEventElapsedTime(&ms[i], s->ev_k[i], s->ev_k[i + 1]);
+// Starts a timed span of `n` kernels: reserves n + 1 markers (summing and
+// emptying the pool first when it is full) and records the first.
+hipError_t begin_span(cgs_session s, int n, const int *kinds, TimedSpan **out);
+
+// Sums the durations of every recorded span and empties the pool.
+hipError_t collect_times(cgs_session s) {
+  if (s->t_spans.empty()) return hipSuccess;
+  hipError_t e = hipEventSynchronize(s->t_ev[s->t_ev_used - 1]);
+  for (const TimedSpan &sp : s->t_spans) {
+    for (int k = 0; k < sp.n && e == hipSuccess; ++k) {
+      float ms = 0.0f;
+      e = hipEventElapsedTime(&ms, s->t_ev[sp.ev + k], s->t_ev[sp.ev + k + 1]);
+      if (e == hipSuccess && sp.kind[k] <= 2) {
+        s->kernel_ms[sp.kind[k]] += ms;
+        s->kernel_n[sp.kind[k]] += 1;
+      }
+    }
+  }
+  if (e == hipSuccess && s->t_step >= 0) {
+    const TimedSpan &st = s->t_spans[s->t_step];
+    e = hipEventElapsedTime(&s->step_ms, s->t_ev[st.ev], s->t_ev[st.ev + st.n]);
+  }
   if (e != hipSuccess) return e;
-  s->kernel_ms[0] += ms[0];
-  s->kernel_ms[1] += ms[1];
-  s->kernel_n[0] += 1;
-  s->kernel_n[1] += 1;
-  s->step_times_pending = false;
+  s->t_step = -1;
+  s->t_spans.clear();
+  s->t_ev_used = 0;
   return hipSuccess;
+}
+
+hipError_t begin_span(cgs_session s, int n, const int *kinds, TimedSpan **out) {
+  hipError_t e = hipSuccess;
+  if (s->t_ev_used + n + 1 > kTimeEvents) e = collect_times(s);
+  if (e != hipSuccess) return e;
+  TimedSpan sp{s->t_ev_used, n, {0, 0, 0}};
+  for (int k = 0; k < n; ++k) sp.kind[k] = kinds[k];
+  s->t_ev_used += (uint32_t)n + 1;
+  s->t_spans.push_back(sp);
+  *out = &s->t_spans.back();
+  return hipEventRecord(s->t_ev[sp.ev], s->space->stream);
+}
+
+// Records the marker after kernel k of a span.
+hipError_t mark_span(cgs_session s, const TimedSpan *sp, int k) {
+  return hipEventRecord(s->t_ev[sp->ev + k + 1], s->space->stream);
+}
+
+// Waits for the draw numbered s->seq.  The draw publishes its result in
+// pinned memory before its kernel ends, so the host polls that instead of
+// sleeping on the stream; past kSpinLimit it waits for the stream, and a
+// draw that still has not published is an error.
+cgs_status wait_draw(cgs_session s, const DrawResult *res, uint64_t seq) {
+  constexpr auto kSpinLimit = std::chrono::milliseconds(5);
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t it = 0;; ++it) {
+    if (__atomic_load_n(&res->seq, __ATOMIC_ACQUIRE) == seq) return CGS_OK;
+    if ((it & 1023u) == 1023u && std::chrono::steady_clock::now() - t0 > kSpinLimit) break;
+#if defined(__x86_64__) && !defined(__HIP_DEVICE_COMPILE__)
+    __builtin_ia32_pause();
+#endif
+  }
+  HIP_TRY(hipStreamSynchronize(s->space->stream));
+  if (__atomic_load_n(&res->seq, __ATOMIC_ACQUIRE) != seq)
+    return fail(CGS_EDEVICE, "draw %llu did not publish its result", (unsigned long long)seq);
+  return CGS_OK;
 }
 
 // Enqueues the recorded step: score pass, weight pass, and either its first
@@ -957,36 +1023,38 @@ hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
   cgs_space sp = s->space;
   cgs_model m = s->pending_model;
   const uint32_t nv = (uint32_t)sp->n_valid;
-  const bool timing = s->params.timing != 0;
-  hipError_t e = hipSuccess;
-  if (timing && s->step_times_pending) e = collect_step_times(s);
   StepAcc *acc = s->d_acc + s->parity * kAccSlots;
   StepAcc *acc_next = s->d_acc + (s->parity ^ 1) * kAccSlots;
   const uint32_t prof = s->pending_profile;
-  if (e == hipSuccess) e = hipEventRecord(s->ev_begin, sp->stream);
-  if (e == hipSuccess && timing) e = hipEventRecord(s->ev_k[0], sp->stream);
+  const bool timed = s->params.timing > 0 && s->n_launched % (uint64_t)s->params.timing == 0;
+  hipError_t e = hipSuccess;
+  TimedSpan *span = nullptr;
+  if (timed) {
+    const int kinds[3] = {0, 1, do_draw ? 2 : 3};
+    e = begin_span(s, 3, kinds, &span);
+    s->t_step = (int32_t)(s->t_spans.size() - 1);
+  }
   if (e == hipSuccess)
     e = launch_score_pass(m->d_P, m->stride, prof, s->pending_act, s->d_explored, nv, s->d_s, acc,
                           sp->stream);
-  if (e == hipSuccess && timing) e = hipEventRecord(s->ev_k[1], sp->stream);
+  if (e == hipSuccess && timed) e = mark_span(s, span, 0);
   if (e == hipSuccess)
     e = launch_weight_pass(s->d_s, s->d_explored, nv, prof, acc, acc_next, s->params.gamma,
                            s->params.w_min, s->block_log2, s->d_bsum, s->n_blocks, sp->stream);
-  if (e == hipSuccess && timing) e = hipEventRecord(s->ev_k[2], sp->stream);
-  if (e == hipSuccess && do_draw && timing) e = hipEventRecord(s->ev_k[3], sp->stream);
+  if (e == hipSuccess && timed) e = mark_span(s, span, 1);
   if (e == hipSuccess) {
     if (do_draw)
       e = launch_draw(s->d_s, s->d_explored, nv, prof, true, acc, s->params.gamma, s->params.w_min,
-                      s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, s->d_res,
+                      s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, s->d_res, ++s->seq,
                       sp->stream);
     else
       e = launch_mark_one(s->d_explored, prof, nv, sp->stream);
   }
-  if (e == hipSuccess && do_draw && timing) e = hipEventRecord(s->ev_k[4], sp->stream);
-  if (e == hipSuccess) e = hipEventRecord(s->ev_end, sp->stream);
+  if (e == hipSuccess && timed) e = mark_span(s, span, 2);
   if (e != hipSuccess) return e;
-  s->events_valid = true;
-  s->step_times_pending = timing;
+  ++s->n_launched;
+  s->step_timed = timed;
+  s->ran_in_batch = false;
   s->cur_acc = s->parity;
   s->parity ^= 1;
   s->pending = false;
@@ -1002,7 +1070,7 @@ cgs_status flush_pending(cgs_session s) {
 
 extern "C" cgs_status cgs_session_kernel_times(cgs_session s, double *total_ms, uint64_t *launches) {
   if (!s || !total_ms || !launches) return fail(CGS_EINVAL, "NULL argument");
-  if (s->params.timing && s->step_times_pending) HIP_TRY(collect_step_times(s));
+  HIP_TRY(collect_times(s));
   for (int i = 0; i < 4; ++i) {
     total_ms[i] = s->kernel_ms[i];
     launches[i] = s->kernel_n[i];
@@ -1020,6 +1088,7 @@ extern "C" cgs_status cgs_session_create(cgs_space sp, const cgs_params *params,
   if (!std::isfinite(p.gamma) || p.gamma > 0.0f)
     return fail(CGS_EINVAL, "gamma must be finite and <= 0");
   if (!(p.w_min > 0.0f) || !(p.w_min <= 1.0f)) return fail(CGS_EINVAL, "w_min must be in (0, 1]");
+  if (p.timing < 0) return fail(CGS_EINVAL, "timing must be >= 0");
   if (p.block_log2 != 0 && (p.block_log2 < 12 || p.block_log2 > 20))
     return fail(CGS_ERANGE, "block_log2 must be 0 or 12..20");
   cgs_session s = new (std::nothrow) cgs_session_s();
@@ -1040,13 +1109,20 @@ extern "C" cgs_status cgs_session_create(cgs_space sp, const cgs_params *params,
   if (e == hipSuccess) e = dalloc(&s->d_bsum, s->n_blocks);
   if (e == hipSuccess) e = dalloc(&s->d_acc, 2 * kAccSlots);
   if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void **>(&s->h_res), sizeof(DrawResult), hipHostMallocMapped);
-  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->d_res), s->h_res, 0);
+    e = hipHostMalloc(reinterpret_cast<void **>(&s->h_res), sizeof(DrawResult),
+                      hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) {
+    std::memset(s->h_res, 0, sizeof(DrawResult));
+    e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->d_res), s->h_res, 0);
+  }
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void **>(&s->h_acc), kAccSlots * sizeof(StepAcc), 0);
-  if (e == hipSuccess) e = hipEventCreate(&s->ev_begin);
-  if (e == hipSuccess) e = hipEventCreate(&s->ev_end);
-  for (int i = 0; i < 5 && e == hipSuccess && p.timing; ++i) e = hipEventCreate(&s->ev_k[i]);
+  if (e == hipSuccess && p.timing > 0) {
+    s->t_ev.assign(kTimeEvents, nullptr);
+    s->t_spans.reserve(kTimeEvents / 2);
+    for (uint32_t i = 0; i < kTimeEvents && e == hipSuccess; ++i)
+      e = hipEventCreateWithFlags(&s->t_ev[i], hipEventDisableSystemFence);
+  }
   if (e == hipSuccess)
     e = hipMemsetAsync(s->d_explored, 0, std::max<uint64_t>(n_words, 1) * sizeof(uint32_t),
                        sp->stream);
@@ -1119,26 +1195,22 @@ extern "C" cgs_status cgs_sample_next(cgs_session s, uint64_t u64, uint64_t *raw
   if (!s->stepped) return fail(CGS_ESTATE, "cgs_sample_next before any cgs_search_step");
   cgs_space sp = s->space;
   if (sp->n_valid == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
-  const bool timing = s->params.timing != 0;
   if (s->pending) {
     HIP_TRY(launch_pending(s, true, u64));
   } else {
-    if (timing) HIP_TRY(hipEventRecord(s->ev_k[3], sp->stream));
+    TimedSpan *span = nullptr;
+    if (s->step_timed) {
+      const int kinds[1] = {2};
+      HIP_TRY(begin_span(s, 1, kinds, &span));
+    }
     HIP_TRY(launch_draw(s->d_s, s->d_explored, (uint32_t)sp->n_valid, kNoProfile, false,
                         s->d_acc + s->cur_acc * kAccSlots, s->params.gamma, s->params.w_min,
-                        s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, s->d_res,
+                        s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, s->d_res, ++s->seq,
                         sp->stream));
-    if (timing) HIP_TRY(hipEventRecord(s->ev_k[4], sp->stream));
-    HIP_TRY(hipEventRecord(s->ev_end, sp->stream));
+    if (span) HIP_TRY(mark_span(s, span, 0));
   }
-  HIP_TRY(hipStreamSynchronize(sp->stream));
-  if (timing) {
-    if (s->step_times_pending) HIP_TRY(collect_step_times(s));
-    float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, s->ev_k[3], s->ev_k[4]));
-    s->kernel_ms[2] += ms;
-    s->kernel_n[2] += 1;
-  }
+  const cgs_status ws = wait_draw(s, s->h_res, s->seq);
+  if (ws != CGS_OK) return ws;
   DrawResult r;
   std::memcpy(&r, const_cast<const DrawResult *>(static_cast<volatile DrawResult *>(s->h_res)),
               sizeof r);
@@ -1177,8 +1249,13 @@ extern "C" cgs_status cgs_session_step_info(cgs_session s, cgs_step_info *out) {
   out->total_weight = s->last_total;
   out->s_min = a.n_unexplored ? key_to_float(a.min_key) : 0.0f;
   out->s_max = a.n_unexplored ? key_to_float(a.max_key) : 0.0f;
-  float ms = s->batch_ms;
-  if (s->events_valid) HIP_TRY(hipEventElapsedTime(&ms, s->ev_begin, s->ev_end));
+  float ms = 0.0f;
+  if (s->ran_in_batch) {
+    ms = s->batch_ms;
+  } else if (s->params.timing > 0) {
+    HIP_TRY(collect_times(s));
+    ms = s->step_ms;
+  }
   out->device_ms = ms;
   out->n_active = s->n_active;
   return CGS_OK;
@@ -1276,6 +1353,7 @@ struct cgs_batch_s {
   hipGraphExec_t exec = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   float last_ms = 0.0f;
+  uint64_t seq = 0; // sequence number of the last batch step's draws
 };
 
 namespace {
@@ -1409,8 +1487,8 @@ extern "C" cgs_status cgs_batch_create(int n, const cgs_session *sessions, const
     e = hipHostMalloc(reinterpret_cast<void **>(&b->h_res), (size_t)n * sizeof(DrawResult),
                       hipHostMallocMapped);
   if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&b->d_res), b->h_res, 0);
-  if (e == hipSuccess) e = hipEventCreate(&b->e0);
-  if (e == hipSuccess) e = hipEventCreate(&b->e1);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->e0, hipEventDisableSystemFence);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->e1, hipEventDisableSystemFence);
   if (e == hipSuccess) {
     for (int i = 0; i < n; ++i) desc[i].res = b->d_res + i;
     e = hipMemcpyAsync(b->d_sess, desc.data(), (size_t)n * sizeof(BatchSess), hipMemcpyHostToDevice,
@@ -1484,6 +1562,7 @@ extern "C" cgs_status cgs_batch_step(cgs_batch b, const uint64_t *profile_raw, c
     st.parity = s->parity;
     st.draw = 1;
     st.u64 = u64[i];
+    st.seq = b->seq + 1;
   }
   HIP_TRY(hipEventRecord(b->e0, b->stream));
   if (b->sched.use_graph) {
@@ -1493,6 +1572,7 @@ extern "C" cgs_status cgs_batch_step(cgs_batch b, const uint64_t *profile_raw, c
     HIP_TRY(enqueue_batch(b, true));
   }
   HIP_TRY(hipEventRecord(b->e1, b->stream));
+  ++b->seq;
   HIP_TRY(hipStreamSynchronize(b->stream));
   HIP_TRY(hipEventElapsedTime(&b->last_ms, b->e0, b->e1));
   for (int i = 0; i < b->n; ++i) {
@@ -1502,7 +1582,7 @@ extern "C" cgs_status cgs_batch_step(cgs_batch b, const uint64_t *profile_raw, c
     s->parity ^= 1;
     s->stepped = true;
     s->pending = false;
-    s->events_valid = false;
+    s->ran_in_batch = true;
     s->batch_ms = b->last_ms;
     s->n_active = b->h_step[i].n_act;
     DrawResult r;
@@ -1561,6 +1641,7 @@ extern "C" cgs_status cgs_batch_autotune(cgs_batch b, const char *cache_path,
     st.parity = s->parity ^ 1;
     st.draw = 0;
     st.u64 = 0;
+    st.seq = 0;
   }
   HIP_TRY(hipMemcpyAsync(b->d_step, b->h_step, (size_t)b->n * sizeof(BatchStep),
                          hipMemcpyHostToDevice, b->stream));

@@ -60,6 +60,7 @@ struct DrawResult {
   uint64_t raw;    // its raw index
   uint64_t total;  // Q at this draw
   uint64_t r;      // floor(U * Q / 2^64)
+  uint64_t seq;    // sequence number of the draw, stored last (release)
 };
 
 constexpr uint64_t kNoPick = ~0ull;
@@ -88,6 +89,7 @@ struct BatchStep {
   int32_t parity;   // accumulator set of this step
   int32_t draw;     // 0: score and weigh only (timing)
   uint64_t u64;
+  uint64_t seq;     // sequence number the draw publishes
   uint32_t ctr[CGS_MAX_COUNTERS];
   float delta[CGS_MAX_COUNTERS];
 };
@@ -178,10 +180,12 @@ hipError_t launch_weight_pass(const float *d_s, const uint32_t *d_explored, uint
                               uint32_t profile, const StepAcc *d_acc, StepAcc *d_acc_next,
                               float gamma, float w_min, int block_log2, uint64_t *d_bsum,
                               uint32_t n_blocks, hipStream_t stream);
+// The draw stores its result, then `seq` with a system-scope release.
 hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid, uint32_t profile,
                        bool mark_profile, const StepAcc *d_acc, float gamma, float w_min,
                        int block_log2, uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64,
-                       const uint32_t *d_idx, DrawResult *d_res, hipStream_t stream);
+                       const uint32_t *d_idx, DrawResult *d_res, uint64_t seq,
+                       hipStream_t stream);
 hipError_t launch_mark_one(uint32_t *d_explored, uint32_t l, uint32_t n_valid, hipStream_t stream);
 hipError_t launch_copy_weights(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
                                const StepAcc *d_acc, float gamma, float w_min, uint32_t first,

@@ -27,10 +27,13 @@
 //                 would pay for with an L2 write-back per workgroup)
 //   draw          one workgroup per draw; the step's first draw also marks the
 //                 profiled configuration explored.
-// A draw: Q = sum of block sums, r = mulhi64(U, Q), scan of the block sums
-// to the block holding r, recompute that block's q and scan it to l with
+// A draw: one scan of the block sums gives Q and the block holding
+// r = mulhi64(U, Q); recompute that block's q and scan it to l with
 // prefix_l <= r < prefix_l + q_l; mark l explored and subtract q_l from its
-// block sum (Alg. 1 zeroes S_l before the next draw of the iteration).
+// block sum (Alg. 1 zeroes S_l before the next draw of the iteration).  The
+// result goes to pinned host memory, closed by a sequence number that the
+// host polls.  Every phase issues all of its loads before the first use, so
+// a draw costs about four dependent memory round trips.
 #include <algorithm>
 
 #include "device_common.h"
@@ -174,130 +177,235 @@ __global__ __launch_bounds__(kScoreThreads) void score_pass(
   flush_acc(kmin, kmax, cnt, acc + (blockIdx.x & (kAccSlots - 1)));
 }
 
+// Folds the accumulator slot each lane of wave 0 loaded into the step's
+// min / max / count and leaves them in `out` (LDS).  No barrier: the caller
+// publishes `out` with its next one.
+__device__ __forceinline__ void reduce_slot_values(const StepAcc &slot, StepAccSums *out) {
+  if (threadIdx.x < kWave) {
+    const uint32_t mn = wave_umin(slot.min_key), mx = wave_umax(slot.max_key);
+    const uint32_t n = wave_sum(slot.n_unexplored);
+    if (threadIdx.x == 0) *out = StepAccSums{mn, mx, n};
+  }
+}
+
 // Quantised weight of valid index l (0 past the end, for explored
-// configurations and for the profiled one).
+// configurations and for the profiled one).  The step's s_min / s_max come
+// from its accumulator slots in three stages, so a draw can overlap their
+// load with its first loads: stage_load (every thread), stage_reduce (after
+// the caller's own loads), then a barrier, then stage_read.
 struct ScoreWeights {
   const float *s;
   uint32_t *explored;
   uint32_t n;
   uint32_t profile;
-  float s_min, s_max, gamma, w_min;
+  const StepAcc *acc;
+  float gamma, w_min;
+  float s_min = 0.0f, s_max = 0.0f;
+  StepAcc slot{};
+  __device__ void stage_load() {
+    if (threadIdx.x < kWave) slot = acc[threadIdx.x];
+  }
+  __device__ void stage_reduce(StepAccSums *sh) const { reduce_slot_values(slot, sh); }
+  __device__ void stage_read(const StepAccSums *sh) {
+    s_min = key_float(sh->min_key);
+    s_max = key_float(sh->max_key);
+  }
   __device__ uint32_t operator()(uint32_t l) const {
     if (l >= n) return 0u;
     return quantized_weight(s[l], explored_bit(explored, l) || l == profile, s_min, s_max, gamma,
                             w_min);
+  }
+  // Weights of l = first .. first + cnt - 1 (cnt <= K) into q[], 0 beyond;
+  // every load is issued before the first is used.
+  template <int K> __device__ void run(uint32_t first, uint32_t cnt, uint32_t (&q)[K]) const {
+    float sv[K];
+    uint32_t ew[K];
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      const uint32_t l = first + e;
+      const bool in = (uint32_t)e < cnt && l < n;
+      sv[e] = in ? s[l] : 0.0f;
+      ew[e] = in ? explored[l >> 5] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      const uint32_t l = first + e;
+      const bool ex = ((ew[e] >> (l & 31u)) & 1u) || l == profile;
+      q[e] = quantized_weight(sv[e], ex, s_min, s_max, gamma, w_min);
+    }
   }
   __device__ void remove(uint32_t l) const { atomicOr(&explored[l >> 5], 1u << (l & 31u)); }
 };
 struct ArrayWeights {
   uint32_t *q;
   uint32_t n;
+  __device__ void stage_load() {}
+  __device__ void stage_reduce(StepAccSums *) const {}
+  __device__ void stage_read(const StepAccSums *) {}
   __device__ uint32_t operator()(uint32_t l) const { return l < n ? q[l] : 0u; }
+  template <int K> __device__ void run(uint32_t first, uint32_t cnt, uint32_t (&out)[K]) const {
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      const uint32_t l = first + e;
+      out[e] = ((uint32_t)e < cnt && l < n) ? q[l] : 0u;
+    }
+  }
   __device__ void remove(uint32_t l) const { q[l] = 0u; }
 };
 
-__device__ __forceinline__ uint64_t load_coherent(const uint64_t *p) { return *p; }
-
-// The draw result lives in mapped pinned host memory: system-scope stores, so
-// the host reads it right after the stream synchronises (no copy kernel).
+// The draw result lives in mapped, coherent pinned host memory.  The thread
+// that settles a draw stores its fields with system-scope stores and then
+// `seq` with a system-scope release, so a host that sees `seq` sees the
+// fields (the host polls `seq` instead of waiting for the stream).
 __device__ __forceinline__ void put(uint64_t *field, uint64_t v) {
   __hip_atomic_store(field, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+__device__ __forceinline__ void publish(DrawResult *res, uint64_t valid, uint64_t raw,
+                                        uint64_t total, uint64_t r, uint64_t seq) {
+  put(&res->valid, valid);
+  put(&res->raw, raw);
+  put(&res->total, total);
+  put(&res->r, r);
+  __hip_atomic_store(&res->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
+constexpr uint32_t kNoLane = 0xffffffffu;
+constexpr uint32_t kKeepWeights = 8; // weights per thread kept in registers
+
+// One draw by one workgroup of NT threads.
+//  1. Thread t owns the contiguous run of block sums [t * per, t * per + per);
+//     one exclusive scan over the run totals gives Q and, for the thread
+//     whose run holds r, the block b with prefix_b <= r < prefix_b + bsum_b.
+//  2. Every thread takes 2^block_log2 / NT consecutive configurations of
+//     block b; a second scan finds l with prefix_l <= r' < prefix_l + q_l.
+// The winner removes l, subtracts q_l from bsum_b and publishes the result.
 template <int NT, typename W>
-__device__ void draw_body(const W &wsrc, int block_log2, uint64_t *__restrict__ bsum,
+__device__ void draw_body(W &wsrc, int block_log2, uint64_t *__restrict__ bsum,
                           uint32_t n_blocks, uint64_t u64, const uint32_t *__restrict__ idx,
-                          DrawResult *__restrict__ res) {
+                          DrawResult *__restrict__ res, uint64_t seq) {
   __shared__ uint64_t scratch[NT / kWave];
-  __shared__ uint64_t found_block, found_rem;
-  __shared__ int found;
+  __shared__ StepAccSums sums;
+  __shared__ uint32_t found_block;
+  __shared__ uint64_t found_rem;
+  __shared__ int picked;
   const uint32_t tid = threadIdx.x;
 
-  // Q = sum of block sums
-  uint64_t part = 0;
-  for (uint32_t b = tid; b < n_blocks; b += NT) part += load_coherent(bsum + b);
-  const uint64_t Q = block_sum<NT>(part, scratch);
+  wsrc.stage_load();
+  const uint32_t per = (n_blocks + NT - 1) / NT;
+  const uint32_t b0 = tid * per;
+  const uint32_t b1 = min(n_blocks, b0 + per);
+  constexpr uint32_t kChunk = 4; // block sums loaded per round trip
+  uint64_t mine = 0;
+  for (uint32_t c = b0; c < b1; c += kChunk) {
+    uint64_t v[kChunk];
+#pragma unroll
+    for (uint32_t k = 0; k < kChunk; ++k) v[k] = c + k < b1 ? bsum[c + k] : 0ull;
+#pragma unroll
+    for (uint32_t k = 0; k < kChunk; ++k) mine += v[k];
+  }
+  wsrc.stage_reduce(&sums);
+  if (tid == 0) picked = 0;
+  uint64_t Q;
+  const uint64_t pre = block_excl_scan<NT>(mine, scratch, Q); // barriers publish sums
+  wsrc.stage_read(&sums);
   if (Q == 0) {
-    if (tid == 0) {
-      put(&res->valid, kNoPick);
-      put(&res->raw, kNoPick);
-      put(&res->total, 0);
-      put(&res->r, 0);
-    }
+    if (tid == 0) publish(res, kNoPick, kNoPick, 0, 0, seq);
     return;
   }
   const uint64_t r = __umul64hi(u64, Q);
-  if (tid == 0) {
-    // overwritten by the thread that finds the pick; stays "no pick" only if
-    // the block sums disagree with the weights (reported as an error)
-    put(&res->valid, kNoPick);
-    put(&res->raw, kNoPick);
-    put(&res->total, Q);
-    put(&res->r, r);
-    found = 0;
-    found_block = 0;
-    found_rem = 0;
-  }
-
-  // block b with prefix_b <= r < prefix_b + bsum[b]
-  uint64_t running = 0;
-  for (uint32_t base = 0; base < n_blocks; base += NT) {
-    const uint32_t b = base + tid;
-    const uint64_t v = b < n_blocks ? load_coherent(bsum + b) : 0ull;
-    uint64_t chunk;
-    const uint64_t excl = running + block_excl_scan<NT>(v, scratch, chunk);
-    if (v != 0 && excl <= r && r < excl + v) {
-      found_block = b;
-      found_rem = r - excl;
-      found = 1;
+  if (mine != 0 && pre <= r && r < pre + mine) {
+    uint64_t run = pre;
+    bool hit = false;
+    for (uint32_t c = b0; c < b1 && !hit; c += kChunk) {
+      uint64_t v[kChunk];
+#pragma unroll
+      for (uint32_t k = 0; k < kChunk; ++k) v[k] = c + k < b1 ? bsum[c + k] : 0ull;
+#pragma unroll
+      for (uint32_t k = 0; k < kChunk; ++k) {
+        if (!hit && r < run + v[k]) {
+          found_block = c + k;
+          found_rem = r - run;
+          hit = true;
+        }
+        run += v[k];
+      }
     }
-    running += chunk;
-    __syncthreads();
-    if (found) break;
   }
-  if (!found) return;
-  const uint32_t blk = (uint32_t)found_block;
+  __syncthreads();
+  const uint32_t blk = found_block;
   const uint64_t rem = found_rem;
 
-  // configuration inside the block: thread tid owns a contiguous run
-  const uint32_t B = 1u << block_log2;
-  const uint32_t per = B / NT;
-  const uint32_t first = (blk << block_log2) + tid * per;
-  uint64_t mine = 0;
-  for (uint32_t e = 0; e < per; ++e) mine += wsrc(first + e);
+  // 2^block_log2 / NT >= 4 consecutive configurations per thread, weighed in
+  // chunks of kKeepWeights (the first chunk stays in registers)
+  const uint32_t per2 = (1u << block_log2) / NT;
+  const uint32_t first = (blk << block_log2) + tid * per2;
+  uint32_t qk[kKeepWeights];
+  wsrc.run(first, min(per2, kKeepWeights), qk);
+  uint64_t mine2 = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < kKeepWeights; ++e) mine2 += qk[e];
+  for (uint32_t c = kKeepWeights; c < per2; c += kKeepWeights) {
+    uint32_t t[kKeepWeights];
+    wsrc.run(first + c, min(per2 - c, kKeepWeights), t);
+#pragma unroll
+    for (uint32_t e = 0; e < kKeepWeights; ++e) mine2 += t[e];
+  }
   uint64_t blk_total;
-  uint64_t pre = block_excl_scan<NT>(mine, scratch, blk_total);
-  if (mine != 0 && pre <= rem && rem < pre + mine) {
-    for (uint32_t e = 0; e < per; ++e) {
-      const uint32_t q = wsrc(first + e);
-      if (rem < pre + q) {
-        const uint32_t l = first + e;
-        wsrc.remove(l);
-        bsum[blk] = load_coherent(bsum + blk) - q;
-        put(&res->valid, l);
-        put(&res->raw, idx ? idx[l] : l);
-        break;
+  const uint64_t pre2 = block_excl_scan<NT>(mine2, scratch, blk_total);
+  if (mine2 != 0 && pre2 <= rem && rem < pre2 + mine2) {
+    uint32_t l = kNoLane, ql = 0;
+    uint64_t run = pre2;
+#pragma unroll
+    for (uint32_t e = 0; e < kKeepWeights; ++e) {
+      if (l == kNoLane && rem < run + qk[e]) {
+        l = first + e;
+        ql = qk[e];
       }
-      pre += q;
+      run += qk[e];
+    }
+    for (uint32_t c = kKeepWeights; l == kNoLane && c < per2; c += kKeepWeights) {
+      uint32_t t[kKeepWeights];
+      wsrc.run(first + c, min(per2 - c, kKeepWeights), t);
+#pragma unroll
+      for (uint32_t e = 0; e < kKeepWeights; ++e) {
+        if (l == kNoLane && rem < run + t[e]) {
+          l = first + e + c;
+          ql = t[e];
+        }
+        run += t[e];
+      }
+    }
+    if (l != kNoLane) {
+      wsrc.remove(l);
+      bsum[blk] -= ql;
+      picked = 1;
+      publish(res, l, idx ? idx[l] : l, Q, r, seq);
     }
   }
+  __syncthreads();
+  // no pick although Q > 0: the block sums disagree with the weights
+  if (tid == 0 && !picked) publish(res, kNoPick, kNoPick, Q, r, seq);
 }
 
 // Sum of the quantised weights of block `blk` (2^block_log2 configurations),
-// returned to every thread.
+// returned to every thread.  The step's accumulator slots and the block's
+// first 4096 scores are loaded together; s_min / s_max are known once both
+// have arrived.
 __device__ __forceinline__ uint64_t weight_block_sum(const float *__restrict__ s,
                                                      const uint32_t *__restrict__ explored,
                                                      uint32_t n_valid, uint32_t profile,
-                                                     float s_min, float s_max, float gamma,
+                                                     const StepAcc *__restrict__ acc, float gamma,
                                                      float w_min, int block_log2, uint32_t blk) {
   __shared__ uint64_t scratch[kWeightThreads / kWave];
+  __shared__ StepAccSums sums;
+  constexpr uint32_t kRound = 16u * kWeightThreads; // 4 float4 per thread
   const uint32_t base = blk << block_log2;
   const uint32_t end = min(n_valid, base + (1u << block_log2));
-  uint64_t sum = 0;
-  // 4096 configurations per round: 4 float4 of scores per thread, loaded first
-  for (uint32_t r0 = base; r0 < end; r0 += 16u * kWeightThreads) {
-    float4 sv[4];
-    uint32_t ex[4];
+  StepAcc slot{};
+  if (threadIdx.x < kWave) slot = acc[threadIdx.x];
+  float4 sv[4];
+  uint32_t ex[4];
+  auto load_round = [&](uint32_t r0) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t l0 = r0 + 4u * (threadIdx.x + k * kWeightThreads);
@@ -306,6 +414,13 @@ __device__ __forceinline__ uint64_t weight_block_sum(const float *__restrict__ s
         ex[k] = explored[l0 >> 5];
       }
     }
+  };
+  load_round(base);
+  reduce_slot_values(slot, &sums);
+  __syncthreads();
+  const float s_min = key_float(sums.min_key), s_max = key_float(sums.max_key);
+  uint64_t sum = 0;
+  for (uint32_t r0 = base;;) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t l0 = r0 + 4u * (threadIdx.x + k * kWeightThreads);
@@ -319,8 +434,11 @@ __device__ __forceinline__ uint64_t weight_block_sum(const float *__restrict__ s
             sum += quantized_weight(ss[e], (ex4 >> e) & 1u, s_min, s_max, gamma, w_min);
       }
     }
+    r0 += kRound;
+    if (r0 >= end) break;
+    load_round(r0);
   }
-  return block_sum<kWeightThreads>(sum, scratch);
+  return block_sum<kWeightThreads>(sum, scratch); // its barriers also retire `sums`
 }
 
 __device__ __forceinline__ void clear_acc(StepAcc *acc_next) {
@@ -336,11 +454,9 @@ __global__ __launch_bounds__(kWeightThreads) void weight_pass(
     const float *__restrict__ s, const uint32_t *__restrict__ explored, uint32_t n_valid,
     uint32_t profile, const StepAcc *__restrict__ acc, StepAcc *__restrict__ acc_next,
     float gamma, float w_min, int block_log2, uint64_t *__restrict__ bsum) {
-  const StepAccSums a = reduce_slots(acc);
-  const float s_min = key_float(a.min_key), s_max = key_float(a.max_key);
   if (blockIdx.x == 0) clear_acc(acc_next); // the next step's accumulators
-  const uint64_t total = weight_block_sum(s, explored, n_valid, profile, s_min, s_max, gamma,
-                                          w_min, block_log2, blockIdx.x);
+  const uint64_t total = weight_block_sum(s, explored, n_valid, profile, acc, gamma, w_min,
+                                          block_log2, blockIdx.x);
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
@@ -350,11 +466,9 @@ __global__ __launch_bounds__(kDrawThreads) void draw_scores(
     const float *__restrict__ s, uint32_t *__restrict__ explored, uint32_t n_valid,
     uint32_t profile, int mark_profile, const StepAcc *__restrict__ acc, float gamma,
     float w_min, int block_log2, uint64_t *__restrict__ bsum, uint32_t n_blocks, uint64_t u64,
-    const uint32_t *__restrict__ idx, DrawResult *__restrict__ res) {
-  const StepAccSums a = reduce_slots(acc);
-  ScoreWeights w{s, explored, n_valid, profile, key_float(a.min_key), key_float(a.max_key),
-                 gamma, w_min};
-  draw_body<kDrawThreads>(w, block_log2, bsum, n_blocks, u64, idx, res);
+    const uint32_t *__restrict__ idx, DrawResult *__restrict__ res, uint64_t seq) {
+  ScoreWeights w{s, explored, n_valid, profile, acc, gamma, w_min};
+  draw_body<kDrawThreads>(w, block_log2, bsum, n_blocks, u64, idx, res, seq);
   __syncthreads();
   if (threadIdx.x == 0 && mark_profile && profile < n_valid)
     atomicOr(&explored[profile >> 5], 1u << (profile & 31u));
@@ -400,11 +514,10 @@ __global__ __launch_bounds__(kWeightThreads) void batch_weight(
     const BatchSess &d = sess[si];
     const BatchStep &st = step[si];
     const uint32_t lb = b - d.blk0;
-    const StepAccSums a = reduce_slots(d.acc + st.parity * kAccSlots);
     if (lb == 0) clear_acc(d.acc + (st.parity ^ 1) * kAccSlots);
     const uint64_t total =
-        weight_block_sum(d.s, d.explored, d.n_valid, st.profile, key_float(a.min_key),
-                         key_float(a.max_key), d.gamma, d.w_min, d.block_log2, lb);
+        weight_block_sum(d.s, d.explored, d.n_valid, st.profile, d.acc + st.parity * kAccSlots,
+                         d.gamma, d.w_min, d.block_log2, lb);
     if (threadIdx.x == 0) d.bsum[lb] = total;
   }
 }
@@ -415,10 +528,9 @@ __global__ __launch_bounds__(kDrawThreads) void batch_draw(const BatchSess *__re
   const BatchSess &d = sess[blockIdx.x];
   const BatchStep &st = step[blockIdx.x];
   if (!st.draw) return;
-  const StepAccSums a = reduce_slots(d.acc + st.parity * kAccSlots);
-  ScoreWeights w{d.s, d.explored, d.n_valid, st.profile, key_float(a.min_key),
-                 key_float(a.max_key), d.gamma, d.w_min};
-  draw_body<kDrawThreads>(w, d.block_log2, d.bsum, d.n_blocks, st.u64, d.idx, d.res);
+  ScoreWeights w{d.s, d.explored, d.n_valid, st.profile, d.acc + st.parity * kAccSlots, d.gamma,
+                 d.w_min};
+  draw_body<kDrawThreads>(w, d.block_log2, d.bsum, d.n_blocks, st.u64, d.idx, d.res, st.seq);
   __syncthreads();
   if (threadIdx.x == 0 && st.profile < d.n_valid)
     atomicOr(&d.explored[st.profile >> 5], 1u << (st.profile & 31u));
@@ -436,7 +548,7 @@ __global__ __launch_bounds__(kDrawThreads) void draw_array(uint32_t *__restrict_
                                                            uint32_t n_blocks, uint64_t u64,
                                                            DrawResult *__restrict__ res) {
   ArrayWeights w{q, n};
-  draw_body<kDrawThreads>(w, block_log2, bsum, n_blocks, u64, nullptr, res);
+  draw_body<kDrawThreads>(w, block_log2, bsum, n_blocks, u64, nullptr, res, 1);
 }
 
 __global__ __launch_bounds__(kWeightThreads) void array_block_sums(const uint32_t *__restrict__ q,
@@ -463,8 +575,9 @@ __global__ __launch_bounds__(256) void copy_weights(const float *__restrict__ s,
   const StepAccSums a = reduce_slots(acc);
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
-  ScoreWeights w{s, explored, n_valid, kNoProfile, key_float(a.min_key), key_float(a.max_key),
-                 gamma, w_min};
+  ScoreWeights w{s, explored, n_valid, kNoProfile, acc, gamma, w_min};
+  w.s_min = key_float(a.min_key);
+  w.s_max = key_float(a.max_key);
   q[i] = w(first + i);
 }
 
@@ -508,10 +621,11 @@ hipError_t launch_weight_pass(const float *d_s, const uint32_t *d_explored, uint
 hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid, uint32_t profile,
                        bool mark_profile, const StepAcc *d_acc, float gamma, float w_min,
                        int block_log2, uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64,
-                       const uint32_t *d_idx, DrawResult *d_res, hipStream_t stream) {
+                       const uint32_t *d_idx, DrawResult *d_res, uint64_t seq,
+                       hipStream_t stream) {
   hipLaunchKernelGGL(draw_scores, dim3(1), dim3(kDrawThreads), 0, stream, d_s, d_explored, n_valid,
                      profile, mark_profile ? 1 : 0, d_acc, gamma, w_min, block_log2, d_bsum,
-                     n_blocks, u64, d_idx, d_res);
+                     n_blocks, u64, d_idx, d_res, seq);
   return hipGetLastError();
 }
 

@@ -48,3 +48,18 @@ def test_large_uniform_closed_form():
     q = np.full(n, 1 << 23, dtype=np.uint32)
     for u in synth.uniforms_u64(synth.rng(82), 50):
         assert sp.sample_weights(q, [u])[0] == (int(u) * n) >> 64
+
+
+def test_many_blocks_per_draw_thread():
+    """20M weights: 4883 blocks of 4096, so each draw thread scans a run of 5
+    block sums in two load rounds."""
+    m, sp = _space()
+    g = np.random.default_rng(5)
+    n = 20_000_000
+    q = g.integers(0, 1 << 31, n, dtype=np.uint64)
+    q[g.random(n) < 0.5] = 0
+    U = synth.uniforms_u64(synth.rng(83), 12)
+    U[:2] = [0, np.iinfo(np.uint64).max]
+    q32 = q.astype(np.uint32)
+    for u in U:
+        assert sp.sample_weights(q32, [u])[0] == S.pick(q, int(u))

@@ -68,7 +68,7 @@ class Pair:
 
 
 def test_c1_single_step_configuration():
-    """configs[0]: start from a uniform draw, then one scored step with 12
+    """The 30,720-configuration space: start from a uniform draw, then one scored step with 12
     bottleneck weights ~ U(-1,1) and one seeded uniform."""
     spec = synth.space_c1()
     pair = Pair(spec, synth.forest_c1(spec))
@@ -162,14 +162,16 @@ def test_measured_counters_path_matches_oracle_expert_system():
         prof = ref.picks[0]
 
 
-def test_block_size_and_ragged_tail():
-    """Explicit 2^12-configuration weight blocks over a space whose valid count
-    (498,750) is neither a multiple of the block nor of 4."""
+@pytest.mark.parametrize("block_log2", [12, 16])
+def test_block_size_and_ragged_tail(block_log2):
+    """Explicit 2^12- and 2^16-configuration weight blocks (4 and 64 weights
+    per draw thread) over a space whose valid count (498,750) is neither a
+    multiple of the block nor of 4."""
     m = cgs()
     spec = synth.space_batch(63)
     forest = synth.random_forest(synth.rng(63, 2), spec.radix, 4, 8, 6)
     p = m.cgs_default_params()
-    p.block_log2 = 12
+    p.block_log2 = block_log2
     pair = Pair(spec, forest, p)
     n = len(pair.prep.valid)
     assert n % 4096 != 0 and n % 4 != 0
@@ -177,3 +179,28 @@ def test_block_size_and_ragged_tail():
     U = synth.uniforms_u64(g, 5)
     ref, _ = pair.step(None, np.zeros(6, np.float32), U[:1])
     ref, _ = pair.step(ref.picks[0], synth.deltas(g, 1, 6)[0], U[1:])
+
+
+def test_sampled_timing_counts_and_leaves_picks_unchanged():
+    """timing = 3 times launched steps 0, 3, 6, 9 (and their further draws);
+    the picks stay those of the oracle."""
+    m = cgs()
+    spec = synth.space_c1()
+    p = m.cgs_default_params()
+    p.timing = 3
+    pair = Pair(spec, synth.forest_c1(spec), p)
+    g = synth.rng(1, 7)
+    U = synth.uniforms_u64(g, 1 + 9 * 2)
+    deltas = synth.deltas(g, 9, 12)
+    ref, _ = pair.step(None, np.zeros(12, np.float32), [U[0]], check_scores=False)
+    for i in range(9):
+        ref, info = pair.step(ref.picks[0], deltas[i], U[1 + 2 * i: 3 + 2 * i], check_scores=False)
+    ms, n = pair.sess.kernel_times()
+    assert n.tolist() == [4, 4, 1 + 3 * 2, 0]
+    assert (ms[:3] > 0).all()
+    assert info.device_ms > 0        # step 9 is timed
+    # no timing: zeros
+    plain = Pair(spec, synth.forest_c1(spec))
+    plain.step(None, np.zeros(12, np.float32), [U[0]], check_scores=False)
+    ms, n = plain.sess.kernel_times()
+    assert n.tolist() == [0, 0, 0, 0] and plain.sess.step_info().device_ms == 0.0
