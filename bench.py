@@ -21,6 +21,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -68,6 +69,32 @@ def run_search(cgs, sp, model, U, pcs, thr, n_steps, timing):
         raw, l = sess.sample_next(int(U[i + 1]))
         picks.append(l)
     return picks, sess
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "score_pass_c2_traffic.md")
+SWEEP_SOURCES = ("sweep.hip", "device_common.h", "internal.h")
+
+
+def pmc_traffic(active_counts):
+    """HBM bytes per score-pass launch, averaged over launches with the given
+    active-counter counts, from the committed FETCH_SIZE / WRITE_SIZE profile
+    (already scaled by the copy-kernel calibration); None when the profile is
+    missing, lacks a count, or was taken on other kernel sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        doc = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2102_05297_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != doc.get("source_sha256"):
+        return None
+    per = {int(k): float(v) for k, v in doc["bytes_per_launch_by_active"].items()}
+    if not active_counts or any(a not in per for a in active_counts):
+        return None
+    return sum(per[a] for a in active_counts) / len(active_counts)
 
 
 def copy_probe(n_bytes: int = 1 << 30, reps: int = 5) -> dict:
@@ -427,6 +454,7 @@ def main() -> int:
     assert len(timed) == int(launches[0])
     act = [0] + n_active
     bytes_score = sum(n_valid * (4 + 0.125 + 4.0 * act[j]) for j in timed)
+    traffic = pmc_traffic([act[j] for j in timed])
     score_s = ms[0] / 1e3
     achieved = bytes_score / score_s / 1e9 if score_s > 0 else 0.0
 
@@ -489,7 +517,8 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_score / len(timed),
             "launches": int(launches[0]),
             "avg_us": ms[0] / max(1, launches[0]) * 1e3,
         },

@@ -255,6 +255,239 @@ __global__ __launch_bounds__(LDSW ? 512 : 256) void mlp_forward(MlpFwdArgs a) {
 #undef W1F
 }
 
+// ------------------------------------------------------------- inference
+// P[c][l] = max(y_c, 0) over the valid configurations idx[0..n), written for
+// throughput.  One wave per SIMD (up to 512 registers) carries T tiles of 32
+// configurations (T = 2 where registers allow, so every weight fragment read
+// from LDS feeds two MFMAs) and keeps their hidden activations in registers.
+//   resident: W1, W2, W3 and the biases live in LDS for the whole launch
+//             (when they fit: H <= 256).
+//   stream:   W3, W1 and the biases live in LDS; W2 passes through a double
+//             buffer one 32-row block at a time, the next block's global
+//             loads overlapping the current block's MFMAs.
+// Either way the bias + GELU epilogue of one layer-2 block is independent of
+// the next block's MFMAs, so the two interleave.
+constexpr int kInferWaves = 4;
+template <int H> constexpr int infer_tiles() { return H <= 256 ? 2 : 1; }
+
+template <int T, int S1>
+__device__ __forceinline__ void infer_features(const MlpFwdArgs &a, uint32_t first, int hh,
+                                               int col, bf16x8 (&xb)[T][S1], bool (&ok)[T]) {
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const uint32_t i = first + 32 * t + col;
+    ok[t] = i < a.n;
+    uint64_t lo = 0, hi = 0;
+    if (ok[t]) decode_packed(a.idx[i], a.sp, lo, hi);
+#pragma unroll
+    for (int s = 0; s < S1; ++s)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = 16 * s + 8 * hh + j;
+        const float f = (ok[t] && k < a.F) ? (float)digit_of(lo, hi, (uint32_t)k) * 0.125f : 0.0f;
+        xb[t][s][j] = (__bf16)f;
+      }
+  }
+}
+
+// Bias + GELU of one 32x32 accumulator block, as the two bf16 B fragments of
+// the next layer's K steps 2r and 2r + 1; `b` points at bias[32 r + 4 hh].
+__device__ __forceinline__ void gelu_frags(const f32x16 &acc, const float *b, bf16x8 &f0,
+                                           bf16x8 &f1) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 bb = *reinterpret_cast<const float4 *>(b + 8 * q);
+    const float z[4] = {acc[4 * q] + bb.x, acc[4 * q + 1] + bb.y, acc[4 * q + 2] + bb.z,
+                        acc[4 * q + 3] + bb.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const __bf16 v = (__bf16)gelu(z[t]);
+      if (q < 2) f0[q * 4 + t] = v;
+      else f1[(q - 2) * 4 + t] = v;
+    }
+  }
+}
+
+template <int T, int NB3>
+__device__ __forceinline__ void infer_store(const MlpFwdArgs &a, const f32x16 (&accy)[NB3][T],
+                                            const float *b3, uint32_t first, int hh, int col,
+                                            const bool (&ok)[T]) {
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    if (!ok[t]) continue;
+    const uint32_t i = first + 32 * t + col;
+#pragma unroll
+    for (int r3 = 0; r3 < NB3; ++r3)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = 32 * r3 + 8 * q + 4 * hh + u;
+          if (c < a.C) a.P[(size_t)c * a.stride + i] = fmaxf(accy[r3][t][4 * q + u] + b3[c], 0.0f);
+        }
+  }
+}
+
+// Stages n 16-byte units from global to LDS with every thread of the block.
+__device__ __forceinline__ void stage_units(bf16x8 *dst, const bf16x8 *src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Biases in LDS: b1[H], b2[H], b3[32 NB3] (zero past C).
+__device__ __forceinline__ void stage_biases(float *bias, const MlpFwdArgs &a, int H, int NB3) {
+  for (int i = threadIdx.x; i < H; i += blockDim.x) {
+    bias[i] = a.b1[i];
+    bias[H + i] = a.b2[i];
+  }
+  for (int i = threadIdx.x; i < 32 * NB3; i += blockDim.x) bias[2 * H + i] = i < a.C ? a.b3[i] : 0.0f;
+}
+
+// Layer 1 of the wave's tiles: h1[2r + sp][t] for every block r.
+template <int H, int T, int S1>
+__device__ __forceinline__ void infer_layer1(const bf16x8 *w1, const float *bias, int lane, int hh,
+                                             const bf16x8 (&xb)[T][S1], bf16x8 (&h1)[H / 16][T]) {
+#pragma unroll
+  for (int r = 0; r < H / 32; ++r) {
+    bf16x8 wf[S1];
+#pragma unroll
+    for (int s = 0; s < S1; ++s) wf[s] = w1[(r * S1 + s) * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int s = 0; s < S1; ++s) acc = mfma(wf[s], xb[t][s], acc);
+      gelu_frags(acc, bias + 32 * r + 4 * hh, h1[2 * r][t], h1[2 * r + 1][t]);
+    }
+    __builtin_amdgcn_sched_barrier(0); // one block's temporaries live at a time
+  }
+}
+
+// Epilogue of layer-2 block r: bias + GELU, then its two K steps of layer 3.
+template <int H, int T, int NB3>
+__device__ __forceinline__ void infer_block_out(const f32x16 (&acc)[T], int r, const bf16x8 *w3,
+                                                const float *bias, int lane, int hh,
+                                                f32x16 (&accy)[NB3][T]) {
+  constexpr int S2 = H / 16;
+  bf16x8 w3f[NB3][2];
+#pragma unroll
+  for (int r3 = 0; r3 < NB3; ++r3)
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) w3f[r3][sp] = w3[(r3 * S2 + 2 * r + sp) * 64 + lane];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    bf16x8 f0, f1;
+    gelu_frags(acc[t], bias + H + 32 * r + 4 * hh, f0, f1);
+#pragma unroll
+    for (int r3 = 0; r3 < NB3; ++r3) {
+      accy[r3][t] = mfma(w3f[r3][0], f0, accy[r3][t]);
+      accy[r3][t] = mfma(w3f[r3][1], f1, accy[r3][t]);
+    }
+  }
+}
+
+template <int H, int NB3, int S1, bool RESIDENT, bool W1LDS>
+constexpr size_t infer_lds() {
+  return (size_t)((RESIDENT ? H * H : 2 * 32 * H) + NB3 * 32 * H + (W1LDS ? H * 16 * S1 : 0)) * 2 +
+         (size_t)(2 * H + 32 * NB3) * 4;
+}
+
+// RESIDENT: W2 stays in LDS; otherwise its 32-row blocks pass through a
+// double buffer.  Blocks are taken in pairs (A, B) so that one block's
+// epilogue is independent of the next block's MFMAs in the same stretch of
+// code.
+template <int H, int NB3, int S1, bool RESIDENT, bool W1LDS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mlp_infer(
+    MlpFwdArgs a) {
+  constexpr int T = infer_tiles<H>(), NB = H / 32, S2 = H / 16;
+  constexpr int NBLK = S2 * 64; // 16-byte units of one 32-row block of W2p
+  constexpr int PER = NBLK / 256;
+  constexpr int N2 = RESIDENT ? NB * NBLK : 2 * NBLK;
+  constexpr int N3 = NB3 * 32 * H / 8, N1 = H * 16 * S1 / 8;
+  static_assert(NB % 2 == 0 && NBLK % 256 == 0, "block pairs, whole units per thread");
+  extern __shared__ bf16x8 lds[];
+  bf16x8 *w2 = lds, *w3 = lds + N2, *w1l = w3 + N3;
+  float *bias = reinterpret_cast<float *>(w1l + (W1LDS ? N1 : 0));
+  const bf16x8 *w1 = W1LDS ? w1l : a.w1p;
+  if (RESIDENT) stage_units(w2, a.w2p, N2);
+  stage_units(w3, a.w3p, N3);
+  if (W1LDS) stage_units(w1l, a.w1p, N1);
+  stage_biases(bias, a, H, NB3);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, hh = lane >> 5, col = lane & 31;
+  const int tid = threadIdx.x;
+  constexpr uint32_t kWgConfigs = 32 * T * kInferWaves;
+  const uint32_t n_wg = (a.n + kWgConfigs - 1) / kWgConfigs;
+  // every wave of the block runs the same iterations (block barriers)
+  for (uint32_t wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
+    const uint32_t first = wg * kWgConfigs + (uint32_t)(tid / 64) * 32 * T;
+    if (!RESIDENT) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) w2[u * 256 + tid] = a.w2p[u * 256 + tid];
+    }
+    bf16x8 xb[T][S1];
+    bool ok[T];
+    infer_features<T, S1>(a, first, hh, col, xb, ok);
+    bf16x8 h1[S2][T];
+    infer_layer1<H, T, S1>(w1, bias, lane, hh, xb, h1);
+    f32x16 accy[NB3][T];
+#pragma unroll
+    for (int r3 = 0; r3 < NB3; ++r3)
+#pragma unroll
+      for (int t = 0; t < T; ++t) accy[r3][t] = f32x16{};
+    if (!RESIDENT) __syncthreads(); // block 0 in the first buffer
+    f32x16 accA[T], accB[T];
+#pragma unroll 1
+    for (int r = 0; r < NB; r += 2) {
+      const bf16x8 *wa = RESIDENT ? w2 + r * NBLK : w2;
+      const bf16x8 *wb = RESIDENT ? w2 + (r + 1) * NBLK : w2 + NBLK;
+      // block r; block r + 1 staged; epilogue of block r - 1
+      bf16x8 st[RESIDENT ? 1 : PER];
+      if (!RESIDENT) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) st[u] = a.w2p[(size_t)(r + 1) * NBLK + u * 256 + tid];
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) accA[t] = f32x16{};
+#pragma unroll
+      for (int ks = 0; ks < S2; ++ks) {
+        const bf16x8 wf = wa[ks * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < T; ++t) accA[t] = mfma(wf, h1[ks][t], accA[t]);
+      }
+      if (r > 0) infer_block_out<H, T, NB3>(accB, r - 1, w3, bias, lane, hh, accy);
+      if (!RESIDENT) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) w2[NBLK + u * 256 + tid] = st[u];
+        __syncthreads();
+      }
+      // block r + 1; block r + 2 staged; epilogue of block r
+      const bool more = r + 2 < NB;
+      if (!RESIDENT && more) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) st[u] = a.w2p[(size_t)(r + 2) * NBLK + u * 256 + tid];
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) accB[t] = f32x16{};
+#pragma unroll
+      for (int ks = 0; ks < S2; ++ks) {
+        const bf16x8 wf = wb[ks * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < T; ++t) accB[t] = mfma(wf, h1[ks][t], accB[t]);
+      }
+      infer_block_out<H, T, NB3>(accA, r, w3, bias, lane, hh, accy);
+      if (!RESIDENT) {
+        if (more) {
+#pragma unroll
+          for (int u = 0; u < PER; ++u) w2[u * 256 + tid] = st[u];
+        }
+        __syncthreads();
+      }
+    }
+    infer_block_out<H, T, NB3>(accB, NB - 1, w3, bias, lane, hh, accy);
+    infer_store<T, NB3>(a, accy, bias + 2 * H, first, hh, col, ok);
+  }
+}
+
 // ------------------------------------------------------------------ GEMM
 // C[M][N] = sum_k A(m, k) B(k, n), bf16 operands (converted on load), fp32
 // accumulation; one 32x32 output tile per wave.  Operands are addressed with
@@ -428,6 +661,44 @@ __global__ __launch_bounds__(256) void adam_pack(MlpShape sh, float *__restrict_
   pack_one(sh, p, th, w1p, w2p, w3p);
 }
 
+template <typename K>
+hipError_t launch_infer_kernel(K kernel, size_t lds, uint32_t grid, const MlpFwdArgs &a,
+                               hipStream_t stream) {
+  if (grid == 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), lds, stream, a);
+  return hipGetLastError();
+}
+
+constexpr size_t kLdsBytes = 160 * 1024;
+
+template <int H, int NB3, int S1>
+hipError_t launch_infer_h(const MlpFwdArgs &a, hipStream_t stream) {
+  const uint32_t cu = (uint32_t)std::max(a.n_cu, 1);
+  constexpr uint32_t wg_cfg = 32 * infer_tiles<H>() * kInferWaves;
+  const uint32_t grid = std::min<uint32_t>((a.n + wg_cfg - 1) / wg_cfg, cu);
+  if constexpr (infer_lds<H, NB3, S1, true, true>() <= kLdsBytes)
+    return launch_infer_kernel(mlp_infer<H, NB3, S1, true, true>,
+                               infer_lds<H, NB3, S1, true, true>(), grid, a, stream);
+  else if constexpr (infer_lds<H, NB3, S1, false, true>() <= kLdsBytes)
+    return launch_infer_kernel(mlp_infer<H, NB3, S1, false, true>,
+                               infer_lds<H, NB3, S1, false, true>(), grid, a, stream);
+  else
+    return launch_infer_kernel(mlp_infer<H, NB3, S1, false, false>,
+                               infer_lds<H, NB3, S1, false, false>(), grid, a, stream);
+}
+
+template <int H> hipError_t launch_infer_nb(const MlpFwdArgs &a, hipStream_t s) {
+  const int nb3 = (a.C + 31) / 32, s1 = a.K1 / 16;
+  if (nb3 == 1 && s1 == 1) return launch_infer_h<H, 1, 1>(a, s);
+  if (nb3 == 1 && s1 == 2) return launch_infer_h<H, 1, 2>(a, s);
+  if (nb3 == 2 && s1 == 1) return launch_infer_h<H, 2, 1>(a, s);
+  if (nb3 == 2 && s1 == 2) return launch_infer_h<H, 2, 2>(a, s);
+  return hipErrorInvalidValue;
+}
+
 template <int H, int NB3, int S1, bool TRAIN, bool LDSW>
 hipError_t launch_fwd_t(const MlpFwdArgs &a, hipStream_t stream) {
   const uint32_t n_tiles = (a.n + 31) / 32;
@@ -467,11 +738,8 @@ hipError_t launch_fwd_t(const MlpFwdArgs &a, hipStream_t stream) {
 
 template <int H, int NB3, int S1>
 hipError_t launch_fwd_h(const MlpFwdArgs &a, bool train, hipStream_t stream) {
-  constexpr size_t lds = (size_t)(H * H + NB3 * 32 * H + H * 16 * S1) * 2;
-  constexpr bool fits = H <= 256 && lds <= 160 * 1024;
   if (train) return launch_fwd_t<H, NB3, S1, true, false>(a, stream);
-  if (fits) return launch_fwd_t<H, NB3, S1, false, fits>(a, stream);
-  return launch_fwd_t<H, NB3, S1, false, false>(a, stream);
+  return launch_infer_h<H, NB3, S1>(a, stream);
 }
 
 template <int H> hipError_t launch_fwd_nb(const MlpFwdArgs &a, bool train, hipStream_t s) {

@@ -57,8 +57,12 @@ def test_forward_matches_bf16_oracle(H, C):
     assert cos > 0.99999
 
 
-@pytest.mark.parametrize("H,C", [(64, 12), (256, 24), (512, 32)])
+@pytest.mark.parametrize("H,C", [(64, 12), (128, 40), (256, 24), (256, 40), (512, 32),
+                                 (512, 40)])
 def test_full_space_predictions_are_clamped_forward(H, C):
+    """Every valid configuration of the 30,720-configuration space (a ragged
+    last tile), through the inference kernels: weights resident in LDS
+    (H <= 256 when they fit) or the second layer's streamed through it."""
     m = cgs()
     spec, valid = _space()
     sp = m.Space.from_spec(spec)
@@ -69,6 +73,27 @@ def test_full_space_predictions_are_clamped_forward(H, C):
     ref = np.maximum(M.forward_bf16([np.asarray(p, np.float64) for p in params], X), 0.0)
     assert P.min() >= 0.0
     assert (np.abs(P - ref) <= _bound(params, X)).all()
+
+
+@pytest.mark.parametrize("H,C", [(64, 8), (256, 40), (512, 8), (512, 40)])
+def test_twenty_parameter_inference(H, C):
+    """Full-space inference with 20 inputs (two first-layer K steps), checked
+    on 4,000 sampled configurations and the last 70; at 512 / 40 the first
+    layer's weights are read from global memory instead of LDS."""
+    m = cgs()
+    radix = [2] * 20
+    values = [[1, 2]] * 20
+    sp = m.Space(radix, values, [("PROD_LE", 0, 1, 0, 2)])
+    params = _params(20, H, C, (33, H, C))
+    model = m.MLPModel(sp, params)
+    P = model.copy_predictions().astype(np.float64)
+    valid = sp.copy_valid()
+    g = np.random.default_rng(H + C)
+    pick = np.concatenate([g.choice(len(valid), 4000, replace=False),
+                           np.arange(len(valid) - 70, len(valid))])
+    X = M.features(SP.digits_of(valid[pick].astype(np.int64), radix))
+    ref = np.maximum(M.forward_bf16([np.asarray(p, np.float64) for p in params], X), 0.0)
+    assert (np.abs(P[pick] - ref) <= _bound(params, X)).all()
 
 
 def test_twenty_parameter_inputs_use_two_k_steps():
