@@ -45,10 +45,18 @@ __device__ __forceinline__ void normal_cdf_pdf(float z, float &cdf, float &pdf) 
   cdf = 0.5f * (1.0f + (z >= 0.0f ? erf_abs : -erf_abs));
   pdf = e * 0.3989422804014327f;
 }
+// GELU(z) = z Phi(z) = max(z, 0) - |z| Phi(-|z|), where 2 Phi(-|z|) =
+// erfc(|z| / sqrt 2) = t P(t) exp(-z^2 / 2) with t = 1 / (1 + p |z| / sqrt 2)
+// (A&S 7.1.26; the coefficients below are P's halved).  The tail term is
+// formed directly, so negative z lose nothing to cancellation.
 __device__ __forceinline__ float gelu(float z) {
-  float c, p;
-  normal_cdf_pdf(z, c, p);
-  return z * c;
+  const float az = fabsf(z);
+  const float t = __builtin_amdgcn_rcpf(fmaf(az, 0.3275911f * 0.70710678118654752f, 1.0f));
+  const float e = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f); // exp(-z^2 / 2)
+  const float poly =
+      0.127414796f +
+      t * (-0.142248368f + t * (0.7107068705f + t * (-0.7265760135f + t * 0.5307027145f)));
+  return fmaf(-(az * e) * t, poly, fmaxf(z, 0.0f));
 }
 __device__ __forceinline__ float gelu_grad(float z) {
   float c, p;
@@ -257,18 +265,20 @@ __global__ __launch_bounds__(LDSW ? 512 : 256) void mlp_forward(MlpFwdArgs a) {
 
 // ------------------------------------------------------------- inference
 // P[c][l] = max(y_c, 0) over the valid configurations idx[0..n), written for
-// throughput.  One wave per SIMD (up to 512 registers) carries T tiles of 32
-// configurations (T = 2 where registers allow, so every weight fragment read
-// from LDS feeds two MFMAs) and keeps their hidden activations in registers.
+// throughput.  One workgroup per CU, normally eight waves (two per SIMD); a
+// wave carries T tiles of 32 configurations and keeps their hidden
+// activations in registers, so one wave's bias + GELU epilogue (VALU) runs
+// beside the other wave's MFMAs.
 //   resident: W1, W2, W3 and the biases live in LDS for the whole launch
 //             (when they fit: H <= 256).
 //   stream:   W3, W1 and the biases live in LDS; W2 passes through a double
 //             buffer one 32-row block at a time, the next block's global
 //             loads overlapping the current block's MFMAs.
-// Either way the bias + GELU epilogue of one layer-2 block is independent of
-// the next block's MFMAs, so the two interleave.
-constexpr int kInferWaves = 4;
-template <int H> constexpr int infer_tiles() { return H <= 256 ? 2 : 1; }
+// tiles of 32 configurations per wave; waves per workgroup: two per SIMD
+// (256 registers each), or one (512) where two output blocks and wide hidden
+// layers would not fit
+template <int H> constexpr int infer_tiles() { return 1; }
+template <int H, int NB3> constexpr int infer_waves() { return NB3 == 2 && H >= 256 ? 4 : 8; }
 
 template <int T, int S1>
 __device__ __forceinline__ void infer_features(const MlpFwdArgs &a, uint32_t first, int hh,
@@ -292,6 +302,8 @@ __device__ __forceinline__ void infer_features(const MlpFwdArgs &a, uint32_t fir
 
 // Bias + GELU of one 32x32 accumulator block, as the two bf16 B fragments of
 // the next layer's K steps 2r and 2r + 1; `b` points at bias[32 r + 4 hh].
+// LOWREG: four values at a time (fewer live temporaries).
+template <bool LOWREG = false>
 __device__ __forceinline__ void gelu_frags(const f32x16 &acc, const float *b, bf16x8 &f0,
                                            bf16x8 &f1) {
 #pragma unroll
@@ -305,6 +317,7 @@ __device__ __forceinline__ void gelu_frags(const f32x16 &acc, const float *b, bf
       if (q < 2) f0[q * 4 + t] = v;
       else f1[(q - 2) * 4 + t] = v;
     }
+    if (LOWREG) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -363,7 +376,7 @@ __device__ __forceinline__ void infer_layer1(const bf16x8 *w1, const float *bias
 }
 
 // Epilogue of layer-2 block r: bias + GELU, then its two K steps of layer 3.
-template <int H, int T, int NB3>
+template <int H, int T, int NB3, bool LOWREG = false>
 __device__ __forceinline__ void infer_block_out(const f32x16 (&acc)[T], int r, const bf16x8 *w3,
                                                 const float *bias, int lane, int hh,
                                                 f32x16 (&accy)[NB3][T]) {
@@ -376,7 +389,7 @@ __device__ __forceinline__ void infer_block_out(const f32x16 (&acc)[T], int r, c
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     bf16x8 f0, f1;
-    gelu_frags(acc[t], bias + H + 32 * r + 4 * hh, f0, f1);
+    gelu_frags<LOWREG>(acc[t], bias + H + 32 * r + 4 * hh, f0, f1);
 #pragma unroll
     for (int r3 = 0; r3 < NB3; ++r3) {
       accy[r3][t] = mfma(w3f[r3][0], f0, accy[r3][t]);
@@ -392,18 +405,19 @@ constexpr size_t infer_lds() {
 }
 
 // RESIDENT: W2 stays in LDS; otherwise its 32-row blocks pass through a
-// double buffer.  Blocks are taken in pairs (A, B) so that one block's
-// epilogue is independent of the next block's MFMAs in the same stretch of
-// code.
+// double buffer.
 template <int H, int NB3, int S1, bool RESIDENT, bool W1LDS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mlp_infer(
+__global__ __launch_bounds__((infer_waves<H, NB3>() * 64))
+__attribute__((amdgpu_waves_per_eu((infer_waves<H, NB3>() / 4), (infer_waves<H, NB3>() / 4)))) void
+mlp_infer(
     MlpFwdArgs a) {
   constexpr int T = infer_tiles<H>(), NB = H / 32, S2 = H / 16;
+  constexpr int NW = infer_waves<H, NB3>(), NT = NW * 64;
   constexpr int NBLK = S2 * 64; // 16-byte units of one 32-row block of W2p
-  constexpr int PER = NBLK / 256;
+  constexpr int PER = RESIDENT ? 1 : NBLK / NT; // staged units per thread per block
   constexpr int N2 = RESIDENT ? NB * NBLK : 2 * NBLK;
   constexpr int N3 = NB3 * 32 * H / 8, N1 = H * 16 * S1 / 8;
-  static_assert(NB % 2 == 0 && NBLK % 256 == 0, "block pairs, whole units per thread");
+  static_assert(RESIDENT || NBLK % NT == 0, "whole staged units per thread");
   extern __shared__ bf16x8 lds[];
   bf16x8 *w2 = lds, *w3 = lds + N2, *w1l = w3 + N3;
   float *bias = reinterpret_cast<float *>(w1l + (W1LDS ? N1 : 0));
@@ -415,14 +429,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   __syncthreads();
   const int lane = threadIdx.x & 63, hh = lane >> 5, col = lane & 31;
   const int tid = threadIdx.x;
-  constexpr uint32_t kWgConfigs = 32 * T * kInferWaves;
+  constexpr uint32_t kWgConfigs = 32 * T * NW;
   const uint32_t n_wg = (a.n + kWgConfigs - 1) / kWgConfigs;
   // every wave of the block runs the same iterations (block barriers)
   for (uint32_t wg = blockIdx.x; wg < n_wg; wg += gridDim.x) {
     const uint32_t first = wg * kWgConfigs + (uint32_t)(tid / 64) * 32 * T;
     if (!RESIDENT) {
 #pragma unroll
-      for (int u = 0; u < PER; ++u) w2[u * 256 + tid] = a.w2p[u * 256 + tid];
+      for (int u = 0; u < PER; ++u) w2[u * NT + tid] = a.w2p[u * NT + tid];
     }
     bf16x8 xb[T][S1];
     bool ok[T];
@@ -435,55 +449,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
       for (int t = 0; t < T; ++t) accy[r3][t] = f32x16{};
     if (!RESIDENT) __syncthreads(); // block 0 in the first buffer
-    f32x16 accA[T], accB[T];
+    // with two waves per SIMD the other wave's MFMAs cover this one's epilogue
 #pragma unroll 1
-    for (int r = 0; r < NB; r += 2) {
-      const bf16x8 *wa = RESIDENT ? w2 + r * NBLK : w2;
-      const bf16x8 *wb = RESIDENT ? w2 + (r + 1) * NBLK : w2 + NBLK;
-      // block r; block r + 1 staged; epilogue of block r - 1
+    for (int r = 0; r < NB; ++r) {
+      const bf16x8 *wr = RESIDENT ? w2 + r * NBLK : w2 + (r & 1) * NBLK;
+      const bool more = !RESIDENT && r + 1 < NB;
       bf16x8 st[RESIDENT ? 1 : PER];
-      if (!RESIDENT) {
+      if (more) {
 #pragma unroll
-        for (int u = 0; u < PER; ++u) st[u] = a.w2p[(size_t)(r + 1) * NBLK + u * 256 + tid];
+        for (int u = 0; u < PER; ++u) st[u] = a.w2p[(size_t)(r + 1) * NBLK + u * NT + tid];
       }
+      f32x16 acc[T];
 #pragma unroll
-      for (int t = 0; t < T; ++t) accA[t] = f32x16{};
+      for (int t = 0; t < T; ++t) acc[t] = f32x16{};
 #pragma unroll
       for (int ks = 0; ks < S2; ++ks) {
-        const bf16x8 wf = wa[ks * 64 + lane];
+        const bf16x8 wf = wr[ks * 64 + lane];
 #pragma unroll
-        for (int t = 0; t < T; ++t) accA[t] = mfma(wf, h1[ks][t], accA[t]);
+        for (int t = 0; t < T; ++t) acc[t] = mfma(wf, h1[ks][t], acc[t]);
+        // at most four fragments in flight ahead of their MFMAs
+        if (ks % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       }
-      if (r > 0) infer_block_out<H, T, NB3>(accB, r - 1, w3, bias, lane, hh, accy);
-      if (!RESIDENT) {
+      infer_block_out<H, T, NB3, true>(acc, r, w3, bias, lane, hh, accy);
+      if (more) {
 #pragma unroll
-        for (int u = 0; u < PER; ++u) w2[NBLK + u * 256 + tid] = st[u];
-        __syncthreads();
+        for (int u = 0; u < PER; ++u) w2[((r + 1) & 1) * NBLK + u * NT + tid] = st[u];
       }
-      // block r + 1; block r + 2 staged; epilogue of block r
-      const bool more = r + 2 < NB;
-      if (!RESIDENT && more) {
-#pragma unroll
-        for (int u = 0; u < PER; ++u) st[u] = a.w2p[(size_t)(r + 2) * NBLK + u * 256 + tid];
-      }
-#pragma unroll
-      for (int t = 0; t < T; ++t) accB[t] = f32x16{};
-#pragma unroll
-      for (int ks = 0; ks < S2; ++ks) {
-        const bf16x8 wf = wb[ks * 64 + lane];
-#pragma unroll
-        for (int t = 0; t < T; ++t) accB[t] = mfma(wf, h1[ks][t], accB[t]);
-      }
-      infer_block_out<H, T, NB3>(accA, r, w3, bias, lane, hh, accy);
-      if (!RESIDENT) {
-        if (more) {
-#pragma unroll
-          for (int u = 0; u < PER; ++u) w2[u * 256 + tid] = st[u];
-        }
-        __syncthreads();
-      }
+      if (!RESIDENT) __syncthreads();
     }
-    infer_block_out<H, T, NB3>(accB, NB - 1, w3, bias, lane, hh, accy);
     infer_store<T, NB3>(a, accy, bias + 2 * H, first, hh, col, ok);
   }
 }
@@ -662,13 +655,13 @@ __global__ __launch_bounds__(256) void adam_pack(MlpShape sh, float *__restrict_
 }
 
 template <typename K>
-hipError_t launch_infer_kernel(K kernel, size_t lds, uint32_t grid, const MlpFwdArgs &a,
-                               hipStream_t stream) {
+hipError_t launch_infer_kernel(K kernel, size_t lds, uint32_t grid, uint32_t threads,
+                               const MlpFwdArgs &a, hipStream_t stream) {
   if (grid == 0) return hipSuccess;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), lds, stream, a);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -677,17 +670,18 @@ constexpr size_t kLdsBytes = 160 * 1024;
 template <int H, int NB3, int S1>
 hipError_t launch_infer_h(const MlpFwdArgs &a, hipStream_t stream) {
   const uint32_t cu = (uint32_t)std::max(a.n_cu, 1);
-  constexpr uint32_t wg_cfg = 32 * infer_tiles<H>() * kInferWaves;
+  constexpr uint32_t threads = infer_waves<H, NB3>() * 64;
+  constexpr uint32_t wg_cfg = 32 * infer_tiles<H>() * infer_waves<H, NB3>();
   const uint32_t grid = std::min<uint32_t>((a.n + wg_cfg - 1) / wg_cfg, cu);
   if constexpr (infer_lds<H, NB3, S1, true, true>() <= kLdsBytes)
     return launch_infer_kernel(mlp_infer<H, NB3, S1, true, true>,
-                               infer_lds<H, NB3, S1, true, true>(), grid, a, stream);
+                               infer_lds<H, NB3, S1, true, true>(), grid, threads, a, stream);
   else if constexpr (infer_lds<H, NB3, S1, false, true>() <= kLdsBytes)
     return launch_infer_kernel(mlp_infer<H, NB3, S1, false, true>,
-                               infer_lds<H, NB3, S1, false, true>(), grid, a, stream);
+                               infer_lds<H, NB3, S1, false, true>(), grid, threads, a, stream);
   else
     return launch_infer_kernel(mlp_infer<H, NB3, S1, false, false>,
-                               infer_lds<H, NB3, S1, false, false>(), grid, a, stream);
+                               infer_lds<H, NB3, S1, false, false>(), grid, threads, a, stream);
 }
 
 template <int H> hipError_t launch_infer_nb(const MlpFwdArgs &a, hipStream_t s) {
