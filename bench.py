@@ -62,17 +62,40 @@ def run_search(cgs, sp, model, U, pcs, thr, n_steps, timing):
     sess.search_step(model, cgs.NO_PROFILE)
     raw, l = sess.sample_next(int(U[0]))
     picks.append(l)
+    sess.step_wall_s = []
     for i in range(n_steps):
+        t0 = time.perf_counter()
         ep = cgs.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=CORES_PROFILED,
                                    threads=float(thr[i]))
         sess.search_step(model, raw, measured=pcs[i], expert=ep)
         raw, l = sess.sample_next(int(U[i + 1]))
+        sess.step_wall_s.append(time.perf_counter() - t0)
         picks.append(l)
     return picks, sess
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "score_pass_c2_traffic.md")
+VALU_PROFILE = os.path.join(ROOT, "profiles", "mlp_infer_valu.md")
 SWEEP_SOURCES = ("sweep.hip", "device_common.h", "internal.h")
+MLP_SOURCES = ("mlp.hip", "device_common.h", "internal.h")
+# VALU issue peak with packed FP32 off: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def counter_profile(path, sources):
+    """The JSON block of a committed counter profile, or None when it is
+    missing or was taken on other kernel sources (SHA-256 of the sources,
+    concatenated in order)."""
+    try:
+        text = open(path).read()
+        doc = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for name in sources:
+        with open(os.path.join(ROOT, "paper_2102_05297_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return doc if h.hexdigest() == doc.get("source_sha256") else None
 
 
 def pmc_traffic(active_counts):
@@ -80,21 +103,27 @@ def pmc_traffic(active_counts):
     active-counter counts, from the committed FETCH_SIZE / WRITE_SIZE profile
     (already scaled by the copy-kernel calibration); None when the profile is
     missing, lacks a count, or was taken on other kernel sources."""
-    try:
-        text = open(TRAFFIC_PROFILE).read()
-        doc = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    except (OSError, IndexError, ValueError):
-        return None
-    h = hashlib.sha256()
-    for name in SWEEP_SOURCES:
-        with open(os.path.join(ROOT, "paper_2102_05297_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != doc.get("source_sha256"):
+    doc = counter_profile(TRAFFIC_PROFILE, SWEEP_SOURCES)
+    if doc is None:
         return None
     per = {int(k): float(v) for k, v in doc["bytes_per_launch_by_active"].items()}
     if not active_counts or any(a not in per for a in active_counts):
         return None
     return sum(per[a] for a in active_counts) / len(active_counts)
+
+
+def valu_roofline(shape, n_configs, ms):
+    """ALU roofline of a perceptron inference sweep: VALU lane instructions
+    per second (counter-measured instructions per configuration x configs /
+    the live duration) against the issue peak; None without a matching
+    profile."""
+    doc = counter_profile(VALU_PROFILE, MLP_SOURCES)
+    per = None if doc is None else doc["valu_wave_instr_per_config"].get(shape)
+    if per is None or ms <= 0:
+        return None
+    achieved = per * 64 * n_configs / (ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_T,
+            "unit": "T VALU lane-instructions/s", "frac": achieved / VALU_PEAK_T}
 
 
 def copy_probe(n_bytes: int = 1 << 30, reps: int = 5) -> dict:
@@ -130,10 +159,11 @@ def copy_probe(n_bytes: int = 1 << 30, reps: int = 5) -> dict:
 BF16_PEAK_TFLOPS = 2500.0
 
 
-def mlp_path(cgs, sp, tree, U, pcs, thr, n_pairs=8192, steps=2000, batch=256, top_pairs=10):
+def mlp_path(cgs, sp, tree, n_pairs=8192, steps=2000, batch=256, top_pairs=100):
     """Learned surrogate: train on forest samples + N(0, 0.02) noise, predict
     every valid configuration, compare with the tree and time both uses."""
     import synth
+    U, pcs, thr = workload_inputs(max(top_pairs, 22))
     F_, H, Cn = len(sp.radix), 256, tree.n_counters
     valid = sp.copy_valid()
     g = synth.rng(3, 1)
@@ -200,6 +230,7 @@ def mlp_path(cgs, sp, tree, U, pcs, thr, n_pairs=8192, steps=2000, batch=256, to
         "inference_tflops": tflops,
         "mfma_roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_PEAK_TFLOPS,
                           "unit": "TFLOP/s", "frac": tflops / BF16_PEAK_TFLOPS},
+        "valu_roofline": valu_roofline(f"{F_}-{H}-{H}-{Cn}", sp.n_valid, inf_ms),
         "rmse_vs_tree": rmse, "rmse_sample": 65536,
         "top10_agreement": float(np.mean(agree)), "top10_pairs": top_pairs,
         "scored_per_s_cached": scored / (step_ms / 1e3),
@@ -351,6 +382,7 @@ def online_path(cgs, n_steps=200):
         "n_raw": sp.n_raw, "n_valid": sp.n_valid, "space_create_ms": t_space * 1e3,
         "tree_eval_ms": tree.eval_ms(), "mlp_first_train_ms": t_first * 1e3,
         "mlp_inference_ms": inf_ms, "mlp_inference_tflops": flop / (inf_ms / 1e3) / 1e12,
+        "mlp_inference_valu_roofline": valu_roofline(f"16-512-512-{C}", sp.n_valid, inf_ms),
         "windows": log["windows"], "retrain_ms_mean": float(np.mean(log["retrain_ms"])),
         "step_ms_median": float(np.median(log["step_ms"])), "steps": len(log["step_ms"]),
         "scored_per_s": float(sp.n_valid / (np.median(log["step_ms"]) / 1e3)),
@@ -388,13 +420,38 @@ def cpu_baseline(spec, forest, n_steps):
         t4 = time.perf_counter()
     t_eval, t_steps = t2 - t1, t4 - t3
     rate = len(sample) * n_steps / (t_eval + t_steps)
+    cpu_model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
-        "value": rate, "unit": "configs/s", "cores": 1, "kind": "oracle",
+        "value": rate, "unit": "configs/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model,
         "sample": (f"valid configurations with raw index < 2^22 of the same space ({len(sample)}): "
                    f"oracle model evaluation {t_eval:.2f} s + {n_steps} scored steps "
                    f"{t_steps:.2f} s; NumPy, one thread (enumeration {t1 - t0:.2f} s and the "
                    f"uniform start not counted)"),
     }
+
+
+def inference_sweeps(cgs):
+    """The perceptron inference of both workloads, untrained weights: the
+    12-256-256-24 network over the 2^24 space and the 16-512-512-32 network
+    over the 1.07e8 space (model load + two refreshes each)."""
+    import synth
+    for spec_fn, H, C, key in ((synth.space_c2, 256, 24, (3, 2)), (synth.space_c5, 512, 32, (5, 6))):
+        spec = spec_fn()
+        sp = cgs.Space.from_spec(spec)
+        init = synth.mlp_init(key, len(spec.radix), H, C)
+        model = cgs.MLPModel(sp, [init.w[0], init.b[0], init.w[1], init.b[1], init.w[2], init.b[2]])
+        for _ in range(2):
+            model.refresh()
+        log(f"inference {len(spec.radix)}-{H}-{H}-{C}: {sp.n_valid} configs, {model.eval_ms():.3f} ms")
+        model.close()
+        sp.close()
 
 
 def main() -> int:
@@ -406,6 +463,8 @@ def main() -> int:
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-online", action="store_true")
+    ap.add_argument("--inference-only", action="store_true",
+                    help="only the two perceptron inference sweeps (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the sweep runs on a single MI355X "
@@ -418,6 +477,10 @@ def main() -> int:
 
     import synth
     from paper_2102_05297_amd import cgs   # fails loudly without the HIP library
+
+    if args.inference_only:
+        inference_sweeps(cgs)
+        return 0
 
     spec = synth.space_c2()
     forest = synth.forest_c2(spec)
@@ -457,6 +520,9 @@ def main() -> int:
     value = scored / t_total
 
     ms, launches = sess.kernel_times()
+    wall = np.asarray(sess.step_wall_s) * 1e3
+    kavg = [ms[k] / max(1, launches[k]) for k in range(3)]  # ms per launch
+    device_step_ms = sum(kavg)
     # score pass of step j (0 = the uniform start, no active counter): reads
     # the rows of P of its active counters, writes s, reads the explored bits;
     # the timed launches are those of steps 0, k, 2k, ...
@@ -493,7 +559,7 @@ def main() -> int:
 
     mlp = None
     if not args.no_mlp:
-        mlp = mlp_path(cgs, sp, model, U, pcs, thr)
+        mlp = mlp_path(cgs, sp, model)
         log(f"mlp: {mlp}")
 
     cpu = None
@@ -532,6 +598,11 @@ def main() -> int:
             "launches": int(launches[0]),
             "avg_us": ms[0] / max(1, launches[0]) * 1e3,
         },
+        "step_wall_ms": {"median": float(np.median(wall)), "p10": float(np.percentile(wall, 10)),
+                         "p90": float(np.percentile(wall, 90))},
+        # N_u over the device time of one step (score + weight + draw averages
+        # over the timed steps); the wall-clock value above adds the host side
+        "device_rate_per_s": n_valid / (device_step_ms / 1e3) if device_step_ms > 0 else None,
         "kernel_avg_us": {
             "score_pass": ms[0] / max(1, launches[0]) * 1e3,
             "weight_pass": ms[1] / max(1, launches[1]) * 1e3,

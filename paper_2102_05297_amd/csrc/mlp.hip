@@ -483,24 +483,26 @@ mlp_infer(
 
 // ------------------------------------------------------------------ GEMM
 // C[M][N] = sum_k A(m, k) B(k, n), bf16 operands (converted on load), fp32
-// accumulation; one 32x32 output tile per wave.  Operands are addressed with
-// arbitrary strides so transposed products need no copies.
+// accumulation; one 32x32 output tile per workgroup, its K range split over
+// the workgroup's waves (kGemmThreads / 64), partial tiles summed in LDS.
+// Operands are addressed with arbitrary strides so transposed products need
+// no copies.
 template <typename T> __device__ __forceinline__ __bf16 to_bf16(T v);
 template <> __device__ __forceinline__ __bf16 to_bf16<float>(float v) { return (__bf16)v; }
 template <> __device__ __forceinline__ __bf16 to_bf16<__bf16>(__bf16 v) { return v; }
 
 template <typename TA, typename TB, int EPI>
 __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g) {
+  constexpr int NW = kGemmThreads / 64;
+  __shared__ float part[NW - 1][16][64];
   const TA *A = static_cast<const TA *>(g.A);
   const TB *B = static_cast<const TB *>(g.B);
-  const int tiles_n = (g.N + 31) / 32, tiles_m = (g.M + 31) / 32;
-  const int wave = blockIdx.x * (kGemmThreads / 64) + threadIdx.x / 64;
-  if (wave >= tiles_m * tiles_n) return;
-  const int m0 = (wave / tiles_n) * 32, n0 = (wave % tiles_n) * 32;
-  const int lane = threadIdx.x & 63, hh = lane >> 5, c = lane & 31;
+  const int tiles_n = (g.N + 31) / 32;
+  const int m0 = (blockIdx.x / tiles_n) * 32, n0 = (blockIdx.x % tiles_n) * 32;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hh = lane >> 5, c = lane & 31;
   const int m = m0 + c, n = n0 + c;
   f32x16 acc = {};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
+  for (int k0 = 16 * w; k0 < g.K; k0 += 16 * NW) {
     bf16x8 af, bf;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -512,8 +514,16 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g) {
     }
     acc = mfma(af, bf, acc);
   }
+  if (w > 0) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) part[w - 1][i][lane] = acc[i];
+  }
+  __syncthreads();
+  if (w != 0) return;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
+#pragma unroll
+    for (int q = 0; q < NW - 1; ++q) acc[i] += part[q][i][lane];
     const int row = m0 + 8 * (i / 4) + 4 * hh + (i % 4), cl = n0 + c;
     if (row >= g.M || cl >= g.N) continue;
     const size_t o = (size_t)row * g.ldc + cl;
@@ -558,28 +568,39 @@ __global__ __launch_bounds__(1024) void mse_grad(const float *__restrict__ Y, in
   }
 }
 
-// Bias gradients: column sums over the batch.
-__global__ __launch_bounds__(256) void bias_grads(const float *__restrict__ dz1,
-                                                  const float *__restrict__ dz2,
-                                                  const float *__restrict__ dyf, int n, int H,
-                                                  int C, int Cp, float *__restrict__ gb1,
-                                                  float *__restrict__ gb2,
-                                                  float *__restrict__ gb3) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t < H) {
-    float s = 0.0f;
-    for (int b = 0; b < n; ++b) s += dz1[(size_t)b * H + t];
-    gb1[t] = s;
-  } else if (t < 2 * H) {
-    const int h = t - H;
-    float s = 0.0f;
-    for (int b = 0; b < n; ++b) s += dz2[(size_t)b * H + h];
-    gb2[h] = s;
-  } else if (t < 2 * H + C) {
-    const int c = t - 2 * H;
-    float s = 0.0f;
-    for (int b = 0; b < n; ++b) s += dyf[(size_t)b * Cp + c];
-    gb3[c] = s;
+// Bias gradients: column sums over the batch.  A workgroup takes 64
+// consecutive columns (lane = column, coalesced rows); its 16 waves split the
+// rows and their partial sums meet in LDS.
+constexpr int kBiasWaves = 16;
+__global__ __launch_bounds__(kBiasWaves * 64) void bias_grads(
+    const float *__restrict__ dz1, const float *__restrict__ dz2, const float *__restrict__ dyf,
+    int n, int H, int C, int Cp, float *__restrict__ gb1, float *__restrict__ gb2,
+    float *__restrict__ gb3) {
+  __shared__ float part[kBiasWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const float *src = nullptr;
+  float *dst = nullptr;
+  int ld = 0, col = 0;
+  if (c < H) {
+    src = dz1, dst = gb1, ld = H, col = c;
+  } else if (c < 2 * H) {
+    src = dz2, dst = gb2, ld = H, col = c - H;
+  } else if (c < 2 * H + C) {
+    src = dyf, dst = gb3, ld = Cp, col = c - 2 * H;
+  }
+  float sum = 0.0f;
+  if (src) {
+#pragma unroll 4
+    for (int b = w; b < n; b += kBiasWaves) sum += src[(size_t)b * ld + col];
+  }
+  part[w][lane] = sum;
+  __syncthreads();
+  if (w == 0 && src) {
+    float t = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kBiasWaves; ++k) t += part[k][lane];
+    dst[col] = t;
   }
 }
 
@@ -758,9 +779,9 @@ hipError_t launch_mlp_forward(const MlpFwdArgs &a, bool train, hipStream_t strea
 }
 
 hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipStream_t stream) {
-  const int waves = ((g.M + 31) / 32) * ((g.N + 31) / 32);
-  if (waves == 0) return hipSuccess;
-  const dim3 grid((waves + 3) / 4), block(kGemmThreads);
+  const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+  if (tiles == 0) return hipSuccess;
+  const dim3 grid(tiles), block(kGemmThreads);
 #define GEMM_CASE(TA, TB, E)                                                                   \
   hipLaunchKernelGGL((gemm_bf16<TA, TB, E>), grid, block, 0, stream, g)
   if (a_bf16 && b_bf16 && epi == 0) GEMM_CASE(__bf16, __bf16, 0);
@@ -784,8 +805,8 @@ hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dy
                              int C, int Cp, float *gb1, float *gb2, float *gb3,
                              hipStream_t stream) {
   const int total = 2 * H + C;
-  hipLaunchKernelGGL(bias_grads, dim3((total + 255) / 256), dim3(256), 0, stream, dz1, dz2, dyf, n,
-                     H, C, Cp, gb1, gb2, gb3);
+  hipLaunchKernelGGL(bias_grads, dim3((total + 63) / 64), dim3(kBiasWaves * 64), 0, stream, dz1,
+                     dz2, dyf, n, H, C, Cp, gb1, gb2, gb3);
   return hipGetLastError();
 }
 
