@@ -323,7 +323,7 @@ def online_search(cgs, sp, tree, mlp, n_steps, deltas, U, noise, seed_cfg, seed_
     raw, l = sess.sample_next(int(U[0]))
     log["picks"].append(l)
     cfg.append(raw)
-    tgt.append(tree.copy_predictions(l, 1)[0] + noise[0])
+    tgt.append(tree.gather_predictions([l])[0] + noise[0])
     for i in range(1, n_steps + 1):
         if i % retrain_every == 0:
             t0 = time.perf_counter()
@@ -342,7 +342,7 @@ def online_search(cgs, sp, tree, mlp, n_steps, deltas, U, noise, seed_cfg, seed_
         raw, l = r
         log["picks"].append(l)
         cfg.append(raw)
-        tgt.append(tree.copy_predictions(l, 1)[0] + noise[i])
+        tgt.append(tree.gather_predictions([l])[0] + noise[i])
     return log
 
 
@@ -363,10 +363,7 @@ def online_path(cgs, n_steps=200):
     noise = synth.normal_noise(g, (n_steps + 1, C), 0.02)
     valid = sp.copy_valid()
     seed_pos = synth.uniform_indices(synth.rng(5, 4), 8192, sp.n_valid)
-    seed_tgt = np.empty((8192, C), dtype=np.float32)
-    for k in range(0, 8192, 1024):
-        sel = seed_pos[k:k + 1024]
-        seed_tgt[k:k + 1024] = np.stack([tree.copy_predictions(int(l), 1)[0] for l in sel])
+    seed_tgt = tree.gather_predictions(seed_pos)
     seed_tgt += synth.normal_noise(synth.rng(5, 5), (8192, C), 0.02)
     init = synth.mlp_init((5, 6), len(spec.radix), 512, C)
     mlp = cgs.MLPModel(sp, [init.w[0], init.b[0], init.w[1], init.b[1], init.w[2], init.b[2]])

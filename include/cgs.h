@@ -180,6 +180,11 @@ cgs_status cgs_model_refresh(cgs_model model);
 /* Predictions of valid configurations [first, first+count): dst[count][C]. */
 cgs_status cgs_model_copy_predictions(cgs_model model, uint64_t first, uint64_t count,
                                       float *dst_host);
+/* Predictions of the valid configurations listed in valid_idx_host[n] (any
+ * order, repeats allowed): dst[n][C].  An index outside the valid list is
+ * CGS_EINVAL. */
+cgs_status cgs_model_gather_predictions(cgs_model model, const uint32_t *valid_idx_host, uint64_t n,
+                                        float *dst_host);
 /* Root-mean-square difference of two models' predictions (same space, same
  * counters) over valid indices sample_host[n]: sqrt(mean over the sampled
  * configurations and the counters of (Pa - Pb)^2), summed in float64. */

@@ -38,6 +38,7 @@ EXPORTS = (
     "cgs_mlp_train", "cgs_mlp_gradients", "cgs_mlp_forward", "cgs_mlp_copy_params",
     "cgs_batch_create", "cgs_batch_step", "cgs_batch_step_time", "cgs_batch_autotune",
     "cgs_batch_set_schedule", "cgs_batch_destroy", "cgs_model_rmse",
+    "cgs_model_gather_predictions",
 )
 
 
@@ -116,6 +117,7 @@ _sig("cgs_model_refresh", [_p])
 _sig("cgs_model_copy_predictions", [_p, _u64, _u64, _p])
 _sig("cgs_model_copy_leaf_ids", [_p, _u64, _u64, _p])
 _sig("cgs_model_rmse", [_p, _p, _p, _u64, _ptr(C.c_double)])
+_sig("cgs_model_gather_predictions", [_p, _p, _u64, _p])
 _sig("cgs_model_destroy", [_p], None)
 _sig("cgs_session_create", [_p, _ptr(cgs_params), _ptr(_p)])
 _sig("cgs_search_step", [_p, _p, _u64, _p, _p, _ptr(cgs_expert_params)])
@@ -275,6 +277,14 @@ class _Model:
         out = np.zeros((count, self.n_counters), dtype=np.float32)
         _check(_lib.cgs_model_copy_predictions(self.h, first, count, _ptrof(out)),
                "cgs_model_copy_predictions")
+        return out
+
+    def gather_predictions(self, valid_idx) -> np.ndarray:
+        """Predictions [n][C] of the listed valid indices."""
+        idx = _arr(valid_idx, np.uint32)
+        out = np.zeros((len(idx), self.n_counters), dtype=np.float32)
+        _check(_lib.cgs_model_gather_predictions(self.h, _ptrof(idx), len(idx), _ptrof(out)),
+               "cgs_model_gather_predictions")
         return out
 
     def rmse(self, other: "_Model", sample) -> float:

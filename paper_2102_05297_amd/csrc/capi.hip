@@ -564,6 +564,38 @@ extern "C" cgs_status cgs_model_copy_predictions(cgs_model m, uint64_t first, ui
   return CGS_OK;
 }
 
+extern "C" cgs_status cgs_model_gather_predictions(cgs_model m, const uint32_t *idx, uint64_t n,
+                                                   float *dst) {
+  if (!m || ((!idx || !dst) && n)) return fail(CGS_EINVAL, "NULL argument");
+  if (n > 0xffffffffull / (uint64_t)CGS_MAX_COUNTERS)
+    return fail(CGS_ERANGE, "too many configurations in one gather");
+  if (n == 0) return CGS_OK;
+  cgs_space sp = m->space;
+  for (uint64_t i = 0; i < n; ++i)
+    if (idx[i] >= sp->n_valid)
+      return fail(CGS_EINVAL, "index %llu = %u is outside the valid list", (unsigned long long)i,
+                  idx[i]);
+  uint32_t *d_idx = nullptr;
+  float *d_out = nullptr;
+  hipError_t e = dalloc(&d_idx, n);
+  if (e == hipSuccess) e = dalloc(&d_out, n * (uint64_t)m->n_counters);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_idx, idx, n * sizeof(uint32_t), hipMemcpyHostToDevice, sp->stream);
+  if (e == hipSuccess)
+    e = launch_gather_rows(m->d_P, m->stride, m->n_counters, d_idx, (uint32_t)n, d_out,
+                           sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst, d_out, n * (uint64_t)m->n_counters * sizeof(float),
+                       hipMemcpyDeviceToHost, sp->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
+  dfree(d_idx);
+  dfree(d_out);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "gather: %s",
+                hipGetErrorString(e));
+  return CGS_OK;
+}
+
 extern "C" cgs_status cgs_model_rmse(cgs_model a, cgs_model b, const uint32_t *sample,
                                      uint64_t n, double *rmse) {
   if (!a || !b || !rmse || (!sample && n)) return fail(CGS_EINVAL, "NULL argument");

@@ -106,7 +106,29 @@ __global__ __launch_bounds__(256) void sq_diff(const float *__restrict__ Pa,
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Predictions of listed valid configurations: out[i][c] = P[c][idx[i]].
+__global__ __launch_bounds__(256) void gather_rows(const float *__restrict__ P, uint64_t stride,
+                                                   int n_counters,
+                                                   const uint32_t *__restrict__ idx, uint32_t n,
+                                                   float *__restrict__ out) {
+  const uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (uint64_t)n * n_counters) return;
+  const uint32_t i = (uint32_t)(e / n_counters);
+  const int c = (int)(e % n_counters);
+  out[e] = P[(size_t)c * stride + idx[i]];
+}
+
 } // namespace
+
+hipError_t launch_gather_rows(const float *P, uint64_t stride, int n_counters,
+                              const uint32_t *d_idx, uint32_t n, float *d_out,
+                              hipStream_t stream) {
+  const uint64_t total = (uint64_t)n * n_counters;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, P,
+                     stride, n_counters, d_idx, n, d_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_sq_diff(const float *Pa, const float *Pb, uint64_t stride_a, uint64_t stride_b,
                           int n_counters, const uint32_t *sample, uint32_t n, double *partial,

@@ -169,6 +169,9 @@ hipError_t launch_forest_eval(const SpaceDev *d_space, const uint32_t *d_idx, ui
                               uint16_t *d_leaf_out, uint32_t leaf_first, uint32_t leaf_count,
                               hipStream_t stream);
 
+hipError_t launch_gather_rows(const float *P, uint64_t stride, int n_counters,
+                              const uint32_t *d_idx, uint32_t n, float *d_out,
+                              hipStream_t stream);
 hipError_t launch_sq_diff(const float *Pa, const float *Pb, uint64_t stride_a, uint64_t stride_b,
                           int n_counters, const uint32_t *sample, uint32_t n, double *partial,
                           uint32_t grid, hipStream_t stream);

@@ -95,3 +95,25 @@ def test_forest_rejects_bad_input():
     with pytest.raises(m.CgsError) as ei:
         m.ForestModel(sp, np.array([[0]], np.uint8), np.array([[0]], np.uint8), bad)
     assert ei.value.status == m.EINVAL
+
+
+def test_gather_predictions_equal_the_oracle():
+    """Predictions of listed valid indices (unsorted, with repeats, both ends
+    of the list): equal to the full copy and to the oracle's float32 mean."""
+    m = cgs()
+    spec = synth.space_c1()
+    forest = synth.forest_c1(spec)
+    sp = m.Space.from_spec(spec)
+    model = m.ForestModel.from_spec(sp, forest)
+    valid = sp.copy_valid()
+    g = np.random.default_rng(11)
+    idx = np.concatenate([[len(valid) - 1, 0, 0], g.integers(0, len(valid), 5000)]).astype(np.uint32)
+    got = model.gather_predictions(idx)
+    assert (got == model.copy_predictions()[idx]).all()
+    ids = F.leaf_ids(forest.feat, forest.thr, forest.depth,
+                     SP.digits_of(valid[idx].astype(np.int64), spec.radix))
+    assert (got == F.predict_fp32(forest.leaves, ids)).all()
+    assert model.gather_predictions(np.zeros(0, np.uint32)).shape == (0, 12)
+    with pytest.raises(m.CgsError) as ei:
+        model.gather_predictions([len(valid)])
+    assert ei.value.status == m.EINVAL
