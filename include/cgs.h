@@ -69,6 +69,8 @@ typedef enum {
 #define CGS_MAX_COUNTERS 64         /* counters per model                      */
 #define CGS_MAX_TREES 64
 #define CGS_MAX_DEPTH 14
+#define CGS_MAX_RADIUS 3            /* neighbourhood radius of a restricted step */
+#define CGS_MAX_NEIGHBOURS 65536    /* neighbours of one restricted step        */
 /* raw space size: at most 2^32 - 1 configurations */
 
 /* Constraint kinds, over parameter values v[] of one configuration.
@@ -276,10 +278,42 @@ cgs_status cgs_search_step(cgs_session session, cgs_model model, uint64_t profil
                            const float *delta_host, const double *measured_host,
                            const cgs_expert_params *expert);
 
+/* Restricted step (Sect. 3.7, footnote to the scoring line of Alg. 1: for
+ * huge spaces only the neighbourhood of the profiled configuration need be
+ * scored).  Candidates: the valid, unexplored configurations whose parameter
+ * values differ from the profiled configuration's in 1..radius positions,
+ * in the order: distance, then the set of changed parameters
+ * (lexicographic), then their new digits (lexicographic, the profile's own
+ * digit skipped).  The step scores only the candidates (the score equation,
+ * same float32 chain as cgs_search_step), normalises over them (s_min /
+ * s_max over the candidates) and quantises the same way; draws
+ * (cgs_sample_next) pick among the candidates in candidate order.
+ *   profile_raw   must be a valid configuration (no CGS_NO_PROFILE)
+ *   radius        1..CGS_MAX_RADIUS
+ *   delta_host, measured_host, expert: as for cgs_search_step
+ * CGS_ERANGE when the neighbourhood has more than CGS_MAX_NEIGHBOURS
+ * configurations (valid or not), CGS_EEMPTY when it has none.  Records the
+ * step like cgs_search_step; cgs_session_copy_scores and
+ * cgs_session_copy_weights then answer CGS_ESTATE. */
+cgs_status cgs_search_step_neighbourhood(cgs_session session, cgs_model model,
+                                         uint64_t profile_raw, int radius,
+                                         const float *delta_host, const double *measured_host,
+                                         const cgs_expert_params *expert);
+
+/* The last restricted step's candidates in candidate order: valid indices,
+ * scores and quantised weights (weights of configurations drawn since are
+ * 0).  Each output may be NULL; *count receives the number of candidates
+ * (CGS_ERANGE when above capacity).  Synchronises.  CGS_ESTATE when the
+ * last step was not restricted. */
+cgs_status cgs_session_copy_neighbourhood(cgs_session session, uint64_t capacity,
+                                          uint32_t *valid_idx_host, float *scores_host,
+                                          uint32_t *q_host, uint64_t *count);
+
 /* Draw one configuration (Alg. 1): r = floor(u64 * Q / 2^64) with Q the sum
  * of weights; pick l with sum_{i<l} q_i <= r < sum_{i<=l} q_i (valid-index
- * order); mark it explored and zero its weight for further draws of this
- * step.  Synchronises.  CGS_EEMPTY when Q == 0.
+ * order, or candidate order after a restricted step); mark it explored and
+ * zero its weight for further draws of this step.  Synchronises.
+ * CGS_EEMPTY when Q == 0.
  *   raw_out / valid_out may be NULL. */
 cgs_status cgs_sample_next(cgs_session session, uint64_t u64, uint64_t *raw_out,
                            uint64_t *valid_out);
@@ -288,9 +322,10 @@ cgs_status cgs_sample_next(cgs_session session, uint64_t u64, uint64_t *raw_out,
 cgs_status cgs_session_step_info(cgs_session session, cgs_step_info *out);
 
 /* Device time per kernel kind, summed over the timed launches since session
- * creation (sessions created with params.timing > 0; zeros otherwise):
+ * creation (sessions created with params.timing > 0; zeros otherwise); slot
+ * [3] is the scoring of restricted steps (candidates and weights):
  *   total_ms[4] / launches[4]: [0] score pass, [1] weight pass, [2] draws,
- *   [3] reserved (0).  Synchronises. */
+ *   [3] restricted scoring (one launch = one step).  Synchronises. */
 cgs_status cgs_session_kernel_times(cgs_session session, double *total_ms, uint64_t *launches);
 
 /* Mark raw index k explored (must be valid). */

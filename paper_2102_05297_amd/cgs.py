@@ -23,6 +23,7 @@ _lib = C.CDLL(_LIB_PATH)
 OK, EINVAL, ENOMEM, EDEVICE, EEMPTY, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5, -6
 KIND_CODES = {"DIV": 0, "DIV2": 1, "PROD_LE": 2, "PROD3_LE": 3, "PROD_GE": 4, "LE": 5}
 MAX_PARAMS, MAX_RADIX, MAX_COUNTERS, MAX_TREES, MAX_DEPTH = 32, 16, 64, 64, 14
+MAX_RADIUS, MAX_NEIGHBOURS = 3, 65536
 NO_PROFILE = (1 << 64) - 1
 
 # The C-ABI function names, for symbol checks.
@@ -38,7 +39,8 @@ EXPORTS = (
     "cgs_mlp_train", "cgs_mlp_gradients", "cgs_mlp_forward", "cgs_mlp_copy_params",
     "cgs_batch_create", "cgs_batch_step", "cgs_batch_step_time", "cgs_batch_autotune",
     "cgs_batch_set_schedule", "cgs_batch_destroy", "cgs_model_rmse",
-    "cgs_model_gather_predictions",
+    "cgs_model_gather_predictions", "cgs_search_step_neighbourhood",
+    "cgs_session_copy_neighbourhood",
 )
 
 
@@ -121,6 +123,8 @@ _sig("cgs_model_gather_predictions", [_p, _p, _u64, _p])
 _sig("cgs_model_destroy", [_p], None)
 _sig("cgs_session_create", [_p, _ptr(cgs_params), _ptr(_p)])
 _sig("cgs_search_step", [_p, _p, _u64, _p, _p, _ptr(cgs_expert_params)])
+_sig("cgs_search_step_neighbourhood", [_p, _p, _u64, C.c_int, _p, _p, _ptr(cgs_expert_params)])
+_sig("cgs_session_copy_neighbourhood", [_p, _u64, _p, _p, _p, _ptr(_u64)])
 _sig("cgs_sample_next", [_p, _u64, _ptr(_u64), _ptr(_u64)])
 _sig("cgs_session_step_info", [_p, _ptr(cgs_step_info)])
 _sig("cgs_session_kernel_times", [_p, _p, _p])
@@ -413,6 +417,28 @@ class Session:
         m = None if measured is None else _arr(measured, np.float64)
         _check(_lib.cgs_search_step(self.h, model.h, int(profile_raw), _ptrof(d), _ptrof(m),
                                     C.byref(expert) if expert else None), "cgs_search_step")
+
+    def search_step_neighbourhood(self, model, profile_raw: int, radius: int, delta=None,
+                                  measured=None, expert: Optional[cgs_expert_params] = None) -> None:
+        d = None if delta is None else _arr(delta, np.float32)
+        m = None if measured is None else _arr(measured, np.float64)
+        _check(_lib.cgs_search_step_neighbourhood(self.h, model.h, int(profile_raw), int(radius),
+                                                  _ptrof(d), _ptrof(m),
+                                                  C.byref(expert) if expert else None),
+               "cgs_search_step_neighbourhood")
+
+    def copy_neighbourhood(self):
+        """(valid indices, scores, quantised weights) of the last restricted
+        step's candidates, in candidate order."""
+        n = _u64()
+        cap = MAX_NEIGHBOURS
+        idx = np.zeros(cap, dtype=np.uint32)
+        sc = np.zeros(cap, dtype=np.float32)
+        q = np.zeros(cap, dtype=np.uint32)
+        _check(_lib.cgs_session_copy_neighbourhood(self.h, cap, _ptrof(idx), _ptrof(sc), _ptrof(q),
+                                                   C.byref(n)), "cgs_session_copy_neighbourhood")
+        k = int(n.value)
+        return idx[:k].copy(), sc[:k].copy(), q[:k].copy()
 
     def sample_next(self, u64: int):
         """(raw index, valid index) of the drawn configuration; None when exhausted."""

@@ -70,6 +70,7 @@ struct cgs_space_s {
   SpaceDev *d_desc = nullptr;
   uint32_t *d_mask = nullptr;
   uint32_t *d_idx = nullptr;
+  uint32_t *d_rank = nullptr;  // valid configurations before each mask word
   std::vector<uint32_t> h_idx; // valid raw indices, for raw -> valid lookups
   // scratch for the standalone sampler
   DrawResult *d_res = nullptr;
@@ -111,7 +112,7 @@ constexpr uint32_t kTimeEvents = 512; // event markers of 128 timed steps
 struct TimedSpan {
   uint32_t ev;
   int n;
-  int kind[3]; // 0 score, 1 weight, 2 draw, 3 profile mark
+  int kind[3]; // 0 score, 1 weight, 2 draw, 3 profile mark, 4 neighbourhood score / finish
 };
 
 struct cgs_session_s {
@@ -146,6 +147,18 @@ struct cgs_session_s {
   int parity = 0;     // accumulator set of the next launched step
   int cur_acc = 0;    // accumulator set of the last launched step
   bool stepped = false;
+  // neighbourhood-restricted steps: the recorded one, the last launched one,
+  // the subset table on the device (built per radius) and candidate buffers
+  bool pending_nb = false;
+  NbStep pending_nbstep{};
+  bool last_nb = false;
+  int nb_radius = 0;
+  uint32_t *d_sub_off = nullptr, *d_sub_code = nullptr;
+  uint32_t *d_nb_tmp_idx = nullptr, *d_nb_idx = nullptr, *d_nb_q = nullptr;
+  float *d_nb_tmp_s = nullptr, *d_nb_s = nullptr;
+  uint64_t *d_nb_bsum = nullptr;
+  NbStats *d_nb_stats = nullptr;
+  StepAcc *d_nb_acc = nullptr;
   bool ran_in_batch = false; // the last step ran inside a batch step
   float batch_ms = 0.0f;     // device time of that batch step
   uint64_t seq = 0;          // sequence number of the last launched draw
@@ -198,6 +211,7 @@ void destroy_space(cgs_space sp) {
   dfree(sp->d_desc);
   dfree(sp->d_mask);
   dfree(sp->d_idx);
+  dfree(sp->d_rank);
   if (sp->h_res) (void)hipHostFree(sp->h_res);
   if (sp->own_stream && sp->stream) (void)hipStreamDestroy(sp->stream);
   delete sp;
@@ -282,6 +296,7 @@ extern "C" cgs_status cgs_space_create(int n_params, const int32_t *radix, const
   }
   SP_TRY(dalloc(&sp->d_desc, 1));
   SP_TRY(dalloc(&sp->d_mask, desc.n_words));
+  SP_TRY(dalloc(&sp->d_rank, desc.n_words));
   SP_TRY(hipHostMalloc(reinterpret_cast<void **>(&sp->h_res), sizeof(DrawResult),
                        hipHostMallocMapped));
   SP_TRY(hipHostGetDevicePointer(reinterpret_cast<void **>(&sp->d_res), sp->h_res, 0));
@@ -299,7 +314,7 @@ extern "C" cgs_status cgs_space_create(int n_params, const int32_t *radix, const
   hipError_t e = hipMemcpyAsync(sp->d_desc, &desc, sizeof(desc), hipMemcpyHostToDevice, sp->stream);
   if (e == hipSuccess)
     e = launch_enumeration(sp->d_desc, (uint32_t)n_raw, sp->d_mask, d_tile_count, d_tile_off,
-                           d_total, nullptr, 0, sp->stream);
+                           d_total, nullptr, nullptr, 0, sp->stream);
   uint64_t n_valid = 0;
   if (e == hipSuccess)
     e = hipMemcpyAsync(&n_valid, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, sp->stream);
@@ -307,7 +322,7 @@ extern "C" cgs_status cgs_space_create(int n_params, const int32_t *radix, const
   if (e == hipSuccess) e = dalloc(&sp->d_idx, n_valid);
   if (e == hipSuccess && n_valid > 0)
     e = launch_enumeration(sp->d_desc, (uint32_t)n_raw, sp->d_mask, d_tile_count, d_tile_off,
-                           d_total, sp->d_idx, 1, sp->stream);
+                           d_total, sp->d_idx, sp->d_rank, 1, sp->stream);
   if (e == hipSuccess && n_valid > 0) {
     try {
       sp->h_idx.resize(n_valid);
@@ -968,6 +983,16 @@ void destroy_session(cgs_session s) {
   dfree(s->d_s);
   dfree(s->d_bsum);
   dfree(s->d_acc);
+  dfree(s->d_sub_off);
+  dfree(s->d_sub_code);
+  dfree(s->d_nb_tmp_idx);
+  dfree(s->d_nb_idx);
+  dfree(s->d_nb_q);
+  dfree(s->d_nb_tmp_s);
+  dfree(s->d_nb_s);
+  dfree(s->d_nb_bsum);
+  dfree(s->d_nb_stats);
+  dfree(s->d_nb_acc);
   if (s->h_res) (void)hipHostFree(s->h_res);
   if (s->h_acc) (void)hipHostFree(s->h_acc);
   for (hipEvent_t ev : s->t_ev)
@@ -995,9 +1020,11 @@ hipError_t collect_times(cgs_session s) {
     for (int k = 0; k < sp.n && e == hipSuccess; ++k) {
       float ms = 0.0f;
       e = hipEventElapsedTime(&ms, s->t_ev[sp.ev + k], s->t_ev[sp.ev + k + 1]);
-      if (e == hipSuccess && sp.kind[k] <= 2) {
-        s->kernel_ms[sp.kind[k]] += ms;
-        s->kernel_n[sp.kind[k]] += 1;
+      // slots: 0 score pass, 1 weight pass, 2 draws, 3 restricted scoring
+      const int slot = sp.kind[k] <= 2 ? sp.kind[k] : sp.kind[k] == 4 ? 3 : -1;
+      if (e == hipSuccess && slot >= 0) {
+        s->kernel_ms[slot] += ms;
+        s->kernel_n[slot] += 1;
       }
     }
   }
@@ -1051,7 +1078,50 @@ cgs_status wait_draw(cgs_session s, const DrawResult *res, uint64_t seq) {
 
 // Enqueues the recorded step: score pass, weight pass, and either its first
 // draw (do_draw) or just the marking of its profiled configuration.
+// Enqueues the recorded neighbourhood step: candidate scoring, compaction and
+// weights, then either its first draw or the marking of its profile.
+hipError_t launch_pending_nb(cgs_session s, bool do_draw, uint64_t u64) {
+  cgs_space sp = s->space;
+  cgs_model m = s->pending_model;
+  const NbStep &st = s->pending_nbstep;
+  const uint32_t nv = (uint32_t)sp->n_valid;
+  const bool timed = s->params.timing > 0 && s->n_launched % (uint64_t)s->params.timing == 0;
+  hipError_t e = hipSuccess;
+  TimedSpan *span = nullptr;
+  if (timed) {
+    const int kinds[2] = {4, do_draw ? 2 : 3};
+    e = begin_span(s, 2, kinds, &span);
+    s->t_step = (int32_t)(s->t_spans.size() - 1);
+  }
+  if (e == hipSuccess)
+    e = launch_nb_score(st, s->d_sub_off, s->d_sub_code, sp->d_mask, sp->d_rank, s->d_explored,
+                        m->d_P, m->stride, s->d_nb_tmp_idx, s->d_nb_tmp_s, s->d_nb_acc,
+                        sp->stream);
+  if (e == hipSuccess)
+    e = launch_nb_finish(st.total, s->d_nb_tmp_idx, s->d_nb_tmp_s, s->d_nb_acc, s->params.gamma,
+                         s->params.w_min, s->d_nb_idx, s->d_nb_s, s->d_nb_q, s->d_nb_bsum,
+                         s->d_nb_stats, sp->stream);
+  if (e == hipSuccess && timed) e = mark_span(s, span, 0);
+  if (e == hipSuccess) {
+    if (do_draw)
+      e = launch_nb_draw(s->d_nb_q, s->d_nb_idx, s->d_nb_stats, s->d_nb_bsum, s->d_explored,
+                         st.profile, 1, nv, u64, sp->d_idx, s->d_res, ++s->seq, sp->stream);
+    else
+      e = launch_mark_one(s->d_explored, st.profile, nv, sp->stream);
+  }
+  if (e == hipSuccess && timed) e = mark_span(s, span, 1);
+  if (e != hipSuccess) return e;
+  ++s->n_launched;
+  s->step_timed = timed;
+  s->ran_in_batch = false;
+  s->last_nb = true;
+  s->pending = false;
+  s->pending_nb = false;
+  return hipSuccess;
+}
+
 hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
+  if (s->pending_nb) return launch_pending_nb(s, do_draw, u64);
   cgs_space sp = s->space;
   cgs_model m = s->pending_model;
   const uint32_t nv = (uint32_t)sp->n_valid;
@@ -1087,6 +1157,7 @@ hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
   ++s->n_launched;
   s->step_timed = timed;
   s->ran_in_batch = false;
+  s->last_nb = false;
   s->cur_acc = s->parity;
   s->parity ^= 1;
   s->pending = false;
@@ -1170,19 +1241,14 @@ extern "C" cgs_status cgs_session_create(cgs_space sp, const cgs_params *params,
   return CGS_OK;
 }
 
-extern "C" cgs_status cgs_search_step(cgs_session s, cgs_model m, uint64_t profile_raw,
-                                      const float *delta, const double *measured,
-                                      const cgs_expert_params *expert) {
-  if (!s || !m) return fail(CGS_EINVAL, "NULL session or model");
-  cgs_space sp = s->space;
-  if (m->space != sp) return fail(CGS_EINVAL, "model and session belong to different spaces");
+namespace {
+
+// Counters entering a step's score: dpc from `delta` (each in [-1, 1]) or
+// from the expert system on `measured` (24 Table 1 counters); none for the
+// start of a search.
+cgs_status step_counters(cgs_model m, bool no_profile, const float *delta, const double *measured,
+                         const cgs_expert_params *expert, ActiveCounters *act) {
   const int C = m->n_counters;
-  const bool no_profile = profile_raw == CGS_NO_PROFILE;
-  const int64_t prof = no_profile ? 0 : valid_index_of(sp, profile_raw);
-  if (prof < 0)
-    return fail(CGS_EINVAL, "profile %llu is not a valid configuration",
-                (unsigned long long)profile_raw);
-  if (sp->n_valid == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
   float dpc[CGS_MAX_COUNTERS] = {};
   if (no_profile) {
     // every score 0: uniform draw over unexplored configurations
@@ -1201,23 +1267,199 @@ extern "C" cgs_status cgs_search_step(cgs_session s, cgs_model m, uint64_t profi
     if (st != CGS_OK) return fail(st, "expert system rejected the measured counters");
     for (int c = 0; c < 24; ++c) dpc[c] = (float)d[c];
   }
-  // a step recorded but never drawn from still marks its profile and scores
-  const cgs_status st = flush_pending(s);
-  if (st != CGS_OK) return st;
-  ActiveCounters act{};
+  *act = ActiveCounters{};
   for (int c = 0; c < C; ++c)
     if (dpc[c] != 0.0f) {
-      act.ctr[act.n] = (uint32_t)c;
-      act.delta[act.n] = dpc[c];
-      ++act.n;
+      act->ctr[act->n] = (uint32_t)c;
+      act->delta[act->n] = dpc[c];
+      ++act->n;
     }
+  return CGS_OK;
+}
+
+// Subsets of 1..radius parameters in lexicographic order with the offset of
+// each subset's first neighbour; subsets containing a parameter with a
+// single value have no neighbours and are left out.
+cgs_status build_subsets(cgs_session s, int radius, uint32_t *n_subsets, uint32_t *total) {
+  const std::vector<int32_t> &r = s->space->radix;
+  const int P = (int)r.size();
+  std::vector<uint32_t> off{0}, code;
+  uint64_t run = 0;
+  auto add = [&](int n, int j0, int j1, int j2) {
+    uint64_t c = (uint64_t)(r[j0] - 1);
+    if (n > 1) c *= (uint64_t)(r[j1] - 1);
+    if (n > 2) c *= (uint64_t)(r[j2] - 1);
+    if (c == 0) return;
+    code.push_back((uint32_t)j0 | (uint32_t)(n > 1 ? j1 : 0) << 8 |
+                   (uint32_t)(n > 2 ? j2 : 0) << 16 | (uint32_t)n << 24);
+    run += c;
+    off.push_back((uint32_t)std::min<uint64_t>(run, 0xffffffffull));
+  };
+  for (int j = 0; j < P; ++j) add(1, j, 0, 0);
+  if (radius >= 2)
+    for (int j = 0; j < P; ++j)
+      for (int k = j + 1; k < P; ++k) add(2, j, k, 0);
+  if (radius >= 3)
+    for (int j = 0; j < P; ++j)
+      for (int k = j + 1; k < P; ++k)
+        for (int l = k + 1; l < P; ++l) add(3, j, k, l);
+  if (run > kNbMaxCandidates)
+    return fail(CGS_ERANGE, "radius %d gives %llu neighbours, more than %u", radius,
+                (unsigned long long)run, kNbMaxCandidates);
+  if (run == 0) return fail(CGS_EEMPTY, "the neighbourhood of radius %d is empty", radius);
+  const uint32_t n = (uint32_t)code.size();
+  dfree(s->d_sub_off);
+  dfree(s->d_sub_code);
+  s->nb_radius = 0;
+  hipError_t e = dalloc(&s->d_sub_off, n + 1);
+  if (e == hipSuccess) e = dalloc(&s->d_sub_code, n);
+  hipStream_t st = s->space->stream;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_sub_off, off.data(), (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice,
+                       st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_sub_code, code.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice,
+                       st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "subset table: %s",
+                hipGetErrorString(e));
+  s->nb_radius = radius;
+  *n_subsets = n;
+  *total = (uint32_t)run;
+  return CGS_OK;
+}
+
+// Candidate buffers of restricted steps, allocated on first use.
+cgs_status ensure_nb_buffers(cgs_session s) {
+  if (s->d_nb_stats) return CGS_OK;
+  hipError_t e = dalloc(&s->d_nb_tmp_idx, kNbMaxCandidates);
+  if (e == hipSuccess) e = dalloc(&s->d_nb_tmp_s, kNbMaxCandidates);
+  if (e == hipSuccess) e = dalloc(&s->d_nb_idx, kNbMaxCandidates);
+  if (e == hipSuccess) e = dalloc(&s->d_nb_s, kNbMaxCandidates);
+  if (e == hipSuccess) e = dalloc(&s->d_nb_q, kNbMaxCandidates);
+  if (e == hipSuccess) e = dalloc(&s->d_nb_bsum, kNbBlocks);
+  if (e == hipSuccess) e = dalloc(&s->d_nb_acc, kAccSlots);
+  if (e == hipSuccess) e = launch_reset_acc(s->d_nb_acc, kAccSlots, s->space->stream);
+  if (e == hipSuccess) e = dalloc(&s->d_nb_stats, 1);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->space->stream);
+  if (e != hipSuccess) {
+    dfree(s->d_nb_stats);
+    s->d_nb_stats = nullptr;
+    return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "neighbourhood buffers: %s",
+                hipGetErrorString(e));
+  }
+  return CGS_OK;
+}
+
+} // namespace
+
+extern "C" cgs_status cgs_search_step(cgs_session s, cgs_model m, uint64_t profile_raw,
+                                      const float *delta, const double *measured,
+                                      const cgs_expert_params *expert) {
+  if (!s || !m) return fail(CGS_EINVAL, "NULL session or model");
+  cgs_space sp = s->space;
+  if (m->space != sp) return fail(CGS_EINVAL, "model and session belong to different spaces");
+  const bool no_profile = profile_raw == CGS_NO_PROFILE;
+  const int64_t prof = no_profile ? 0 : valid_index_of(sp, profile_raw);
+  if (prof < 0)
+    return fail(CGS_EINVAL, "profile %llu is not a valid configuration",
+                (unsigned long long)profile_raw);
+  if (sp->n_valid == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
+  ActiveCounters act{};
+  cgs_status st = step_counters(m, no_profile, delta, measured, expert, &act);
+  if (st != CGS_OK) return st;
+  // a step recorded but never drawn from still marks its profile and scores
+  st = flush_pending(s);
+  if (st != CGS_OK) return st;
   s->pending = true;
+  s->pending_nb = false;
   s->pending_model = m;
   s->pending_profile = no_profile ? kNoProfile : (uint32_t)prof;
   s->pending_act = act;
   s->stepped = true;
   s->n_active = act.n;
   s->last_total = 0;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_search_step_neighbourhood(cgs_session s, cgs_model m,
+                                                    uint64_t profile_raw, int radius,
+                                                    const float *delta, const double *measured,
+                                                    const cgs_expert_params *expert) {
+  if (!s || !m) return fail(CGS_EINVAL, "NULL session or model");
+  cgs_space sp = s->space;
+  if (m->space != sp) return fail(CGS_EINVAL, "model and session belong to different spaces");
+  if (radius < 1 || radius > CGS_MAX_RADIUS)
+    return fail(CGS_EINVAL, "radius %d outside 1..%d", radius, CGS_MAX_RADIUS);
+  if (profile_raw == CGS_NO_PROFILE)
+    return fail(CGS_EINVAL, "a restricted step needs a profiled configuration");
+  const int64_t prof = valid_index_of(sp, profile_raw);
+  if (prof < 0)
+    return fail(CGS_EINVAL, "profile %llu is not a valid configuration",
+                (unsigned long long)profile_raw);
+  ActiveCounters act{};
+  cgs_status st = step_counters(m, false, delta, measured, expert, &act);
+  if (st != CGS_OK) return st;
+  st = flush_pending(s);
+  if (st != CGS_OK) return st;
+  st = ensure_nb_buffers(s);
+  if (st != CGS_OK) return st;
+  NbStep &nb = s->pending_nbstep;
+  if (s->nb_radius != radius) {
+    st = build_subsets(s, radius, &nb.n_subsets, &nb.total);
+    if (st != CGS_OK) return st;
+  }
+  const int P = sp->n_params;
+  uint64_t k = profile_raw, stride = 1;
+  for (int j = P - 1; j >= 0; --j) {
+    const uint32_t r = (uint32_t)sp->radix[j];
+    nb.radix[j] = (uint8_t)r;
+    nb.pdig[j] = (uint8_t)(k % r);
+    k /= r;
+    nb.stride[j] = (uint32_t)stride;
+    stride *= r;
+  }
+  nb.profile_raw = (uint32_t)profile_raw;
+  nb.profile = (uint32_t)prof;
+  nb.act = act;
+  s->pending = true;
+  s->pending_nb = true;
+  s->pending_model = m;
+  s->pending_profile = (uint32_t)prof;
+  s->pending_act = act;
+  s->stepped = true;
+  s->n_active = act.n;
+  s->last_total = 0;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_session_copy_neighbourhood(cgs_session s, uint64_t capacity,
+                                                     uint32_t *valid_idx, float *scores,
+                                                     uint32_t *q, uint64_t *count) {
+  if (!s || !count) return fail(CGS_EINVAL, "NULL argument");
+  const cgs_status st = flush_pending(s);
+  if (st != CGS_OK) return st;
+  if (!s->last_nb) return fail(CGS_ESTATE, "the last step was not restricted to a neighbourhood");
+  cgs_space sp = s->space;
+  NbStats stats{};
+  HIP_TRY(hipMemcpyAsync(&stats, s->d_nb_stats, sizeof stats, hipMemcpyDeviceToHost, sp->stream));
+  HIP_TRY(hipStreamSynchronize(sp->stream));
+  *count = stats.count;
+  if (stats.count > capacity)
+    return fail(CGS_ERANGE, "%u candidates, capacity %llu", stats.count,
+                (unsigned long long)capacity);
+  if (stats.count == 0) return CGS_OK;
+  if (valid_idx)
+    HIP_TRY(hipMemcpyAsync(valid_idx, s->d_nb_idx, stats.count * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, sp->stream));
+  if (scores)
+    HIP_TRY(hipMemcpyAsync(scores, s->d_nb_s, stats.count * sizeof(float), hipMemcpyDeviceToHost,
+                           sp->stream));
+  if (q)
+    HIP_TRY(hipMemcpyAsync(q, s->d_nb_q, stats.count * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           sp->stream));
+  HIP_TRY(hipStreamSynchronize(sp->stream));
   return CGS_OK;
 }
 
@@ -1235,10 +1477,15 @@ extern "C" cgs_status cgs_sample_next(cgs_session s, uint64_t u64, uint64_t *raw
       const int kinds[1] = {2};
       HIP_TRY(begin_span(s, 1, kinds, &span));
     }
-    HIP_TRY(launch_draw(s->d_s, s->d_explored, (uint32_t)sp->n_valid, kNoProfile, false,
-                        s->d_acc + s->cur_acc * kAccSlots, s->params.gamma, s->params.w_min,
-                        s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, s->d_res, ++s->seq,
-                        sp->stream));
+    if (s->last_nb)
+      HIP_TRY(launch_nb_draw(s->d_nb_q, s->d_nb_idx, s->d_nb_stats, s->d_nb_bsum, s->d_explored,
+                             kNoProfile, 0, (uint32_t)sp->n_valid, u64, sp->d_idx, s->d_res,
+                             ++s->seq, sp->stream));
+    else
+      HIP_TRY(launch_draw(s->d_s, s->d_explored, (uint32_t)sp->n_valid, kNoProfile, false,
+                          s->d_acc + s->cur_acc * kAccSlots, s->params.gamma, s->params.w_min,
+                          s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, s->d_res,
+                          ++s->seq, sp->stream));
     if (span) HIP_TRY(mark_span(s, span, 0));
   }
   const cgs_status ws = wait_draw(s, s->h_res, s->seq);
@@ -1262,14 +1509,23 @@ extern "C" cgs_status cgs_session_step_info(cgs_session s, cgs_step_info *out) {
   const cgs_status st = flush_pending(s);
   if (st != CGS_OK) return st;
   cgs_space sp = s->space;
-  HIP_TRY(hipMemcpyAsync(s->h_acc, s->d_acc + s->cur_acc * kAccSlots, kAccSlots * sizeof(StepAcc),
-                         hipMemcpyDeviceToHost, sp->stream));
-  HIP_TRY(hipStreamSynchronize(sp->stream));
   StepAccSums a{0xffffffffu, 0u, 0u};
-  for (int i = 0; i < kAccSlots; ++i) {
-    a.min_key = std::min(a.min_key, s->h_acc[i].min_key);
-    a.max_key = std::max(a.max_key, s->h_acc[i].max_key);
-    a.n_unexplored += s->h_acc[i].n_unexplored;
+  if (s->last_nb) {
+    // a restricted step: its candidates
+    NbStats stats{};
+    HIP_TRY(hipMemcpyAsync(&stats, s->d_nb_stats, sizeof stats, hipMemcpyDeviceToHost,
+                           sp->stream));
+    HIP_TRY(hipStreamSynchronize(sp->stream));
+    a = StepAccSums{stats.min_key, stats.max_key, stats.count};
+  } else {
+    HIP_TRY(hipMemcpyAsync(s->h_acc, s->d_acc + s->cur_acc * kAccSlots,
+                           kAccSlots * sizeof(StepAcc), hipMemcpyDeviceToHost, sp->stream));
+    HIP_TRY(hipStreamSynchronize(sp->stream));
+    for (int i = 0; i < kAccSlots; ++i) {
+      a.min_key = std::min(a.min_key, s->h_acc[i].min_key);
+      a.max_key = std::max(a.max_key, s->h_acc[i].max_key);
+      a.n_unexplored += s->h_acc[i].n_unexplored;
+    }
   }
   auto key_to_float = [](uint32_t k) {
     const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
@@ -1319,6 +1575,7 @@ extern "C" cgs_status cgs_session_copy_scores(cgs_session s, uint64_t first, uin
     return fail(CGS_ERANGE, "range outside the valid list");
   const cgs_status st = flush_pending(s);
   if (st != CGS_OK) return st;
+  if (s->last_nb) return fail(CGS_ESTATE, "the last step was restricted to a neighbourhood");
   if (count == 0) return CGS_OK;
   HIP_TRY(hipMemcpyAsync(dst, s->d_s + first, count * sizeof(float), hipMemcpyDeviceToHost,
                          sp->stream));
@@ -1335,6 +1592,7 @@ extern "C" cgs_status cgs_session_copy_weights(cgs_session s, uint64_t first, ui
     return fail(CGS_ERANGE, "range outside the valid list");
   const cgs_status st = flush_pending(s);
   if (st != CGS_OK) return st;
+  if (s->last_nb) return fail(CGS_ESTATE, "the last step was restricted to a neighbourhood");
   if (count == 0) return CGS_OK;
   uint32_t *d_q = nullptr;
   HIP_TRY(dalloc(&d_q, count));

@@ -9,7 +9,9 @@
 //   scan     one workgroup: exclusive scan of the tile counts -> tile offsets
 //            and the number of valid configurations
 //   compact  per tile: re-read the bitmask, rank set bits with popcounts and
-//            write the raw indices, ascending
+//            write the raw indices, ascending, and the rank of every mask
+//            word (valid configurations before it), so that a raw index
+//            maps to its valid index with one load and a popcount
 // Integer-only; the output is independent of scheduling.
 #include "device_common.h"
 
@@ -81,7 +83,8 @@ __global__ __launch_bounds__(kScanThreads) void enum_scan(const uint32_t *__rest
 __global__ __launch_bounds__(kEnumThreads) void enum_compact(const SpaceDev *__restrict__ sp,
                                                              const uint32_t *__restrict__ mask,
                                                              const uint32_t *__restrict__ tile_off,
-                                                             uint32_t *__restrict__ idx) {
+                                                             uint32_t *__restrict__ idx,
+                                                             uint32_t *__restrict__ word_rank) {
   __shared__ uint32_t wave_cnt[kEnumThreads / kWave];
   const uint32_t n_words = sp->n_words;
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
@@ -99,6 +102,8 @@ __global__ __launch_bounds__(kEnumThreads) void enum_compact(const SpaceDev *__r
     const uint64_t lo = wi < n_words ? mask[wi] : 0u;
     const uint64_t hi = wi + 1 < n_words ? mask[wi + 1] : 0u;
     const uint64_t bits = lo | (hi << 32);
+    if (lane == 0 && wi < n_words) word_rank[wi] = off;
+    if (lane == 1 && wi + 1 < n_words) word_rank[wi + 1] = off + (uint32_t)__popc((uint32_t)lo);
     if ((bits >> lane) & 1ull) {
       const uint32_t rank = (uint32_t)__popcll(bits & ((1ull << lane) - 1ull));
       idx[off + rank] = (uint32_t)(wave_base + (uint64_t)row * kWave + lane);
@@ -113,10 +118,11 @@ uint32_t enumeration_tiles(uint32_t n_raw) {
   return (uint32_t)(((uint64_t)n_raw + kTile - 1) / kTile);
 }
 
-// phase 0: mark + scan (then the host reads *d_total); phase 1: compact.
+// phase 0: mark + scan (then the host reads *d_total); phase 1: compact and
+// word ranks.
 hipError_t launch_enumeration(const SpaceDev *d_space, uint32_t n_raw, uint32_t *d_mask,
                               uint32_t *d_tile_count, uint32_t *d_tile_off, uint64_t *d_total,
-                              uint32_t *d_idx, int phase, hipStream_t stream) {
+                              uint32_t *d_idx, uint32_t *d_rank, int phase, hipStream_t stream) {
   const uint32_t n_tiles = enumeration_tiles(n_raw);
   if (n_tiles == 0) return hipSuccess;
   if (phase == 0) {
@@ -126,7 +132,7 @@ hipError_t launch_enumeration(const SpaceDev *d_space, uint32_t n_raw, uint32_t 
                        d_tile_off, d_total);
   } else {
     hipLaunchKernelGGL(enum_compact, dim3(n_tiles), dim3(kEnumThreads), 0, stream, d_space,
-                       d_mask, d_tile_off, d_idx);
+                       d_mask, d_tile_off, d_idx, d_rank);
   }
   return hipGetLastError();
 }

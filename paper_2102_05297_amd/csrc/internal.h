@@ -66,6 +66,32 @@ struct DrawResult {
 constexpr uint64_t kNoPick = ~0ull;
 constexpr uint32_t kNoProfile = ~0u; // step prologue: no configuration to mark
 
+// ---- neighbourhood-restricted steps
+// Candidates are the configurations that differ from the profiled one in
+// 1..radius parameters, ordered by the set of changed parameters (a table of
+// subsets in that order, with the offset of each subset's first candidate)
+// and then by the new digits.  Arguments of one step, by value.
+constexpr uint32_t kNbMaxCandidates = 65536;
+constexpr int kNbBlockLog2 = 12;
+constexpr uint32_t kNbBlocks = kNbMaxCandidates >> kNbBlockLog2;
+struct NbStep {
+  uint32_t profile_raw;
+  uint32_t profile;  // valid index of the profiled configuration
+  uint32_t total;    // candidates before filtering
+  uint32_t n_subsets;
+  uint32_t stride[CGS_MAX_PARAMS]; // raw place values
+  uint8_t radix[CGS_MAX_PARAMS];
+  uint8_t pdig[CGS_MAX_PARAMS];    // the profile's digits
+  ActiveCounters act;
+};
+// Per-step results of the restricted step (device memory).
+struct NbStats {
+  uint32_t count;    // candidates kept (valid, unexplored)
+  uint32_t pad;
+  uint64_t total;    // sum of their quantised weights
+  uint32_t min_key, max_key;
+};
+
 // ---- batched sessions: one descriptor per session (device memory) and one
 // step record per session (refreshed from pinned memory before each step)
 struct BatchSess {
@@ -160,7 +186,7 @@ hipError_t launch_adam_pack(const MlpShape &sh, float *theta, float *m, float *v
 // ---- launchers (each enqueues on `stream`; return hipSuccess or an error)
 hipError_t launch_enumeration(const SpaceDev *d_space, uint32_t n_raw, uint32_t *d_mask,
                               uint32_t *d_tile_count, uint32_t *d_tile_off, uint64_t *d_total,
-                              uint32_t *d_idx, int phase, hipStream_t stream);
+                              uint32_t *d_idx, uint32_t *d_rank, int phase, hipStream_t stream);
 uint32_t enumeration_tiles(uint32_t n_raw);
 
 hipError_t launch_forest_eval(const SpaceDev *d_space, const uint32_t *d_idx, uint32_t n_valid,
@@ -190,6 +216,22 @@ hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
                        const uint32_t *d_idx, DrawResult *d_res, uint64_t seq,
                        hipStream_t stream);
 hipError_t launch_mark_one(uint32_t *d_explored, uint32_t l, uint32_t n_valid, hipStream_t stream);
+// Neighbourhood-restricted step: score the candidates (tmp arrays indexed by
+// candidate, accumulators in nb_acc), then compact, weigh and block-sum them.
+hipError_t launch_nb_score(const NbStep &st, const uint32_t *d_sub_off, const uint32_t *d_sub_code,
+                           const uint32_t *d_mask, const uint32_t *d_rank,
+                           const uint32_t *d_explored, const float *d_P, uint64_t stride,
+                           uint32_t *d_tmp_idx, float *d_tmp_s, StepAcc *d_nb_acc,
+                           hipStream_t stream);
+hipError_t launch_nb_finish(uint32_t total, const uint32_t *d_tmp_idx, const float *d_tmp_s,
+                            StepAcc *d_nb_acc, float gamma, float w_min, uint32_t *d_nb_idx,
+                            float *d_nb_s, uint32_t *d_nb_q, uint64_t *d_nb_bsum,
+                            NbStats *d_stats, hipStream_t stream);
+// One draw among the candidates; the step's first draw also marks `profile`.
+hipError_t launch_nb_draw(uint32_t *d_nb_q, const uint32_t *d_nb_idx, const NbStats *d_stats,
+                          uint64_t *d_nb_bsum, uint32_t *d_explored, uint32_t profile,
+                          int mark_profile, uint32_t n_valid, uint64_t u64, const uint32_t *d_idx,
+                          DrawResult *d_res, uint64_t seq, hipStream_t stream);
 hipError_t launch_copy_weights(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
                                const StepAcc *d_acc, float gamma, float w_min, uint32_t first,
                                uint32_t count, uint32_t *d_q, hipStream_t stream);

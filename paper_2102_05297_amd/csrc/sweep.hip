@@ -235,6 +235,8 @@ struct ScoreWeights {
     }
   }
   __device__ void remove(uint32_t l) const { atomicOr(&explored[l >> 5], 1u << (l & 31u)); }
+  __device__ uint64_t valid_of(uint32_t l) const { return l; }
+  __device__ uint64_t raw_of(uint32_t l, const uint32_t *idx) const { return idx ? idx[l] : l; }
 };
 struct ArrayWeights {
   uint32_t *q;
@@ -251,6 +253,34 @@ struct ArrayWeights {
     }
   }
   __device__ void remove(uint32_t l) const { q[l] = 0u; }
+  __device__ uint64_t valid_of(uint32_t l) const { return l; }
+  __device__ uint64_t raw_of(uint32_t l, const uint32_t *idx) const { return idx ? idx[l] : l; }
+};
+// Quantised weights of a restricted step's candidates (position l in
+// candidate order): drawing candidate l removes it and marks its
+// configuration nb[l] explored.
+struct NbWeights {
+  uint32_t *q;
+  const uint32_t *nb;
+  uint32_t *explored;
+  uint32_t n;
+  __device__ void stage_load() {}
+  __device__ void stage_reduce(StepAccSums *) const {}
+  __device__ void stage_read(const StepAccSums *) {}
+  __device__ uint32_t operator()(uint32_t l) const { return l < n ? q[l] : 0u; }
+  template <int K> __device__ void run(uint32_t first, uint32_t cnt, uint32_t (&out)[K]) const {
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      const uint32_t l = first + e;
+      out[e] = ((uint32_t)e < cnt && l < n) ? q[l] : 0u;
+    }
+  }
+  __device__ void remove(uint32_t l) const {
+    q[l] = 0u;
+    atomicOr(&explored[nb[l] >> 5], 1u << (nb[l] & 31u));
+  }
+  __device__ uint64_t valid_of(uint32_t l) const { return nb[l]; }
+  __device__ uint64_t raw_of(uint32_t l, const uint32_t *idx) const { return idx[nb[l]]; }
 };
 
 // The draw result lives in mapped, coherent pinned host memory.  The thread
@@ -379,7 +409,7 @@ __device__ void draw_body(W &wsrc, int block_log2, uint64_t *__restrict__ bsum,
       wsrc.remove(l);
       bsum[blk] -= ql;
       picked = 1;
-      publish(res, l, idx ? idx[l] : l, Q, r, seq);
+      publish(res, wsrc.valid_of(l), wsrc.raw_of(l, idx), Q, r, seq);
     }
   }
   __syncthreads();
@@ -536,6 +566,158 @@ __global__ __launch_bounds__(kDrawThreads) void batch_draw(const BatchSess *__re
     atomicOr(&d.explored[st.profile >> 5], 1u << (st.profile & 31u));
 }
 
+// ------------------------------------------------------------ neighbourhood
+// The restricted step scores only candidates near the profiled configuration:
+// one thread per candidate (before filtering) unranks it, keeps it if it is
+// valid and unexplored, and scores it with the float32 chain of the full
+// pass; one workgroup then compacts the kept candidates in candidate order,
+// quantises their weights over the kept set and forms the block sums.
+constexpr int kNbThreads = 256;
+constexpr uint32_t kNbMaxSubsets = 32 + 32 * 31 / 2 + 32 * 31 * 30 / 6; // radius <= 3
+
+__global__ __launch_bounds__(kNbThreads) void nb_score(
+    NbStep st, const uint32_t *__restrict__ sub_off, const uint32_t *__restrict__ sub_code,
+    const uint32_t *__restrict__ mask, const uint32_t *__restrict__ rank,
+    const uint32_t *__restrict__ explored, const float *__restrict__ P, uint64_t stride,
+    uint32_t *__restrict__ tmp_idx, float *__restrict__ tmp_s, StepAcc *__restrict__ acc) {
+  __shared__ uint32_t off_lds[kNbMaxSubsets + 1];
+  __shared__ float a_lds[CGS_MAX_COUNTERS];
+  for (uint32_t i = threadIdx.x; i <= st.n_subsets; i += kNbThreads) off_lds[i] = sub_off[i];
+  if (threadIdx.x < (uint32_t)st.act.n)
+    a_lds[threadIdx.x] = P[(size_t)st.act.ctr[threadIdx.x] * stride + st.profile];
+  __syncthreads();
+  uint32_t kmin = 0xffffffffu, kmax = 0u, cnt = 0u;
+  const uint32_t f = blockIdx.x * kNbThreads + threadIdx.x;
+  if (f < st.total) {
+    // subset holding candidate f: the last one whose first candidate <= f
+    uint32_t lo = 0, hi = st.n_subsets;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (off_lds[mid] <= f) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t code = sub_code[lo];
+    uint32_t u = f - off_lds[lo];
+    int64_t raw = st.profile_raw;
+    // new digits of the changed parameters, the last one fastest; the
+    // profile's own digit is skipped
+    for (int k = (int)(code >> 24) - 1; k >= 0; --k) {
+      const uint32_t j = (code >> (8 * k)) & 0xffu;
+      const uint32_t alt = st.radix[j] - 1u;
+      const uint32_t a = u % alt;
+      u /= alt;
+      const uint32_t pd = st.pdig[j];
+      const uint32_t v = a < pd ? a : a + 1u;
+      raw += ((int64_t)v - (int64_t)pd) * (int64_t)st.stride[j];
+    }
+    const uint32_t rw = (uint32_t)raw;
+    const uint32_t word = mask[rw >> 5], rk = rank[rw >> 5];
+    bool keep = (word >> (rw & 31u)) & 1u;
+    uint32_t l = 0;
+    if (keep) {
+      l = rk + (uint32_t)__popc(word & ((1u << (rw & 31u)) - 1u));
+      keep = !((explored[l >> 5] >> (l & 31u)) & 1u);
+    }
+    float s = 0.0f;
+    if (keep) {
+      for (int j0 = 0; j0 < st.act.n; j0 += kRowsInFlight) {
+        float x[kRowsInFlight];
+#pragma unroll
+        for (int u2 = 0; u2 < kRowsInFlight; ++u2)
+          if (j0 + u2 < st.act.n) x[u2] = P[(size_t)st.act.ctr[j0 + u2] * stride + l];
+#pragma unroll
+        for (int u2 = 0; u2 < kRowsInFlight; ++u2) {
+          if (j0 + u2 < st.act.n && a_lds[j0 + u2] != 0.0f) {
+            const float ap = a_lds[j0 + u2];
+            const float t = (x[u2] - ap) / (ap + x[u2]);
+            s = (x[u2] != 0.0f) ? s + st.act.delta[j0 + u2] * t : s;
+          }
+        }
+      }
+      const uint32_t k = float_key(s);
+      kmin = k;
+      kmax = k;
+      cnt = 1;
+    }
+    tmp_idx[f] = keep ? l : 0xffffffffu;
+    tmp_s[f] = s;
+  }
+  flush_acc(kmin, kmax, cnt, acc + (blockIdx.x & (kAccSlots - 1)));
+}
+
+constexpr int kNbFinishThreads = 1024;
+
+__global__ __launch_bounds__(kNbFinishThreads) void nb_finish(
+    uint32_t total, const uint32_t *__restrict__ tmp_idx, const float *__restrict__ tmp_s,
+    StepAcc *__restrict__ acc, float gamma, float w_min, uint32_t *__restrict__ nb_idx,
+    float *__restrict__ nb_s, uint32_t *__restrict__ nb_q, uint64_t *__restrict__ nb_bsum,
+    NbStats *__restrict__ stats) {
+  constexpr uint32_t kChunk = 8;
+  __shared__ uint64_t scratch[kNbFinishThreads / kWave];
+  __shared__ StepAccSums sums;
+  __shared__ unsigned long long bsum_lds[kNbBlocks];
+  const uint32_t tid = threadIdx.x;
+  StepAcc slot{};
+  if (tid < kWave) slot = acc[tid];
+  if (tid < kNbBlocks) bsum_lds[tid] = 0ull;
+  const uint32_t per = (total + kNbFinishThreads - 1) / kNbFinishThreads;
+  const uint32_t f0 = min(total, tid * per), f1 = min(total, f0 + per);
+  uint32_t kept = 0;
+  for (uint32_t f = f0; f < f1; f += kChunk) {
+    uint32_t v[kChunk];
+#pragma unroll
+    for (uint32_t k = 0; k < kChunk; ++k) v[k] = f + k < f1 ? tmp_idx[f + k] : 0xffffffffu;
+#pragma unroll
+    for (uint32_t k = 0; k < kChunk; ++k) kept += v[k] != 0xffffffffu;
+  }
+  reduce_slot_values(slot, &sums);
+  uint64_t count;
+  uint64_t pos = block_excl_scan<kNbFinishThreads>(kept, scratch, count); // barriers publish sums
+  const float s_min = key_float(sums.min_key), s_max = key_float(sums.max_key);
+  for (uint32_t f = f0; f < f1; f += kChunk) {
+    uint32_t v[kChunk];
+    float sv[kChunk];
+#pragma unroll
+    for (uint32_t k = 0; k < kChunk; ++k) {
+      v[k] = f + k < f1 ? tmp_idx[f + k] : 0xffffffffu;
+      sv[k] = f + k < f1 ? tmp_s[f + k] : 0.0f;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kChunk; ++k) {
+      if (v[k] == 0xffffffffu) continue;
+      const uint32_t q = quantized_weight(sv[k], false, s_min, s_max, gamma, w_min);
+      nb_idx[pos] = v[k];
+      nb_s[pos] = sv[k];
+      nb_q[pos] = q;
+      atomicAdd(&bsum_lds[pos >> kNbBlockLog2], (unsigned long long)q);
+      ++pos;
+    }
+  }
+  __syncthreads();
+  if (tid < kNbBlocks) nb_bsum[tid] = bsum_lds[tid];
+  if (tid == 0) {
+    uint64_t q_total = 0;
+    for (uint32_t b = 0; b < kNbBlocks; ++b) q_total += bsum_lds[b];
+    stats->count = (uint32_t)count;
+    stats->total = q_total;
+    stats->min_key = sums.min_key;
+    stats->max_key = sums.max_key;
+  }
+  clear_acc(acc); // every slot was read before the scan's barriers
+}
+
+__global__ __launch_bounds__(kDrawThreads) void nb_draw(
+    uint32_t *__restrict__ q, const uint32_t *__restrict__ nb, const NbStats *__restrict__ stats,
+    uint64_t *__restrict__ bsum, uint32_t *__restrict__ explored, uint32_t profile,
+    int mark_profile, uint32_t n_valid, uint64_t u64, const uint32_t *__restrict__ idx,
+    DrawResult *__restrict__ res, uint64_t seq) {
+  NbWeights w{q, nb, explored, stats->count};
+  draw_body<kDrawThreads>(w, kNbBlockLog2, bsum, kNbBlocks, u64, idx, res, seq);
+  __syncthreads();
+  if (threadIdx.x == 0 && mark_profile && profile < n_valid)
+    atomicOr(&explored[profile >> 5], 1u << (profile & 31u));
+}
+
 // Marks the profiled configuration explored (a step read without a draw).
 __global__ __launch_bounds__(64) void mark_one(uint32_t *__restrict__ explored, uint32_t l,
                                                uint32_t n_valid) {
@@ -657,6 +839,39 @@ hipError_t launch_batch_draw(const BatchSess *d_sess, const BatchStep *d_step, u
 hipError_t launch_mark_one(uint32_t *d_explored, uint32_t l, uint32_t n_valid,
                            hipStream_t stream) {
   hipLaunchKernelGGL(mark_one, dim3(1), dim3(64), 0, stream, d_explored, l, n_valid);
+  return hipGetLastError();
+}
+
+hipError_t launch_nb_score(const NbStep &st, const uint32_t *d_sub_off, const uint32_t *d_sub_code,
+                           const uint32_t *d_mask, const uint32_t *d_rank,
+                           const uint32_t *d_explored, const float *d_P, uint64_t stride,
+                           uint32_t *d_tmp_idx, float *d_tmp_s, StepAcc *d_nb_acc,
+                           hipStream_t stream) {
+  if (st.total == 0 || st.total > kNbMaxCandidates || st.n_subsets > kNbMaxSubsets)
+    return hipErrorInvalidValue;
+  const uint32_t grid = (st.total + kNbThreads - 1) / kNbThreads;
+  hipLaunchKernelGGL(nb_score, dim3(grid), dim3(kNbThreads), 0, stream, st, d_sub_off, d_sub_code,
+                     d_mask, d_rank, d_explored, d_P, stride, d_tmp_idx, d_tmp_s, d_nb_acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_nb_finish(uint32_t total, const uint32_t *d_tmp_idx, const float *d_tmp_s,
+                            StepAcc *d_nb_acc, float gamma, float w_min, uint32_t *d_nb_idx,
+                            float *d_nb_s, uint32_t *d_nb_q, uint64_t *d_nb_bsum,
+                            NbStats *d_stats, hipStream_t stream) {
+  if (total > kNbMaxCandidates) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(nb_finish, dim3(1), dim3(kNbFinishThreads), 0, stream, total, d_tmp_idx,
+                     d_tmp_s, d_nb_acc, gamma, w_min, d_nb_idx, d_nb_s, d_nb_q, d_nb_bsum,
+                     d_stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_nb_draw(uint32_t *d_nb_q, const uint32_t *d_nb_idx, const NbStats *d_stats,
+                          uint64_t *d_nb_bsum, uint32_t *d_explored, uint32_t profile,
+                          int mark_profile, uint32_t n_valid, uint64_t u64, const uint32_t *d_idx,
+                          DrawResult *d_res, uint64_t seq, hipStream_t stream) {
+  hipLaunchKernelGGL(nb_draw, dim3(1), dim3(kDrawThreads), 0, stream, d_nb_q, d_nb_idx, d_stats,
+                     d_nb_bsum, d_explored, profile, mark_profile, n_valid, u64, d_idx, d_res, seq);
   return hipGetLastError();
 }
 
