@@ -386,6 +386,49 @@ def online_path(cgs, n_steps=200):
     }
 
 
+def neighbourhood_path(cgs, n_steps=200):
+    """Restricted steps (the neighbourhood of the profiled configuration, Sect.
+    3.7 footnote) on the 1.07e8-configuration space with its tree: radius 1,
+    2 and 3, n_steps each, one draw per step (the pick profiled next),
+    counter changes ~ U(-1, 1)."""
+    import synth
+    spec = synth.space_c5()
+    sp = cgs.Space.from_spec(spec)
+    tree = cgs.ForestModel.from_spec(sp, synth.forest_c5(spec))
+    g = synth.rng(6, 1)
+    deltas = synth.deltas(g, n_steps, tree.n_counters)
+    U = synth.uniforms_u64(g, n_steps + 1)
+    out = {"n_raw": sp.n_raw, "n_valid": sp.n_valid}
+    for radius in (1, 2, 3):
+        params = cgs.cgs_default_params()
+        params.timing = TIMING_PERIOD
+        sess = cgs.Session(sp, params)
+        sess.search_step(tree, cgs.NO_PROFILE)
+        raw, _ = sess.sample_next(int(U[0]))
+        wall, cand = [], []
+        for i in range(n_steps):
+            t0 = time.perf_counter()
+            sess.search_step_neighbourhood(tree, raw, radius, delta=deltas[i])
+            r = sess.sample_next(int(U[i + 1]))
+            wall.append(time.perf_counter() - t0)
+            cand.append(sess.step_info().n_unexplored)
+            if r is None:
+                break
+            raw = r[0]
+        ms, n = sess.kernel_times()
+        step_ms = float(np.median(wall)) * 1e3
+        out[f"radius_{radius}"] = {
+            "steps": len(wall), "candidates_mean": float(np.mean(cand)),
+            "step_wall_ms_median": step_ms,
+            "scoring_us": ms[3] / max(1, n[3]) * 1e3, "draw_us": ms[2] / max(1, n[2]) * 1e3,
+            "scored_per_s": float(np.mean(cand)) / (step_ms / 1e3),
+        }
+        sess.close()
+    tree.close()
+    sp.close()
+    return out
+
+
 def cpu_baseline(spec, forest, n_steps):
     """The oracle, untouched, on a bounded sample of the workload: the valid
     configurations with raw index below 2^22 (a quarter of the raw space),
@@ -460,6 +503,7 @@ def main() -> int:
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-online", action="store_true")
+    ap.add_argument("--no-neighbourhood", action="store_true")
     ap.add_argument("--inference-only", action="store_true",
                     help="only the two perceptron inference sweeps (for counter runs)")
     args = ap.parse_args()
@@ -554,6 +598,11 @@ def main() -> int:
         online = online_path(cgs)
         log(f"online: {online}")
 
+    nbh = None
+    if not args.no_neighbourhood:
+        nbh = neighbourhood_path(cgs)
+        log(f"neighbourhood: {nbh}")
+
     mlp = None
     if not args.no_mlp:
         mlp = mlp_path(cgs, sp, model)
@@ -609,6 +658,7 @@ def main() -> int:
         "mlp": mlp,
         "batch": batch,
         "online": online,
+        "neighbourhood": nbh,
         "hbm_copy_probe": probe,
         "model_eval_ms": model.eval_ms(),
         "space_create_ms": t_enum * 1e3,
