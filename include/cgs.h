@@ -198,6 +198,58 @@ cgs_status cgs_model_copy_leaf_ids(cgs_model model, uint64_t first, uint64_t cou
                                    uint16_t *dst_host);
 void cgs_model_destroy(cgs_model model);
 
+/* Regression-tree fitting (Sect. 3.4.2): grow one multi-output regression
+ * tree from measured (configuration, counter) pairs on the device, choose
+ * its depth on a held-out half, and load it like cgs_model_load_forest.
+ *
+ *   points_host[n]        valid indices of the measured configurations
+ *                         (repeats allowed); n >= 2, n * n_counters < 2^31
+ *   targets_host[n][C]    their measured counters, finite
+ *   keys_host[n]          one random 64-bit number per point: the training
+ *                         half is the ceil(n/2) points first in the order of
+ *                         (key >> 32, point index), the rest is the test half
+ *   max_depth             0..CGS_MAX_DEPTH; min_leaf >= 1
+ *
+ * Counter c is quantised to integers q = rint(y * 2^s_c), s_c = 22 - e_c,
+ * with 2^(e_c - 1) <= max |y_c| < 2^e_c (e_c = 0 when all are 0), so every
+ * node sum is exact.  Growth is greedy, level by level: a node with at least
+ * max(2, 2 min_leaf) training points takes the binary split (parameter j,
+ * digit <= t) with both sides >= min_leaf that maximises
+ * sum_c (S_L^2/n_L + S_R^2/n_R) (float64, c ascending; ties to the lower j,
+ * then t), if that exceeds its own sum_c S^2/n; otherwise it stays whole
+ * ("always left": parameter 0, threshold 255).  Node values are
+ * rint(S/n).  The candidate trees are the grown tree cut at depths
+ * 0..max_depth; on the test half each has exact error sums A_d = sum |e|,
+ * B_d = sum e^2 (e = node value - q, all points and counters); the model
+ * is the cut with the lowest A_d, then B_d, then depth, with leaf values
+ * float32(value * 2^-s_c).  The model's predictions of every valid
+ * configuration are computed as for a loaded forest.
+ *
+ * CGS_EINVAL for a point outside the valid list or a non-finite target,
+ * CGS_ERANGE for sizes outside the limits.  Synchronises; `report` may be
+ * NULL. */
+typedef struct {
+  int32_t depth;                           /* selected cut depth              */
+  int32_t max_depth, min_leaf, n_counters;
+  uint64_t n_train, n_test;
+  uint32_t n_split;                        /* nodes of the grown tree that split */
+  float fit_ms;                            /* device time of the fit          */
+  int32_t scale_log2[CGS_MAX_COUNTERS];    /* s_c                             */
+  uint64_t abs_err[CGS_MAX_DEPTH + 1];     /* A_d                             */
+  uint64_t sq_err[CGS_MAX_DEPTH + 1][2];   /* B_d = [1] * 2^64 + [0]          */
+} cgs_tree_fit_report;
+
+cgs_status cgs_model_fit_tree(cgs_space space, uint64_t n, int n_counters,
+                              const uint32_t *points_host, const float *targets_host,
+                              const uint64_t *keys_host, int max_depth, int min_leaf,
+                              cgs_model *out, cgs_tree_fit_report *report);
+/* Forest models only: number of trees and depth, then the trees in the
+ * layout of cgs_model_load_forest (feat, thr [n_trees][2^depth - 1],
+ * leaves [n_trees][2^depth][n_counters]). */
+cgs_status cgs_model_forest_shape(cgs_model model, int *n_trees, int *depth);
+cgs_status cgs_model_copy_forest(cgs_model model, uint8_t *feat_host, uint8_t *thr_host,
+                                 float *leaves_host);
+
 /* Multilayer-perceptron surrogate of the counter model (an extension: it
  * stands in for the trees of Sect. 3.4).  Features x_j = digit_j / 8 of
  * every parameter; z1 = W1 x + b1, h1 = gelu(z1), z2 = W2 h1 + b2,

@@ -36,6 +36,7 @@ SOURCES = {
     "forest.hip": ["-ffp-contract=off"],
     "sweep.hip": ["-ffp-contract=off"],
     "mlp.hip": ["-ffp-contract=fast"],
+    "treefit.hip": ["-ffp-contract=off"],
 }
 
 

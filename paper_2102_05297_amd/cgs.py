@@ -40,7 +40,8 @@ EXPORTS = (
     "cgs_batch_create", "cgs_batch_step", "cgs_batch_step_time", "cgs_batch_autotune",
     "cgs_batch_set_schedule", "cgs_batch_destroy", "cgs_model_rmse",
     "cgs_model_gather_predictions", "cgs_search_step_neighbourhood",
-    "cgs_session_copy_neighbourhood",
+    "cgs_session_copy_neighbourhood", "cgs_model_fit_tree", "cgs_model_forest_shape",
+    "cgs_model_copy_forest",
 )
 
 
@@ -87,6 +88,14 @@ class cgs_batch_schedule(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class cgs_tree_fit_report(C.Structure):
+    _fields_ = [("depth", C.c_int32), ("max_depth", C.c_int32), ("min_leaf", C.c_int32),
+                ("n_counters", C.c_int32), ("n_train", C.c_uint64), ("n_test", C.c_uint64),
+                ("n_split", C.c_uint32), ("fit_ms", C.c_float),
+                ("scale_log2", C.c_int32 * 64), ("abs_err", C.c_uint64 * 15),
+                ("sq_err", (C.c_uint64 * 2) * 15)]
+
+
 _p = C.c_void_p
 _u64 = C.c_uint64
 _i32 = C.c_int32
@@ -121,6 +130,10 @@ _sig("cgs_model_copy_leaf_ids", [_p, _u64, _u64, _p])
 _sig("cgs_model_rmse", [_p, _p, _p, _u64, _ptr(C.c_double)])
 _sig("cgs_model_gather_predictions", [_p, _p, _u64, _p])
 _sig("cgs_model_destroy", [_p], None)
+_sig("cgs_model_fit_tree", [_p, _u64, C.c_int, _p, _p, _p, C.c_int, C.c_int, _ptr(_p),
+                            _ptr(cgs_tree_fit_report)])
+_sig("cgs_model_forest_shape", [_p, _ptr(C.c_int), _ptr(C.c_int)])
+_sig("cgs_model_copy_forest", [_p, _p, _p, _p])
 _sig("cgs_session_create", [_p, _ptr(cgs_params), _ptr(_p)])
 _sig("cgs_search_step", [_p, _p, _u64, _p, _p, _ptr(cgs_expert_params)])
 _sig("cgs_search_step_neighbourhood", [_p, _p, _u64, C.c_int, _p, _p, _ptr(cgs_expert_params)])
@@ -326,6 +339,48 @@ class ForestModel(_Model):
     @classmethod
     def from_spec(cls, space: Space, forest) -> "ForestModel":
         return cls(space, forest.feat, forest.thr, forest.leaves)
+
+    @classmethod
+    def fit(cls, space: Space, points, targets, keys, max_depth: int, min_leaf: int = 1):
+        """Fit one regression tree on measured pairs (cgs_model_fit_tree):
+        points = valid indices [n], targets [n][C], keys = 64-bit random
+        numbers [n] that choose the training half.  Returns (model, report)."""
+        pts = _arr(points, np.uint32)
+        y = _arr(targets, np.float32)
+        if y.ndim != 2 or len(y) != len(pts):
+            raise ValueError("targets must be [n][C] with one row per point")
+        ks = _arr(keys, np.uint64)
+        if len(ks) != len(pts):
+            raise ValueError("one key per point")
+        rep = cgs_tree_fit_report()
+        h = C.c_void_p()
+        _check(_lib.cgs_model_fit_tree(space.h, len(pts), y.shape[1], _ptrof(pts), _ptrof(y),
+                                       _ptrof(ks), int(max_depth), int(min_leaf), C.byref(h),
+                                       C.byref(rep)), "cgs_model_fit_tree")
+        m = cls.__new__(cls)
+        m.h, m.space = h, space
+        m.n_trees, m.depth, m.n_counters = 1, int(rep.depth), int(y.shape[1])
+        D = int(max_depth)
+        report = {
+            "depth": int(rep.depth), "n_train": int(rep.n_train), "n_test": int(rep.n_test),
+            "n_split": int(rep.n_split), "fit_ms": float(rep.fit_ms),
+            "scale_log2": [int(v) for v in rep.scale_log2[: y.shape[1]]],
+            "abs_err": [int(v) for v in rep.abs_err[: D + 1]],
+            "sq_err": [int(rep.sq_err[d][0]) | (int(rep.sq_err[d][1]) << 64) for d in range(D + 1)],
+        }
+        return m, report
+
+    def copy_forest(self):
+        """(feat, thr, leaves) in the layout of the constructor."""
+        T, D = C.c_int(), C.c_int()
+        _check(_lib.cgs_model_forest_shape(self.h, C.byref(T), C.byref(D)), "cgs_model_forest_shape")
+        n_int = (1 << D.value) - 1
+        feat = np.zeros((T.value, n_int), dtype=np.uint8)
+        thr = np.zeros((T.value, n_int), dtype=np.uint8)
+        leaves = np.zeros((T.value, 1 << D.value, self.n_counters), dtype=np.float32)
+        _check(_lib.cgs_model_copy_forest(self.h, _ptrof(feat), _ptrof(thr), _ptrof(leaves)),
+               "cgs_model_copy_forest")
+        return feat, thr, leaves
 
     def copy_leaf_ids(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         count = self.space.n_valid - first if count is None else count

@@ -194,15 +194,15 @@ extern "C" cgs_status cgs_synchronize(cgs_space sp) {
 }
 
 // ------------------------------------------------------------------ space
-namespace {
-
-FastDiv make_fastdiv(uint32_t d) {
+FastDiv cgs::make_fastdiv(uint32_t d) {
   uint32_t l = 0;
   while ((1ull << l) < d) ++l;
   const uint64_t m = ((((uint64_t)1 << l) - d) << 32) / d + 1;
   const uint32_t sh1 = l < 1 ? l : 1, sh2 = l > 1 ? l - 1 : 0;
   return FastDiv{(uint32_t)m, sh1 | (sh2 << 8)};
 }
+
+namespace {
 
 void destroy_space(cgs_space sp) {
   if (!sp) return;
@@ -546,6 +546,158 @@ extern "C" cgs_status cgs_model_load_forest(cgs_space sp, int n_trees, int depth
     return st;
   }
   *out = m;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_model_fit_tree(cgs_space sp, uint64_t n, int n_counters,
+                                         const uint32_t *points, const float *targets,
+                                         const uint64_t *keys, int max_depth, int min_leaf,
+                                         cgs_model *out, cgs_tree_fit_report *report) {
+  if (!out) return fail(CGS_EINVAL, "NULL out");
+  *out = nullptr;
+  if (!sp || !points || !targets || !keys) return fail(CGS_EINVAL, "NULL argument");
+  if (n_counters < 1 || n_counters > CGS_MAX_COUNTERS)
+    return fail(CGS_ERANGE, "n_counters %d outside 1..%d", n_counters, CGS_MAX_COUNTERS);
+  if (n < 2 || n * (uint64_t)n_counters >= ((uint64_t)1 << 31))
+    return fail(CGS_ERANGE, "need 2 <= n and n * n_counters < 2^31 (n = %llu)",
+                (unsigned long long)n);
+  if (max_depth < 0 || max_depth > CGS_MAX_DEPTH)
+    return fail(CGS_ERANGE, "max_depth %d outside 0..%d", max_depth, CGS_MAX_DEPTH);
+  if (min_leaf < 1 || (uint64_t)min_leaf > n)
+    return fail(CGS_ERANGE, "min_leaf %d outside 1..n", min_leaf);
+  if (sp->n_valid == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
+
+  uint32_t *d_pts = nullptr;
+  float *d_y = nullptr;
+  uint64_t *d_keys = nullptr;
+  TreeFitWork *work = nullptr;
+  cgs_model m = nullptr;
+  auto cleanup = [&]() {
+    if (sp->stream) (void)hipStreamSynchronize(sp->stream);
+    dfree(d_pts);
+    dfree(d_y);
+    dfree(d_keys);
+    tree_fit_release(work);
+    work = nullptr;
+  };
+  hipError_t e = dalloc(&d_pts, n);
+  if (e == hipSuccess) e = dalloc(&d_y, n * (size_t)n_counters);
+  if (e == hipSuccess) e = dalloc(&d_keys, n);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_pts, points, n * 4, hipMemcpyHostToDevice, sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_y, targets, n * (size_t)n_counters * 4, hipMemcpyHostToDevice,
+                       sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_keys, keys, n * 8, hipMemcpyHostToDevice, sp->stream);
+  TreeFitOut fo{};
+  if (e == hipSuccess) {
+    TreeFitIn in{};
+    in.d_space = sp->d_desc;
+    in.d_idx = sp->d_idx;
+    in.n_valid = (uint32_t)sp->n_valid;
+    in.n_params = sp->n_params;
+    in.radix = sp->radix.data();
+    in.n = (uint32_t)n;
+    in.n_counters = n_counters;
+    in.d_points = d_pts;
+    in.d_targets = d_y;
+    in.d_keys = d_keys;
+    in.max_depth = max_depth;
+    in.min_leaf = min_leaf;
+    e = tree_fit_run(in, fo, &work, sp->stream);
+  }
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "tree fit: %s",
+                hipGetErrorString(e));
+  }
+  if (fo.err) {
+    cleanup();
+    return fail(CGS_EINVAL, "%s", (fo.err & 1u) ? "a point is outside the valid list"
+                                                : "a target is not finite");
+  }
+  const int depth = fo.depth;
+  m = new (std::nothrow) cgs_model_s();
+  if (!m) {
+    cleanup();
+    return fail(CGS_ENOMEM, "host allocation");
+  }
+  m->space = sp;
+  ++sp->refs;
+  m->kind = 0;
+  m->n_counters = n_counters;
+  m->n_trees = 1;
+  m->depth = depth;
+  m->stride = (sp->n_valid + 63) & ~(uint64_t)63;
+  const size_t n_int = ((size_t)1 << depth) - 1, n_leaf_vals = ((size_t)1 << depth) * n_counters;
+  e = dalloc(&m->d_nodes, n_int);
+  if (e == hipSuccess) e = dalloc(&m->d_leaves, n_leaf_vals);
+  if (e == hipSuccess) e = dalloc(&m->d_P, (size_t)n_counters * m->stride);
+  if (e == hipSuccess) e = tree_fit_emit(work, depth, m->d_nodes, m->d_leaves, sp->stream);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(m->d_P, 0, (size_t)n_counters * m->stride * sizeof(float), sp->stream);
+  cleanup();
+  if (e != hipSuccess) {
+    destroy_model(m);
+    return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "fitted model: %s",
+                hipGetErrorString(e));
+  }
+  const cgs_status st = evaluate_model(m);
+  if (st != CGS_OK) {
+    destroy_model(m);
+    return st;
+  }
+  if (report) {
+    std::memset(report, 0, sizeof(*report));
+    report->depth = depth;
+    report->max_depth = max_depth;
+    report->min_leaf = min_leaf;
+    report->n_counters = n_counters;
+    report->n_train = fo.n_train;
+    report->n_test = fo.n_test;
+    report->n_split = fo.n_split;
+    report->fit_ms = fo.ms;
+    for (int c = 0; c < n_counters; ++c) report->scale_log2[c] = fo.scale[c];
+    for (int d = 0; d <= max_depth; ++d) {
+      report->abs_err[d] = fo.abs_err[d];
+      const unsigned __int128 b =
+          ((unsigned __int128)fo.sq_hi32[d] << 32) + (unsigned __int128)fo.sq_lo32[d];
+      report->sq_err[d][0] = (uint64_t)b;
+      report->sq_err[d][1] = (uint64_t)(b >> 64);
+    }
+  }
+  *out = m;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_model_forest_shape(cgs_model m, int *n_trees, int *depth) {
+  if (!m) return fail(CGS_EINVAL, "NULL model");
+  if (m->kind != 0) return fail(CGS_EINVAL, "not a forest model");
+  if (n_trees) *n_trees = m->n_trees;
+  if (depth) *depth = m->depth;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_model_copy_forest(cgs_model m, uint8_t *feat, uint8_t *thr,
+                                            float *leaves) {
+  if (!m) return fail(CGS_EINVAL, "NULL model");
+  if (m->kind != 0) return fail(CGS_EINVAL, "not a forest model");
+  const size_t n_int = (size_t)m->n_trees * (((size_t)1 << m->depth) - 1);
+  const size_t n_leaf_vals = (size_t)m->n_trees * ((size_t)1 << m->depth) * m->n_counters;
+  if ((n_int && (!feat || !thr)) || !leaves) return fail(CGS_EINVAL, "NULL argument");
+  std::vector<uint16_t> nodes(n_int);
+  cgs_space sp = m->space;
+  if (n_int)
+    HIP_TRY(hipMemcpyAsync(nodes.data(), m->d_nodes, n_int * sizeof(uint16_t),
+                           hipMemcpyDeviceToHost, sp->stream));
+  HIP_TRY(hipMemcpyAsync(leaves, m->d_leaves, n_leaf_vals * sizeof(float), hipMemcpyDeviceToHost,
+                         sp->stream));
+  HIP_TRY(hipStreamSynchronize(sp->stream));
+  for (size_t i = 0; i < n_int; ++i) {
+    feat[i] = (uint8_t)(nodes[i] & 0xffu);
+    thr[i] = (uint8_t)(nodes[i] >> 8);
+  }
   return CGS_OK;
 }
 

@@ -242,4 +242,39 @@ hipError_t launch_array_draw(uint32_t *d_q, uint32_t n, int block_log2, uint64_t
                              uint32_t n_blocks, uint64_t u64, DrawResult *d_res,
                              hipStream_t stream);
 
+// ---- regression-tree fitting (Sect. 3.4.2)
+FastDiv make_fastdiv(uint32_t d);
+
+struct TreeFitIn {
+  const SpaceDev *d_space;
+  const uint32_t *d_idx;    // valid raw indices of the space
+  uint32_t n_valid;
+  int n_params;
+  const int32_t *radix;     // host [n_params]
+  uint32_t n;               // measured points, 2 .. 2^31 - 1
+  int n_counters;
+  const uint32_t *d_points; // valid indices [n]
+  const float *d_targets;   // [n][n_counters]
+  const uint64_t *d_keys;   // [n]
+  int max_depth, min_leaf;
+};
+struct TreeFitOut {
+  uint32_t err; // bit 0: a point outside the valid list; bit 1: a non-finite target
+  int32_t depth;
+  uint32_t n_train, n_test, n_split;
+  int32_t scale[CGS_MAX_COUNTERS];
+  uint64_t abs_err[CGS_MAX_DEPTH + 1];
+  uint64_t sq_lo32[CGS_MAX_DEPTH + 1], sq_hi32[CGS_MAX_DEPTH + 1]; // sum e^2 = hi 2^32 + lo
+  float ms;
+};
+struct TreeFitWork;
+// Runs the whole fit on `stream` and synchronises; *work holds the grown tree
+// until tree_fit_release (also after an error, when non-null).
+hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work,
+                        hipStream_t stream);
+// Writes the tree cut at `depth` in the evaluator's layout.
+hipError_t tree_fit_emit(const TreeFitWork *work, int depth, uint16_t *d_nodes, float *d_leaves,
+                         hipStream_t stream);
+void tree_fit_release(TreeFitWork *work);
+
 } // namespace cgs

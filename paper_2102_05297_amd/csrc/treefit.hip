@@ -1,0 +1,988 @@
+// Regression-tree fitting on the device (Sect. 3.4.2).
+//
+// The paper grows its counter model as a regression tree: greedy top-down
+// splits chosen by a squared-error criterion, a set of candidate trees, a
+// random half of the measured configurations for training and the other half
+// for testing, and the candidate with the lowest test MAE (then RMSE) kept.
+//
+// Readings (shared with the CPU restatement the tests compare against):
+//  * training half: the ceil(n/2) points first in the order of
+//    (key >> 32, index), found by an 8-pass radix select over the distinct
+//    64-bit keys ((key >> 32) << 32) | index;
+//  * targets are quantised per counter, q = rint(y 2^s_c), s_c = 22 - e_c
+//    with 2^(e_c-1) <= max|y_c| < 2^e_c, so node sums are exact integers and
+//    nothing depends on the order of the device's additions;
+//  * binary splits on a parameter's digit (left when digit <= t); score of an
+//    admissible split sum_c (S_L^2/n_L + S_R^2/n_R) in float64, c ascending;
+//    the best score wins, ties to the lower (parameter, threshold); a node
+//    splits only when that beats its own sum_c S^2/n;
+//  * level-by-level growth to depth D; a node that does not split becomes
+//    "always left" (parameter 0, threshold 255) and is not searched again;
+//  * node value rint(S/n) (float64 quotient); candidates are the tree cut at
+//    depths 0..D, scored on the test half with exact integer sums of |e| and
+//    e^2; the selected depth minimises (sum|e|, sum e^2, depth).
+//
+// Layout: every point becomes a row of W = PW + C 32-bit words: the digits
+// (one byte per parameter, PW = ceil(P/4) words), then q[C].  The training
+// rows of the nodes still searched are kept contiguous, segment by segment in
+// heap order, and are repartitioned into the next level's segments after each
+// level.  Histograms hold, per open node, the sum of q for every (parameter,
+// digit, counter) plus a count column: [sum_j R_j][C + 1] int64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "device_common.h"
+
+namespace cgs {
+
+// Device-resident state of one fit.  The host fills the first block; the
+// kernels write the rest (uploaded as zeros).
+struct FitDev {
+  uint32_t n, n_train, n_test, n_valid;
+  uint32_t C, P, PW, W;
+  uint32_t D, min_leaf, min_split, sumR;
+  uint32_t entries, items, pad0, pad1;
+  FastDiv divW;
+  uint32_t radix[CGS_MAX_PARAMS];
+  uint32_t roff[CGS_MAX_PARAMS + 1]; // first bin of parameter j; roff[P] = sumR
+  // written by the kernels
+  uint32_t err;
+  uint32_t key_done;
+  uint64_t key_prefix, key_k, key_T;
+  uint32_t key_hist[256];
+  uint32_t absmax[CGS_MAX_COUNTERS];
+  int32_t s[CGS_MAX_COUNTERS];
+  uint32_t cur_train, cur_test;
+  uint32_t n_split;
+  uint32_t lvl_K[2], lvl_R[2];
+  int32_t depth_sel;
+  uint64_t A[CGS_MAX_DEPTH + 1], Blo[CGS_MAX_DEPTH + 1], Bhi[CGS_MAX_DEPTH + 1];
+};
+
+namespace {
+
+constexpr int kFitThreads = 256;
+constexpr uint32_t kFitGrid = 1024;       // workgroups of the grid-stride passes
+constexpr uint32_t kTile = 256;           // rows per staged tile (int32 sums stay below 2^31)
+constexpr uint16_t kAlwaysLeftNode = (uint16_t)(255u << 8);
+constexpr uint32_t kLayoutThreads = 1024;
+
+__device__ __forceinline__ uint64_t split_key(uint64_t key, uint64_t i) {
+  return (key & 0xFFFFFFFF00000000ull) | i;
+}
+
+__device__ __forceinline__ uint32_t row_digit(const uint32_t *row, uint32_t j) {
+  return (row[j >> 2] >> (8u * (j & 3u))) & 255u;
+}
+
+// Row `first + r` of `dst` = staged row src[r], for r < count; rows at or
+// past `cap` (the buffer's size in rows) are not written.
+__device__ __forceinline__ void copy_rows_out(const uint32_t *lds, const uint32_t *src,
+                                              uint32_t count, uint32_t W, FastDiv divW,
+                                              uint32_t *__restrict__ dst, uint32_t first,
+                                              uint32_t cap) {
+  if (first >= cap) return;
+  const uint32_t words = min(count, cap - first) * W;
+  uint32_t *out = dst + (uint64_t)first * W;
+  for (uint32_t k = threadIdx.x; k < words; k += blockDim.x) {
+    const uint32_t r = fastdiv(k, divW);
+    out[k] = lds[src[r] * W + (k - r * W)];
+  }
+}
+
+// Largest slot s in [0, K) with seg_start[s] <= a (segments are non-empty).
+__device__ __forceinline__ uint32_t slot_containing(const uint32_t *seg_start, uint32_t K,
+                                                    uint32_t a) {
+  uint32_t lo = 0, hi = K;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (seg_start[mid] <= a) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void fit_zero(uint64_t *__restrict__ p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// Validation, per-counter max |y| and the histogram of the keys' top byte.
+__global__ __launch_bounds__(kFitThreads) void fit_prepare(FitDev *__restrict__ fd,
+                                                           const uint32_t *__restrict__ pts,
+                                                           const float *__restrict__ Y,
+                                                           const uint64_t *__restrict__ keys) {
+  __shared__ uint32_t s_max[CGS_MAX_COUNTERS];
+  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_err;
+  const uint32_t t = threadIdx.x;
+  const uint32_t n = fd->n, C = fd->C, nv = fd->n_valid;
+  if (t < CGS_MAX_COUNTERS) s_max[t] = 0;
+  s_hist[t] = 0;
+  if (t == 0) s_err = 0;
+  __syncthreads();
+  uint32_t err = 0;
+  const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + t;
+  // a stride that is a multiple of C keeps each thread on one counter
+  const uint64_t step = gsz / C * C, total = (uint64_t)n * C;
+  if (gid < step) {
+    uint32_t mx = 0;
+    for (uint64_t k = gid; k < total; k += step) {
+      const float y = Y[k];
+      if (!isfinite(y)) err |= 2u;
+      else mx = max(mx, __float_as_uint(fabsf(y)));
+    }
+    if (mx) atomicMax(&s_max[gid % C], mx);
+  }
+  for (uint64_t i = gid; i < n; i += gsz) {
+    if (pts[i] >= nv) err |= 1u;
+    atomicAdd(&s_hist[(uint32_t)(split_key(keys[i], i) >> 56)], 1u);
+  }
+  if (err) atomicOr(&s_err, err);
+  __syncthreads();
+  if (t < C && s_max[t]) atomicMax(&fd->absmax[t], s_max[t]);
+  if (s_hist[t]) atomicAdd(&fd->key_hist[t], s_hist[t]);
+  if (t == 0 && s_err) atomicOr(&fd->err, s_err);
+}
+
+// Radix select, pass `pass` (bits 56 - 8 pass .. 63 - 8 pass): pick the bin
+// holding the key of rank key_k within the current prefix.  When that bin is
+// taken whole (or the last byte is fixed), the threshold is final.
+__global__ __launch_bounds__(256) void fit_key_pick(FitDev *__restrict__ fd, int pass) {
+  __shared__ uint64_t scratch[4];
+  if (fd->key_done) return;
+  const uint32_t t = threadIdx.x;
+  const uint32_t h = fd->key_hist[t];
+  // read the state before the scan's barriers: one thread rewrites it below
+  const uint64_t k = fd->key_k, prefix0 = fd->key_prefix;
+  uint64_t tot;
+  const uint64_t before = block_excl_scan<256>(h, scratch, tot);
+  const int shift = 56 - 8 * pass;
+  if (before < k && k <= before + h) {
+    const uint64_t prefix = prefix0 | ((uint64_t)t << shift);
+    const uint64_t kn = k - before;
+    fd->key_prefix = prefix;
+    fd->key_k = kn;
+    if (h == kn || shift == 0) {
+      fd->key_T = prefix | (shift ? ((1ull << shift) - 1ull) : 0ull);
+      fd->key_done = 1;
+    }
+  }
+  __syncthreads();
+  fd->key_hist[t] = 0;
+}
+
+__global__ __launch_bounds__(kFitThreads) void fit_key_hist(FitDev *__restrict__ fd,
+                                                            const uint64_t *__restrict__ keys,
+                                                            int pass) {
+  __shared__ uint32_t s_hist[256];
+  if (fd->key_done) return;
+  const uint32_t t = threadIdx.x;
+  s_hist[t] = 0;
+  __syncthreads();
+  const int shift = 56 - 8 * pass; // pass >= 1
+  const uint64_t want = fd->key_prefix >> (shift + 8);
+  const uint64_t n = fd->n, gsz = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + t; i < n; i += gsz) {
+    const uint64_t kk = split_key(keys[i], i);
+    if ((kk >> (shift + 8)) == want) atomicAdd(&s_hist[(uint32_t)(kk >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  if (s_hist[t]) atomicAdd(&fd->key_hist[t], s_hist[t]);
+}
+
+// Rows of every point: digits and quantised targets; training rows and test
+// rows each packed contiguously (order within a half is immaterial: every sum
+// taken over rows is an exact integer).
+__global__ __launch_bounds__(kFitThreads) void fit_scatter(
+    FitDev *__restrict__ fd, const SpaceDev *__restrict__ sp, const uint32_t *__restrict__ idx,
+    const uint32_t *__restrict__ pts, const float *__restrict__ Y,
+    const uint64_t *__restrict__ keys, uint32_t *__restrict__ rows,
+    uint32_t *__restrict__ test_rows) {
+  extern __shared__ uint32_t lds[]; // [kTile][W] rows, then [kTile][C] targets
+  __shared__ int32_t s_scale[CGS_MAX_COUNTERS];
+  __shared__ uint32_t s_src[2][kTile];
+  __shared__ uint64_t scratch[kFitThreads / 64];
+  __shared__ uint32_t s_base[2];
+  const uint32_t t = threadIdx.x;
+  const uint32_t n = fd->n, C = fd->C, P = fd->P, PW = fd->PW, W = fd->W, nv = fd->n_valid;
+  const uint64_t T = fd->key_T;
+  float *ytile = reinterpret_cast<float *>(lds + kTile * W);
+  if (t < C) {
+    const float mx = __uint_as_float(fd->absmax[t]);
+    int e = 0;
+    if (mx > 0.0f) (void)frexpf(mx, &e);
+    s_scale[t] = 22 - e;
+    if (blockIdx.x == 0) fd->s[t] = 22 - e;
+  }
+  for (uint32_t tile = blockIdx.x * kTile; tile < n; tile += gridDim.x * kTile) {
+    const uint32_t nr = min(kTile, n - tile);
+    __syncthreads();
+    for (uint32_t k = t; k < nr * C; k += kFitThreads) ytile[k] = Y[(uint64_t)tile * C + k];
+    __syncthreads();
+    const bool live = t < nr;
+    bool train = false;
+    if (live) {
+      const uint32_t i = tile + t;
+      train = split_key(keys[i], i) <= T;
+      const uint32_t p = pts[i];
+      uint64_t lo = 0, hi = 0;
+      if (p < nv) decode_packed(idx[p], sp, lo, hi);
+      uint32_t *row = lds + t * W;
+      for (uint32_t w = 0; w < PW; ++w) {
+        uint32_t word = 0;
+        for (uint32_t b = 0; b < 4; ++b) {
+          const uint32_t j = 4 * w + b;
+          if (j < P) word |= digit_of(lo, hi, j) << (8 * b);
+        }
+        row[w] = word;
+      }
+      for (uint32_t c = 0; c < C; ++c) {
+        const float y = ytile[t * C + c];
+        const double v = isfinite(y) ? ldexp((double)y, s_scale[c]) : 0.0;
+        row[PW + c] = (uint32_t)(int32_t)rint(v);
+      }
+    }
+    const uint64_t flag = live ? (train ? 1ull : (1ull << 32)) : 0ull;
+    uint64_t tot;
+    const uint64_t rank = block_excl_scan<kFitThreads>(flag, scratch, tot);
+    const uint32_t ntr = (uint32_t)tot, nte = (uint32_t)(tot >> 32);
+    if (t == 0) {
+      s_base[0] = ntr ? atomicAdd(&fd->cur_train, ntr) : 0u;
+      s_base[1] = nte ? atomicAdd(&fd->cur_test, nte) : 0u;
+    }
+    if (live) {
+      if (train) s_src[0][(uint32_t)rank] = t;
+      else s_src[1][(uint32_t)(rank >> 32)] = t;
+    }
+    __syncthreads();
+    copy_rows_out(lds, s_src[0], ntr, W, fd->divW, rows, s_base[0], fd->n_train);
+    copy_rows_out(lds, s_src[1], nte, W, fd->divW, test_rows, s_base[1], fd->n_test);
+  }
+}
+
+// Sum of q over the training rows: the root's sums.
+__global__ __launch_bounds__(kFitThreads) void fit_root_sums(const FitDev *__restrict__ fd,
+                                                             const uint32_t *__restrict__ rows,
+                                                             int64_t *__restrict__ nsum) {
+  __shared__ int64_t s_sum[CGS_MAX_COUNTERS];
+  const uint32_t t = threadIdx.x, C = fd->C, PW = fd->PW, W = fd->W;
+  const uint64_t n = fd->n_train;
+  if (t < CGS_MAX_COUNTERS) s_sum[t] = 0;
+  __syncthreads();
+  const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + t;
+  const uint64_t rstep = gsz / C; // rows per round; thread keeps counter gid % C
+  if (gid < rstep * C) {
+    const uint32_t c = (uint32_t)(gid % C);
+    int64_t acc = 0;
+    for (uint64_t r = gid / C; r < n; r += rstep) acc += (int32_t)rows[r * W + PW + c];
+    if (acc) atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[c]), (unsigned long long)acc);
+  }
+  __syncthreads();
+  if (t < C && s_sum[t])
+    atomicAdd(reinterpret_cast<unsigned long long *>(&nsum[t]), (unsigned long long)s_sum[t]);
+}
+
+__device__ __forceinline__ int32_t node_value(int64_t S, uint32_t n) {
+  return (int32_t)rint((double)S / (double)n);
+}
+
+__global__ void fit_root(const FitDev *__restrict__ fd, uint32_t *__restrict__ ncount,
+                         const int64_t *__restrict__ nsum, int32_t *__restrict__ nmean,
+                         uint8_t *__restrict__ nstate) {
+  const uint32_t n = fd->n_train, C = fd->C;
+  for (uint32_t c = threadIdx.x; c < C; c += blockDim.x) nmean[c] = node_value(nsum[c], n);
+  if (threadIdx.x == 0) {
+    ncount[0] = n;
+    nstate[0] = (fd->D > 0 && n >= fd->min_split) ? 1 : 0;
+  }
+}
+
+// Segments of the open nodes of level L (heap order): slot, first row and
+// write cursor of each, and the level's totals.
+__global__ __launch_bounds__(kLayoutThreads) void fit_layout(
+    FitDev *__restrict__ fd, int L, const uint8_t *__restrict__ nstate,
+    const uint32_t *__restrict__ ncount, uint32_t *__restrict__ open_node,
+    uint32_t *__restrict__ seg_start, uint32_t *__restrict__ cursor,
+    uint32_t *__restrict__ slot_of, uint32_t kcap) {
+  __shared__ uint64_t scratch[kLayoutThreads / 64];
+  const uint32_t t = threadIdx.x, cnt = 1u << L, base = cnt - 1;
+  const uint32_t per = (cnt + kLayoutThreads - 1) / kLayoutThreads;
+  const uint32_t a = min(cnt, t * per), b = min(cnt, a + per);
+  uint64_t mine = 0; // rows << 16 | open nodes
+  for (uint32_t k = a; k < b; ++k)
+    if (nstate[base + k]) mine += ((uint64_t)ncount[base + k] << 16) | 1ull;
+  uint64_t tot;
+  const uint64_t before = block_excl_scan<kLayoutThreads>(mine, scratch, tot);
+  uint32_t slot = (uint32_t)(before & 0xffffu);
+  uint32_t row = (uint32_t)(before >> 16);
+  for (uint32_t k = a; k < b; ++k) {
+    if (nstate[base + k] && slot < kcap) {
+      open_node[slot] = base + k;
+      seg_start[slot] = row;
+      cursor[slot] = row;
+      slot_of[k] = slot;
+      row += ncount[base + k];
+      ++slot;
+    } else {
+      slot_of[k] = ~0u;
+    }
+  }
+  if (t == 0) {
+    // at most n_train / min_split nodes hold min_split rows each
+    const uint32_t K = min((uint32_t)(tot & 0xffffu), kcap);
+    if (K < (uint32_t)(tot & 0xffffu)) atomicOr(&fd->err, 4u);
+    seg_start[K] = (uint32_t)(tot >> 16);
+    fd->lvl_K[L & 1] = K;
+    fd->lvl_R[L & 1] = (uint32_t)(tot >> 16);
+  }
+}
+
+// Histograms of level L: each workgroup takes a contiguous range of the
+// level's rows, stages tiles of one node in LDS, accumulates int32 sums per
+// (parameter, digit, counter) there, folds them into int64 registers after
+// every tile and adds them to the node's histogram when its segment ends.
+// Thread t owns items t, t + NT, ... of the P x (C + 1) (parameter, column)
+// items, so no two threads touch one LDS entry.
+template <int IPT>
+__global__ __launch_bounds__(1024) void fit_hist(const FitDev *__restrict__ fd, int L,
+                                                 const uint32_t *__restrict__ rows,
+                                                 const uint32_t *__restrict__ seg_start,
+                                                 int64_t *__restrict__ ghist, uint32_t CH) {
+  extern __shared__ uint32_t lds[]; // [entries] int32 sums, then [CH][W] rows
+  const uint32_t set = L & 1, K = fd->lvl_K[set], R = fd->lvl_R[set];
+  if (R == 0) return;
+  const uint32_t a = (uint32_t)((uint64_t)R * blockIdx.x / gridDim.x);
+  const uint32_t b = (uint32_t)((uint64_t)R * (blockIdx.x + 1) / gridDim.x);
+  if (a >= b) return;
+  const uint32_t t = threadIdx.x, NT = blockDim.x;
+  const uint32_t C = fd->C, C1 = C + 1, PW = fd->PW, W = fd->W, I = fd->items, E = fd->entries;
+  int32_t *h32 = reinterpret_cast<int32_t *>(lds);
+  uint32_t *rl = lds + E;
+
+  uint32_t jj[IPT], cc[IPT], off[IPT], rr[IPT];
+  int64_t acc[IPT][CGS_MAX_RADIX];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const uint32_t it = t + k * NT;
+    rr[k] = 0;
+    jj[k] = 0;
+    cc[k] = 0;
+    off[k] = 0;
+    if (it < I) {
+      const uint32_t j = it / C1, c = it - j * C1;
+      jj[k] = j;
+      cc[k] = c;
+      rr[k] = fd->radix[j];
+      off[k] = fd->roff[j] * C1 + c;
+    }
+#pragma unroll
+    for (int v = 0; v < CGS_MAX_RADIX; ++v) acc[k][v] = 0;
+  }
+  for (uint32_t e = t; e < E; e += NT) h32[e] = 0;
+
+  uint32_t slot = slot_containing(seg_start, K, a);
+  uint32_t seg_end = seg_start[slot + 1];
+  uint32_t pos = a;
+  while (pos < b) {
+    const uint32_t end = min(min(b, seg_end), pos + CH);
+    if (end <= pos) break; // segments are never empty
+    const uint32_t nr = end - pos;
+    __syncthreads();
+    const uint32_t *src = rows + (uint64_t)pos * W;
+    for (uint32_t k = t; k < nr * W; k += NT) rl[k] = src[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      if (rr[k]) {
+        const uint32_t dw = jj[k] >> 2, sh = 8u * (jj[k] & 3u), c = cc[k], o = off[k];
+        const bool cnt = c == C;
+        for (uint32_t r = 0; r < nr; ++r) {
+          const uint32_t *row = rl + r * W;
+          const uint32_t v = (row[dw] >> sh) & 255u;
+          const int32_t val = cnt ? 1 : (int32_t)row[PW + c];
+          atomicAdd(&h32[o + v * C1], val);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+#pragma unroll
+      for (int v = 0; v < CGS_MAX_RADIX; ++v) {
+        if ((uint32_t)v < rr[k]) {
+          const uint32_t e = off[k] + v * C1;
+          acc[k][v] += h32[e];
+          h32[e] = 0;
+        }
+      }
+    }
+    pos = end;
+    if (pos == seg_end || pos == b) {
+      int64_t *H = ghist + (uint64_t)slot * E;
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+#pragma unroll
+        for (int v = 0; v < CGS_MAX_RADIX; ++v) {
+          if ((uint32_t)v < rr[k] && acc[k][v]) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(H + off[k] + v * C1),
+                      (unsigned long long)acc[k][v]);
+            acc[k][v] = 0;
+          }
+        }
+      }
+      if (pos < b) {
+        ++slot;
+        seg_end = seg_start[slot + 1];
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void inherit_children(uint32_t node, uint32_t C,
+                                                 uint32_t *__restrict__ ncount,
+                                                 int64_t *__restrict__ nsum,
+                                                 int32_t *__restrict__ nmean,
+                                                 uint8_t *__restrict__ nstate,
+                                                 uint16_t *__restrict__ nodes) {
+  const uint32_t l = 2 * node + 1, r = l + 1;
+  if (threadIdx.x == 0) {
+    nodes[node] = kAlwaysLeftNode;
+    ncount[l] = ncount[node];
+    ncount[r] = 0;
+    nstate[l] = 0;
+    nstate[r] = 0;
+  }
+  for (uint32_t c = threadIdx.x; c < C; c += blockDim.x) {
+    const int32_t m = nmean[(uint64_t)node * C + c];
+    nsum[(uint64_t)l * C + c] = nsum[(uint64_t)node * C + c];
+    nsum[(uint64_t)r * C + c] = 0;
+    nmean[(uint64_t)l * C + c] = m;
+    nmean[(uint64_t)r * C + c] = m;
+  }
+}
+
+__device__ __forceinline__ bool better(double s, uint32_t k, double s2, uint32_t k2) {
+  // (s, k) beats (s2, k2): a valid candidate, higher score, then lower index
+  if (k == ~0u) return false;
+  if (k2 == ~0u) return true;
+  return s > s2 || (s == s2 && k < k2);
+}
+
+// Split search of level L: one workgroup per node of the level.  Candidate
+// k enumerates (parameter, threshold) pairs in ascending order: parameter j
+// contributes thresholds 0 .. R_j - 2, from index roff[j] - j.
+__global__ __launch_bounds__(kFitThreads) void fit_split(
+    FitDev *__restrict__ fd, int L, int64_t *__restrict__ ghist,
+    const uint32_t *__restrict__ slot_of, uint32_t cap_entries, uint32_t *__restrict__ ncount,
+    int64_t *__restrict__ nsum, int32_t *__restrict__ nmean, uint8_t *__restrict__ nstate,
+    uint16_t *__restrict__ nodes) {
+  extern __shared__ int64_t ps[]; // prefix sums over digits of one parameter group
+  __shared__ int64_t s_S[CGS_MAX_COUNTERS];
+  __shared__ double s_score[kFitThreads / 64];
+  __shared__ uint32_t s_k[kFitThreads / 64];
+  __shared__ uint32_t s_split, s_j, s_t, s_nl;
+  const uint32_t t = threadIdx.x, local = blockIdx.x;
+  const uint32_t node = (1u << L) - 1 + local;
+  const uint32_t C = fd->C, C1 = C + 1, P = fd->P;
+  if (!nstate[node]) {
+    inherit_children(node, C, ncount, nsum, nmean, nstate, nodes);
+    return;
+  }
+  int64_t *H = ghist + (uint64_t)slot_of[local] * fd->entries;
+  const uint32_t n = ncount[node], min_leaf = fd->min_leaf;
+  for (uint32_t c = t; c < C; c += kFitThreads) s_S[c] = nsum[(uint64_t)node * C + c];
+
+  double best = 0.0;
+  uint32_t best_k = ~0u;
+  uint32_t j0 = 0;
+  while (j0 < P) {
+    uint32_t j1 = j0, bins = 0;
+    while (j1 < P && (bins + fd->radix[j1]) * C1 <= cap_entries) bins += fd->radix[j1++];
+    const uint32_t b0 = fd->roff[j0];
+    __syncthreads();
+    for (uint32_t it = t; it < (j1 - j0) * C1; it += kFitThreads) {
+      const uint32_t jl = j0 + it / C1, c = it % C1;
+      const uint32_t rb = fd->roff[jl];
+      int64_t run = 0;
+      for (uint32_t v = 0; v < fd->radix[jl]; ++v) {
+        run += H[(uint64_t)(rb + v) * C1 + c];
+        ps[(rb - b0 + v) * C1 + c] = run;
+      }
+    }
+    __syncthreads();
+    const uint32_t k0 = fd->roff[j0] - j0, k1 = fd->roff[j1] - j1;
+    for (uint32_t k = k0 + t; k < k1; k += kFitThreads) {
+      uint32_t jl = j0;
+      while (fd->roff[jl + 1] - (jl + 1) <= k) ++jl;
+      const uint32_t th = k - (fd->roff[jl] - jl);
+      const int64_t *pr = ps + (fd->roff[jl] - b0 + th) * C1;
+      const uint32_t nL = (uint32_t)pr[C], nR = n - nL;
+      if (nL < min_leaf || nR < min_leaf) continue;
+      const double dL = (double)nL, dR = (double)nR;
+      double acc = 0.0;
+      for (uint32_t c = 0; c < C; ++c) {
+        const double x = (double)pr[c];
+        const double y = (double)(s_S[c] - pr[c]);
+        acc = acc + ((x * x) / dL + (y * y) / dR);
+      }
+      if (better(acc, k, best, best_k)) {
+        best = acc;
+        best_k = k;
+      }
+    }
+    j0 = j1;
+  }
+  // argmax over the workgroup
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double s2 = __shfl_xor(best, o, 64);
+    const uint32_t k2 = (uint32_t)__shfl_xor((int)best_k, o, 64);
+    if (better(s2, k2, best, best_k)) {
+      best = s2;
+      best_k = k2;
+    }
+  }
+  if ((t & 63u) == 0) {
+    s_score[t >> 6] = best;
+    s_k[t >> 6] = best_k;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < kFitThreads / 64; ++w)
+      if (better(s_score[w], s_k[w], best, best_k)) {
+        best = s_score[w];
+        best_k = s_k[w];
+      }
+    double parent = 0.0;
+    const double dn = (double)n;
+    for (uint32_t c = 0; c < C; ++c) {
+      const double x = (double)s_S[c];
+      parent = parent + (x * x) / dn;
+    }
+    uint32_t split = 0, j = 0, th = 0;
+    if (best_k != ~0u && best > parent) {
+      split = 1;
+      while (fd->roff[j + 1] - (j + 1) <= best_k) ++j;
+      th = best_k - (fd->roff[j] - j);
+      uint32_t nl = 0;
+      for (uint32_t v = 0; v <= th; ++v) nl += (uint32_t)H[(uint64_t)(fd->roff[j] + v) * C1 + C];
+      s_nl = nl;
+    }
+    s_split = split;
+    s_j = j;
+    s_t = th;
+  }
+  __syncthreads();
+  if (!s_split) {
+    inherit_children(node, C, ncount, nsum, nmean, nstate, nodes);
+  } else {
+    const uint32_t j = s_j, th = s_t, nl = s_nl, nr = n - nl;
+    const uint32_t l = 2 * node + 1, r = l + 1;
+    for (uint32_t c = t; c < C; c += kFitThreads) {
+      int64_t sl = 0;
+      for (uint32_t v = 0; v <= th; ++v) sl += H[(uint64_t)(fd->roff[j] + v) * C1 + c];
+      const int64_t sr = s_S[c] - sl;
+      nsum[(uint64_t)l * C + c] = sl;
+      nsum[(uint64_t)r * C + c] = sr;
+      nmean[(uint64_t)l * C + c] = node_value(sl, nl);
+      nmean[(uint64_t)r * C + c] = node_value(sr, nr);
+    }
+    if (t == 0) {
+      const bool deeper = (uint32_t)L + 1 < fd->D;
+      nodes[node] = (uint16_t)(j | (th << 8));
+      ncount[l] = nl;
+      ncount[r] = nr;
+      nstate[l] = (deeper && nl >= fd->min_split) ? 1 : 0;
+      nstate[r] = (deeper && nr >= fd->min_split) ? 1 : 0;
+      atomicAdd(&fd->n_split, 1u);
+    }
+  }
+  // the histogram slot is reused by the next level
+  __syncthreads();
+  for (uint32_t e = t; e < fd->entries; e += kFitThreads) H[e] = 0;
+}
+
+// Moves the rows of level L's open nodes into the segments of their open
+// children (rows of closed children are dropped).
+__global__ __launch_bounds__(kFitThreads) void fit_partition(
+    const FitDev *__restrict__ fd, int L, const uint32_t *__restrict__ rows_in,
+    uint32_t *__restrict__ rows_out, const uint32_t *__restrict__ seg_start,
+    const uint32_t *__restrict__ open_node, uint32_t *__restrict__ cursor_next,
+    const uint32_t *__restrict__ slot_of_next, const uint8_t *__restrict__ nstate,
+    const uint16_t *__restrict__ nodes) {
+  extern __shared__ uint32_t rl[]; // [kTile][W]
+  __shared__ uint32_t s_src[2][kTile];
+  __shared__ uint64_t scratch[kFitThreads / 64];
+  __shared__ uint32_t s_base[2];
+  const uint32_t set = L & 1, K = fd->lvl_K[set], R = fd->lvl_R[set];
+  if (R == 0) return;
+  const uint32_t a = (uint32_t)((uint64_t)R * blockIdx.x / gridDim.x);
+  const uint32_t b = (uint32_t)((uint64_t)R * (blockIdx.x + 1) / gridDim.x);
+  if (a >= b) return;
+  const uint32_t t = threadIdx.x, W = fd->W;
+  const uint32_t child_base = (2u << L) - 1;
+  uint32_t slot = slot_containing(seg_start, K, a);
+  uint32_t seg_end = seg_start[slot + 1];
+  uint32_t pos = a;
+  while (pos < b) {
+    const uint32_t end = min(min(b, seg_end), pos + kTile);
+    if (end <= pos) break; // segments are never empty
+    const uint32_t nr = end - pos;
+    const uint32_t node = open_node[slot];
+    const uint16_t nd = nodes[node];
+    const uint32_t j = nd & 255u, thr = nd >> 8;
+    const uint32_t lc = 2 * node + 1, rc = lc + 1;
+    const bool lopen = nstate[lc] != 0, ropen = nstate[rc] != 0;
+    __syncthreads();
+    const uint32_t *src = rows_in + (uint64_t)pos * W;
+    for (uint32_t k = t; k < nr * W; k += kFitThreads) rl[k] = src[k];
+    __syncthreads();
+    bool keep = false, left = false;
+    if (t < nr) {
+      left = row_digit(rl + t * W, j) <= thr;
+      keep = left ? lopen : ropen;
+    }
+    const uint64_t flag = keep ? (left ? 1ull : (1ull << 32)) : 0ull;
+    uint64_t tot;
+    const uint64_t rank = block_excl_scan<kFitThreads>(flag, scratch, tot);
+    const uint32_t nl = (uint32_t)tot, nrr = (uint32_t)(tot >> 32);
+    if (t == 0) {
+      s_base[0] = nl ? atomicAdd(&cursor_next[slot_of_next[lc - child_base]], nl) : 0u;
+      s_base[1] = nrr ? atomicAdd(&cursor_next[slot_of_next[rc - child_base]], nrr) : 0u;
+    }
+    if (keep) {
+      if (left) s_src[0][(uint32_t)rank] = t;
+      else s_src[1][(uint32_t)(rank >> 32)] = t;
+    }
+    __syncthreads();
+    copy_rows_out(rl, s_src[0], nl, W, fd->divW, rows_out, s_base[0], fd->n_train);
+    copy_rows_out(rl, s_src[1], nrr, W, fd->divW, rows_out, s_base[1], fd->n_train);
+    pos = end;
+    if (pos == seg_end && pos < b) {
+      ++slot;
+      seg_end = seg_start[slot + 1];
+    }
+  }
+}
+
+// Test errors of the cut trees: each test row walks the grown tree once and
+// adds |e| and e^2 (split in 32-bit halves) at every depth.
+__global__ __launch_bounds__(kFitThreads) void fit_test(FitDev *__restrict__ fd,
+                                                        const uint32_t *__restrict__ test_rows,
+                                                        const uint16_t *__restrict__ nodes,
+                                                        const int32_t *__restrict__ nmean) {
+  extern __shared__ uint32_t rl[]; // [kTile][W]
+  constexpr int ND = CGS_MAX_DEPTH + 1;
+  const uint32_t t = threadIdx.x, n = fd->n_test, C = fd->C, PW = fd->PW, W = fd->W;
+  const uint32_t D = fd->D;
+  uint64_t A[ND], BL[ND], BH[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) A[d] = BL[d] = BH[d] = 0;
+  for (uint32_t tile = blockIdx.x * kTile; tile < n; tile += gridDim.x * kTile) {
+    const uint32_t nr = min(kTile, n - tile);
+    __syncthreads();
+    const uint32_t *src = test_rows + (uint64_t)tile * W;
+    for (uint32_t k = t; k < nr * W; k += kFitThreads) rl[k] = src[k];
+    __syncthreads();
+    if (t < nr) {
+      const uint32_t *row = rl + t * W;
+      uint32_t node = 0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        if ((uint32_t)d <= D) {
+          const int32_t *m = nmean + (uint64_t)node * C;
+          uint64_t ea = 0, el = 0, eh = 0;
+          for (uint32_t c = 0; c < C; ++c) {
+            const int64_t e = (int64_t)m[c] - (int64_t)(int32_t)row[PW + c];
+            const uint64_t e2 = (uint64_t)(e * e);
+            ea += (uint64_t)(e < 0 ? -e : e);
+            el += e2 & 0xffffffffull;
+            eh += e2 >> 32;
+          }
+          A[d] += ea;
+          BL[d] += el;
+          BH[d] += eh;
+          if ((uint32_t)d < D) {
+            const uint16_t nd = nodes[node];
+            node = 2 * node + (row_digit(row, nd & 255u) <= (uint32_t)(nd >> 8) ? 1u : 2u);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    if ((uint32_t)d <= D) {
+      const uint64_t a = wave_sum(A[d]), l = wave_sum(BL[d]), h = wave_sum(BH[d]);
+      if ((t & 63u) == 0) {
+        if (a) atomicAdd(reinterpret_cast<unsigned long long *>(&fd->A[d]), a);
+        if (l) atomicAdd(reinterpret_cast<unsigned long long *>(&fd->Blo[d]), l);
+        if (h) atomicAdd(reinterpret_cast<unsigned long long *>(&fd->Bhi[d]), h);
+      }
+    }
+  }
+}
+
+// Lowest (sum|e|, sum e^2, depth); sum e^2 = Bhi 2^32 + Blo.
+__global__ void fit_select(FitDev *__restrict__ fd) {
+  if (threadIdx.x != 0) return;
+  uint32_t best = 0;
+  auto hi = [&](uint32_t d) { return fd->Bhi[d] + (fd->Blo[d] >> 32); };
+  auto lo = [&](uint32_t d) { return fd->Blo[d] & 0xffffffffull; };
+  for (uint32_t d = 1; d <= fd->D; ++d) {
+    const bool lt = fd->A[d] < fd->A[best] ||
+                    (fd->A[d] == fd->A[best] &&
+                     (hi(d) < hi(best) || (hi(d) == hi(best) && lo(d) < lo(best))));
+    if (lt) best = d;
+  }
+  fd->depth_sel = (int32_t)best;
+}
+
+// The tree cut at `depth` in the evaluator's layout: heap nodes, leaf
+// values float32(m 2^-s_c).
+__global__ void fit_emit(const FitDev *__restrict__ fd, int depth,
+                         const uint16_t *__restrict__ nodes, const int32_t *__restrict__ nmean,
+                         uint16_t *__restrict__ out_nodes, float *__restrict__ out_leaves) {
+  const uint32_t C = fd->C, n_int = (1u << depth) - 1, n_leaf_vals = (1u << depth) * C;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < max(n_int, n_leaf_vals);
+       i += gridDim.x * blockDim.x) {
+    if (i < n_int) out_nodes[i] = nodes[i];
+    if (i < n_leaf_vals) {
+      const uint32_t c = i % C;
+      out_leaves[i] = (float)ldexp((double)nmean[(uint64_t)n_int * C + i], -fd->s[c]);
+    }
+  }
+}
+
+template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+} // namespace
+
+struct TreeFitWork {
+  void *base = nullptr;
+  FitDev *fd = nullptr;
+  uint16_t *nodes = nullptr;
+  int32_t *nmean = nullptr;
+  int C = 0;
+};
+
+hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work_out,
+                        hipStream_t stream) {
+  *work_out = nullptr;
+  std::memset(&out, 0, sizeof(out));
+  const uint32_t n = in.n, C = (uint32_t)in.n_counters, P = (uint32_t)in.n_params;
+  const uint32_t D = (uint32_t)in.max_depth;
+  const uint32_t n_train = n - n / 2, n_test = n / 2;
+
+  FitDev h{};
+  h.n = n;
+  h.n_train = n_train;
+  h.n_test = n_test;
+  h.n_valid = in.n_valid;
+  h.C = C;
+  h.P = P;
+  h.PW = (P + 3) / 4;
+  h.W = h.PW + C;
+  h.D = D;
+  h.min_leaf = (uint32_t)in.min_leaf;
+  h.min_split = std::max<uint32_t>(2u, 2u * (uint32_t)in.min_leaf);
+  h.divW = make_fastdiv(h.W);
+  uint32_t sumR = 0;
+  for (uint32_t j = 0; j < P; ++j) {
+    h.radix[j] = (uint32_t)in.radix[j];
+    h.roff[j] = sumR;
+    sumR += (uint32_t)in.radix[j];
+  }
+  h.roff[P] = sumR;
+  h.sumR = sumR;
+  h.entries = sumR * (C + 1);
+  h.items = P * (C + 1);
+  h.key_k = n_train;
+
+  // open nodes of one level: at most 2^(D-1), and each holds min_split rows
+  const uint64_t n_nodes = ((uint64_t)2 << D) - 1;
+  const uint64_t n_int = ((uint64_t)1 << D) - 1;
+  const uint64_t level_cap = D ? ((uint64_t)1 << (D - 1)) : 1;
+  const uint64_t kcap = std::max<uint64_t>(1, std::min<uint64_t>(level_cap, n_train / h.min_split));
+  const uint64_t hist_entries = D ? kcap * h.entries : 0;
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const size_t o_fd = take(sizeof(FitDev));
+  const size_t o_hist = take(hist_entries * sizeof(int64_t));
+  const size_t o_nsum = take(n_nodes * C * sizeof(int64_t));
+  const size_t zero_end = off; // the histograms and node sums start at zero
+  const size_t o_rows0 = take((size_t)n_train * h.W * 4);
+  const size_t o_rows1 = take(D > 1 ? (size_t)n_train * h.W * 4 : 0);
+  const size_t o_test = take((size_t)n_test * h.W * 4);
+  const size_t o_ncount = take(n_nodes * 4);
+  const size_t o_nmean = take(n_nodes * C * 4);
+  const size_t o_nstate = take(n_nodes);
+  const size_t o_nodes = take(n_int * 2);
+  size_t o_open[2], o_seg[2], o_cur[2], o_slot[2];
+  for (int s = 0; s < 2; ++s) {
+    o_open[s] = take(kcap * 4);
+    o_seg[s] = take((kcap + 1) * 4);
+    o_cur[s] = take(kcap * 4);
+    o_slot[s] = take(level_cap * 4);
+  }
+  char *base = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(&base), off);
+  if (e != hipSuccess) return e;
+  TreeFitWork *w = new (std::nothrow) TreeFitWork();
+  if (!w) {
+    (void)hipFree(base);
+    return hipErrorOutOfMemory;
+  }
+  w->base = base;
+  w->fd = reinterpret_cast<FitDev *>(base + o_fd);
+  w->nodes = reinterpret_cast<uint16_t *>(base + o_nodes);
+  w->nmean = reinterpret_cast<int32_t *>(base + o_nmean);
+  w->C = (int)C;
+  *work_out = w;
+
+  FitDev *fd = w->fd;
+  int64_t *ghist = reinterpret_cast<int64_t *>(base + o_hist);
+  int64_t *nsum = reinterpret_cast<int64_t *>(base + o_nsum);
+  uint32_t *rows[2] = {reinterpret_cast<uint32_t *>(base + o_rows0),
+                       reinterpret_cast<uint32_t *>(base + o_rows1)};
+  uint32_t *test_rows = reinterpret_cast<uint32_t *>(base + o_test);
+  uint32_t *ncount = reinterpret_cast<uint32_t *>(base + o_ncount);
+  uint8_t *nstate = reinterpret_cast<uint8_t *>(base + o_nstate);
+  uint32_t *open_node[2], *seg_start[2], *cursor[2], *slot_of[2];
+  for (int s = 0; s < 2; ++s) {
+    open_node[s] = reinterpret_cast<uint32_t *>(base + o_open[s]);
+    seg_start[s] = reinterpret_cast<uint32_t *>(base + o_seg[s]);
+    cursor[s] = reinterpret_cast<uint32_t *>(base + o_cur[s]);
+    slot_of[s] = reinterpret_cast<uint32_t *>(base + o_slot[s]);
+  }
+
+  // launch shapes
+  const uint32_t NT_h = std::min<uint32_t>(1024, (h.items + 63) / 64 * 64);
+  const uint32_t ipt = (h.items + NT_h - 1) / NT_h;
+  const size_t hist_lds_budget =
+      std::min<size_t>(160 * 1024, std::max<size_t>(65536, (size_t)h.entries * 4 + 16 * h.W * 4));
+  const uint32_t CH = (uint32_t)std::min<size_t>(
+      kTile, (hist_lds_budget - (size_t)h.entries * 4) / ((size_t)h.W * 4));
+  const size_t hist_lds = ((size_t)h.entries + (size_t)CH * h.W) * 4;
+  const uint32_t cap_entries =
+      std::max<uint32_t>(CGS_MAX_RADIX * (C + 1), std::min<uint32_t>(h.entries, 8192));
+  const size_t split_lds = (size_t)cap_entries * 8;
+  const size_t tile_lds = (size_t)kTile * h.W * 4;
+  const size_t scatter_lds = tile_lds + (size_t)kTile * C * 4;
+  const uint32_t g_rows = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>(kFitGrid, ((uint64_t)n_train + kTile - 1) / kTile));
+  const uint32_t g_test = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>(kFitGrid, ((uint64_t)n_test + kTile - 1) / kTile));
+  const uint32_t g_pts = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>(kFitGrid, ((uint64_t)n + kTile - 1) / kTile));
+
+  auto kh = ipt == 1 ? fit_hist<1> : ipt == 2 ? fit_hist<2> : fit_hist<3>;
+  if (e == hipSuccess) e = allow_lds(kh, hist_lds);
+  if (e == hipSuccess) e = allow_lds(fit_split, split_lds);
+  if (e == hipSuccess) e = allow_lds(fit_partition, tile_lds);
+  if (e == hipSuccess) e = allow_lds(fit_test, tile_lds);
+  if (e == hipSuccess) e = allow_lds(fit_scatter, scatter_lds);
+  if (e != hipSuccess) return e;
+
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e == hipSuccess) e = hipMemcpyAsync(fd, &h, sizeof(h), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+  const uint64_t zwords = (zero_end - o_hist) / 8;
+  if (e == hipSuccess) {
+    fit_zero<<<(uint32_t)std::min<uint64_t>(2048, (zwords + 255) / 256), 256, 0, stream>>>(
+        reinterpret_cast<uint64_t *>(base + o_hist), zwords);
+    fit_prepare<<<g_pts, kFitThreads, 0, stream>>>(fd, in.d_points, in.d_targets, in.d_keys);
+    fit_key_pick<<<1, 256, 0, stream>>>(fd, 0);
+    for (int p = 1; p < 8; ++p) {
+      fit_key_hist<<<g_pts, kFitThreads, 0, stream>>>(fd, in.d_keys, p);
+      fit_key_pick<<<1, 256, 0, stream>>>(fd, p);
+    }
+    fit_scatter<<<g_pts, kFitThreads, scatter_lds, stream>>>(fd, in.d_space, in.d_idx,
+                                                            in.d_points, in.d_targets,
+                                                            in.d_keys, rows[0], test_rows);
+    fit_root_sums<<<g_rows, kFitThreads, 0, stream>>>(fd, rows[0], nsum);
+    fit_root<<<1, 64, 0, stream>>>(fd, ncount, nsum, w->nmean, nstate);
+    if (D > 0)
+      fit_layout<<<1, kLayoutThreads, 0, stream>>>(fd, 0, nstate, ncount, open_node[0],
+                                                  seg_start[0], cursor[0], slot_of[0],
+                                                  (uint32_t)kcap);
+    for (uint32_t L = 0; L < D; ++L) {
+      const int s = L & 1;
+      kh<<<g_rows, NT_h, hist_lds, stream>>>(fd, (int)L, rows[s], seg_start[s], ghist, CH);
+      fit_split<<<1u << L, kFitThreads, split_lds, stream>>>(fd, (int)L, ghist, slot_of[s],
+                                                             cap_entries, ncount, nsum,
+                                                             w->nmean, nstate, w->nodes);
+      if (L + 1 < D) {
+        fit_layout<<<1, kLayoutThreads, 0, stream>>>(fd, (int)L + 1, nstate, ncount,
+                                                    open_node[s ^ 1], seg_start[s ^ 1],
+                                                    cursor[s ^ 1], slot_of[s ^ 1],
+                                                    (uint32_t)kcap);
+        fit_partition<<<g_rows, kFitThreads, tile_lds, stream>>>(
+            fd, (int)L, rows[s], rows[s ^ 1], seg_start[s], open_node[s], cursor[s ^ 1],
+            slot_of[s ^ 1], nstate, w->nodes);
+      }
+    }
+    fit_test<<<g_test, kFitThreads, tile_lds, stream>>>(fd, test_rows, w->nodes, w->nmean);
+    fit_select<<<1, 64, 0, stream>>>(fd);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(ev[1], stream);
+  FitDev r{};
+  if (e == hipSuccess) e = hipMemcpyAsync(&r, fd, sizeof(r), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return e;
+  out.err = r.err;
+  out.depth = r.depth_sel;
+  out.n_train = r.cur_train;
+  out.n_test = r.cur_test;
+  out.n_split = r.n_split;
+  for (uint32_t c = 0; c < C; ++c) out.scale[c] = r.s[c];
+  for (uint32_t d = 0; d <= D; ++d) {
+    out.abs_err[d] = r.A[d];
+    out.sq_lo32[d] = r.Blo[d];
+    out.sq_hi32[d] = r.Bhi[d];
+  }
+  out.ms = ms;
+  return hipSuccess;
+}
+
+hipError_t tree_fit_emit(const TreeFitWork *w, int depth, uint16_t *d_nodes, float *d_leaves,
+                         hipStream_t stream) {
+  const uint32_t n = std::max<uint32_t>((1u << depth) - 1, (1u << depth) * (uint32_t)w->C);
+  fit_emit<<<std::min<uint32_t>(1024, (n + 255) / 256), 256, 0, stream>>>(
+      w->fd, depth, w->nodes, w->nmean, d_nodes, d_leaves);
+  return hipGetLastError();
+}
+
+void tree_fit_release(TreeFitWork *w) {
+  if (!w) return;
+  if (w->base) (void)hipFree(w->base);
+  delete w;
+}
+
+} // namespace cgs

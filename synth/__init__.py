@@ -319,3 +319,33 @@ def minibatches(g: np.random.Generator, n_steps: int, batch: int, n_pairs: int) 
 def uniform_indices(g: np.random.Generator, n: int, upper: int) -> np.ndarray:
     """``n`` uniform integers in [0, upper), int64 (e.g. positions in a valid list)."""
     return g.integers(0, upper, size=n, dtype=np.int64)
+
+
+# --------------------------------------------------------------------------
+# Measured (configuration, counter) pairs for model fitting
+# --------------------------------------------------------------------------
+def measured_counters(g: np.random.Generator, digits: np.ndarray, radix: Sequence[int],
+                      n_counters: int, noise: float = 0.02) -> np.ndarray:
+    """Synthetic measured counters of configurations, float32 [n][C].
+
+    Each counter is a sum of four axis-aligned steps on random parameters
+    (what a tuning parameter switching a code path does), a smooth product
+    of two normalised parameter values and multiplicative Gaussian noise; the
+    counters' magnitudes spread over eight decades, like transaction counts
+    next to utilisation percentages."""
+    digits = np.asarray(digits)
+    n, P = digits.shape
+    x = digits.astype(np.float64) / np.maximum(np.asarray(radix, dtype=np.float64) - 1.0, 1.0)
+    Y = np.empty((n, n_counters), dtype=np.float32)
+    for c in range(n_counters):
+        js = g.integers(0, P, 4)
+        th = g.random(4)
+        w = g.random(4) + 0.2
+        a, b = g.integers(0, P, 2)
+        scale = 10.0 ** g.uniform(-2.0, 6.0)
+        v = 0.1 + 0.5 * x[:, a] * x[:, b]
+        for k in range(4):
+            v = v + w[k] * (x[:, js[k]] > th[k])
+        v = v * (1.0 + noise * g.standard_normal(n))
+        Y[:, c] = (scale * v).astype(np.float32)
+    return Y
