@@ -429,6 +429,83 @@ def neighbourhood_path(cgs, n_steps=200):
     return out
 
 
+def _digits(raw, radix):
+    """Digits of raw indices (parameter 0 most significant), for the
+    synthetic measured counters."""
+    raw = np.asarray(raw, dtype=np.int64)
+    out = np.empty((len(raw), len(radix)), dtype=np.int64)
+    for j in range(len(radix) - 1, -1, -1):
+        out[:, j] = raw % radix[j]
+        raw = raw // radix[j]
+    return out
+
+
+FIT_DEPTH, FIT_MIN_LEAF, FIT_COUNTERS = 12, 4, 24
+
+
+_FIT_INPUTS = {}
+
+
+def fit_inputs(spec, valid_raw):
+    """Every valid configuration measured once: synthetic counters (steps on
+    random parameters, a smooth term, 2% noise) and the split keys."""
+    import synth
+    if "Y" not in _FIT_INPUTS:
+        g = synth.rng(7, 1)
+        _FIT_INPUTS["Y"] = synth.measured_counters(g, _digits(valid_raw, spec.radix), spec.radix,
+                                                   FIT_COUNTERS)
+        _FIT_INPUTS["keys"] = synth.uniforms_u64(g, len(valid_raw))
+    return _FIT_INPUTS["Y"], _FIT_INPUTS["keys"]
+
+
+def tree_fit_path(cgs, sp, spec, repeats=5):
+    """Regression-tree fitting (Sect. 3.4.2) on the 2^24 space: all
+    4,813,824 valid configurations as measured points, 24 counters, depth
+    12, leaves of at least 4 points.  fit_ms is the device time of the whole
+    fit (select, quantise, grow, test, choose), inputs resident."""
+    valid = sp.copy_valid()
+    Y, keys = fit_inputs(spec, valid)
+    points = np.arange(len(valid), dtype=np.uint32)
+    runs, walls = [], []
+    rep = None
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        model, rep = cgs.ForestModel.fit(sp, points, Y, keys, FIT_DEPTH, FIT_MIN_LEAF)
+        walls.append(time.perf_counter() - t0)
+        runs.append(rep["fit_ms"])
+        eval_ms = model.eval_ms()
+        model.close()
+    fit_ms = float(np.median(runs))
+    n_test = rep["n_test"] * FIT_COUNTERS
+    return {
+        "points": len(points), "counters": FIT_COUNTERS, "max_depth": FIT_DEPTH,
+        "min_leaf": FIT_MIN_LEAF, "fit_ms_median": fit_ms, "fit_ms_all": runs,
+        "points_per_s": len(points) / (fit_ms / 1e3),
+        "wall_ms_median": float(np.median(walls)) * 1e3,
+        "selected_depth": rep["depth"], "split_nodes": rep["n_split"],
+        "test_mae_by_depth": [a / n_test for a in rep["abs_err"]],
+        "model_eval_ms": eval_ms,
+    }
+
+
+def cpu_fit_baseline(spec, sp, n_sample=250000):
+    """The oracle's tree fit, untouched, single thread, on the first
+    n_sample points of the same fit workload (same counters and keys)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import treefit as TF
+    valid = sp.copy_valid()
+    Y, keys = fit_inputs(spec, valid)
+    digits = _digits(valid[:n_sample], spec.radix)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        r = TF.fit(digits, Y[:n_sample], keys[:n_sample], spec.radix, FIT_DEPTH, FIT_MIN_LEAF)
+        dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sample} of the 4,813,824 fit points, depth {FIT_DEPTH}, "
+                      f"{FIT_COUNTERS} counters ({dt:.1f} s)", "selected_depth": r.depth}
+
+
 def cpu_baseline(spec, forest, n_steps):
     """The oracle, untouched, on a bounded sample of the workload: the valid
     configurations with raw index below 2^22 (a quarter of the raw space),
@@ -504,6 +581,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-online", action="store_true")
     ap.add_argument("--no-neighbourhood", action="store_true")
+    ap.add_argument("--no-fit", action="store_true")
     ap.add_argument("--inference-only", action="store_true",
                     help="only the two perceptron inference sweeps (for counter runs)")
     args = ap.parse_args()
@@ -603,6 +681,11 @@ def main() -> int:
         nbh = neighbourhood_path(cgs)
         log(f"neighbourhood: {nbh}")
 
+    fit = None
+    if not args.no_fit:
+        fit = tree_fit_path(cgs, sp, spec)
+        log(f"tree fit: {fit}")
+
     mlp = None
     if not args.no_mlp:
         mlp = mlp_path(cgs, sp, model)
@@ -612,6 +695,9 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")
         cpu = cpu_baseline(spec, forest, K)
+        if fit is not None:
+            fit["cpu_baseline"] = cpu_fit_baseline(spec, sp)
+            log(f"tree fit cpu baseline: {fit['cpu_baseline']}")
 
     out = {
         "metric": "configs scored/sec per search step (tree vs MLP surrogate) at oracle-exact pick",
@@ -659,6 +745,7 @@ def main() -> int:
         "batch": batch,
         "online": online,
         "neighbourhood": nbh,
+        "tree_fit": fit,
         "hbm_copy_probe": probe,
         "model_eval_ms": model.eval_ms(),
         "space_create_ms": t_enum * 1e3,

@@ -26,8 +26,12 @@
 // (one byte per parameter, PW = ceil(P/4) words), then q[C].  The training
 // rows of the nodes still searched are kept contiguous, segment by segment in
 // heap order, and are repartitioned into the next level's segments after each
-// level.  Histograms hold, per open node, the sum of q for every (parameter,
-// digit, counter) plus a count column: [sum_j R_j][C + 1] int64.
+// level.  Segments are cut into chunks of at most 256 rows; the partition
+// counts each chunk's rows per child, scans the counts and moves every chunk
+// to fixed offsets, so the row order is stable and no two workgroups contend
+// for an output cursor.  Histograms hold, per open node, the sum of q for
+// every (parameter, digit, counter) plus a count column:
+// [sum_j R_j][C + 1] int64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,8 +49,8 @@ struct FitDev {
   uint32_t n, n_train, n_test, n_valid;
   uint32_t C, P, PW, W;
   uint32_t D, min_leaf, min_split, sumR;
-  uint32_t entries, items, pad0, pad1;
-  FastDiv divW;
+  uint32_t entries, items, Cp, pad0;
+  FastDiv divW, divC;
   uint32_t radix[CGS_MAX_PARAMS];
   uint32_t roff[CGS_MAX_PARAMS + 1]; // first bin of parameter j; roff[P] = sumR
   // written by the kernels
@@ -56,9 +60,8 @@ struct FitDev {
   uint32_t key_hist[256];
   uint32_t absmax[CGS_MAX_COUNTERS];
   int32_t s[CGS_MAX_COUNTERS];
-  uint32_t cur_train, cur_test;
   uint32_t n_split;
-  uint32_t lvl_K[2], lvl_R[2];
+  uint32_t lvl_K[2], lvl_R[2], lvl_NCH[2];
   int32_t depth_sel;
   uint64_t A[CGS_MAX_DEPTH + 1], Blo[CGS_MAX_DEPTH + 1], Bhi[CGS_MAX_DEPTH + 1];
 };
@@ -67,9 +70,10 @@ namespace {
 
 constexpr int kFitThreads = 256;
 constexpr uint32_t kFitGrid = 1024;       // workgroups of the grid-stride passes
-constexpr uint32_t kTile = 256;           // rows per staged tile (int32 sums stay below 2^31)
+constexpr uint32_t kTile = 256;           // rows per chunk / staged tile
 constexpr uint16_t kAlwaysLeftNode = (uint16_t)(255u << 8);
-constexpr uint32_t kLayoutThreads = 1024;
+constexpr uint32_t kScanThreads = 1024;
+constexpr int kHistUnroll = 1;            // rows per round of the histogram loop
 
 __device__ __forceinline__ uint64_t split_key(uint64_t key, uint64_t i) {
   return (key & 0xFFFFFFFF00000000ull) | i;
@@ -94,13 +98,13 @@ __device__ __forceinline__ void copy_rows_out(const uint32_t *lds, const uint32_
   }
 }
 
-// Largest slot s in [0, K) with seg_start[s] <= a (segments are non-empty).
-__device__ __forceinline__ uint32_t slot_containing(const uint32_t *seg_start, uint32_t K,
-                                                    uint32_t a) {
+// Largest s in [0, K) with start[s] <= a (start ascending, start[0] = 0).
+__device__ __forceinline__ uint32_t last_at_or_below(const uint32_t *start, uint32_t K,
+                                                     uint32_t a) {
   uint32_t lo = 0, hi = K;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (seg_start[mid] <= a) lo = mid;
+    if (start[mid] <= a) lo = mid;
     else hi = mid;
   }
   return lo;
@@ -110,6 +114,27 @@ __global__ void fit_zero(uint64_t *__restrict__ p, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = 0;
+}
+
+// Exclusive prefix sums of in[0..n) (one workgroup; each thread scans a run
+// of consecutive entries).  n is *n_dev when given, else n_host.
+__global__ __launch_bounds__(kScanThreads) void fit_excl_scan(const uint64_t *__restrict__ in,
+                                                              uint64_t *__restrict__ out,
+                                                              const uint32_t *__restrict__ n_dev,
+                                                              uint32_t n_host) {
+  __shared__ uint64_t scratch[kScanThreads / 64];
+  const uint32_t n = n_dev ? *n_dev : n_host;
+  const uint32_t t = threadIdx.x, per = (n + kScanThreads - 1) / kScanThreads;
+  const uint32_t a = min(n, t * per), b = min(n, a + per);
+  uint64_t mine = 0;
+  for (uint32_t i = a; i < b; ++i) mine += in[i];
+  uint64_t tot;
+  uint64_t run = block_excl_scan<kScanThreads>(mine, scratch, tot);
+  for (uint32_t i = a; i < b; ++i) {
+    const uint64_t v = in[i];
+    out[i] = run;
+    run += v;
+  }
 }
 
 // Validation, per-counter max |y| and the histogram of the keys' top byte.
@@ -133,14 +158,40 @@ __global__ __launch_bounds__(kFitThreads) void fit_prepare(FitDev *__restrict__ 
   const uint64_t step = gsz / C * C, total = (uint64_t)n * C;
   if (gid < step) {
     uint32_t mx = 0;
-    for (uint64_t k = gid; k < total; k += step) {
+    uint64_t k = gid;
+    for (; k + 3 * step < total; k += 4 * step) {
+      float y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = Y[k + u * step];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!isfinite(y[u])) err |= 2u;
+        else mx = max(mx, __float_as_uint(fabsf(y[u])));
+      }
+    }
+    for (; k < total; k += step) {
       const float y = Y[k];
       if (!isfinite(y)) err |= 2u;
       else mx = max(mx, __float_as_uint(fabsf(y)));
     }
     if (mx) atomicMax(&s_max[gid % C], mx);
   }
-  for (uint64_t i = gid; i < n; i += gsz) {
+  uint64_t i = gid;
+  for (; i + 3 * gsz < n; i += 4 * gsz) {
+    uint32_t p[4];
+    uint64_t kk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      p[u] = pts[i + u * gsz];
+      kk[u] = keys[i + u * gsz];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (p[u] >= nv) err |= 1u;
+      atomicAdd(&s_hist[(uint32_t)(split_key(kk[u], i + u * gsz) >> 56)], 1u);
+    }
+  }
+  for (; i < n; i += gsz) {
     if (pts[i] >= nv) err |= 1u;
     atomicAdd(&s_hist[(uint32_t)(split_key(keys[i], i) >> 56)], 1u);
   }
@@ -197,21 +248,35 @@ __global__ __launch_bounds__(kFitThreads) void fit_key_hist(FitDev *__restrict__
   if (s_hist[t]) atomicAdd(&fd->key_hist[t], s_hist[t]);
 }
 
-// Rows of every point: digits and quantised targets; training rows and test
-// rows each packed contiguously (order within a half is immaterial: every sum
-// taken over rows is an exact integer).
+// Training points per tile of 256 points (for the scatter's offsets).
+__global__ __launch_bounds__(kFitThreads) void fit_tile_count(const FitDev *__restrict__ fd,
+                                                              const uint64_t *__restrict__ keys,
+                                                              uint64_t *__restrict__ cnt) {
+  __shared__ uint64_t scratch[kFitThreads / 64];
+  const uint32_t n = fd->n, t = threadIdx.x;
+  const uint64_t T = fd->key_T;
+  for (uint32_t tile = blockIdx.x; (uint64_t)tile * kTile < n; tile += gridDim.x) {
+    const uint32_t i = tile * kTile + t;
+    const uint64_t f = (i < n && split_key(keys[i], i) <= T) ? 1ull : 0ull;
+    const uint64_t s = block_sum<kFitThreads>(f, scratch);
+    if (t == 0) cnt[tile] = s;
+  }
+}
+
+// Rows of every point: digits and quantised targets, training and test
+// rows each packed contiguously in point order.
 __global__ __launch_bounds__(kFitThreads) void fit_scatter(
     FitDev *__restrict__ fd, const SpaceDev *__restrict__ sp, const uint32_t *__restrict__ idx,
     const uint32_t *__restrict__ pts, const float *__restrict__ Y,
-    const uint64_t *__restrict__ keys, uint32_t *__restrict__ rows,
-    uint32_t *__restrict__ test_rows) {
-  extern __shared__ uint32_t lds[]; // [kTile][W] rows, then [kTile][C] targets
+    const uint64_t *__restrict__ keys, const uint64_t *__restrict__ tile_off,
+    uint32_t *__restrict__ rows, uint32_t *__restrict__ test_rows) {
+  extern __shared__ uint32_t lds[]; // [kTile][W] rows, then [kTile][Cp] targets
   __shared__ int32_t s_scale[CGS_MAX_COUNTERS];
   __shared__ uint32_t s_src[2][kTile];
   __shared__ uint64_t scratch[kFitThreads / 64];
-  __shared__ uint32_t s_base[2];
   const uint32_t t = threadIdx.x;
-  const uint32_t n = fd->n, C = fd->C, P = fd->P, PW = fd->PW, W = fd->W, nv = fd->n_valid;
+  const uint32_t n = fd->n, C = fd->C, Cp = fd->Cp, P = fd->P, PW = fd->PW, W = fd->W;
+  const uint32_t nv = fd->n_valid;
   const uint64_t T = fd->key_T;
   float *ytile = reinterpret_cast<float *>(lds + kTile * W);
   if (t < C) {
@@ -221,15 +286,19 @@ __global__ __launch_bounds__(kFitThreads) void fit_scatter(
     s_scale[t] = 22 - e;
     if (blockIdx.x == 0) fd->s[t] = 22 - e;
   }
-  for (uint32_t tile = blockIdx.x * kTile; tile < n; tile += gridDim.x * kTile) {
-    const uint32_t nr = min(kTile, n - tile);
+  for (uint32_t tile = blockIdx.x; (uint64_t)tile * kTile < n; tile += gridDim.x) {
+    const uint32_t first = tile * kTile, nr = min(kTile, n - first);
     __syncthreads();
-    for (uint32_t k = t; k < nr * C; k += kFitThreads) ytile[k] = Y[(uint64_t)tile * C + k];
+    const float *ysrc = Y + (uint64_t)first * C;
+    for (uint32_t k = t; k < nr * C; k += kFitThreads) {
+      const uint32_t r = fastdiv(k, fd->divC);
+      ytile[r * Cp + (k - r * C)] = ysrc[k];
+    }
     __syncthreads();
     const bool live = t < nr;
     bool train = false;
     if (live) {
-      const uint32_t i = tile + t;
+      const uint32_t i = first + t;
       train = split_key(keys[i], i) <= T;
       const uint32_t p = pts[i];
       uint64_t lo = 0, hi = 0;
@@ -244,7 +313,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_scatter(
         row[w] = word;
       }
       for (uint32_t c = 0; c < C; ++c) {
-        const float y = ytile[t * C + c];
+        const float y = ytile[t * Cp + c];
         const double v = isfinite(y) ? ldexp((double)y, s_scale[c]) : 0.0;
         row[PW + c] = (uint32_t)(int32_t)rint(v);
       }
@@ -253,17 +322,14 @@ __global__ __launch_bounds__(kFitThreads) void fit_scatter(
     uint64_t tot;
     const uint64_t rank = block_excl_scan<kFitThreads>(flag, scratch, tot);
     const uint32_t ntr = (uint32_t)tot, nte = (uint32_t)(tot >> 32);
-    if (t == 0) {
-      s_base[0] = ntr ? atomicAdd(&fd->cur_train, ntr) : 0u;
-      s_base[1] = nte ? atomicAdd(&fd->cur_test, nte) : 0u;
-    }
     if (live) {
       if (train) s_src[0][(uint32_t)rank] = t;
       else s_src[1][(uint32_t)(rank >> 32)] = t;
     }
     __syncthreads();
-    copy_rows_out(lds, s_src[0], ntr, W, fd->divW, rows, s_base[0], fd->n_train);
-    copy_rows_out(lds, s_src[1], nte, W, fd->divW, test_rows, s_base[1], fd->n_test);
+    const uint32_t base_tr = (uint32_t)tile_off[tile], base_te = first - base_tr;
+    copy_rows_out(lds, s_src[0], ntr, W, fd->divW, rows, base_tr, fd->n_train);
+    copy_rows_out(lds, s_src[1], nte, W, fd->divW, test_rows, base_te, fd->n_test);
   }
 }
 
@@ -282,7 +348,14 @@ __global__ __launch_bounds__(kFitThreads) void fit_root_sums(const FitDev *__res
   if (gid < rstep * C) {
     const uint32_t c = (uint32_t)(gid % C);
     int64_t acc = 0;
-    for (uint64_t r = gid / C; r < n; r += rstep) acc += (int32_t)rows[r * W + PW + c];
+    uint64_t r = gid / C;
+    for (; r + 3 * rstep < n; r += 4 * rstep) {
+      int32_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = (int32_t)rows[(r + u * rstep) * W + PW + c];
+      acc += (int64_t)v[0] + v[1] + v[2] + v[3];
+    }
+    for (; r < n; r += rstep) acc += (int32_t)rows[r * W + PW + c];
     if (acc) atomicAdd(reinterpret_cast<unsigned long long *>(&s_sum[c]), (unsigned long long)acc);
   }
   __syncthreads();
@@ -306,30 +379,35 @@ __global__ void fit_root(const FitDev *__restrict__ fd, uint32_t *__restrict__ n
 }
 
 // Segments of the open nodes of level L (heap order): slot, first row and
-// write cursor of each, and the level's totals.
-__global__ __launch_bounds__(kLayoutThreads) void fit_layout(
+// first chunk of each, and the level's totals.
+__global__ __launch_bounds__(kScanThreads) void fit_layout(
     FitDev *__restrict__ fd, int L, const uint8_t *__restrict__ nstate,
     const uint32_t *__restrict__ ncount, uint32_t *__restrict__ open_node,
-    uint32_t *__restrict__ seg_start, uint32_t *__restrict__ cursor,
+    uint32_t *__restrict__ seg_start, uint32_t *__restrict__ chunk_start,
     uint32_t *__restrict__ slot_of, uint32_t kcap) {
-  __shared__ uint64_t scratch[kLayoutThreads / 64];
+  __shared__ uint64_t scratch[kScanThreads / 64];
   const uint32_t t = threadIdx.x, cnt = 1u << L, base = cnt - 1;
-  const uint32_t per = (cnt + kLayoutThreads - 1) / kLayoutThreads;
+  const uint32_t per = (cnt + kScanThreads - 1) / kScanThreads;
   const uint32_t a = min(cnt, t * per), b = min(cnt, a + per);
-  uint64_t mine = 0; // rows << 16 | open nodes
+  uint64_t mine = 0, mine_ch = 0; // rows << 16 | open nodes; chunks
   for (uint32_t k = a; k < b; ++k)
-    if (nstate[base + k]) mine += ((uint64_t)ncount[base + k] << 16) | 1ull;
-  uint64_t tot;
-  const uint64_t before = block_excl_scan<kLayoutThreads>(mine, scratch, tot);
+    if (nstate[base + k]) {
+      mine += ((uint64_t)ncount[base + k] << 16) | 1ull;
+      mine_ch += (ncount[base + k] + kTile - 1) / kTile;
+    }
+  uint64_t tot, tot_ch;
+  const uint64_t before = block_excl_scan<kScanThreads>(mine, scratch, tot);
+  const uint64_t before_ch = block_excl_scan<kScanThreads>(mine_ch, scratch, tot_ch);
   uint32_t slot = (uint32_t)(before & 0xffffu);
-  uint32_t row = (uint32_t)(before >> 16);
+  uint32_t row = (uint32_t)(before >> 16), ch = (uint32_t)before_ch;
   for (uint32_t k = a; k < b; ++k) {
     if (nstate[base + k] && slot < kcap) {
       open_node[slot] = base + k;
       seg_start[slot] = row;
-      cursor[slot] = row;
+      chunk_start[slot] = ch;
       slot_of[k] = slot;
       row += ncount[base + k];
+      ch += (ncount[base + k] + kTile - 1) / kTile;
       ++slot;
     } else {
       slot_of[k] = ~0u;
@@ -340,109 +418,117 @@ __global__ __launch_bounds__(kLayoutThreads) void fit_layout(
     const uint32_t K = min((uint32_t)(tot & 0xffffu), kcap);
     if (K < (uint32_t)(tot & 0xffffu)) atomicOr(&fd->err, 4u);
     seg_start[K] = (uint32_t)(tot >> 16);
+    chunk_start[K] = (uint32_t)tot_ch;
     fd->lvl_K[L & 1] = K;
     fd->lvl_R[L & 1] = (uint32_t)(tot >> 16);
+    fd->lvl_NCH[L & 1] = (uint32_t)tot_ch;
   }
 }
 
-// Histograms of level L: each workgroup takes a contiguous range of the
-// level's rows, stages tiles of one node in LDS, accumulates int32 sums per
-// (parameter, digit, counter) there, folds them into int64 registers after
-// every tile and adds them to the node's histogram when its segment ends.
-// Thread t owns items t, t + NT, ... of the P x (C + 1) (parameter, column)
-// items, so no two threads touch one LDS entry.
-template <int IPT>
-__global__ __launch_bounds__(1024) void fit_hist(const FitDev *__restrict__ fd, int L,
-                                                 const uint32_t *__restrict__ rows,
-                                                 const uint32_t *__restrict__ seg_start,
-                                                 int64_t *__restrict__ ghist, uint32_t CH) {
-  extern __shared__ uint32_t lds[]; // [entries] int32 sums, then [CH][W] rows
+// Histograms of level L.  Each workgroup takes a contiguous range of the
+// level's rows and cuts it at segment (node) boundaries; within one node's
+// part, row group g of G = 256 / (C + 1) groups takes a contiguous run of
+// rows and lane (g, c) handles column c of them (column C is the count).
+// Rows arrive in configuration order, so most parameters keep their digit
+// over long runs: each lane keeps, per parameter, the digit of the current
+// run and its sum in registers and adds the sum to the workgroup's int64
+// LDS histogram only when the digit changes.  At the end of a node's part the
+// workgroup adds its LDS histogram to the node's histogram in device memory.
+template <int MAXP>
+__global__ __launch_bounds__(kFitThreads) void fit_hist(const FitDev *__restrict__ fd, int L,
+                                                        const uint32_t *__restrict__ rows,
+                                                        const uint32_t *__restrict__ seg_start,
+                                                        int64_t *__restrict__ ghist) {
+  extern __shared__ int64_t h64[]; // [entries]
   const uint32_t set = L & 1, K = fd->lvl_K[set], R = fd->lvl_R[set];
   if (R == 0) return;
   const uint32_t a = (uint32_t)((uint64_t)R * blockIdx.x / gridDim.x);
   const uint32_t b = (uint32_t)((uint64_t)R * (blockIdx.x + 1) / gridDim.x);
   if (a >= b) return;
-  const uint32_t t = threadIdx.x, NT = blockDim.x;
-  const uint32_t C = fd->C, C1 = C + 1, PW = fd->PW, W = fd->W, I = fd->items, E = fd->entries;
-  int32_t *h32 = reinterpret_cast<int32_t *>(lds);
-  uint32_t *rl = lds + E;
-
-  uint32_t jj[IPT], cc[IPT], off[IPT], rr[IPT];
-  int64_t acc[IPT][CGS_MAX_RADIX];
+  const uint32_t t = threadIdx.x;
+  const uint32_t C = fd->C, C1 = C + 1, P = fd->P, PW = fd->PW, W = fd->W, E = fd->entries;
+  const uint32_t G = kFitThreads / C1, g = t / C1, c = t - g * C1;
+  const bool active = g < G;
+  uint32_t roffc[MAXP]; // (first bin of j) * (C + 1) + c
 #pragma unroll
-  for (int k = 0; k < IPT; ++k) {
-    const uint32_t it = t + k * NT;
-    rr[k] = 0;
-    jj[k] = 0;
-    cc[k] = 0;
-    off[k] = 0;
-    if (it < I) {
-      const uint32_t j = it / C1, c = it - j * C1;
-      jj[k] = j;
-      cc[k] = c;
-      rr[k] = fd->radix[j];
-      off[k] = fd->roff[j] * C1 + c;
-    }
-#pragma unroll
-    for (int v = 0; v < CGS_MAX_RADIX; ++v) acc[k][v] = 0;
-  }
-  for (uint32_t e = t; e < E; e += NT) h32[e] = 0;
+  for (int j = 0; j < MAXP; ++j) roffc[j] = (j < (int)P) ? fd->roff[j] * C1 + c : 0u;
+  for (uint32_t e = t; e < E; e += kFitThreads) h64[e] = 0;
+  __syncthreads();
 
-  uint32_t slot = slot_containing(seg_start, K, a);
-  uint32_t seg_end = seg_start[slot + 1];
+  uint32_t slot = last_at_or_below(seg_start, K, a);
   uint32_t pos = a;
   while (pos < b) {
-    const uint32_t end = min(min(b, seg_end), pos + CH);
+    const uint32_t seg_end = seg_start[slot + 1];
+    const uint32_t end = min(b, seg_end);
     if (end <= pos) break; // segments are never empty
-    const uint32_t nr = end - pos;
-    __syncthreads();
-    const uint32_t *src = rows + (uint64_t)pos * W;
-    for (uint32_t k = t; k < nr * W; k += NT) rl[k] = src[k];
-    __syncthreads();
+    if (active) {
+      const uint32_t m = end - pos;
+      const uint32_t r0 = pos + (uint32_t)((uint64_t)m * g / G);
+      const uint32_t r1 = pos + (uint32_t)((uint64_t)m * (g + 1) / G);
+      uint32_t cur[MAXP];
+      int64_t acc[MAXP];
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-      if (rr[k]) {
-        const uint32_t dw = jj[k] >> 2, sh = 8u * (jj[k] & 3u), c = cc[k], o = off[k];
-        const bool cnt = c == C;
-        for (uint32_t r = 0; r < nr; ++r) {
-          const uint32_t *row = rl + r * W;
-          const uint32_t v = (row[dw] >> sh) & 255u;
-          const int32_t val = cnt ? 1 : (int32_t)row[PW + c];
-          atomicAdd(&h32[o + v * C1], val);
-        }
+      for (int j = 0; j < MAXP; ++j) {
+        cur[j] = 0xffu;
+        acc[j] = 0;
       }
-    }
-    __syncthreads();
+      constexpr int NW = (MAXP + 3) / 4, U = kHistUnroll;
+      auto add_row = [&](const uint32_t *dw, int64_t q) {
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-#pragma unroll
-      for (int v = 0; v < CGS_MAX_RADIX; ++v) {
-        if ((uint32_t)v < rr[k]) {
-          const uint32_t e = off[k] + v * C1;
-          acc[k][v] += h32[e];
-          h32[e] = 0;
-        }
-      }
-    }
-    pos = end;
-    if (pos == seg_end || pos == b) {
-      int64_t *H = ghist + (uint64_t)slot * E;
-#pragma unroll
-      for (int k = 0; k < IPT; ++k) {
-#pragma unroll
-        for (int v = 0; v < CGS_MAX_RADIX; ++v) {
-          if ((uint32_t)v < rr[k] && acc[k][v]) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(H + off[k] + v * C1),
-                      (unsigned long long)acc[k][v]);
-            acc[k][v] = 0;
+        for (int j = 0; j < MAXP; ++j) {
+          if (j < (int)P) {
+            const uint32_t v = (dw[j >> 2] >> (8 * (j & 3))) & 255u;
+            if (v != cur[j]) {
+              if (cur[j] != 0xffu)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&h64[roffc[j] + cur[j] * C1]),
+                          (unsigned long long)acc[j]);
+              cur[j] = v;
+              acc[j] = 0;
+            }
+            acc[j] += q;
           }
         }
+      };
+      uint32_t r = r0;
+      // U rows per round: their loads all issue before the first is used
+      for (; r + U <= r1; r += U) {
+        uint32_t dw[U][NW];
+        int64_t q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t *row = rows + (uint64_t)(r + u) * W;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) dw[u][w] = (w < (int)PW) ? row[w] : 0u;
+          q[u] = c < C ? (int64_t)(int32_t)row[PW + c] : 1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) add_row(dw[u], q[u]);
       }
-      if (pos < b) {
-        ++slot;
-        seg_end = seg_start[slot + 1];
+      for (; r < r1; ++r) {
+        const uint32_t *row = rows + (uint64_t)r * W;
+        uint32_t dw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) dw[w] = (w < (int)PW) ? row[w] : 0u;
+        add_row(dw, c < C ? (int64_t)(int32_t)row[PW + c] : 1);
+      }
+#pragma unroll
+      for (int j = 0; j < MAXP; ++j)
+        if (j < (int)P && cur[j] != 0xffu)
+          atomicAdd(reinterpret_cast<unsigned long long *>(&h64[roffc[j] + cur[j] * C1]),
+                    (unsigned long long)acc[j]);
+    }
+    __syncthreads();
+    int64_t *H = ghist + (uint64_t)slot * E;
+    for (uint32_t e = t; e < E; e += kFitThreads) {
+      const int64_t v = h64[e];
+      if (v) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(H + e), (unsigned long long)v);
+        h64[e] = 0;
       }
     }
+    __syncthreads();
+    pos = end;
+    ++slot;
   }
 }
 
@@ -610,109 +696,176 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
   for (uint32_t e = t; e < fd->entries; e += kFitThreads) H[e] = 0;
 }
 
+// Chunk ch of level L: its segment, first row and row count.
+struct ChunkRef {
+  uint32_t slot, first, nr;
+};
+__device__ __forceinline__ ChunkRef chunk_ref(uint32_t ch, const uint32_t *chunk_start,
+                                              const uint32_t *seg_start, uint32_t K) {
+  ChunkRef c;
+  c.slot = last_at_or_below(chunk_start, K, ch);
+  c.first = seg_start[c.slot] + (ch - chunk_start[c.slot]) * kTile;
+  c.nr = min(kTile, seg_start[c.slot + 1] - c.first);
+  return c;
+}
+
+// The split a chunk's rows follow: parameter, threshold, and whether each
+// child is searched at the next level (rows of the others are dropped).
+struct ChunkSplit {
+  uint32_t j, thr, lc, rc;
+  bool lopen, ropen;
+};
+__device__ __forceinline__ ChunkSplit chunk_split(uint32_t slot, const uint32_t *open_node,
+                                                  const uint16_t *nodes, const uint8_t *nstate) {
+  ChunkSplit s;
+  const uint32_t node = open_node[slot];
+  const uint16_t nd = nodes[node];
+  s.j = nd & 255u;
+  s.thr = nd >> 8;
+  s.lc = 2 * node + 1;
+  s.rc = s.lc + 1;
+  s.lopen = nstate[s.lc] != 0;
+  s.ropen = nstate[s.rc] != 0;
+  return s;
+}
+
+// Rows of each chunk kept for the left and the right child:
+// cnt[ch] = n_left | n_right << 32.
+__global__ __launch_bounds__(kFitThreads) void fit_pcount(
+    const FitDev *__restrict__ fd, int L, const uint32_t *__restrict__ rows_in,
+    const uint32_t *__restrict__ seg_start, const uint32_t *__restrict__ chunk_start,
+    const uint32_t *__restrict__ open_node, const uint8_t *__restrict__ nstate,
+    const uint16_t *__restrict__ nodes, uint64_t *__restrict__ cnt) {
+  __shared__ uint64_t scratch[kFitThreads / 64];
+  const uint32_t set = L & 1, K = fd->lvl_K[set], NCH = fd->lvl_NCH[set], W = fd->W;
+  const uint32_t t = threadIdx.x;
+  for (uint32_t ch = blockIdx.x; ch < NCH; ch += gridDim.x) {
+    const ChunkRef c = chunk_ref(ch, chunk_start, seg_start, K);
+    const ChunkSplit s = chunk_split(c.slot, open_node, nodes, nstate);
+    uint64_t f = 0;
+    if (t < c.nr) {
+      const bool left = row_digit(rows_in + (uint64_t)(c.first + t) * W, s.j) <= s.thr;
+      if (left ? s.lopen : s.ropen) f = left ? 1ull : (1ull << 32);
+    }
+    const uint64_t sum = block_sum<kFitThreads>(f, scratch);
+    if (t == 0) cnt[ch] = sum;
+  }
+}
+
 // Moves the rows of level L's open nodes into the segments of their open
-// children (rows of closed children are dropped).
+// children, chunk by chunk at the offsets the scanned counts give (stable).
 __global__ __launch_bounds__(kFitThreads) void fit_partition(
     const FitDev *__restrict__ fd, int L, const uint32_t *__restrict__ rows_in,
     uint32_t *__restrict__ rows_out, const uint32_t *__restrict__ seg_start,
-    const uint32_t *__restrict__ open_node, uint32_t *__restrict__ cursor_next,
+    const uint32_t *__restrict__ chunk_start, const uint32_t *__restrict__ open_node,
+    const uint64_t *__restrict__ pre, const uint32_t *__restrict__ seg_start_next,
     const uint32_t *__restrict__ slot_of_next, const uint8_t *__restrict__ nstate,
     const uint16_t *__restrict__ nodes) {
   extern __shared__ uint32_t rl[]; // [kTile][W]
   __shared__ uint32_t s_src[2][kTile];
   __shared__ uint64_t scratch[kFitThreads / 64];
-  __shared__ uint32_t s_base[2];
-  const uint32_t set = L & 1, K = fd->lvl_K[set], R = fd->lvl_R[set];
-  if (R == 0) return;
-  const uint32_t a = (uint32_t)((uint64_t)R * blockIdx.x / gridDim.x);
-  const uint32_t b = (uint32_t)((uint64_t)R * (blockIdx.x + 1) / gridDim.x);
-  if (a >= b) return;
-  const uint32_t t = threadIdx.x, W = fd->W;
+  const uint32_t set = L & 1, K = fd->lvl_K[set], NCH = fd->lvl_NCH[set], W = fd->W;
+  const uint32_t t = threadIdx.x;
   const uint32_t child_base = (2u << L) - 1;
-  uint32_t slot = slot_containing(seg_start, K, a);
-  uint32_t seg_end = seg_start[slot + 1];
-  uint32_t pos = a;
-  while (pos < b) {
-    const uint32_t end = min(min(b, seg_end), pos + kTile);
-    if (end <= pos) break; // segments are never empty
-    const uint32_t nr = end - pos;
-    const uint32_t node = open_node[slot];
-    const uint16_t nd = nodes[node];
-    const uint32_t j = nd & 255u, thr = nd >> 8;
-    const uint32_t lc = 2 * node + 1, rc = lc + 1;
-    const bool lopen = nstate[lc] != 0, ropen = nstate[rc] != 0;
+  for (uint32_t ch = blockIdx.x; ch < NCH; ch += gridDim.x) {
+    const ChunkRef c = chunk_ref(ch, chunk_start, seg_start, K);
+    const ChunkSplit s = chunk_split(c.slot, open_node, nodes, nstate);
     __syncthreads();
-    const uint32_t *src = rows_in + (uint64_t)pos * W;
-    for (uint32_t k = t; k < nr * W; k += kFitThreads) rl[k] = src[k];
+    const uint32_t *src = rows_in + (uint64_t)c.first * W;
+    for (uint32_t k = t; k < c.nr * W; k += kFitThreads) rl[k] = src[k];
     __syncthreads();
     bool keep = false, left = false;
-    if (t < nr) {
-      left = row_digit(rl + t * W, j) <= thr;
-      keep = left ? lopen : ropen;
+    if (t < c.nr) {
+      left = row_digit(rl + t * W, s.j) <= s.thr;
+      keep = left ? s.lopen : s.ropen;
     }
     const uint64_t flag = keep ? (left ? 1ull : (1ull << 32)) : 0ull;
     uint64_t tot;
     const uint64_t rank = block_excl_scan<kFitThreads>(flag, scratch, tot);
-    const uint32_t nl = (uint32_t)tot, nrr = (uint32_t)(tot >> 32);
-    if (t == 0) {
-      s_base[0] = nl ? atomicAdd(&cursor_next[slot_of_next[lc - child_base]], nl) : 0u;
-      s_base[1] = nrr ? atomicAdd(&cursor_next[slot_of_next[rc - child_base]], nrr) : 0u;
-    }
     if (keep) {
       if (left) s_src[0][(uint32_t)rank] = t;
       else s_src[1][(uint32_t)(rank >> 32)] = t;
     }
     __syncthreads();
-    copy_rows_out(rl, s_src[0], nl, W, fd->divW, rows_out, s_base[0], fd->n_train);
-    copy_rows_out(rl, s_src[1], nrr, W, fd->divW, rows_out, s_base[1], fd->n_train);
-    pos = end;
-    if (pos == seg_end && pos < b) {
-      ++slot;
-      seg_end = seg_start[slot + 1];
+    // offsets within each child's segment: kept rows of this segment's
+    // earlier chunks
+    const uint64_t before = pre[ch] - pre[chunk_start[c.slot]];
+    const uint32_t nl = (uint32_t)tot, nrr = (uint32_t)(tot >> 32);
+    if (nl) {
+      const uint32_t base = seg_start_next[slot_of_next[s.lc - child_base]] + (uint32_t)before;
+      copy_rows_out(rl, s_src[0], nl, W, fd->divW, rows_out, base, fd->n_train);
+    }
+    if (nrr) {
+      const uint32_t base =
+          seg_start_next[slot_of_next[s.rc - child_base]] + (uint32_t)(before >> 32);
+      copy_rows_out(rl, s_src[1], nrr, W, fd->divW, rows_out, base, fd->n_train);
     }
   }
 }
 
-// Test errors of the cut trees: each test row walks the grown tree once and
-// adds |e| and e^2 (split in 32-bit halves) at every depth.
+// Test errors of the cut trees, per staged tile of test rows in two phases:
+// one thread per row walks the grown tree (node table in LDS) and records
+// the node it reaches at every depth; then thread t handles counter t % C of
+// rows t / C, t / C + 256 / C, ... and adds |e| and e^2 at every depth, the
+// C lanes of one row reading one node's values together.
 __global__ __launch_bounds__(kFitThreads) void fit_test(FitDev *__restrict__ fd,
                                                         const uint32_t *__restrict__ test_rows,
                                                         const uint16_t *__restrict__ nodes,
                                                         const int32_t *__restrict__ nmean) {
-  extern __shared__ uint32_t rl[]; // [kTile][W]
+  extern __shared__ uint32_t lds[]; // [kTile][W] rows, [kTile][ND] path, nodes
   constexpr int ND = CGS_MAX_DEPTH + 1;
   const uint32_t t = threadIdx.x, n = fd->n_test, C = fd->C, PW = fd->PW, W = fd->W;
-  const uint32_t D = fd->D;
-  uint64_t A[ND], BL[ND], BH[ND];
+  const uint32_t D = fd->D, n_int = (1u << D) - 1;
+  uint32_t *rl = lds;
+  uint32_t *path = lds + kTile * W; // node * C at every depth
+  uint16_t *tree = reinterpret_cast<uint16_t *>(path + kTile * ND);
+  for (uint32_t k = t; k < n_int; k += kFitThreads) tree[k] = nodes[k];
+  const uint32_t RP = kFitThreads / C; // rows per round (C <= 64)
+  const uint32_t rs = t / C, c = t - rs * C;
+  const bool active = rs < RP;
+  // per thread: |e| and e^2 sums (at most 2^46 per term, few terms per thread)
+  uint64_t A[ND], B[ND];
 #pragma unroll
-  for (int d = 0; d < ND; ++d) A[d] = BL[d] = BH[d] = 0;
-  for (uint32_t tile = blockIdx.x * kTile; tile < n; tile += gridDim.x * kTile) {
-    const uint32_t nr = min(kTile, n - tile);
+  for (int d = 0; d < ND; ++d) A[d] = B[d] = 0;
+  for (uint32_t tile = blockIdx.x; (uint64_t)tile * kTile < n; tile += gridDim.x) {
+    const uint32_t first = tile * kTile, nr = min(kTile, n - first);
     __syncthreads();
-    const uint32_t *src = test_rows + (uint64_t)tile * W;
+    const uint32_t *src = test_rows + (uint64_t)first * W;
     for (uint32_t k = t; k < nr * W; k += kFitThreads) rl[k] = src[k];
     __syncthreads();
     if (t < nr) {
       const uint32_t *row = rl + t * W;
       uint32_t node = 0;
+      path[t * ND] = 0;
+      for (uint32_t d = 0; d < D; ++d) {
+        const uint16_t nd = tree[node];
+        node = 2 * node + (row_digit(row, nd & 255u) <= (uint32_t)(nd >> 8) ? 1u : 2u);
+        path[t * ND + d + 1] = node * C;
+      }
+    }
+    __syncthreads();
+    if (active) {
+      // four rows per round: their node-value loads are in flight together
+      for (uint32_t r = rs; r < nr; r += 4 * RP) {
+        int32_t m[4][ND], q[4];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        if ((uint32_t)d <= D) {
-          const int32_t *m = nmean + (uint64_t)node * C;
-          uint64_t ea = 0, el = 0, eh = 0;
-          for (uint32_t c = 0; c < C; ++c) {
-            const int64_t e = (int64_t)m[c] - (int64_t)(int32_t)row[PW + c];
-            const uint64_t e2 = (uint64_t)(e * e);
-            ea += (uint64_t)(e < 0 ? -e : e);
-            el += e2 & 0xffffffffull;
-            eh += e2 >> 32;
-          }
-          A[d] += ea;
-          BL[d] += el;
-          BH[d] += eh;
-          if ((uint32_t)d < D) {
-            const uint16_t nd = nodes[node];
-            node = 2 * node + (row_digit(row, nd & 255u) <= (uint32_t)(nd >> 8) ? 1u : 2u);
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t ru = r + u * RP;
+          q[u] = ru < nr ? (int32_t)rl[ru * W + PW + c] : 0;
+          const uint32_t *pr = path + ru * ND;
+#pragma unroll
+          for (int d = 0; d < ND; ++d) m[u][d] = (ru < nr && (uint32_t)d <= D) ? nmean[pr[d] + c] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            // |m|, |q| <= 2^22: |e| < 2^24 and e^2 < 2^48; rows past the
+            // tile contribute m = q = 0
+            const int32_t e = m[u][d] - q[u];
+            const uint32_t ae = (uint32_t)(e < 0 ? -e : e);
+            A[d] += ae;
+            B[d] += (uint64_t)ae * ae;
           }
         }
       }
@@ -721,7 +874,8 @@ __global__ __launch_bounds__(kFitThreads) void fit_test(FitDev *__restrict__ fd,
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     if ((uint32_t)d <= D) {
-      const uint64_t a = wave_sum(A[d]), l = wave_sum(BL[d]), h = wave_sum(BH[d]);
+      const uint64_t a = wave_sum(A[d]);
+      const uint64_t l = wave_sum(B[d] & 0xffffffffull), h = wave_sum(B[d] >> 32);
       if ((t & 63u) == 0) {
         if (a) atomicAdd(reinterpret_cast<unsigned long long *>(&fd->A[d]), a);
         if (l) atomicAdd(reinterpret_cast<unsigned long long *>(&fd->Blo[d]), l);
@@ -794,6 +948,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   h.n_test = n_test;
   h.n_valid = in.n_valid;
   h.C = C;
+  h.Cp = C | 1u; // odd LDS stride for the staged targets
   h.P = P;
   h.PW = (P + 3) / 4;
   h.W = h.PW + C;
@@ -801,6 +956,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   h.min_leaf = (uint32_t)in.min_leaf;
   h.min_split = std::max<uint32_t>(2u, 2u * (uint32_t)in.min_leaf);
   h.divW = make_fastdiv(h.W);
+  h.divC = make_fastdiv(C);
   uint32_t sumR = 0;
   for (uint32_t j = 0; j < P; ++j) {
     h.radix[j] = (uint32_t)in.radix[j];
@@ -812,6 +968,9 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   h.entries = sumR * (C + 1);
   h.items = P * (C + 1);
   h.key_k = n_train;
+  // the level histogram lives in LDS (int64): sum_j R_j <= 137 for any space
+  // with fewer than 2^32 raw configurations, so this always fits
+  if ((size_t)h.entries * 8 > 160 * 1024) return hipErrorInvalidValue;
 
   // open nodes of one level: at most 2^(D-1), and each holds min_split rows
   const uint64_t n_nodes = ((uint64_t)2 << D) - 1;
@@ -819,6 +978,8 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   const uint64_t level_cap = D ? ((uint64_t)1 << (D - 1)) : 1;
   const uint64_t kcap = std::max<uint64_t>(1, std::min<uint64_t>(level_cap, n_train / h.min_split));
   const uint64_t hist_entries = D ? kcap * h.entries : 0;
+  const uint64_t n_tiles = ((uint64_t)n + kTile - 1) / kTile;
+  const uint64_t max_chunks = (uint64_t)n_train / kTile + kcap + 1;
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -837,11 +998,15 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   const size_t o_nmean = take(n_nodes * C * 4);
   const size_t o_nstate = take(n_nodes);
   const size_t o_nodes = take(n_int * 2);
-  size_t o_open[2], o_seg[2], o_cur[2], o_slot[2];
+  const size_t o_tcnt = take(n_tiles * 8);
+  const size_t o_toff = take(n_tiles * 8);
+  const size_t o_ccnt = take(max_chunks * 8);
+  const size_t o_cpre = take(max_chunks * 8);
+  size_t o_open[2], o_seg[2], o_chs[2], o_slot[2];
   for (int s = 0; s < 2; ++s) {
     o_open[s] = take(kcap * 4);
     o_seg[s] = take((kcap + 1) * 4);
-    o_cur[s] = take(kcap * 4);
+    o_chs[s] = take((kcap + 1) * 4);
     o_slot[s] = take(level_cap * 4);
   }
   char *base = nullptr;
@@ -867,39 +1032,37 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   uint32_t *test_rows = reinterpret_cast<uint32_t *>(base + o_test);
   uint32_t *ncount = reinterpret_cast<uint32_t *>(base + o_ncount);
   uint8_t *nstate = reinterpret_cast<uint8_t *>(base + o_nstate);
-  uint32_t *open_node[2], *seg_start[2], *cursor[2], *slot_of[2];
+  uint64_t *tile_cnt = reinterpret_cast<uint64_t *>(base + o_tcnt);
+  uint64_t *tile_off = reinterpret_cast<uint64_t *>(base + o_toff);
+  uint64_t *chunk_cnt = reinterpret_cast<uint64_t *>(base + o_ccnt);
+  uint64_t *chunk_pre = reinterpret_cast<uint64_t *>(base + o_cpre);
+  uint32_t *open_node[2], *seg_start[2], *chunk_start[2], *slot_of[2];
   for (int s = 0; s < 2; ++s) {
     open_node[s] = reinterpret_cast<uint32_t *>(base + o_open[s]);
     seg_start[s] = reinterpret_cast<uint32_t *>(base + o_seg[s]);
-    cursor[s] = reinterpret_cast<uint32_t *>(base + o_cur[s]);
+    chunk_start[s] = reinterpret_cast<uint32_t *>(base + o_chs[s]);
     slot_of[s] = reinterpret_cast<uint32_t *>(base + o_slot[s]);
   }
 
   // launch shapes
-  const uint32_t NT_h = std::min<uint32_t>(1024, (h.items + 63) / 64 * 64);
-  const uint32_t ipt = (h.items + NT_h - 1) / NT_h;
-  const size_t hist_lds_budget =
-      std::min<size_t>(160 * 1024, std::max<size_t>(65536, (size_t)h.entries * 4 + 16 * h.W * 4));
-  const uint32_t CH = (uint32_t)std::min<size_t>(
-      kTile, (hist_lds_budget - (size_t)h.entries * 4) / ((size_t)h.W * 4));
-  const size_t hist_lds = ((size_t)h.entries + (size_t)CH * h.W) * 4;
+  const size_t hist_lds = (size_t)h.entries * 8;
   const uint32_t cap_entries =
       std::max<uint32_t>(CGS_MAX_RADIX * (C + 1), std::min<uint32_t>(h.entries, 8192));
   const size_t split_lds = (size_t)cap_entries * 8;
   const size_t tile_lds = (size_t)kTile * h.W * 4;
-  const size_t scatter_lds = tile_lds + (size_t)kTile * C * 4;
-  const uint32_t g_rows = (uint32_t)std::max<uint64_t>(
-      1, std::min<uint64_t>(kFitGrid, ((uint64_t)n_train + kTile - 1) / kTile));
-  const uint32_t g_test = (uint32_t)std::max<uint64_t>(
-      1, std::min<uint64_t>(kFitGrid, ((uint64_t)n_test + kTile - 1) / kTile));
-  const uint32_t g_pts = (uint32_t)std::max<uint64_t>(
-      1, std::min<uint64_t>(kFitGrid, ((uint64_t)n + kTile - 1) / kTile));
+  const size_t test_lds = tile_lds + (size_t)kTile * (CGS_MAX_DEPTH + 1) * 4 + n_int * 2;
+  const size_t scatter_lds = tile_lds + (size_t)kTile * h.Cp * 4;
+  auto grid_for = [](uint64_t items) {
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kFitGrid, (items + kTile - 1) / kTile));
+  };
+  const uint32_t g_rows = grid_for(n_train), g_test = grid_for(n_test), g_pts = grid_for(n);
+  const uint32_t g_chunks = (uint32_t)std::min<uint64_t>(4 * kFitGrid, max_chunks);
 
-  auto kh = ipt == 1 ? fit_hist<1> : ipt == 2 ? fit_hist<2> : fit_hist<3>;
+  auto kh = P <= 8 ? fit_hist<8> : P <= 16 ? fit_hist<16> : fit_hist<32>;
   if (e == hipSuccess) e = allow_lds(kh, hist_lds);
   if (e == hipSuccess) e = allow_lds(fit_split, split_lds);
   if (e == hipSuccess) e = allow_lds(fit_partition, tile_lds);
-  if (e == hipSuccess) e = allow_lds(fit_test, tile_lds);
+  if (e == hipSuccess) e = allow_lds(fit_test, test_lds);
   if (e == hipSuccess) e = allow_lds(fit_scatter, scatter_lds);
   if (e != hipSuccess) return e;
 
@@ -918,32 +1081,38 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
       fit_key_hist<<<g_pts, kFitThreads, 0, stream>>>(fd, in.d_keys, p);
       fit_key_pick<<<1, 256, 0, stream>>>(fd, p);
     }
+    fit_tile_count<<<g_pts, kFitThreads, 0, stream>>>(fd, in.d_keys, tile_cnt);
+    fit_excl_scan<<<1, kScanThreads, 0, stream>>>(tile_cnt, tile_off, nullptr, (uint32_t)n_tiles);
     fit_scatter<<<g_pts, kFitThreads, scatter_lds, stream>>>(fd, in.d_space, in.d_idx,
                                                             in.d_points, in.d_targets,
-                                                            in.d_keys, rows[0], test_rows);
+                                                            in.d_keys, tile_off, rows[0],
+                                                            test_rows);
     fit_root_sums<<<g_rows, kFitThreads, 0, stream>>>(fd, rows[0], nsum);
     fit_root<<<1, 64, 0, stream>>>(fd, ncount, nsum, w->nmean, nstate);
     if (D > 0)
-      fit_layout<<<1, kLayoutThreads, 0, stream>>>(fd, 0, nstate, ncount, open_node[0],
-                                                  seg_start[0], cursor[0], slot_of[0],
-                                                  (uint32_t)kcap);
+      fit_layout<<<1, kScanThreads, 0, stream>>>(fd, 0, nstate, ncount, open_node[0],
+                                                seg_start[0], chunk_start[0], slot_of[0],
+                                                (uint32_t)kcap);
     for (uint32_t L = 0; L < D; ++L) {
-      const int s = L & 1;
-      kh<<<g_rows, NT_h, hist_lds, stream>>>(fd, (int)L, rows[s], seg_start[s], ghist, CH);
+      const int s = L & 1, s1 = s ^ 1;
+      kh<<<g_rows, kFitThreads, hist_lds, stream>>>(fd, (int)L, rows[s], seg_start[s], ghist);
       fit_split<<<1u << L, kFitThreads, split_lds, stream>>>(fd, (int)L, ghist, slot_of[s],
                                                              cap_entries, ncount, nsum,
                                                              w->nmean, nstate, w->nodes);
       if (L + 1 < D) {
-        fit_layout<<<1, kLayoutThreads, 0, stream>>>(fd, (int)L + 1, nstate, ncount,
-                                                    open_node[s ^ 1], seg_start[s ^ 1],
-                                                    cursor[s ^ 1], slot_of[s ^ 1],
-                                                    (uint32_t)kcap);
-        fit_partition<<<g_rows, kFitThreads, tile_lds, stream>>>(
-            fd, (int)L, rows[s], rows[s ^ 1], seg_start[s], open_node[s], cursor[s ^ 1],
-            slot_of[s ^ 1], nstate, w->nodes);
+        fit_layout<<<1, kScanThreads, 0, stream>>>(fd, (int)L + 1, nstate, ncount,
+                                                  open_node[s1], seg_start[s1], chunk_start[s1],
+                                                  slot_of[s1], (uint32_t)kcap);
+        fit_pcount<<<g_chunks, kFitThreads, 0, stream>>>(fd, (int)L, rows[s], seg_start[s],
+                                                         chunk_start[s], open_node[s], nstate,
+                                                         w->nodes, chunk_cnt);
+        fit_excl_scan<<<1, kScanThreads, 0, stream>>>(chunk_cnt, chunk_pre, &fd->lvl_NCH[s], 0);
+        fit_partition<<<g_chunks, kFitThreads, tile_lds, stream>>>(
+            fd, (int)L, rows[s], rows[s1], seg_start[s], chunk_start[s], open_node[s],
+            chunk_pre, seg_start[s1], slot_of[s1], nstate, w->nodes);
       }
     }
-    fit_test<<<g_test, kFitThreads, tile_lds, stream>>>(fd, test_rows, w->nodes, w->nmean);
+    fit_test<<<g_test, kFitThreads, test_lds, stream>>>(fd, test_rows, w->nodes, w->nmean);
     fit_select<<<1, 64, 0, stream>>>(fd);
     e = hipGetLastError();
   }
@@ -958,8 +1127,8 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   if (e != hipSuccess) return e;
   out.err = r.err;
   out.depth = r.depth_sel;
-  out.n_train = r.cur_train;
-  out.n_test = r.cur_test;
+  out.n_train = n_train;
+  out.n_test = n_test;
   out.n_split = r.n_split;
   for (uint32_t c = 0; c < C; ++c) out.scale[c] = r.s[c];
   for (uint32_t d = 0; d <= D; ++d) {

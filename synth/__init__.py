@@ -335,17 +335,18 @@ def measured_counters(g: np.random.Generator, digits: np.ndarray, radix: Sequenc
     next to utilisation percentages."""
     digits = np.asarray(digits)
     n, P = digits.shape
-    x = digits.astype(np.float64) / np.maximum(np.asarray(radix, dtype=np.float64) - 1.0, 1.0)
-    Y = np.empty((n, n_counters), dtype=np.float32)
+    x = (digits / np.maximum(np.asarray(radix, dtype=np.float64) - 1.0, 1.0)).astype(np.float32)
+    xt = np.ascontiguousarray(x.T)
+    Yt = np.empty((n_counters, n), dtype=np.float32)
     for c in range(n_counters):
         js = g.integers(0, P, 4)
-        th = g.random(4)
-        w = g.random(4) + 0.2
+        th = g.random(4).astype(np.float32)
+        w = (g.random(4) + 0.2).astype(np.float32)
         a, b = g.integers(0, P, 2)
-        scale = 10.0 ** g.uniform(-2.0, 6.0)
-        v = 0.1 + 0.5 * x[:, a] * x[:, b]
+        scale = np.float32(10.0 ** g.uniform(-2.0, 6.0))
+        v = np.float32(0.5) * xt[a] * xt[b] + np.float32(0.1)
         for k in range(4):
-            v = v + w[k] * (x[:, js[k]] > th[k])
-        v = v * (1.0 + noise * g.standard_normal(n))
-        Y[:, c] = (scale * v).astype(np.float32)
-    return Y
+            v += np.where(xt[js[k]] > th[k], w[k], np.float32(0.0))
+        v *= np.float32(1.0) + np.float32(noise) * g.standard_normal(n, dtype=np.float32)
+        np.multiply(v, scale, out=Yt[c])
+    return np.ascontiguousarray(Yt.T)
