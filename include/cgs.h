@@ -243,6 +243,53 @@ cgs_status cgs_model_fit_tree(cgs_space space, uint64_t n, int n_counters,
                               const uint32_t *points_host, const float *targets_host,
                               const uint64_t *keys_host, int max_depth, int min_leaf,
                               cgs_model *out, cgs_tree_fit_report *report);
+/* Least-squares polynomial counter models (Sect. 3.4.1).  Parameters with
+ * two values are binary: their digits select one of 2^B subspaces (bit i =
+ * digit of the i-th binary parameter).  Parameters with three or more values
+ * are non-binary, with feature x_j = (2 v - v_max - v_min) / (v_max - v_min).
+ * In every subspace each counter is a polynomial over the basis: the product
+ * of x_j over every set of non-binary parameters of size <= order (sets by
+ * size, then lexicographically; the empty set is the constant term), then x_j^2
+ * for every non-binary j.  Its coefficients solve
+ * (F^T F + lam I) beta = F^T Y over the subspace's training points, float64,
+ * lam = 1e-9 trace(F^T F) / T (keeps rank-deficient designs defined); a
+ * subspace without training points has beta = 0.  Predictions of every valid
+ * configuration are evaluated in float32 and kept like a forest's. */
+#define CGS_POLY_MAX_TERMS 176
+#define CGS_POLY_MAX_ORDER 4
+#define CGS_POLY_MAX_BINARY 16
+
+/* The design the paper measures: valid configurations whose every non-binary
+ * digit is 0, R_j - 1 or the digit whose value is nearest to the middle of the
+ * value range (the lower one on a tie), as ascending valid indices.  *count is
+ * always set; CGS_ERANGE (with the first `capacity` written) when it exceeds
+ * capacity. */
+cgs_status cgs_poly_design(cgs_space space, uint64_t capacity, uint32_t *valid_idx_host,
+                           uint64_t *count);
+
+typedef struct {
+  int32_t n_subspaces, n_terms, order, n_counters;
+  uint64_t n_points;
+  float fit_ms;        /* device time of features, Gram matrices and solves */
+  float eval_ms;       /* device time of the evaluation of every valid configuration */
+  int32_t pivot_clamped; /* 1 when a Cholesky pivot was not positive (then clamped) */
+  int32_t reserved;
+} cgs_poly_fit_report;
+
+/* Fit the polynomials on measured pairs: points_host[n] valid indices
+ * (1 <= n < 2^31, repeats allowed), targets_host[n][n_counters] finite;
+ * order 0..CGS_POLY_MAX_ORDER.  CGS_ERANGE when the basis exceeds
+ * CGS_POLY_MAX_TERMS terms or the space has more than CGS_POLY_MAX_BINARY binary
+ * parameters; CGS_EINVAL for an index outside the valid list or a non-finite
+ * target.  Synchronises; `report` may be NULL. */
+cgs_status cgs_model_fit_poly(cgs_space space, uint64_t n, int n_counters,
+                              const uint32_t *points_host, const float *targets_host, int order,
+                              cgs_model *out, cgs_poly_fit_report *report);
+/* Polynomial models only: subspaces and terms, then the float64 coefficients
+ * beta_host[n_subspaces][n_terms][n_counters]. */
+cgs_status cgs_poly_shape(cgs_model model, int *n_subspaces, int *n_terms);
+cgs_status cgs_poly_copy_coefficients(cgs_model model, double *beta_host);
+
 /* Forest models only: number of trees and depth, then the trees in the
  * layout of cgs_model_load_forest (feat, thr [n_trees][2^depth - 1],
  * leaves [n_trees][2^depth][n_counters]). */

@@ -37,6 +37,7 @@ SOURCES = {
     "sweep.hip": ["-ffp-contract=off"],
     "mlp.hip": ["-ffp-contract=fast"],
     "treefit.hip": ["-ffp-contract=off"],
+    "poly.hip": ["-ffp-contract=fast"],
 }
 
 

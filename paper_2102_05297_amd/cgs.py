@@ -41,7 +41,8 @@ EXPORTS = (
     "cgs_batch_set_schedule", "cgs_batch_destroy", "cgs_model_rmse",
     "cgs_model_gather_predictions", "cgs_search_step_neighbourhood",
     "cgs_session_copy_neighbourhood", "cgs_model_fit_tree", "cgs_model_forest_shape",
-    "cgs_model_copy_forest",
+    "cgs_model_copy_forest", "cgs_poly_design", "cgs_model_fit_poly", "cgs_poly_shape",
+    "cgs_poly_copy_coefficients",
 )
 
 
@@ -96,6 +97,12 @@ class cgs_tree_fit_report(C.Structure):
                 ("sq_err", (C.c_uint64 * 2) * 15)]
 
 
+class cgs_poly_fit_report(C.Structure):
+    _fields_ = [("n_subspaces", C.c_int32), ("n_terms", C.c_int32), ("order", C.c_int32),
+                ("n_counters", C.c_int32), ("n_points", C.c_uint64), ("fit_ms", C.c_float),
+                ("eval_ms", C.c_float), ("pivot_clamped", C.c_int32), ("reserved", C.c_int32)]
+
+
 _p = C.c_void_p
 _u64 = C.c_uint64
 _i32 = C.c_int32
@@ -134,6 +141,11 @@ _sig("cgs_model_fit_tree", [_p, _u64, C.c_int, _p, _p, _p, C.c_int, C.c_int, _pt
                             _ptr(cgs_tree_fit_report)])
 _sig("cgs_model_forest_shape", [_p, _ptr(C.c_int), _ptr(C.c_int)])
 _sig("cgs_model_copy_forest", [_p, _p, _p, _p])
+_sig("cgs_poly_design", [_p, _u64, _p, _ptr(_u64)])
+_sig("cgs_model_fit_poly", [_p, _u64, C.c_int, _p, _p, C.c_int, _ptr(_p),
+                            _ptr(cgs_poly_fit_report)])
+_sig("cgs_poly_shape", [_p, _ptr(C.c_int), _ptr(C.c_int)])
+_sig("cgs_poly_copy_coefficients", [_p, _p])
 _sig("cgs_session_create", [_p, _ptr(cgs_params), _ptr(_p)])
 _sig("cgs_search_step", [_p, _p, _u64, _p, _p, _ptr(cgs_expert_params)])
 _sig("cgs_search_step_neighbourhood", [_p, _p, _u64, C.c_int, _p, _p, _ptr(cgs_expert_params)])
@@ -387,6 +399,40 @@ class ForestModel(_Model):
         out = np.zeros((self.n_trees, count), dtype=np.uint16)
         _check(_lib.cgs_model_copy_leaf_ids(self.h, first, count, _ptrof(out)),
                "cgs_model_copy_leaf_ids")
+        return out
+
+
+class PolyModel(_Model):
+    """Least-squares polynomial counter models per binary subspace
+    (cgs_model_fit_poly)."""
+
+    def __init__(self, space: Space, points, targets, order: int):
+        pts = _arr(points, np.uint32)
+        y = _arr(targets, np.float32)
+        if y.ndim != 2 or len(y) != len(pts):
+            raise ValueError("targets must be [n][C] with one row per point")
+        rep = cgs_poly_fit_report()
+        h = C.c_void_p()
+        _check(_lib.cgs_model_fit_poly(space.h, len(pts), y.shape[1], _ptrof(pts), _ptrof(y),
+                                       int(order), C.byref(h), C.byref(rep)), "cgs_model_fit_poly")
+        self.h, self.space = h, space
+        self.n_counters, self.order = int(y.shape[1]), int(order)
+        self.report = {k: getattr(rep, k) for k, _ in cgs_poly_fit_report._fields_}
+
+    @staticmethod
+    def design(space: Space) -> np.ndarray:
+        """Valid indices of the design configurations (cgs_poly_design)."""
+        n = C.c_uint64()
+        out = np.zeros(max(1, space.n_valid), dtype=np.uint32)
+        _check(_lib.cgs_poly_design(space.h, len(out), _ptrof(out), C.byref(n)), "cgs_poly_design")
+        return out[: n.value].copy()
+
+    def coefficients(self) -> np.ndarray:
+        """float64 [subspaces][terms][counters]."""
+        S, T = C.c_int(), C.c_int()
+        _check(_lib.cgs_poly_shape(self.h, C.byref(S), C.byref(T)), "cgs_poly_shape")
+        out = np.zeros((S.value, T.value, self.n_counters), dtype=np.float64)
+        _check(_lib.cgs_poly_copy_coefficients(self.h, _ptrof(out)), "cgs_poly_copy_coefficients")
         return out
 
 

@@ -79,7 +79,7 @@ struct cgs_space_s {
 
 struct cgs_model_s {
   cgs_space space = nullptr;
-  int kind = 0; // 0 = forest, 1 = perceptron
+  int kind = 0; // 0 = forest, 1 = perceptron, 2 = least-squares polynomials
   int n_counters = 0;
   float *d_P = nullptr; // predictions [C][stride] of every valid configuration
   uint64_t stride = 0;
@@ -103,6 +103,11 @@ struct cgs_model_s {
          *d_dz2b = nullptr;
   float *d_z1 = nullptr, *d_z2 = nullptr, *d_y = nullptr, *d_dyf = nullptr, *d_dz1f = nullptr,
         *d_dz2f = nullptr;
+  // least-squares polynomials: descriptor and coefficients [S][T][C]
+  PolyDev poly{};
+  PolyDev *d_poly = nullptr;
+  double *d_beta64 = nullptr;
+  float *d_beta32 = nullptr;
 };
 
 constexpr uint32_t kTimeEvents = 512; // event markers of 128 timed steps
@@ -435,6 +440,9 @@ void destroy_model(cgs_model m) {
   dfree(m->d_w1p);
   dfree(m->d_w2p);
   dfree(m->d_w3p);
+  dfree(m->d_poly);
+  dfree(m->d_beta64);
+  dfree(m->d_beta32);
   free_mlp_scratch(m);
   destroy_space(m->space);
   delete m;
@@ -472,6 +480,9 @@ cgs_status evaluate_model(cgs_model m) {
     e = launch_forest_eval(sp->d_desc, sp->d_idx, (uint32_t)sp->n_valid, m->d_nodes, m->d_leaves,
                            m->n_trees, m->depth, m->n_counters, m->d_P, m->stride, nullptr, 0, 0,
                            sp->stream);
+  } else if (m->kind == 2) {
+    e = launch_poly_eval(m->d_poly, m->poly.T, m->poly.C, m->poly.S, sp->d_desc, sp->d_idx,
+                         (uint32_t)sp->n_valid, m->d_beta32, m->d_P, m->stride, sp->stream);
   } else {
     MlpFwdArgs a = mlp_args(m);
     a.n = (uint32_t)sp->n_valid;
@@ -668,6 +679,264 @@ extern "C" cgs_status cgs_model_fit_tree(cgs_space sp, uint64_t n, int n_counter
     }
   }
   *out = m;
+  return CGS_OK;
+}
+
+// ------------------------------------------------------- polynomial models
+namespace {
+
+// Digit of parameter j whose value is nearest to the middle of its range
+// (the lower one on a tie).
+int mid_digit(const cgs_space_s *sp, int j) {
+  const int r = sp->radix[j];
+  const double lo = sp->host_desc.table[j * CGS_MAX_RADIX],
+               hi = sp->host_desc.table[j * CGS_MAX_RADIX + r - 1];
+  const double mid = (lo + hi) / 2.0;
+  int best = 0;
+  for (int d = 1; d < r; ++d)
+    if (std::fabs(sp->host_desc.table[j * CGS_MAX_RADIX + d] - mid) <
+        std::fabs(sp->host_desc.table[j * CGS_MAX_RADIX + best] - mid))
+      best = d;
+  return best;
+}
+
+// Binary parameters (two values) pick the subspace; non-binary ones (three or
+// more) carry features; the basis is every set of non-binary parameters of
+// size <= order (by size, then lexicographically), then their squares.
+cgs_status poly_describe(const cgs_space_s *sp, int order, int n_counters, PolyDev &pd) {
+  std::memset(&pd, 0, sizeof(pd));
+  std::vector<int> nb;
+  for (int j = 0; j < sp->n_params; ++j) {
+    if (sp->radix[j] == 2) {
+      if (pd.B >= kPolyMaxBinary)
+        return fail(CGS_ERANGE, "more than %d binary parameters", kPolyMaxBinary);
+      pd.bin_params[pd.B++] = (uint32_t)j;
+    } else if (sp->radix[j] >= 3) {
+      nb.push_back(j);
+    }
+  }
+  pd.P = sp->n_params;
+  pd.k = (int)nb.size();
+  pd.S = 1 << pd.B;
+  pd.C = n_counters;
+  pd.order = order;
+  std::vector<uint32_t> terms;
+  const int k = pd.k, top = std::min(order, k);
+  for (int size = 0; size <= top && terms.size() <= (size_t)kPolyMaxTerms; ++size) {
+    std::vector<int> pick(size);
+    for (int i = 0; i < size; ++i) pick[i] = i;
+    while (terms.size() <= (size_t)kPolyMaxTerms) {
+      uint32_t d = (uint32_t)size;
+      for (int i = 0; i < size; ++i) d |= (uint32_t)nb[pick[i]] << (3 + 5 * i);
+      terms.push_back(d);
+      int i = size - 1;
+      while (i >= 0 && pick[i] == k - size + i) --i;
+      if (i < 0) break;
+      ++pick[i];
+      for (int q = i + 1; q < size; ++q) pick[q] = pick[q - 1] + 1;
+    }
+  }
+  for (int i = 0; i < k && terms.size() <= (size_t)kPolyMaxTerms; ++i)
+    terms.push_back(2u | ((uint32_t)nb[i] << 3) | ((uint32_t)nb[i] << 8));
+  if (terms.size() > (size_t)kPolyMaxTerms)
+    return fail(CGS_ERANGE, "order %d gives more than %d basis terms for %d non-binary parameters",
+                order, kPolyMaxTerms, k);
+  pd.T = (int)terms.size();
+  for (size_t i = 0; i < terms.size(); ++i) pd.terms[i] = terms[i];
+  for (int j : nb) {
+    const int r = sp->radix[j];
+    const double lo = sp->host_desc.table[j * CGS_MAX_RADIX],
+                 hi = sp->host_desc.table[j * CGS_MAX_RADIX + r - 1];
+    for (int d = 0; d < r; ++d) {
+      const double v = sp->host_desc.table[j * CGS_MAX_RADIX + d];
+      const double x = (2.0 * v - hi - lo) / (hi - lo);
+      pd.xv64[j * CGS_MAX_RADIX + d] = x;
+      pd.xv32[j * CGS_MAX_RADIX + d] = (float)x;
+    }
+  }
+  return CGS_OK;
+}
+
+} // namespace
+
+extern "C" cgs_status cgs_poly_design(cgs_space sp, uint64_t capacity, uint32_t *valid_idx,
+                                      uint64_t *count) {
+  if (!sp || !count || (capacity && !valid_idx)) return fail(CGS_EINVAL, "NULL argument");
+  *count = 0;
+  const uint32_t nv = (uint32_t)sp->n_valid;
+  if (nv == 0) return CGS_OK;
+  std::vector<uint32_t> allowed(CGS_MAX_PARAMS, 0);
+  for (int j = 0; j < sp->n_params; ++j) {
+    const int r = sp->radix[j];
+    if (r >= 3) allowed[j] = (1u << 0) | (1u << mid_digit(sp, j)) | (1u << (r - 1));
+    else allowed[j] = (1u << r) - 1u;
+  }
+  const uint32_t tiles = (nv + 255) / 256;
+  uint32_t *d_allowed = nullptr, *d_out = nullptr;
+  uint64_t *d_cnt = nullptr, *d_off = nullptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(sp->stream);
+    dfree(d_allowed);
+    dfree(d_out);
+    dfree(d_cnt);
+    dfree(d_off);
+  };
+  hipError_t e = dalloc(&d_allowed, CGS_MAX_PARAMS);
+  if (e == hipSuccess) e = dalloc(&d_out, nv);
+  if (e == hipSuccess) e = dalloc(&d_cnt, tiles);
+  if (e == hipSuccess) e = dalloc(&d_off, tiles);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_allowed, allowed.data(), CGS_MAX_PARAMS * 4, hipMemcpyHostToDevice,
+                       sp->stream);
+  if (e == hipSuccess)
+    e = launch_poly_design(sp->d_desc, sp->d_idx, nv, d_allowed, d_cnt, d_off, d_out, sp->stream);
+  uint64_t last[2] = {0, 0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&last[0], d_off + tiles - 1, 8, hipMemcpyDeviceToHost, sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&last[1], d_cnt + tiles - 1, 8, hipMemcpyDeviceToHost, sp->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
+  const uint64_t n = last[0] + last[1];
+  if (e == hipSuccess && capacity && n)
+    e = hipMemcpy(valid_idx, d_out, std::min<uint64_t>(n, capacity) * 4, hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) return fail(CGS_EDEVICE, "design: %s", hipGetErrorString(e));
+  *count = n;
+  if (capacity < n)
+    return fail(CGS_ERANGE, "the design has %llu configurations, capacity %llu",
+                (unsigned long long)n, (unsigned long long)capacity);
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_model_fit_poly(cgs_space sp, uint64_t n, int n_counters,
+                                         const uint32_t *points, const float *targets, int order,
+                                         cgs_model *out, cgs_poly_fit_report *report) {
+  if (!out) return fail(CGS_EINVAL, "NULL out");
+  *out = nullptr;
+  if (!sp || !points || !targets) return fail(CGS_EINVAL, "NULL argument");
+  if (n_counters < 1 || n_counters > CGS_MAX_COUNTERS)
+    return fail(CGS_ERANGE, "n_counters %d outside 1..%d", n_counters, CGS_MAX_COUNTERS);
+  if (order < 0 || order > kPolyMaxOrder)
+    return fail(CGS_ERANGE, "order %d outside 0..%d", order, kPolyMaxOrder);
+  if (n < 1 || n >= ((uint64_t)1 << 31)) return fail(CGS_ERANGE, "n = %llu", (unsigned long long)n);
+  if (sp->n_valid == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
+  PolyDev pd;
+  cgs_status st = poly_describe(sp, order, n_counters, pd);
+  if (st != CGS_OK) return st;
+  const int T = pd.T, C = n_counters, S = pd.S, Ta = T + C;
+  if ((uint64_t)n * Ta * 8 > ((uint64_t)16 << 30))
+    return fail(CGS_ERANGE, "n * (terms + counters) too large for the feature matrix");
+  if ((uint64_t)S * Ta * Ta * 8 > ((uint64_t)16 << 30))
+    return fail(CGS_ERANGE, "%d subspaces of %d columns: Gram matrices too large", S, Ta);
+  const int nbk = (Ta + 31) / 32;
+  std::vector<uint32_t> pairs;
+  for (int a = 0; a < nbk; ++a)
+    for (int b = a; b < nbk; ++b) pairs.push_back((uint32_t)a | ((uint32_t)b << 16));
+
+  cgs_model m = new (std::nothrow) cgs_model_s();
+  if (!m) return fail(CGS_ENOMEM, "host allocation");
+  m->space = sp;
+  ++sp->refs;
+  m->kind = 2;
+  m->n_counters = C;
+  m->poly = pd;
+  m->stride = (sp->n_valid + 63) & ~(uint64_t)63;
+  uint32_t *d_pts = nullptr, *d_sub = nullptr, *d_pairs = nullptr, *d_err = nullptr;
+  float *d_y = nullptr;
+  double *d_F = nullptr, *d_G = nullptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(sp->stream);
+    dfree(d_pts);
+    dfree(d_sub);
+    dfree(d_pairs);
+    dfree(d_err);
+    dfree(d_y);
+    dfree(d_F);
+    dfree(d_G);
+  };
+  hipError_t e = dalloc(&m->d_poly, 1);
+  if (e == hipSuccess) e = dalloc(&m->d_beta64, (size_t)S * T * C);
+  if (e == hipSuccess) e = dalloc(&m->d_beta32, (size_t)S * T * C);
+  if (e == hipSuccess) e = dalloc(&m->d_P, (size_t)C * m->stride);
+  if (e == hipSuccess) e = dalloc(&d_pts, n);
+  if (e == hipSuccess) e = dalloc(&d_y, n * (size_t)C);
+  if (e == hipSuccess) e = dalloc(&d_sub, n);
+  if (e == hipSuccess) e = dalloc(&d_F, n * (size_t)Ta);
+  if (e == hipSuccess) e = dalloc(&d_G, (size_t)S * Ta * Ta);
+  if (e == hipSuccess) e = dalloc(&d_pairs, pairs.size());
+  if (e == hipSuccess) e = dalloc(&d_err, 1);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->d_poly, &pd, sizeof(pd), hipMemcpyHostToDevice, sp->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_pts, points, n * 4, hipMemcpyHostToDevice, sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_y, targets, n * (size_t)C * 4, hipMemcpyHostToDevice, sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice,
+                       sp->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d_err, 0, 4, sp->stream);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(m->d_P, 0, (size_t)C * m->stride * sizeof(float), sp->stream);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], sp->stream);
+  if (e == hipSuccess)
+    e = launch_poly_fit(m->d_poly, T, C, S, sp->d_desc, sp->d_idx, (uint32_t)sp->n_valid, d_pts,
+                        d_y, (uint32_t)n, d_F, d_sub, d_pairs, (uint32_t)pairs.size(), d_G,
+                        m->d_beta64, m->d_beta32, d_err, sp->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], sp->stream);
+  uint32_t err = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, sp->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
+  float fit_ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&fit_ms, ev[0], ev[1]);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  cleanup();
+  if (e != hipSuccess) {
+    destroy_model(m);
+    return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "polynomial fit: %s",
+                hipGetErrorString(e));
+  }
+  if (err & 3u) {
+    destroy_model(m);
+    return fail(CGS_EINVAL, "%s",
+                (err & 1u) ? "a point is outside the valid list" : "a target is not finite");
+  }
+  st = evaluate_model(m);
+  if (st != CGS_OK) {
+    destroy_model(m);
+    return st;
+  }
+  if (report) {
+    std::memset(report, 0, sizeof(*report));
+    report->n_subspaces = S;
+    report->n_terms = T;
+    report->order = order;
+    report->n_counters = C;
+    report->n_points = n;
+    report->fit_ms = fit_ms;
+    report->eval_ms = m->eval_ms;
+    report->pivot_clamped = (err & 4u) ? 1 : 0;
+  }
+  *out = m;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_poly_shape(cgs_model m, int *n_subspaces, int *n_terms) {
+  if (!m) return fail(CGS_EINVAL, "NULL model");
+  if (m->kind != 2) return fail(CGS_EINVAL, "not a polynomial model");
+  if (n_subspaces) *n_subspaces = m->poly.S;
+  if (n_terms) *n_terms = m->poly.T;
+  return CGS_OK;
+}
+
+extern "C" cgs_status cgs_poly_copy_coefficients(cgs_model m, double *beta) {
+  if (!m || !beta) return fail(CGS_EINVAL, "NULL argument");
+  if (m->kind != 2) return fail(CGS_EINVAL, "not a polynomial model");
+  const size_t n = (size_t)m->poly.S * m->poly.T * m->poly.C;
+  HIP_TRY(hipMemcpyAsync(beta, m->d_beta64, n * 8, hipMemcpyDeviceToHost, m->space->stream));
+  HIP_TRY(hipStreamSynchronize(m->space->stream));
   return CGS_OK;
 }
 

@@ -277,4 +277,31 @@ hipError_t tree_fit_emit(const TreeFitWork *work, int depth, uint16_t *d_nodes, 
                          hipStream_t stream);
 void tree_fit_release(TreeFitWork *work);
 
+// ---- least-squares polynomial models per binary subspace (Sect. 3.4.1)
+constexpr int kPolyMaxTerms = CGS_POLY_MAX_TERMS;   // the solve keeps the packed factor in LDS
+constexpr int kPolyMaxOrder = CGS_POLY_MAX_ORDER;   // variables per basis term
+constexpr int kPolyMaxBinary = CGS_POLY_MAX_BINARY; // at most 65,536 subspaces
+// Term descriptor: bits 0..2 the number of factors, then 5 bits per factor
+// (a parameter index); squares repeat their parameter.
+struct PolyDev {
+  int32_t P, k, B, T, C, S, order, pad;
+  uint32_t bin_params[CGS_MAX_PARAMS]; // parameter of subspace bit i
+  uint32_t terms[kPolyMaxTerms];
+  double xv64[CGS_MAX_PARAMS * CGS_MAX_RADIX]; // feature of (parameter, digit)
+  float xv32[CGS_MAX_PARAMS * CGS_MAX_RADIX];
+};
+size_t poly_solve_lds(int T);
+hipError_t launch_poly_design(const SpaceDev *d_space, const uint32_t *d_idx, uint32_t nv,
+                              const uint32_t *d_allowed, uint64_t *d_tile_cnt,
+                              uint64_t *d_tile_off, uint32_t *d_out, hipStream_t stream);
+hipError_t launch_poly_fit(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,
+                           const uint32_t *d_idx, uint32_t nv, const uint32_t *d_pts,
+                           const float *d_Y, uint32_t n, double *d_F, uint32_t *d_sub,
+                           const uint32_t *d_pairs, uint32_t n_pairs, double *d_G,
+                           double *d_beta64, float *d_beta32, uint32_t *d_err,
+                           hipStream_t stream);
+hipError_t launch_poly_eval(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,
+                            const uint32_t *d_idx, uint32_t nv, const float *d_beta32, float *d_P,
+                            uint64_t stride, hipStream_t stream);
+
 } // namespace cgs

@@ -1,0 +1,384 @@
+// Least-squares polynomial counter models per binary subspace (Sect. 3.4.1).
+//
+// The binary parameters' digits select a subspace; within it every counter is
+// a polynomial in the non-binary parameters: products of their features over
+// all parameter sets up to the chosen order (main effects and interactions),
+// plus squares.  Feature x_j = (2 v - v_max - v_min) / (v_max - v_min).
+//
+// Fit: F[i][t] (float64) for every measured point and basis term, with the
+// point's counters appended as columns T..T+C-1; per subspace the Gram matrix
+// of those columns gives F^T F and F^T Y; a ridge 1e-9 trace / T is added and
+// one workgroup per subspace factors it (Cholesky, packed lower triangle in
+// LDS) and solves for every counter.  Evaluation: one thread per valid
+// configuration, float32, coefficients of a group of subspaces in LDS.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "device_common.h"
+
+namespace cgs {
+
+namespace {
+
+constexpr int kPolyThreads = 256;
+constexpr int kGB = 32;        // Gram block edge
+constexpr int kGramChunk = 64; // points staged per round of the Gram kernel
+constexpr double kRidge = 1e-9;
+
+__device__ __forceinline__ uint32_t term_count(uint32_t d) { return d & 7u; }
+__device__ __forceinline__ uint32_t term_var(uint32_t d, uint32_t i) {
+  return (d >> (3 + 5 * i)) & 31u;
+}
+
+__device__ __forceinline__ uint32_t subspace_of(const PolyDev *pd, uint64_t lo, uint64_t hi) {
+  uint32_t s = 0;
+  for (int i = 0; i < pd->B; ++i) s |= digit_of(lo, hi, pd->bin_params[i]) << i;
+  return s;
+}
+
+// Exclusive prefix sums of in[0..n) in one workgroup.
+__global__ __launch_bounds__(1024) void poly_excl_scan(const uint64_t *__restrict__ in,
+                                                       uint64_t *__restrict__ out, uint32_t n) {
+  __shared__ uint64_t scratch[16];
+  const uint32_t t = threadIdx.x, per = (n + 1023) / 1024;
+  const uint32_t a = min(n, t * per), b = min(n, a + per);
+  uint64_t mine = 0;
+  for (uint32_t i = a; i < b; ++i) mine += in[i];
+  uint64_t tot;
+  uint64_t run = block_excl_scan<1024>(mine, scratch, tot);
+  for (uint32_t i = a; i < b; ++i) {
+    const uint64_t v = in[i];
+    out[i] = run;
+    run += v;
+  }
+}
+
+// ---------------------------------------------------------------- design
+__device__ __forceinline__ bool in_design(const SpaceDev *sp, const uint32_t *allowed,
+                                          uint32_t raw) {
+  uint64_t lo, hi;
+  decode_packed(raw, sp, lo, hi);
+  bool ok = true;
+  for (int j = 0; j < sp->n_params; ++j) ok = ok && ((allowed[j] >> digit_of(lo, hi, j)) & 1u);
+  return ok;
+}
+
+__global__ __launch_bounds__(kPolyThreads) void poly_design_count(
+    const SpaceDev *__restrict__ sp, const uint32_t *__restrict__ idx, uint32_t nv,
+    const uint32_t *__restrict__ allowed, uint64_t *__restrict__ cnt) {
+  __shared__ uint64_t scratch[kPolyThreads / 64];
+  for (uint32_t tile = blockIdx.x; (uint64_t)tile * kPolyThreads < nv; tile += gridDim.x) {
+    const uint32_t l = tile * kPolyThreads + threadIdx.x;
+    const uint64_t f = (l < nv && in_design(sp, allowed, idx[l])) ? 1ull : 0ull;
+    const uint64_t s = block_sum<kPolyThreads>(f, scratch);
+    if (threadIdx.x == 0) cnt[tile] = s;
+  }
+}
+
+__global__ __launch_bounds__(kPolyThreads) void poly_design_write(
+    const SpaceDev *__restrict__ sp, const uint32_t *__restrict__ idx, uint32_t nv,
+    const uint32_t *__restrict__ allowed, const uint64_t *__restrict__ off,
+    uint32_t *__restrict__ out) {
+  __shared__ uint64_t scratch[kPolyThreads / 64];
+  for (uint32_t tile = blockIdx.x; (uint64_t)tile * kPolyThreads < nv; tile += gridDim.x) {
+    const uint32_t l = tile * kPolyThreads + threadIdx.x;
+    const bool f = l < nv && in_design(sp, allowed, idx[l]);
+    uint64_t tot;
+    const uint64_t r = block_excl_scan<kPolyThreads>(f ? 1ull : 0ull, scratch, tot);
+    if (f) out[off[tile] + r] = l;
+  }
+}
+
+// ---------------------------------------------------------------- fit
+// F[i][t]: basis term t of point i for t < T, its counter t - T for t >= T;
+// sub[i]: its subspace.  err bit 0: a point outside the valid list, bit 1: a
+// non-finite target.
+__global__ __launch_bounds__(kPolyThreads) void poly_features(
+    const PolyDev *__restrict__ pd, const SpaceDev *__restrict__ sp,
+    const uint32_t *__restrict__ idx, uint32_t nv, const uint32_t *__restrict__ pts,
+    const float *__restrict__ Y, uint32_t n, double *__restrict__ F, uint32_t *__restrict__ sub,
+    uint32_t *__restrict__ err) {
+  const uint32_t T = pd->T, C = pd->C, Ta = T + C;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (uint64_t)n * Ta;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t i = (uint32_t)(e / Ta), t = (uint32_t)(e - (uint64_t)i * Ta);
+    const uint32_t p = pts[i];
+    uint64_t lo = 0, hi = 0;
+    if (p < nv) decode_packed(idx[p], sp, lo, hi);
+    else if (t == 0) atomicOr(err, 1u);
+    double v;
+    if (t < T) {
+      const uint32_t d = pd->terms[t];
+      v = 1.0;
+      for (uint32_t q = 0; q < term_count(d); ++q) {
+        const uint32_t j = term_var(d, q);
+        v *= pd->xv64[j * CGS_MAX_RADIX + digit_of(lo, hi, j)];
+      }
+    } else {
+      const float y = Y[(uint64_t)i * C + (t - T)];
+      if (!isfinite(y)) atomicOr(err, 2u);
+      v = isfinite(y) ? (double)y : 0.0;
+    }
+    F[e] = v;
+    if (t == 0) sub[i] = subspace_of(pd, lo, hi);
+  }
+}
+
+// One kGB x kGB block (rows a0.., columns b0..) of every subspace's Gram
+// matrix of the columns of F: blockIdx.x = subspace, blockIdx.y = block pair
+// (a-block <= b-block).  The points are visited in input order, so the sums
+// are the same on every run.
+__global__ __launch_bounds__(kPolyThreads) void poly_gram(const PolyDev *__restrict__ pd,
+                                                          const double *__restrict__ F,
+                                                          const uint32_t *__restrict__ sub,
+                                                          uint32_t n,
+                                                          const uint32_t *__restrict__ pairs,
+                                                          double *__restrict__ G) {
+  __shared__ double fa[kGramChunk][kGB + 1], fb[kGramChunk][kGB + 1];
+  __shared__ uint32_t list[kGramChunk];
+  __shared__ uint64_t scratch[kPolyThreads / 64];
+  const uint32_t T = pd->T, Ta = T + pd->C, s = blockIdx.x;
+  const uint32_t pr = pairs[blockIdx.y];
+  const uint32_t a0 = (pr & 0xffffu) * kGB, b0 = (pr >> 16) * kGB;
+  const uint32_t t = threadIdx.x;
+  const uint32_t ra = (t / (kGB / 2)) * 2, cb = (t % (kGB / 2)) * 2; // 2 x 2 outputs
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (uint32_t base = 0; base < n; base += kGramChunk) {
+    // points of this subspace among the next kGramChunk, in order
+    const uint32_t i = base + t;
+    const bool f = t < kGramChunk && i < n && sub[i] == s;
+    uint64_t tot;
+    const uint64_t r = block_excl_scan<kPolyThreads>(f ? 1ull : 0ull, scratch, tot);
+    if (f) list[r] = i;
+    __syncthreads();
+    const uint32_t m = (uint32_t)tot;
+    for (uint32_t e = t; e < m * kGB; e += kPolyThreads) {
+      const uint32_t p = e / kGB, c = e % kGB;
+      const double *row = F + (uint64_t)list[p] * Ta;
+      fa[p][c] = a0 + c < Ta ? row[a0 + c] : 0.0;
+      fb[p][c] = b0 + c < Ta ? row[b0 + c] : 0.0;
+    }
+    __syncthreads();
+    for (uint32_t p = 0; p < m; ++p) {
+      const double x0 = fa[p][ra], x1 = fa[p][ra + 1], y0 = fb[p][cb], y1 = fb[p][cb + 1];
+      acc[0][0] += x0 * y0;
+      acc[0][1] += x0 * y1;
+      acc[1][0] += x1 * y0;
+      acc[1][1] += x1 * y1;
+    }
+    __syncthreads();
+  }
+  double *Gs = G + (uint64_t)s * Ta * Ta;
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      const uint32_t a = a0 + ra + u, b = b0 + cb + v;
+      if (a < Ta && b < Ta) {
+        Gs[(uint64_t)a * Ta + b] = acc[u][v];
+        Gs[(uint64_t)b * Ta + a] = acc[u][v];
+      }
+    }
+}
+
+__device__ __forceinline__ uint32_t pk(uint32_t i, uint32_t j) { return i * (i + 1) / 2 + j; }
+
+// One workgroup per subspace: (G + lam I) beta = R by Cholesky in LDS.
+__global__ __launch_bounds__(kPolyThreads) void poly_solve(const PolyDev *__restrict__ pd,
+                                                           const double *__restrict__ G,
+                                                           double *__restrict__ beta64,
+                                                           float *__restrict__ beta32,
+                                                           uint32_t *__restrict__ err) {
+  extern __shared__ double L[]; // packed lower triangle, then z[T][kRhs]
+  constexpr uint32_t kRhs = 16;
+  __shared__ double s_lam;
+  const uint32_t T = pd->T, C = pd->C, Ta = T + C, s = blockIdx.x, t = threadIdx.x;
+  const double *Gs = G + (uint64_t)s * Ta * Ta;
+  double *z = L + (uint64_t)T * (T + 1) / 2;
+  double *b64 = beta64 + (uint64_t)s * T * C;
+  float *b32 = beta32 + (uint64_t)s * T * C;
+  if (Gs[0] == 0.0) { // no point in this subspace (the constant column sums to n_s)
+    for (uint32_t e = t; e < T * C; e += kPolyThreads) {
+      b64[e] = 0.0;
+      b32[e] = 0.0f;
+    }
+    return;
+  }
+  for (uint32_t i = t; i < T; i += kPolyThreads)
+    for (uint32_t j = 0; j <= i; ++j) L[pk(i, j)] = Gs[(uint64_t)i * Ta + j];
+  if (t == 0) {
+    double tr = 0.0;
+    for (uint32_t i = 0; i < T; ++i) tr += Gs[(uint64_t)i * Ta + i];
+    s_lam = kRidge * tr / (double)T;
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < T; i += kPolyThreads) L[pk(i, i)] += s_lam;
+  // right-looking Cholesky, column by column
+  for (uint32_t j = 0; j < T; ++j) {
+    __syncthreads();
+    if (t == 0) {
+      double d = L[pk(j, j)];
+      if (!(d > 0.0)) {
+        atomicOr(err, 4u);
+        d = s_lam;
+      }
+      L[pk(j, j)] = sqrt(d);
+    }
+    __syncthreads();
+    const double djj = L[pk(j, j)];
+    for (uint32_t i = j + 1 + t; i < T; i += kPolyThreads) L[pk(i, j)] /= djj;
+    __syncthreads();
+    for (uint32_t i = j + 1 + t; i < T; i += kPolyThreads) {
+      const double lij = L[pk(i, j)];
+      for (uint32_t k = j + 1; k <= i; ++k) L[pk(i, k)] -= lij * L[pk(k, j)];
+    }
+  }
+  __syncthreads();
+  // L L^T beta = R, kRhs counters at a time: thread c solves column c
+  for (uint32_t c0 = 0; c0 < C; c0 += kRhs) {
+    const uint32_t c = c0 + t;
+    const bool mine = t < kRhs && c < C;
+    if (mine) {
+      for (uint32_t i = 0; i < T; ++i) {
+        double v = Gs[(uint64_t)i * Ta + T + c];
+        for (uint32_t k = 0; k < i; ++k) v -= L[pk(i, k)] * z[k * kRhs + t];
+        z[i * kRhs + t] = v / L[pk(i, i)];
+      }
+      for (uint32_t i = T; i-- > 0;) {
+        double v = z[i * kRhs + t];
+        for (uint32_t k = i + 1; k < T; ++k) v -= L[pk(k, i)] * z[k * kRhs + t];
+        z[i * kRhs + t] = v / L[pk(i, i)];
+      }
+      for (uint32_t i = 0; i < T; ++i) {
+        const double b = z[i * kRhs + t];
+        b64[(uint64_t)i * C + c] = b;
+        b32[(uint64_t)i * C + c] = (float)b;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- evaluate
+// P[c][l] for the valid configurations whose subspace lies in this
+// workgroup's group of SG subspaces (group blockIdx.x / per_group, part
+// blockIdx.x % per_group of the valid list): coefficients of the group,
+// feature table and term descriptors staged in LDS.
+template <int CB>
+__global__ __launch_bounds__(kPolyThreads) void poly_eval(const PolyDev *__restrict__ pd,
+                                                          const SpaceDev *__restrict__ sp,
+                                                          const uint32_t *__restrict__ idx,
+                                                          uint32_t nv,
+                                                          const float *__restrict__ beta32,
+                                                          uint32_t SG, uint32_t per_group,
+                                                          float *__restrict__ P, uint64_t stride) {
+  extern __shared__ float lds[]; // [SG][T][C] coefficients
+  __shared__ float xv[CGS_MAX_PARAMS * CGS_MAX_RADIX];
+  __shared__ uint32_t terms[kPolyMaxTerms];
+  const uint32_t T = pd->T, C = pd->C, S = pd->S, t = threadIdx.x;
+  const uint32_t group = blockIdx.x / per_group, part = blockIdx.x % per_group;
+  const uint32_t g0 = group * SG, g1 = min(S, g0 + SG);
+  for (uint32_t e = t; e < (g1 - g0) * T * C; e += kPolyThreads)
+    lds[e] = beta32[(uint64_t)g0 * T * C + e];
+  for (uint32_t e = t; e < CGS_MAX_PARAMS * CGS_MAX_RADIX; e += kPolyThreads) xv[e] = pd->xv32[e];
+  for (uint32_t e = t; e < T; e += kPolyThreads) terms[e] = pd->terms[e];
+  __syncthreads();
+  for (uint32_t l = part * kPolyThreads + t; l < nv; l += per_group * kPolyThreads) {
+    uint64_t lo, hi;
+    decode_packed(idx[l], sp, lo, hi);
+    const uint32_t s = subspace_of(pd, lo, hi);
+    if (s < g0 || s >= g1) continue;
+    const float *bs = lds + (uint64_t)(s - g0) * T * C;
+    float acc[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
+    for (uint32_t k = 0; k < T; ++k) {
+      const uint32_t d = terms[k];
+      float f = 1.0f;
+      for (uint32_t q = 0; q < term_count(d); ++q) {
+        const uint32_t j = term_var(d, q);
+        f *= xv[j * CGS_MAX_RADIX + digit_of(lo, hi, j)];
+      }
+      const float *bk = bs + k * C;
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+        if ((uint32_t)c < C) acc[c] += f * bk[c];
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+      if ((uint32_t)c < C) P[(uint64_t)c * stride + l] = acc[c];
+  }
+}
+
+template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+constexpr size_t kEvalLds = 96 * 1024;
+
+} // namespace
+
+size_t poly_solve_lds(int T) { return ((size_t)T * (T + 1) / 2 + (size_t)T * 16) * 8; }
+
+hipError_t launch_poly_design(const SpaceDev *d_space, const uint32_t *d_idx, uint32_t nv,
+                              const uint32_t *d_allowed, uint64_t *d_tile_cnt,
+                              uint64_t *d_tile_off, uint32_t *d_out, hipStream_t stream) {
+  const uint32_t tiles = (nv + kPolyThreads - 1) / kPolyThreads;
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(tiles, 4096));
+  poly_design_count<<<grid, kPolyThreads, 0, stream>>>(d_space, d_idx, nv, d_allowed, d_tile_cnt);
+  poly_excl_scan<<<1, 1024, 0, stream>>>(d_tile_cnt, d_tile_off, tiles);
+  poly_design_write<<<grid, kPolyThreads, 0, stream>>>(d_space, d_idx, nv, d_allowed, d_tile_off,
+                                                      d_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_poly_fit(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,
+                           const uint32_t *d_idx, uint32_t nv, const uint32_t *d_pts,
+                           const float *d_Y, uint32_t n, double *d_F, uint32_t *d_sub,
+                           const uint32_t *d_pairs, uint32_t n_pairs, double *d_G,
+                           double *d_beta64, float *d_beta32, uint32_t *d_err,
+                           hipStream_t stream) {
+  const uint64_t fe = (uint64_t)n * (T + C);
+  const uint32_t gf = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8192, (fe + 255) / 256));
+  poly_features<<<gf, kPolyThreads, 0, stream>>>(d_pd, d_space, d_idx, nv, d_pts, d_Y, n, d_F,
+                                                 d_sub, d_err);
+  poly_gram<<<dim3(S, n_pairs), kPolyThreads, 0, stream>>>(d_pd, d_F, d_sub, n, d_pairs, d_G);
+  const size_t lds = poly_solve_lds(T);
+  hipError_t e = allow_lds(poly_solve, lds);
+  if (e != hipSuccess) return e;
+  poly_solve<<<S, kPolyThreads, lds, stream>>>(d_pd, d_G, d_beta64, d_beta32, d_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_poly_eval(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,
+                            const uint32_t *d_idx, uint32_t nv, const float *d_beta32, float *d_P,
+                            uint64_t stride, hipStream_t stream) {
+  const size_t per = (size_t)T * C * 4;
+  const uint32_t SG = (uint32_t)std::max<size_t>(1, std::min<size_t>(S, kEvalLds / per));
+  const uint32_t groups = (S + SG - 1) / SG;
+  const size_t lds = SG * per;
+  const uint32_t grid = std::max<uint32_t>(
+      1, std::min<uint32_t>(2048, (nv + kPolyThreads - 1) / kPolyThreads));
+  hipError_t e = hipSuccess;
+#define CGS_POLY_EVAL(CBV)                                                                      \
+  do {                                                                                          \
+    e = allow_lds(poly_eval<CBV>, lds);                                                         \
+    if (e == hipSuccess)                                                                        \
+      poly_eval<CBV><<<grid * groups, kPolyThreads, lds, stream>>>(                             \
+          d_pd, d_space, d_idx, nv, d_beta32, SG, grid, d_P, stride);                           \
+  } while (0)
+  if (C <= 8) CGS_POLY_EVAL(8);
+  else if (C <= 16) CGS_POLY_EVAL(16);
+  else if (C <= 32) CGS_POLY_EVAL(32);
+  else CGS_POLY_EVAL(64);
+#undef CGS_POLY_EVAL
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+} // namespace cgs
