@@ -488,6 +488,63 @@ def tree_fit_path(cgs, sp, spec, repeats=5):
     }
 
 
+POLY_ORDER, POLY_COUNTERS = 3, 24
+VALU_FP32_PEAK_T = 78.6   # fp32 FMA on the vector units, packed FP32 not used
+
+
+def poly_path(cgs, sp, spec, repeats=3, n_heldout=100000, n_steps=20):
+    """Least-squares polynomial models (Sect. 3.4.1) on the 2^24 space: the
+    three-level design (every non-binary parameter at its lowest, middle and
+    highest value) measured with synthetic counters, order-3 interactions
+    plus squares (139 terms) in each of the 8 binary subspaces, 24 counters.
+    Times the fit and the evaluation of every valid configuration; the
+    counters of 100,000 other configurations (drawn in the same call, so the
+    same synthetic function) give the held-out error; then n_steps search
+    steps run on the fitted model."""
+    import synth
+    valid = sp.copy_valid()
+    design = cgs.PolyModel.design(sp)
+    g = synth.rng(8, 1)
+    held = np.setdiff1d(g.choice(len(valid), n_heldout, replace=False), design)
+    rows = np.concatenate([design, held])
+    Y = synth.measured_counters(g, _digits(valid[rows], spec.radix), spec.radix, POLY_COUNTERS)
+    fits, evals = [], []
+    model = None
+    for _ in range(repeats):
+        if model is not None:
+            model.close()
+        model = cgs.PolyModel(sp, design, Y[: len(design)], POLY_ORDER)
+        fits.append(model.report["fit_ms"])
+        evals.append(model.report["eval_ms"])
+    T = model.report["n_terms"]
+    pred = model.gather_predictions(held.astype(np.uint32))
+    truth = Y[len(design):]
+    rel_mae = float(np.mean(np.abs(pred - truth) / (np.abs(truth).mean(axis=0) + 1e-30)))
+    eval_ms = float(np.median(evals))
+    flop = len(valid) * 2.0 * T * POLY_COUNTERS
+    achieved = flop / (eval_ms / 1e3) / 1e12
+    # the model drives the search like any other
+    U, pcs, thr = workload_inputs(n_steps)
+    t0 = time.perf_counter()
+    _, sess = run_search(cgs, sp, model, U, pcs, thr, n_steps, timing=False)
+    sp.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / n_steps
+    sess.close()
+    model.close()
+    return {
+        "design_points": int(len(design)), "subspaces": model.report["n_subspaces"],
+        "terms": T, "order": POLY_ORDER, "counters": POLY_COUNTERS,
+        "fit_ms_median": float(np.median(fits)), "eval_ms_median": eval_ms,
+        "eval_configs_per_s": len(valid) / (eval_ms / 1e3),
+        "heldout_configs": int(len(held)), "heldout_rel_mae": rel_mae,
+        "search_step_ms": step_ms,
+        "eval_roofline": {"kernel": "poly_eval", "bound": "valu", "achieved": achieved,
+                          "peak": VALU_FP32_PEAK_T, "unit": "TFLOP/s",
+                          "frac": achieved / VALU_FP32_PEAK_T,
+                          "flop_per_config": 2 * T * POLY_COUNTERS},
+    }
+
+
 def cpu_fit_baseline(spec, sp, n_sample=250000):
     """The oracle's tree fit, untouched, single thread, on the first
     n_sample points of the same fit workload (same counters and keys)."""
@@ -582,6 +639,7 @@ def main() -> int:
     ap.add_argument("--no-online", action="store_true")
     ap.add_argument("--no-neighbourhood", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
+    ap.add_argument("--no-poly", action="store_true")
     ap.add_argument("--inference-only", action="store_true",
                     help="only the two perceptron inference sweeps (for counter runs)")
     args = ap.parse_args()
@@ -686,6 +744,11 @@ def main() -> int:
         fit = tree_fit_path(cgs, sp, spec)
         log(f"tree fit: {fit}")
 
+    poly = None
+    if not args.no_poly:
+        poly = poly_path(cgs, sp, spec)
+        log(f"poly: {poly}")
+
     mlp = None
     if not args.no_mlp:
         mlp = mlp_path(cgs, sp, model)
@@ -746,6 +809,7 @@ def main() -> int:
         "online": online,
         "neighbourhood": nbh,
         "tree_fit": fit,
+        "poly": poly,
         "hbm_copy_probe": probe,
         "model_eval_ms": model.eval_ms(),
         "space_create_ms": t_enum * 1e3,

@@ -290,7 +290,7 @@ struct PolyDev {
   double xv64[CGS_MAX_PARAMS * CGS_MAX_RADIX]; // feature of (parameter, digit)
   float xv32[CGS_MAX_PARAMS * CGS_MAX_RADIX];
 };
-size_t poly_solve_lds(int T);
+size_t poly_solve_lds(int T, int C);
 hipError_t launch_poly_design(const SpaceDev *d_space, const uint32_t *d_idx, uint32_t nv,
                               const uint32_t *d_allowed, uint64_t *d_tile_cnt,
                               uint64_t *d_tile_off, uint32_t *d_out, hipStream_t stream);

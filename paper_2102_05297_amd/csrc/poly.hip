@@ -28,6 +28,7 @@ namespace {
 constexpr int kPolyThreads = 256;
 constexpr int kGB = 32;        // Gram block edge
 constexpr int kGramChunk = 64; // points staged per round of the Gram kernel
+constexpr int kEvalThreads = 1024; // one workgroup per CU holds the coefficients
 constexpr double kRidge = 1e-9;
 
 __device__ __forceinline__ uint32_t term_count(uint32_t d) { return d & 7u; }
@@ -186,16 +187,19 @@ __global__ __launch_bounds__(kPolyThreads) void poly_gram(const PolyDev *__restr
 
 __device__ __forceinline__ uint32_t pk(uint32_t i, uint32_t j) { return i * (i + 1) / 2 + j; }
 
-// One workgroup per subspace: (G + lam I) beta = R by Cholesky in LDS.
+// One workgroup per subspace: (G + lam I) beta = R by Cholesky in LDS
+// (packed lower triangle), then the two triangular solves for CC counters at
+// a time, each elimination step spread over (row, counter) pairs.
 __global__ __launch_bounds__(kPolyThreads) void poly_solve(const PolyDev *__restrict__ pd,
                                                            const double *__restrict__ G,
+                                                           uint32_t CC,
                                                            double *__restrict__ beta64,
                                                            float *__restrict__ beta32,
                                                            uint32_t *__restrict__ err) {
-  extern __shared__ double L[]; // packed lower triangle, then z[T][kRhs]
-  constexpr uint32_t kRhs = 16;
+  extern __shared__ double L[]; // packed lower triangle, then z[T][CC]
   __shared__ double s_lam;
   const uint32_t T = pd->T, C = pd->C, Ta = T + C, s = blockIdx.x, t = threadIdx.x;
+  const uint32_t tx = t % 16, ty = t / 16;
   const double *Gs = G + (uint64_t)s * Ta * Ta;
   double *z = L + (uint64_t)T * (T + 1) / 2;
   double *b64 = beta64 + (uint64_t)s * T * C;
@@ -216,7 +220,8 @@ __global__ __launch_bounds__(kPolyThreads) void poly_solve(const PolyDev *__rest
   }
   __syncthreads();
   for (uint32_t i = t; i < T; i += kPolyThreads) L[pk(i, i)] += s_lam;
-  // right-looking Cholesky, column by column
+  // right-looking Cholesky, column by column; the trailing update is tiled
+  // 16 x 16 over (row, column) pairs of the remaining lower triangle
   for (uint32_t j = 0; j < T; ++j) {
     __syncthreads();
     if (t == 0) {
@@ -231,34 +236,44 @@ __global__ __launch_bounds__(kPolyThreads) void poly_solve(const PolyDev *__rest
     const double djj = L[pk(j, j)];
     for (uint32_t i = j + 1 + t; i < T; i += kPolyThreads) L[pk(i, j)] /= djj;
     __syncthreads();
-    for (uint32_t i = j + 1 + t; i < T; i += kPolyThreads) {
+    for (uint32_t i = j + 1 + ty; i < T; i += 16) {
       const double lij = L[pk(i, j)];
-      for (uint32_t k = j + 1; k <= i; ++k) L[pk(i, k)] -= lij * L[pk(k, j)];
+      for (uint32_t k = j + 1 + tx; k <= i; k += 16) L[pk(i, k)] -= lij * L[pk(k, j)];
     }
   }
-  __syncthreads();
-  // L L^T beta = R, kRhs counters at a time: thread c solves column c
-  for (uint32_t c0 = 0; c0 < C; c0 += kRhs) {
-    const uint32_t c = c0 + t;
-    const bool mine = t < kRhs && c < C;
-    if (mine) {
-      for (uint32_t i = 0; i < T; ++i) {
-        double v = Gs[(uint64_t)i * Ta + T + c];
-        for (uint32_t k = 0; k < i; ++k) v -= L[pk(i, k)] * z[k * kRhs + t];
-        z[i * kRhs + t] = v / L[pk(i, i)];
+  // L z = R, then L^T beta = z, CC counters at a time
+  for (uint32_t c0 = 0; c0 < C; c0 += CC) {
+    const uint32_t cc = min(CC, C - c0);
+    __syncthreads();
+    for (uint32_t e = t; e < T * cc; e += kPolyThreads) {
+      const uint32_t i = e / cc, c = e % cc;
+      z[i * CC + c] = Gs[(uint64_t)i * Ta + T + c0 + c];
+    }
+    for (uint32_t i = 0; i < T; ++i) {
+      __syncthreads();
+      if (t < cc) z[i * CC + t] /= L[pk(i, i)];
+      __syncthreads();
+      for (uint32_t e = t; e < (T - 1 - i) * cc; e += kPolyThreads) {
+        const uint32_t k = i + 1 + e / cc, c = e % cc;
+        z[k * CC + c] -= L[pk(k, i)] * z[i * CC + c];
       }
-      for (uint32_t i = T; i-- > 0;) {
-        double v = z[i * kRhs + t];
-        for (uint32_t k = i + 1; k < T; ++k) v -= L[pk(k, i)] * z[k * kRhs + t];
-        z[i * kRhs + t] = v / L[pk(i, i)];
-      }
-      for (uint32_t i = 0; i < T; ++i) {
-        const double b = z[i * kRhs + t];
-        b64[(uint64_t)i * C + c] = b;
-        b32[(uint64_t)i * C + c] = (float)b;
+    }
+    for (uint32_t i = T; i-- > 0;) {
+      __syncthreads();
+      if (t < cc) z[i * CC + t] /= L[pk(i, i)];
+      __syncthreads();
+      for (uint32_t e = t; e < i * cc; e += kPolyThreads) {
+        const uint32_t k = e / cc, c = e % cc;
+        z[k * CC + c] -= L[pk(i, k)] * z[i * CC + c];
       }
     }
     __syncthreads();
+    for (uint32_t e = t; e < T * cc; e += kPolyThreads) {
+      const uint32_t i = e / cc, c = e % cc;
+      const double v = z[i * CC + c];
+      b64[(uint64_t)i * C + c0 + c] = v;
+      b32[(uint64_t)i * C + c0 + c] = (float)v;
+    }
   }
 }
 
@@ -266,32 +281,35 @@ __global__ __launch_bounds__(kPolyThreads) void poly_solve(const PolyDev *__rest
 // P[c][l] for the valid configurations whose subspace lies in this
 // workgroup's group of SG subspaces (group blockIdx.x / per_group, part
 // blockIdx.x % per_group of the valid list): coefficients of the group,
-// feature table and term descriptors staged in LDS.
+// padded with zeros to CB counters so every multiply-add runs unguarded on
+// vector loads, feature table and term descriptors staged in LDS.
 template <int CB>
-__global__ __launch_bounds__(kPolyThreads) void poly_eval(const PolyDev *__restrict__ pd,
+__global__ __launch_bounds__(kEvalThreads) void poly_eval(const PolyDev *__restrict__ pd,
                                                           const SpaceDev *__restrict__ sp,
                                                           const uint32_t *__restrict__ idx,
                                                           uint32_t nv,
                                                           const float *__restrict__ beta32,
                                                           uint32_t SG, uint32_t per_group,
                                                           float *__restrict__ P, uint64_t stride) {
-  extern __shared__ float lds[]; // [SG][T][C] coefficients
+  extern __shared__ float lds[]; // [SG][T][CB] coefficients
   __shared__ float xv[CGS_MAX_PARAMS * CGS_MAX_RADIX];
   __shared__ uint32_t terms[kPolyMaxTerms];
   const uint32_t T = pd->T, C = pd->C, S = pd->S, t = threadIdx.x;
   const uint32_t group = blockIdx.x / per_group, part = blockIdx.x % per_group;
   const uint32_t g0 = group * SG, g1 = min(S, g0 + SG);
-  for (uint32_t e = t; e < (g1 - g0) * T * C; e += kPolyThreads)
-    lds[e] = beta32[(uint64_t)g0 * T * C + e];
-  for (uint32_t e = t; e < CGS_MAX_PARAMS * CGS_MAX_RADIX; e += kPolyThreads) xv[e] = pd->xv32[e];
-  for (uint32_t e = t; e < T; e += kPolyThreads) terms[e] = pd->terms[e];
+  for (uint32_t e = t; e < (g1 - g0) * T * CB; e += kEvalThreads) {
+    const uint32_t c = e % CB, st = e / CB; // st = (s - g0) * T + term
+    lds[e] = c < C ? beta32[((uint64_t)g0 * T + st) * C + c] : 0.0f;
+  }
+  for (uint32_t e = t; e < CGS_MAX_PARAMS * CGS_MAX_RADIX; e += kEvalThreads) xv[e] = pd->xv32[e];
+  for (uint32_t e = t; e < T; e += kEvalThreads) terms[e] = pd->terms[e];
   __syncthreads();
-  for (uint32_t l = part * kPolyThreads + t; l < nv; l += per_group * kPolyThreads) {
+  for (uint32_t l = part * kEvalThreads + t; l < nv; l += per_group * kEvalThreads) {
     uint64_t lo, hi;
     decode_packed(idx[l], sp, lo, hi);
     const uint32_t s = subspace_of(pd, lo, hi);
     if (s < g0 || s >= g1) continue;
-    const float *bs = lds + (uint64_t)(s - g0) * T * C;
+    const float *bs = lds + (uint64_t)(s - g0) * T * CB;
     float acc[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
@@ -302,10 +320,15 @@ __global__ __launch_bounds__(kPolyThreads) void poly_eval(const PolyDev *__restr
         const uint32_t j = term_var(d, q);
         f *= xv[j * CGS_MAX_RADIX + digit_of(lo, hi, j)];
       }
-      const float *bk = bs + k * C;
+      const float4 *bk = reinterpret_cast<const float4 *>(bs + k * CB);
 #pragma unroll
-      for (int c = 0; c < CB; ++c)
-        if ((uint32_t)c < C) acc[c] += f * bk[c];
+      for (int c4 = 0; c4 < CB / 4; ++c4) {
+        const float4 b = bk[c4];
+        acc[4 * c4] += f * b.x;
+        acc[4 * c4 + 1] += f * b.y;
+        acc[4 * c4 + 2] += f * b.z;
+        acc[4 * c4 + 3] += f * b.w;
+      }
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c)
@@ -319,11 +342,21 @@ template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-constexpr size_t kEvalLds = 96 * 1024;
+constexpr size_t kEvalLds = 144 * 1024;
+constexpr size_t kSolveLds = 156 * 1024;
 
 } // namespace
 
-size_t poly_solve_lds(int T) { return ((size_t)T * (T + 1) / 2 + (size_t)T * 16) * 8; }
+// LDS of the solve: the packed factor, then as many counters' right-hand
+// sides as fit in the rest of 160 KB (at least one).
+uint32_t poly_solve_cc(int T, int C) {
+  const size_t tri = (size_t)T * (T + 1) / 2 * 8;
+  const size_t room = tri < kSolveLds ? kSolveLds - tri : 0;
+  return (uint32_t)std::max<size_t>(1, std::min<size_t>(C, room / ((size_t)T * 8)));
+}
+size_t poly_solve_lds(int T, int C) {
+  return ((size_t)T * (T + 1) / 2 + (size_t)T * poly_solve_cc(T, C)) * 8;
+}
 
 hipError_t launch_poly_design(const SpaceDev *d_space, const uint32_t *d_idx, uint32_t nv,
                               const uint32_t *d_allowed, uint64_t *d_tile_cnt,
@@ -348,34 +381,40 @@ hipError_t launch_poly_fit(const PolyDev *d_pd, int T, int C, int S, const Space
   poly_features<<<gf, kPolyThreads, 0, stream>>>(d_pd, d_space, d_idx, nv, d_pts, d_Y, n, d_F,
                                                  d_sub, d_err);
   poly_gram<<<dim3(S, n_pairs), kPolyThreads, 0, stream>>>(d_pd, d_F, d_sub, n, d_pairs, d_G);
-  const size_t lds = poly_solve_lds(T);
+  const size_t lds = poly_solve_lds(T, C);
   hipError_t e = allow_lds(poly_solve, lds);
   if (e != hipSuccess) return e;
-  poly_solve<<<S, kPolyThreads, lds, stream>>>(d_pd, d_G, d_beta64, d_beta32, d_err);
+  poly_solve<<<S, kPolyThreads, lds, stream>>>(d_pd, d_G, poly_solve_cc(T, C), d_beta64,
+                                               d_beta32, d_err);
   return hipGetLastError();
 }
 
 hipError_t launch_poly_eval(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,
                             const uint32_t *d_idx, uint32_t nv, const float *d_beta32, float *d_P,
                             uint64_t stride, hipStream_t stream) {
-  const size_t per = (size_t)T * C * 4;
+  const int CB = C <= 8 ? 8 : C <= 16 ? 16 : C <= 24 ? 24 : C <= 32 ? 32 : C <= 48 ? 48 : 64;
+  const size_t per = (size_t)T * CB * 4;
   const uint32_t SG = (uint32_t)std::max<size_t>(1, std::min<size_t>(S, kEvalLds / per));
   const uint32_t groups = (S + SG - 1) / SG;
   const size_t lds = SG * per;
   const uint32_t grid = std::max<uint32_t>(
-      1, std::min<uint32_t>(2048, (nv + kPolyThreads - 1) / kPolyThreads));
+      1, std::min<uint32_t>(1024, (nv + kEvalThreads - 1) / kEvalThreads));
   hipError_t e = hipSuccess;
 #define CGS_POLY_EVAL(CBV)                                                                      \
   do {                                                                                          \
     e = allow_lds(poly_eval<CBV>, lds);                                                         \
     if (e == hipSuccess)                                                                        \
-      poly_eval<CBV><<<grid * groups, kPolyThreads, lds, stream>>>(                             \
+      poly_eval<CBV><<<grid * groups, kEvalThreads, lds, stream>>>(                             \
           d_pd, d_space, d_idx, nv, d_beta32, SG, grid, d_P, stride);                           \
   } while (0)
-  if (C <= 8) CGS_POLY_EVAL(8);
-  else if (C <= 16) CGS_POLY_EVAL(16);
-  else if (C <= 32) CGS_POLY_EVAL(32);
-  else CGS_POLY_EVAL(64);
+  switch (CB) {
+  case 8: CGS_POLY_EVAL(8); break;
+  case 16: CGS_POLY_EVAL(16); break;
+  case 24: CGS_POLY_EVAL(24); break;
+  case 32: CGS_POLY_EVAL(32); break;
+  case 48: CGS_POLY_EVAL(48); break;
+  default: CGS_POLY_EVAL(64); break;
+  }
 #undef CGS_POLY_EVAL
   if (e != hipSuccess) return e;
   return hipGetLastError();
