@@ -350,3 +350,61 @@ def measured_counters(g: np.random.Generator, digits: np.ndarray, radix: Sequenc
         v *= np.float32(1.0) + np.float32(noise) * g.standard_normal(n, dtype=np.float32)
         np.multiply(v, scale, out=Yt[c])
     return np.ascontiguousarray(Yt.T)
+
+
+# --------------------------------------------------------------------------
+# A synthetic GPU kernel: runtime and Table 1 counters of every configuration
+# --------------------------------------------------------------------------
+@dataclass
+class KernelTable:
+    """Measured runtimes [Nv] (float32, seconds) and Table 1 counter vectors
+    [Nv][24] (float64, pre-Volta scales) of every valid configuration."""
+    runtime: np.ndarray
+    counters: np.ndarray
+
+
+def kernel_table(g: np.random.Generator, digits: np.ndarray, radix: Sequence[int]) -> KernelTable:
+    """A synthetic kernel whose bottlenecks decide its runtime.
+
+    Every configuration moves work between four memory resources (DRAM, L2,
+    texture, shared memory) and the instruction pipes: each resource's
+    transaction count is base * exp(sum_j a_rj (x_j - 1/2)) over the
+    parameters' normalised digits x_j, with random slopes a_rj (a tiling
+    parameter lowers DRAM traffic and raises shared-memory traffic, say).
+    Each resource's time is its count over its peak rate; the runtime is the
+    slowest resource's time over the SM efficiency, so the counters of the
+    bottleneck show full utilisation (10 on the 0..10 scale) and the others
+    show their share of the runtime.  Instruction counts split over the seven
+    classes by a parameter-dependent mix; warp efficiencies 80..100%."""
+    digits = np.asarray(digits)
+    n, P = digits.shape
+    x = digits / np.maximum(np.asarray(radix, dtype=np.float64) - 1.0, 1.0) - 0.5
+    def work(scale, spread):
+        a = g.normal(0.0, spread, size=P)
+        return scale * np.exp(x @ a)
+    dram, l2, tex, shr = work(4e5, 1.2), work(2e6, 1.0), work(3e6, 0.8), work(1e6, 1.4)
+    inst = work(2e5, 0.9)
+    rd = g.uniform(0.5, 0.9, size=4)                    # read share per resource
+    t_mem = np.stack([dram / 1.0e6, l2 / 4.0e6, tex / 6.0e6, shr / 2.5e6])
+    t_inst = inst / 6.0e5
+    sm_e = 100.0 * (0.7 + 0.3 / (1.0 + np.exp(-(x @ g.normal(0.0, 2.0, size=P)))))
+    we = 100.0 * (0.85 + 0.15 / (1.0 + np.exp(-(x @ g.normal(0.0, 2.0, size=P)))))
+    wnpe = 100.0 * (0.8 + 0.2 / (1.0 + np.exp(-(x @ g.normal(0.0, 2.0, size=P)))))
+    t_busy = np.maximum(t_mem.max(axis=0), t_inst)
+    runtime = t_busy / (sm_e / 100.0) * 1e-3 + 2e-6
+    mix = np.abs(g.dirichlet(np.full(7, 0.5)) + 0.2 * np.tanh(x @ g.normal(0.0, 1.0, size=(P, 7))))
+    mix /= mix.sum(axis=1, keepdims=True)
+    c = np.zeros((n, 24), dtype=np.float64)
+    for i, (tot, r) in enumerate(zip((dram, l2, tex, shr), rd)):
+        if i == 2:
+            c[:, 4] = tot                                # TEX_RWT
+        else:
+            k = {0: 0, 1: 2, 3: 6}[i]
+            c[:, k], c[:, k + 1] = tot * r, tot * (1.0 - r)
+    c[:, 5] = 60.0 / (1.0 + np.exp(-(x @ g.normal(0.0, 3.0, size=P)) - 2.0))     # LOC_O
+    c[:, 8:15] = (32.0 * inst * (we / 100.0) * (wnpe / 100.0))[:, None] * mix
+    c[:, 15] = inst
+    c[:, 16] = 100.0 * t_inst / t_busy                                            # INST_ISSUE_U
+    c[:, 17:21] = (10.0 * t_mem / t_busy).T                                       # DRAM_U .. SHR_U
+    c[:, 21], c[:, 22], c[:, 23] = sm_e, we, wnpe
+    return KernelTable(runtime.astype(np.float32), c)
