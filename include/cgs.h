@@ -290,6 +290,45 @@ cgs_status cgs_model_fit_poly(cgs_space space, uint64_t n, int n_counters,
 cgs_status cgs_poly_shape(cgs_model model, int *n_subspaces, int *n_terms);
 cgs_status cgs_poly_copy_coefficients(cgs_model model, double *beta_host);
 
+/* A model whose predictions the caller gives: pred_host[n_valid][n_counters]
+ * (finite), e.g. counters measured on every configuration, the setting of
+ * Sect. 4.3 where the search reads measured counters instead of a model's. */
+cgs_status cgs_model_load_predictions(cgs_space space, int n_counters, const float *pred_host,
+                                      cgs_model *out);
+
+/* The searcher's outer loop, Alg. 1 (Sect. 3.7), on tables of measured
+ * runtimes and counters (the paper's simulated autotuning, Sect. 4.1).  A
+ * uniform draw gives the first configuration; each iteration profiles the
+ * current one (one test: its runtime and Table 1 counters are looked up),
+ * runs the expert system and a scored step with the model, then `draws`
+ * weighted draws, each one test; the fastest of them (the later on a tie) is
+ * profiled next.  The run stops at the first test whose runtime is within
+ * well_factor of the table's best (when stop_at_well), after max_tests
+ * tests, or when no configuration is left.
+ *   runtime_host[n_valid]       float32 runtimes
+ *   counters_host[n_valid][24]  Table 1 counters, pre-Volta scales
+ *   expert                      expert-system settings (cores, threads)
+ *   uniforms_host[n_uniforms]   one 64-bit random number per draw
+ *   tested_host[capacity]       valid indices in test order; profiled_host
+ *                               (may be NULL) 1 for profiled runs
+ *   *n_tests, *tests_to_well    tests made; position (1-based) of the first
+ *                               well-performing test, 0 if none
+ * The model must predict the 24 counters; the session should be fresh.
+ * CGS_ERANGE when the random numbers run out. */
+typedef struct {
+  int32_t draws;          /* runs without counters per profiled run (n), 5 by default */
+  int32_t stop_at_well;   /* 1: stop at the first well-performing test */
+  uint64_t max_tests;     /* 1..capacity */
+  double well_factor;     /* 1.1: within 1.1x of the best runtime */
+} cgs_tuning_opts;
+
+void cgs_default_tuning_opts(cgs_tuning_opts *out);
+cgs_status cgs_tuning_run(cgs_session session, cgs_model model, const float *runtime_host,
+                          const double *counters_host, const cgs_expert_params *expert,
+                          const uint64_t *uniforms_host, uint64_t n_uniforms,
+                          const cgs_tuning_opts *opts, uint64_t capacity, uint64_t *tested_host,
+                          uint8_t *profiled_host, uint64_t *n_tests, uint64_t *tests_to_well);
+
 /* Forest models only: number of trees and depth, then the trees in the
  * layout of cgs_model_load_forest (feat, thr [n_trees][2^depth - 1],
  * leaves [n_trees][2^depth][n_counters]). */

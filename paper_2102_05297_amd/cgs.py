@@ -42,7 +42,8 @@ EXPORTS = (
     "cgs_model_gather_predictions", "cgs_search_step_neighbourhood",
     "cgs_session_copy_neighbourhood", "cgs_model_fit_tree", "cgs_model_forest_shape",
     "cgs_model_copy_forest", "cgs_poly_design", "cgs_model_fit_poly", "cgs_poly_shape",
-    "cgs_poly_copy_coefficients",
+    "cgs_poly_copy_coefficients", "cgs_model_load_predictions", "cgs_default_tuning_opts",
+    "cgs_tuning_run",
 )
 
 
@@ -97,6 +98,11 @@ class cgs_tree_fit_report(C.Structure):
                 ("sq_err", (C.c_uint64 * 2) * 15)]
 
 
+class cgs_tuning_opts(C.Structure):
+    _fields_ = [("draws", C.c_int32), ("stop_at_well", C.c_int32), ("max_tests", C.c_uint64),
+                ("well_factor", C.c_double)]
+
+
 class cgs_poly_fit_report(C.Structure):
     _fields_ = [("n_subspaces", C.c_int32), ("n_terms", C.c_int32), ("order", C.c_int32),
                 ("n_counters", C.c_int32), ("n_points", C.c_uint64), ("fit_ms", C.c_float),
@@ -146,6 +152,10 @@ _sig("cgs_model_fit_poly", [_p, _u64, C.c_int, _p, _p, C.c_int, _ptr(_p),
                             _ptr(cgs_poly_fit_report)])
 _sig("cgs_poly_shape", [_p, _ptr(C.c_int), _ptr(C.c_int)])
 _sig("cgs_poly_copy_coefficients", [_p, _p])
+_sig("cgs_model_load_predictions", [_p, C.c_int, _p, _ptr(_p)])
+_sig("cgs_default_tuning_opts", [_ptr(cgs_tuning_opts)], None)
+_sig("cgs_tuning_run", [_p, _p, _p, _p, _ptr(cgs_expert_params), _p, _u64, _ptr(cgs_tuning_opts),
+                        _u64, _p, _p, _ptr(_u64), _ptr(_u64)])
 _sig("cgs_session_create", [_p, _ptr(cgs_params), _ptr(_p)])
 _sig("cgs_search_step", [_p, _p, _u64, _p, _p, _ptr(cgs_expert_params)])
 _sig("cgs_search_step_neighbourhood", [_p, _p, _u64, C.c_int, _p, _p, _ptr(cgs_expert_params)])
@@ -436,6 +446,19 @@ class PolyModel(_Model):
         return out
 
 
+class TableModel(_Model):
+    """Predictions given by the caller, [n_valid][C] (cgs_model_load_predictions)."""
+
+    def __init__(self, space: Space, predictions):
+        pred = _arr(predictions, np.float32)
+        if pred.ndim != 2 or len(pred) != space.n_valid:
+            raise ValueError("predictions must be [n_valid][C]")
+        h = C.c_void_p()
+        _check(_lib.cgs_model_load_predictions(space.h, pred.shape[1], _ptrof(pred), C.byref(h)),
+               "cgs_model_load_predictions")
+        self.h, self.space, self.n_counters = h, space, int(pred.shape[1])
+
+
 def mlp_flatten(params) -> np.ndarray:
     """[W1, b1, W2, b2, W3, b3] -> the library's fp32 parameter vector."""
     return np.concatenate([np.asarray(p, dtype=np.float32).ravel() for p in params])
@@ -549,6 +572,27 @@ class Session:
             return None
         _check(st, "cgs_sample_next")
         return int(raw.value), int(valid.value)
+
+    def tuning_run(self, model, runtime, counters, uniforms, draws: int = 5,
+                   max_tests: Optional[int] = None, stop_at_well: bool = True,
+                   well_factor: float = 1.1, expert: Optional["cgs_expert_params"] = None):
+        """Alg. 1 on tables of measured runtimes [n_valid] and counters
+        [n_valid][24] (cgs_tuning_run): (tested valid indices, profiled flags,
+        tests to the first well-performing configuration, 0 if none)."""
+        rt = _arr(runtime, np.float32)
+        pc = _arr(counters, np.float64)
+        us = _arr(uniforms, np.uint64)
+        cap = int(max_tests if max_tests is not None else len(us) + 1)
+        opts = cgs_tuning_opts(int(draws), 1 if stop_at_well else 0, cap, float(well_factor))
+        ep = expert if expert is not None else cgs_default_expert_params()
+        tested = np.zeros(cap, dtype=np.uint64)
+        prof = np.zeros(cap, dtype=np.uint8)
+        nt, tw = _u64(), _u64()
+        _check(_lib.cgs_tuning_run(self.h, model.h, _ptrof(rt), _ptrof(pc), C.byref(ep), _ptrof(us),
+                                   len(us), C.byref(opts), cap, _ptrof(tested), _ptrof(prof),
+                                   C.byref(nt), C.byref(tw)), "cgs_tuning_run")
+        n = int(nt.value)
+        return tested[:n].astype(np.int64), prof[:n].astype(bool), int(tw.value)
 
     def step_info(self) -> cgs_step_info:
         info = cgs_step_info()

@@ -79,7 +79,7 @@ struct cgs_space_s {
 
 struct cgs_model_s {
   cgs_space space = nullptr;
-  int kind = 0; // 0 = forest, 1 = perceptron, 2 = least-squares polynomials
+  int kind = 0; // 0 = forest, 1 = perceptron, 2 = least-squares polynomials, 3 = table
   int n_counters = 0;
   float *d_P = nullptr; // predictions [C][stride] of every valid configuration
   uint64_t stride = 0;
@@ -480,6 +480,8 @@ cgs_status evaluate_model(cgs_model m) {
     e = launch_forest_eval(sp->d_desc, sp->d_idx, (uint32_t)sp->n_valid, m->d_nodes, m->d_leaves,
                            m->n_trees, m->depth, m->n_counters, m->d_P, m->stride, nullptr, 0, 0,
                            sp->stream);
+  } else if (m->kind == 3) {
+    // predictions given by the caller: nothing to evaluate
   } else if (m->kind == 2) {
     e = launch_poly_eval(m->d_poly, m->poly.T, m->poly.C, m->poly.S, sp->d_desc, sp->d_idx,
                          (uint32_t)sp->n_valid, m->d_beta32, m->d_P, m->stride, sp->stream);
@@ -938,6 +940,127 @@ extern "C" cgs_status cgs_poly_copy_coefficients(cgs_model m, double *beta) {
   HIP_TRY(hipMemcpyAsync(beta, m->d_beta64, n * 8, hipMemcpyDeviceToHost, m->space->stream));
   HIP_TRY(hipStreamSynchronize(m->space->stream));
   return CGS_OK;
+}
+
+// ------------------------------------------------- prediction tables, Alg. 1
+extern "C" cgs_status cgs_model_load_predictions(cgs_space sp, int n_counters,
+                                                 const float *pred_host, cgs_model *out) {
+  if (!out) return fail(CGS_EINVAL, "NULL out");
+  *out = nullptr;
+  if (!sp || !pred_host) return fail(CGS_EINVAL, "NULL argument");
+  if (n_counters < 1 || n_counters > CGS_MAX_COUNTERS)
+    return fail(CGS_ERANGE, "n_counters %d outside 1..%d", n_counters, CGS_MAX_COUNTERS);
+  const uint64_t nv = sp->n_valid;
+  if (nv == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
+  for (uint64_t i = 0; i < nv * (uint64_t)n_counters; ++i)
+    if (!std::isfinite(pred_host[i])) return fail(CGS_EINVAL, "prediction %llu is not finite",
+                                                  (unsigned long long)i);
+  cgs_model m = new (std::nothrow) cgs_model_s();
+  if (!m) return fail(CGS_ENOMEM, "host allocation");
+  m->space = sp;
+  ++sp->refs;
+  m->kind = 3;
+  m->n_counters = n_counters;
+  m->stride = (nv + 63) & ~(uint64_t)63;
+  float *d_src = nullptr;
+  hipError_t e = dalloc(&m->d_P, (size_t)n_counters * m->stride);
+  if (e == hipSuccess) e = dalloc(&d_src, nv * (size_t)n_counters);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(m->d_P, 0, (size_t)n_counters * m->stride * sizeof(float), sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_src, pred_host, nv * (size_t)n_counters * sizeof(float),
+                       hipMemcpyHostToDevice, sp->stream);
+  if (e == hipSuccess)
+    e = launch_rows_to_columns(d_src, (uint32_t)nv, n_counters, m->d_P, m->stride, sp->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
+  dfree(d_src);
+  if (e != hipSuccess) {
+    destroy_model(m);
+    return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "prediction table: %s",
+                hipGetErrorString(e));
+  }
+  *out = m;
+  return CGS_OK;
+}
+
+extern "C" void cgs_default_tuning_opts(cgs_tuning_opts *out) {
+  if (!out) return;
+  out->draws = 5;
+  out->stop_at_well = 1;
+  out->max_tests = UINT64_MAX;
+  out->well_factor = 1.1;
+}
+
+extern "C" cgs_status cgs_tuning_run(cgs_session s, cgs_model m, const float *runtime,
+                                     const double *counters, const cgs_expert_params *expert,
+                                     const uint64_t *uniforms, uint64_t n_uniforms,
+                                     const cgs_tuning_opts *opts, uint64_t capacity,
+                                     uint64_t *tested, uint8_t *profiled, uint64_t *n_tests,
+                                     uint64_t *tests_to_well) {
+  if (!s || !m || !runtime || !counters || !uniforms || !opts || !n_tests || !tests_to_well ||
+      (capacity && !tested))
+    return fail(CGS_EINVAL, "NULL argument");
+  *n_tests = 0;
+  *tests_to_well = 0;
+  cgs_space sp = s->space;
+  if (m->space != sp) return fail(CGS_EINVAL, "model and session belong to different spaces");
+  if (m->n_counters != 24) return fail(CGS_EINVAL, "the loop needs a model of the 24 counters");
+  if (opts->draws < 1) return fail(CGS_ERANGE, "draws %d < 1", opts->draws);
+  if (opts->max_tests < 1 || opts->max_tests > capacity)
+    return fail(CGS_ERANGE, "max_tests must be 1..capacity");
+  const uint64_t nv = sp->n_valid;
+  if (nv == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
+  float rmin = runtime[0];
+  for (uint64_t l = 1; l < nv; ++l) rmin = std::min(rmin, runtime[l]);
+  const double thresh = opts->well_factor * (double)rmin;
+  uint64_t u = 0, nt = 0, found = 0;
+  auto test = [&](uint64_t l, bool prof) {
+    tested[nt] = l;
+    if (profiled) profiled[nt] = prof ? 1 : 0;
+    ++nt;
+    if (!found && (double)runtime[l] <= thresh) found = nt;
+    return (opts->stop_at_well && found) || nt >= opts->max_tests;
+  };
+  auto draw = [&](uint64_t *l) -> cgs_status {
+    if (u >= n_uniforms) return fail(CGS_ERANGE, "the run needs more than %llu random numbers",
+                                     (unsigned long long)n_uniforms);
+    uint64_t raw = 0;
+    return cgs_sample_next(s, uniforms[u++], &raw, l);
+  };
+  cgs_status st = cgs_search_step(s, m, CGS_NO_PROFILE, nullptr, nullptr, expert);
+  uint64_t c = 0;
+  if (st == CGS_OK) st = draw(&c);
+  bool have = st == CGS_OK;
+  if (st == CGS_EEMPTY) st = CGS_OK;
+  while (st == CGS_OK && have) {
+    if (test(c, true)) break;
+    st = cgs_search_step(s, m, sp->h_idx[c], nullptr, counters + c * 24, expert);
+    if (st != CGS_OK) break;
+    float best = INFINITY;
+    bool next = false, stop = false;
+    for (int k = 0; k < opts->draws; ++k) {
+      uint64_t l = 0;
+      st = draw(&l);
+      if (st == CGS_EEMPTY) {
+        st = CGS_OK;
+        break;
+      }
+      if (st != CGS_OK) break;
+      if (test(l, false)) {
+        stop = true;
+        break;
+      }
+      if (runtime[l] <= best) {
+        best = runtime[l];
+        c = l;
+        next = true;
+      }
+    }
+    if (stop || !next) break;
+  }
+  *n_tests = nt;
+  *tests_to_well = found;
+  return st;
 }
 
 extern "C" cgs_status cgs_model_forest_shape(cgs_model m, int *n_trees, int *depth) {

@@ -158,4 +158,23 @@ hipError_t launch_forest_eval(const SpaceDev *d_space, const uint32_t *d_idx, ui
   return hipGetLastError();
 }
 
+// Predictions given per configuration, src[l][C], into the model layout
+// P[c][stride].
+__global__ void rows_to_columns(const float *__restrict__ src, uint32_t n, int C,
+                                float *__restrict__ P, uint64_t stride) {
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (uint64_t)n * C;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t l = e / C, c = e - l * C;
+    P[c * stride + l] = src[e];
+  }
+}
+
+hipError_t launch_rows_to_columns(const float *d_src, uint32_t n, int C, float *d_P,
+                                  uint64_t stride, hipStream_t stream) {
+  const uint64_t total = (uint64_t)n * C;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8192, (total + 255) / 256));
+  rows_to_columns<<<grid, 256, 0, stream>>>(d_src, n, C, d_P, stride);
+  return hipGetLastError();
+}
+
 } // namespace cgs

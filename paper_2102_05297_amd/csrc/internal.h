@@ -195,6 +195,8 @@ hipError_t launch_forest_eval(const SpaceDev *d_space, const uint32_t *d_idx, ui
                               uint16_t *d_leaf_out, uint32_t leaf_first, uint32_t leaf_count,
                               hipStream_t stream);
 
+hipError_t launch_rows_to_columns(const float *d_src, uint32_t n, int C, float *d_P,
+                                  uint64_t stride, hipStream_t stream);
 hipError_t launch_gather_rows(const float *P, uint64_t stride, int n_counters,
                               const uint32_t *d_idx, uint32_t n, float *d_out,
                               hipStream_t stream);

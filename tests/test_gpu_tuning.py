@@ -1,0 +1,89 @@
+"""The searcher's outer loop (Alg. 1, Sect. 3.7) on the GPU vs the oracle:
+with the same tables and random numbers, every tested configuration, the
+profiled flags and the tests to the first well-performing configuration are
+equal."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import search as SR
+from oracle import space as SP
+from oracle import tuning as TU
+from tests.helpers import cgs
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(spec, key):
+    valid = SP.enumerate_valid(spec.radix, spec.values, spec.constraints)
+    digits = SP.digits_of(valid, spec.radix)
+    table = synth.kernel_table(synth.rng(*key), digits, spec.radix)
+    P = table.counters
+    prep = SR.Prepared(valid, digits, None, P, P.astype(np.float32))
+    return valid, table, prep
+
+
+def _expert(m):
+    return m.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=1.0, threads=1e9)
+
+
+def _pair(m, spec, table, prep, seed, n_u, **kw):
+    sp = m.Space.from_spec(spec)
+    model = m.TableModel(sp, table.counters.astype(np.float32))
+    U = synth.uniforms_u64(synth.rng(50, seed), n_u)
+    sess = m.Session(sp)
+    print(f"loop: seed {seed} {kw}", flush=True)
+    tested, prof, tw = sess.tuning_run(model, table.runtime, table.counters, U,
+                                       expert=_expert(m), **kw)
+    kw_o = dict(kw)
+    if "max_tests" in kw_o and kw_o["max_tests"] is None:
+        kw_o.pop("max_tests")
+    ref = TU.run(prep, table.runtime, table.counters, U, cores=1.0, threads=1e9, **kw_o)
+    assert tested.tolist() == ref.tested
+    assert prof.tolist() == ref.profiled
+    assert tw == ref.tests_to_well
+    return ref
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_c1_runs_equal_the_oracle(seed):
+    spec = synth.space_c1()
+    valid, table, prep = _setup(spec, (9, 1))
+    ref = _pair(cgs(), spec, table, prep, seed, 20000)
+    assert ref.tests_to_well > 0
+
+
+@pytest.mark.parametrize("seed,draws", [(0, 5), (1, 3), (2, 1)])
+def test_small_space_runs_to_exhaustion(seed, draws):
+    radix = [3, 4, 2, 5, 3]
+    values = [[1, 2, 4], [1, 2, 4, 8], [0, 1], [1, 2, 4, 8, 16], [1, 2, 4]]
+    spec = synth.Space(radix, values, [])
+    valid, table, prep = _setup(spec, (41,))
+    ref = _pair(cgs(), spec, table, prep, 100 + seed, 4000, draws=draws, stop_at_well=False)
+    assert set(ref.tested) == set(range(len(valid)))
+
+
+def test_c2_first_iterations_equal_the_oracle():
+    spec = synth.space_c2()
+    valid, table, prep = _setup(spec, (9, 2))
+    _pair(cgs(), spec, table, prep, 7, 200, max_tests=48, stop_at_well=False)
+
+
+def test_loop_errors():
+    m = cgs()
+    spec = synth.space_c1()
+    valid, table, prep = _setup(spec, (9, 1))
+    sp = m.Space.from_spec(spec)
+    small = m.TableModel(sp, table.counters[:, :12].astype(np.float32))
+    with pytest.raises(m.CgsError) as ei:
+        m.Session(sp).tuning_run(small, table.runtime, table.counters, np.arange(100, dtype=np.uint64))
+    assert ei.value.status == m.EINVAL
+    model = m.TableModel(sp, table.counters.astype(np.float32))
+    with pytest.raises(m.CgsError) as ei:
+        m.Session(sp).tuning_run(model, table.runtime, table.counters,
+                                 synth.uniforms_u64(synth.rng(51), 4), stop_at_well=False,
+                                 max_tests=100)
+    assert ei.value.status == m.ERANGE
+    bad = table.counters[:3].astype(np.float32).copy()
+    with pytest.raises(ValueError):
+        m.TableModel(sp, bad)
