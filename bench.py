@@ -545,6 +545,100 @@ def poly_path(cgs, sp, spec, repeats=3, n_heldout=100000, n_steps=20):
     }
 
 
+def tuning_path(cgs, n_runs=1000, big_runs=40, big_cap=30000):
+    """Alg. 1 (Sect. 3.7) with the evaluation of Sect. 4.1 on a synthetic
+    bottleneck-driven kernel: tests until a configuration within 1.1x of the
+    best runtime is tested, averaged over n_runs runs, against random
+    search's expected (N + 1) / (K + 1).  Models: the measured counters
+    themselves (as in Sect. 4.3), a tree fitted on the counters of a random
+    20% of the configurations (Sect. 3.4.2) and the least-squares
+    polynomials fitted on the three-level design (Sect. 3.4.1).  Space: the
+    6-parameter space (11,496 valid configurations), then big_runs runs
+    capped at big_cap tests on the 2^24 space."""
+    import synth
+    out = {}
+    for name, spec, key, runs, cap in (("c1", synth.space_c1(), (9, 1), n_runs, None),
+                                       ("c2", synth.space_c2(), (9, 2), big_runs, big_cap)):
+        sp = cgs.Space.from_spec(spec)
+        valid = sp.copy_valid()
+        table = synth.kernel_table(synth.rng(*key), _digits(valid, spec.radix), spec.radix)
+        rt = table.runtime.astype(np.float64)
+        well = rt <= 1.1 * rt.min()
+        N, K = len(rt), int(well.sum())
+        rec = {"n_valid": N, "well_performing": K, "random_expected": (N + 1) / (K + 1),
+               "runs": runs, "cap": cap}
+        models = {"measured": cgs.TableModel(sp, table.counters.astype(np.float32))}
+        if name == "c1":
+            g = synth.rng(10, 1)
+            pts = np.sort(g.choice(N, N // 5, replace=False)).astype(np.uint32)
+            tree, rep = cgs.ForestModel.fit(sp, pts, table.counters[pts].astype(np.float32),
+                                            synth.uniforms_u64(g, len(pts)), 8, 2)
+            models["fitted_tree"] = tree
+            design = cgs.PolyModel.design(sp)
+            models["polynomial"] = cgs.PolyModel(sp, design,
+                                                 table.counters[design].astype(np.float32), 2)
+        ep = cgs.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=1.0, threads=1e9)
+        for mname, model in models.items():
+            tests, wall, found_flags = [], [], []
+            for r in range(runs):
+                U = synth.uniforms_u64(synth.rng(11, r), (cap or 4 * N) + 8)
+                sess = cgs.Session(sp)
+                t0 = time.perf_counter()
+                tested, _, tw = sess.tuning_run(model, table.runtime, table.counters, U,
+                                                max_tests=cap, expert=ep)
+                wall.append(time.perf_counter() - t0)
+                tests.append(tw if tw else len(tested))
+                found_flags.append(tw > 0)
+                sess.close()
+            tests = np.asarray(tests, dtype=np.float64)
+            found = [x for x, f in zip(tests, found_flags) if f] if cap else list(tests)
+            r = {"ms_per_run": float(np.mean(wall)) * 1e3,
+                 "us_per_test": float(np.sum(wall) / tests.sum()) * 1e6}
+            if cap:
+                # runs stopped at the cap are censored: compare the share of
+                # runs that found a well-performing configuration within the
+                # cap with random search's probability of doing so
+                p_rand = 1.0 - float(np.exp(np.sum(np.log1p(-K / (N - np.arange(cap))))))
+                r.update({"found_within_cap": len(found), "share_found": len(found) / runs,
+                          "random_share_found": p_rand,
+                          "mean_tests_when_found": float(np.mean(found)) if found else None})
+            else:
+                r.update({"mean_tests": float(tests.mean()), "median_tests": float(np.median(tests)),
+                          "improvement": rec["random_expected"] / float(tests.mean())})
+            rec[mname] = r
+            model.close()
+        out[name] = rec
+        sp.close()
+    return out
+
+
+def cpu_tuning_baseline(n_runs=40):
+    """The oracle's Alg. 1 loop, untouched, single thread, on the first
+    n_runs runs of the c1 measured-counter workload."""
+    import synth
+    from threadpoolctl import threadpool_limits
+
+    from oracle import search as SR
+    from oracle import space as SP
+    from oracle import tuning as TU
+    spec = synth.space_c1()
+    valid = SP.enumerate_valid(spec.radix, spec.values, spec.constraints)
+    digits = SP.digits_of(valid, spec.radix)
+    table = synth.kernel_table(synth.rng(9, 1), digits, spec.radix)
+    prep = SR.Prepared(valid, digits, None, table.counters, table.counters.astype(np.float32))
+    tests = 0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        for r in range(n_runs):
+            U = synth.uniforms_u64(synth.rng(11, r), 4 * len(valid) + 8)
+            tests += TU.run(prep, table.runtime, table.counters, U, cores=1.0,
+                            threads=1e9).tests_to_well
+        dt = time.perf_counter() - t0
+    return {"value": n_runs / dt, "unit": "runs/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_runs} runs of the 11,496-configuration workload, measured "
+                      f"counters as the model ({dt:.1f} s, {tests / dt:.0f} tests/s)"}
+
+
 def cpu_fit_baseline(spec, sp, n_sample=250000):
     """The oracle's tree fit, untouched, single thread, on the first
     n_sample points of the same fit workload (same counters and keys)."""
@@ -640,6 +734,7 @@ def main() -> int:
     ap.add_argument("--no-neighbourhood", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
     ap.add_argument("--no-poly", action="store_true")
+    ap.add_argument("--no-tuning", action="store_true")
     ap.add_argument("--inference-only", action="store_true",
                     help="only the two perceptron inference sweeps (for counter runs)")
     args = ap.parse_args()
@@ -749,6 +844,11 @@ def main() -> int:
         poly = poly_path(cgs, sp, spec)
         log(f"poly: {poly}")
 
+    tuning = None
+    if not args.no_tuning:
+        tuning = tuning_path(cgs)
+        log(f"tuning: {tuning}")
+
     mlp = None
     if not args.no_mlp:
         mlp = mlp_path(cgs, sp, model)
@@ -761,6 +861,9 @@ def main() -> int:
         if fit is not None:
             fit["cpu_baseline"] = cpu_fit_baseline(spec, sp)
             log(f"tree fit cpu baseline: {fit['cpu_baseline']}")
+        if tuning is not None:
+            tuning["cpu_baseline"] = cpu_tuning_baseline()
+            log(f"tuning cpu baseline: {tuning['cpu_baseline']}")
 
     out = {
         "metric": "configs scored/sec per search step (tree vs MLP surrogate) at oracle-exact pick",
@@ -810,6 +913,7 @@ def main() -> int:
         "neighbourhood": nbh,
         "tree_fit": fit,
         "poly": poly,
+        "tuning": tuning,
         "hbm_copy_probe": probe,
         "model_eval_ms": model.eval_ms(),
         "space_create_ms": t_enum * 1e3,
