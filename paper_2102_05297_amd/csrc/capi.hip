@@ -15,6 +15,7 @@
 
 #include "cgs.h"
 #include "internal.h"
+#include "models.h"
 
 using namespace cgs;
 

@@ -11,6 +11,7 @@
 // structure-of-arrays: P[c][l], so a row of P is contiguous over
 // configurations and the sweep reads it coalesced.
 #include "device_common.h"
+#include "models.h"
 
 namespace cgs {
 

@@ -195,8 +195,6 @@ hipError_t launch_forest_eval(const SpaceDev *d_space, const uint32_t *d_idx, ui
                               uint16_t *d_leaf_out, uint32_t leaf_first, uint32_t leaf_count,
                               hipStream_t stream);
 
-hipError_t launch_rows_to_columns(const float *d_src, uint32_t n, int C, float *d_P,
-                                  uint64_t stride, hipStream_t stream);
 hipError_t launch_gather_rows(const float *P, uint64_t stride, int n_counters,
                               const uint32_t *d_idx, uint32_t n, float *d_out,
                               hipStream_t stream);
@@ -243,67 +241,5 @@ hipError_t launch_array_block_sums(const uint32_t *d_q, uint32_t n, int block_lo
 hipError_t launch_array_draw(uint32_t *d_q, uint32_t n, int block_log2, uint64_t *d_bsum,
                              uint32_t n_blocks, uint64_t u64, DrawResult *d_res,
                              hipStream_t stream);
-
-// ---- regression-tree fitting (Sect. 3.4.2)
-FastDiv make_fastdiv(uint32_t d);
-
-struct TreeFitIn {
-  const SpaceDev *d_space;
-  const uint32_t *d_idx;    // valid raw indices of the space
-  uint32_t n_valid;
-  int n_params;
-  const int32_t *radix;     // host [n_params]
-  uint32_t n;               // measured points, 2 .. 2^31 - 1
-  int n_counters;
-  const uint32_t *d_points; // valid indices [n]
-  const float *d_targets;   // [n][n_counters]
-  const uint64_t *d_keys;   // [n]
-  int max_depth, min_leaf;
-};
-struct TreeFitOut {
-  uint32_t err; // bit 0: a point outside the valid list; bit 1: a non-finite target
-  int32_t depth;
-  uint32_t n_train, n_test, n_split;
-  int32_t scale[CGS_MAX_COUNTERS];
-  uint64_t abs_err[CGS_MAX_DEPTH + 1];
-  uint64_t sq_lo32[CGS_MAX_DEPTH + 1], sq_hi32[CGS_MAX_DEPTH + 1]; // sum e^2 = hi 2^32 + lo
-  float ms;
-};
-struct TreeFitWork;
-// Runs the whole fit on `stream` and synchronises; *work holds the grown tree
-// until tree_fit_release (also after an error, when non-null).
-hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work,
-                        hipStream_t stream);
-// Writes the tree cut at `depth` in the evaluator's layout.
-hipError_t tree_fit_emit(const TreeFitWork *work, int depth, uint16_t *d_nodes, float *d_leaves,
-                         hipStream_t stream);
-void tree_fit_release(TreeFitWork *work);
-
-// ---- least-squares polynomial models per binary subspace (Sect. 3.4.1)
-constexpr int kPolyMaxTerms = CGS_POLY_MAX_TERMS;   // the solve keeps the packed factor in LDS
-constexpr int kPolyMaxOrder = CGS_POLY_MAX_ORDER;   // variables per basis term
-constexpr int kPolyMaxBinary = CGS_POLY_MAX_BINARY; // at most 65,536 subspaces
-// Term descriptor: bits 0..2 the number of factors, then 5 bits per factor
-// (a parameter index); squares repeat their parameter.
-struct PolyDev {
-  int32_t P, k, B, T, C, S, order, pad;
-  uint32_t bin_params[CGS_MAX_PARAMS]; // parameter of subspace bit i
-  uint32_t terms[kPolyMaxTerms];
-  double xv64[CGS_MAX_PARAMS * CGS_MAX_RADIX]; // feature of (parameter, digit)
-  float xv32[CGS_MAX_PARAMS * CGS_MAX_RADIX];
-};
-size_t poly_solve_lds(int T, int C);
-hipError_t launch_poly_design(const SpaceDev *d_space, const uint32_t *d_idx, uint32_t nv,
-                              const uint32_t *d_allowed, uint64_t *d_tile_cnt,
-                              uint64_t *d_tile_off, uint32_t *d_out, hipStream_t stream);
-hipError_t launch_poly_fit(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,
-                           const uint32_t *d_idx, uint32_t nv, const uint32_t *d_pts,
-                           const float *d_Y, uint32_t n, double *d_F, uint32_t *d_sub,
-                           const uint32_t *d_pairs, uint32_t n_pairs, double *d_G,
-                           double *d_beta64, float *d_beta32, uint32_t *d_err,
-                           hipStream_t stream);
-hipError_t launch_poly_eval(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,
-                            const uint32_t *d_idx, uint32_t nv, const float *d_beta32, float *d_P,
-                            uint64_t stride, hipStream_t stream);
 
 } // namespace cgs

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "device_common.h"
+#include "models.h"
 
 namespace cgs {
 
