@@ -612,7 +612,7 @@ def tuning_path(cgs, n_runs=1000, big_runs=40, big_cap=30000):
     return out
 
 
-def cpu_tuning_baseline(n_runs=40):
+def cpu_tuning_baseline(n_runs=160):
     """The oracle's Alg. 1 loop, untouched, single thread, on the first
     n_runs runs of the c1 measured-counter workload."""
     import synth
@@ -639,7 +639,7 @@ def cpu_tuning_baseline(n_runs=40):
                       f"counters as the model ({dt:.1f} s, {tests / dt:.0f} tests/s)"}
 
 
-def cpu_fit_baseline(spec, sp, n_sample=250000):
+def cpu_fit_baseline(spec, sp, n_sample=1000000):
     """The oracle's tree fit, untouched, single thread, on the first
     n_sample points of the same fit workload (same counters and keys)."""
     from threadpoolctl import threadpool_limits
