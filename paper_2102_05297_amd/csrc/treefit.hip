@@ -63,6 +63,7 @@ struct FitDev {
   int32_t s[CGS_MAX_COUNTERS];
   uint32_t n_split;
   uint32_t lvl_K[2], lvl_R[2], lvl_NCH[2];
+  uint32_t lvl_Kd[2], lvl_Rd[2]; // open nodes whose histogram is built from rows, their rows
   int32_t depth_sel;
   uint64_t A[CGS_MAX_DEPTH + 1], Blo[CGS_MAX_DEPTH + 1], Bhi[CGS_MAX_DEPTH + 1];
 };
@@ -379,50 +380,110 @@ __global__ void fit_root(const FitDev *__restrict__ fd, uint32_t *__restrict__ n
   }
 }
 
-// Segments of the open nodes of level L (heap order): slot, first row and
-// first chunk of each, and the level's totals.
+// Segments of the open nodes of level L.  Of two open siblings the one with
+// more rows (the right one on a tie) is "derived": its histogram is the
+// parent's minus its sibling's, so only the other ("direct") nodes' rows are
+// histogrammed.  Slots and segments list the direct nodes first, then the
+// derived ones, each group in heap order; der_parent / der_sib hold the
+// parent's slot (level L - 1) and the sibling's slot of every derived slot.
 __global__ __launch_bounds__(kScanThreads) void fit_layout(
     FitDev *__restrict__ fd, int L, const uint8_t *__restrict__ nstate,
     const uint32_t *__restrict__ ncount, uint32_t *__restrict__ open_node,
     uint32_t *__restrict__ seg_start, uint32_t *__restrict__ chunk_start,
-    uint32_t *__restrict__ slot_of, uint32_t kcap) {
+    uint32_t *__restrict__ slot_of, const uint32_t *__restrict__ slot_of_prev,
+    uint32_t *__restrict__ der_parent, uint32_t *__restrict__ der_sib, uint32_t kcap) {
   __shared__ uint64_t scratch[kScanThreads / 64];
   const uint32_t t = threadIdx.x, cnt = 1u << L, base = cnt - 1;
   const uint32_t per = (cnt + kScanThreads - 1) / kScanThreads;
   const uint32_t a = min(cnt, t * per), b = min(cnt, a + per);
-  uint64_t mine = 0, mine_ch = 0; // rows << 16 | open nodes; chunks
-  for (uint32_t k = a; k < b; ++k)
-    if (nstate[base + k]) {
-      mine += ((uint64_t)ncount[base + k] << 16) | 1ull;
-      mine_ch += (ncount[base + k] + kTile - 1) / kTile;
-    }
-  uint64_t tot, tot_ch;
-  const uint64_t before = block_excl_scan<kScanThreads>(mine, scratch, tot);
-  const uint64_t before_ch = block_excl_scan<kScanThreads>(mine_ch, scratch, tot_ch);
-  uint32_t slot = (uint32_t)(before & 0xffffu);
-  uint32_t row = (uint32_t)(before >> 16), ch = (uint32_t)before_ch;
+  auto derived = [&](uint32_t k) { // k: heap index of an open node
+    if (L == 0) return false;
+    const uint32_t sib = (k & 1u) ? k + 1 : k - 1;
+    if (!nstate[sib]) return false;
+    return ncount[k] > ncount[sib] || (ncount[k] == ncount[sib] && !(k & 1u));
+  };
+  // rows << 16 | open nodes, and chunks, of the direct and the derived nodes
+  uint64_t md = 0, mdc = 0, mv = 0, mvc = 0;
   for (uint32_t k = a; k < b; ++k) {
-    if (nstate[base + k] && slot < kcap) {
-      open_node[slot] = base + k;
+    const uint32_t node = base + k;
+    if (!nstate[node]) continue;
+    const uint64_t rows = ((uint64_t)ncount[node] << 16) | 1ull;
+    const uint64_t chunks = (ncount[node] + kTile - 1) / kTile;
+    if (derived(node)) {
+      mv += rows;
+      mvc += chunks;
+    } else {
+      md += rows;
+      mdc += chunks;
+    }
+  }
+  uint64_t td, tdc, tv, tvc;
+  const uint64_t bd = block_excl_scan<kScanThreads>(md, scratch, td);
+  const uint64_t bdc = block_excl_scan<kScanThreads>(mdc, scratch, tdc);
+  const uint64_t bv = block_excl_scan<kScanThreads>(mv, scratch, tv);
+  const uint64_t bvc = block_excl_scan<kScanThreads>(mvc, scratch, tvc);
+  const uint32_t Kd = (uint32_t)(td & 0xffffu), Rd = (uint32_t)(td >> 16);
+  uint32_t sd = (uint32_t)(bd & 0xffffu), rd = (uint32_t)(bd >> 16), cd = (uint32_t)bdc;
+  uint32_t sv = Kd + (uint32_t)(bv & 0xffffu), rv = Rd + (uint32_t)(bv >> 16);
+  uint32_t cv = (uint32_t)tdc + (uint32_t)bvc;
+  for (uint32_t k = a; k < b; ++k) {
+    const uint32_t node = base + k;
+    slot_of[k] = ~0u;
+    if (!nstate[node]) continue;
+    const bool der = derived(node);
+    uint32_t &slot = der ? sv : sd, &row = der ? rv : rd, &ch = der ? cv : cd;
+    if (slot < kcap) {
+      open_node[slot] = node;
       seg_start[slot] = row;
       chunk_start[slot] = ch;
       slot_of[k] = slot;
-      row += ncount[base + k];
-      ch += (ncount[base + k] + kTile - 1) / kTile;
-      ++slot;
-    } else {
-      slot_of[k] = ~0u;
     }
+    row += ncount[node];
+    ch += (ncount[node] + kTile - 1) / kTile;
+    ++slot;
+  }
+  __syncthreads();
+  // a derived slot's parent (level L - 1) and sibling slots
+  for (uint32_t k = a; k < b; ++k) {
+    const uint32_t node = base + k, slot = slot_of[k];
+    if (slot == ~0u || slot < Kd) continue;
+    const uint32_t sib = (node & 1u) ? node + 1 : node - 1;
+    const uint32_t parent = (node - 1) / 2;
+    der_parent[slot - Kd] = slot_of_prev[parent - ((1u << (L - 1)) - 1)];
+    der_sib[slot - Kd] = slot_of[sib - base]; // ~0u only after a slot overflow
   }
   if (t == 0) {
     // at most n_train / min_split nodes hold min_split rows each
-    const uint32_t K = min((uint32_t)(tot & 0xffffu), kcap);
-    if (K < (uint32_t)(tot & 0xffffu)) atomicOr(&fd->err, 4u);
-    seg_start[K] = (uint32_t)(tot >> 16);
-    chunk_start[K] = (uint32_t)tot_ch;
+    const uint32_t Kall = Kd + (uint32_t)(tv & 0xffffu);
+    const uint32_t K = min(Kall, kcap);
+    if (K < Kall) atomicOr(&fd->err, 4u);
+    seg_start[K] = Rd + (uint32_t)(tv >> 16);
+    chunk_start[K] = (uint32_t)(tdc + tvc);
     fd->lvl_K[L & 1] = K;
-    fd->lvl_R[L & 1] = (uint32_t)(tot >> 16);
-    fd->lvl_NCH[L & 1] = (uint32_t)tot_ch;
+    fd->lvl_R[L & 1] = Rd + (uint32_t)(tv >> 16);
+    fd->lvl_NCH[L & 1] = (uint32_t)(tdc + tvc);
+    fd->lvl_Kd[L & 1] = min(Kd, K);
+    fd->lvl_Rd[L & 1] = Rd;
+  }
+}
+
+// Histograms of the derived slots of level L: parent minus sibling (exact
+// int64 sums).  A parent has one derived child, so its entries are read here
+// once and cleared for the level after next.
+__global__ __launch_bounds__(kFitThreads) void fit_hist_derive(
+    const FitDev *__restrict__ fd, int L, int64_t *__restrict__ hist_prev,
+    int64_t *__restrict__ hist, const uint32_t *__restrict__ der_parent,
+    const uint32_t *__restrict__ der_sib, uint32_t kcap) {
+  const uint32_t set = L & 1, K = fd->lvl_K[set], Kd = fd->lvl_Kd[set], E = fd->entries;
+  const uint64_t total = (uint64_t)(K - Kd) * E;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = (uint32_t)(e / E), i = (uint32_t)(e - (uint64_t)v * E);
+    const uint32_t ps = der_parent[v], ss = der_sib[v];
+    if (ps >= kcap || ss >= kcap) continue; // only after a slot overflow (err bit 4)
+    int64_t *hp = hist_prev + (uint64_t)ps * E + i;
+    hist[(uint64_t)(Kd + v) * E + i] = *hp - hist[(uint64_t)ss * E + i];
+    *hp = 0;
   }
 }
 
@@ -441,7 +502,8 @@ __global__ __launch_bounds__(kFitThreads) void fit_hist(const FitDev *__restrict
                                                         const uint32_t *__restrict__ seg_start,
                                                         int64_t *__restrict__ ghist) {
   extern __shared__ int64_t h64[]; // [entries]
-  const uint32_t set = L & 1, K = fd->lvl_K[set], R = fd->lvl_R[set];
+  // the direct nodes' rows come first: [0, Rd), segments 0..Kd-1
+  const uint32_t set = L & 1, K = fd->lvl_Kd[set], R = fd->lvl_Rd[set];
   if (R == 0) return;
   const uint32_t a = (uint32_t)((uint64_t)R * blockIdx.x / gridDim.x);
   const uint32_t b = (uint32_t)((uint64_t)R * (blockIdx.x + 1) / gridDim.x);
@@ -575,7 +637,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
   __shared__ int64_t s_S[CGS_MAX_COUNTERS];
   __shared__ double s_score[kFitThreads / 64];
   __shared__ uint32_t s_k[kFitThreads / 64];
-  __shared__ uint32_t s_split, s_j, s_t, s_nl;
+  __shared__ uint32_t s_split, s_j, s_t, s_nl, s_keep;
   const uint32_t t = threadIdx.x, local = blockIdx.x;
   const uint32_t node = (1u << L) - 1 + local;
   const uint32_t C = fd->C, C1 = C + 1, P = fd->P;
@@ -684,17 +746,22 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
     }
     if (t == 0) {
       const bool deeper = (uint32_t)L + 1 < fd->D;
+      const bool lo = deeper && nl >= fd->min_split, ro = deeper && nr >= fd->min_split;
       nodes[node] = (uint16_t)(j | (th << 8));
       ncount[l] = nl;
       ncount[r] = nr;
-      nstate[l] = (deeper && nl >= fd->min_split) ? 1 : 0;
-      nstate[r] = (deeper && nr >= fd->min_split) ? 1 : 0;
+      nstate[l] = lo ? 1 : 0;
+      nstate[r] = ro ? 1 : 0;
+      s_keep = lo && ro;
       atomicAdd(&fd->n_split, 1u);
     }
   }
-  // the histogram slot is reused by the next level
+  // The slot is used again two levels down.  With both children open, one
+  // child's histogram is derived from this one, which clears it there;
+  // otherwise clear it now.
   __syncthreads();
-  for (uint32_t e = t; e < fd->entries; e += kFitThreads) H[e] = 0;
+  if (!(s_split && s_keep))
+    for (uint32_t e = t; e < fd->entries; e += kFitThreads) H[e] = 0;
 }
 
 // Chunk ch of level L: its segment, first row and row count.
@@ -978,7 +1045,9 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   const uint64_t n_int = ((uint64_t)1 << D) - 1;
   const uint64_t level_cap = D ? ((uint64_t)1 << (D - 1)) : 1;
   const uint64_t kcap = std::max<uint64_t>(1, std::min<uint64_t>(level_cap, n_train / h.min_split));
-  const uint64_t hist_entries = D ? kcap * h.entries : 0;
+  // level histograms, one set per level parity (a derived histogram reads
+  // its parent's from the level above)
+  const uint64_t hist_entries = D ? 2 * kcap * h.entries : 0;
   const uint64_t n_tiles = ((uint64_t)n + kTile - 1) / kTile;
   const uint64_t max_chunks = (uint64_t)n_train / kTile + kcap + 1;
 
@@ -1003,6 +1072,8 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   const size_t o_toff = take(n_tiles * 8);
   const size_t o_ccnt = take(max_chunks * 8);
   const size_t o_cpre = take(max_chunks * 8);
+  const size_t o_dpar = take(kcap * 4);
+  const size_t o_dsib = take(kcap * 4);
   size_t o_open[2], o_seg[2], o_chs[2], o_slot[2];
   for (int s = 0; s < 2; ++s) {
     o_open[s] = take(kcap * 4);
@@ -1026,7 +1097,10 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   *work_out = w;
 
   FitDev *fd = w->fd;
-  int64_t *ghist = reinterpret_cast<int64_t *>(base + o_hist);
+  int64_t *ghist[2] = {reinterpret_cast<int64_t *>(base + o_hist),
+                       reinterpret_cast<int64_t *>(base + o_hist) + hist_entries / 2};
+  uint32_t *der_parent = reinterpret_cast<uint32_t *>(base + o_dpar);
+  uint32_t *der_sib = reinterpret_cast<uint32_t *>(base + o_dsib);
   int64_t *nsum = reinterpret_cast<int64_t *>(base + o_nsum);
   uint32_t *rows[2] = {reinterpret_cast<uint32_t *>(base + o_rows0),
                        reinterpret_cast<uint32_t *>(base + o_rows1)};
@@ -1058,6 +1132,8 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   };
   const uint32_t g_rows = grid_for(n_train), g_test = grid_for(n_test), g_pts = grid_for(n);
   const uint32_t g_chunks = (uint32_t)std::min<uint64_t>(4 * kFitGrid, max_chunks);
+  const uint32_t g_derive =
+      (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kFitGrid, (kcap / 2 * h.entries + 255) / 256));
 
   auto kh = P <= 8 ? fit_hist<8> : P <= 16 ? fit_hist<16> : fit_hist<32>;
   if (e == hipSuccess) e = allow_lds(kh, hist_lds);
@@ -1093,17 +1169,22 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
     if (D > 0)
       fit_layout<<<1, kScanThreads, 0, stream>>>(fd, 0, nstate, ncount, open_node[0],
                                                 seg_start[0], chunk_start[0], slot_of[0],
-                                                (uint32_t)kcap);
+                                                slot_of[1], der_parent, der_sib, (uint32_t)kcap);
     for (uint32_t L = 0; L < D; ++L) {
       const int s = L & 1, s1 = s ^ 1;
-      kh<<<g_rows, kFitThreads, hist_lds, stream>>>(fd, (int)L, rows[s], seg_start[s], ghist);
-      fit_split<<<1u << L, kFitThreads, split_lds, stream>>>(fd, (int)L, ghist, slot_of[s],
+      kh<<<g_rows, kFitThreads, hist_lds, stream>>>(fd, (int)L, rows[s], seg_start[s], ghist[s]);
+      if (L > 0)
+        fit_hist_derive<<<g_derive, kFitThreads, 0, stream>>>(fd, (int)L, ghist[s1], ghist[s],
+                                                              der_parent, der_sib,
+                                                              (uint32_t)kcap);
+      fit_split<<<1u << L, kFitThreads, split_lds, stream>>>(fd, (int)L, ghist[s], slot_of[s],
                                                              cap_entries, ncount, nsum,
                                                              w->nmean, nstate, w->nodes);
       if (L + 1 < D) {
         fit_layout<<<1, kScanThreads, 0, stream>>>(fd, (int)L + 1, nstate, ncount,
                                                   open_node[s1], seg_start[s1], chunk_start[s1],
-                                                  slot_of[s1], (uint32_t)kcap);
+                                                  slot_of[s1], slot_of[s], der_parent, der_sib,
+                                                  (uint32_t)kcap);
         fit_pcount<<<g_chunks, kFitThreads, 0, stream>>>(fd, (int)L, rows[s], seg_start[s],
                                                          chunk_start[s], open_node[s], nstate,
                                                          w->nodes, chunk_cnt);
