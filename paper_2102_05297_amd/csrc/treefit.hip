@@ -875,13 +875,17 @@ __global__ __launch_bounds__(kFitThreads) void fit_partition(
 // one thread per row walks the grown tree (node table in LDS) and records
 // the node it reaches at every depth; then thread t handles counter t % C of
 // rows t / C, t / C + 256 / C, ... and adds |e| and e^2 at every depth, the
-// C lanes of one row reading one node's values together.
-__global__ __launch_bounds__(kFitThreads) void fit_test(FitDev *__restrict__ fd,
+// C lanes of one row reading one node's values together.  Each workgroup
+// writes its sums to part[q * gridDim.x + blockIdx.x], q = 3 d + (0: sum |e|,
+// 1: sum of the low 32 bits of e^2, 2: sum of the high 32 bits).
+__global__ __launch_bounds__(kFitThreads) void fit_test(const FitDev *__restrict__ fd,
                                                         const uint32_t *__restrict__ test_rows,
                                                         const uint16_t *__restrict__ nodes,
-                                                        const int32_t *__restrict__ nmean) {
+                                                        const int32_t *__restrict__ nmean,
+                                                        uint64_t *__restrict__ part) {
   extern __shared__ uint32_t lds[]; // [kTile][W] rows, [kTile][ND] path, nodes
   constexpr int ND = CGS_MAX_DEPTH + 1;
+  __shared__ uint64_t s_red[kFitThreads / 64][3 * ND];
   const uint32_t t = threadIdx.x, n = fd->n_test, C = fd->C, PW = fd->PW, W = fd->W;
   const uint32_t D = fd->D, n_int = (1u << D) - 1;
   uint32_t *rl = lds;
@@ -901,36 +905,45 @@ __global__ __launch_bounds__(kFitThreads) void fit_test(FitDev *__restrict__ fd,
     const uint32_t *src = test_rows + (uint64_t)first * W;
     for (uint32_t k = t; k < nr * W; k += kFitThreads) rl[k] = src[k];
     __syncthreads();
-    if (t < nr) {
+    // every path entry holds a node of the grown tree (depths past D repeat
+    // the leaf, rows past the tile the root), so phase two loads without
+    // conditions; kFitThreads == kTile, one path per thread
+    {
       const uint32_t *row = rl + t * W;
       uint32_t node = 0;
       path[t * ND] = 0;
       for (uint32_t d = 0; d < D; ++d) {
-        const uint16_t nd = tree[node];
-        node = 2 * node + (row_digit(row, nd & 255u) <= (uint32_t)(nd >> 8) ? 1u : 2u);
+        if (t < nr) {
+          const uint16_t nd = tree[node];
+          node = 2 * node + (row_digit(row, nd & 255u) <= (uint32_t)(nd >> 8) ? 1u : 2u);
+        }
         path[t * ND + d + 1] = node * C;
       }
+      for (uint32_t d = D + 1; d < (uint32_t)ND; ++d) path[t * ND + d] = node * C;
     }
     __syncthreads();
     if (active) {
       // four rows per round: their node-value loads are in flight together
       for (uint32_t r = rs; r < nr; r += 4 * RP) {
         int32_t m[4][ND], q[4];
+        bool ok[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const uint32_t ru = r + u * RP;
-          q[u] = ru < nr ? (int32_t)rl[ru * W + PW + c] : 0;
-          const uint32_t *pr = path + ru * ND;
+          ok[u] = ru < nr;
+          const uint32_t rr = ok[u] ? ru : r; // r < nr
+          q[u] = (int32_t)rl[rr * W + PW + c];
+          const uint32_t *pr = path + rr * ND;
 #pragma unroll
-          for (int d = 0; d < ND; ++d) m[u][d] = (ru < nr && (uint32_t)d <= D) ? nmean[pr[d] + c] : 0;
+          for (int d = 0; d < ND; ++d) m[u][d] = nmean[pr[d] + c];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
 #pragma unroll
           for (int d = 0; d < ND; ++d) {
-            // |m|, |q| <= 2^22: |e| < 2^24 and e^2 < 2^48; rows past the
-            // tile contribute m = q = 0
-            const int32_t e = m[u][d] - q[u];
+            // |m|, |q| <= 2^22: |e| < 2^24 and e^2 < 2^48; repeated rows
+            // count zero, depths past D are never read
+            const int32_t e = ok[u] ? m[u][d] - q[u] : 0;
             const uint32_t ae = (uint32_t)(e < 0 ? -e : e);
             A[d] += ae;
             B[d] += (uint64_t)ae * ae;
@@ -941,21 +954,44 @@ __global__ __launch_bounds__(kFitThreads) void fit_test(FitDev *__restrict__ fd,
   }
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    if ((uint32_t)d <= D) {
-      const uint64_t a = wave_sum(A[d]);
-      const uint64_t l = wave_sum(B[d] & 0xffffffffull), h = wave_sum(B[d] >> 32);
-      if ((t & 63u) == 0) {
-        if (a) atomicAdd(reinterpret_cast<unsigned long long *>(&fd->A[d]), a);
-        if (l) atomicAdd(reinterpret_cast<unsigned long long *>(&fd->Blo[d]), l);
-        if (h) atomicAdd(reinterpret_cast<unsigned long long *>(&fd->Bhi[d]), h);
-      }
+    const uint64_t a = wave_sum(A[d]);
+    const uint64_t l = wave_sum(B[d] & 0xffffffffull), h = wave_sum(B[d] >> 32);
+    if ((t & 63u) == 0) {
+      s_red[t >> 6][3 * d] = a;
+      s_red[t >> 6][3 * d + 1] = l;
+      s_red[t >> 6][3 * d + 2] = h;
     }
+  }
+  __syncthreads();
+  if (t < 3 * ND) {
+    uint64_t s = 0;
+    for (int w = 0; w < kFitThreads / 64; ++w) s += s_red[w][t];
+    part[(uint64_t)t * gridDim.x + blockIdx.x] = s;
   }
 }
 
-// Lowest (sum|e|, sum e^2, depth); sum e^2 = Bhi 2^32 + Blo.
-__global__ void fit_select(FitDev *__restrict__ fd) {
-  if (threadIdx.x != 0) return;
+// Sums of the test workgroups' partials (one wave per quantity, exact), then
+// the lowest (sum|e|, sum e^2, depth); sum e^2 = Bhi 2^32 + Blo.
+__global__ __launch_bounds__(kScanThreads) void fit_select(FitDev *__restrict__ fd,
+                                                           const uint64_t *__restrict__ part,
+                                                           uint32_t G) {
+  constexpr int ND = CGS_MAX_DEPTH + 1;
+  const uint32_t t = threadIdx.x, lane = t & 63u;
+  for (uint32_t q = t >> 6; q < 3 * ND; q += kScanThreads / 64) {
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kFitGrid / 64; ++i) { // G <= kFitGrid: all loads in flight
+      const uint32_t g = lane + 64 * i;
+      if (g < G) s += part[(uint64_t)q * G + g];
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+      const uint32_t d = q / 3, k = q - 3 * d;
+      (k == 0 ? fd->A : k == 1 ? fd->Blo : fd->Bhi)[d] = s;
+    }
+  }
+  __syncthreads();
+  if (t != 0) return;
   uint32_t best = 0;
   auto hi = [&](uint32_t d) { return fd->Bhi[d] + (fd->Blo[d] >> 32); };
   auto lo = [&](uint32_t d) { return fd->Blo[d] & 0xffffffffull; };
@@ -1072,6 +1108,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   const size_t o_toff = take(n_tiles * 8);
   const size_t o_ccnt = take(max_chunks * 8);
   const size_t o_cpre = take(max_chunks * 8);
+  const size_t o_part = take((size_t)3 * (CGS_MAX_DEPTH + 1) * kFitGrid * 8);
   const size_t o_dpar = take(kcap * 4);
   const size_t o_dsib = take(kcap * 4);
   size_t o_open[2], o_seg[2], o_chs[2], o_slot[2];
@@ -1100,6 +1137,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   int64_t *ghist[2] = {reinterpret_cast<int64_t *>(base + o_hist),
                        reinterpret_cast<int64_t *>(base + o_hist) + hist_entries / 2};
   uint32_t *der_parent = reinterpret_cast<uint32_t *>(base + o_dpar);
+  uint64_t *test_part = reinterpret_cast<uint64_t *>(base + o_part);
   uint32_t *der_sib = reinterpret_cast<uint32_t *>(base + o_dsib);
   int64_t *nsum = reinterpret_cast<int64_t *>(base + o_nsum);
   uint32_t *rows[2] = {reinterpret_cast<uint32_t *>(base + o_rows0),
@@ -1194,8 +1232,9 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
             chunk_pre, seg_start[s1], slot_of[s1], nstate, w->nodes);
       }
     }
-    fit_test<<<g_test, kFitThreads, test_lds, stream>>>(fd, test_rows, w->nodes, w->nmean);
-    fit_select<<<1, 64, 0, stream>>>(fd);
+    fit_test<<<g_test, kFitThreads, test_lds, stream>>>(fd, test_rows, w->nodes, w->nmean,
+                                                        test_part);
+    fit_select<<<1, kScanThreads, 0, stream>>>(fd, test_part, g_test);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipEventRecord(ev[1], stream);
