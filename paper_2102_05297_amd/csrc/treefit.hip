@@ -75,7 +75,7 @@ constexpr uint32_t kFitGrid = 1024;       // workgroups of the grid-stride passe
 constexpr uint32_t kTile = 256;           // rows per chunk / staged tile
 constexpr uint16_t kAlwaysLeftNode = (uint16_t)(255u << 8);
 constexpr uint32_t kScanThreads = 1024;
-constexpr int kHistUnroll = 1;            // rows per round of the histogram loop
+constexpr uint32_t kHistGrid = 1024;      // workgroups of the histogram pass
 
 __device__ __forceinline__ uint64_t split_key(uint64_t key, uint64_t i) {
   return (key & 0xFFFFFFFF00000000ull) | i;
@@ -386,15 +386,15 @@ __global__ void fit_root(const FitDev *__restrict__ fd, uint32_t *__restrict__ n
 // histogrammed.  Slots and segments list the direct nodes first, then the
 // derived ones, each group in heap order; der_parent / der_sib hold the
 // parent's slot (level L - 1) and the sibling's slot of every derived slot.
-__global__ __launch_bounds__(kScanThreads) void fit_layout(
+__global__ __launch_bounds__(kFitThreads) void fit_layout(
     FitDev *__restrict__ fd, int L, const uint8_t *__restrict__ nstate,
     const uint32_t *__restrict__ ncount, uint32_t *__restrict__ open_node,
     uint32_t *__restrict__ seg_start, uint32_t *__restrict__ chunk_start,
     uint32_t *__restrict__ slot_of, const uint32_t *__restrict__ slot_of_prev,
     uint32_t *__restrict__ der_parent, uint32_t *__restrict__ der_sib, uint32_t kcap) {
-  __shared__ uint64_t scratch[kScanThreads / 64];
+  __shared__ uint64_t scratch[kFitThreads / 64];
   const uint32_t t = threadIdx.x, cnt = 1u << L, base = cnt - 1;
-  const uint32_t per = (cnt + kScanThreads - 1) / kScanThreads;
+  const uint32_t per = (cnt + kFitThreads - 1) / kFitThreads;
   const uint32_t a = min(cnt, t * per), b = min(cnt, a + per);
   auto derived = [&](uint32_t k) { // k: heap index of an open node
     if (L == 0) return false;
@@ -418,10 +418,10 @@ __global__ __launch_bounds__(kScanThreads) void fit_layout(
     }
   }
   uint64_t td, tdc, tv, tvc;
-  const uint64_t bd = block_excl_scan<kScanThreads>(md, scratch, td);
-  const uint64_t bdc = block_excl_scan<kScanThreads>(mdc, scratch, tdc);
-  const uint64_t bv = block_excl_scan<kScanThreads>(mv, scratch, tv);
-  const uint64_t bvc = block_excl_scan<kScanThreads>(mvc, scratch, tvc);
+  const uint64_t bd = block_excl_scan<kFitThreads>(md, scratch, td);
+  const uint64_t bdc = block_excl_scan<kFitThreads>(mdc, scratch, tdc);
+  const uint64_t bv = block_excl_scan<kFitThreads>(mv, scratch, tv);
+  const uint64_t bvc = block_excl_scan<kFitThreads>(mvc, scratch, tvc);
   const uint32_t Kd = (uint32_t)(td & 0xffffu), Rd = (uint32_t)(td >> 16);
   uint32_t sd = (uint32_t)(bd & 0xffffu), rd = (uint32_t)(bd >> 16), cd = (uint32_t)bdc;
   uint32_t sv = Kd + (uint32_t)(bv & 0xffffu), rv = Rd + (uint32_t)(bv >> 16);
@@ -431,16 +431,23 @@ __global__ __launch_bounds__(kScanThreads) void fit_layout(
     slot_of[k] = ~0u;
     if (!nstate[node]) continue;
     const bool der = derived(node);
-    uint32_t &slot = der ? sv : sd, &row = der ? rv : rd, &ch = der ? cv : cd;
+    const uint32_t slot = der ? sv : sd, row = der ? rv : rd, ch = der ? cv : cd;
     if (slot < kcap) {
       open_node[slot] = node;
       seg_start[slot] = row;
       chunk_start[slot] = ch;
       slot_of[k] = slot;
     }
-    row += ncount[node];
-    ch += (ncount[node] + kTile - 1) / kTile;
-    ++slot;
+    const uint32_t nr = ncount[node], nch = (nr + kTile - 1) / kTile;
+    if (der) {
+      ++sv;
+      rv += nr;
+      cv += nch;
+    } else {
+      ++sd;
+      rd += nr;
+      cd += nch;
+    }
   }
   __syncthreads();
   // a derived slot's parent (level L - 1) and sibling slots
@@ -492,9 +499,11 @@ __global__ __launch_bounds__(kFitThreads) void fit_hist_derive(
 // part, row group g of G = 256 / (C + 1) groups takes a contiguous run of
 // rows and lane (g, c) handles column c of them (column C is the count).
 // Rows arrive in configuration order, so most parameters keep their digit
-// over long runs: each lane keeps, per parameter, the digit of the current
-// run and its sum in registers and adds the sum to the workgroup's int64
-// LDS histogram only when the digit changes.  At the end of a node's part the
+// over long runs and consecutive rows differ in few digits: each lane keeps
+// the running sum of its column and, per parameter, the sum at which the
+// current run of equal digits began; a word compare with the previous row
+// finds the parameters whose digit changed, and only those add their run's
+// sum to the workgroup's int64 LDS histogram.  At the end of a node's part the
 // workgroup adds its LDS histogram to the node's histogram in device memory.
 template <int MAXP>
 __global__ __launch_bounds__(kFitThreads) void fit_hist(const FitDev *__restrict__ fd, int L,
@@ -528,57 +537,53 @@ __global__ __launch_bounds__(kFitThreads) void fit_hist(const FitDev *__restrict
       const uint32_t m = end - pos;
       const uint32_t r0 = pos + (uint32_t)((uint64_t)m * g / G);
       const uint32_t r1 = pos + (uint32_t)((uint64_t)m * (g + 1) / G);
-      uint32_t cur[MAXP];
-      int64_t acc[MAXP];
+      constexpr int NW = (MAXP + 3) / 4;
+      // S: running sum of column c over the lane's rows; st[j]: S where
+      // parameter j's current run of equal digits began.  A run's sum
+      // S - st[j] goes to the LDS bin of its digit when the digit changes.
+      // prev holds the previous row's packed digits (0xff bytes: no run yet).
+      uint32_t prev[NW];
+      int64_t st[MAXP];
 #pragma unroll
-      for (int j = 0; j < MAXP; ++j) {
-        cur[j] = 0xffu;
-        acc[j] = 0;
-      }
-      constexpr int NW = (MAXP + 3) / 4, U = kHistUnroll;
-      auto add_row = [&](const uint32_t *dw, int64_t q) {
+      for (int w = 0; w < NW; ++w) prev[w] = 0xffffffffu;
 #pragma unroll
-        for (int j = 0; j < MAXP; ++j) {
-          if (j < (int)P) {
-            const uint32_t v = (dw[j >> 2] >> (8 * (j & 3))) & 255u;
-            if (v != cur[j]) {
-              if (cur[j] != 0xffu)
-                atomicAdd(reinterpret_cast<unsigned long long *>(&h64[roffc[j] + cur[j] * C1]),
-                          (unsigned long long)acc[j]);
-              cur[j] = v;
-              acc[j] = 0;
+      for (int j = 0; j < MAXP; ++j) st[j] = 0;
+      int64_t S = 0;
+      auto process = [&](const uint32_t (&dw)[NW], int64_t q) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t x = dw[w] ^ prev[w];
+          if (w < (int)PW && x) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int j = 4 * w + k;
+              if (j < (int)P && ((x >> (8 * k)) & 255u)) {
+                const uint32_t old = (prev[w] >> (8 * k)) & 255u;
+                if (old != 0xffu)
+                  atomicAdd(reinterpret_cast<unsigned long long *>(&h64[roffc[j] + old * C1]),
+                            (unsigned long long)(S - st[j]));
+                st[j] = S;
+              }
             }
-            acc[j] += q;
+            prev[w] = dw[w];
           }
         }
+        S += q;
       };
-      uint32_t r = r0;
-      // U rows per round: their loads all issue before the first is used
-      for (; r + U <= r1; r += U) {
-        uint32_t dw[U][NW];
-        int64_t q[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint32_t *row = rows + (uint64_t)(r + u) * W;
-#pragma unroll
-          for (int w = 0; w < NW; ++w) dw[u][w] = (w < (int)PW) ? row[w] : 0u;
-          q[u] = c < C ? (int64_t)(int32_t)row[PW + c] : 1;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) add_row(dw[u], q[u]);
-      }
-      for (; r < r1; ++r) {
+      for (uint32_t r = r0; r < r1; ++r) {
         const uint32_t *row = rows + (uint64_t)r * W;
         uint32_t dw[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) dw[w] = (w < (int)PW) ? row[w] : 0u;
-        add_row(dw, c < C ? (int64_t)(int32_t)row[PW + c] : 1);
+        process(dw, c < C ? (int64_t)(int32_t)row[PW + c] : 1);
       }
 #pragma unroll
-      for (int j = 0; j < MAXP; ++j)
-        if (j < (int)P && cur[j] != 0xffu)
-          atomicAdd(reinterpret_cast<unsigned long long *>(&h64[roffc[j] + cur[j] * C1]),
-                    (unsigned long long)acc[j]);
+      for (int j = 0; j < MAXP; ++j) {
+        const uint32_t old = (prev[j >> 2] >> (8 * (j & 3))) & 255u;
+        if (j < (int)P && old != 0xffu)
+          atomicAdd(reinterpret_cast<unsigned long long *>(&h64[roffc[j] + old * C1]),
+                    (unsigned long long)(S - st[j]));
+      }
     }
     __syncthreads();
     int64_t *H = ghist + (uint64_t)slot * E;
@@ -1169,6 +1174,8 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
     return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kFitGrid, (items + kTile - 1) / kTile));
   };
   const uint32_t g_rows = grid_for(n_train), g_test = grid_for(n_test), g_pts = grid_for(n);
+  const uint32_t g_hist =
+      (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kHistGrid, ((uint64_t)n_train + 63) / 64));
   const uint32_t g_chunks = (uint32_t)std::min<uint64_t>(4 * kFitGrid, max_chunks);
   const uint32_t g_derive =
       (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kFitGrid, (kcap / 2 * h.entries + 255) / 256));
@@ -1205,12 +1212,12 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
     fit_root_sums<<<g_rows, kFitThreads, 0, stream>>>(fd, rows[0], nsum);
     fit_root<<<1, 64, 0, stream>>>(fd, ncount, nsum, w->nmean, nstate);
     if (D > 0)
-      fit_layout<<<1, kScanThreads, 0, stream>>>(fd, 0, nstate, ncount, open_node[0],
+      fit_layout<<<1, kFitThreads, 0, stream>>>(fd, 0, nstate, ncount, open_node[0],
                                                 seg_start[0], chunk_start[0], slot_of[0],
                                                 slot_of[1], der_parent, der_sib, (uint32_t)kcap);
     for (uint32_t L = 0; L < D; ++L) {
       const int s = L & 1, s1 = s ^ 1;
-      kh<<<g_rows, kFitThreads, hist_lds, stream>>>(fd, (int)L, rows[s], seg_start[s], ghist[s]);
+      kh<<<g_hist, kFitThreads, hist_lds, stream>>>(fd, (int)L, rows[s], seg_start[s], ghist[s]);
       if (L > 0)
         fit_hist_derive<<<g_derive, kFitThreads, 0, stream>>>(fd, (int)L, ghist[s1], ghist[s],
                                                               der_parent, der_sib,
@@ -1219,7 +1226,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
                                                              cap_entries, ncount, nsum,
                                                              w->nmean, nstate, w->nodes);
       if (L + 1 < D) {
-        fit_layout<<<1, kScanThreads, 0, stream>>>(fd, (int)L + 1, nstate, ncount,
+        fit_layout<<<1, kFitThreads, 0, stream>>>(fd, (int)L + 1, nstate, ncount,
                                                   open_node[s1], seg_start[s1], chunk_start[s1],
                                                   slot_of[s1], slot_of[s], der_parent, der_sib,
                                                   (uint32_t)kcap);
