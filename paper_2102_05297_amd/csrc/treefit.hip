@@ -85,8 +85,41 @@ __device__ __forceinline__ uint32_t row_digit(const uint32_t *row, uint32_t j) {
   return (row[j >> 2] >> (8u * (j & 3u))) & 255u;
 }
 
+// Words in flight per thread in the staging copies below: a plain loop would
+// wait for each load before its LDS store (one memory latency per word).
+constexpr int kStageBatch = 16;
+
+// lds[k] = src[k] for k < n, by the whole workgroup (kFitThreads threads).
+template <typename T>
+__device__ __forceinline__ void stage_words(const T *__restrict__ src, uint32_t n, T *lds) {
+  constexpr uint32_t kSpan = kStageBatch * kFitThreads;
+  const uint32_t full = n / kSpan * kSpan; // whole batches need no bounds checks
+  uint32_t k0 = threadIdx.x;
+  for (; k0 < full; k0 += kSpan) {
+    T v[kStageBatch];
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b) v[b] = src[k0 + b * kFitThreads];
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b) lds[k0 + b * kFitThreads] = v[b];
+  }
+  if (k0 < n) {
+    T v[kStageBatch];
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b) {
+      const uint32_t k = k0 + b * kFitThreads;
+      v[b] = k < n ? src[k] : T(0);
+    }
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b) {
+      const uint32_t k = k0 + b * kFitThreads;
+      if (k < n) lds[k] = v[b];
+    }
+  }
+}
+
 // Row `first + r` of `dst` = staged row src[r], for r < count; rows at or
-// past `cap` (the buffer's size in rows) are not written.
+// past `cap` are dropped.  Words go out in batches so their LDS reads
+// overlap.
 __device__ __forceinline__ void copy_rows_out(const uint32_t *lds, const uint32_t *src,
                                               uint32_t count, uint32_t W, FastDiv divW,
                                               uint32_t *__restrict__ dst, uint32_t first,
@@ -94,9 +127,19 @@ __device__ __forceinline__ void copy_rows_out(const uint32_t *lds, const uint32_
   if (first >= cap) return;
   const uint32_t words = min(count, cap - first) * W;
   uint32_t *out = dst + (uint64_t)first * W;
-  for (uint32_t k = threadIdx.x; k < words; k += blockDim.x) {
-    const uint32_t r = fastdiv(k, divW);
-    out[k] = lds[src[r] * W + (k - r * W)];
+  for (uint32_t k0 = threadIdx.x; k0 < words; k0 += kStageBatch * kFitThreads) {
+    uint32_t v[kStageBatch];
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b) {
+      const uint32_t k = k0 + b * kFitThreads;
+      const uint32_t r = fastdiv(min(k, words - 1), divW);
+      v[b] = lds[src[r] * W + (min(k, words - 1) - r * W)];
+    }
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b) {
+      const uint32_t k = k0 + b * kFitThreads;
+      if (k < words) out[k] = v[b];
+    }
   }
 }
 
@@ -292,9 +335,21 @@ __global__ __launch_bounds__(kFitThreads) void fit_scatter(
     const uint32_t first = tile * kTile, nr = min(kTile, n - first);
     __syncthreads();
     const float *ysrc = Y + (uint64_t)first * C;
-    for (uint32_t k = t; k < nr * C; k += kFitThreads) {
-      const uint32_t r = fastdiv(k, fd->divC);
-      ytile[r * Cp + (k - r * C)] = ysrc[k];
+    for (uint32_t k0 = t; k0 < nr * C; k0 += kStageBatch * kFitThreads) {
+      float v[kStageBatch]; // all loads in flight before the first LDS store
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b) {
+        const uint32_t k = k0 + b * kFitThreads;
+        v[b] = k < nr * C ? ysrc[k] : 0.0f;
+      }
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b) {
+        const uint32_t k = k0 + b * kFitThreads;
+        if (k < nr * C) {
+          const uint32_t r = fastdiv(k, fd->divC);
+          ytile[r * Cp + (k - r * C)] = v[b];
+        }
+      }
     }
     __syncthreads();
     const bool live = t < nr;
@@ -391,7 +446,8 @@ __global__ __launch_bounds__(kFitThreads) void fit_layout(
     const uint32_t *__restrict__ ncount, uint32_t *__restrict__ open_node,
     uint32_t *__restrict__ seg_start, uint32_t *__restrict__ chunk_start,
     uint32_t *__restrict__ slot_of, const uint32_t *__restrict__ slot_of_prev,
-    uint32_t *__restrict__ der_parent, uint32_t *__restrict__ der_sib, uint32_t kcap) {
+    uint32_t *__restrict__ der_parent, uint32_t *__restrict__ der_sib,
+    uint4 *__restrict__ slot_info_prev, uint32_t kcap) {
   __shared__ uint64_t scratch[kFitThreads / 64];
   const uint32_t t = threadIdx.x, cnt = 1u << L, base = cnt - 1;
   const uint32_t per = (cnt + kFitThreads - 1) / kFitThreads;
@@ -450,13 +506,20 @@ __global__ __launch_bounds__(kFitThreads) void fit_layout(
     }
   }
   __syncthreads();
-  // a derived slot's parent (level L - 1) and sibling slots
+  // the parent's (level L - 1) record gets each open child's first row; a
+  // derived slot's parent and sibling slots
   for (uint32_t k = a; k < b; ++k) {
     const uint32_t node = base + k, slot = slot_of[k];
-    if (slot == ~0u || slot < Kd) continue;
-    const uint32_t sib = (node & 1u) ? node + 1 : node - 1;
+    if (slot == ~0u || L == 0) continue;
     const uint32_t parent = (node - 1) / 2;
-    der_parent[slot - Kd] = slot_of_prev[parent - ((1u << (L - 1)) - 1)];
+    const uint32_t pslot = slot_of_prev[parent - ((1u << (L - 1)) - 1)];
+    if (pslot < kcap) {
+      if (node & 1u) slot_info_prev[pslot].y = seg_start[slot];
+      else slot_info_prev[pslot].z = seg_start[slot];
+    }
+    if (slot < Kd) continue;
+    const uint32_t sib = (node & 1u) ? node + 1 : node - 1;
+    der_parent[slot - Kd] = pslot;
     der_sib[slot - Kd] = slot_of[sib - base]; // ~0u only after a slot overflow
   }
   if (t == 0) {
@@ -637,7 +700,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
     FitDev *__restrict__ fd, int L, int64_t *__restrict__ ghist,
     const uint32_t *__restrict__ slot_of, uint32_t cap_entries, uint32_t *__restrict__ ncount,
     int64_t *__restrict__ nsum, int32_t *__restrict__ nmean, uint8_t *__restrict__ nstate,
-    uint16_t *__restrict__ nodes) {
+    uint16_t *__restrict__ nodes, uint4 *__restrict__ slot_info) {
   extern __shared__ int64_t ps[]; // prefix sums over digits of one parameter group
   __shared__ int64_t s_S[CGS_MAX_COUNTERS];
   __shared__ double s_score[kFitThreads / 64];
@@ -650,7 +713,8 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
     inherit_children(node, C, ncount, nsum, nmean, nstate, nodes);
     return;
   }
-  int64_t *H = ghist + (uint64_t)slot_of[local] * fd->entries;
+  const uint32_t slot = slot_of[local];
+  int64_t *H = ghist + (uint64_t)slot * fd->entries;
   const uint32_t n = ncount[node], min_leaf = fd->min_leaf;
   for (uint32_t c = t; c < C; c += kFitThreads) s_S[c] = nsum[(uint64_t)node * C + c];
 
@@ -737,6 +801,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
   __syncthreads();
   if (!s_split) {
     inherit_children(node, C, ncount, nsum, nmean, nstate, nodes);
+    if (t == 0) slot_info[slot].x = kAlwaysLeftNode; // no child is searched
   } else {
     const uint32_t j = s_j, th = s_t, nl = s_nl, nr = n - nl;
     const uint32_t l = 2 * node + 1, r = l + 1;
@@ -757,6 +822,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
       ncount[r] = nr;
       nstate[l] = lo ? 1 : 0;
       nstate[r] = ro ? 1 : 0;
+      slot_info[slot].x = (j | (th << 8)) | (lo ? 1u << 16 : 0u) | (ro ? 1u << 17 : 0u);
       s_keep = lo && ro;
       atomicAdd(&fd->n_split, 1u);
     }
@@ -769,36 +835,45 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
     for (uint32_t e = t; e < fd->entries; e += kFitThreads) H[e] = 0;
 }
 
-// Chunk ch of level L: its segment, first row and row count.
+// Chunk ch of level L: its segment, first row, row count and the segment's
+// first chunk, from the level's segment and chunk starts staged in LDS.
 struct ChunkRef {
-  uint32_t slot, first, nr;
+  uint32_t slot, first, nr, first_chunk;
 };
-__device__ __forceinline__ ChunkRef chunk_ref(uint32_t ch, const uint32_t *chunk_start,
-                                              const uint32_t *seg_start, uint32_t K) {
+__device__ __forceinline__ ChunkRef chunk_ref(uint32_t ch, const uint32_t *cs, const uint32_t *ss,
+                                              uint32_t K) {
   ChunkRef c;
-  c.slot = last_at_or_below(chunk_start, K, ch);
-  c.first = seg_start[c.slot] + (ch - chunk_start[c.slot]) * kTile;
-  c.nr = min(kTile, seg_start[c.slot + 1] - c.first);
+  c.slot = last_at_or_below(cs, K, ch);
+  c.first_chunk = cs[c.slot];
+  c.first = ss[c.slot] + (ch - c.first_chunk) * kTile;
+  c.nr = min(kTile, ss[c.slot + 1] - c.first);
   return c;
 }
 
-// The split a chunk's rows follow: parameter, threshold, and whether each
-// child is searched at the next level (rows of the others are dropped).
-struct ChunkSplit {
-  uint32_t j, thr, lc, rc;
+// seg_start[0..K] and chunk_start[0..K] of a level into LDS.
+__device__ __forceinline__ void stage_starts(const uint32_t *__restrict__ seg_start,
+                                             const uint32_t *__restrict__ chunk_start, uint32_t K,
+                                             uint32_t *ss, uint32_t *cs) {
+  for (uint32_t i = threadIdx.x; i <= K; i += blockDim.x) {
+    ss[i] = seg_start[i];
+    cs[i] = chunk_start[i];
+  }
+  __syncthreads();
+}
+
+// The split a slot's rows follow (slot_info[slot].x): parameter, threshold,
+// and whether each child is searched at the next level (rows of the others
+// are dropped).
+struct SlotSplit {
+  uint32_t j, thr;
   bool lopen, ropen;
 };
-__device__ __forceinline__ ChunkSplit chunk_split(uint32_t slot, const uint32_t *open_node,
-                                                  const uint16_t *nodes, const uint8_t *nstate) {
-  ChunkSplit s;
-  const uint32_t node = open_node[slot];
-  const uint16_t nd = nodes[node];
-  s.j = nd & 255u;
-  s.thr = nd >> 8;
-  s.lc = 2 * node + 1;
-  s.rc = s.lc + 1;
-  s.lopen = nstate[s.lc] != 0;
-  s.ropen = nstate[s.rc] != 0;
+__device__ __forceinline__ SlotSplit slot_split(uint32_t x) {
+  SlotSplit s;
+  s.j = x & 255u;
+  s.thr = (x >> 8) & 255u;
+  s.lopen = (x >> 16) & 1u;
+  s.ropen = (x >> 17) & 1u;
   return s;
 }
 
@@ -807,21 +882,27 @@ __device__ __forceinline__ ChunkSplit chunk_split(uint32_t slot, const uint32_t 
 __global__ __launch_bounds__(kFitThreads) void fit_pcount(
     const FitDev *__restrict__ fd, int L, const uint32_t *__restrict__ rows_in,
     const uint32_t *__restrict__ seg_start, const uint32_t *__restrict__ chunk_start,
-    const uint32_t *__restrict__ open_node, const uint8_t *__restrict__ nstate,
-    const uint16_t *__restrict__ nodes, uint64_t *__restrict__ cnt) {
+    const uint4 *__restrict__ slot_info, uint64_t *__restrict__ cnt,
+    uint32_t *__restrict__ chunk_slot) {
+  extern __shared__ uint32_t starts[]; // [K + 1] segment starts, [K + 1] chunk starts
   __shared__ uint64_t scratch[kFitThreads / 64];
   const uint32_t set = L & 1, K = fd->lvl_K[set], NCH = fd->lvl_NCH[set], W = fd->W;
   const uint32_t t = threadIdx.x;
+  uint32_t *ss = starts, *cs = starts + K + 1;
+  stage_starts(seg_start, chunk_start, K, ss, cs);
   for (uint32_t ch = blockIdx.x; ch < NCH; ch += gridDim.x) {
-    const ChunkRef c = chunk_ref(ch, chunk_start, seg_start, K);
-    const ChunkSplit s = chunk_split(c.slot, open_node, nodes, nstate);
+    const ChunkRef c = chunk_ref(ch, cs, ss, K);
+    const SlotSplit s = slot_split(slot_info[c.slot].x);
     uint64_t f = 0;
     if (t < c.nr) {
       const bool left = row_digit(rows_in + (uint64_t)(c.first + t) * W, s.j) <= s.thr;
       if (left ? s.lopen : s.ropen) f = left ? 1ull : (1ull << 32);
     }
     const uint64_t sum = block_sum<kFitThreads>(f, scratch);
-    if (t == 0) cnt[ch] = sum;
+    if (t == 0) {
+      cnt[ch] = sum;
+      chunk_slot[ch] = c.slot;
+    }
   }
 }
 
@@ -830,22 +911,26 @@ __global__ __launch_bounds__(kFitThreads) void fit_pcount(
 __global__ __launch_bounds__(kFitThreads) void fit_partition(
     const FitDev *__restrict__ fd, int L, const uint32_t *__restrict__ rows_in,
     uint32_t *__restrict__ rows_out, const uint32_t *__restrict__ seg_start,
-    const uint32_t *__restrict__ chunk_start, const uint32_t *__restrict__ open_node,
-    const uint64_t *__restrict__ pre, const uint32_t *__restrict__ seg_start_next,
-    const uint32_t *__restrict__ slot_of_next, const uint8_t *__restrict__ nstate,
-    const uint16_t *__restrict__ nodes) {
+    const uint32_t *__restrict__ chunk_start, const uint64_t *__restrict__ pre,
+    const uint4 *__restrict__ slot_info, const uint32_t *__restrict__ chunk_slot) {
   extern __shared__ uint32_t rl[]; // [kTile][W]
   __shared__ uint32_t s_src[2][kTile];
   __shared__ uint64_t scratch[kFitThreads / 64];
-  const uint32_t set = L & 1, K = fd->lvl_K[set], NCH = fd->lvl_NCH[set], W = fd->W;
+  const uint32_t NCH = fd->lvl_NCH[L & 1], W = fd->W;
   const uint32_t t = threadIdx.x;
-  const uint32_t child_base = (2u << L) - 1;
   for (uint32_t ch = blockIdx.x; ch < NCH; ch += gridDim.x) {
-    const ChunkRef c = chunk_ref(ch, chunk_start, seg_start, K);
-    const ChunkSplit s = chunk_split(c.slot, open_node, nodes, nstate);
+    // the chunk's slot (found by fit_pcount), then its segment and record
+    ChunkRef c;
+    c.slot = chunk_slot[ch];
+    c.first_chunk = chunk_start[c.slot];
+    c.first = seg_start[c.slot] + (ch - c.first_chunk) * kTile;
+    c.nr = min(kTile, seg_start[c.slot + 1] - c.first);
+    const uint4 info = slot_info[c.slot];
+    const SlotSplit s = slot_split(info.x);
+    const uint64_t before = pre[ch] - pre[c.first_chunk];
     __syncthreads();
     const uint32_t *src = rows_in + (uint64_t)c.first * W;
-    for (uint32_t k = t; k < c.nr * W; k += kFitThreads) rl[k] = src[k];
+    stage_words(src, c.nr * W, rl);
     __syncthreads();
     bool keep = false, left = false;
     if (t < c.nr) {
@@ -860,19 +945,14 @@ __global__ __launch_bounds__(kFitThreads) void fit_partition(
       else s_src[1][(uint32_t)(rank >> 32)] = t;
     }
     __syncthreads();
-    // offsets within each child's segment: kept rows of this segment's
-    // earlier chunks
-    const uint64_t before = pre[ch] - pre[chunk_start[c.slot]];
+    // offsets within each child's segment (info.y, info.z): kept rows of
+    // this segment's earlier chunks
     const uint32_t nl = (uint32_t)tot, nrr = (uint32_t)(tot >> 32);
-    if (nl) {
-      const uint32_t base = seg_start_next[slot_of_next[s.lc - child_base]] + (uint32_t)before;
-      copy_rows_out(rl, s_src[0], nl, W, fd->divW, rows_out, base, fd->n_train);
-    }
-    if (nrr) {
-      const uint32_t base =
-          seg_start_next[slot_of_next[s.rc - child_base]] + (uint32_t)(before >> 32);
-      copy_rows_out(rl, s_src[1], nrr, W, fd->divW, rows_out, base, fd->n_train);
-    }
+    if (nl) copy_rows_out(rl, s_src[0], nl, W, fd->divW, rows_out, info.y + (uint32_t)before,
+                          fd->n_train);
+    if (nrr)
+      copy_rows_out(rl, s_src[1], nrr, W, fd->divW, rows_out, info.z + (uint32_t)(before >> 32),
+                    fd->n_train);
   }
 }
 
@@ -896,7 +976,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_test(const FitDev *__restrict
   uint32_t *rl = lds;
   uint32_t *path = lds + kTile * W; // node * C at every depth
   uint16_t *tree = reinterpret_cast<uint16_t *>(path + kTile * ND);
-  for (uint32_t k = t; k < n_int; k += kFitThreads) tree[k] = nodes[k];
+  stage_words(nodes, n_int, tree);
   const uint32_t RP = kFitThreads / C; // rows per round (C <= 64)
   const uint32_t rs = t / C, c = t - rs * C;
   const bool active = rs < RP;
@@ -908,7 +988,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_test(const FitDev *__restrict
     const uint32_t first = tile * kTile, nr = min(kTile, n - first);
     __syncthreads();
     const uint32_t *src = test_rows + (uint64_t)first * W;
-    for (uint32_t k = t; k < nr * W; k += kFitThreads) rl[k] = src[k];
+    stage_words(src, nr * W, rl);
     __syncthreads();
     // every path entry holds a node of the grown tree (depths past D repeat
     // the leaf, rows past the tile the root), so phase two loads without
@@ -1114,6 +1194,8 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   const size_t o_ccnt = take(max_chunks * 8);
   const size_t o_cpre = take(max_chunks * 8);
   const size_t o_part = take((size_t)3 * (CGS_MAX_DEPTH + 1) * kFitGrid * 8);
+  const size_t o_sinfo = take(kcap * sizeof(uint4));
+  const size_t o_cslot = take(max_chunks * 4);
   const size_t o_dpar = take(kcap * 4);
   const size_t o_dsib = take(kcap * 4);
   size_t o_open[2], o_seg[2], o_chs[2], o_slot[2];
@@ -1143,6 +1225,8 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
                        reinterpret_cast<int64_t *>(base + o_hist) + hist_entries / 2};
   uint32_t *der_parent = reinterpret_cast<uint32_t *>(base + o_dpar);
   uint64_t *test_part = reinterpret_cast<uint64_t *>(base + o_part);
+  uint4 *slot_info = reinterpret_cast<uint4 *>(base + o_sinfo);
+  uint32_t *chunk_slot = reinterpret_cast<uint32_t *>(base + o_cslot);
   uint32_t *der_sib = reinterpret_cast<uint32_t *>(base + o_dsib);
   int64_t *nsum = reinterpret_cast<int64_t *>(base + o_nsum);
   uint32_t *rows[2] = {reinterpret_cast<uint32_t *>(base + o_rows0),
@@ -1168,6 +1252,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
       std::max<uint32_t>(CGS_MAX_RADIX * (C + 1), std::min<uint32_t>(h.entries, 8192));
   const size_t split_lds = (size_t)cap_entries * 8;
   const size_t tile_lds = (size_t)kTile * h.W * 4;
+  const size_t starts_lds = (size_t)2 * (kcap + 1) * 4; // a level's segment and chunk starts
   const size_t test_lds = tile_lds + (size_t)kTile * (CGS_MAX_DEPTH + 1) * 4 + n_int * 2;
   const size_t scatter_lds = tile_lds + (size_t)kTile * h.Cp * 4;
   auto grid_for = [](uint64_t items) {
@@ -1183,6 +1268,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   auto kh = P <= 8 ? fit_hist<8> : P <= 16 ? fit_hist<16> : fit_hist<32>;
   if (e == hipSuccess) e = allow_lds(kh, hist_lds);
   if (e == hipSuccess) e = allow_lds(fit_split, split_lds);
+  if (e == hipSuccess) e = allow_lds(fit_pcount, starts_lds);
   if (e == hipSuccess) e = allow_lds(fit_partition, tile_lds);
   if (e == hipSuccess) e = allow_lds(fit_test, test_lds);
   if (e == hipSuccess) e = allow_lds(fit_scatter, scatter_lds);
@@ -1214,7 +1300,8 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
     if (D > 0)
       fit_layout<<<1, kFitThreads, 0, stream>>>(fd, 0, nstate, ncount, open_node[0],
                                                 seg_start[0], chunk_start[0], slot_of[0],
-                                                slot_of[1], der_parent, der_sib, (uint32_t)kcap);
+                                                slot_of[1], der_parent, der_sib, slot_info,
+                                                (uint32_t)kcap);
     for (uint32_t L = 0; L < D; ++L) {
       const int s = L & 1, s1 = s ^ 1;
       kh<<<g_hist, kFitThreads, hist_lds, stream>>>(fd, (int)L, rows[s], seg_start[s], ghist[s]);
@@ -1224,19 +1311,19 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
                                                               (uint32_t)kcap);
       fit_split<<<1u << L, kFitThreads, split_lds, stream>>>(fd, (int)L, ghist[s], slot_of[s],
                                                              cap_entries, ncount, nsum,
-                                                             w->nmean, nstate, w->nodes);
+                                                             w->nmean, nstate, w->nodes,
+                                                             slot_info);
       if (L + 1 < D) {
         fit_layout<<<1, kFitThreads, 0, stream>>>(fd, (int)L + 1, nstate, ncount,
                                                   open_node[s1], seg_start[s1], chunk_start[s1],
                                                   slot_of[s1], slot_of[s], der_parent, der_sib,
-                                                  (uint32_t)kcap);
-        fit_pcount<<<g_chunks, kFitThreads, 0, stream>>>(fd, (int)L, rows[s], seg_start[s],
-                                                         chunk_start[s], open_node[s], nstate,
-                                                         w->nodes, chunk_cnt);
+                                                  slot_info, (uint32_t)kcap);
+        fit_pcount<<<g_chunks, kFitThreads, starts_lds, stream>>>(
+            fd, (int)L, rows[s], seg_start[s], chunk_start[s], slot_info, chunk_cnt, chunk_slot);
         fit_excl_scan<<<1, kScanThreads, 0, stream>>>(chunk_cnt, chunk_pre, &fd->lvl_NCH[s], 0);
         fit_partition<<<g_chunks, kFitThreads, tile_lds, stream>>>(
-            fd, (int)L, rows[s], rows[s1], seg_start[s], chunk_start[s], open_node[s],
-            chunk_pre, seg_start[s1], slot_of[s1], nstate, w->nodes);
+            fd, (int)L, rows[s], rows[s1], seg_start[s], chunk_start[s], chunk_pre, slot_info,
+            chunk_slot);
       }
     }
     fit_test<<<g_test, kFitThreads, test_lds, stream>>>(fd, test_rows, w->nodes, w->nmean,
