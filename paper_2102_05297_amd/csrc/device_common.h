@@ -95,28 +95,24 @@ __device__ __forceinline__ float key_float(uint32_t k) {
 
 // Normalised weight of the score-normalisation equation, quantised to
 // rint(w * 2^23).  The eighth power is three squarings; s == 0 maps to 1.
+// One division per configuration: the divisor (s_max for s > 0, s_min
+// otherwise) is selected per lane, so a wave holding scores of both signs
+// does not run two divisions; every value is the same float as with the
+// two-branch form.
 __device__ __forceinline__ uint32_t quantized_weight(float s, bool explored, float s_min,
                                                      float s_max, float gamma, float w_min) {
-  if (explored) return 0u;
-  float w;
-  if (s > 0.0f) {
-    const float y = 1.0f + s / s_max;
-    const float y2 = y * y;
-    const float y4 = y2 * y2;
-    w = y4 * y4;
-  } else if (s > gamma) {
-    if (s == 0.0f) {
-      w = 1.0f;
-    } else {
-      const float y = 1.0f - s / s_min;
-      const float y2 = y * y;
-      const float y4 = y2 * y2;
-      w = fmaxf(w_min, y4 * y4);
-    }
-  } else {
-    w = w_min;
-  }
-  return (uint32_t)rintf(w * 8388608.0f);
+  const bool pos = s > 0.0f;
+  const float t = s / (pos ? s_max : s_min);
+  const float y = pos ? 1.0f + t : 1.0f - t;
+  const float y2 = y * y;
+  const float y4 = y2 * y2;
+  const float y8 = y4 * y4;
+  float w = w_min;
+  if (pos)
+    w = y8;
+  else if (s > gamma)
+    w = (s == 0.0f) ? 1.0f : fmaxf(w_min, y8);
+  return explored ? 0u : (uint32_t)rintf(w * 8388608.0f);
 }
 
 __device__ __forceinline__ bool explored_bit(const uint32_t *__restrict__ ex, uint32_t l) {

@@ -18,6 +18,7 @@ namespace cgs {
 namespace {
 
 constexpr int kForestThreads = 256;
+constexpr int kForestBatch = 16; // loads in flight per thread (node staging, leaf gathers)
 
 __global__ __launch_bounds__(kForestThreads) void forest_eval(
     const SpaceDev *__restrict__ sp, const uint32_t *__restrict__ idx, uint32_t first,
@@ -39,7 +40,21 @@ __global__ __launch_bounds__(kForestThreads) void forest_eval(
   for (int t = 0; t < n_trees; ++t) {
     __syncthreads();
     const uint16_t *tn = nodes + (size_t)t * n_int;
-    for (uint32_t j = threadIdx.x; j < n_int; j += kForestThreads) lnodes[j] = tn[j];
+    // the tree's nodes, kForestBatch loads per thread issued before the
+    // first LDS store (a plain loop waits for every load in turn)
+    for (uint32_t j0 = threadIdx.x; j0 < n_int; j0 += kForestBatch * kForestThreads) {
+      uint16_t v[kForestBatch];
+#pragma unroll
+      for (int b = 0; b < kForestBatch; ++b) {
+        const uint32_t j = j0 + b * kForestThreads;
+        v[b] = j < n_int ? tn[j] : (uint16_t)0;
+      }
+#pragma unroll
+      for (int b = 0; b < kForestBatch; ++b) {
+        const uint32_t j = j0 + b * kForestThreads;
+        if (j < n_int) lnodes[j] = v[b];
+      }
+    }
     __syncthreads();
     uint32_t node = 0;
     for (int lev = 0; lev < depth; ++lev) {
@@ -56,17 +71,32 @@ __global__ __launch_bounds__(kForestThreads) void forest_eval(
   const uint32_t n_leaf = 1u << depth;
   const float t_div = (float)n_trees;
   if ((n_counters & 3) == 0) {
+    // leaf vectors of kForestBatch / 2 trees in flight at once; the sums
+    // still run in ascending tree order from tree 0
+    constexpr int TB = kForestBatch / 2;
     for (int c = 0; c < n_counters; c += 4) {
-      const uint32_t leaf0 = lleaf[threadIdx.x];
-      float4 acc = *reinterpret_cast<const float4 *>(leaves + (size_t)leaf0 * n_counters + c);
-      for (int t = 1; t < n_trees; ++t) {
-        const uint32_t lf = lleaf[t * kForestThreads + threadIdx.x];
-        const float4 v = *reinterpret_cast<const float4 *>(
-            leaves + ((size_t)t * n_leaf + lf) * n_counters + c);
-        acc.x = acc.x + v.x;
-        acc.y = acc.y + v.y;
-        acc.z = acc.z + v.z;
-        acc.w = acc.w + v.w;
+      float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      for (int t0 = 0; t0 < n_trees; t0 += TB) {
+        float4 v[TB];
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          const int t = min(t0 + u, n_trees - 1);
+          const uint32_t lf = lleaf[t * kForestThreads + threadIdx.x];
+          v[u] = *reinterpret_cast<const float4 *>(leaves + ((size_t)t * n_leaf + lf) * n_counters +
+                                                   c);
+        }
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          if (t0 + u >= n_trees) break;
+          if (t0 + u == 0) {
+            acc = v[0];
+          } else {
+            acc.x = acc.x + v[u].x;
+            acc.y = acc.y + v[u].y;
+            acc.z = acc.z + v[u].z;
+            acc.w = acc.w + v[u].w;
+          }
+        }
       }
       P[(size_t)(c + 0) * stride + l] = acc.x / t_div;
       P[(size_t)(c + 1) * stride + l] = acc.y / t_div;

@@ -341,9 +341,24 @@ __device__ __forceinline__ void infer_store(const MlpFwdArgs &a, const f32x16 (&
   }
 }
 
-// Stages n 16-byte units from global to LDS with every thread of the block.
+// Stages n 16-byte units from global to LDS with every thread of the block,
+// 8 loads per thread in flight before the first LDS store (a plain loop
+// waits for every load in turn).
 __device__ __forceinline__ void stage_units(bf16x8 *dst, const bf16x8 *src, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  constexpr int B = 8;
+  for (int i0 = threadIdx.x; i0 < n; i0 += B * (int)blockDim.x) {
+    bf16x8 v[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int i = i0 + b * (int)blockDim.x;
+      v[b] = i < n ? src[i] : bf16x8{};
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int i = i0 + b * (int)blockDim.x;
+      if (i < n) dst[i] = v[b];
+    }
+  }
 }
 
 // Biases in LDS: b1[H], b2[H], b3[32 NB3] (zero past C).

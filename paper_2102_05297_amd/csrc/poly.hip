@@ -298,9 +298,23 @@ __global__ __launch_bounds__(kEvalThreads) void poly_eval(const PolyDev *__restr
   const uint32_t T = pd->T, C = pd->C, S = pd->S, t = threadIdx.x;
   const uint32_t group = blockIdx.x / per_group, part = blockIdx.x % per_group;
   const uint32_t g0 = group * SG, g1 = min(S, g0 + SG);
-  for (uint32_t e = t; e < (g1 - g0) * T * CB; e += kEvalThreads) {
-    const uint32_t c = e % CB, st = e / CB; // st = (s - g0) * T + term
-    lds[e] = c < C ? beta32[((uint64_t)g0 * T + st) * C + c] : 0.0f;
+  // 16 coefficient loads per thread in flight before the first LDS store (a
+  // plain loop waits for every load in turn)
+  constexpr int kB = 16;
+  const uint32_t n_co = (g1 - g0) * T * CB;
+  for (uint32_t e0 = t; e0 < n_co; e0 += kB * kEvalThreads) {
+    float v[kB];
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const uint32_t e = e0 + b * kEvalThreads;
+      const uint32_t c = e % CB, st = e / CB; // st = (s - g0) * T + term
+      v[b] = (e < n_co && c < C) ? beta32[((uint64_t)g0 * T + st) * C + c] : 0.0f;
+    }
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const uint32_t e = e0 + b * kEvalThreads;
+      if (e < n_co) lds[e] = v[b];
+    }
   }
   for (uint32_t e = t; e < CGS_MAX_PARAMS * CGS_MAX_RADIX; e += kEvalThreads) xv[e] = pd->xv32[e];
   for (uint32_t e = t; e < T; e += kEvalThreads) terms[e] = pd->terms[e];
