@@ -76,6 +76,7 @@ constexpr uint32_t kTile = 256;           // rows per chunk / staged tile
 constexpr uint16_t kAlwaysLeftNode = (uint16_t)(255u << 8);
 constexpr uint32_t kScanThreads = 1024;
 constexpr uint32_t kHistGrid = 1024;      // workgroups of the histogram pass
+constexpr uint32_t kHistTile = 128;       // rows per staged tile of the histogram pass
 
 __device__ __forceinline__ uint64_t split_key(uint64_t key, uint64_t i) {
   return (key & 0xFFFFFFFF00000000ull) | i;
@@ -558,9 +559,10 @@ __global__ __launch_bounds__(kFitThreads) void fit_hist_derive(
 }
 
 // Histograms of level L.  Each workgroup takes a contiguous range of the
-// level's rows and cuts it at segment (node) boundaries; within one node's
-// part, row group g of G = 256 / (C + 1) groups takes a contiguous run of
-// rows and lane (g, c) handles column c of them (column C is the count).
+// level's rows and cuts it at segment (node) boundaries; one node's part
+// passes through LDS in tiles of kHistTile rows, row group g of
+// G = 256 / (C + 1) groups takes a contiguous share of each tile and lane
+// (g, c) handles column c of those rows (column C is the count).
 // Rows arrive in configuration order, so most parameters keep their digit
 // over long runs and consecutive rows differ in few digits: each lane keeps
 // the running sum of its column and, per parameter, the sum at which the
@@ -573,7 +575,8 @@ __global__ __launch_bounds__(kFitThreads) void fit_hist(const FitDev *__restrict
                                                         const uint32_t *__restrict__ rows,
                                                         const uint32_t *__restrict__ seg_start,
                                                         int64_t *__restrict__ ghist) {
-  extern __shared__ int64_t h64[]; // [entries]
+  extern __shared__ int64_t h64[]; // [entries], then a [kHistTile][W] row tile
+  uint32_t *rl = reinterpret_cast<uint32_t *>(h64 + fd->entries);
   // the direct nodes' rows come first: [0, Rd), segments 0..Kd-1
   const uint32_t set = L & 1, K = fd->lvl_Kd[set], R = fd->lvl_Rd[set];
   if (R == 0) return;
@@ -596,50 +599,59 @@ __global__ __launch_bounds__(kFitThreads) void fit_hist(const FitDev *__restrict
     const uint32_t seg_end = seg_start[slot + 1];
     const uint32_t end = min(b, seg_end);
     if (end <= pos) break; // segments are never empty
-    if (active) {
-      const uint32_t m = end - pos;
-      const uint32_t r0 = pos + (uint32_t)((uint64_t)m * g / G);
-      const uint32_t r1 = pos + (uint32_t)((uint64_t)m * (g + 1) / G);
-      constexpr int NW = (MAXP + 3) / 4;
-      // S: running sum of column c over the lane's rows; st[j]: S where
-      // parameter j's current run of equal digits began.  A run's sum
-      // S - st[j] goes to the LDS bin of its digit when the digit changes.
-      // prev holds the previous row's packed digits (0xff bytes: no run yet).
-      uint32_t prev[NW];
-      int64_t st[MAXP];
+    constexpr int NW = (MAXP + 3) / 4;
+    // S: running sum of column c over the lane's rows; st[j]: S where
+    // parameter j's current run of equal digits began.  A run's sum
+    // S - st[j] goes to the LDS bin of its digit when the digit changes.
+    // prev holds the previous row's packed digits (0xff bytes: no run yet).
+    uint32_t prev[NW];
+    int64_t st[MAXP];
 #pragma unroll
-      for (int w = 0; w < NW; ++w) prev[w] = 0xffffffffu;
+    for (int w = 0; w < NW; ++w) prev[w] = 0xffffffffu;
 #pragma unroll
-      for (int j = 0; j < MAXP; ++j) st[j] = 0;
-      int64_t S = 0;
-      auto process = [&](const uint32_t (&dw)[NW], int64_t q) {
+    for (int j = 0; j < MAXP; ++j) st[j] = 0;
+    int64_t S = 0;
+    auto process = [&](const uint32_t (&dw)[NW], int64_t q) {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          const uint32_t x = dw[w] ^ prev[w];
-          if (w < (int)PW && x) {
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t x = dw[w] ^ prev[w];
+        if (w < (int)PW && x) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const int j = 4 * w + k;
-              if (j < (int)P && ((x >> (8 * k)) & 255u)) {
-                const uint32_t old = (prev[w] >> (8 * k)) & 255u;
-                if (old != 0xffu)
-                  atomicAdd(reinterpret_cast<unsigned long long *>(&h64[roffc[j] + old * C1]),
-                            (unsigned long long)(S - st[j]));
-                st[j] = S;
-              }
+          for (int k = 0; k < 4; ++k) {
+            const int j = 4 * w + k;
+            if (j < (int)P && ((x >> (8 * k)) & 255u)) {
+              const uint32_t old = (prev[w] >> (8 * k)) & 255u;
+              if (old != 0xffu)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&h64[roffc[j] + old * C1]),
+                          (unsigned long long)(S - st[j]));
+              st[j] = S;
             }
-            prev[w] = dw[w];
           }
+          prev[w] = dw[w];
         }
-        S += q;
-      };
-      for (uint32_t r = r0; r < r1; ++r) {
-        const uint32_t *row = rows + (uint64_t)r * W;
-        uint32_t dw[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) dw[w] = (w < (int)PW) ? row[w] : 0u;
-        process(dw, c < C ? (int64_t)(int32_t)row[PW + c] : 1);
       }
+      S += q;
+    };
+    // the node's rows pass through LDS in tiles (all loads of a tile in
+    // flight together); group g takes a contiguous share of each tile
+    for (uint32_t tp = pos; tp < end; tp += kHistTile) {
+      const uint32_t nr = min(kHistTile, end - tp);
+      __syncthreads();
+      stage_words(rows + (uint64_t)tp * W, nr * W, rl);
+      __syncthreads();
+      if (active) {
+        const uint32_t r0 = (uint32_t)((uint64_t)nr * g / G);
+        const uint32_t r1 = (uint32_t)((uint64_t)nr * (g + 1) / G);
+        for (uint32_t r = r0; r < r1; ++r) {
+          const uint32_t *row = rl + r * W;
+          uint32_t dw[NW];
+#pragma unroll
+          for (int w = 0; w < NW; ++w) dw[w] = (w < (int)PW) ? row[w] : 0u;
+          process(dw, c < C ? (int64_t)(int32_t)row[PW + c] : 1);
+        }
+      }
+    }
+    if (active) {
 #pragma unroll
       for (int j = 0; j < MAXP; ++j) {
         const uint32_t old = (prev[j >> 2] >> (8 * (j & 3))) & 255u;
@@ -1157,9 +1169,10 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   h.entries = sumR * (C + 1);
   h.items = P * (C + 1);
   h.key_k = n_train;
-  // the level histogram lives in LDS (int64): sum_j R_j <= 137 for any space
-  // with fewer than 2^32 raw configurations, so this always fits
-  if ((size_t)h.entries * 8 > 160 * 1024) return hipErrorInvalidValue;
+  // the level histogram (int64) and a row tile live in LDS: sum_j R_j <= 137
+  // for any space with fewer than 2^32 raw configurations, so this always fits
+  if ((size_t)h.entries * 8 + (size_t)kHistTile * h.W * 4 > 160 * 1024)
+    return hipErrorInvalidValue;
 
   // open nodes of one level: at most 2^(D-1), and each holds min_split rows
   const uint64_t n_nodes = ((uint64_t)2 << D) - 1;
@@ -1247,7 +1260,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   }
 
   // launch shapes
-  const size_t hist_lds = (size_t)h.entries * 8;
+  const size_t hist_lds = (size_t)h.entries * 8 + (size_t)kHistTile * h.W * 4;
   const uint32_t cap_entries =
       std::max<uint32_t>(CGS_MAX_RADIX * (C + 1), std::min<uint32_t>(h.entries, 8192));
   const size_t split_lds = (size_t)cap_entries * 8;
