@@ -172,14 +172,29 @@ __global__ __launch_bounds__(kScanThreads) void fit_excl_scan(const uint64_t *__
   const uint32_t n = n_dev ? *n_dev : n_host;
   const uint32_t t = threadIdx.x, per = (n + kScanThreads - 1) / kScanThreads;
   const uint32_t a = min(n, t * per), b = min(n, a + per);
+  // the run is read in batches of kStageBatch loads in flight (a plain loop
+  // waits for every load before the next)
   uint64_t mine = 0;
-  for (uint32_t i = a; i < b; ++i) mine += in[i];
+  for (uint32_t i0 = a; i0 < b; i0 += kStageBatch) {
+    uint64_t v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) v[u] = i0 + u < b ? in[i0 + u] : 0ull;
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) mine += v[u];
+  }
   uint64_t tot;
   uint64_t run = block_excl_scan<kScanThreads>(mine, scratch, tot);
-  for (uint32_t i = a; i < b; ++i) {
-    const uint64_t v = in[i];
-    out[i] = run;
-    run += v;
+  for (uint32_t i0 = a; i0 < b; i0 += kStageBatch) {
+    uint64_t v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) v[u] = i0 + u < b ? in[i0 + u] : 0ull;
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      if (i0 + u < b) {
+        out[i0 + u] = run;
+        run += v[u];
+      }
+    }
   }
 }
 
@@ -740,11 +755,18 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
     __syncthreads();
     for (uint32_t it = t; it < (j1 - j0) * C1; it += kFitThreads) {
       const uint32_t jl = j0 + it / C1, c = it % C1;
-      const uint32_t rb = fd->roff[jl];
+      const uint32_t rb = fd->roff[jl], R = fd->radix[jl];
+      int64_t hv[CGS_MAX_RADIX]; // every digit's entry in flight at once
+#pragma unroll
+      for (uint32_t v = 0; v < CGS_MAX_RADIX; ++v)
+        hv[v] = H[(uint64_t)(rb + min(v, R - 1)) * C1 + c]; // in bounds; v >= R unused
       int64_t run = 0;
-      for (uint32_t v = 0; v < fd->radix[jl]; ++v) {
-        run += H[(uint64_t)(rb + v) * C1 + c];
-        ps[(rb - b0 + v) * C1 + c] = run;
+#pragma unroll
+      for (uint32_t v = 0; v < CGS_MAX_RADIX; ++v) {
+        if (v < R) {
+          run += hv[v];
+          ps[(rb - b0 + v) * C1 + c] = run;
+        }
       }
     }
     __syncthreads();
@@ -803,7 +825,11 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
       while (fd->roff[j + 1] - (j + 1) <= best_k) ++j;
       th = best_k - (fd->roff[j] - j);
       uint32_t nl = 0;
-      for (uint32_t v = 0; v <= th; ++v) nl += (uint32_t)H[(uint64_t)(fd->roff[j] + v) * C1 + C];
+#pragma unroll
+      for (uint32_t v = 0; v < CGS_MAX_RADIX; ++v) {
+        const uint32_t x = (uint32_t)H[(uint64_t)(fd->roff[j] + min(v, th)) * C1 + C];
+        nl += v <= th ? x : 0u;
+      }
       s_nl = nl;
     }
     s_split = split;
@@ -819,7 +845,11 @@ __global__ __launch_bounds__(kFitThreads) void fit_split(
     const uint32_t l = 2 * node + 1, r = l + 1;
     for (uint32_t c = t; c < C; c += kFitThreads) {
       int64_t sl = 0;
-      for (uint32_t v = 0; v <= th; ++v) sl += H[(uint64_t)(fd->roff[j] + v) * C1 + c];
+#pragma unroll
+      for (uint32_t v = 0; v < CGS_MAX_RADIX; ++v) {
+        const int64_t x = H[(uint64_t)(fd->roff[j] + min(v, th)) * C1 + c];
+        sl += v <= th ? x : 0;
+      }
       const int64_t sr = s_S[c] - sl;
       nsum[(uint64_t)l * C + c] = sl;
       nsum[(uint64_t)r * C + c] = sr;
@@ -866,10 +896,8 @@ __device__ __forceinline__ ChunkRef chunk_ref(uint32_t ch, const uint32_t *cs, c
 __device__ __forceinline__ void stage_starts(const uint32_t *__restrict__ seg_start,
                                              const uint32_t *__restrict__ chunk_start, uint32_t K,
                                              uint32_t *ss, uint32_t *cs) {
-  for (uint32_t i = threadIdx.x; i <= K; i += blockDim.x) {
-    ss[i] = seg_start[i];
-    cs[i] = chunk_start[i];
-  }
+  stage_words(seg_start, K + 1, ss);
+  stage_words(chunk_start, K + 1, cs);
   __syncthreads();
 }
 
