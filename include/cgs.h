@@ -509,6 +509,14 @@ cgs_status cgs_batch_step(cgs_batch batch, const uint64_t *profile_raw_host,
                           const float *deltas_host, const uint64_t *u64_host,
                           uint64_t *raw_out_host, uint64_t *valid_out_host,
                           int32_t *status_out_host);
+/* One more draw in every session from the weights of the batch's last step
+ * (the further draws of an Alg. 1 iteration, Sect. 3.7): u64_host[n]
+ * uniforms; outputs as for cgs_batch_step.  Each drawn configuration is
+ * marked explored and its weight removed, as cgs_sample_next does.
+ * CGS_ESTATE when a session has stepped on its own since the batch step.
+ * Synchronises. */
+cgs_status cgs_batch_draw(cgs_batch batch, const uint64_t *u64_host, uint64_t *raw_out_host,
+                          uint64_t *valid_out_host, int32_t *status_out_host);
 /* Device time of the last batch step (ms, HIP events around the launch). */
 cgs_status cgs_batch_step_time(cgs_batch batch, float *ms);
 /* Picks the score and weight grid sizes by timing candidates with HIP events
@@ -521,6 +529,23 @@ cgs_status cgs_batch_autotune(cgs_batch batch, const char *cache_path,
                               cgs_batch_schedule *chosen);
 cgs_status cgs_batch_set_schedule(cgs_batch batch, const cgs_batch_schedule *sched);
 void cgs_batch_destroy(cgs_batch batch);
+
+/* Alg. 1 for every session of a batch at once: run i uses session i (fresh)
+ * and model i (24 counters, all on one space) and the random numbers
+ * uniforms_host[i][n_uniforms]; every run makes exactly the tests
+ * cgs_tuning_run would make with the same numbers.  Runs advance in
+ * lockstep: one batch step (the scored step and first draw of every run),
+ * then draws - 1 batched draws; a finished run keeps stepping unprofiled
+ * until the last run ends, its results ignored.
+ *   tested_host[n][capacity], profiled_host[n][capacity] (may be NULL),
+ *   n_tests[n], tests_to_well[n]   as for cgs_tuning_run, per run
+ * The options and outputs are those of cgs_tuning_run (above). */
+cgs_status cgs_tuning_run_batch(cgs_batch batch, const float *runtime_host,
+                                const double *counters_host, const cgs_expert_params *expert,
+                                const uint64_t *uniforms_host, uint64_t n_uniforms,
+                                const cgs_tuning_opts *opts, uint64_t capacity,
+                                uint64_t *tested_host, uint8_t *profiled_host, uint64_t *n_tests,
+                                uint64_t *tests_to_well);
 
 /* ------------------------------------------------ standalone sampler */
 /* The draw of Alg. 1 on caller-given integer weights: n_draws consecutive

@@ -43,7 +43,7 @@ EXPORTS = (
     "cgs_session_copy_neighbourhood", "cgs_model_fit_tree", "cgs_model_forest_shape",
     "cgs_model_copy_forest", "cgs_poly_design", "cgs_model_fit_poly", "cgs_poly_shape",
     "cgs_poly_copy_coefficients", "cgs_model_load_predictions", "cgs_default_tuning_opts",
-    "cgs_tuning_run",
+    "cgs_tuning_run", "cgs_batch_draw", "cgs_tuning_run_batch",
 )
 
 
@@ -179,6 +179,9 @@ _sig("cgs_mlp_copy_params", [_p, _p, _u64])
 _sig("cgs_batch_create", [C.c_int, _p, _p, _ptr(cgs_batch_schedule), _ptr(_p)])
 _sig("cgs_batch_step", [_p, _p, _p, _p, _p, _p, _p])
 _sig("cgs_batch_step_time", [_p, _ptr(C.c_float)])
+_sig("cgs_batch_draw", [_p, _p, _p, _p, _p])
+_sig("cgs_tuning_run_batch", [_p, _p, _p, _ptr(cgs_expert_params), _p, _u64, _ptr(cgs_tuning_opts),
+                              _u64, _p, _p, _p, _p])
 _sig("cgs_batch_autotune", [_p, C.c_char_p, _ptr(cgs_batch_schedule)])
 _sig("cgs_batch_set_schedule", [_p, _ptr(cgs_batch_schedule)])
 _sig("cgs_batch_destroy", [_p], None)
@@ -662,6 +665,42 @@ class Batch:
         _check(_lib.cgs_batch_step(self.h, _ptrof(pr), _ptrof(d), _ptrof(u), _ptrof(raw),
                                    _ptrof(val), _ptrof(st)), "cgs_batch_step")
         return raw, val, st
+
+    def draw(self, uniforms):
+        """One more draw in every session from its last batch step's weights
+        (cgs_batch_draw): (raw[n], valid[n], status[n])."""
+        u = _arr(uniforms, np.uint64)
+        raw = np.zeros(self.n, dtype=np.uint64)
+        val = np.zeros(self.n, dtype=np.uint64)
+        st = np.zeros(self.n, dtype=np.int32)
+        _check(_lib.cgs_batch_draw(self.h, _ptrof(u), _ptrof(raw), _ptrof(val), _ptrof(st)),
+               "cgs_batch_draw")
+        return raw, val, st
+
+    def tuning_run(self, runtime, counters, uniforms, draws: int = 5,
+                   max_tests: Optional[int] = None, stop_at_well: bool = True,
+                   well_factor: float = 1.1, expert: Optional["cgs_expert_params"] = None):
+        """Alg. 1 for every session at once (cgs_tuning_run_batch); uniforms
+        [n][k] are run i's random numbers.  Per run: (tested valid indices,
+        profiled flags, tests to the first well-performing configuration)."""
+        rt = _arr(runtime, np.float32)
+        pc = _arr(counters, np.float64)
+        us = _arr(uniforms, np.uint64)
+        if us.ndim != 2 or us.shape[0] != self.n:
+            raise ValueError("uniforms must be [n_sessions][k]")
+        cap = int(max_tests if max_tests is not None else us.shape[1] + 1)
+        opts = cgs_tuning_opts(int(draws), 1 if stop_at_well else 0, cap, float(well_factor))
+        ep = expert if expert is not None else cgs_default_expert_params()
+        tested = np.zeros((self.n, cap), dtype=np.uint64)
+        prof = np.zeros((self.n, cap), dtype=np.uint8)
+        nt = np.zeros(self.n, dtype=np.uint64)
+        tw = np.zeros(self.n, dtype=np.uint64)
+        _check(_lib.cgs_tuning_run_batch(self.h, _ptrof(rt), _ptrof(pc), C.byref(ep), _ptrof(us),
+                                         us.shape[1], C.byref(opts), cap, _ptrof(tested),
+                                         _ptrof(prof), _ptrof(nt), _ptrof(tw)),
+               "cgs_tuning_run_batch")
+        return [(tested[i, :int(nt[i])].astype(np.int64), prof[i, :int(nt[i])].astype(bool),
+                 int(tw[i])) for i in range(self.n)]
 
     def step_ms(self) -> float:
         ms = C.c_float()

@@ -2535,6 +2535,196 @@ extern "C" cgs_status cgs_batch_autotune(cgs_batch b, const char *cache_path,
   return CGS_OK;
 }
 
+extern "C" cgs_status cgs_batch_draw(cgs_batch b, const uint64_t *u64, uint64_t *raw_out,
+                                     uint64_t *valid_out, int32_t *status_out) {
+  if (!b || !u64) return fail(CGS_EINVAL, "NULL argument");
+  for (int i = 0; i < b->n; ++i) {
+    cgs_session s = b->sess[i];
+    // the session must still hold the weights of the batch's last step
+    if (!s->stepped || !s->ran_in_batch || s->pending || s->cur_acc != b->h_step[i].parity)
+      return fail(CGS_ESTATE, "session %d: no batch step to draw from", i);
+    BatchStep &st = b->h_step[i];
+    st.draw = 1;
+    st.u64 = u64[i];
+    st.seq = b->seq + 1;
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_step, b->h_step, (size_t)b->n * sizeof(BatchStep),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(launch_batch_draw(b->d_sess, b->d_step, (uint32_t)b->n, b->stream));
+  ++b->seq;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int i = 0; i < b->n; ++i) {
+    DrawResult r;
+    std::memcpy(&r, const_cast<const DrawResult *>(static_cast<volatile DrawResult *>(b->h_res + i)),
+                sizeof r);
+    b->sess[i]->last_total = r.total;
+    int32_t status = CGS_OK;
+    if (r.total == 0) status = CGS_EEMPTY;
+    else if (r.valid == kNoPick) return fail(CGS_EDEVICE, "session %d: no pick although Q > 0", i);
+    if (status_out) status_out[i] = status;
+    if (raw_out) raw_out[i] = status == CGS_OK ? r.raw : kNoPick;
+    if (valid_out) valid_out[i] = status == CGS_OK ? r.valid : kNoPick;
+  }
+  return CGS_OK;
+}
+
+// Alg. 1 for every session of a batch at once.  Each run follows exactly the
+// steps of cgs_tuning_run with its own random numbers; the runs advance in
+// lockstep (one batch step, then batched draws), and a run that has ended
+// keeps stepping with no profile while its results are ignored.
+extern "C" cgs_status cgs_tuning_run_batch(cgs_batch b, const float *runtime,
+                                           const double *counters,
+                                           const cgs_expert_params *expert,
+                                           const uint64_t *uniforms, uint64_t n_uniforms,
+                                           const cgs_tuning_opts *opts, uint64_t capacity,
+                                           uint64_t *tested, uint8_t *profiled,
+                                           uint64_t *n_tests, uint64_t *tests_to_well) {
+  if (!b || !runtime || !counters || !uniforms || !opts || !n_tests || !tests_to_well ||
+      (capacity && !tested))
+    return fail(CGS_EINVAL, "NULL argument");
+  const int n = b->n;
+  cgs_space sp = b->sess[0]->space;
+  for (int i = 0; i < n; ++i) {
+    n_tests[i] = 0;
+    tests_to_well[i] = 0;
+    if (b->sess[i]->space != sp) return fail(CGS_EINVAL, "the runs must share one space");
+    if (b->models[i]->n_counters != 24)
+      return fail(CGS_EINVAL, "the loop needs models of the 24 counters");
+  }
+  if (opts->draws < 1) return fail(CGS_ERANGE, "draws %d < 1", opts->draws);
+  if (opts->max_tests < 1 || opts->max_tests > capacity)
+    return fail(CGS_ERANGE, "max_tests must be 1..capacity");
+  const uint64_t nv = sp->n_valid;
+  if (nv == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
+  float rmin = runtime[0];
+  for (uint64_t l = 1; l < nv; ++l) rmin = std::min(rmin, runtime[l]);
+  const double thresh = opts->well_factor * (double)rmin;
+
+  struct Run {
+    uint64_t u = 0, c = 0, nt = 0, found = 0, next_c = 0;
+    float best = INFINITY;
+    bool active = true, drawing = false, stop = false, next = false;
+  };
+  std::vector<Run> run(n);
+  std::vector<uint64_t> prof(n), u64(n), valid(n);
+  std::vector<int32_t> status(n);
+  std::vector<float> deltas((size_t)n * 24);
+  auto test = [&](int i, uint64_t l, bool p) {
+    Run &r = run[i];
+    tested[(uint64_t)i * capacity + r.nt] = l;
+    if (profiled) profiled[(uint64_t)i * capacity + r.nt] = p ? 1 : 0;
+    ++r.nt;
+    if (!r.found && (double)runtime[l] <= thresh) r.found = r.nt;
+    return (opts->stop_at_well && r.found) || r.nt >= opts->max_tests;
+  };
+  auto take_uniform = [&](int i) -> cgs_status {
+    Run &r = run[i];
+    if (r.u >= n_uniforms)
+      return fail(CGS_ERANGE, "run %d needs more than %llu random numbers", i,
+                  (unsigned long long)n_uniforms);
+    u64[i] = uniforms[(uint64_t)i * n_uniforms + r.u++];
+    return CGS_OK;
+  };
+  auto finish = [&]() {
+    for (int i = 0; i < n; ++i) {
+      n_tests[i] = run[i].nt;
+      tests_to_well[i] = run[i].found;
+    }
+  };
+
+  // uniform start: the first draw of every run
+  for (int i = 0; i < n; ++i) {
+    prof[i] = CGS_NO_PROFILE;
+    const cgs_status st = take_uniform(i);
+    if (st != CGS_OK) return st;
+  }
+  cgs_status st = cgs_batch_step(b, prof.data(), nullptr, u64.data(), nullptr, valid.data(),
+                                 status.data());
+  if (st != CGS_OK) return st;
+  int n_active = 0;
+  for (int i = 0; i < n; ++i) {
+    run[i].active = status[i] == CGS_OK;
+    run[i].c = valid[i];
+    n_active += run[i].active;
+  }
+  while (n_active > 0) {
+    // profile the current configurations
+    for (int i = 0; i < n; ++i) {
+      Run &r = run[i];
+      prof[i] = CGS_NO_PROFILE;
+      u64[i] = 0;
+      std::fill(deltas.begin() + (size_t)i * 24, deltas.begin() + (size_t)i * 24 + 24, 0.0f);
+      if (!r.active) continue;
+      if (test(i, r.c, true)) {
+        r.active = false;
+        --n_active;
+        continue;
+      }
+      double bn[18], d[24];
+      st = cgs_expert_system(counters + r.c * 24, expert, bn, d, nullptr);
+      if (st != CGS_OK) return fail(st, "run %d: expert system rejected the counters", i);
+      for (int c = 0; c < 24; ++c) deltas[(size_t)i * 24 + c] = (float)d[c];
+      prof[i] = sp->h_idx[r.c];
+      st = take_uniform(i);
+      if (st != CGS_OK) return st;
+      r.best = INFINITY;
+      r.next = false;
+      r.stop = false;
+      r.drawing = true;
+    }
+    if (n_active == 0) break;
+    // the scored step and its first draw, then the further draws
+    st = cgs_batch_step(b, prof.data(), deltas.data(), u64.data(), nullptr, valid.data(),
+                        status.data());
+    for (int k = 0; st == CGS_OK; ++k) {
+      bool more = false;
+      for (int i = 0; i < n; ++i) {
+        Run &r = run[i];
+        if (!r.active || !r.drawing) continue;
+        if (status[i] != CGS_OK) { // no configuration left
+          r.drawing = false;
+          continue;
+        }
+        const uint64_t l = valid[i];
+        if (test(i, l, false)) {
+          r.stop = true;
+          r.drawing = false;
+          continue;
+        }
+        if (runtime[l] <= r.best) {
+          r.best = runtime[l];
+          r.next_c = l;
+          r.next = true;
+        }
+        if (k + 1 < opts->draws) more = true;
+        else r.drawing = false;
+      }
+      if (!more) break;
+      for (int i = 0; i < n; ++i) {
+        u64[i] = 0;
+        if (run[i].active && run[i].drawing) {
+          st = take_uniform(i);
+          if (st != CGS_OK) return st;
+        }
+      }
+      st = cgs_batch_draw(b, u64.data(), nullptr, valid.data(), status.data());
+    }
+    if (st != CGS_OK) return st;
+    for (int i = 0; i < n; ++i) {
+      Run &r = run[i];
+      if (!r.active) continue;
+      if (r.stop || !r.next) {
+        r.active = false;
+        --n_active;
+      } else {
+        r.c = r.next_c;
+      }
+    }
+  }
+  finish();
+  return CGS_OK;
+}
+
 extern "C" void cgs_batch_destroy(cgs_batch b) { destroy_batch(b); }
 
 // ------------------------------------------------------- standalone sampler

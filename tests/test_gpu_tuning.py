@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import expert as EX
 from oracle import search as SR
 from oracle import space as SP
 from oracle import tuning as TU
@@ -87,3 +88,101 @@ def test_loop_errors():
     bad = table.counters[:3].astype(np.float32).copy()
     with pytest.raises(ValueError):
         m.TableModel(sp, bad)
+
+
+# ---------------------------------------------------- runs of a batch at once
+def _batch(m, spec, table, n):
+    sp = m.Space.from_spec(spec)
+    models = [m.TableModel(sp, table.counters.astype(np.float32)) for _ in range(n)]
+    sessions = [m.Session(sp) for _ in range(n)]
+    return m.Batch(sessions, models)
+
+
+def _batch_vs_oracle(spec, key, seeds, n_u, **kw):
+    m = cgs()
+    valid, table, prep = _setup(spec, key)
+    U = np.stack([synth.uniforms_u64(synth.rng(52, s), n_u) for s in seeds])
+    b = _batch(m, spec, table, len(seeds))
+    print(f"batched loop: seeds {list(seeds)} {kw}", flush=True)
+    runs = b.tuning_run(table.runtime, table.counters, U, expert=_expert(m), **kw)
+    kw_o = {k: v for k, v in kw.items() if not (k == "max_tests" and v is None)}
+    refs = []
+    for i, (tested, prof, tw) in enumerate(runs):
+        ref = TU.run(prep, table.runtime, table.counters, U[i], cores=1.0, threads=1e9, **kw_o)
+        assert tested.tolist() == ref.tested, f"run {i}"
+        assert prof.tolist() == ref.profiled, f"run {i}"
+        assert tw == ref.tests_to_well, f"run {i}"
+        refs.append(ref)
+    return refs
+
+
+def test_batched_c1_runs_equal_the_oracle():
+    refs = _batch_vs_oracle(synth.space_c1(), (9, 1), range(12), 20000)
+    assert all(r.tests_to_well > 0 for r in refs)
+    assert len({len(r.tested) for r in refs}) > 1   # the runs end at different tests
+
+
+@pytest.mark.parametrize("draws", [1, 3])
+def test_batched_small_space_runs_to_exhaustion(draws):
+    radix = [3, 4, 2, 5, 3]
+    values = [[1, 2, 4], [1, 2, 4, 8], [0, 1], [1, 2, 4, 8, 16], [1, 2, 4]]
+    spec = synth.Space(radix, values, [])
+    refs = _batch_vs_oracle(spec, (41,), range(200, 205), 4000, draws=draws, stop_at_well=False)
+    for r in refs:
+        assert sorted(set(r.tested)) == list(range(360))
+
+
+def test_batched_c2_first_iterations_equal_the_oracle():
+    # a mix of run lengths: some runs stop at max_tests, the batch goes on
+    _batch_vs_oracle(synth.space_c2(), (9, 2), range(300, 303), 200, max_tests=36,
+                     stop_at_well=False)
+
+
+def test_batched_draws_equal_the_oracle_step():
+    """cgs_batch_draw: the further draws of a step, session by session, are
+    the picks of the oracle's step with the same random numbers."""
+    m = cgs()
+    spec = synth.space_c1()
+    valid, table, prep = _setup(spec, (9, 1))
+    n, k = 3, 4
+    b = _batch(m, spec, table, n)
+    profiles = [17, 4000, 9000]
+    deltas, prof_raw = [], []
+    for l in profiles:
+        # the oracle's expert system, with the settings of _expert
+        _, _, d32, _ = EX.expert_system(table.counters[l], False, 1.0, 1e9, 0.7)
+        deltas.append(np.asarray(d32, dtype=np.float32))
+        prof_raw.append(int(valid[l]))
+    U = synth.uniforms_u64(synth.rng(53), n * (k + 1)).reshape(k + 1, n)
+    picks = [[] for _ in range(n)]
+    _, val, st = b.step(prof_raw, deltas, U[0])
+    assert (st == 0).all()
+    for i in range(n):
+        picks[i].append(int(val[i]))
+    for j in range(1, k + 1):
+        _, val, st = b.draw(U[j])
+        assert (st == 0).all()
+        for i in range(n):
+            picks[i].append(int(val[i]))
+    for i, l in enumerate(profiles):
+        explored = np.zeros(len(valid), dtype=bool)
+        ref = SR.step(prep, explored, l, deltas[i], [int(U[j][i]) for j in range(k + 1)],
+                      with_fp64=False)
+        assert picks[i] == ref.picks, f"session {i}"
+
+
+def test_batched_loop_errors():
+    m = cgs()
+    spec = synth.space_c1()
+    valid, table, prep = _setup(spec, (9, 1))
+    b = _batch(m, spec, table, 2)
+    with pytest.raises(m.CgsError) as ei:               # no batch step yet
+        b.draw(np.arange(2, dtype=np.uint64))
+    assert ei.value.status == m.ESTATE
+    with pytest.raises(ValueError):
+        b.tuning_run(table.runtime, table.counters, np.arange(6, dtype=np.uint64))
+    with pytest.raises(m.CgsError) as ei:               # random numbers run out
+        b.tuning_run(table.runtime, table.counters,
+                     synth.uniforms_u64(synth.rng(54), 8).reshape(2, 4), stop_at_well=False,
+                     max_tests=100)
+    assert ei.value.status == m.ERANGE
