@@ -554,7 +554,10 @@ def tuning_path(cgs, n_runs=1000, big_runs=40, big_cap=30000):
     20% of the configurations (Sect. 3.4.2) and the least-squares
     polynomials fitted on the three-level design (Sect. 3.4.1).  Space: the
     6-parameter space (11,496 valid configurations), then big_runs runs
-    capped at big_cap tests on the 2^24 space."""
+    capped at big_cap tests on the 2^24 space.  The measured-counter runs
+    also run as batches (cgs_tuning_run_batch: 64 runs at once on the small
+    space, all big_runs at once on the big one, which runs only batched);
+    each batched run makes the tests of its sequential run."""
     import synth
     out = {}
     for name, spec, key, runs, cap in (("c1", synth.space_c1(), (9, 1), n_runs, None),
@@ -578,7 +581,10 @@ def tuning_path(cgs, n_runs=1000, big_runs=40, big_cap=30000):
             models["polynomial"] = cgs.PolyModel(sp, design,
                                                  table.counters[design].astype(np.float32), 2)
         ep = cgs.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=1.0, threads=1e9)
+        seq_tests = {}
         for mname, model in models.items():
+            if cap:
+                continue   # the capped runs on the big space run as one batch below
             tests, wall, found_flags = [], [], []
             for r in range(runs):
                 U = synth.uniforms_u64(synth.rng(11, r), (cap or 4 * N) + 8)
@@ -606,6 +612,40 @@ def tuning_path(cgs, n_runs=1000, big_runs=40, big_cap=30000):
                 r.update({"mean_tests": float(tests.mean()), "median_tests": float(np.median(tests)),
                           "improvement": rec["random_expected"] / float(tests.mean())})
             rec[mname] = r
+            seq_tests[mname] = tests
+        # the measured-counter runs again, many at once (cgs_tuning_run_batch):
+        # every run makes the tests of its sequential run
+        model = models["measured"]
+        bsize = 64 if cap is None else runs
+        tests, found_flags, wall = [], [], 0.0
+        for b0 in range(0, runs, bsize):
+            ids = list(range(b0, min(runs, b0 + bsize)))
+            U = np.stack([synth.uniforms_u64(synth.rng(11, r), (cap or 4 * N) + 8) for r in ids])
+            sessions = [cgs.Session(sp) for _ in ids]
+            batch = cgs.Batch(sessions, [model] * len(ids))
+            t0 = time.perf_counter()
+            res = batch.tuning_run(table.runtime, table.counters, U, max_tests=cap, expert=ep)
+            wall += time.perf_counter() - t0
+            batch.close()
+            for s in sessions:
+                s.close()
+            for tested, _, tw in res:
+                tests.append(tw if tw else len(tested))
+                found_flags.append(tw > 0)
+        tests = np.asarray(tests, dtype=np.float64)
+        rb = {"batch": bsize, "runs_per_s": runs / wall, "us_per_test": float(wall / tests.sum() * 1e6)}
+        if cap:
+            found = [x for x, f in zip(tests, found_flags) if f]
+            p_rand = 1.0 - float(np.exp(np.sum(np.log1p(-K / (N - np.arange(cap))))))
+            rb.update({"found_within_cap": len(found), "share_found": len(found) / runs,
+                       "random_share_found": p_rand,
+                       "mean_tests_when_found": float(np.mean(found)) if found else None})
+        else:
+            rb.update({"mean_tests": float(tests.mean()),
+                       "equal_to_sequential": bool(np.array_equal(tests, seq_tests["measured"])),
+                       "sequential_runs_per_s": 1e3 / rec["measured"]["ms_per_run"]})
+        rec["measured_batched"] = rb
+        for model in models.values():
             model.close()
         out[name] = rec
         sp.close()
