@@ -535,8 +535,9 @@ void cgs_batch_destroy(cgs_batch batch);
  * uniforms_host[i][n_uniforms]; every run makes exactly the tests
  * cgs_tuning_run would make with the same numbers.  Runs advance in
  * lockstep: one batch step (the scored step and first draw of every run),
- * then draws - 1 batched draws; a finished run keeps stepping unprofiled
- * until the last run ends, its results ignored.
+ * then draws - 1 batched draws; a finished run steps unprofiled, its
+ * results ignored, until half of the batch has finished: the live runs then
+ * continue in a new batch of their sessions and models (freed on return).
  *   tested_host[n][capacity], profiled_host[n][capacity] (may be NULL),
  *   n_tests[n], tests_to_well[n]   as for cgs_tuning_run, per run
  * The options and outputs are those of cgs_tuning_run (above). */

@@ -2617,12 +2617,12 @@ extern "C" cgs_status cgs_tuning_run_batch(cgs_batch b, const float *runtime,
     if (!r.found && (double)runtime[l] <= thresh) r.found = r.nt;
     return (opts->stop_at_well && r.found) || r.nt >= opts->max_tests;
   };
-  auto take_uniform = [&](int i) -> cgs_status {
+  auto take_uniform = [&](int i, uint64_t *out) -> cgs_status { // run i's next number
     Run &r = run[i];
     if (r.u >= n_uniforms)
       return fail(CGS_ERANGE, "run %d needs more than %llu random numbers", i,
                   (unsigned long long)n_uniforms);
-    u64[i] = uniforms[(uint64_t)i * n_uniforms + r.u++];
+    *out = uniforms[(uint64_t)i * n_uniforms + r.u++];
     return CGS_OK;
   };
   auto finish = [&]() {
@@ -2632,10 +2632,23 @@ extern "C" cgs_status cgs_tuning_run_batch(cgs_batch b, const float *runtime,
     }
   };
 
+  // Slot j of the current batch runs run[map[j]]; per-slot arrays below.
+  // Once half of a batch's runs have ended, the live ones move to a new,
+  // smaller batch (built from the same sessions and models) between
+  // iterations, so finished runs stop costing score passes.
+  cgs_batch cur = b, own = nullptr;
+  std::vector<int> map(n);
+  for (int i = 0; i < n; ++i) map[i] = i;
+  auto release = [&](cgs_status st) {
+    if (own) cgs_batch_destroy(own);
+    if (st == CGS_OK) finish();
+    return st;
+  };
+
   // uniform start: the first draw of every run
   for (int i = 0; i < n; ++i) {
     prof[i] = CGS_NO_PROFILE;
-    const cgs_status st = take_uniform(i);
+    const cgs_status st = take_uniform(i, &u64[i]);
     if (st != CGS_OK) return st;
   }
   cgs_status st = cgs_batch_step(b, prof.data(), nullptr, u64.data(), nullptr, valid.data(),
@@ -2648,12 +2661,14 @@ extern "C" cgs_status cgs_tuning_run_batch(cgs_batch b, const float *runtime,
     n_active += run[i].active;
   }
   while (n_active > 0) {
+    const int m = cur->n;
     // profile the current configurations
-    for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < m; ++j) {
+      const int i = map[j];
       Run &r = run[i];
-      prof[i] = CGS_NO_PROFILE;
-      u64[i] = 0;
-      std::fill(deltas.begin() + (size_t)i * 24, deltas.begin() + (size_t)i * 24 + 24, 0.0f);
+      prof[j] = CGS_NO_PROFILE;
+      u64[j] = 0;
+      std::fill(deltas.begin() + (size_t)j * 24, deltas.begin() + (size_t)j * 24 + 24, 0.0f);
       if (!r.active) continue;
       if (test(i, r.c, true)) {
         r.active = false;
@@ -2662,11 +2677,11 @@ extern "C" cgs_status cgs_tuning_run_batch(cgs_batch b, const float *runtime,
       }
       double bn[18], d[24];
       st = cgs_expert_system(counters + r.c * 24, expert, bn, d, nullptr);
-      if (st != CGS_OK) return fail(st, "run %d: expert system rejected the counters", i);
-      for (int c = 0; c < 24; ++c) deltas[(size_t)i * 24 + c] = (float)d[c];
-      prof[i] = sp->h_idx[r.c];
-      st = take_uniform(i);
-      if (st != CGS_OK) return st;
+      if (st != CGS_OK) return release(fail(st, "run %d: expert system rejected the counters", i));
+      for (int c = 0; c < 24; ++c) deltas[(size_t)j * 24 + c] = (float)d[c];
+      prof[j] = sp->h_idx[r.c];
+      st = take_uniform(i, &u64[j]);
+      if (st != CGS_OK) return release(st);
       r.best = INFINITY;
       r.next = false;
       r.stop = false;
@@ -2674,19 +2689,19 @@ extern "C" cgs_status cgs_tuning_run_batch(cgs_batch b, const float *runtime,
     }
     if (n_active == 0) break;
     // the scored step and its first draw, then the further draws
-    st = cgs_batch_step(b, prof.data(), deltas.data(), u64.data(), nullptr, valid.data(),
+    st = cgs_batch_step(cur, prof.data(), deltas.data(), u64.data(), nullptr, valid.data(),
                         status.data());
     for (int k = 0; st == CGS_OK; ++k) {
       bool more = false;
-      for (int i = 0; i < n; ++i) {
-        Run &r = run[i];
+      for (int j = 0; j < m; ++j) {
+        Run &r = run[map[j]];
         if (!r.active || !r.drawing) continue;
-        if (status[i] != CGS_OK) { // no configuration left
+        if (status[j] != CGS_OK) { // no configuration left
           r.drawing = false;
           continue;
         }
-        const uint64_t l = valid[i];
-        if (test(i, l, false)) {
+        const uint64_t l = valid[j];
+        if (test(map[j], l, false)) {
           r.stop = true;
           r.drawing = false;
           continue;
@@ -2700,18 +2715,19 @@ extern "C" cgs_status cgs_tuning_run_batch(cgs_batch b, const float *runtime,
         else r.drawing = false;
       }
       if (!more) break;
-      for (int i = 0; i < n; ++i) {
-        u64[i] = 0;
+      for (int j = 0; j < m; ++j) {
+        const int i = map[j];
+        u64[j] = 0;
         if (run[i].active && run[i].drawing) {
-          st = take_uniform(i);
-          if (st != CGS_OK) return st;
+          st = take_uniform(i, &u64[j]);
+          if (st != CGS_OK) return release(st);
         }
       }
-      st = cgs_batch_draw(b, u64.data(), nullptr, valid.data(), status.data());
+      st = cgs_batch_draw(cur, u64.data(), nullptr, valid.data(), status.data());
     }
-    if (st != CGS_OK) return st;
-    for (int i = 0; i < n; ++i) {
-      Run &r = run[i];
+    if (st != CGS_OK) return release(st);
+    for (int j = 0; j < m; ++j) {
+      Run &r = run[map[j]];
       if (!r.active) continue;
       if (r.stop || !r.next) {
         r.active = false;
@@ -2720,9 +2736,25 @@ extern "C" cgs_status cgs_tuning_run_batch(cgs_batch b, const float *runtime,
         r.c = r.next_c;
       }
     }
+    if (n_active > 0 && 2 * n_active <= m && m >= 4) {
+      std::vector<cgs_session> ss;
+      std::vector<cgs_model> ms;
+      std::vector<int> keep;
+      for (int j = 0; j < m; ++j)
+        if (run[map[j]].active) {
+          keep.push_back(map[j]);
+          ss.push_back(cur->sess[j]);
+          ms.push_back(cur->models[j]);
+        }
+      cgs_batch nb = nullptr;
+      st = cgs_batch_create((int)ss.size(), ss.data(), ms.data(), nullptr, &nb);
+      if (st != CGS_OK) return release(st);
+      if (own) cgs_batch_destroy(own);
+      own = cur = nb;
+      map = keep;
+    }
   }
-  finish();
-  return CGS_OK;
+  return release(CGS_OK);
 }
 
 extern "C" void cgs_batch_destroy(cgs_batch b) { destroy_batch(b); }
