@@ -118,28 +118,34 @@ __device__ __forceinline__ void stage_words(const T *__restrict__ src, uint32_t 
   }
 }
 
-// Row `first + r` of `dst` = staged row src[r], for r < count; rows at or
-// past `cap` are dropped.  Words go out in batches so their LDS reads
-// overlap.
+// Row `first + r` of `dst` (W words per row) = staged row src[r], for
+// r < count; rows at or past `cap` are dropped.  When `digs` is given, its
+// row `first + r` (PW words) gets the row's digit words too.  Words go out
+// in batches so their LDS reads overlap.
 __device__ __forceinline__ void copy_rows_out(const uint32_t *lds, const uint32_t *src,
                                               uint32_t count, uint32_t W, FastDiv divW,
                                               uint32_t *__restrict__ dst, uint32_t first,
-                                              uint32_t cap) {
+                                              uint32_t cap, uint32_t *__restrict__ digs = nullptr,
+                                              uint32_t PW = 0) {
   if (first >= cap) return;
   const uint32_t words = min(count, cap - first) * W;
   uint32_t *out = dst + (uint64_t)first * W;
   for (uint32_t k0 = threadIdx.x; k0 < words; k0 += kStageBatch * kFitThreads) {
-    uint32_t v[kStageBatch];
+    uint32_t v[kStageBatch], rr[kStageBatch];
 #pragma unroll
     for (int b = 0; b < kStageBatch; ++b) {
-      const uint32_t k = k0 + b * kFitThreads;
-      const uint32_t r = fastdiv(min(k, words - 1), divW);
-      v[b] = lds[src[r] * W + (min(k, words - 1) - r * W)];
+      const uint32_t k = min(k0 + b * kFitThreads, words - 1);
+      rr[b] = fastdiv(k, divW);
+      v[b] = lds[src[rr[b]] * W + (k - rr[b] * W)];
     }
 #pragma unroll
     for (int b = 0; b < kStageBatch; ++b) {
       const uint32_t k = k0 + b * kFitThreads;
-      if (k < words) out[k] = v[b];
+      if (k < words) {
+        out[k] = v[b];
+        const uint32_t w = k - rr[b] * W;
+        if (digs && w < PW) digs[(uint64_t)(first + rr[b]) * PW + w] = v[b];
+      }
     }
   }
 }
@@ -330,7 +336,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_scatter(
     FitDev *__restrict__ fd, const SpaceDev *__restrict__ sp, const uint32_t *__restrict__ idx,
     const uint32_t *__restrict__ pts, const float *__restrict__ Y,
     const uint64_t *__restrict__ keys, const uint64_t *__restrict__ tile_off,
-    uint32_t *__restrict__ rows, uint32_t *__restrict__ test_rows) {
+    uint32_t *__restrict__ rows, uint32_t *__restrict__ digs, uint32_t *__restrict__ test_rows) {
   extern __shared__ uint32_t lds[]; // [kTile][W] rows, then [kTile][Cp] targets
   __shared__ int32_t s_scale[CGS_MAX_COUNTERS];
   __shared__ uint32_t s_src[2][kTile];
@@ -401,7 +407,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_scatter(
     }
     __syncthreads();
     const uint32_t base_tr = (uint32_t)tile_off[tile], base_te = first - base_tr;
-    copy_rows_out(lds, s_src[0], ntr, W, fd->divW, rows, base_tr, fd->n_train);
+    copy_rows_out(lds, s_src[0], ntr, W, fd->divW, rows, base_tr, fd->n_train, digs, PW);
     copy_rows_out(lds, s_src[1], nte, W, fd->divW, test_rows, base_te, fd->n_test);
   }
 }
@@ -920,13 +926,13 @@ __device__ __forceinline__ SlotSplit slot_split(uint32_t x) {
 // Rows of each chunk kept for the left and the right child:
 // cnt[ch] = n_left | n_right << 32.
 __global__ __launch_bounds__(kFitThreads) void fit_pcount(
-    const FitDev *__restrict__ fd, int L, const uint32_t *__restrict__ rows_in,
+    const FitDev *__restrict__ fd, int L, const uint32_t *__restrict__ digs_in,
     const uint32_t *__restrict__ seg_start, const uint32_t *__restrict__ chunk_start,
     const uint4 *__restrict__ slot_info, uint64_t *__restrict__ cnt,
     uint32_t *__restrict__ chunk_slot) {
   extern __shared__ uint32_t starts[]; // [K + 1] segment starts, [K + 1] chunk starts
   __shared__ uint64_t scratch[kFitThreads / 64];
-  const uint32_t set = L & 1, K = fd->lvl_K[set], NCH = fd->lvl_NCH[set], W = fd->W;
+  const uint32_t set = L & 1, K = fd->lvl_K[set], NCH = fd->lvl_NCH[set], PW = fd->PW;
   const uint32_t t = threadIdx.x;
   uint32_t *ss = starts, *cs = starts + K + 1;
   stage_starts(seg_start, chunk_start, K, ss, cs);
@@ -935,7 +941,7 @@ __global__ __launch_bounds__(kFitThreads) void fit_pcount(
     const SlotSplit s = slot_split(slot_info[c.slot].x);
     uint64_t f = 0;
     if (t < c.nr) {
-      const bool left = row_digit(rows_in + (uint64_t)(c.first + t) * W, s.j) <= s.thr;
+      const bool left = row_digit(digs_in + (uint64_t)(c.first + t) * PW, s.j) <= s.thr;
       if (left ? s.lopen : s.ropen) f = left ? 1ull : (1ull << 32);
     }
     const uint64_t sum = block_sum<kFitThreads>(f, scratch);
@@ -952,7 +958,8 @@ __global__ __launch_bounds__(kFitThreads) void fit_partition(
     const FitDev *__restrict__ fd, int L, const uint32_t *__restrict__ rows_in,
     uint32_t *__restrict__ rows_out, const uint32_t *__restrict__ seg_start,
     const uint32_t *__restrict__ chunk_start, const uint64_t *__restrict__ pre,
-    const uint4 *__restrict__ slot_info, const uint32_t *__restrict__ chunk_slot) {
+    const uint4 *__restrict__ slot_info, const uint32_t *__restrict__ chunk_slot,
+    uint32_t *__restrict__ digs_out) {
   extern __shared__ uint32_t rl[]; // [kTile][W]
   __shared__ uint32_t s_src[2][kTile];
   __shared__ uint64_t scratch[kFitThreads / 64];
@@ -988,11 +995,12 @@ __global__ __launch_bounds__(kFitThreads) void fit_partition(
     // offsets within each child's segment (info.y, info.z): kept rows of
     // this segment's earlier chunks
     const uint32_t nl = (uint32_t)tot, nrr = (uint32_t)(tot >> 32);
-    if (nl) copy_rows_out(rl, s_src[0], nl, W, fd->divW, rows_out, info.y + (uint32_t)before,
-                          fd->n_train);
+    // rows and their digit words (the compact copy fit_pcount reads)
+    const uint32_t PW = fd->PW;
+    const uint32_t bl = info.y + (uint32_t)before, br = info.z + (uint32_t)(before >> 32);
+    if (nl) copy_rows_out(rl, s_src[0], nl, W, fd->divW, rows_out, bl, fd->n_train, digs_out, PW);
     if (nrr)
-      copy_rows_out(rl, s_src[1], nrr, W, fd->divW, rows_out, info.z + (uint32_t)(before >> 32),
-                    fd->n_train);
+      copy_rows_out(rl, s_src[1], nrr, W, fd->divW, rows_out, br, fd->n_train, digs_out, PW);
   }
 }
 
@@ -1225,6 +1233,9 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   const size_t zero_end = off; // the histograms and node sums start at zero
   const size_t o_rows0 = take((size_t)n_train * h.W * 4);
   const size_t o_rows1 = take(D > 1 ? (size_t)n_train * h.W * 4 : 0);
+  // the training rows' digit words alone, per row parity (read by fit_pcount)
+  const size_t o_dig0 = take((size_t)n_train * h.PW * 4);
+  const size_t o_dig1 = take(D > 1 ? (size_t)n_train * h.PW * 4 : 0);
   const size_t o_test = take((size_t)n_test * h.W * 4);
   const size_t o_ncount = take(n_nodes * 4);
   const size_t o_nmean = take(n_nodes * C * 4);
@@ -1272,6 +1283,8 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   int64_t *nsum = reinterpret_cast<int64_t *>(base + o_nsum);
   uint32_t *rows[2] = {reinterpret_cast<uint32_t *>(base + o_rows0),
                        reinterpret_cast<uint32_t *>(base + o_rows1)};
+  uint32_t *digs[2] = {reinterpret_cast<uint32_t *>(base + o_dig0),
+                       reinterpret_cast<uint32_t *>(base + o_dig1)};
   uint32_t *test_rows = reinterpret_cast<uint32_t *>(base + o_test);
   uint32_t *ncount = reinterpret_cast<uint32_t *>(base + o_ncount);
   uint8_t *nstate = reinterpret_cast<uint8_t *>(base + o_nstate);
@@ -1335,7 +1348,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
     fit_scatter<<<g_pts, kFitThreads, scatter_lds, stream>>>(fd, in.d_space, in.d_idx,
                                                             in.d_points, in.d_targets,
                                                             in.d_keys, tile_off, rows[0],
-                                                            test_rows);
+                                                            digs[0], test_rows);
     fit_root_sums<<<g_rows, kFitThreads, 0, stream>>>(fd, rows[0], nsum);
     fit_root<<<1, 64, 0, stream>>>(fd, ncount, nsum, w->nmean, nstate);
     if (D > 0)
@@ -1360,11 +1373,11 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
                                                   slot_of[s1], slot_of[s], der_parent, der_sib,
                                                   slot_info, (uint32_t)kcap);
         fit_pcount<<<g_chunks, kFitThreads, starts_lds, stream>>>(
-            fd, (int)L, rows[s], seg_start[s], chunk_start[s], slot_info, chunk_cnt, chunk_slot);
+            fd, (int)L, digs[s], seg_start[s], chunk_start[s], slot_info, chunk_cnt, chunk_slot);
         fit_excl_scan<<<1, kScanThreads, 0, stream>>>(chunk_cnt, chunk_pre, &fd->lvl_NCH[s], 0);
         fit_partition<<<g_chunks, kFitThreads, tile_lds, stream>>>(
             fd, (int)L, rows[s], rows[s1], seg_start[s], chunk_start[s], chunk_pre, slot_info,
-            chunk_slot);
+            chunk_slot, digs[s1]);
       }
     }
     fit_test<<<g_test, kFitThreads, test_lds, stream>>>(fd, test_rows, w->nodes, w->nmean,
