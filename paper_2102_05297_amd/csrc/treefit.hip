@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "device_common.h"
@@ -1011,14 +1012,16 @@ __global__ __launch_bounds__(kFitThreads) void fit_partition(
 // C lanes of one row reading one node's values together.  Each workgroup
 // writes its sums to part[q * gridDim.x + blockIdx.x], q = 3 d + (0: sum |e|,
 // 1: sum of the low 32 bits of e^2, 2: sum of the high 32 bits).
+// ND >= D + 1 depths are evaluated (a few instantiations cover every D).
+template <int ND>
 __global__ __launch_bounds__(kFitThreads) void fit_test(const FitDev *__restrict__ fd,
                                                         const uint32_t *__restrict__ test_rows,
                                                         const uint16_t *__restrict__ nodes,
                                                         const int32_t *__restrict__ nmean,
                                                         uint64_t *__restrict__ part) {
   extern __shared__ uint32_t lds[]; // [kTile][W] rows, [kTile][ND] path, nodes
-  constexpr int ND = CGS_MAX_DEPTH + 1;
-  __shared__ uint64_t s_red[kFitThreads / 64][3 * ND];
+  constexpr int NQ = 3 * (CGS_MAX_DEPTH + 1); // partial sums per workgroup (all depths)
+  __shared__ uint64_t s_red[kFitThreads / 64][NQ];
   const uint32_t t = threadIdx.x, n = fd->n_test, C = fd->C, PW = fd->PW, W = fd->W;
   const uint32_t D = fd->D, n_int = (1u << D) - 1;
   uint32_t *rl = lds;
@@ -1056,14 +1059,16 @@ __global__ __launch_bounds__(kFitThreads) void fit_test(const FitDev *__restrict
     }
     __syncthreads();
     if (active) {
-      // four rows per round: their node-value loads are in flight together
-      for (uint32_t r = rs; r < nr; r += 4 * RP) {
+      // four rows per round: their node-value loads are in flight together;
+      // only the last round of a tile can hold rows past its end (TAIL)
+      auto round = [&](uint32_t r, auto tail) {
+        constexpr bool TAIL = decltype(tail)::value;
         int32_t m[4][ND], q[4];
         bool ok[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const uint32_t ru = r + u * RP;
-          ok[u] = ru < nr;
+          ok[u] = !TAIL || ru < nr;
           const uint32_t rr = ok[u] ? ru : r; // r < nr
           q[u] = (int32_t)rl[rr * W + PW + c];
           const uint32_t *pr = path + rr * ND;
@@ -1076,13 +1081,16 @@ __global__ __launch_bounds__(kFitThreads) void fit_test(const FitDev *__restrict
           for (int d = 0; d < ND; ++d) {
             // |m|, |q| <= 2^22: |e| < 2^24 and e^2 < 2^48; repeated rows
             // count zero, depths past D are never read
-            const int32_t e = ok[u] ? m[u][d] - q[u] : 0;
+            const int32_t e = (!TAIL || ok[u]) ? m[u][d] - q[u] : 0;
             const uint32_t ae = (uint32_t)(e < 0 ? -e : e);
             A[d] += ae;
             B[d] += (uint64_t)ae * ae;
           }
         }
-      }
+      };
+      uint32_t r = rs;
+      for (; r + 3 * RP < nr; r += 4 * RP) round(r, std::false_type{});
+      if (r < nr) round(r, std::true_type{});
     }
   }
 #pragma unroll
@@ -1095,8 +1103,9 @@ __global__ __launch_bounds__(kFitThreads) void fit_test(const FitDev *__restrict
       s_red[t >> 6][3 * d + 2] = h;
     }
   }
+  for (uint32_t q = 3 * ND + (t & 63u); q < (uint32_t)NQ; q += 64) s_red[t >> 6][q] = 0;
   __syncthreads();
-  if (t < 3 * ND) {
+  if (t < (uint32_t)NQ) {
     uint64_t s = 0;
     for (int w = 0; w < kFitThreads / 64; ++w) s += s_red[w][t];
     part[(uint64_t)t * gridDim.x + blockIdx.x] = s;
@@ -1324,7 +1333,10 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
   if (e == hipSuccess) e = allow_lds(fit_split, split_lds);
   if (e == hipSuccess) e = allow_lds(fit_pcount, starts_lds);
   if (e == hipSuccess) e = allow_lds(fit_partition, tile_lds);
-  if (e == hipSuccess) e = allow_lds(fit_test, test_lds);
+  static_assert(CGS_MAX_DEPTH + 1 <= 15, "fit_test instantiations");
+  auto kt = D + 1 <= 5 ? fit_test<5> : D + 1 <= 9 ? fit_test<9> : D + 1 <= 13 ? fit_test<13>
+                                                                               : fit_test<15>;
+  if (e == hipSuccess) e = allow_lds(kt, test_lds);
   if (e == hipSuccess) e = allow_lds(fit_scatter, scatter_lds);
   if (e != hipSuccess) return e;
 
@@ -1380,8 +1392,7 @@ hipError_t tree_fit_run(const TreeFitIn &in, TreeFitOut &out, TreeFitWork **work
             chunk_slot, digs[s1]);
       }
     }
-    fit_test<<<g_test, kFitThreads, test_lds, stream>>>(fd, test_rows, w->nodes, w->nmean,
-                                                        test_part);
+    kt<<<g_test, kFitThreads, test_lds, stream>>>(fd, test_rows, w->nodes, w->nmean, test_part);
     fit_select<<<1, kScanThreads, 0, stream>>>(fd, test_part, g_test);
     e = hipGetLastError();
   }
