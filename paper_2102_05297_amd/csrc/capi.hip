@@ -1928,6 +1928,40 @@ extern "C" cgs_status cgs_search_step(cgs_session s, cgs_model m, uint64_t profi
   return CGS_OK;
 }
 
+// n_steps steps of the counter-guided search, each the work of one
+// cgs_search_step with measured counters plus one cgs_sample_next, run from
+// host code without returning to the caller in between.
+extern "C" cgs_status cgs_search_run(cgs_session s, cgs_model m, int n_steps,
+                                     const double *measured, const cgs_expert_params *expert,
+                                     const uint64_t *u64, uint64_t *raw_out, uint64_t *valid_out,
+                                     double *step_us) {
+  if (!s || !m || !u64 || !raw_out || (n_steps > 0 && (!measured || !expert)))
+    return fail(CGS_EINVAL, "NULL argument");
+  if (n_steps < 0) return fail(CGS_EINVAL, "negative n_steps");
+  for (int i = 0; i <= n_steps; ++i) {
+    raw_out[i] = CGS_NO_PROFILE;
+    if (valid_out) valid_out[i] = CGS_NO_PROFILE;
+  }
+  cgs_status st = cgs_search_step(s, m, CGS_NO_PROFILE, nullptr, nullptr, nullptr);
+  uint64_t raw = 0, valid = 0;
+  if (st == CGS_OK) st = cgs_sample_next(s, u64[0], &raw, &valid);
+  if (st != CGS_OK) return st;
+  raw_out[0] = raw;
+  if (valid_out) valid_out[0] = valid;
+  for (int i = 0; i < n_steps; ++i) {
+    const auto t0 = std::chrono::steady_clock::now();
+    st = cgs_search_step(s, m, raw, nullptr, measured + (size_t)i * 24, expert + i);
+    if (st == CGS_OK) st = cgs_sample_next(s, u64[i + 1], &raw, &valid);
+    if (st != CGS_OK) return st;
+    if (step_us)
+      step_us[i] =
+          std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    raw_out[i + 1] = raw;
+    if (valid_out) valid_out[i + 1] = valid;
+  }
+  return CGS_OK;
+}
+
 extern "C" cgs_status cgs_search_step_neighbourhood(cgs_session s, cgs_model m,
                                                     uint64_t profile_raw, int radius,
                                                     const float *delta, const double *measured,

@@ -57,3 +57,23 @@ def test_c2_hundred_steps_bit_exact():
         assert info.n_active == r["n_active"], i
         if i > 0:
             assert info.s_min == np.float32(r["s_min"]) and info.s_max == np.float32(r["s_max"]), i
+
+
+def test_c2_hundred_steps_in_one_call():
+    """cgs_search_run: the whole search from host code in the library gives
+    the oracle's 101 picks."""
+    m = cgs()
+    ref = golden("c2_search.json")
+    spec = synth.space_c2()
+    sp = m.Space.from_spec(spec)
+    model = m.ForestModel.from_spec(sp, synth.forest_c2(spec))
+    sess = m.Session(sp)
+    U, pcs, thr = _inputs()
+    eps = [m.cgs_expert_params(inst_reaction=0.7, volta=0, reserved=0, cores=ref["cores"],
+                               threads=float(thr[i])) for i in range(100)]
+    raw, val, t_us = sess.search_run(model, pcs, eps, U)
+    assert val.tolist() == [r["pick"] for r in ref["steps"]]
+    assert raw.tolist() == [r["pick_raw"] for r in ref["steps"]]
+    assert len(t_us) == 100 and (t_us > 0).all()
+    with pytest.raises(ValueError):
+        sess.search_run(model, pcs, eps[:99], U)
