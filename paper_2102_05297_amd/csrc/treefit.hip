@@ -23,15 +23,19 @@
 //    e^2; the selected depth minimises (sum|e|, sum e^2, depth).
 //
 // Layout: every point becomes a row of W = PW + C 32-bit words: the digits
-// (one byte per parameter, PW = ceil(P/4) words), then q[C].  The training
-// rows of the nodes still searched are kept contiguous, segment by segment in
-// heap order, and are repartitioned into the next level's segments after each
-// level.  Segments are cut into chunks of at most 256 rows; the partition
-// counts each chunk's rows per child, scans the counts and moves every chunk
-// to fixed offsets, so the row order is stable and no two workgroups contend
-// for an output cursor.  Histograms hold, per open node, the sum of q for
-// every (parameter, digit, counter) plus a count column:
-// [sum_j R_j][C + 1] int64.
+// (one byte per parameter, PW = ceil(P/4) words), then q[C]; the training
+// rows' digit words are also kept alone (PW words per row) for the chunk
+// counts.  The training rows of the nodes still searched are kept
+// contiguous, one segment per node, and are repartitioned into the next
+// level's segments after each level.  Segments are cut into chunks of at
+// most 256 rows; the partition counts each chunk's rows per child, scans the
+// counts and moves every chunk to fixed offsets, so the row order within a
+// segment is stable and no two workgroups contend for an output cursor.
+// Histograms hold, per open node, the sum of q for every (parameter, digit,
+// counter) plus a count column: [sum_j R_j][C + 1] int64.  Of two open
+// siblings only the one with fewer rows is histogrammed from its rows (its
+// segment is laid out first); the other's histogram is the parent's minus
+// it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
