@@ -844,18 +844,51 @@ extern "C" cgs_status cgs_model_fit_poly(cgs_space sp, uint64_t n, int n_counter
   m->n_counters = C;
   m->poly = pd;
   m->stride = (sp->n_valid + 63) & ~(uint64_t)63;
+  // each subspace's points in input order (a stable counting sort on the
+  // host: digits of the points' raw indices, parameter 0 most significant)
+  std::vector<uint32_t> h_off((size_t)S + 1, 0), h_list, h_sub(n);
+  {
+    const int P = (int)sp->radix.size();
+    std::vector<uint32_t> dg(P);
+    for (uint64_t i = 0; i < n; ++i) {
+      h_sub[i] = (uint32_t)S; // points outside the valid list: in no list (the fit flags them)
+      if (points[i] >= sp->n_valid) continue;
+      uint64_t raw = sp->h_idx[points[i]];
+      for (int j = P - 1; j >= 0; --j) {
+        dg[j] = (uint32_t)(raw % (uint64_t)sp->radix[j]);
+        raw /= (uint64_t)sp->radix[j];
+      }
+      uint32_t s = 0;
+      for (int b = 0; b < pd.B; ++b) s |= dg[pd.bin_params[b]] << b;
+      h_sub[i] = s;
+      ++h_off[(size_t)s + 1];
+    }
+    for (int s = 0; s < S; ++s) h_off[(size_t)s + 1] += h_off[s];
+    h_list.resize(h_off[S]);
+    std::vector<uint32_t> pos(h_off.begin(), h_off.end() - 1);
+    for (uint64_t i = 0; i < n; ++i)
+      if (h_sub[i] < (uint32_t)S) h_list[pos[h_sub[i]]++] = (uint32_t)i;
+  }
   uint32_t *d_pts = nullptr, *d_sub = nullptr, *d_pairs = nullptr, *d_err = nullptr;
+  uint32_t *d_list = nullptr, *d_off = nullptr;
   float *d_y = nullptr;
-  double *d_F = nullptr, *d_G = nullptr;
+  double *d_F = nullptr, *d_G = nullptr, *d_Gp = nullptr;
+  // the Gram sums of each subspace split into parts when there are few
+  // subspaces (a partial buffer, only when it stays modest)
+  uint32_t parts = poly_gram_parts(S, (uint32_t)pairs.size());
+  if ((uint64_t)parts * S * Ta * Ta * 8 > ((uint64_t)1 << 30)) parts = 1;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(sp->stream);
     dfree(d_pts);
+    dfree(d_list);
+    dfree(d_off);
     dfree(d_sub);
     dfree(d_pairs);
     dfree(d_err);
     dfree(d_y);
     dfree(d_F);
     dfree(d_G);
+    dfree(d_Gp);
   };
   hipError_t e = dalloc(&m->d_poly, 1);
   if (e == hipSuccess) e = dalloc(&m->d_beta64, (size_t)S * T * C);
@@ -864,8 +897,16 @@ extern "C" cgs_status cgs_model_fit_poly(cgs_space sp, uint64_t n, int n_counter
   if (e == hipSuccess) e = dalloc(&d_pts, n);
   if (e == hipSuccess) e = dalloc(&d_y, n * (size_t)C);
   if (e == hipSuccess) e = dalloc(&d_sub, n);
+  if (e == hipSuccess) e = dalloc(&d_list, std::max<size_t>(1, h_list.size()));
+  if (e == hipSuccess) e = dalloc(&d_off, h_off.size());
+  if (e == hipSuccess && !h_list.empty())
+    e = hipMemcpyAsync(d_list, h_list.data(), h_list.size() * 4, hipMemcpyHostToDevice,
+                       sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_off, h_off.data(), h_off.size() * 4, hipMemcpyHostToDevice, sp->stream);
   if (e == hipSuccess) e = dalloc(&d_F, n * (size_t)Ta);
   if (e == hipSuccess) e = dalloc(&d_G, (size_t)S * Ta * Ta);
+  if (e == hipSuccess && parts > 1) e = dalloc(&d_Gp, (size_t)parts * S * Ta * Ta);
   if (e == hipSuccess) e = dalloc(&d_pairs, pairs.size());
   if (e == hipSuccess) e = dalloc(&d_err, 1);
   if (e == hipSuccess)
@@ -885,7 +926,8 @@ extern "C" cgs_status cgs_model_fit_poly(cgs_space sp, uint64_t n, int n_counter
   if (e == hipSuccess) e = hipEventRecord(ev[0], sp->stream);
   if (e == hipSuccess)
     e = launch_poly_fit(m->d_poly, T, C, S, sp->d_desc, sp->d_idx, (uint32_t)sp->n_valid, d_pts,
-                        d_y, (uint32_t)n, d_F, d_sub, d_pairs, (uint32_t)pairs.size(), d_G,
+                        d_y, (uint32_t)n, d_F, d_sub, d_list, d_off, d_pairs,
+                        (uint32_t)pairs.size(), d_G, d_Gp,
                         m->d_beta64, m->d_beta32, d_err, sp->stream);
   if (e == hipSuccess) e = hipEventRecord(ev[1], sp->stream);
   uint32_t err = 0;

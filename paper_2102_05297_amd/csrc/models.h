@@ -64,10 +64,17 @@ size_t poly_solve_lds(int T, int C);
 hipError_t launch_poly_design(const SpaceDev *d_space, const uint32_t *d_idx, uint32_t nv,
                               const uint32_t *d_allowed, uint64_t *d_tile_cnt,
                               uint64_t *d_tile_off, uint32_t *d_out, hipStream_t stream);
+// Parts each subspace's Gram sums are split into (a partial Gram buffer
+// of parts * S * (T + C)^2 doubles is needed when above 1).
+uint32_t poly_gram_parts(int S, uint32_t n_pairs);
+// d_list[d_off[s] .. d_off[s + 1]): the points (positions in d_pts) of
+// subspace s in input order.  d_Gp: the partial Gram buffer, or NULL (no
+// parts).
 hipError_t launch_poly_fit(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,
                            const uint32_t *d_idx, uint32_t nv, const uint32_t *d_pts,
                            const float *d_Y, uint32_t n, double *d_F, uint32_t *d_sub,
-                           const uint32_t *d_pairs, uint32_t n_pairs, double *d_G,
+                           const uint32_t *d_list, const uint32_t *d_off,
+                           const uint32_t *d_pairs, uint32_t n_pairs, double *d_G, double *d_Gp,
                            double *d_beta64, float *d_beta32, uint32_t *d_err,
                            hipStream_t stream);
 hipError_t launch_poly_eval(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,

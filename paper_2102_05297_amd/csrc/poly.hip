@@ -28,7 +28,7 @@ namespace {
 
 constexpr int kPolyThreads = 256;
 constexpr int kGB = 32;        // Gram block edge
-constexpr int kGramChunk = 64; // points staged per round of the Gram kernel
+constexpr int kGramChunk = 128; // points staged per round of the Gram kernel
 constexpr int kEvalThreads = 1024; // one workgroup per CU holds the coefficients
 constexpr double kRidge = 1e-9;
 
@@ -131,39 +131,53 @@ __global__ __launch_bounds__(kPolyThreads) void poly_features(
   }
 }
 
-// One kGB x kGB block (rows a0.., columns b0..) of every subspace's Gram
-// matrix of the columns of F: blockIdx.x = subspace, blockIdx.y = block pair
-// (a-block <= b-block).  The points are visited in input order, so the sums
-// are the same on every run.
+// Gram matrix [F | Y]^T [F | Y] of one subspace's points, one 32 x 32 block
+// of it per workgroup: blockIdx.x = subspace, blockIdx.y = block pair
+// (a-block <= b-block), blockIdx.z = part: part q of gridDim.z sums the q-th
+// contiguous share of list[off[s] .. off[s + 1]) (the subspace's points in
+// input order) into G + q * S * Ta^2; poly_gram_sum adds the parts in order,
+// so the sums are the same on every run.  The rows of a chunk of points are
+// staged in LDS with all loads in flight.
 __global__ __launch_bounds__(kPolyThreads) void poly_gram(const PolyDev *__restrict__ pd,
                                                           const double *__restrict__ F,
-                                                          const uint32_t *__restrict__ sub,
-                                                          uint32_t n,
+                                                          const uint32_t *__restrict__ list,
+                                                          const uint32_t *__restrict__ off,
                                                           const uint32_t *__restrict__ pairs,
                                                           double *__restrict__ G) {
-  __shared__ double fa[kGramChunk][kGB + 1], fb[kGramChunk][kGB + 1];
-  __shared__ uint32_t list[kGramChunk];
-  __shared__ uint64_t scratch[kPolyThreads / 64];
+  extern __shared__ double gl[]; // fa[kGramChunk][kGB + 1], fb[kGramChunk][kGB + 1]
+  double(*fa)[kGB + 1] = reinterpret_cast<double(*)[kGB + 1]>(gl);
+  double(*fb)[kGB + 1] = reinterpret_cast<double(*)[kGB + 1]>(gl + kGramChunk * (kGB + 1));
   const uint32_t T = pd->T, Ta = T + pd->C, s = blockIdx.x;
   const uint32_t pr = pairs[blockIdx.y];
   const uint32_t a0 = (pr & 0xffffu) * kGB, b0 = (pr >> 16) * kGB;
   const uint32_t t = threadIdx.x;
   const uint32_t ra = (t / (kGB / 2)) * 2, cb = (t % (kGB / 2)) * 2; // 2 x 2 outputs
+  const uint32_t q0 = off[s], len = off[s + 1] - q0;
+  const uint32_t p0 = q0 + (uint32_t)((uint64_t)len * blockIdx.z / gridDim.z);
+  const uint32_t p1 = q0 + (uint32_t)((uint64_t)len * (blockIdx.z + 1) / gridDim.z);
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  for (uint32_t base = 0; base < n; base += kGramChunk) {
-    // points of this subspace among the next kGramChunk, in order
-    const uint32_t i = base + t;
-    const bool f = t < kGramChunk && i < n && sub[i] == s;
-    uint64_t tot;
-    const uint64_t r = block_excl_scan<kPolyThreads>(f ? 1ull : 0ull, scratch, tot);
-    if (f) list[r] = i;
+  constexpr int kB = 8;
+  for (uint32_t base = p0; base < p1; base += kGramChunk) {
+    const uint32_t m = min((uint32_t)kGramChunk, p1 - base);
     __syncthreads();
-    const uint32_t m = (uint32_t)tot;
-    for (uint32_t e = t; e < m * kGB; e += kPolyThreads) {
-      const uint32_t p = e / kGB, c = e % kGB;
-      const double *row = F + (uint64_t)list[p] * Ta;
-      fa[p][c] = a0 + c < Ta ? row[a0 + c] : 0.0;
-      fb[p][c] = b0 + c < Ta ? row[b0 + c] : 0.0;
+    for (uint32_t e0 = t; e0 < m * kGB; e0 += kB * kPolyThreads) {
+      double va[kB], vb[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const uint32_t e = min(e0 + u * kPolyThreads, m * kGB - 1);
+        const uint32_t p = e / kGB, c = e % kGB;
+        const double *row = F + (uint64_t)list[base + p] * Ta;
+        va[u] = a0 + c < Ta ? row[a0 + c] : 0.0;
+        vb[u] = b0 + c < Ta ? row[b0 + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const uint32_t e = e0 + u * kPolyThreads;
+        if (e < m * kGB) {
+          fa[e / kGB][e % kGB] = va[u];
+          fb[e / kGB][e % kGB] = vb[u];
+        }
+      }
     }
     __syncthreads();
     for (uint32_t p = 0; p < m; ++p) {
@@ -173,9 +187,8 @@ __global__ __launch_bounds__(kPolyThreads) void poly_gram(const PolyDev *__restr
       acc[1][0] += x1 * y0;
       acc[1][1] += x1 * y1;
     }
-    __syncthreads();
   }
-  double *Gs = G + (uint64_t)s * Ta * Ta;
+  double *Gs = G + ((uint64_t)blockIdx.z * gridDim.x + s) * Ta * Ta;
   for (int u = 0; u < 2; ++u)
     for (int v = 0; v < 2; ++v) {
       const uint32_t a = a0 + ra + u, b = b0 + cb + v;
@@ -184,6 +197,18 @@ __global__ __launch_bounds__(kPolyThreads) void poly_gram(const PolyDev *__restr
         Gs[(uint64_t)b * Ta + a] = acc[u][v];
       }
     }
+}
+
+// G[e] = sum of the parts' entries e, parts in order (Gp: [parts][S Ta^2]).
+__global__ __launch_bounds__(256) void poly_gram_sum(const double *__restrict__ Gp,
+                                                     uint64_t total, uint32_t parts,
+                                                     double *__restrict__ G) {
+  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * 256) {
+    double x = Gp[e];
+    for (uint32_t q = 1; q < parts; ++q) x += Gp[(uint64_t)q * total + e];
+    G[e] = x;
+  }
 }
 
 __device__ __forceinline__ uint32_t pk(uint32_t i, uint32_t j) { return i * (i + 1) / 2 + j; }
@@ -385,19 +410,36 @@ hipError_t launch_poly_design(const SpaceDev *d_space, const uint32_t *d_idx, ui
   return hipGetLastError();
 }
 
+uint32_t poly_gram_parts(int S, uint32_t n_pairs) {
+  const uint64_t wgs = (uint64_t)S * n_pairs;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, 1024 / std::max<uint64_t>(wgs, 1)));
+}
+
 hipError_t launch_poly_fit(const PolyDev *d_pd, int T, int C, int S, const SpaceDev *d_space,
                            const uint32_t *d_idx, uint32_t nv, const uint32_t *d_pts,
                            const float *d_Y, uint32_t n, double *d_F, uint32_t *d_sub,
-                           const uint32_t *d_pairs, uint32_t n_pairs, double *d_G,
+                           const uint32_t *d_list, const uint32_t *d_off,
+                           const uint32_t *d_pairs, uint32_t n_pairs, double *d_G, double *d_Gp,
                            double *d_beta64, float *d_beta32, uint32_t *d_err,
                            hipStream_t stream) {
   const uint64_t fe = (uint64_t)n * (T + C);
   const uint32_t gf = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8192, (fe + 255) / 256));
   poly_features<<<gf, kPolyThreads, 0, stream>>>(d_pd, d_space, d_idx, nv, d_pts, d_Y, n, d_F,
                                                  d_sub, d_err);
-  poly_gram<<<dim3(S, n_pairs), kPolyThreads, 0, stream>>>(d_pd, d_F, d_sub, n, d_pairs, d_G);
+  const size_t gram_lds = (size_t)2 * kGramChunk * (kGB + 1) * sizeof(double);
+  hipError_t e = allow_lds(poly_gram, gram_lds);
+  if (e != hipSuccess) return e;
+  // few (subspace, block pair) workgroups: each subspace's points in parts
+  const uint32_t parts = d_Gp ? poly_gram_parts(S, n_pairs) : 1u;
+  poly_gram<<<dim3(S, n_pairs, parts), kPolyThreads, gram_lds, stream>>>(
+      d_pd, d_F, d_list, d_off, d_pairs, parts > 1 ? d_Gp : d_G);
+  if (parts > 1) {
+    const uint64_t total = (uint64_t)S * (T + C) * (T + C);
+    const uint32_t g = (uint32_t)std::min<uint64_t>(4096, (total + 255) / 256);
+    poly_gram_sum<<<g, 256, 0, stream>>>(d_Gp, total, parts, d_G);
+  }
   const size_t lds = poly_solve_lds(T, C);
-  hipError_t e = allow_lds(poly_solve, lds);
+  e = allow_lds(poly_solve, lds);
   if (e != hipSuccess) return e;
   poly_solve<<<S, kPolyThreads, lds, stream>>>(d_pd, d_G, poly_solve_cc(T, C), d_beta64,
                                                d_beta32, d_err);
