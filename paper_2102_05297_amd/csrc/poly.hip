@@ -237,11 +237,27 @@ __global__ __launch_bounds__(kPolyThreads) void poly_solve(const PolyDev *__rest
     }
     return;
   }
-  for (uint32_t i = t; i < T; i += kPolyThreads)
-    for (uint32_t j = 0; j <= i; ++j) L[pk(i, j)] = Gs[(uint64_t)i * Ta + j];
-  if (t == 0) {
+  // G's lower triangle into L by the whole workgroup, 8 loads per thread in
+  // flight (one thread per row would wait for up to T loads in turn)
+  constexpr int kB = 8;
+  const uint32_t nt = T * T;
+  for (uint32_t e0 = t; e0 < nt; e0 += kB * kPolyThreads) {
+    double v[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const uint32_t e = min(e0 + u * kPolyThreads, nt - 1);
+      v[u] = Gs[(uint64_t)(e / T) * Ta + e % T];
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const uint32_t e = e0 + u * kPolyThreads, i = e / T, j = e % T;
+      if (e < nt && j <= i) L[pk(i, j)] = v[u];
+    }
+  }
+  __syncthreads();
+  if (t == 0) { // the trace in index order
     double tr = 0.0;
-    for (uint32_t i = 0; i < T; ++i) tr += Gs[(uint64_t)i * Ta + i];
+    for (uint32_t i = 0; i < T; ++i) tr += L[pk(i, i)];
     s_lam = kRidge * tr / (double)T;
   }
   __syncthreads();
@@ -271,9 +287,18 @@ __global__ __launch_bounds__(kPolyThreads) void poly_solve(const PolyDev *__rest
   for (uint32_t c0 = 0; c0 < C; c0 += CC) {
     const uint32_t cc = min(CC, C - c0);
     __syncthreads();
-    for (uint32_t e = t; e < T * cc; e += kPolyThreads) {
-      const uint32_t i = e / cc, c = e % cc;
-      z[i * CC + c] = Gs[(uint64_t)i * Ta + T + c0 + c];
+    for (uint32_t e0 = t; e0 < T * cc; e0 += kB * kPolyThreads) {
+      double v[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const uint32_t e = min(e0 + u * kPolyThreads, T * cc - 1);
+        v[u] = Gs[(uint64_t)(e / cc) * Ta + T + c0 + e % cc];
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const uint32_t e = e0 + u * kPolyThreads;
+        if (e < T * cc) z[(e / cc) * CC + e % cc] = v[u];
+      }
     }
     for (uint32_t i = 0; i < T; ++i) {
       __syncthreads();
