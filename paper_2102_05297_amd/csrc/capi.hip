@@ -1303,7 +1303,8 @@ hipError_t mlp_forward_rows(cgs_model m, const uint32_t *d_cfg, const int32_t *d
   a.h1out = m->d_h1;
   a.h2out = m->d_h2;
   a.yout = m->d_y;
-  return launch_mlp_forward(a, true, m->space->stream);
+  return launch_mlp_train_forward(a, m->d_theta, m->d_theta + m->off_w2, m->d_theta + m->off_w3,
+                                  m->space->stream);
 }
 
 // Forward + loss + backward of n rows into m->d_grad; loss to *d_loss.

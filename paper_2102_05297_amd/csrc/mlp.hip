@@ -17,9 +17,15 @@
 //   kperm(s, h, j) = 32(s/2) + 16(s%2) + 8(j/4) + 4h + (j%4)
 // GELU uses erf from Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7), far
 // below the bf16 rounding of the activations.
+//
+// Training runs the forward pass as one GEMM per layer (gemm_bf16 with the
+// bias and GELU in its epilogue, 32 x 32 output tiles, so a batch of a few
+// hundred configurations still spreads over tens of workgroups) and the
+// backward pass with the same GEMM kernel.
 #include <algorithm>
 
 #include "device_common.h"
+#include "models.h"
 
 namespace cgs {
 
@@ -62,205 +68,6 @@ __device__ __forceinline__ float gelu_grad(float z) {
   float c, p;
   normal_cdf_pdf(z, c, p);
   return c + z * p;
-}
-
-// ---------------------------------------------------------------- forward
-// TRAIN: configurations cfg_raw[batch[i]] (batch may be null: i), writes
-// X (bf16 [n][K1]), Z1, Z2 (fp32 [n][H]), H1, H2 (bf16 [n][H]) and the
-// unclamped output Y (fp32 [n][Cp]).  Otherwise: the valid configurations
-// idx[0..n) and P[c][l] = max(y_c, 0).
-//
-// H <= 256: layer-1 block r is computed right before layer 2 consumes its
-// two K steps, accumulating all H/32 layer-2 blocks at once.
-// H = 512: each wave first parks its layer-1 output in a private LDS region
-// in fragment order ([r][s'][lane][8] bf16, conflict-free 16-byte reads),
-// then accumulates layer 2 in groups of 8 output blocks.
-// LDSW: packed weights staged in LDS once per workgroup (H <= 256).
-template <int H, int NB3, int S1, bool TRAIN, bool LDSW>
-__global__ __launch_bounds__(LDSW ? 512 : 256) void mlp_forward(MlpFwdArgs a) {
-  constexpr int NB = H / 32;
-  constexpr int S2 = H / 16;
-  constexpr int K1 = 16 * S1;
-  constexpr bool H1_IN_LDS = H > 256;
-  constexpr int G = H1_IN_LDS ? 8 : NB; // layer-2 output blocks per group
-  static_assert(!(LDSW && H1_IN_LDS), "weights and hidden activations cannot both use LDS");
-  extern __shared__ bf16x8 lds[];
-  constexpr int N2 = H * H / 8, N3 = NB3 * 32 * H / 8, N1 = H * K1 / 8;
-  if constexpr (LDSW) {
-    for (int i = threadIdx.x; i < N2; i += blockDim.x) lds[i] = a.w2p[i];
-    for (int i = threadIdx.x; i < N3; i += blockDim.x) lds[N2 + i] = a.w3p[i];
-    for (int i = threadIdx.x; i < N1; i += blockDim.x) lds[N2 + N3 + i] = a.w1p[i];
-    __syncthreads();
-  }
-#define W2F(ix) (LDSW ? lds[(ix)] : a.w2p[(ix)])
-#define W3F(ix) (LDSW ? lds[N2 + (ix)] : a.w3p[(ix)])
-#define W1F(ix) (LDSW ? lds[N2 + N3 + (ix)] : a.w1p[(ix)])
-  const int lane = threadIdx.x & 63, hh = lane >> 5, col = lane & 31;
-  const uint32_t wave_in_block = threadIdx.x / 64;
-  // private hidden-activation region of this wave (H1_IN_LDS): NB * 2 * 64 fragments
-  bf16x8 *h1lds = lds + (size_t)wave_in_block * NB * 2 * 64;
-  const uint32_t waves_per_block = blockDim.x / 64;
-  const uint32_t n_waves = gridDim.x * waves_per_block;
-  const uint32_t n_tiles = (a.n + 31) / 32;
-  for (uint32_t tile = blockIdx.x * waves_per_block + wave_in_block; tile < n_tiles;
-       tile += n_waves) {
-    const uint32_t i = tile * 32 + col;
-    const bool ok = i < a.n;
-    uint32_t raw = 0;
-    if (ok) raw = TRAIN ? a.cfg_raw[a.batch ? (uint32_t)a.batch[i] : i] : a.idx[i];
-    uint64_t lo = 0, hi = 0;
-    if (ok) decode_packed(raw, a.sp, lo, hi);
-    bf16x8 xb[S1];
-#pragma unroll
-    for (int s = 0; s < S1; ++s)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = 16 * s + 8 * hh + j;
-        const float f = (ok && k < a.F) ? (float)digit_of(lo, hi, (uint32_t)k) * 0.125f : 0.0f;
-        xb[s][j] = (__bf16)f;
-        if (TRAIN && ok) a.xout[(size_t)i * K1 + k] = xb[s][j];
-      }
-
-    // layer-1 block r -> its two B fragments for layer 2
-    auto layer1 = [&](int r, bf16x8 &f0, bf16x8 &f1) {
-      f32x16 acc = {};
-#pragma unroll
-      for (int s = 0; s < S1; ++s) acc = mfma(W1F((r * S1 + s) * 64 + lane), xb[s], acc);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row0 = 32 * r + 8 * q + 4 * hh;
-        const float4 bb = *reinterpret_cast<const float4 *>(a.b1 + row0);
-        const float z[4] = {acc[4 * q] + bb.x, acc[4 * q + 1] + bb.y, acc[4 * q + 2] + bb.z,
-                            acc[4 * q + 3] + bb.w};
-        if (TRAIN && ok)
-          *reinterpret_cast<float4 *>(a.z1out + (size_t)i * H + row0) =
-              make_float4(z[0], z[1], z[2], z[3]);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const __bf16 v = (__bf16)gelu(z[t]);
-          if (q < 2) f0[q * 4 + t] = v;
-          else f1[(q - 2) * 4 + t] = v;
-          if (TRAIN && ok) a.h1out[(size_t)i * H + row0 + t] = v;
-        }
-      }
-    };
-
-    if constexpr (H1_IN_LDS) {
-#pragma unroll 2
-      for (int r = 0; r < NB; ++r) {
-        bf16x8 f0, f1;
-        layer1(r, f0, f1);
-        h1lds[(r * 2 + 0) * 64 + lane] = f0;
-        h1lds[(r * 2 + 1) * 64 + lane] = f1;
-      }
-    }
-
-    f32x16 accy[NB3];
-#pragma unroll
-    for (int r3 = 0; r3 < NB3; ++r3) accy[r3] = f32x16{};
-#pragma unroll
-    for (int g = 0; g < NB / G; ++g) {
-      f32x16 acc2[G];
-#pragma unroll
-      for (int gi = 0; gi < G; ++gi) acc2[gi] = f32x16{};
-      // B fragments of layer-2 K steps 2r, 2r+1
-      auto hidden = [&](int r, bf16x8 (&f)[2]) {
-        if constexpr (H1_IN_LDS) {
-          f[0] = h1lds[(r * 2 + 0) * 64 + lane];
-          f[1] = h1lds[(r * 2 + 1) * 64 + lane];
-        } else {
-          layer1(r, f[0], f[1]);
-        }
-      };
-      auto load_w = [&](int r, bf16x8 (&w)[2][G]) {
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-          for (int gi = 0; gi < G; ++gi) w[sp][gi] = W2F(((g * G + gi) * S2 + 2 * r + sp) * 64 + lane);
-      };
-      auto multiply = [&](const bf16x8 (&w)[2][G], const bf16x8 (&f)[2]) {
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-          for (int gi = 0; gi < G; ++gi) acc2[gi] = mfma(w[sp][gi], f[sp], acc2[gi]);
-      };
-      if constexpr (LDSW) {
-        // LDS fragments: short latency, one K step's fragments at a time
-#pragma unroll 1
-        for (int r = 0; r < NB; ++r) {
-          bf16x8 f[2];
-          hidden(r, f);
-#pragma unroll
-          for (int sp = 0; sp < 2; ++sp) {
-            bf16x8 w[G];
-#pragma unroll
-            for (int gi = 0; gi < G; ++gi) w[gi] = W2F(((g * G + gi) * S2 + 2 * r + sp) * 64 + lane);
-#pragma unroll
-            for (int gi = 0; gi < G; ++gi) acc2[gi] = mfma(w[gi], f[sp], acc2[gi]);
-          }
-        }
-      } else {
-        // global fragments: the next K step's loads overlap this step's MFMAs
-        bf16x8 wa[2][G], wb[2][G];
-        load_w(0, wa);
-#pragma unroll 1
-        for (int r = 0; r < NB; r += 2) {
-          bf16x8 f[2];
-          load_w(r + 1, wb);
-          hidden(r, f);
-          multiply(wa, f);
-          if (r + 2 < NB) load_w(r + 2, wa);
-          hidden(r + 1, f);
-          multiply(wb, f);
-        }
-      }
-#pragma unroll
-      for (int gi = 0; gi < G; ++gi) {
-        bf16x8 h2[2];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row0 = 32 * (g * G + gi) + 8 * q + 4 * hh;
-          const float4 bb = *reinterpret_cast<const float4 *>(a.b2 + row0);
-          const float z[4] = {acc2[gi][4 * q] + bb.x, acc2[gi][4 * q + 1] + bb.y,
-                              acc2[gi][4 * q + 2] + bb.z, acc2[gi][4 * q + 3] + bb.w};
-          if (TRAIN && ok)
-            *reinterpret_cast<float4 *>(a.z2out + (size_t)i * H + row0) =
-                make_float4(z[0], z[1], z[2], z[3]);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const __bf16 v = (__bf16)gelu(z[t]);
-            h2[q >> 1][(q & 1) * 4 + t] = v;
-            if (TRAIN && ok) a.h2out[(size_t)i * H + row0 + t] = v;
-          }
-        }
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-          for (int r3 = 0; r3 < NB3; ++r3)
-            accy[r3] = mfma(W3F((r3 * S2 + 2 * (g * G + gi) + sp) * 64 + lane), h2[sp], accy[r3]);
-      }
-    }
-
-    // output
-#pragma unroll
-    for (int r3 = 0; r3 < NB3; ++r3)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int c = 32 * r3 + 8 * q + 4 * hh + t;
-          if (ok && c < a.C) {
-            const float y = accy[r3][4 * q + t] + a.b3[c];
-            if (TRAIN)
-              a.yout[(size_t)i * (32 * NB3) + c] = y;
-            else
-              a.P[(size_t)c * a.stride + i] = fmaxf(y, 0.0f);
-          }
-        }
-  }
-#undef W2F
-#undef W3F
-#undef W1F
 }
 
 // ------------------------------------------------------------- inference
@@ -506,8 +313,10 @@ template <typename T> __device__ __forceinline__ __bf16 to_bf16(T v);
 template <> __device__ __forceinline__ __bf16 to_bf16<float>(float v) { return (__bf16)v; }
 template <> __device__ __forceinline__ __bf16 to_bf16<__bf16>(__bf16 v) { return v; }
 
+// EPI 0: C = A B; 1: dZ = (A B) * gelu'(Z) (fp32 and bf16); 2: Z = A B + bias
+// (fp32) and H = gelu(Z) (bf16); 3: Y = A B + bias (fp32).  bias[N] for 2, 3.
 template <typename TA, typename TB, int EPI>
-__global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g) {
+__global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const float *bias) {
   constexpr int NW = kGemmThreads / 64;
   __shared__ float part[NW - 1][16][64];
   const TA *A = static_cast<const TA *>(g.A);
@@ -544,12 +353,33 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g) {
     const size_t o = (size_t)row * g.ldc + cl;
     if (EPI == 0) {
       g.Cf[o] = acc[i];
-    } else { // dZ = dH * gelu'(Z)
+    } else if (EPI == 1) { // dZ = dH * gelu'(Z)
       const float v = acc[i] * gelu_grad(g.Z[o]);
       g.Cf[o] = v;
       g.Cb[o] = (__bf16)v;
+    } else if (EPI == 2) { // Z = W x + b, H = gelu(Z)
+      const float v = acc[i] + bias[cl];
+      g.Cf[o] = v;
+      g.Cb[o] = (__bf16)gelu(v);
+    } else { // Y = W h + b
+      g.Cf[o] = acc[i] + bias[cl];
     }
   }
+}
+
+// Training features: X[i][k] = digit_k / 8 of configuration cfg_raw[batch[i]]
+// (bf16, K1 columns, zero past F), the inputs of the fused forward.
+__global__ __launch_bounds__(256) void mlp_features(const SpaceDev *__restrict__ sp,
+                                                    const uint32_t *__restrict__ cfg_raw,
+                                                    const int32_t *__restrict__ batch, uint32_t n,
+                                                    int F, int K1, __bf16 *__restrict__ x) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint64_t lo, hi;
+  decode_packed(cfg_raw[batch ? (uint32_t)batch[i] : i], sp, lo, hi);
+  for (int k = 0; k < K1; ++k)
+    x[(size_t)i * K1 + k] =
+        (__bf16)(k < F ? (float)digit_of(lo, hi, (uint32_t)k) * 0.125f : 0.0f);
 }
 
 // ------------------------------------------------------ loss, biases, Adam
@@ -729,46 +559,10 @@ template <int H> hipError_t launch_infer_nb(const MlpFwdArgs &a, hipStream_t s) 
   return hipErrorInvalidValue;
 }
 
-template <int H, int NB3, int S1, bool TRAIN, bool LDSW>
-hipError_t launch_fwd_t(const MlpFwdArgs &a, hipStream_t stream) {
-  const uint32_t n_tiles = (a.n + 31) / 32;
-  if (n_tiles == 0) return hipSuccess;
-  if (LDSW) {
-    const size_t lds = (size_t)(H * H + NB3 * 32 * H + H * 16 * S1) * sizeof(__bf16);
-    static bool attr_set = false;
-    if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute(
-          reinterpret_cast<const void *>(&mlp_forward<H, NB3, S1, TRAIN, LDSW>),
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
-    const uint32_t grid = std::min<uint32_t>((n_tiles + 7) / 8, (uint32_t)a.n_cu);
-    hipLaunchKernelGGL((mlp_forward<H, NB3, S1, TRAIN, LDSW>), dim3(grid), dim3(512), lds, stream,
-                       a);
-  } else {
-    // H = 512: each of the 4 waves keeps its layer-1 output in LDS
-    const size_t lds = H > 256 ? (size_t)4 * (H / 32) * 2 * 64 * sizeof(bf16x8) : 0;
-    if (lds > 64 * 1024) {
-      static bool attr_set = false;
-      if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&mlp_forward<H, NB3, S1, TRAIN, LDSW>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-      }
-    }
-    const uint32_t grid = std::min<uint32_t>((n_tiles + 3) / 4, (uint32_t)a.n_cu * 8);
-    hipLaunchKernelGGL((mlp_forward<H, NB3, S1, TRAIN, LDSW>), dim3(grid), dim3(256), lds, stream,
-                       a);
-  }
-  return hipGetLastError();
-}
-
 template <int H, int NB3, int S1>
 hipError_t launch_fwd_h(const MlpFwdArgs &a, bool train, hipStream_t stream) {
-  if (train) return launch_fwd_t<H, NB3, S1, true, false>(a, stream);
+  // the training forward is launch_mlp_train_forward (one GEMM per layer)
+  if (train) return hipErrorInvalidValue;
   return launch_infer_h<H, NB3, S1>(a, stream);
 }
 
@@ -793,12 +587,35 @@ hipError_t launch_mlp_forward(const MlpFwdArgs &a, bool train, hipStream_t strea
   }
 }
 
+hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const float *w2,
+                                   const float *w3, hipStream_t stream) {
+  if (a.n == 0) return hipSuccess;
+  const int Cp = 32 * ((a.C + 31) / 32);
+  hipLaunchKernelGGL(mlp_features, dim3((a.n + 255) / 256), dim3(256), 0, stream, a.sp,
+                     a.cfg_raw, a.batch, a.n, a.F, a.K1, a.xout);
+  auto gemm = [&](const GemmArgs &g, const float *bias, int epi) {
+    const dim3 grid(((g.M + 31) / 32) * ((g.N + 31) / 32)), block(kGemmThreads);
+    if (epi == 2)
+      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 2>), grid, block, 0, stream, g, bias);
+    else
+      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 3>), grid, block, 0, stream, g, bias);
+  };
+  // Z1 = X W1^T + b1, H1 = gelu(Z1); Z2 = H1 W2^T + b2, H2 = gelu(Z2); Y = H2 W3^T + b3
+  const int n = (int)a.n;
+  gemm(GemmArgs{n, a.H, a.F, a.xout, a.K1, 1, w1, 1, a.F, a.z1out, a.h1out, nullptr, a.H}, a.b1,
+       2);
+  gemm(GemmArgs{n, a.H, a.H, a.h1out, a.H, 1, w2, 1, a.H, a.z2out, a.h2out, nullptr, a.H}, a.b2,
+       2);
+  gemm(GemmArgs{n, a.C, a.H, a.h2out, a.H, 1, w3, 1, a.H, a.yout, nullptr, nullptr, Cp}, a.b3, 3);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipStream_t stream) {
   const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
   if (tiles == 0) return hipSuccess;
   const dim3 grid(tiles), block(kGemmThreads);
 #define GEMM_CASE(TA, TB, E)                                                                   \
-  hipLaunchKernelGGL((gemm_bf16<TA, TB, E>), grid, block, 0, stream, g)
+  hipLaunchKernelGGL((gemm_bf16<TA, TB, E>), grid, block, 0, stream, g, nullptr)
   if (a_bf16 && b_bf16 && epi == 0) GEMM_CASE(__bf16, __bf16, 0);
   else if (a_bf16 && !b_bf16 && epi == 1) GEMM_CASE(__bf16, float, 1);
   else if (a_bf16 && !b_bf16 && epi == 0) GEMM_CASE(__bf16, float, 0);

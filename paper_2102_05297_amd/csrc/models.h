@@ -12,6 +12,12 @@ namespace cgs {
 hipError_t launch_rows_to_columns(const float *d_src, uint32_t n, int C, float *d_P,
                                   uint64_t stride, hipStream_t stream);
 
+// The perceptron's training forward pass (features, then one GEMM per layer
+// with the bias and GELU in its epilogue) into a.xout, z1out, h1out, z2out,
+// h2out, yout; w1, w2, w3: the fp32 master weights ([H][F], [H][H], [C][H]).
+hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const float *w2,
+                                   const float *w3, hipStream_t stream);
+
 // ---- regression-tree fitting (Sect. 3.4.2)
 FastDiv make_fastdiv(uint32_t d);
 
