@@ -312,6 +312,24 @@ mlp_infer(
 template <typename T> __device__ __forceinline__ __bf16 to_bf16(T v);
 template <> __device__ __forceinline__ __bf16 to_bf16<float>(float v) { return (__bf16)v; }
 template <> __device__ __forceinline__ __bf16 to_bf16<__bf16>(__bf16 v) { return v; }
+// 8 consecutive values (16-byte aligned for bf16, 32-byte for float) as bf16.
+__device__ __forceinline__ bf16x8 load_bf16x8(const __bf16 *p) {
+  return *reinterpret_cast<const bf16x8 *>(p);
+}
+__device__ __forceinline__ bf16x8 load_bf16x8(const float *p) {
+  const float4 lo = *reinterpret_cast<const float4 *>(p);
+  const float4 hi = *reinterpret_cast<const float4 *>(p + 4);
+  bf16x8 r;
+  r[0] = (__bf16)lo.x;
+  r[1] = (__bf16)lo.y;
+  r[2] = (__bf16)lo.z;
+  r[3] = (__bf16)lo.w;
+  r[4] = (__bf16)hi.x;
+  r[5] = (__bf16)hi.y;
+  r[6] = (__bf16)hi.z;
+  r[7] = (__bf16)hi.w;
+  return r;
+}
 
 // EPI 0: C = A B; 1: dZ = (A B) * gelu'(Z) (fp32 and bf16); 2: Z = A B + bias
 // (fp32) and H = gelu(Z) (bf16); 3: Y = A B + bias (fp32).  bias[N] for 2, 3.
@@ -326,15 +344,35 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const floa
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hh = lane >> 5, c = lane & 31;
   const int m = m0 + c, n = n0 + c;
   f32x16 acc = {};
+  // unit stride along K (and 8-element aligned rows): a fragment's 8 values
+  // are one contiguous, 16-byte aligned run, loaded as vectors
+  const bool a_vec =
+      g.a_sk == 1 && g.a_sm % 8 == 0 && (reinterpret_cast<uintptr_t>(A) & 15u) == 0;
+  const bool b_vec =
+      g.b_sk == 1 && g.b_sn % 8 == 0 && (reinterpret_cast<uintptr_t>(B) & 15u) == 0;
   for (int k0 = 16 * w; k0 < g.K; k0 += 16 * NW) {
     bf16x8 af, bf;
+    const int kf = k0 + 8 * hh; // first k of this lane's fragment
+    const bool full = kf + 8 <= g.K;
+    if (a_vec && full && m < g.M) {
+      af = load_bf16x8(A + (size_t)m * g.a_sm + kf);
+    } else {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = k0 + 8 * hh + j;
-      af[j] = (m < g.M && k < g.K) ? to_bf16(A[(size_t)m * g.a_sm + (size_t)k * g.a_sk])
-                                   : (__bf16)0.0f;
-      bf[j] = (n < g.N && k < g.K) ? to_bf16(B[(size_t)k * g.b_sk + (size_t)n * g.b_sn])
-                                   : (__bf16)0.0f;
+      for (int j = 0; j < 8; ++j) {
+        const int k = kf + j;
+        af[j] = (m < g.M && k < g.K) ? to_bf16(A[(size_t)m * g.a_sm + (size_t)k * g.a_sk])
+                                     : (__bf16)0.0f;
+      }
+    }
+    if (b_vec && full && n < g.N) {
+      bf = load_bf16x8(B + (size_t)n * g.b_sn + kf);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = kf + j;
+        bf[j] = (n < g.N && k < g.K) ? to_bf16(B[(size_t)k * g.b_sk + (size_t)n * g.b_sn])
+                                     : (__bf16)0.0f;
+      }
     }
     acc = mfma(af, bf, acc);
   }
