@@ -95,6 +95,7 @@ struct cgs_model_s {
   size_t off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
   float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
   __bf16 *d_w1p = nullptr, *d_w2p = nullptr, *d_w3p = nullptr;
+  __bf16 *d_w2t = nullptr, *d_w3t = nullptr; // [H][H], [H][Cp]: backward operands
   size_t n_w1p = 0, n_w2p = 0, n_w3p = 0;
   uint64_t adam_t = 0;
   int n_cu = 256;
@@ -441,6 +442,8 @@ void destroy_model(cgs_model m) {
   dfree(m->d_w1p);
   dfree(m->d_w2p);
   dfree(m->d_w3p);
+  dfree(m->d_w2t);
+  dfree(m->d_w3t);
   dfree(m->d_poly);
   dfree(m->d_beta64);
   dfree(m->d_beta32);
@@ -1322,22 +1325,22 @@ hipError_t mlp_backward_rows(cgs_model m, const uint32_t *d_cfg, const float *d_
     ga = GemmArgs{C, H, (int)n, m->d_dyb, 1, Cp, m->d_h2, H, 1, g + m->off_w3, nullptr, nullptr, H};
     e = launch_gemm(ga, 1, 1, 0, st);
   }
-  // dZ2 = (dY W3) * gelu'(Z2)
+  // dZ2 = (dY W3) * gelu'(Z2), W3 read from its transposed bf16 copy
   if (e == hipSuccess) {
-    ga = GemmArgs{(int)n, H, C, m->d_dyb, Cp, 1, m->d_theta + m->off_w3, H, 1, m->d_dz2f,
-                  m->d_dz2b, m->d_z2, H};
-    e = launch_gemm(ga, 1, 0, 1, st);
+    ga = GemmArgs{(int)n, H, C, m->d_dyb, Cp, 1, m->d_w3t, 1, Cp, m->d_dz2f, m->d_dz2b, m->d_z2,
+                  H};
+    e = launch_gemm(ga, 1, 1, 1, st);
   }
   // dW2 = dZ2^T H1
   if (e == hipSuccess) {
     ga = GemmArgs{H, H, (int)n, m->d_dz2b, 1, H, m->d_h1, H, 1, g + m->off_w2, nullptr, nullptr, H};
     e = launch_gemm(ga, 1, 1, 0, st);
   }
-  // dZ1 = (dZ2 W2) * gelu'(Z1)
+  // dZ1 = (dZ2 W2) * gelu'(Z1), W2 read from its transposed bf16 copy
   if (e == hipSuccess) {
-    ga = GemmArgs{(int)n, H, H, m->d_dz2b, H, 1, m->d_theta + m->off_w2, H, 1, m->d_dz1f,
-                  m->d_dz1b, m->d_z1, H};
-    e = launch_gemm(ga, 1, 0, 1, st);
+    ga = GemmArgs{(int)n, H, H, m->d_dz2b, H, 1, m->d_w2t, 1, H, m->d_dz1f, m->d_dz1b, m->d_z1,
+                  H};
+    e = launch_gemm(ga, 1, 1, 1, st);
   }
   // dW1 = dZ1^T X
   if (e == hipSuccess) {
@@ -1425,6 +1428,8 @@ extern "C" cgs_status cgs_model_load_mlp(cgs_space sp, const cgs_mlp_desc *desc,
   if (e == hipSuccess) e = dalloc(&m->d_w1p, m->n_w1p);
   if (e == hipSuccess) e = dalloc(&m->d_w2p, m->n_w2p);
   if (e == hipSuccess) e = dalloc(&m->d_w3p, m->n_w3p);
+  if (e == hipSuccess) e = dalloc(&m->d_w2t, m->n_w2p);
+  if (e == hipSuccess) e = dalloc(&m->d_w3t, m->n_w3p);
   if (e == hipSuccess) e = dalloc(&m->d_P, (size_t)C * m->stride);
   if (e == hipSuccess)
     e = hipMemcpyAsync(m->d_theta, params, n * sizeof(float), hipMemcpyHostToDevice, st);
@@ -1433,7 +1438,9 @@ extern "C" cgs_status cgs_model_load_mlp(cgs_space sp, const cgs_mlp_desc *desc,
   if (e == hipSuccess) e = hipMemsetAsync(m->d_w1p, 0, m->n_w1p * sizeof(__bf16), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->d_w3p, 0, m->n_w3p * sizeof(__bf16), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->d_P, 0, (size_t)C * m->stride * sizeof(float), st);
-  if (e == hipSuccess) e = launch_pack_weights(m->sh, m->d_theta, n, m->d_w1p, m->d_w2p, m->d_w3p, st);
+  if (e == hipSuccess)
+    e = launch_pack_weights_t(m->sh, m->d_theta, n, m->d_w1p, m->d_w2p, m->d_w3p, m->d_w2t,
+                              m->d_w3t, st);
   if (e != hipSuccess) {
     destroy_model(m);
     return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "perceptron buffers: %s",
@@ -1482,9 +1489,9 @@ extern "C" cgs_status cgs_mlp_train(cgs_model m, const uint32_t *cfg, const floa
     m->adam_t += 1;
     const double c1 = 1.0 / (1.0 - std::pow((double)o->beta1, (double)m->adam_t));
     const double c2 = 1.0 / (1.0 - std::pow((double)o->beta2, (double)m->adam_t));
-    e = launch_adam_pack(m->sh, m->d_theta, m->d_m, m->d_v, m->d_grad, m->n_theta, o->lr,
-                         o->beta1, o->beta2, o->eps, (float)c1, (float)c2, m->d_w1p, m->d_w2p,
-                         m->d_w3p, st);
+    e = launch_adam_pack_t(m->sh, m->d_theta, m->d_m, m->d_v, m->d_grad, m->n_theta, o->lr,
+                           o->beta1, o->beta2, o->eps, (float)c1, (float)c2, m->d_w1p, m->d_w2p,
+                           m->d_w3p, m->d_w2t, m->d_w3t, st);
   }
   if (e == hipSuccess && loss_host && o->steps > 0)
     e = hipMemcpyAsync(loss_host, d_loss, o->steps * sizeof(float), hipMemcpyDeviceToHost, st);

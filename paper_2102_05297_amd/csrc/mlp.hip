@@ -532,11 +532,31 @@ __device__ __forceinline__ void pack_one(const MlpShape &sh, size_t p, float v, 
   else if (which == 3) w3p[pos] = (__bf16)v;
 }
 
+// Transposed bf16 copies of W2 and W3, K-contiguous for the backward
+// products dH = dZ W (so their weight fragments are vector loads):
+// w2t[k][o] = W2[o][k] (row length H), w3t[k][c] = W3[c][k] (row length Cp,
+// the padding never read).  Null pointers skip them.
+__device__ __forceinline__ void pack_transposed(const MlpShape &sh, size_t p, float v,
+                                                __bf16 *w2t, __bf16 *w3t) {
+  if (w2t == nullptr) return;
+  const size_t H = sh.H, first_w2 = H * sh.F + H, first_w3 = first_w2 + H * H + H;
+  if (p >= first_w2 && p < first_w2 + H * H) {
+    const size_t q = p - first_w2;
+    w2t[(q % H) * H + q / H] = (__bf16)v;
+  } else if (p >= first_w3 && p < first_w3 + (size_t)sh.C * H) {
+    const size_t q = p - first_w3, Cp = 32 * (((size_t)sh.C + 31) / 32);
+    w3t[(q % H) * Cp + q / H] = (__bf16)v;
+  }
+}
+
 __global__ __launch_bounds__(256) void pack_weights(MlpShape sh, const float *__restrict__ theta,
                                                     size_t n, __bf16 *w1p, __bf16 *w2p,
-                                                    __bf16 *w3p) {
+                                                    __bf16 *w3p, __bf16 *w2t, __bf16 *w3t) {
   const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (p < n) pack_one(sh, p, theta[p], w1p, w2p, w3p);
+  if (p >= n) return;
+  const float th = theta[p];
+  pack_one(sh, p, th, w1p, w2p, w3p);
+  pack_transposed(sh, p, th, w2t, w3t);
 }
 
 // Adam (Kingma & Ba, Algorithm 1); c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t).
@@ -545,7 +565,7 @@ __global__ __launch_bounds__(256) void adam_pack(MlpShape sh, float *__restrict_
                                                  const float *__restrict__ grad, size_t n,
                                                  float lr, float b1, float b2, float eps, float c1,
                                                  float c2, __bf16 *w1p, __bf16 *w2p,
-                                                 __bf16 *w3p) {
+                                                 __bf16 *w3p, __bf16 *w2t, __bf16 *w3t) {
   const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
   const float g = grad[p];
@@ -556,6 +576,7 @@ __global__ __launch_bounds__(256) void adam_pack(MlpShape sh, float *__restrict_
   const float th = theta[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
   theta[p] = th;
   pack_one(sh, p, th, w1p, w2p, w3p);
+  pack_transposed(sh, p, th, w2t, w3t);
 }
 
 template <typename K>
@@ -680,20 +701,32 @@ hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dy
   return hipGetLastError();
 }
 
-hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
-                               __bf16 *w2p, __bf16 *w3p, hipStream_t stream) {
+hipError_t launch_pack_weights_t(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
+                                 __bf16 *w2p, __bf16 *w3p, __bf16 *w2t, __bf16 *w3t,
+                                 hipStream_t stream) {
   hipLaunchKernelGGL(pack_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh,
-                     theta, n, w1p, w2p, w3p);
+                     theta, n, w1p, w2p, w3p, w2t, w3t);
   return hipGetLastError();
 }
+hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
+                               __bf16 *w2p, __bf16 *w3p, hipStream_t stream) {
+  return launch_pack_weights_t(sh, theta, n, w1p, w2p, w3p, nullptr, nullptr, stream);
+}
 
+hipError_t launch_adam_pack_t(const MlpShape &sh, float *theta, float *m, float *v,
+                              const float *grad, size_t n, float lr, float b1, float b2,
+                              float eps, float c1, float c2, __bf16 *w1p, __bf16 *w2p,
+                              __bf16 *w3p, __bf16 *w2t, __bf16 *w3t, hipStream_t stream) {
+  hipLaunchKernelGGL(adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh, theta,
+                     m, v, grad, n, lr, b1, b2, eps, c1, c2, w1p, w2p, w3p, w2t, w3t);
+  return hipGetLastError();
+}
 hipError_t launch_adam_pack(const MlpShape &sh, float *theta, float *m, float *v,
                             const float *grad, size_t n, float lr, float b1, float b2, float eps,
                             float c1, float c2, __bf16 *w1p, __bf16 *w2p, __bf16 *w3p,
                             hipStream_t stream) {
-  hipLaunchKernelGGL(adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh, theta,
-                     m, v, grad, n, lr, b1, b2, eps, c1, c2, w1p, w2p, w3p);
-  return hipGetLastError();
+  return launch_adam_pack_t(sh, theta, m, v, grad, n, lr, b1, b2, eps, c1, c2, w1p, w2p, w3p,
+                            nullptr, nullptr, stream);
 }
 
 } // namespace cgs
