@@ -143,6 +143,58 @@ def test_gradients_match_float64_backprop(H):
         assert np.abs(got - ref).max() <= 2e-2 * np.abs(ref).max()
 
 
+def test_gradients_with_two_output_tiles():
+    """C = 40 outputs: dY spans two 32-column tiles, the transposed bf16 copy
+    of W3 has rows of 64, and the 40-deep product dY W3 ends on a full
+    8-value fragment."""
+    m = cgs()
+    spec, valid = _space()
+    sp = m.Space.from_spec(spec)
+    params = _params(6, 128, 40, (36, 128))
+    model = m.MLPModel(sp, params)
+    cfg, _, X = _pairs(spec, valid, 256, 2)
+    T = synth.normal_noise(synth.rng(36, 5), (256, 40), 1.0).astype(np.float32)
+    g_gpu, loss = model.gradients(cfg, T)
+    pr = [np.asarray(p, np.float64) for p in params]
+    pr = [M.bf16(p).astype(np.float64) if i % 2 == 0 else p for i, p in enumerate(pr)]
+    loss_ref, g_ref = M.loss_and_grads(pr, X, T.astype(np.float64))
+    assert abs(loss - loss_ref) <= 1e-2 * loss_ref
+    for got, ref in zip(model.unflatten(g_gpu), g_ref):
+        got = got.astype(np.float64)
+        cos = (got * ref).sum() / np.sqrt((got * got).sum() * (ref * ref).sum())
+        assert cos > 0.999, cos
+        assert np.abs(got - ref).max() <= 2e-2 * np.abs(ref).max()
+
+
+def test_gradients_after_adam_steps_use_the_updated_weights():
+    """Adam rewrites the bf16 weight copies that the backward products read:
+    after five steps (lr 1e-2, so W2 moves far beyond its bf16 rounding) the
+    gradients must match the oracle's at the trained parameters."""
+    m = cgs()
+    spec, valid = _space()
+    sp = m.Space.from_spec(spec)
+    params = _params(6, 128, 40, (37, 128))
+    model = m.MLPModel(sp, params)
+    cfg, _, X = _pairs(spec, valid, 256, 4)
+    T = synth.normal_noise(synth.rng(37, 5), (256, 40), 1.0).astype(np.float32)
+    batches = np.tile(np.arange(256, dtype=np.int32), (5, 1))
+    model.train(cfg, T, batches, lr=1e-2)
+    trained = model.unflatten(model.copy_params())
+    moved = np.abs(trained[2] - np.asarray(params[2])).max() / np.abs(params[2]).max()
+    assert moved > 0.1, moved  # the oracle's training moves W2 by 0.23 of its max here
+    g_gpu, loss = model.gradients(cfg, T)
+    pr = [np.asarray(p, np.float64) for p in trained]
+    pr = [M.bf16(p.astype(np.float32)).astype(np.float64) if i % 2 == 0 else p
+          for i, p in enumerate(pr)]
+    loss_ref, g_ref = M.loss_and_grads(pr, X, T.astype(np.float64))
+    assert abs(loss - loss_ref) <= 1e-2 * loss_ref
+    for got, ref in zip(model.unflatten(g_gpu), g_ref):
+        got = got.astype(np.float64)
+        cos = (got * ref).sum() / np.sqrt((got * got).sum() * (ref * ref).sum())
+        assert cos > 0.999, cos
+        assert np.abs(got - ref).max() <= 2e-2 * np.abs(ref).max()
+
+
 def test_first_adam_step_closed_form():
     m = cgs()
     spec, valid = _space()
