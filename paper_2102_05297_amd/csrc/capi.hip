@@ -1439,8 +1439,8 @@ extern "C" cgs_status cgs_model_load_mlp(cgs_space sp, const cgs_mlp_desc *desc,
   if (e == hipSuccess) e = hipMemsetAsync(m->d_w3p, 0, m->n_w3p * sizeof(__bf16), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->d_P, 0, (size_t)C * m->stride * sizeof(float), st);
   if (e == hipSuccess)
-    e = launch_pack_weights_t(m->sh, m->d_theta, n, m->d_w1p, m->d_w2p, m->d_w3p, m->d_w2t,
-                              m->d_w3t, st);
+    e = launch_pack_weights(m->sh, m->d_theta, n, m->d_w1p, m->d_w2p, m->d_w3p, m->d_w2t,
+                            m->d_w3t, st);
   if (e != hipSuccess) {
     destroy_model(m);
     return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "perceptron buffers: %s",
@@ -1489,9 +1489,9 @@ extern "C" cgs_status cgs_mlp_train(cgs_model m, const uint32_t *cfg, const floa
     m->adam_t += 1;
     const double c1 = 1.0 / (1.0 - std::pow((double)o->beta1, (double)m->adam_t));
     const double c2 = 1.0 / (1.0 - std::pow((double)o->beta2, (double)m->adam_t));
-    e = launch_adam_pack_t(m->sh, m->d_theta, m->d_m, m->d_v, m->d_grad, m->n_theta, o->lr,
-                           o->beta1, o->beta2, o->eps, (float)c1, (float)c2, m->d_w1p, m->d_w2p,
-                           m->d_w3p, m->d_w2t, m->d_w3t, st);
+    e = launch_adam_pack(m->sh, m->d_theta, m->d_m, m->d_v, m->d_grad, m->n_theta, o->lr,
+                         o->beta1, o->beta2, o->eps, (float)c1, (float)c2, m->d_w1p, m->d_w2p,
+                         m->d_w3p, m->d_w2t, m->d_w3t, st);
   }
   if (e == hipSuccess && loss_host && o->steps > 0)
     e = hipMemcpyAsync(loss_host, d_loss, o->steps * sizeof(float), hipMemcpyDeviceToHost, st);

@@ -176,12 +176,6 @@ hipError_t launch_mse_grad(const float *Y, int Cp, int C, int n, const float *ta
 hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dyf, int n, int H,
                              int C, int Cp, float *gb1, float *gb2, float *gb3,
                              hipStream_t stream);
-hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
-                               __bf16 *w2p, __bf16 *w3p, hipStream_t stream);
-hipError_t launch_adam_pack(const MlpShape &sh, float *theta, float *m, float *v,
-                            const float *grad, size_t n, float lr, float b1, float b2, float eps,
-                            float c1, float c2, __bf16 *w1p, __bf16 *w2p, __bf16 *w3p,
-                            hipStream_t stream);
 
 // ---- launchers (each enqueues on `stream`; return hipSuccess or an error)
 hipError_t launch_enumeration(const SpaceDev *d_space, uint32_t n_raw, uint32_t *d_mask,

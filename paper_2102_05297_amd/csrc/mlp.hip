@@ -535,10 +535,9 @@ __device__ __forceinline__ void pack_one(const MlpShape &sh, size_t p, float v, 
 // Transposed bf16 copies of W2 and W3, K-contiguous for the backward
 // products dH = dZ W (so their weight fragments are vector loads):
 // w2t[k][o] = W2[o][k] (row length H), w3t[k][c] = W3[c][k] (row length Cp,
-// the padding never read).  Null pointers skip them.
+// the padding never read).
 __device__ __forceinline__ void pack_transposed(const MlpShape &sh, size_t p, float v,
                                                 __bf16 *w2t, __bf16 *w3t) {
-  if (w2t == nullptr) return;
   const size_t H = sh.H, first_w2 = H * sh.F + H, first_w3 = first_w2 + H * H + H;
   if (p >= first_w2 && p < first_w2 + H * H) {
     const size_t q = p - first_w2;
@@ -701,32 +700,21 @@ hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dy
   return hipGetLastError();
 }
 
-hipError_t launch_pack_weights_t(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
-                                 __bf16 *w2p, __bf16 *w3p, __bf16 *w2t, __bf16 *w3t,
-                                 hipStream_t stream) {
+hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
+                               __bf16 *w2p, __bf16 *w3p, __bf16 *w2t, __bf16 *w3t,
+                               hipStream_t stream) {
   hipLaunchKernelGGL(pack_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh,
                      theta, n, w1p, w2p, w3p, w2t, w3t);
   return hipGetLastError();
 }
-hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
-                               __bf16 *w2p, __bf16 *w3p, hipStream_t stream) {
-  return launch_pack_weights_t(sh, theta, n, w1p, w2p, w3p, nullptr, nullptr, stream);
-}
 
-hipError_t launch_adam_pack_t(const MlpShape &sh, float *theta, float *m, float *v,
-                              const float *grad, size_t n, float lr, float b1, float b2,
-                              float eps, float c1, float c2, __bf16 *w1p, __bf16 *w2p,
-                              __bf16 *w3p, __bf16 *w2t, __bf16 *w3t, hipStream_t stream) {
-  hipLaunchKernelGGL(adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh, theta,
-                     m, v, grad, n, lr, b1, b2, eps, c1, c2, w1p, w2p, w3p, w2t, w3t);
-  return hipGetLastError();
-}
 hipError_t launch_adam_pack(const MlpShape &sh, float *theta, float *m, float *v,
                             const float *grad, size_t n, float lr, float b1, float b2, float eps,
                             float c1, float c2, __bf16 *w1p, __bf16 *w2p, __bf16 *w3p,
-                            hipStream_t stream) {
-  return launch_adam_pack_t(sh, theta, m, v, grad, n, lr, b1, b2, eps, c1, c2, w1p, w2p, w3p,
-                            nullptr, nullptr, stream);
+                            __bf16 *w2t, __bf16 *w3t, hipStream_t stream) {
+  hipLaunchKernelGGL(adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh, theta,
+                     m, v, grad, n, lr, b1, b2, eps, c1, c2, w1p, w2p, w3p, w2t, w3t);
+  return hipGetLastError();
 }
 
 } // namespace cgs

@@ -17,17 +17,19 @@ hipError_t launch_rows_to_columns(const float *d_src, uint32_t n, int C, float *
 // h2out, yout; w1, w2, w3: the fp32 master weights ([H][F], [H][H], [C][H]).
 hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const float *w2,
                                    const float *w3, hipStream_t stream);
-// Weight packing and Adam as launch_pack_weights / launch_adam_pack, also
-// writing the transposed bf16 copies w2t[k][o] = W2[o][k] ([H][H]) and
+// The bf16 weights from the fp32 masters theta[n]: the inference fragments
+// w1p, w2p, w3p, and the transposed copies w2t[k][o] = W2[o][k] ([H][H]) and
 // w3t[k][c] = W3[c][k] ([H][Cp], Cp = C rounded up to 32) that the backward
 // products read.
-hipError_t launch_pack_weights_t(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
-                                 __bf16 *w2p, __bf16 *w3p, __bf16 *w2t, __bf16 *w3t,
-                                 hipStream_t stream);
-hipError_t launch_adam_pack_t(const MlpShape &sh, float *theta, float *m, float *v,
-                              const float *grad, size_t n, float lr, float b1, float b2,
-                              float eps, float c1, float c2, __bf16 *w1p, __bf16 *w2p,
-                              __bf16 *w3p, __bf16 *w2t, __bf16 *w3t, hipStream_t stream);
+hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
+                               __bf16 *w2p, __bf16 *w3p, __bf16 *w2t, __bf16 *w3t,
+                               hipStream_t stream);
+// One Adam step on theta (moments m, v; c1, c2 the bias corrections of this
+// step), then the same packing of the updated weights.
+hipError_t launch_adam_pack(const MlpShape &sh, float *theta, float *m, float *v,
+                            const float *grad, size_t n, float lr, float b1, float b2, float eps,
+                            float c1, float c2, __bf16 *w1p, __bf16 *w2p, __bf16 *w3p,
+                            __bf16 *w2t, __bf16 *w3t, hipStream_t stream);
 
 // ---- regression-tree fitting (Sect. 3.4.2)
 FastDiv make_fastdiv(uint32_t d);
