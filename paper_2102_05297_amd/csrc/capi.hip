@@ -104,7 +104,7 @@ struct cgs_model_s {
   __bf16 *d_x = nullptr, *d_h1 = nullptr, *d_h2 = nullptr, *d_dyb = nullptr, *d_dz1b = nullptr,
          *d_dz2b = nullptr;
   float *d_z1 = nullptr, *d_z2 = nullptr, *d_y = nullptr, *d_dyf = nullptr, *d_dz1f = nullptr,
-        *d_dz2f = nullptr;
+        *d_dz2f = nullptr, *d_loss_part = nullptr;
   // least-squares polynomials: descriptor and coefficients [S][T][C]
   PolyDev poly{};
   PolyDev *d_poly = nullptr;
@@ -426,6 +426,7 @@ void free_mlp_scratch(cgs_model m) {
   dfree(m->d_dyf);
   dfree(m->d_dz1f);
   dfree(m->d_dz2f);
+  dfree(m->d_loss_part);
   m->scratch_rows = 0;
 }
 
@@ -1286,6 +1287,7 @@ hipError_t ensure_mlp_scratch(cgs_model m, uint32_t rows) {
   if (e == hipSuccess) e = dalloc(&m->d_dyf, rows * Cp);
   if (e == hipSuccess) e = dalloc(&m->d_dz1f, rows * H);
   if (e == hipSuccess) e = dalloc(&m->d_dz2f, rows * H);
+  if (e == hipSuccess) e = dalloc(&m->d_loss_part, (rows + 31) / 32 * (Cp / 32)); // output tiles
   if (e != hipSuccess) {
     free_mlp_scratch(m);
     return e;
@@ -1295,7 +1297,8 @@ hipError_t ensure_mlp_scratch(cgs_model m, uint32_t rows) {
 }
 
 // Forward of n rows (cfg_raw[batch[i]]) storing the activations.
-hipError_t mlp_forward_rows(cgs_model m, const uint32_t *d_cfg, const int32_t *d_batch, uint32_t n) {
+hipError_t mlp_forward_rows(cgs_model m, const uint32_t *d_cfg, const int32_t *d_batch, uint32_t n,
+                            const LossArgs *loss = nullptr) {
   MlpFwdArgs a = mlp_args(m);
   a.cfg_raw = d_cfg;
   a.batch = d_batch;
@@ -1307,7 +1310,7 @@ hipError_t mlp_forward_rows(cgs_model m, const uint32_t *d_cfg, const int32_t *d
   a.h2out = m->d_h2;
   a.yout = m->d_y;
   return launch_mlp_train_forward(a, m->d_theta, m->d_theta + m->off_w2, m->d_theta + m->off_w3,
-                                  m->space->stream);
+                                  loss, m->space->stream);
 }
 
 // Forward + loss + backward of n rows into m->d_grad; loss to *d_loss.
@@ -1315,9 +1318,11 @@ hipError_t mlp_backward_rows(cgs_model m, const uint32_t *d_cfg, const float *d_
                              const int32_t *d_batch, uint32_t n, float *d_loss) {
   hipStream_t st = m->space->stream;
   const int H = m->sh.H, F = m->sh.F, C = m->sh.C, K1 = m->sh.K1, Cp = 32 * ((C + 31) / 32);
-  hipError_t e = mlp_forward_rows(m, d_cfg, d_batch, n);
-  if (e == hipSuccess)
-    e = launch_mse_grad(m->d_y, Cp, C, (int)n, d_targets, d_batch, m->d_dyf, m->d_dyb, d_loss, st);
+  // the output layer's epilogue also writes dY and the squared errors per tile
+  const LossArgs loss{d_targets, d_batch, 2.0f / (float)(n * (uint32_t)C), m->d_dyf, m->d_dyb,
+                      m->d_loss_part};
+  const int n_tiles = (int)((n + 31) / 32) * ((C + 31) / 32);
+  hipError_t e = mlp_forward_rows(m, d_cfg, d_batch, n, &loss);
   float *g = m->d_grad;
   GemmArgs ga{};
   // dW3 = dY^T H2
@@ -1349,7 +1354,7 @@ hipError_t mlp_backward_rows(cgs_model m, const uint32_t *d_cfg, const float *d_
   }
   if (e == hipSuccess)
     e = launch_bias_grads(m->d_dz1f, m->d_dz2f, m->d_dyf, (int)n, H, C, Cp, g + m->off_b1,
-                          g + m->off_b2, g + m->off_b3, st);
+                          g + m->off_b2, g + m->off_b3, m->d_loss_part, n_tiles, d_loss, st);
   return e;
 }
 

@@ -170,12 +170,6 @@ struct GemmArgs {
 
 hipError_t launch_mlp_forward(const MlpFwdArgs &a, bool train, hipStream_t stream);
 hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipStream_t stream);
-hipError_t launch_mse_grad(const float *Y, int Cp, int C, int n, const float *targets,
-                           const int32_t *batch, float *dYf, __bf16 *dYb, float *loss_out,
-                           hipStream_t stream);
-hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dyf, int n, int H,
-                             int C, int Cp, float *gb1, float *gb2, float *gb3,
-                             hipStream_t stream);
 
 // ---- launchers (each enqueues on `stream`; return hipSuccess or an error)
 hipError_t launch_enumeration(const SpaceDev *d_space, uint32_t n_raw, uint32_t *d_mask,

@@ -332,9 +332,12 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const float *p) {
 }
 
 // EPI 0: C = A B; 1: dZ = (A B) * gelu'(Z) (fp32 and bf16); 2: Z = A B + bias
-// (fp32) and H = gelu(Z) (bf16); 3: Y = A B + bias (fp32).  bias[N] for 2, 3.
+// (fp32) and H = gelu(Z) (bf16); 3: Y = A B + bias (fp32); 4: as 3, plus the
+// training loss terms of LossArgs (dY and one sum of squared errors per
+// tile).  bias[N] for 2, 3, 4.
 template <typename TA, typename TB, int EPI>
-__global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const float *bias) {
+__global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const float *bias,
+                                                          LossArgs la) {
   constexpr int NW = kGemmThreads / 64;
   __shared__ float part[NW - 1][16][64];
   const TA *A = static_cast<const TA *>(g.A);
@@ -382,6 +385,22 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const floa
   }
   __syncthreads();
   if (w != 0) return;
+  float sq = 0.0f; // EPI 4: this lane's squared errors
+  float tv[16];    // EPI 4: the targets of this lane's 16 outputs
+  if (EPI == 4) {
+    // every target load issued before the first dY store (the stores could
+    // alias them); rows and columns past the end read row 0, column 0
+    int src[16];
+    const int cl = n0 + c < g.N ? n0 + c : 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = m0 + 8 * (i / 4) + 4 * hh + (i % 4);
+      const int r = row < g.M ? row : 0;
+      src[i] = la.batch ? la.batch[r] : r;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) tv[i] = la.targets[(size_t)src[i] * g.N + cl];
+  }
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
 #pragma unroll
@@ -399,9 +418,20 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const floa
       const float v = acc[i] + bias[cl];
       g.Cf[o] = v;
       g.Cb[o] = (__bf16)gelu(v);
-    } else { // Y = W h + b
+    } else if (EPI == 3) { // Y = W h + b
       g.Cf[o] = acc[i] + bias[cl];
+    } else { // Y, then d = Y - T and dY = scale * d
+      const float y = acc[i] + bias[cl];
+      g.Cf[o] = y;
+      const float d = y - tv[i];
+      sq += d * d;
+      la.dyf[o] = la.scale * d;
+      la.dyb[o] = (__bf16)(la.scale * d);
     }
+  }
+  if (EPI == 4) {
+    sq = wave_sum(sq);
+    if (lane == 0) la.partial[blockIdx.x] = sq;
   }
 }
 
@@ -421,35 +451,7 @@ __global__ __launch_bounds__(256) void mlp_features(const SpaceDev *__restrict__
 }
 
 // ------------------------------------------------------ loss, biases, Adam
-// dY = 2 (Y - T) / (n C) in fp32 and bf16, and the mean squared error.
-__global__ __launch_bounds__(1024) void mse_grad(const float *__restrict__ Y, int Cp, int C, int n,
-                                                 const float *__restrict__ targets,
-                                                 const int32_t *__restrict__ batch,
-                                                 float *__restrict__ dYf, __bf16 *__restrict__ dYb,
-                                                 float *__restrict__ loss_out) {
-  __shared__ float red[16];
-  const float scale = 2.0f / (float)(n * C);
-  float sum = 0.0f;
-  for (int e = threadIdx.x; e < n * Cp; e += 1024) {
-    const int b = e / Cp, cc = e % Cp;
-    float d = 0.0f;
-    if (cc < C) {
-      const int src = batch ? batch[b] : b;
-      d = Y[(size_t)b * Cp + cc] - targets[(size_t)src * C + cc];
-      sum += d * d;
-    }
-    dYf[e] = scale * d;
-    dYb[e] = (__bf16)(scale * d);
-  }
-  sum = wave_sum(sum);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float t = 0.0f;
-    for (int w = 0; w < 16; ++w) t += red[w];
-    *loss_out = t / (float)(n * C);
-  }
-}
+// (dY and the squared errors come from the output layer's GEMM epilogue.)
 
 // Bias gradients: column sums over the batch.  A workgroup takes 64
 // consecutive columns (lane = column, coalesced rows); its 16 waves split the
@@ -458,8 +460,14 @@ constexpr int kBiasWaves = 16;
 __global__ __launch_bounds__(kBiasWaves * 64) void bias_grads(
     const float *__restrict__ dz1, const float *__restrict__ dz2, const float *__restrict__ dyf,
     int n, int H, int C, int Cp, float *__restrict__ gb1, float *__restrict__ gb2,
-    float *__restrict__ gb3) {
+    float *__restrict__ gb3, const float *__restrict__ partial, int n_partial,
+    float *__restrict__ loss_out) {
   __shared__ float part[kBiasWaves][64];
+  if (blockIdx.x == 0 && threadIdx.x == 0) { // the loss, tile partials in order
+    float t = 0.0f;
+    for (int k = 0; k < n_partial; ++k) t += partial[k];
+    *loss_out = t / (float)(n * C);
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + lane;
   const float *src = nullptr;
@@ -646,7 +654,7 @@ hipError_t launch_mlp_forward(const MlpFwdArgs &a, bool train, hipStream_t strea
 }
 
 hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const float *w2,
-                                   const float *w3, hipStream_t stream) {
+                                   const float *w3, const LossArgs *loss, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
   const int Cp = 32 * ((a.C + 31) / 32);
   hipLaunchKernelGGL(mlp_features, dim3((a.n + 255) / 256), dim3(256), 0, stream, a.sp,
@@ -654,9 +662,13 @@ hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const 
   auto gemm = [&](const GemmArgs &g, const float *bias, int epi) {
     const dim3 grid(((g.M + 31) / 32) * ((g.N + 31) / 32)), block(kGemmThreads);
     if (epi == 2)
-      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 2>), grid, block, 0, stream, g, bias);
+      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 2>), grid, block, 0, stream, g, bias,
+                         LossArgs{});
+    else if (loss == nullptr)
+      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 3>), grid, block, 0, stream, g, bias,
+                         LossArgs{});
     else
-      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 3>), grid, block, 0, stream, g, bias);
+      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 4>), grid, block, 0, stream, g, bias, *loss);
   };
   // Z1 = X W1^T + b1, H1 = gelu(Z1); Z2 = H1 W2^T + b2, H2 = gelu(Z2); Y = H2 W3^T + b3
   const int n = (int)a.n;
@@ -673,7 +685,7 @@ hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipSt
   if (tiles == 0) return hipSuccess;
   const dim3 grid(tiles), block(kGemmThreads);
 #define GEMM_CASE(TA, TB, E)                                                                   \
-  hipLaunchKernelGGL((gemm_bf16<TA, TB, E>), grid, block, 0, stream, g, nullptr)
+  hipLaunchKernelGGL((gemm_bf16<TA, TB, E>), grid, block, 0, stream, g, nullptr, LossArgs{})
   if (a_bf16 && b_bf16 && epi == 0) GEMM_CASE(__bf16, __bf16, 0);
   else if (a_bf16 && !b_bf16 && epi == 1) GEMM_CASE(__bf16, float, 1);
   else if (a_bf16 && !b_bf16 && epi == 0) GEMM_CASE(__bf16, float, 0);
@@ -683,20 +695,13 @@ hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_mse_grad(const float *Y, int Cp, int C, int n, const float *targets,
-                           const int32_t *batch, float *dYf, __bf16 *dYb, float *loss_out,
-                           hipStream_t stream) {
-  hipLaunchKernelGGL(mse_grad, dim3(1), dim3(1024), 0, stream, Y, Cp, C, n, targets, batch, dYf,
-                     dYb, loss_out);
-  return hipGetLastError();
-}
-
 hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dyf, int n, int H,
                              int C, int Cp, float *gb1, float *gb2, float *gb3,
+                             const float *partial, int n_partial, float *loss_out,
                              hipStream_t stream) {
   const int total = 2 * H + C;
   hipLaunchKernelGGL(bias_grads, dim3((total + 63) / 64), dim3(kBiasWaves * 64), 0, stream, dz1,
-                     dz2, dyf, n, H, C, Cp, gb1, gb2, gb3);
+                     dz2, dyf, n, H, C, Cp, gb1, gb2, gb3, partial, n_partial, loss_out);
   return hipGetLastError();
 }
 

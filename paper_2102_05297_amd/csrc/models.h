@@ -15,8 +15,27 @@ hipError_t launch_rows_to_columns(const float *d_src, uint32_t n, int C, float *
 // The perceptron's training forward pass (features, then one GEMM per layer
 // with the bias and GELU in its epilogue) into a.xout, z1out, h1out, z2out,
 // h2out, yout; w1, w2, w3: the fp32 master weights ([H][F], [H][H], [C][H]).
+// With `loss` set (training), the output layer's epilogue also forms the
+// error d = Y - T against the targets and writes dY = scale * d (fp32 dyf and
+// bf16 dyb, [n][Cp] like Y, padding columns untouched) and, per 32 x 32
+// output tile, the sum of d^2 into partial[tile] (ceil(n/32) * ceil(C/32)
+// tiles, row-major over the tiles).
+struct LossArgs {
+  const float *targets; // [rows][C]; output row i takes target row batch[i] (or i)
+  const int32_t *batch;
+  float scale;          // 2 / (n C)
+  float *dyf;
+  __bf16 *dyb;
+  float *partial;
+};
 hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const float *w2,
-                                   const float *w3, hipStream_t stream);
+                                   const float *w3, const LossArgs *loss, hipStream_t stream);
+// Bias gradients (column sums of dZ1, dZ2 [n][H] and dY [n][Cp]) and the
+// mean squared error: loss_out = (partial[0] + ... + partial[n_partial - 1]) / (n C).
+hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dyf, int n, int H,
+                             int C, int Cp, float *gb1, float *gb2, float *gb3,
+                             const float *partial, int n_partial, float *loss_out,
+                             hipStream_t stream);
 // The bf16 weights from the fp32 masters theta[n]: the inference fragments
 // w1p, w2p, w3p, and the transposed copies w2t[k][o] = W2[o][k] ([H][H]) and
 // w3t[k][c] = W3[c][k] ([H][Cp], Cp = C rounded up to 32) that the backward
