@@ -166,6 +166,29 @@ def test_gradients_with_two_output_tiles():
         assert np.abs(got - ref).max() <= 2e-2 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n", [1, 45, 200])
+def test_gradients_of_a_ragged_batch(n):
+    """Batches that are not a multiple of 32 rows: the last output tile is
+    partly past the end (its rows read no targets and add no squared error),
+    and a single row is a batch of one tile."""
+    m = cgs()
+    spec, valid = _space()
+    sp = m.Space.from_spec(spec)
+    params = _params(6, 64, 12, (38, n))
+    model = m.MLPModel(sp, params)
+    cfg, T, X = _pairs(spec, valid, n, 5)
+    g_gpu, loss = model.gradients(cfg, T)
+    pr = [np.asarray(p, np.float64) for p in params]
+    pr = [M.bf16(p).astype(np.float64) if i % 2 == 0 else p for i, p in enumerate(pr)]
+    loss_ref, g_ref = M.loss_and_grads(pr, X, T.astype(np.float64))
+    assert abs(loss - loss_ref) <= 1e-2 * loss_ref
+    for got, ref in zip(model.unflatten(g_gpu), g_ref):
+        got = got.astype(np.float64)
+        cos = (got * ref).sum() / np.sqrt((got * got).sum() * (ref * ref).sum())
+        assert cos > 0.999, cos
+        assert np.abs(got - ref).max() <= 2e-2 * np.abs(ref).max()
+
+
 def test_gradients_after_adam_steps_use_the_updated_weights():
     """Adam rewrites the bf16 weight copies that the backward products read:
     after five steps (lr 1e-2, so W2 moves far beyond its bf16 rounding) the
