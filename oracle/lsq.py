@@ -31,7 +31,11 @@ Readings (the paper fixes none of these details):
   lam = 1e-9 * trace(F^T F) / T, a ridge that keeps the solve defined when
   constraints leave the design rank-deficient; a subspace without training
   points has beta = 0;
-* predictions are F(x) beta of the configuration's subspace.
+* predictions are F(x) beta of the configuration's subspace, clamped at 0:
+  the score equation (Sect. 3.6) divides by the sum of two counters and
+  assumes both are non-negative, so a negative polynomial value would let a
+  term leave [-1, 1] or divide by zero.  A clamped prediction of exactly 0
+  drops the counter from PC_used for that configuration.
 """
 from __future__ import annotations
 
@@ -145,11 +149,17 @@ def fit(values, radix, digits, Y, order: int) -> PolyModel:
     return PolyModel(order, S, tt, beta, lam, count)
 
 
-def predict(model: PolyModel, values, radix, digits) -> np.ndarray:
-    """Predictions [n][C] in float64."""
+def value(model: PolyModel, values, radix, digits) -> np.ndarray:
+    """The fitted polynomials' values [n][C] in float64 (unclamped)."""
     F = basis(features(values, radix, digits), model.order)
     s = subspace(radix, digits)
     return np.einsum("nt,ntc->nc", F, model.beta[s])
+
+
+def predict(model: PolyModel, values, radix, digits) -> np.ndarray:
+    """Predicted counters [n][C] in float64: the polynomial values clamped
+    at 0 (counters are non-negative)."""
+    return np.maximum(value(model, values, radix, digits), 0.0)
 
 
 def abs_terms(model: PolyModel, values, radix, digits) -> np.ndarray:

@@ -75,6 +75,79 @@ def forward_bf16(params, X, round_activations: bool = True):
     return h2 @ w3.T + b3
 
 
+# ------------------------------------------------ bounds of a device forward
+# A forward pass with the device's precision choices (bf16 weights, inputs and
+# hidden activations, biases in float32, products summed in float32, GELU by
+# a published erfc approximation) differs from forward_bf16 by:
+#   * summation: any order of K float32 additions (round to nearest, or any
+#     rounding of at most one float32 ulp) errs by at most
+#     (K + 1) 2^-23 (sum |w x| + |b|), plus 2^-126 per product for a
+#     flushed subnormal;
+#   * GELU: max(z, 0) - |z| Phi(-|z|) with erfc by Abramowitz & Stegun
+#     7.1.26 (|error| <= 1.5e-7), so |z| Phi(-|z|) errs by 0.75e-7 |z|; the
+#     float32 evaluation of the tail term (reciprocal, exp2 of a rounded
+#     argument, polynomial, products) by (16 + z^2) 2^-24 relative, at most
+#     2^-24 * 3 absolute since (16 + z^2) |z| Phi(-|z|) <= 2.9; the final
+#     rounding by 2^-24 |gelu(z)|; doubled for safety;
+#   * bf16 rounding of an activation: the device rounds its float32 GELU
+#     value, which lies within the two bounds above of the exact GELU of the
+#     exact pre-activation; rounding is monotone, so the device's bf16 value
+#     lies between the roundings of the interval's ends, and equals the
+#     oracle's whenever no rounding boundary falls inside the interval.
+def gelu_error_bound(z):
+    """Bound of |device GELU(z) - gelu(z)| for float32 evaluation (above)."""
+    az = np.abs(z)
+    tail = np.minimum(0.5 * az, 0.2)
+    return 2.0 * (0.75e-7 * az + 2.0 ** -24 * (16.0 + z * z) * tail
+                  + 2.0 ** -24 * np.abs(gelu(z))) + 1e-30
+
+
+def _sum_bound(absW, absA, absb, K):
+    return (K + 1) * 2.0 ** -23 * (absA @ absW.T + absb) + K * 2.0 ** -126
+
+
+def _bf16_range(g, dg):
+    """bf16 values a float32 rounding of anything in [g - dg, g + dg] can give."""
+    lo32 = np.asarray(g - dg, np.float32)
+    lo32 = np.where(lo32.astype(np.float64) > g - dg, np.nextafter(lo32, np.float32(-np.inf)), lo32)
+    hi32 = np.asarray(g + dg, np.float32)
+    hi32 = np.where(hi32.astype(np.float64) < g + dg, np.nextafter(hi32, np.float32(np.inf)), hi32)
+    return bf16(lo32).astype(np.float64), bf16(hi32).astype(np.float64)
+
+
+def forward_bf16_interval(params, X):
+    """forward_bf16's output y and a bound E with |y_device - y| <= E for
+    every device forward with the precision choices above (the same bf16
+    weights, inputs and activation rounding, float32 sums in any order, a
+    GELU within gelu_error_bound).  Returns (y, E), both [n][C] float64."""
+    W1, b1, W2, b2, W3, b3 = params
+    w1, w2, w3 = (bf16(w).astype(np.float64) for w in (W1, W2, W3))
+    b1, b2, b3 = (np.asarray(b, np.float32).astype(np.float64) for b in (b1, b2, b3))
+    x = bf16(X).astype(np.float64)
+    K1, H = w1.shape[1], w1.shape[0]
+    # layer 1: exact inputs and weights; only the sum rounds
+    z1 = x @ w1.T + b1
+    dz1 = _sum_bound(np.abs(w1), np.abs(x), np.abs(b1), K1)
+    g1 = gelu(z1)
+    dg1 = 1.1295 * dz1 + gelu_error_bound(z1)      # |gelu'| <= 1.1295
+    h1 = bf16(g1).astype(np.float64)
+    lo, hi = _bf16_range(g1, dg1)
+    dh1 = np.maximum(h1 - lo, hi - h1)
+    # layer 2: the device's h1 differs by at most dh1
+    z2 = h1 @ w2.T + b2
+    a2 = np.abs(w2)
+    dz2 = dh1 @ a2.T + _sum_bound(a2, np.abs(h1) + dh1, np.abs(b2), H)
+    g2 = gelu(z2)
+    dg2 = 1.1295 * dz2 + gelu_error_bound(z2)
+    h2 = bf16(g2).astype(np.float64)
+    lo, hi = _bf16_range(g2, dg2)
+    dh2 = np.maximum(h2 - lo, hi - h2)
+    a3 = np.abs(w3)
+    y = h2 @ w3.T + b3
+    E = dh2 @ a3.T + _sum_bound(a3, np.abs(h2) + dh2, np.abs(b3), H)
+    return y, E
+
+
 def predict(params, X) -> np.ndarray:
     return np.maximum(forward(params, X)[0], 0.0)
 

@@ -69,7 +69,7 @@ def test_recovers_a_polynomial_in_its_basis(seed, order):
     des = LS.design(values, radix, d)
     m = LS.fit(values, radix, d[des], Y[des], order)
     assert np.allclose(m.beta, truth, rtol=1e-5, atol=1e-5)
-    assert np.allclose(LS.predict(m, values, radix, d), Y, rtol=1e-5, atol=1e-5)
+    assert np.allclose(LS.value(m, values, radix, d), Y, rtol=1e-5, atol=1e-5)
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -106,12 +106,16 @@ def test_three_levels_interpolate_the_quadratic():
     d = _grid(radix)
     y = np.array([[3.0], [-1.0], [10.0]])
     m = LS.fit(values, radix, d, y, 1)
-    assert np.allclose(LS.predict(m, values, radix, d), y, rtol=1e-7)
+    assert np.allclose(LS.value(m, values, radix, d), y, rtol=1e-7)
     # value at x = 0 from the Lagrange form through x = -1, -1/3, 1
     xs = [-1.0, -1.0 / 3.0, 1.0]
     lag = sum(y[i, 0] * np.prod([(0 - xs[j]) / (xs[i] - xs[j]) for j in range(3) if j != i])
               for i in range(3))
     assert np.isclose(m.beta[0, 0, 0], lag, rtol=1e-7)
+    # predicted counters are the values clamped at 0: the negative middle
+    # value becomes exactly 0, the others are unchanged
+    p = LS.predict(m, values, radix, d)
+    assert p[1, 0] == 0.0 and np.allclose(p[[0, 2]], y[[0, 2]], rtol=1e-7)
 
 
 def test_rank_deficient_design_approaches_the_minimum_norm_solution():
@@ -122,7 +126,7 @@ def test_rank_deficient_design_approaches_the_minimum_norm_solution():
     F = LS.basis(LS.features(values, radix, d), 2)
     ref = np.linalg.pinv(F) @ y
     assert np.allclose(m.beta[0], ref, rtol=1e-3, atol=1e-4)
-    assert np.allclose(LS.predict(m, values, radix, d), y, rtol=1e-6)
+    assert np.allclose(LS.value(m, values, radix, d), y, rtol=1e-6)
 
 
 def test_normalisation_does_not_change_predictions():
@@ -140,7 +144,7 @@ def test_normalisation_does_not_change_predictions():
     for k in range(4):
         b = np.linalg.lstsq(Fr[s == k], Y[s == k], rcond=None)[0]
         pred[s == k] = Fr[s == k] @ b
-    assert np.allclose(LS.predict(m, values, radix, d), pred, rtol=1e-6, atol=1e-6)
+    assert np.allclose(LS.value(m, values, radix, d), pred, rtol=1e-6, atol=1e-6)
 
 
 def test_empty_subspace_has_zero_coefficients():

@@ -104,3 +104,80 @@ def test_bf16_forward_reduces_to_plain_forward():
     w2, w3 = np.abs(pb[2]), np.abs(pb[4])
     bound = (np.abs(h2) @ w3.T + (np.abs(h1) @ w2.T) @ w3.T * 1.2) * 2.0 ** -8
     assert (np.abs(yb - y) <= bound + 1e-12).all()
+
+
+# ------------------------------------------- bound of a device-like forward
+# A float32 model of the device's arithmetic, written from the published
+# formulas (not from the kernels): products of bf16 values summed in float32
+# in a random order, the bias added in float32, GELU as max(z, 0) minus the
+# erfc tail of Abramowitz & Stegun 7.1.26 evaluated in float32 with the
+# reciprocal and the exponential perturbed by up to 2 ulps (hardware
+# approximations), then rounded to bf16.
+AS_P = np.float32(0.3275911)
+AS_A = [np.float32(v) for v in (0.254829592, -0.284496736, 1.421413741, -1.453152027,
+                                1.061405429)]
+
+
+def _ulps(g, v, k=2):
+    for _ in range(int(g.integers(0, k + 1))):
+        v = np.nextafter(v, np.where(g.random(v.shape) < 0.5, np.float32(np.inf),
+                                     np.float32(-np.inf))).astype(np.float32)
+    return v
+
+
+def _gelu_f32(g, z):
+    z = np.asarray(z, np.float32)
+    az = np.abs(z)
+    x = (az * np.float32(1 / np.sqrt(2))).astype(np.float32)
+    t = _ulps(g, (np.float32(1) / (np.float32(1) + AS_P * x)).astype(np.float32))
+    e = _ulps(g, np.exp2((-(x * x) * np.float32(1 / np.log(2))).astype(np.float32)))
+    poly = AS_A[4]
+    for a in AS_A[3::-1]:
+        poly = (a + t * poly).astype(np.float32)
+    poly = (t * poly).astype(np.float32)
+    tail = (np.float32(0.5) * az * poly * e).astype(np.float32)
+    return (np.maximum(z, np.float32(0)) - tail).astype(np.float32)
+
+
+def test_gelu_error_bound_covers_a_float32_evaluation():
+    g = np.random.default_rng(5)
+    z = np.concatenate([np.linspace(-15, 15, 400001), g.normal(0, 3, 100000),
+                        [-40.0, -1e-30, 0.0, 1e-30, 40.0]]).astype(np.float32)
+    for _ in range(3):
+        got = _gelu_f32(g, z).astype(np.float64)
+        zz = z.astype(np.float64)
+        assert (np.abs(got - M.gelu(zz)) <= M.gelu_error_bound(zz)).all()
+
+
+def _device_like_forward(g, params, X):
+    W1, b1, W2, b2, W3, b3 = params
+    h = M.bf16(X)
+    for W, b, act in ((W1, b1, True), (W2, b2, True), (W3, b3, False)):
+        w = M.bf16(W)
+        z = np.zeros((h.shape[0], w.shape[0]), np.float32)
+        for k in g.permutation(w.shape[1]):
+            z = (z + np.outer(h[:, k], w[:, k]).astype(np.float32)).astype(np.float32)
+        z = (z + np.asarray(b, np.float32)).astype(np.float32)
+        h = M.bf16(_gelu_f32(g, z)) if act else z
+    return h.astype(np.float64)
+
+
+@pytest.mark.parametrize("seed,H", [(0, 16), (1, 64), (2, 64)])
+def test_forward_bound_covers_device_like_forwards(seed, H):
+    g = np.random.default_rng(seed)
+    F_, C, n = 6, 5, 400
+    params = [g.normal(0, 1.0, (H, F_)).astype(np.float32), g.normal(0, 0.5, H).astype(np.float32),
+              g.normal(0, 2.0 / np.sqrt(H), (H, H)).astype(np.float32),
+              g.normal(0, 0.5, H).astype(np.float32),
+              g.normal(0, 2.0 / np.sqrt(H), (C, H)).astype(np.float32),
+              g.normal(0, 0.5, C).astype(np.float32)]
+    X = g.integers(0, 8, (n, F_)) / 8.0
+    y, E = M.forward_bf16_interval(params, X)
+    assert np.allclose(y, M.forward_bf16(params, X), rtol=0, atol=1e-12)
+    worst = 0.0
+    for _ in range(4):
+        got = _device_like_forward(g, params, X)
+        assert (np.abs(got - y) <= E).all()
+        worst = max(worst, float((np.abs(got - y) / E).max()))
+    # the bound is not vacuous: some forward comes within a factor 50 of it
+    assert worst > 0.02
