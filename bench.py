@@ -156,6 +156,14 @@ def copy_probe(n_bytes: int = 1 << 30, reps: int = 5) -> dict:
 BF16_PEAK_TFLOPS = 2500.0
 
 
+def mean_predictor_rmse(P_tree) -> float:
+    """RMSE against the tree of the constant model that predicts each
+    counter's mean over the same sample: what a surrogate that learned
+    nothing of the configurations would score."""
+    P = np.asarray(P_tree, dtype=np.float64)
+    return float(np.sqrt(np.mean((P - P.mean(axis=0)) ** 2)))
+
+
 def mlp_path(cgs, sp, tree, n_pairs=8192, steps=2000, batch=256, top_pairs=100):
     """Learned surrogate: train on forest samples + N(0, 0.02) noise, predict
     every valid configuration, compare with the tree and time both uses."""
@@ -189,6 +197,7 @@ def mlp_path(cgs, sp, tree, n_pairs=8192, steps=2000, batch=256, top_pairs=100):
     P_mlp = model.copy_predictions()
     sample = synth.uniform_indices(synth.rng(3, 4), 65536, sp.n_valid)
     rmse = float(np.sqrt(np.mean((P_mlp[sample].astype(np.float64) - P_tree_all[sample]) ** 2)))
+    rmse_mean = mean_predictor_rmse(P_tree_all[sample])
     # top-10 agreement on the first scoring pairs of the search trajectory
     agree = []
     sess_t = cgs.Session(sp)
@@ -229,6 +238,7 @@ def mlp_path(cgs, sp, tree, n_pairs=8192, steps=2000, batch=256, top_pairs=100):
                           "unit": "TFLOP/s", "frac": tflops / BF16_PEAK_TFLOPS},
         "valu_roofline": valu_roofline(f"{F_}-{H}-{H}-{Cn}", sp.n_valid, inf_ms),
         "rmse_vs_tree": rmse, "rmse_sample": 65536,
+        "rmse_mean_predictor": rmse_mean,
         "top10_agreement": float(np.mean(agree)), "top10_pairs": top_pairs,
         "scored_per_s_cached": scored / (step_ms / 1e3),
         "scored_per_s_eval_in_step": sp.n_valid / ((inf_ms + step_ms) / 1e3),
@@ -298,51 +308,6 @@ def batch_path(cgs, n_sess=64, n_steps=10):
     }
 
 
-def online_search(cgs, sp, tree, mlp, n_steps, deltas, U, noise, seed_cfg, seed_tgt, val_sample,
-                  retrain_every=20, threshold=0.05, train_steps=500, batch=256, lr=1e-3,
-                  batch_rng=None):
-    """Search with the surrogate retrained online (an extension): every
-    `retrain_every` steps the perceptron is trained further on the seed pairs
-    plus the pairs the search collected (configuration, counters measured by
-    the synthetic profiler = tree prediction + noise); for the next window the
-    surrogate scores only if its RMSE against the tree over `val_sample` is at
-    most `threshold`, else the tree does.  Returns the per-step log."""
-    import synth
-    cfg = list(np.asarray(seed_cfg, dtype=np.uint32))
-    tgt = list(np.asarray(seed_tgt, dtype=np.float32))
-    rng = batch_rng if batch_rng is not None else synth.rng(5, 9)
-    rmse = mlp.rmse(tree, val_sample)
-    use_mlp = rmse <= threshold
-    log = {"windows": [], "picks": [], "step_ms": [], "retrain_ms": []}
-    log["windows"].append({"step": 0, "rmse": rmse, "model": "mlp" if use_mlp else "tree"})
-    sess = cgs.Session(sp)
-    sess.search_step(tree, cgs.NO_PROFILE)
-    raw, l = sess.sample_next(int(U[0]))
-    log["picks"].append(l)
-    cfg.append(raw)
-    tgt.append(tree.gather_predictions([l])[0] + noise[0])
-    for i in range(1, n_steps + 1):
-        if i % retrain_every == 0:
-            t0 = time.perf_counter()
-            idx = synth.minibatches(rng, train_steps, batch, len(cfg))
-            mlp.train(np.array(cfg, np.uint32), np.array(tgt, np.float32), idx, lr=lr)
-            rmse = mlp.rmse(tree, val_sample)
-            log["retrain_ms"].append((time.perf_counter() - t0) * 1e3)
-            use_mlp = rmse <= threshold
-            log["windows"].append({"step": i, "rmse": rmse, "model": "mlp" if use_mlp else "tree"})
-        t0 = time.perf_counter()
-        sess.search_step(mlp if use_mlp else tree, raw, delta=deltas[i - 1])
-        r = sess.sample_next(int(U[i]))
-        log["step_ms"].append((time.perf_counter() - t0) * 1e3)
-        if r is None:
-            break
-        raw, l = r
-        log["picks"].append(l)
-        cfg.append(raw)
-        tgt.append(tree.gather_predictions([l])[0] + noise[i])
-    return log
-
-
 def online_path(cgs, n_steps=200):
     """The 16-parameter space (2^14 * 3^8 = 107,495,424 raw configurations),
     forest of 16 depth-12 trees over 32 counters as the tree model and the
@@ -368,8 +333,12 @@ def online_path(cgs, n_steps=200):
     mlp.train(valid[seed_pos], seed_tgt, synth.minibatches(synth.rng(5, 7), 2000, 256, 8192))
     t_first = time.perf_counter() - t0
     val_sample = synth.uniform_indices(synth.rng(5, 8), 65536, sp.n_valid)
-    log = online_search(cgs, sp, tree, mlp, n_steps, deltas, U, noise, valid[seed_pos], seed_tgt,
-                        val_sample)
+    opts = cgs.cgs_default_online_opts()
+    n_windows = 1 + n_steps // opts.retrain_every
+    batch_u64 = synth.uniforms_u64(synth.rng(5, 9),
+                                   (n_windows - 1) * opts.train_steps * opts.batch)
+    log = cgs.Session(sp).online_run(tree, mlp, deltas, U, noise, valid[seed_pos], seed_tgt,
+                                     val_sample, batch_u64, opts)
     inf_ms = mlp.eval_ms()
     flop = 2.0 * (16 * 512 + 512 * 512 + 512 * C) * sp.n_valid
     return {
@@ -378,8 +347,9 @@ def online_path(cgs, n_steps=200):
         "mlp_inference_ms": inf_ms, "mlp_inference_tflops": flop / (inf_ms / 1e3) / 1e12,
         "mlp_inference_valu_roofline": valu_roofline(f"16-512-512-{C}", sp.n_valid, inf_ms),
         "windows": log["windows"], "retrain_ms_mean": float(np.mean(log["retrain_ms"])),
-        "step_ms_median": float(np.median(log["step_ms"])), "steps": len(log["step_ms"]),
-        "scored_per_s": float(sp.n_valid / (np.median(log["step_ms"]) / 1e3)),
+        "rmse_mean_predictor": mean_predictor_rmse(tree.gather_predictions(val_sample)),
+        "step_ms_median": float(np.median(log["step_us"])) / 1e3, "steps": len(log["step_us"]),
+        "scored_per_s": float(sp.n_valid / (np.median(log["step_us"]) / 1e6)),
     }
 
 

@@ -169,7 +169,9 @@ void cgs_space_destroy(cgs_space space);
  * trees' leaf vectors: sum over t ascending in float32, then one division by
  * n_trees.
  *   feat, thr [n_trees][2^depth - 1]   uint8
- *   leaves    [n_trees][2^depth][n_counters]  float32
+ *   leaves    [n_trees][2^depth][n_counters]  float32, finite and >= 0
+ *             (counters are non-negative: the score equation divides by
+ *             the sum of two predictions; CGS_EINVAL otherwise)
  * The predictions of all valid configurations are kept on the device
  * (n_counters * n_valid floats) and reused by every search step. */
 cgs_status cgs_model_load_forest(cgs_space space, int n_trees, int depth, int n_counters,
@@ -204,7 +206,7 @@ void cgs_model_destroy(cgs_model model);
  *
  *   points_host[n]        valid indices of the measured configurations
  *                         (repeats allowed); n >= 2, n * n_counters < 2^31
- *   targets_host[n][C]    their measured counters, finite
+ *   targets_host[n][C]    their measured counters, finite and >= 0
  *   keys_host[n]          one random 64-bit number per point: the training
  *                         half is the ceil(n/2) points first in the order of
  *                         (key >> 32, point index), the rest is the test half
@@ -225,7 +227,7 @@ void cgs_model_destroy(cgs_model model);
  * float32(value * 2^-s_c).  The model's predictions of every valid
  * configuration are computed as for a loaded forest.
  *
- * CGS_EINVAL for a point outside the valid list or a non-finite target,
+ * CGS_EINVAL for a point outside the valid list or a negative or non-finite target,
  * CGS_ERANGE for sizes outside the limits.  Synchronises; `report` may be
  * NULL. */
 typedef struct {
@@ -254,7 +256,9 @@ cgs_status cgs_model_fit_tree(cgs_space space, uint64_t n, int n_counters,
  * (F^T F + lam I) beta = F^T Y over the subspace's training points, float64,
  * lam = 1e-9 trace(F^T F) / T (keeps rank-deficient designs defined); a
  * subspace without training points has beta = 0.  Predictions of every valid
- * configuration are evaluated in float32 and kept like a forest's. */
+ * configuration are evaluated in float32, clamped at 0 (a polynomial can go
+ * negative where counters cannot; a prediction of exactly 0 drops the
+ * counter from the score of that configuration) and kept like a forest's. */
 #define CGS_POLY_MAX_TERMS 176
 #define CGS_POLY_MAX_ORDER 4
 #define CGS_POLY_MAX_BINARY 16
@@ -291,7 +295,7 @@ cgs_status cgs_poly_shape(cgs_model model, int *n_subspaces, int *n_terms);
 cgs_status cgs_poly_copy_coefficients(cgs_model model, double *beta_host);
 
 /* A model whose predictions the caller gives: pred_host[n_valid][n_counters]
- * (finite), e.g. counters measured on every configuration, the setting of
+ * (finite and >= 0, else CGS_EINVAL), e.g. counters measured on every configuration, the setting of
  * Sect. 4.3 where the search reads measured counters instead of a model's. */
 cgs_status cgs_model_load_predictions(cgs_space space, int n_counters, const float *pred_host,
                                       cgs_model *out);
@@ -471,6 +475,56 @@ cgs_status cgs_search_run(cgs_session session, cgs_model model, int n_steps,
                           const double *measured_host, const cgs_expert_params *expert,
                           const uint64_t *u64_host, uint64_t *raw_out_host,
                           uint64_t *valid_out_host, double *step_us_host);
+
+/* Online retraining of the perceptron surrogate with tree fallback (an
+ * extension: the model of Sect. 3.4 stands in for measured counters; here a
+ * perceptron stands in for the tree, and the tree judges it).  A search of
+ * Alg. 1 with one draw per step, like cgs_search_run but with counter
+ * changes given per step, that collects (configuration, counters) pairs as
+ * it goes: each pick's counters as measured by a synthetic profiler, the
+ * tree's prediction plus noise_host[i][C].  Steps are grouped in windows of
+ * retrain_every steps.  Before step 0 and at every window start the
+ * surrogate's RMSE against the tree over the valid indices val_sample_host
+ * [n_val] (cgs_model_rmse) decides the model of the window: the surrogate
+ * if RMSE <= threshold, else the tree.  At the start of window w >= 1 the
+ * surrogate first takes train_steps Adam steps (cgs_mlp_train) on the seed
+ * pairs seed_cfg_raw_host[n_seed] / seed_targets_host[n_seed][C] followed
+ * by every pair collected so far, in pick order; entry b of Adam step k
+ * uses pair floor(u * n_pairs / 2^64) with
+ * u = batch_u64_host[(w - 1)][k][b].
+ *   step 0          the uniform start (cgs_search_step without a profile on
+ *                   the tree, cgs_sample_next with u64_host[0])
+ *   step i >= 1     profile the last pick with changes delta_host[i - 1][C],
+ *                   draw with u64_host[i]
+ *   raw_out_host[n_steps + 1], valid_out_host (may be NULL): picks; unmade
+ *                   picks stay 2^64 - 1
+ *   window_rmse_host[W], window_mlp_host[W] (1: surrogate, 0: tree), for the
+ *                   W = 1 + n_steps / retrain_every windows
+ *   step_us_host[n_steps], retrain_ms_host[W - 1] (may be NULL): wall times
+ *                   of each step with its draw, and of each retraining with
+ *                   its RMSE check
+ * tree: any model (normally a forest); mlp: a perceptron with the same
+ * counters on the same space; the session should be fresh.  Returns the
+ * first failing call's status (CGS_EEMPTY when the space runs out). */
+typedef struct {
+  int32_t retrain_every; /* steps per window (20)                          */
+  int32_t train_steps;   /* Adam steps per retraining (500); 0: none        */
+  int32_t batch;         /* pairs per Adam step, 1..4096 (256)              */
+  int32_t reserved;
+  float lr, beta1, beta2, eps; /* Adam (1e-3, 0.9, 0.999, 1e-8)            */
+  double threshold;      /* largest RMSE at which the surrogate scores (0.05) */
+} cgs_online_opts;
+
+void cgs_default_online_opts(cgs_online_opts *out);
+cgs_status cgs_online_run(cgs_session session, cgs_model tree, cgs_model mlp, int n_steps,
+                          const float *delta_host, const uint64_t *u64_host,
+                          const float *noise_host, uint64_t n_seed,
+                          const uint32_t *seed_cfg_raw_host, const float *seed_targets_host,
+                          uint64_t n_val, const uint32_t *val_sample_host,
+                          const uint64_t *batch_u64_host, const cgs_online_opts *opts,
+                          uint64_t *raw_out_host, uint64_t *valid_out_host,
+                          double *window_rmse_host, int32_t *window_mlp_host,
+                          double *step_us_host, double *retrain_ms_host);
 
 /* Statistics of the last step (synchronises). */
 cgs_status cgs_session_step_info(cgs_session session, cgs_step_info *out);

@@ -44,6 +44,7 @@ EXPORTS = (
     "cgs_model_copy_forest", "cgs_poly_design", "cgs_model_fit_poly", "cgs_poly_shape",
     "cgs_poly_copy_coefficients", "cgs_model_load_predictions", "cgs_default_tuning_opts",
     "cgs_tuning_run", "cgs_batch_draw", "cgs_tuning_run_batch", "cgs_search_run",
+    "cgs_default_online_opts", "cgs_online_run",
 )
 
 
@@ -103,6 +104,12 @@ class cgs_tuning_opts(C.Structure):
                 ("well_factor", C.c_double)]
 
 
+class cgs_online_opts(C.Structure):
+    _fields_ = [("retrain_every", C.c_int32), ("train_steps", C.c_int32), ("batch", C.c_int32),
+                ("reserved", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("threshold", C.c_double)]
+
+
 class cgs_poly_fit_report(C.Structure):
     _fields_ = [("n_subspaces", C.c_int32), ("n_terms", C.c_int32), ("order", C.c_int32),
                 ("n_counters", C.c_int32), ("n_points", C.c_uint64), ("fit_ms", C.c_float),
@@ -159,6 +166,9 @@ _sig("cgs_tuning_run", [_p, _p, _p, _p, _ptr(cgs_expert_params), _p, _u64, _ptr(
 _sig("cgs_session_create", [_p, _ptr(cgs_params), _ptr(_p)])
 _sig("cgs_search_run", [_p, _p, C.c_int, _p, _p, _p, _p, _p, _p])
 _sig("cgs_search_step", [_p, _p, _u64, _p, _p, _ptr(cgs_expert_params)])
+_sig("cgs_default_online_opts", [_ptr(cgs_online_opts)], None)
+_sig("cgs_online_run", [_p, _p, _p, C.c_int, _p, _p, _p, _u64, _p, _p, _u64, _p, _p,
+                        _ptr(cgs_online_opts), _p, _p, _p, _p, _p, _p])
 _sig("cgs_search_step_neighbourhood", [_p, _p, _u64, C.c_int, _p, _p, _ptr(cgs_expert_params)])
 _sig("cgs_session_copy_neighbourhood", [_p, _u64, _p, _p, _p, _ptr(_u64)])
 _sig("cgs_sample_next", [_p, _u64, _ptr(_u64), _ptr(_u64)])
@@ -213,6 +223,17 @@ def cgs_default_params() -> cgs_params:
     p = cgs_params()
     _lib.cgs_default_params(C.byref(p))
     return p
+
+
+def cgs_default_online_opts(**kw) -> cgs_online_opts:
+    """Online-retraining settings: retrain every 20 steps with 500 Adam steps
+    of 256 pairs (lr 1e-3), surrogate kept while its RMSE is <= 0.05;
+    keyword arguments override fields."""
+    o = cgs_online_opts()
+    _lib.cgs_default_online_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
 
 
 def cgs_default_expert_params() -> cgs_expert_params:
@@ -596,6 +617,51 @@ class Session:
                                    _ptrof(us), _ptrof(raw), _ptrof(val), _ptrof(t_us)),
                "cgs_search_run")
         return raw, val, t_us[:n]
+
+    def online_run(self, tree, mlp, deltas, uniforms, noise, seed_cfg, seed_targets, val_sample,
+                   batch_u64=None, opts: Optional[cgs_online_opts] = None):
+        """A search with the perceptron surrogate retrained online and the tree
+        as fallback, in the library (cgs_online_run).  deltas [n][C],
+        uniforms [n + 1], noise [n + 1][C]; batch_u64 [windows - 1][steps]
+        [batch] 64-bit numbers choosing the training rows.  Returns a dict:
+        raw / valid picks, per-window RMSE and model, step and retrain times."""
+        o = opts if opts is not None else cgs_default_online_opts()
+        d = _arr(deltas, np.float32)
+        n = d.shape[0]
+        Cn = tree.n_counters
+        d = d.reshape(n, Cn)
+        us = _arr(uniforms, np.uint64)
+        nz = _arr(noise, np.float32).reshape(-1, Cn)
+        if len(us) < n + 1 or nz.shape[0] < n + 1:
+            raise ValueError("n_steps + 1 uniforms and noise rows needed")
+        cfg = _arr(seed_cfg, np.uint32)
+        tg = _arr(seed_targets, np.float32).reshape(len(cfg), Cn)
+        val = _arr(val_sample, np.uint32)
+        W = 1 + n // o.retrain_every
+        bu = None
+        if batch_u64 is not None:
+            bu = _arr(batch_u64, np.uint64)
+            if bu.size < (W - 1) * o.train_steps * o.batch:
+                raise ValueError("batch_u64 needs (windows - 1) * train_steps * batch numbers")
+        raw = np.zeros(n + 1, np.uint64)
+        valid = np.zeros(n + 1, np.uint64)
+        rmse = np.zeros(W, np.float64)
+        use = np.zeros(W, np.int32)
+        step_us = np.zeros(max(n, 1), np.float64)
+        retrain_ms = np.zeros(max(W - 1, 1), np.float64)
+        st = _lib.cgs_online_run(self.h, tree.h, mlp.h, n, _ptrof(d), _ptrof(us), _ptrof(nz),
+                                 len(cfg), _ptrof(cfg), _ptrof(tg), len(val), _ptrof(val),
+                                 _ptrof(bu), C.byref(o), _ptrof(raw), _ptrof(valid),
+                                 _ptrof(rmse), _ptrof(use), _ptrof(step_us), _ptrof(retrain_ms))
+        done = int((raw != np.uint64(2 ** 64 - 1)).sum())
+        if st != EEMPTY:
+            _check(st, "cgs_online_run")
+        return {"raw": raw[:done], "picks": [int(x) for x in valid[:done]],
+                "windows": [{"step": w * o.retrain_every, "rmse": float(rmse[w]),
+                             "model": "mlp" if use[w] == 1 else "tree"}
+                            for w in range(W) if use[w] >= 0],
+                "step_us": step_us[:max(done - 1, 0)],
+                "retrain_ms": retrain_ms[:W - 1]}
 
     def tuning_run(self, model, runtime, counters, uniforms, draws: int = 5,
                    max_tests: Optional[int] = None, stop_at_well: bool = True,

@@ -530,7 +530,8 @@ extern "C" cgs_status cgs_model_load_forest(cgs_space sp, int n_trees, int depth
   }
   const size_t n_leaf_vals = (size_t)n_trees * n_leaf * n_counters;
   for (size_t i = 0; i < n_leaf_vals; ++i)
-    if (!std::isfinite(leaves[i])) return fail(CGS_EINVAL, "leaf value %zu is not finite", i);
+    if (!(leaves[i] >= 0.0f) || !std::isfinite(leaves[i]))
+      return fail(CGS_EINVAL, "leaf value %zu is negative or not finite", i);
 
   cgs_model m = new (std::nothrow) cgs_model_s();
   if (!m) return fail(CGS_ENOMEM, "host allocation");
@@ -633,7 +634,7 @@ extern "C" cgs_status cgs_model_fit_tree(cgs_space sp, uint64_t n, int n_counter
   if (fo.err) {
     cleanup();
     return fail(CGS_EINVAL, "%s", (fo.err & 1u) ? "a point is outside the valid list"
-                                                : "a target is not finite");
+                                                : "a target is negative or not finite");
   }
   const int depth = fo.depth;
   m = new (std::nothrow) cgs_model_s();
@@ -1000,8 +1001,8 @@ extern "C" cgs_status cgs_model_load_predictions(cgs_space sp, int n_counters,
   const uint64_t nv = sp->n_valid;
   if (nv == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
   for (uint64_t i = 0; i < nv * (uint64_t)n_counters; ++i)
-    if (!std::isfinite(pred_host[i])) return fail(CGS_EINVAL, "prediction %llu is not finite",
-                                                  (unsigned long long)i);
+    if (!(pred_host[i] >= 0.0f) || !std::isfinite(pred_host[i]))
+      return fail(CGS_EINVAL, "prediction %llu is negative or not finite", (unsigned long long)i);
   cgs_model m = new (std::nothrow) cgs_model_s();
   if (!m) return fail(CGS_ENOMEM, "host allocation");
   m->space = sp;
@@ -2013,6 +2014,135 @@ extern "C" cgs_status cgs_search_run(cgs_session s, cgs_model m, int n_steps,
           std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     raw_out[i + 1] = raw;
     if (valid_out) valid_out[i + 1] = valid;
+  }
+  return CGS_OK;
+}
+
+extern "C" void cgs_default_online_opts(cgs_online_opts *o) {
+  if (!o) return;
+  o->retrain_every = 20;
+  o->train_steps = 500;
+  o->batch = 256;
+  o->reserved = 0;
+  o->lr = 1e-3f;
+  o->beta1 = 0.9f;
+  o->beta2 = 0.999f;
+  o->eps = 1e-8f;
+  o->threshold = 0.05;
+}
+
+// The online policy around the library's own calls: per window one
+// cgs_model_rmse (and, after the first window, one cgs_mlp_train), per step
+// one cgs_search_step and one cgs_sample_next.  Targets of the collected pairs
+// are gathered from the tree once per window.
+extern "C" cgs_status cgs_online_run(cgs_session s, cgs_model tree, cgs_model mlp, int n_steps,
+                                     const float *delta, const uint64_t *u64, const float *noise,
+                                     uint64_t n_seed, const uint32_t *seed_cfg,
+                                     const float *seed_targets, uint64_t n_val,
+                                     const uint32_t *val_sample, const uint64_t *batch_u64,
+                                     const cgs_online_opts *opts, uint64_t *raw_out,
+                                     uint64_t *valid_out, double *window_rmse,
+                                     int32_t *window_mlp, double *step_us, double *retrain_ms) {
+  if (!s || !tree || !mlp || !u64 || !noise || !val_sample || !opts || !raw_out ||
+      !window_rmse || !window_mlp || (n_seed && (!seed_cfg || !seed_targets)))
+    return fail(CGS_EINVAL, "NULL argument");
+  if (n_steps < 0) return fail(CGS_EINVAL, "negative n_steps");
+  if (n_steps > 0 && !delta) return fail(CGS_EINVAL, "NULL delta");
+  if (mlp->kind != 1) return fail(CGS_EINVAL, "the surrogate is not a perceptron model");
+  if (tree->space != s->space || mlp->space != s->space)
+    return fail(CGS_EINVAL, "models and session belong to different spaces");
+  if (tree->n_counters != mlp->n_counters) return fail(CGS_EINVAL, "models differ in counters");
+  const int W = opts->retrain_every;
+  if (W < 1) return fail(CGS_EINVAL, "retrain_every %d < 1", W);
+  if (opts->train_steps < 0 || opts->batch < 1 || opts->batch > 4096)
+    return fail(CGS_ERANGE, "train_steps %d / batch %d outside 0.. / 1..4096", opts->train_steps,
+                opts->batch);
+  if (opts->train_steps > 0 && n_steps >= W && !batch_u64)
+    return fail(CGS_EINVAL, "NULL batch_u64");
+  if (!std::isfinite(opts->threshold)) return fail(CGS_EINVAL, "threshold must be finite");
+  const int C = tree->n_counters;
+  const int n_windows = 1 + n_steps / W;
+  for (int i = 0; i <= n_steps; ++i) {
+    raw_out[i] = CGS_NO_PROFILE;
+    if (valid_out) valid_out[i] = CGS_NO_PROFILE;
+  }
+  for (int w = 0; w < n_windows; ++w) {
+    window_rmse[w] = NAN;
+    window_mlp[w] = -1;
+  }
+  std::vector<uint32_t> cfg(seed_cfg, seed_cfg + n_seed);
+  std::vector<float> tgt(seed_targets, seed_targets + n_seed * (uint64_t)C);
+  std::vector<uint32_t> fresh;     // valid indices of picks whose targets are not gathered yet
+  std::vector<int> fresh_step;     // and the step that picked them (row of noise)
+  std::vector<float> pred;
+  std::vector<int32_t> rows;
+  auto gather_fresh = [&]() -> cgs_status {
+    if (fresh.empty()) return CGS_OK;
+    pred.resize(fresh.size() * (size_t)C);
+    const cgs_status st = cgs_model_gather_predictions(tree, fresh.data(), fresh.size(), pred.data());
+    if (st != CGS_OK) return st;
+    for (size_t k = 0; k < fresh.size(); ++k)
+      for (int c = 0; c < C; ++c)
+        tgt.push_back(pred[k * C + c] + noise[(size_t)fresh_step[k] * C + c]);
+    fresh.clear();
+    fresh_step.clear();
+    return CGS_OK;
+  };
+  double rmse = 0.0;
+  cgs_status st = cgs_model_rmse(mlp, tree, val_sample, n_val, &rmse);
+  if (st != CGS_OK) return st;
+  bool use_mlp = rmse <= opts->threshold;
+  window_rmse[0] = rmse;
+  window_mlp[0] = use_mlp;
+  st = cgs_search_step(s, tree, CGS_NO_PROFILE, nullptr, nullptr, nullptr);
+  uint64_t raw = 0, valid = 0;
+  if (st == CGS_OK) st = cgs_sample_next(s, u64[0], &raw, &valid);
+  if (st != CGS_OK) return st;
+  raw_out[0] = raw;
+  if (valid_out) valid_out[0] = valid;
+  cfg.push_back((uint32_t)raw);
+  fresh.push_back((uint32_t)valid);
+  fresh_step.push_back(0);
+  for (int i = 1; i <= n_steps; ++i) {
+    if (i % W == 0) {
+      const int w = i / W;
+      const auto t0 = std::chrono::steady_clock::now();
+      st = gather_fresh();
+      if (st != CGS_OK) return st;
+      if (opts->train_steps > 0) {
+        // row of each batch entry: floor(u * n_pairs / 2^64), one u per entry
+        const uint64_t np = cfg.size(), per = (uint64_t)opts->train_steps * opts->batch;
+        const uint64_t *u = batch_u64 + (uint64_t)(w - 1) * per;
+        rows.resize(per);
+        for (uint64_t k = 0; k < per; ++k)
+          rows[k] = (int32_t)(((unsigned __int128)u[k] * np) >> 64);
+        const cgs_train_opts to{opts->lr,    opts->beta1, opts->beta2,
+                                opts->eps,   opts->batch, opts->train_steps};
+        st = cgs_mlp_train(mlp, cfg.data(), tgt.data(), np, rows.data(), &to, nullptr);
+        if (st != CGS_OK) return st;
+      }
+      st = cgs_model_rmse(mlp, tree, val_sample, n_val, &rmse);
+      if (st != CGS_OK) return st;
+      use_mlp = rmse <= opts->threshold;
+      window_rmse[w] = rmse;
+      window_mlp[w] = use_mlp;
+      if (retrain_ms)
+        retrain_ms[w - 1] =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    st = cgs_search_step(s, use_mlp ? mlp : tree, raw, delta + (size_t)(i - 1) * C, nullptr,
+                         nullptr);
+    if (st == CGS_OK) st = cgs_sample_next(s, u64[i], &raw, &valid);
+    if (st != CGS_OK) return st;
+    if (step_us)
+      step_us[i - 1] =
+          std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    raw_out[i] = raw;
+    if (valid_out) valid_out[i] = valid;
+    cfg.push_back((uint32_t)raw);
+    fresh.push_back((uint32_t)valid);
+    fresh_step.push_back(i);
   }
   return CGS_OK;
 }

@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kEvalThreads) void poly_eval(const PolyDev *__restr
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c)
-      if ((uint32_t)c < C) P[(uint64_t)c * stride + l] = acc[c];
+      if ((uint32_t)c < C) P[(uint64_t)c * stride + l] = fmaxf(acc[c], 0.0f); // counters >= 0
   }
 }
 

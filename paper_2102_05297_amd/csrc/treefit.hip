@@ -237,13 +237,13 @@ __global__ __launch_bounds__(kFitThreads) void fit_prepare(FitDev *__restrict__ 
       for (int u = 0; u < 4; ++u) y[u] = Y[k + u * step];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (!isfinite(y[u])) err |= 2u;
+        if (!(y[u] >= 0.0f) || !isfinite(y[u])) err |= 2u; // counters are non-negative
         else mx = max(mx, __float_as_uint(fabsf(y[u])));
       }
     }
     for (; k < total; k += step) {
       const float y = Y[k];
-      if (!isfinite(y)) err |= 2u;
+      if (!(y >= 0.0f) || !isfinite(y)) err |= 2u;
       else mx = max(mx, __float_as_uint(fabsf(y)));
     }
     if (mx) atomicMax(&s_max[gid % C], mx);

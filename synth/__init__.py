@@ -161,6 +161,20 @@ def space_c5(variant: int = C5_VARIANT) -> Space:
     return Space(list(C5_RADIX), vals, cons)
 
 
+C5_SLICE_RADIX = (3, 2, 2, 3, 2, 2, 2, 3, 2, 2, 2, 2, 2, 2, 2, 2)
+C5_SLICE_VARIANT = 2
+
+
+def space_c5_slice(variant: int = C5_SLICE_VARIANT) -> Space:
+    """16 parameters like the large space but 2^13 * 3^3 = 221,184 raw
+    configurations and 4 constraints: a size at which the oracle evaluates
+    the 16 -> 512 -> 512 -> 32 perceptron on every configuration."""
+    vals = value_tables(C5_SLICE_RADIX, binary_radix2=True)
+    cons = random_constraints(rng(7, 1, variant), vals, 4,
+                              ("DIV", "PROD_LE", "PROD3_LE", "PROD_GE", "LE"), loose=0.6)
+    return Space(list(C5_SLICE_RADIX), vals, cons)
+
+
 def fit_radices(g: np.random.Generator, target: float, n_params: int) -> List[int]:
     """Greedy radices in {2..8} whose product approaches ``target`` from below."""
     radix = [2] * n_params

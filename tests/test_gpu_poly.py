@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import bounds as B
 from oracle import lsq as LS
 from oracle import space as SP
 from tests.helpers import cgs
@@ -141,22 +142,90 @@ def test_binary_only_space_and_empty_subspaces():
     assert (P[np.isin(s, [1, 3, 7])] == 0).all()
 
 
-def test_search_step_runs_on_a_polynomial_model():
+def _prediction_bounds(m, spec, digits, pts, Y, order, model):
+    """Oracle prediction intervals of every valid configuration for the
+    device's fit: the float64 polynomial values, widened by the bound the
+    fit tests derive (conditioning of each subspace's normal equations plus
+    float32 evaluation), clamped at 0 like the predictions."""
+    ref = LS.fit(spec.values, spec.radix, digits[pts], Y, order)
+    T = len(ref.terms)
+    F = LS.basis(LS.features(spec.values, spec.radix, digits[pts]), order)
+    s_pts = LS.subspace(spec.radix, digits[pts])
+    rtol = np.full(ref.n_subspaces, 1e-6)
+    for k in range(ref.n_subspaces):
+        rows = s_pts == k
+        if rows.any():
+            A = F[rows].T @ F[rows] + ref.lam[k] * np.eye(T)
+            rtol[k] = min(1e-2, max(1e-6, np.linalg.cond(A) * (rows.sum() + T) * 2.0 ** -53))
+    v = LS.value(ref, spec.values, spec.radix, digits)
+    mag = LS.abs_terms(ref, spec.values, spec.radix, digits)
+    b = 2 * (T + 8) * U * mag + rtol[LS.subspace(spec.radix, digits)][:, None] * mag
+    return v, np.maximum(v - b, 0.0), np.maximum(v + b, 0.0)
+
+
+def _tiny_space():
+    radix = [3, 4, 2, 3, 2, 4]
+    return synth.Space(radix, synth.value_tables(radix, binary_radix2=True), [])
+
+
+@pytest.mark.parametrize("which,order", [("tiny", 1), ("c1", 1), ("c1", 2)])
+def test_scored_steps_on_a_polynomial_model(which, order):
+    """Polynomials that go negative between the design points (predictions
+    clamped at 0), scored steps from seeded states (explored sets, profiles,
+    counter changes) and six draws each: every score, quantised weight and
+    pick inside the oracle's intervals propagated from the prediction bound
+    (oracle/bounds.py); picks that only one configuration can take are
+    equal.  Reports the share of draws that could go to more than one: on
+    the 576-configuration space most draws are certain, on the 11,496 one
+    most are not (the bound of each prediction is summed over the space)."""
     m = cgs()
-    spec = synth.space_c1()
+    spec = _tiny_space() if which == "tiny" else synth.space_c1()
     sp = m.Space.from_spec(spec)
     valid, digits = _space(spec)
+    nv = len(valid)
     pts = LS.design(spec.values, spec.radix, digits).astype(np.uint32)
-    Y = synth.measured_counters(synth.rng(35), digits[pts], spec.radix, 12)
-    model = m.PolyModel(sp, pts, Y, 2)
-    sess = m.Session(sp)
-    sess.search_step(model, m.NO_PROFILE)
-    raw, l = sess.sample_next(12345)
-    sess.search_step(model, raw, delta=synth.deltas(synth.rng(36), 1, 12)[0])
-    raw2, l2 = sess.sample_next(67890)
-    assert l2 != l and 0 <= l2 < sp.n_valid and raw2 == valid[l2]
-    info = sess.step_info()
-    assert info.n_unexplored == sp.n_valid - 1
+    Y = synth.measured_counters(synth.rng(35, order), digits[pts], spec.radix, 12)
+    model = m.PolyModel(sp, pts, Y, order)
+    v, lo, hi = _prediction_bounds(m, spec, digits, pts, Y, order, model)
+    if which == "c1":
+        assert (v < 0).any()                 # the clamp is exercised
+    P = model.copy_predictions().astype(np.float64)
+    assert ((P >= lo) & (P <= hi)).all() and P.min() >= 0.0
+    g = synth.rng(36, order)
+    certain = flagged = 0
+    for state in range(6):
+        explored = np.zeros(nv, bool)
+        explored[synth.uniform_indices(g, int(g.integers(0, min(200, nv // 4))), nv)] = True
+        prof = int(synth.uniform_indices(g, 1, nv)[0])
+        delta = synth.deltas(g, 1, 12)[0]
+        Us = synth.uniforms_u64(g, 6)
+        sess = m.Session(sp)
+        for l in np.flatnonzero(explored):
+            sess.mark_explored(int(valid[l]))
+        explored[prof] = True
+        sess.search_step(model, int(valid[prof]), delta=delta)
+        s = sess.copy_scores().astype(np.float64)
+        q = sess.copy_weights().astype(np.uint64)
+        s_lo, s_hi = B.score_interval(lo[prof], hi[prof], lo, hi, delta)
+        un = ~explored
+        assert ((s[un] >= s_lo[un]) & (s[un] <= s_hi[un])).all(), state
+        w_lo, w_hi = B.weight_interval(s_lo, s_hi, explored)
+        q_lo, q_hi = B.q_interval(w_lo, w_hi)
+        assert ((q >= q_lo) & (q <= q_hi)).all(), state
+        for U_ in Us:
+            raw, l = sess.sample_next(int(U_))
+            first, last, sure = B.feasible_picks(q_lo, q_hi, int(U_))
+            assert first <= l <= last and q_hi[l] > 0 and raw == valid[l], (state, l, first, last)
+            if not sure:
+                flagged += 1
+                break                        # later draws depend on this pick
+            certain += 1
+            assert l == first
+            q_lo[l] = q_hi[l] = 0
+    print(f"{which} order {order}: {certain} certain draws, {flagged} flagged", flush=True)
+    assert certain + flagged >= 6
+    if which == "tiny":
+        assert certain >= flagged
 
 
 def test_fit_errors():
