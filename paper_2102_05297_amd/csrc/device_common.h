@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "internal.h"
+#include "stepdiv.h"
 
 namespace cgs {
 
@@ -93,17 +94,42 @@ __device__ __forceinline__ float key_float(uint32_t k) {
   return __uint_as_float(u);
 }
 
+// The constants of one step's normalisation: the two divisors with their
+// reciprocals (stepdiv.h), the cut-off and the smallest weight.
+struct StepNorm {
+  StepDivisor pos, neg; // s_max (for s > 0) and s_min (for s <= 0)
+  float gamma, w_min;
+};
+// The reciprocals are made opaque to the optimiser: it would otherwise
+// turn the per-lane choice between two reciprocals back into one division
+// per configuration.
+__device__ __forceinline__ float opaque(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+__device__ __forceinline__ StepNorm step_norm(float s_min, float s_max, float gamma, float w_min) {
+  StepNorm nm{step_divisor(s_max), step_divisor(s_min), gamma, w_min};
+  nm.pos.r = opaque(nm.pos.r);
+  nm.neg.r = opaque(nm.neg.r);
+  return nm;
+}
+
 // Normalised weight of the score-normalisation equation, quantised to
 // rint(w * 2^23).  The eighth power is three squarings; s == 0 maps to 1.
-// One division per configuration: the divisor (s_max for s > 0, s_min
-// otherwise) is selected per lane, so a wave holding scores of both signs
-// does not run two divisions; every value is the same float as with the
-// two-branch form.
-__device__ __forceinline__ uint32_t quantized_weight(float s, bool explored, float s_min,
-                                                     float s_max, float gamma, float w_min) {
+// One division per configuration, correctly rounded through the step's
+// reciprocal (div_by gives s / divisor exactly as the IEEE division): the
+// divisor (s_max for s > 0, s_min otherwise) is selected per lane, so a wave
+// holding scores of both signs does not run two divisions; every value is
+// the same float as with the two-branch form.
+__device__ __forceinline__ uint32_t quantized_weight(float s, bool explored, const StepNorm &nm) {
   const bool pos = s > 0.0f;
-  const float t = s / (pos ? s_max : s_min);
+  const float d = pos ? nm.pos.d : nm.neg.d;
+  const bool ok = div_fast_ok(s, pos ? nm.pos.fast : nm.neg.fast);
+  float t = div_fast(s, d, pos ? nm.pos.r : nm.neg.r);
+  // operands outside the fast path's range (t is not used when s == 0)
+  if (__any(!ok && s != 0.0f)) t = ok ? t : s / d;
   const float y = pos ? 1.0f + t : 1.0f - t;
+  const float gamma = nm.gamma, w_min = nm.w_min;
   const float y2 = y * y;
   const float y4 = y2 * y2;
   const float y8 = y4 * y4;

@@ -121,9 +121,13 @@ struct BatchStep {
 };
 constexpr uint32_t kBatchTile = 1024; // configurations per score tile
 
+// variant: 0..kBatchScoreVariants-1, counter rows in flight x waves per SIMD
+// (0: 8 rows, unconstrained; 1: 4 rows, 4 waves; 2: 16 rows, 2 waves;
+// 3: 8 rows, 4 waves; 4: 4 rows, 8 waves)
+constexpr int kBatchScoreVariants = 5;
 hipError_t launch_batch_score(const BatchSess *d_sess, const BatchStep *d_step,
                               const uint16_t *d_tile_sess, uint32_t total_tiles, uint32_t grid,
-                              hipStream_t stream);
+                              int variant, hipStream_t stream);
 hipError_t launch_batch_weight(const BatchSess *d_sess, const BatchStep *d_step,
                                const uint16_t *d_blk_sess, uint32_t total_blocks, uint32_t grid,
                                hipStream_t stream);

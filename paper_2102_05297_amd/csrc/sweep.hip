@@ -67,6 +67,7 @@ __device__ __forceinline__ StepAccSums reduce_slots(const StepAcc *__restrict__ 
 // Scores the 4 configurations of this thread in `tile` (4 * kScoreThreads
 // configurations per tile) and folds the unexplored ones into the running
 // min / max keys and count.  Counters ctr[0..n) with changes delta[].
+template <int RIF = kRowsInFlight>
 __device__ __forceinline__ void score_tile(const float *__restrict__ P, uint64_t stride,
                                            uint32_t profile, int n, const uint32_t *ctr,
                                            const float *delta,
@@ -84,11 +85,11 @@ __device__ __forceinline__ void score_tile(const float *__restrict__ P, uint64_t
   if (tail < 4u) ex4 |= (0xfu << tail) & 0xfu;
   if (profile - l0 < 4u) ex4 |= 1u << (profile - l0);
   const float *__restrict__ col = P + l0;
-  for (int j0 = 0; j0 < n; j0 += kRowsInFlight) {
-    float4 x[kRowsInFlight];
-    float av[kRowsInFlight];
+  for (int j0 = 0; j0 < n; j0 += RIF) {
+    float4 x[RIF];
+    float av[RIF];
 #pragma unroll
-    for (int u = 0; u < kRowsInFlight; ++u) {
+    for (int u = 0; u < RIF; ++u) {
       if (j0 + u < n) {
         const size_t row = (size_t)ctr[j0 + u] * stride;
         x[u] = *reinterpret_cast<const float4 *>(col + row);
@@ -96,7 +97,7 @@ __device__ __forceinline__ void score_tile(const float *__restrict__ P, uint64_t
       }
     }
 #pragma unroll
-    for (int u = 0; u < kRowsInFlight; ++u) {
+    for (int u = 0; u < RIF; ++u) {
       if (j0 + u < n && av[u] != 0.0f) { // a_p == 0: counter not in PC_used
         const float ap = av[u];
         const float d = delta[j0 + u];
@@ -200,20 +201,18 @@ struct ScoreWeights {
   uint32_t profile;
   const StepAcc *acc;
   float gamma, w_min;
-  float s_min = 0.0f, s_max = 0.0f;
+  StepNorm nm{};
   StepAcc slot{};
   __device__ void stage_load() {
     if (threadIdx.x < kWave) slot = acc[threadIdx.x];
   }
   __device__ void stage_reduce(StepAccSums *sh) const { reduce_slot_values(slot, sh); }
   __device__ void stage_read(const StepAccSums *sh) {
-    s_min = key_float(sh->min_key);
-    s_max = key_float(sh->max_key);
+    nm = step_norm(key_float(sh->min_key), key_float(sh->max_key), gamma, w_min);
   }
   __device__ uint32_t operator()(uint32_t l) const {
     if (l >= n) return 0u;
-    return quantized_weight(s[l], explored_bit(explored, l) || l == profile, s_min, s_max, gamma,
-                            w_min);
+    return quantized_weight(s[l], explored_bit(explored, l) || l == profile, nm);
   }
   // Weights of l = first .. first + cnt - 1 (cnt <= K) into q[], 0 beyond;
   // every load is issued before the first is used.
@@ -231,7 +230,7 @@ struct ScoreWeights {
     for (int e = 0; e < K; ++e) {
       const uint32_t l = first + e;
       const bool ex = ((ew[e] >> (l & 31u)) & 1u) || l == profile;
-      q[e] = quantized_weight(sv[e], ex, s_min, s_max, gamma, w_min);
+      q[e] = quantized_weight(sv[e], ex, nm);
     }
   }
   __device__ void remove(uint32_t l) const { atomicOr(&explored[l >> 5], 1u << (l & 31u)); }
@@ -442,27 +441,30 @@ __device__ __forceinline__ uint64_t weight_block_sum(const float *__restrict__ s
       if (l0 < end) {
         sv[k] = *reinterpret_cast<const float4 *>(s + l0);
         ex[k] = explored[l0 >> 5];
+      } else { // past the block: weight 0, like explored configurations
+        sv[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        ex[k] = 0xffffffffu;
       }
     }
   };
   load_round(base);
   reduce_slot_values(slot, &sums);
   __syncthreads();
-  const float s_min = key_float(sums.min_key), s_max = key_float(sums.max_key);
+  const StepNorm nm = step_norm(key_float(sums.min_key), key_float(sums.max_key), gamma, w_min);
   uint64_t sum = 0;
   for (uint32_t r0 = base;;) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+      // no per-configuration branches: positions past the end (and the
+      // profiled configuration) count as explored and weigh 0
       const uint32_t l0 = r0 + 4u * (threadIdx.x + k * kWeightThreads);
-      if (l0 < end) {
-        uint32_t ex4 = (ex[k] >> (l0 & 31u)) & 0xfu;
-        if (profile - l0 < 4u) ex4 |= 1u << (profile - l0);
-        const float ss[4] = {sv[k].x, sv[k].y, sv[k].z, sv[k].w};
+      uint32_t ex4 = (ex[k] >> (l0 & 31u)) & 0xfu;
+      const uint32_t tail = end - l0;
+      if (tail < 4u) ex4 |= (0xfu << tail) & 0xfu;
+      if (profile - l0 < 4u) ex4 |= 1u << (profile - l0);
+      const float ss[4] = {sv[k].x, sv[k].y, sv[k].z, sv[k].w};
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (l0 + e < end)
-            sum += quantized_weight(ss[e], (ex4 >> e) & 1u, s_min, s_max, gamma, w_min);
-      }
+      for (int e = 0; e < 4; ++e) sum += quantized_weight(ss[e], (ex4 >> e) & 1u, nm);
     }
     r0 += kRound;
     if (r0 >= end) break;
@@ -507,10 +509,14 @@ __global__ __launch_bounds__(kDrawThreads) void draw_scores(
 // ------------------------------------------------------------ batched
 // Score tiles of every session, grid-stride over the concatenated tile list;
 // a workgroup flushes its accumulators whenever the session changes.
-__global__ __launch_bounds__(kScoreThreads) void batch_score(const BatchSess *__restrict__ sess,
-                                                             const BatchStep *__restrict__ step,
-                                                             const uint16_t *__restrict__ tile_sess,
-                                                             uint32_t total_tiles) {
+// RIF: counter rows in flight per thread; WPE: waves per SIMD the compiler
+// plans registers for (the autotuner's variants).
+template <int RIF, int WPE>
+__global__ __launch_bounds__(kScoreThreads)
+__attribute__((amdgpu_waves_per_eu(WPE, 8))) void batch_score(const BatchSess *__restrict__ sess,
+                                                              const BatchStep *__restrict__ step,
+                                                              const uint16_t *__restrict__ tile_sess,
+                                                              uint32_t total_tiles) {
   uint32_t kmin = 0xffffffffu, kmax = 0u, cnt = 0u;
   uint32_t cur = 0xffffffffu;
   for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
@@ -527,7 +533,7 @@ __global__ __launch_bounds__(kScoreThreads) void batch_score(const BatchSess *__
     const BatchSess &d = sess[si];
     const BatchStep &st = step[si];
     const int n = st.profile < d.n_valid ? st.n_act : 0;
-    score_tile(d.P, d.stride, st.profile, n, st.ctr, st.delta, d.explored, d.n_valid, d.s,
+    score_tile<RIF>(d.P, d.stride, st.profile, n, st.ctr, st.delta, d.explored, d.n_valid, d.s,
                t - d.tile0, kmin, kmax, cnt);
   }
   if (cur != 0xffffffffu)
@@ -673,7 +679,7 @@ __global__ __launch_bounds__(kNbFinishThreads) void nb_finish(
   reduce_slot_values(slot, &sums);
   uint64_t count;
   uint64_t pos = block_excl_scan<kNbFinishThreads>(kept, scratch, count); // barriers publish sums
-  const float s_min = key_float(sums.min_key), s_max = key_float(sums.max_key);
+  const StepNorm nm = step_norm(key_float(sums.min_key), key_float(sums.max_key), gamma, w_min);
   for (uint32_t f = f0; f < f1; f += kChunk) {
     uint32_t v[kChunk];
     float sv[kChunk];
@@ -685,7 +691,7 @@ __global__ __launch_bounds__(kNbFinishThreads) void nb_finish(
 #pragma unroll
     for (uint32_t k = 0; k < kChunk; ++k) {
       if (v[k] == 0xffffffffu) continue;
-      const uint32_t q = quantized_weight(sv[k], false, s_min, s_max, gamma, w_min);
+      const uint32_t q = quantized_weight(sv[k], false, nm);
       nb_idx[pos] = v[k];
       nb_s[pos] = sv[k];
       nb_q[pos] = q;
@@ -758,8 +764,7 @@ __global__ __launch_bounds__(256) void copy_weights(const float *__restrict__ s,
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
   ScoreWeights w{s, explored, n_valid, kNoProfile, acc, gamma, w_min};
-  w.s_min = key_float(a.min_key);
-  w.s_max = key_float(a.max_key);
+  w.nm = step_norm(key_float(a.min_key), key_float(a.max_key), gamma, w_min);
   q[i] = w(first + i);
 }
 
@@ -813,10 +818,19 @@ hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
 
 hipError_t launch_batch_score(const BatchSess *d_sess, const BatchStep *d_step,
                               const uint16_t *d_tile_sess, uint32_t total_tiles, uint32_t grid,
-                              hipStream_t stream) {
+                              int variant, hipStream_t stream) {
   if (total_tiles == 0 || grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_score, dim3(grid), dim3(kScoreThreads), 0, stream, d_sess, d_step,
-                     d_tile_sess, total_tiles);
+#define CGS_BATCH_SCORE(RIF, WPE)                                                               \
+  hipLaunchKernelGGL((batch_score<RIF, WPE>), dim3(grid), dim3(kScoreThreads), 0, stream,      \
+                     d_sess, d_step, d_tile_sess, total_tiles)
+  switch (variant) {
+  case 1: CGS_BATCH_SCORE(4, 4); break;
+  case 2: CGS_BATCH_SCORE(16, 2); break;
+  case 3: CGS_BATCH_SCORE(8, 4); break;
+  case 4: CGS_BATCH_SCORE(4, 8); break;
+  default: CGS_BATCH_SCORE(8, 1); break; // the unconstrained kernel
+  }
+#undef CGS_BATCH_SCORE
   return hipGetLastError();
 }
 
