@@ -335,15 +335,17 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const float *p) {
 // (fp32) and H = gelu(Z) (bf16); 3: Y = A B + bias (fp32); 4: as 3, plus the
 // training loss terms of LossArgs (dY and one sum of squared errors per
 // tile).  bias[N] for 2, 3, 4.
+// Output tile `tile` (row-major over 32 x 32 tiles) by one workgroup of
+// kGemmThreads; shared by the plain launch and the grouped backward launch.
 template <typename TA, typename TB, int EPI>
-__global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const float *bias,
-                                                          LossArgs la) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, const float *bias, const LossArgs &la,
+                                          int tile) {
   constexpr int NW = kGemmThreads / 64;
   __shared__ float part[NW - 1][16][64];
   const TA *A = static_cast<const TA *>(g.A);
   const TB *B = static_cast<const TB *>(g.B);
   const int tiles_n = (g.N + 31) / 32;
-  const int m0 = (blockIdx.x / tiles_n) * 32, n0 = (blockIdx.x % tiles_n) * 32;
+  const int m0 = (tile / tiles_n) * 32, n0 = (tile % tiles_n) * 32;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hh = lane >> 5, c = lane & 31;
   const int m = m0 + c, n = n0 + c;
   f32x16 acc = {};
@@ -431,8 +433,68 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const floa
   }
   if (EPI == 4) {
     sq = wave_sum(sq);
-    if (lane == 0) la.partial[blockIdx.x] = sq;
+    if (lane == 0) la.partial[tile] = sq;
   }
+}
+
+template <typename TA, typename TB, int EPI>
+__global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const float *bias,
+                                                          LossArgs la) {
+  gemm_tile<TA, TB, EPI>(g, bias, la, blockIdx.x);
+}
+
+// Column sums of src[nrows][ld] over columns [64 b, 64 b + 64) of ncols by
+// one workgroup: lanes take columns (coalesced rows), the waves split the
+// rows and meet in LDS, added in wave order.  Block 0 also forms the loss
+// from the per-tile partials, in tile order.
+__device__ __forceinline__ void colsum_block(const ColSumJob &cs, int b) {
+  constexpr int NW = kGemmThreads / 64;
+  __shared__ float part[NW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (b == 0 && threadIdx.x == 0 && cs.loss_out) {
+    float t = 0.0f;
+    for (int k = 0; k < cs.n_partial; ++k) t += cs.partial[k];
+    *cs.loss_out = t / cs.loss_div;
+  }
+  const int col = b * 64 + lane;
+  float sum = 0.0f;
+  if (col < cs.ncols) {
+#pragma unroll 4
+    for (int r = w; r < cs.nrows; r += NW) sum += cs.src[(size_t)r * cs.ld + col];
+  }
+  part[w][lane] = sum;
+  __syncthreads();
+  if (w == 0 && col < cs.ncols) {
+    float t = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) t += part[k][lane];
+    cs.dst[col] = t;
+  }
+}
+
+__device__ __forceinline__ int gemm_tiles(const GemmArgs &g) {
+  return g.M > 0 && g.N > 0 ? ((g.M + 31) / 32) * ((g.N + 31) / 32) : 0;
+}
+
+// One level of the backward pass in one launch: two independent bf16 x bf16
+// products (epilogue 0: plain, 1: times gelu'(Z)) and one set of bias
+// gradients, each workgroup working on one of them.
+__global__ __launch_bounds__(kGemmThreads) void gemm_bwd_group(GemmArgs g0, int epi0, GemmArgs g1,
+                                                               int epi1, ColSumJob cs) {
+  int b = blockIdx.x;
+  const int t0 = gemm_tiles(g0), t1 = gemm_tiles(g1);
+  if (b < t0) {
+    if (epi0) gemm_tile<__bf16, __bf16, 1>(g0, nullptr, LossArgs{}, b);
+    else gemm_tile<__bf16, __bf16, 0>(g0, nullptr, LossArgs{}, b);
+    return;
+  }
+  b -= t0;
+  if (b < t1) {
+    if (epi1) gemm_tile<__bf16, __bf16, 1>(g1, nullptr, LossArgs{}, b);
+    else gemm_tile<__bf16, __bf16, 0>(g1, nullptr, LossArgs{}, b);
+    return;
+  }
+  colsum_block(cs, b - t1);
 }
 
 // Training features: X[i][k] = digit_k / 8 of configuration cfg_raw[batch[i]]
@@ -692,6 +754,18 @@ hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipSt
   else if (a_bf16 && b_bf16 && epi == 1) GEMM_CASE(__bf16, __bf16, 1);
   else return hipErrorInvalidValue;
 #undef GEMM_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_group(const GemmArgs &g0, int epi0, const GemmArgs &g1, int epi1,
+                            const ColSumJob &cs, hipStream_t stream) {
+  auto tiles = [](const GemmArgs &g) {
+    return g.M > 0 && g.N > 0 ? ((g.M + 31) / 32) * ((g.N + 31) / 32) : 0;
+  };
+  const int blocks = tiles(g0) + tiles(g1) + (cs.ncols + 63) / 64;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm_bwd_group, dim3(blocks), dim3(kGemmThreads), 0, stream, g0, epi0, g1,
+                     epi1, cs);
   return hipGetLastError();
 }
 

@@ -30,6 +30,23 @@ struct LossArgs {
 };
 hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const float *w2,
                                    const float *w3, const LossArgs *loss, hipStream_t stream);
+// Column sums dst[c] = sum over rows r < nrows of src[r * ld + c], c < ncols,
+// in row order split over the waves of a workgroup; with loss_out set, also
+// *loss_out = (partial[0] + ... + partial[n_partial - 1]) / loss_div.
+struct ColSumJob {
+  const float *src;
+  int ld, nrows, ncols;
+  float *dst;
+  const float *partial;
+  int n_partial;
+  float *loss_out;
+  float loss_div;
+};
+// One level of the backward pass as one launch: products g0 and g1 (bf16
+// operands; epilogue 0: C = A B; 1: dZ = (A B) * gelu'(Z), fp32 and bf16)
+// and the column sums cs; an empty product has M = 0, no sums ncols = 0.
+hipError_t launch_bwd_group(const GemmArgs &g0, int epi0, const GemmArgs &g1, int epi1,
+                            const ColSumJob &cs, hipStream_t stream);
 // Bias gradients (column sums of dZ1, dZ2 [n][H] and dY [n][Cp]) and the
 // mean squared error: loss_out = (partial[0] + ... + partial[n_partial - 1]) / (n C).
 hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dyf, int n, int H,
