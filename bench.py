@@ -277,6 +277,10 @@ def batch_path(cgs, n_sess=64, n_steps=10):
     sched = batch.autotune(None)
     t_tune = time.perf_counter() - t_tune
     run_batch(batch, sessions, False)                       # warm-up run
+    # the default schedule (grids capped at 2048, variant 0, graph) for the gain
+    sessions = [cgs.Session(spc) for spc in spaces]
+    batch = cgs.Batch(sessions, models)
+    _, dev_default = run_batch(batch, sessions, True)
     sessions = [cgs.Session(spc) for spc in spaces]
     batch = cgs.Batch(sessions, models, sched)
     wall, dev = run_batch(batch, sessions, True)
@@ -298,10 +302,22 @@ def batch_path(cgs, n_sess=64, n_steps=10):
         "sessions": n_sess, "steps": n_steps,
         "raw_total": int(sum(sp.n_raw for sp in specs)), "valid_total": int(n_valid.sum()),
         "schedule": {"score_grid": sched.score_grid, "weight_grid": sched.weight_grid,
-                     "use_graph": sched.use_graph},
+                     "use_graph": sched.use_graph, "variant": sched.variant},
         "autotune_ms": t_tune * 1e3,
         "ms_per_batch_step": wall * 1e3 / n_steps,
         "device_ms_per_batch_step": float(np.median(dev)),
+        "device_ms_per_batch_step_default_schedule": float(np.median(dev_default)),
+        "autotune_gain": float(np.median(dev_default)) / max(float(np.median(dev)), 1e-9),
+        # algorithmic bytes of one batch step (every session scores all 16
+        # counters: Delta ~ U(-1, 1) has no zero): score pass 4 * 16 + 4 + 1/8,
+        # weight pass 4 + 1/8 per valid configuration; draws are negligible
+        "step_roofline": {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "algorithmic_bytes": float(n_valid.sum() * (4 * 16 + 4 + 0.125 + 4 + 0.125)),
+            "achieved": float(n_valid.sum() * (4 * 16 + 8.25)) / (float(np.median(dev)) / 1e3) / 1e9,
+            "frac": float(n_valid.sum() * (4 * 16 + 8.25)) / (float(np.median(dev)) / 1e3) / 1e9
+                    / HBM_PEAK_GBS,
+        },
         "scored_per_s": scored / wall,
         "ms_per_step_sessions_one_by_one": wall_single * 1e3 / n_steps,
         "scored_per_s_one_by_one": scored / wall_single,
@@ -806,13 +822,25 @@ def main() -> int:
     # score pass of step j (0 = the uniform start, no active counter): reads
     # the rows of P of its active counters, writes s, reads the explored bits;
     # the timed launches are those of steps 0, k, 2k, ...
-    timed = [j for j in range(K + 1) if j % TIMING_PERIOD == 0]
+    # timed steps: 0, k, 2k, ...; the score-pass totals hold the scored ones
+    # only (step 0, the uniform start, reads no prediction)
+    timed = [j for j in range(1, K + 1) if j % TIMING_PERIOD == 0]
     assert len(timed) == int(launches[0])
     act = [0] + n_active
     bytes_score = sum(n_valid * (4 + 0.125 + 4.0 * act[j]) for j in timed)
     traffic = pmc_traffic([act[j] for j in timed])
     score_s = ms[0] / 1e3
     achieved = bytes_score / score_s / 1e9 if score_s > 0 else 0.0
+    # the whole scored step: score pass as above; weight pass reads s and the
+    # explored bits (4 + 1/8 B per configuration) and writes 8 B per block;
+    # the draw reads the block sums and one block's scores and explored words
+    blk = 1 << max(12, next(b for b in range(12, 21) if (n_valid >> b) < 65536))
+    n_blocks = (n_valid + blk - 1) // blk
+    bytes_weight = n_valid * (4 + 0.125) + 8 * n_blocks
+    bytes_draw = 8 * n_blocks + blk * (4 + 0.125)
+    step_bytes = bytes_score / len(timed) + bytes_weight + bytes_draw
+    step_us = sum(ms[k] / max(1, launches[k]) for k in range(3)) * 1e3
+    step_achieved = step_bytes / (step_us / 1e6) / 1e9 if step_us > 0 else 0.0
 
     # oracle-exact picks: stored oracle trajectory for the same inputs
     golden_path = os.path.join(ROOT, "tests", "golden", "c2_search.json")
@@ -903,6 +931,18 @@ def main() -> int:
             "algorithmic_bytes_per_launch": bytes_score / len(timed),
             "launches": int(launches[0]),
             "avg_us": ms[0] / max(1, launches[0]) * 1e3,
+            "timing": "HIP events around every %d-th scored step's kernels" % TIMING_PERIOD,
+        },
+        # score + weight + draw of one scored step against the same peak
+        "step_roofline": {
+            "kernels": "score_pass + weight_pass + draw",
+            "bound": "hbm",
+            "achieved": step_achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": step_achieved / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_step": step_bytes,
+            "device_us": step_us,
         },
         "step_wall_ms": {"median": float(np.median(wall)), "p10": float(np.percentile(wall, 10)),
                          "p90": float(np.percentile(wall, 90))},

@@ -456,6 +456,10 @@ cgs_status cgs_session_copy_neighbourhood(cgs_session session, uint64_t capacity
  * order, or candidate order after a restricted step); mark it explored and
  * zero its weight for further draws of this step.  Synchronises.
  * CGS_EEMPTY when Q == 0.
+ * No tie flag: the weights are integers fixed by the float32 operation
+ * order documented at cgs_search_step and the prefix sums are exact, so the
+ * pick is a deterministic function of the model's predictions and u64 (a
+ * reference evaluating the same float32 order reproduces it exactly).
  *   raw_out / valid_out may be NULL. */
 cgs_status cgs_sample_next(cgs_session session, uint64_t u64, uint64_t *raw_out,
                            uint64_t *valid_out);
@@ -532,8 +536,11 @@ cgs_status cgs_session_step_info(cgs_session session, cgs_step_info *out);
 /* Device time per kernel kind, summed over the timed launches since session
  * creation (sessions created with params.timing > 0; zeros otherwise); slot
  * [3] is the scoring of restricted steps (candidates and weights):
- *   total_ms[4] / launches[4]: [0] score pass, [1] weight pass, [2] draws,
- *   [3] restricted scoring (one launch = one step).  Synchronises. */
+ *   total_ms[4] / launches[4]: [0] score pass of scored steps (a profile and
+ *   at least one counter with a non-zero change; the pass of an unscored
+ *   step such as the uniform start reads no prediction and is not counted),
+ *   [1] weight pass, [2] draws, [3] restricted scoring (one launch = one
+ *   step).  Synchronises. */
 cgs_status cgs_session_kernel_times(cgs_session session, double *total_ms, uint64_t *launches);
 
 /* Mark raw index k explored (must be valid). */
@@ -560,7 +567,9 @@ typedef struct {
   int32_t score_grid;  /* workgroups of the score pass                     */
   int32_t weight_grid; /* workgroups of the weight pass                    */
   int32_t use_graph;   /* 1: replay the step from a captured hipGraph      */
-  int32_t reserved;
+  int32_t variant;     /* score-pass kernel: counter rows in flight x waves
+                          per SIMD, 0 (8 rows, unconstrained), 1 (4, 4),
+                          2 (16, 2), 3 (8, 4), 4 (4, 8)                   */
 } cgs_batch_schedule;
 
 /* sessions[i] searches its own space with models[i] (same space).  The batch
@@ -589,12 +598,14 @@ cgs_status cgs_batch_draw(cgs_batch batch, const uint64_t *u64_host, uint64_t *r
                           uint64_t *valid_out_host, int32_t *status_out_host);
 /* Device time of the last batch step (ms, HIP events around the launch). */
 cgs_status cgs_batch_step_time(cgs_batch batch, float *ms);
-/* Picks the score and weight grid sizes by timing candidates with HIP events
- * (score records with every counter active; no draw, the explored sets are
- * untouched; the sessions' last-step results become unavailable until their
- * next step).  cache_path (may be NULL): a text file of
- * "<shape key> -> score_grid weight_grid use_graph" lines, read first and
- * appended to. */
+/* Picks the schedule by timing candidates with HIP events (the median of 5
+ * runs after a warm-up; score records with every counter active; no draw,
+ * the explored sets are untouched; the sessions' last-step results become
+ * unavailable until their next step): every score-pass variant at grid
+ * sizes 128..8192, then the weight-pass grid, then graph replay against
+ * plain launches of the step.  cache_path (may be NULL): a text file of
+ * "<shape key> -> score_grid weight_grid use_graph variant" lines, read
+ * first and appended to. */
 cgs_status cgs_batch_autotune(cgs_batch batch, const char *cache_path,
                               cgs_batch_schedule *chosen);
 cgs_status cgs_batch_set_schedule(cgs_batch batch, const cgs_batch_schedule *sched);

@@ -88,7 +88,7 @@ class cgs_train_opts(C.Structure):
 
 class cgs_batch_schedule(C.Structure):
     _fields_ = [("score_grid", C.c_int32), ("weight_grid", C.c_int32), ("use_graph", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("variant", C.c_int32)]
 
 
 class cgs_tree_fit_report(C.Structure):

@@ -1325,37 +1325,30 @@ hipError_t mlp_backward_rows(cgs_model m, const uint32_t *d_cfg, const float *d_
   const int n_tiles = (int)((n + 31) / 32) * ((C + 31) / 32);
   hipError_t e = mlp_forward_rows(m, d_cfg, d_batch, n, &loss);
   float *g = m->d_grad;
-  GemmArgs ga{};
-  // dW3 = dY^T H2
-  if (e == hipSuccess) {
-    ga = GemmArgs{C, H, (int)n, m->d_dyb, 1, Cp, m->d_h2, H, 1, g + m->off_w3, nullptr, nullptr, H};
-    e = launch_gemm(ga, 1, 1, 0, st);
-  }
-  // dZ2 = (dY W3) * gelu'(Z2), W3 read from its transposed bf16 copy
-  if (e == hipSuccess) {
-    ga = GemmArgs{(int)n, H, C, m->d_dyb, Cp, 1, m->d_w3t, 1, Cp, m->d_dz2f, m->d_dz2b, m->d_z2,
-                  H};
-    e = launch_gemm(ga, 1, 1, 1, st);
-  }
-  // dW2 = dZ2^T H1
-  if (e == hipSuccess) {
-    ga = GemmArgs{H, H, (int)n, m->d_dz2b, 1, H, m->d_h1, H, 1, g + m->off_w2, nullptr, nullptr, H};
-    e = launch_gemm(ga, 1, 1, 0, st);
-  }
-  // dZ1 = (dZ2 W2) * gelu'(Z1), W2 read from its transposed bf16 copy
-  if (e == hipSuccess) {
-    ga = GemmArgs{(int)n, H, H, m->d_dz2b, H, 1, m->d_w2t, 1, H, m->d_dz1f, m->d_dz1b, m->d_z1,
-                  H};
-    e = launch_gemm(ga, 1, 1, 1, st);
-  }
-  // dW1 = dZ1^T X
-  if (e == hipSuccess) {
-    ga = GemmArgs{H, F, (int)n, m->d_dz1b, 1, H, m->d_x, K1, 1, g, nullptr, nullptr, F};
-    e = launch_gemm(ga, 1, 1, 0, st);
-  }
+  // three launches, one per level of the chain rule; the products of a
+  // level and the bias sums it can form are independent
+  const int nn = (int)n;
+  // dW3 = dY^T H2; dZ2 = (dY W3) * gelu'(Z2) with W3 from its transposed
+  // bf16 copy; db3 = column sums of dY
   if (e == hipSuccess)
-    e = launch_bias_grads(m->d_dz1f, m->d_dz2f, m->d_dyf, (int)n, H, C, Cp, g + m->off_b1,
-                          g + m->off_b2, g + m->off_b3, m->d_loss_part, n_tiles, d_loss, st);
+    e = launch_bwd_group(
+        GemmArgs{C, H, nn, m->d_dyb, 1, Cp, m->d_h2, H, 1, g + m->off_w3, nullptr, nullptr, H}, 0,
+        GemmArgs{nn, H, C, m->d_dyb, Cp, 1, m->d_w3t, 1, Cp, m->d_dz2f, m->d_dz2b, m->d_z2, H}, 1,
+        ColSumJob{m->d_dyf, Cp, nn, C, g + m->off_b3, nullptr, 0, nullptr, 1.0f}, st);
+  // dW2 = dZ2^T H1; dZ1 = (dZ2 W2) * gelu'(Z1) with W2 transposed; db2
+  if (e == hipSuccess)
+    e = launch_bwd_group(
+        GemmArgs{H, H, nn, m->d_dz2b, 1, H, m->d_h1, H, 1, g + m->off_w2, nullptr, nullptr, H}, 0,
+        GemmArgs{nn, H, H, m->d_dz2b, H, 1, m->d_w2t, 1, H, m->d_dz1f, m->d_dz1b, m->d_z1, H}, 1,
+        ColSumJob{m->d_dz2f, H, nn, H, g + m->off_b2, nullptr, 0, nullptr, 1.0f}, st);
+  // dW1 = dZ1^T X; db1; the loss from the output tiles' partial sums
+  if (e == hipSuccess)
+    e = launch_bwd_group(
+        GemmArgs{H, F, nn, m->d_dz1b, 1, H, m->d_x, K1, 1, g, nullptr, nullptr, F}, 0, GemmArgs{},
+        0,
+        ColSumJob{m->d_dz1f, H, nn, H, g + m->off_b1, m->d_loss_part, n_tiles, d_loss,
+                  (float)(n * (uint32_t)C)},
+        st);
   return e;
 }
 
@@ -1621,7 +1614,8 @@ hipError_t collect_times(cgs_session s) {
     for (int k = 0; k < sp.n && e == hipSuccess; ++k) {
       float ms = 0.0f;
       e = hipEventElapsedTime(&ms, s->t_ev[sp.ev + k], s->t_ev[sp.ev + k + 1]);
-      // slots: 0 score pass, 1 weight pass, 2 draws, 3 restricted scoring
+      // slots: 0 scored score pass, 1 weight pass, 2 draws, 3 restricted
+      // scoring; kinds 3 (profile mark) and 5 (unscored score pass): none
       const int slot = sp.kind[k] <= 2 ? sp.kind[k] : sp.kind[k] == 4 ? 3 : -1;
       if (e == hipSuccess && slot >= 0) {
         s->kernel_ms[slot] += ms;
@@ -1733,7 +1727,10 @@ hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
   hipError_t e = hipSuccess;
   TimedSpan *span = nullptr;
   if (timed) {
-    const int kinds[3] = {0, 1, do_draw ? 2 : 3};
+    // kind 5: a score pass that reads no prediction (no profile or no active
+    // counter, e.g. the uniform start), kept out of the score-pass totals
+    const bool scored = prof < nv && s->pending_act.n > 0;
+    const int kinds[3] = {scored ? 0 : 5, 1, do_draw ? 2 : 3};
     e = begin_span(s, 3, kinds, &span);
     s->t_step = (int32_t)(s->t_spans.size() - 1);
   }
@@ -2441,7 +2438,7 @@ hipError_t enqueue_batch(cgs_batch b, bool draw) {
                                 hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
     e = launch_batch_score(b->d_sess, b->d_step, b->d_tile_sess, b->total_tiles,
-                           (uint32_t)b->sched.score_grid, b->stream);
+                           (uint32_t)b->sched.score_grid, b->sched.variant, b->stream);
   if (e == hipSuccess)
     e = launch_batch_weight(b->d_sess, b->d_step, b->d_blk_sess, b->total_blocks,
                             (uint32_t)b->sched.weight_grid, b->stream);
@@ -2561,6 +2558,11 @@ extern "C" cgs_status cgs_batch_create(int n, const cgs_session *sessions, const
                 hipGetErrorString(e));
   }
   b->sched = sched ? *sched : default_schedule(b);
+  if (b->sched.score_grid < 1 || b->sched.weight_grid < 1 || b->sched.variant < 0 ||
+      b->sched.variant >= kBatchScoreVariants) {
+    destroy_batch(b);
+    return fail(CGS_EINVAL, "schedule: grids must be >= 1, variant 0..%d", kBatchScoreVariants - 1);
+  }
   if (b->sched.score_grid < 1 || b->sched.weight_grid < 1) {
     const cgs_batch_schedule d = default_schedule(b);
     if (b->sched.score_grid < 1) b->sched.score_grid = d.score_grid;
@@ -2573,6 +2575,8 @@ extern "C" cgs_status cgs_batch_create(int n, const cgs_session *sessions, const
 extern "C" cgs_status cgs_batch_set_schedule(cgs_batch b, const cgs_batch_schedule *s) {
   if (!b || !s) return fail(CGS_EINVAL, "NULL argument");
   if (s->score_grid < 1 || s->weight_grid < 1) return fail(CGS_EINVAL, "grids must be >= 1");
+  if (s->variant < 0 || s->variant >= kBatchScoreVariants)
+    return fail(CGS_EINVAL, "variant %d outside 0..%d", s->variant, kBatchScoreVariants - 1);
   b->sched = *s;
   drop_graph(b);
   return CGS_OK;
@@ -2669,9 +2673,10 @@ extern "C" cgs_status cgs_batch_autotune(cgs_batch b, const char *cache_path,
       while (fgets(line, sizeof line, f)) {
         const char *sep = strstr(line, " -> ");
         if (!sep || std::string(line, sep - line) != key) continue;
-        int sg = 0, wg = 0, ug = 1;
-        if (sscanf(sep + 4, "%d %d %d", &sg, &wg, &ug) == 3 && sg > 0 && wg > 0) {
-          b->sched = cgs_batch_schedule{sg, wg, ug, 0};
+        int sg = 0, wg = 0, ug = 1, va = 0;
+        const int got = sscanf(sep + 4, "%d %d %d %d", &sg, &wg, &ug, &va);
+        if (got >= 3 && sg > 0 && wg > 0 && va >= 0 && va < kBatchScoreVariants) {
+          b->sched = cgs_batch_schedule{sg, wg, ug, va};
           drop_graph(b);
           fclose(f);
           if (chosen) *chosen = b->sched;
@@ -2699,54 +2704,96 @@ extern "C" cgs_status cgs_batch_autotune(cgs_batch b, const char *cache_path,
   }
   HIP_TRY(hipMemcpyAsync(b->d_step, b->h_step, (size_t)b->n * sizeof(BatchStep),
                          hipMemcpyHostToDevice, b->stream));
-  auto time_it = [&](bool score, int grid, float &best) -> hipError_t {
-    float total = 1e30f;
-    for (int rep = 0; rep < 4; ++rep) {
+  // the median of 5 timed runs after one warm-up run, HIP events around
+  // the launches on the batch's stream
+  auto time_runs = [&](auto &&launch, float &med) -> hipError_t {
+    float t[6];
+    for (int rep = 0; rep < 6; ++rep) {
       hipError_t e = hipEventRecord(b->e0, b->stream);
-      if (e == hipSuccess)
-        e = score ? launch_batch_score(b->d_sess, b->d_step, b->d_tile_sess, b->total_tiles,
-                                       (uint32_t)grid, b->stream)
-                  : launch_batch_weight(b->d_sess, b->d_step, b->d_blk_sess, b->total_blocks,
-                                        (uint32_t)grid, b->stream);
+      if (e == hipSuccess) e = launch();
       if (e == hipSuccess) e = hipEventRecord(b->e1, b->stream);
       if (e == hipSuccess) e = hipEventSynchronize(b->e1);
-      float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->e0, b->e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t[rep], b->e0, b->e1);
       if (e != hipSuccess) return e;
-      if (rep > 0) total = std::min(total, ms); // first run warms caches
     }
-    best = total;
+    std::sort(t + 1, t + 6);
+    med = t[3];
     return hipSuccess;
   };
   const int cand[] = {128, 256, 512, 1024, 2048, 4096, 8192};
   cgs_batch_schedule best = default_schedule(b);
   float best_s = 1e30f, best_w = 1e30f;
-  for (int g : cand) {
-    if ((uint32_t)g > std::max<uint32_t>(b->total_tiles, 1) && g != cand[0]) break;
-    float t;
-    HIP_TRY(time_it(true, g, t));
-    if (t < best_s) {
-      best_s = t;
-      best.score_grid = g;
+  // score pass: every variant at every grid size
+  for (int v = 0; v < kBatchScoreVariants; ++v) {
+    for (int g : cand) {
+      if ((uint32_t)g > std::max<uint32_t>(b->total_tiles, 1) && g != cand[0]) break;
+      float t = 0.0f;
+      HIP_TRY(time_runs(
+          [&] {
+            return launch_batch_score(b->d_sess, b->d_step, b->d_tile_sess, b->total_tiles,
+                                      (uint32_t)g, v, b->stream);
+          },
+          t));
+      if (t < best_s) {
+        best_s = t;
+        best.score_grid = g;
+        best.variant = v;
+      }
     }
   }
   for (int g : cand) {
     if ((uint32_t)g > std::max<uint32_t>(b->total_blocks, 1) && g != cand[0]) break;
-    float t;
-    HIP_TRY(time_it(false, g, t));
+    float t = 0.0f;
+    HIP_TRY(time_runs(
+        [&] {
+          return launch_batch_weight(b->d_sess, b->d_step, b->d_blk_sess, b->total_blocks,
+                                     (uint32_t)g, b->stream);
+        },
+        t));
     if (t < best_w) {
       best_w = t;
       best.weight_grid = g;
     }
   }
-  best.use_graph = 1;
+  // graph or plain launches: the step's copy, score and weight passes (no
+  // draw) either way
+  float t_plain = 0.0f, t_graph = 1e30f;
+  auto step_launches = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(b->d_step, b->h_step, (size_t)b->n * sizeof(BatchStep),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+      e = launch_batch_score(b->d_sess, b->d_step, b->d_tile_sess, b->total_tiles,
+                             (uint32_t)best.score_grid, best.variant, b->stream);
+    if (e == hipSuccess)
+      e = launch_batch_weight(b->d_sess, b->d_step, b->d_blk_sess, b->total_blocks,
+                              (uint32_t)best.weight_grid, b->stream);
+    return e;
+  };
+  HIP_TRY(time_runs(step_launches, t_plain));
+  {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t ek = step_launches();
+      e = hipStreamEndCapture(b->stream, &g);
+      if (e == hipSuccess) e = ek;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = time_runs([&] { return hipGraphLaunch(ge, b->stream); }, t_graph);
+    if (ge) hipGraphExecDestroy(ge);
+    if (g) hipGraphDestroy(g);
+    HIP_TRY(e);
+  }
+  best.use_graph = t_graph <= t_plain ? 1 : 0;
   b->sched = best;
   drop_graph(b);
   // the sessions' last-step results were overwritten
   for (cgs_session s : b->sess) s->stepped = false;
   if (cache_path) {
     if (FILE *f = fopen(cache_path, "a")) {
-      fprintf(f, "%s -> %d %d %d\n", key.c_str(), best.score_grid, best.weight_grid, best.use_graph);
+      fprintf(f, "%s -> %d %d %d %d\n", key.c_str(), best.score_grid, best.weight_grid,
+              best.use_graph, best.variant);
       fclose(f);
     }
   }

@@ -182,8 +182,9 @@ def test_block_size_and_ragged_tail(block_log2):
 
 
 def test_sampled_timing_counts_and_leaves_picks_unchanged():
-    """timing = 3 times launched steps 0, 3, 6, 9 (and their further draws);
-    the picks stay those of the oracle."""
+    """timing = 3 times launched steps 0, 3, 6, 9 (and their further draws;
+    the score pass of step 0, the uniform start, is not a scored pass); the
+    picks stay those of the oracle."""
     m = cgs()
     spec = synth.space_c1()
     p = m.cgs_default_params()
@@ -196,7 +197,8 @@ def test_sampled_timing_counts_and_leaves_picks_unchanged():
     for i in range(9):
         ref, info = pair.step(ref.picks[0], deltas[i], U[1 + 2 * i: 3 + 2 * i], check_scores=False)
     ms, n = pair.sess.kernel_times()
-    assert n.tolist() == [4, 4, 1 + 3 * 2, 0]
+    # the uniform start's score pass reads no prediction and is not counted
+    assert n.tolist() == [3, 4, 1 + 3 * 2, 0]
     assert (ms[:3] > 0).all()
     assert info.device_ms > 0        # step 9 is timed
     # no timing: zeros
