@@ -637,6 +637,22 @@ cgs_status cgs_tuning_run_batch(cgs_batch batch, const float *runtime_host,
 cgs_status cgs_sample_weights(cgs_space stream_owner, const uint32_t *q_host, uint64_t n,
                               const uint64_t *u64_host, int n_draws, int64_t *picks_host);
 
+/* cgs_sample_weights for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, hosts that forbid hipMalloc):
+ * the same arguments, draws and results, but the working copy of the
+ * weights and the block sums live in one fixed array of device memory that
+ * the library reserves per GPU (16 MiB + 8 KiB, held until the process
+ * ends), so the call makes no hipMalloc or hipFree.
+ *   n       at most 4,194,304 (2^22) weights; more returns CGS_ERANGE
+ *           before any device work
+ * The array is shared by every call on the same GPU and keeps the last
+ * call's contents; each call rewrites all of it that it reads.  Calls that
+ * overlap on one GPU (other threads, other streams) race on it: serialise
+ * them.  Synchronises. */
+cgs_status cgs_sample_weights_noalloc(cgs_space stream_owner, const uint32_t *q_host, uint64_t n,
+                                      const uint64_t *u64_host, int n_draws,
+                                      int64_t *picks_host);
+
 /* -------------------------------------------------- expert system */
 /* Bottleneck analysis and counter changes (Sect. 3.5), host float64.
  *   pc_host[24]       measured counters in Table 1 order

@@ -44,7 +44,7 @@ EXPORTS = (
     "cgs_model_copy_forest", "cgs_poly_design", "cgs_model_fit_poly", "cgs_poly_shape",
     "cgs_poly_copy_coefficients", "cgs_model_load_predictions", "cgs_default_tuning_opts",
     "cgs_tuning_run", "cgs_batch_draw", "cgs_tuning_run_batch", "cgs_search_run",
-    "cgs_default_online_opts", "cgs_online_run",
+    "cgs_default_online_opts", "cgs_online_run", "cgs_sample_weights_noalloc",
 )
 
 
@@ -180,6 +180,7 @@ _sig("cgs_session_copy_weights", [_p, _u64, _u64, _p])
 _sig("cgs_session_copy_explored", [_p, _p, _u64])
 _sig("cgs_session_destroy", [_p], None)
 _sig("cgs_sample_weights", [_p, _p, _u64, _p, C.c_int, _p])
+_sig("cgs_sample_weights_noalloc", [_p, _p, _u64, _p, C.c_int, _p])
 _sig("cgs_expert_system", [_p, _ptr(cgs_expert_params), _p, _p, _ptr(C.c_double)])
 _sig("cgs_mlp_param_count", [_ptr(cgs_mlp_desc)], C.c_uint64)
 _sig("cgs_model_load_mlp", [_p, _ptr(cgs_mlp_desc), _p, _ptr(_p)])
@@ -310,6 +311,16 @@ class Space:
         picks = np.full(len(u), -1, dtype=np.int64)
         _check(_lib.cgs_sample_weights(self.h, _ptrof(q), len(q), _ptrof(u), len(u),
                                        _ptrof(picks)), "cgs_sample_weights")
+        return picks
+
+    def sample_weights_noalloc(self, q, uniforms) -> np.ndarray:
+        """sample_weights through the entry point that allocates no device
+        memory (at most 2^22 weights)."""
+        q = _arr(q, np.uint32)
+        u = _arr(uniforms, np.uint64)
+        picks = np.full(len(u), -1, dtype=np.int64)
+        _check(_lib.cgs_sample_weights_noalloc(self.h, _ptrof(q), len(q), _ptrof(u), len(u),
+                                               _ptrof(picks)), "cgs_sample_weights_noalloc")
         return picks
 
     def close(self) -> None:

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -3026,14 +3027,43 @@ extern "C" cgs_status cgs_tuning_run_batch(cgs_batch b, const float *runtime,
 extern "C" void cgs_batch_destroy(cgs_batch b) { destroy_batch(b); }
 
 // ------------------------------------------------------- standalone sampler
-extern "C" cgs_status cgs_sample_weights(cgs_space sp, const uint32_t *q, uint64_t n,
-                                         const uint64_t *u64, int n_draws, int64_t *picks) {
+namespace {
+
+// n_draws draws with removal over the weights d_q[n] (a device working copy,
+// zeroed where picked) with block sums d_bsum[n_blocks] (2^lg weights per
+// block); the draws of cgs_sample_weights and cgs_sample_weights_noalloc.
+cgs_status sample_resident(cgs_space sp, uint32_t *d_q, uint64_t n, int lg, uint64_t *d_bsum,
+                           uint32_t n_blocks, const uint64_t *u64, int n_draws, int64_t *picks) {
+  hipError_t e = launch_array_block_sums(d_q, (uint32_t)n, lg, d_bsum, sp->stream);
+  for (int i = 0; i < n_draws && e == hipSuccess; ++i) {
+    e = launch_array_draw(d_q, (uint32_t)n, lg, d_bsum, n_blocks, u64[i], sp->d_res, sp->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
+    if (e == hipSuccess) {
+      if (sp->h_res->total == 0) break;
+      if (sp->h_res->valid == kNoPick) return fail(CGS_EDEVICE, "draw found no index although Q > 0");
+      picks[i] = (int64_t)sp->h_res->valid;
+    }
+  }
+  if (e != hipSuccess) return fail(CGS_EDEVICE, "sampler: %s", hipGetErrorString(e));
+  return CGS_OK;
+}
+
+cgs_status sample_args(cgs_space sp, const uint32_t *q, uint64_t n, const uint64_t *u64,
+                       int n_draws, int64_t *picks) {
   if (!sp || (!q && n) || (!u64 && n_draws) || (!picks && n_draws))
     return fail(CGS_EINVAL, "NULL argument");
   if (n > 0xffffffffull) return fail(CGS_ERANGE, "more than 2^32 - 1 weights");
   if (n_draws < 0) return fail(CGS_EINVAL, "negative n_draws");
   for (int i = 0; i < n_draws; ++i) picks[i] = -1;
-  if (n == 0 || n_draws == 0) return CGS_OK;
+  return CGS_OK;
+}
+
+} // namespace
+
+extern "C" cgs_status cgs_sample_weights(cgs_space sp, const uint32_t *q, uint64_t n,
+                                         const uint64_t *u64, int n_draws, int64_t *picks) {
+  const cgs_status st = sample_args(sp, q, n, u64, n_draws, picks);
+  if (st != CGS_OK || n == 0 || n_draws == 0) return st;
   const int lg = auto_block_log2(n);
   const uint32_t n_blocks = (uint32_t)((n + (1ull << lg) - 1) >> lg);
   uint32_t *d_q = nullptr;
@@ -3042,22 +3072,83 @@ extern "C" cgs_status cgs_sample_weights(cgs_space sp, const uint32_t *q, uint64
   hipError_t e = dalloc(&d_bsum, n_blocks);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_q, q, n * sizeof(uint32_t), hipMemcpyHostToDevice, sp->stream);
-  if (e == hipSuccess) e = launch_array_block_sums(d_q, (uint32_t)n, lg, d_bsum, sp->stream);
-  for (int i = 0; i < n_draws && e == hipSuccess; ++i) {
-    e = launch_array_draw(d_q, (uint32_t)n, lg, d_bsum, n_blocks, u64[i], sp->d_res, sp->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
-    if (e == hipSuccess) {
-      if (sp->h_res->total == 0) break;
-      if (sp->h_res->valid == kNoPick) {
-        dfree(d_q);
-        dfree(d_bsum);
-        return fail(CGS_EDEVICE, "draw found no index although Q > 0");
-      }
-      picks[i] = (int64_t)sp->h_res->valid;
-    }
-  }
+  cgs_status r = e == hipSuccess ? sample_resident(sp, d_q, n, lg, d_bsum, n_blocks, u64, n_draws, picks)
+                                 : fail(CGS_EDEVICE, "sampler: %s", hipGetErrorString(e));
   dfree(d_q);
   dfree(d_bsum);
+  return r;
+}
+
+// ------------------------------------------- the sampler without allocation
+// Device memory of cgs_sample_weights_noalloc: the working copy of the
+// weights (a draw zeroes what it picks) from byte 0, the block sums from
+// byte kNoAllocBsumOffset.  Every GPU the library runs on holds its own
+// copy of the array until the process ends.  Host code never hands the
+// array's name to a kernel or a copy (on the host it is only a stand-in for
+// the symbol); it uses the device address hipGetSymbolAddress gives for
+// the stream's device, fetched once per device.
+constexpr uint64_t kNoAllocMaxWeights = 1ull << 22;
+constexpr uint64_t kNoAllocBsumOffset = kNoAllocMaxWeights * sizeof(uint32_t);
+constexpr uint64_t kNoAllocMaxBlocks = 1024; // 2^22 weights in blocks of 2^12
+constexpr uint64_t kNoAllocBytes = kNoAllocBsumOffset + kNoAllocMaxBlocks * sizeof(uint64_t);
+static_assert(kNoAllocBsumOffset % 256 == 0, "block sums stay 256-byte aligned");
+
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device dev (looked up on first use
+// with dev current; the caller's current device is restored).
+hipError_t scratch_on(int dev, uint8_t **out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != dev) e = hipSetDevice(dev);
+    void *ptr = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev >= 0 && prev != dev) {
+      const hipError_t e2 = hipSetDevice(prev);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<uint8_t *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+} // namespace
+
+extern "C" cgs_status cgs_sample_weights_noalloc(cgs_space sp, const uint32_t *q, uint64_t n,
+                                                 const uint64_t *u64, int n_draws,
+                                                 int64_t *picks) {
+  const cgs_status st = sample_args(sp, q, n, u64, n_draws, picks);
+  if (st != CGS_OK) return st;
+  if (n > kNoAllocMaxWeights)
+    return fail(CGS_ERANGE, "cgs_sample_weights_noalloc takes at most %llu weights, got %llu",
+                (unsigned long long)kNoAllocMaxWeights, (unsigned long long)n);
+  if (n == 0 || n_draws == 0) return CGS_OK;
+  const int lg = auto_block_log2(n);
+  const uint32_t n_blocks = (uint32_t)((n + (1ull << lg) - 1) >> lg);
+  if (n_blocks > kNoAllocMaxBlocks)
+    return fail(CGS_ERANGE, "%u weight blocks exceed the %llu the array holds", n_blocks,
+                (unsigned long long)kNoAllocMaxBlocks);
+  int dev = -1;
+  hipError_t e = hipStreamGetDevice(sp->stream, &dev);
+  uint8_t *base = nullptr;
+  if (e == hipSuccess) e = scratch_on(dev, &base);
+  if (e != hipSuccess) return fail(CGS_EDEVICE, "sampler scratch: %s", hipGetErrorString(e));
+  uint32_t *d_q = reinterpret_cast<uint32_t *>(base);
+  uint64_t *d_bsum = reinterpret_cast<uint64_t *>(base + kNoAllocBsumOffset);
+  // every weight and block sum the draws read is written here first
+  e = hipMemcpyAsync(d_q, q, n * sizeof(uint32_t), hipMemcpyHostToDevice, sp->stream);
   if (e != hipSuccess) return fail(CGS_EDEVICE, "sampler: %s", hipGetErrorString(e));
-  return CGS_OK;
+  return sample_resident(sp, d_q, n, lg, d_bsum, n_blocks, u64, n_draws, picks);
 }
