@@ -94,10 +94,17 @@ __device__ __forceinline__ float key_float(uint32_t k) {
   return __uint_as_float(u);
 }
 
-// The constants of one step's normalisation: the two divisors with their
-// reciprocals (stepdiv.h), the cut-off and the smallest weight.
+// The constants of one step's normalisation: the divisors of positive
+// scores (s_max) and of the others (-s_min) with their reciprocals
+// (stepdiv.h), the cut-off and the smallest weight.  1 - s / s_min is
+// formed as 1 + s / (-s_min): the same float, since IEEE division and
+// rounding to nearest are symmetric under a change of sign.  A divisor that
+// no unexplored configuration divides by (s_max <= 0: no positive score;
+// s_min >= 0: only zero scores, whose quotient is 0 for any divisor) is
+// replaced by 1.
 struct StepNorm {
-  StepDivisor pos, neg; // s_max (for s > 0) and s_min (for s <= 0)
+  StepDivisor pos, neg; // s_max and -s_min
+  bool fast;            // both divisors in the fast path's range
   float gamma, w_min;
 };
 // The reciprocals are made opaque to the optimiser: it would otherwise
@@ -108,36 +115,45 @@ __device__ __forceinline__ float opaque(float x) {
   return x;
 }
 __device__ __forceinline__ StepNorm step_norm(float s_min, float s_max, float gamma, float w_min) {
-  StepNorm nm{step_divisor(s_max), step_divisor(s_min), gamma, w_min};
+  StepNorm nm{step_divisor(s_max > 0.0f ? s_max : 1.0f),
+              step_divisor(s_min < 0.0f ? -s_min : 1.0f), false, gamma, w_min};
+  nm.fast = nm.pos.fast && nm.neg.fast;
   nm.pos.r = opaque(nm.pos.r);
   nm.neg.r = opaque(nm.neg.r);
   return nm;
 }
 
 // Normalised weight of the score-normalisation equation, quantised to
-// rint(w * 2^23).  The eighth power is three squarings; s == 0 maps to 1.
-// One division per configuration, correctly rounded through the step's
-// reciprocal (div_by gives s / divisor exactly as the IEEE division): the
-// divisor (s_max for s > 0, s_min otherwise) is selected per lane, so a wave
-// holding scores of both signs does not run two divisions; every value is
-// the same float as with the two-branch form.
+// rint(w * 2^23):
+//   s > 0: (1 + s/s_max)^8;  gamma < s <= 0: max(w_min, (1 - s/s_min)^8),
+//   1 when s == 0;  s <= gamma: w_min;  explored: 0.
+// The eighth power is three squarings.  With gamma <= 0 and w_min <= 1 (the
+// session's parameters are checked for both) the cases fold into
+//   y = 1 + s / D (D = s_max or -s_min by the sign of s),
+//   w = s > gamma ? max(w_min, y^8) : w_min
+// (for s > 0, y^8 >= 1 >= w_min): every value is the same float as the
+// case-by-case form.  The division is correctly rounded through the step's
+// reciprocal (stepdiv.h) wherever the fast path's operand range holds (the
+// divisors are checked once per step; |s| <= D for every unexplored
+// configuration, so only a non-zero |s| below 2^-60 leaves it) and the IEEE
+// division otherwise.
 __device__ __forceinline__ uint32_t quantized_weight(float s, bool explored, const StepNorm &nm) {
   const bool pos = s > 0.0f;
   const float d = pos ? nm.pos.d : nm.neg.d;
-  const bool ok = div_fast_ok(s, pos ? nm.pos.fast : nm.neg.fast);
-  float t = div_fast(s, d, pos ? nm.pos.r : nm.neg.r);
-  // operands outside the fast path's range (t is not used when s == 0)
-  if (__any(!ok && s != 0.0f)) t = ok ? t : s / d;
-  const float y = pos ? 1.0f + t : 1.0f - t;
-  const float gamma = nm.gamma, w_min = nm.w_min;
+  float t;
+  if (nm.fast) {
+    t = div_fast_core(s, d, pos ? nm.pos.r : nm.neg.r); // +-0 for s == 0
+    const uint32_t ab = __float_as_uint(s) & 0x7fffffffu;
+    const bool slow = !explored && ab - 1u < 0x217fffffu; // 0 < |s| < 2^-60
+    if (__any(slow)) t = slow ? s / d : t;
+  } else {
+    t = s == 0.0f ? 0.0f : s / d;
+  }
+  const float y = 1.0f + t;
   const float y2 = y * y;
   const float y4 = y2 * y2;
   const float y8 = y4 * y4;
-  float w = w_min;
-  if (pos)
-    w = y8;
-  else if (s > gamma)
-    w = (s == 0.0f) ? 1.0f : fmaxf(w_min, y8);
+  const float w = s > nm.gamma ? fmaxf(nm.w_min, y8) : nm.w_min;
   return explored ? 0u : (uint32_t)rintf(w * 8388608.0f);
 }
 

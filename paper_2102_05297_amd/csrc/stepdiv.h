@@ -43,15 +43,22 @@ __host__ __device__ __forceinline__ bool div_fast_ok(float s, bool fast) {
   return fast && ((as >= 0x1p-60f && as <= 0x1p60f) || s == 0.0f);
 }
 
-// s / d through r = RN(1 / d); equal to the IEEE quotient whenever
-// div_fast_ok(s, step_divisor(d).fast).
-__host__ __device__ __forceinline__ float div_fast(float s, float d, float r) {
+// The correction sequence above; equal to s / d for non-zero s in the fast
+// path's range, and +-0 (the sign of s * r, which may differ from the
+// quotient's) for s == 0.
+__host__ __device__ __forceinline__ float div_fast_core(float s, float d, float r) {
   const float q0 = s * r;
   const float e0 = fmaf(-q0, d, s);
   const float q1 = fmaf(e0, r, q0);
   const float e1 = fmaf(-q1, d, s);
-  const float q2 = fmaf(e1, r, q1);
-  return s == 0.0f ? q0 : q2; // +-0 keeps the quotient's sign, as q0 does
+  return fmaf(e1, r, q1);
+}
+
+// s / d through r = RN(1 / d); equal to the IEEE quotient whenever
+// div_fast_ok(s, step_divisor(d).fast).
+__host__ __device__ __forceinline__ float div_fast(float s, float d, float r) {
+  const float q0 = s * r;
+  return s == 0.0f ? q0 : div_fast_core(s, d, r); // +-0 keeps the quotient's sign, as q0 does
 }
 
 // The quotient s / v.d for every input (the reference composition; device
