@@ -468,13 +468,21 @@ cgs_status cgs_sample_next(cgs_session session, uint64_t u64, uint64_t *raw_out,
  * host code in the library: the uniform start (cgs_search_step without a
  * profile, cgs_sample_next with u64_host[0]), then for i = 0..n_steps-1 a
  * step profiling the last pick with measured_host[i][24] and expert[i],
- * and a draw with u64_host[i + 1] -- exactly those calls, in that order.
+ * and a draw with u64_host[i + 1] -- the results of exactly those calls,
+ * in that order.  The counter changes of every step follow from the
+ * measured counters alone, so the library runs the expert system for all
+ * steps first and enqueues the steps ahead of their picks (up to 255
+ * ahead): each step's kernels read the configuration to profile from
+ * device memory, where the previous draw left it, and the host collects
+ * the picks as they are published.
  *   raw_out_host[n_steps + 1]     picks (raw indices); valid_out_host may
  *                                 be NULL; unmade picks stay 2^64 - 1
- *   step_us_host[n_steps]         wall time of each profiled step and its
- *                                 draw in microseconds (may be NULL)
+ *   step_us_host[n_steps]         wall time between the publication of
+ *                                 each step's pick and the previous one,
+ *                                 in microseconds (may be NULL)
  * Returns the first failing call's status (CGS_EEMPTY when the space runs
- * out). */
+ * out); the steps enqueued after that one find no profile and draw
+ * nothing.  The session's stream is idle on return. */
 cgs_status cgs_search_run(cgs_session session, cgs_model model, int n_steps,
                           const double *measured_host, const cgs_expert_params *expert,
                           const uint64_t *u64_host, uint64_t *raw_out_host,

@@ -114,6 +114,7 @@ struct cgs_model_s {
 };
 
 constexpr uint32_t kTimeEvents = 512; // event markers of 128 timed steps
+constexpr uint32_t kResultRing = 256; // draw results of steps enqueued ahead
 
 // Launches between consecutive markers t_ev[ev .. ev + n]: kernel k runs
 // between markers ev + k and ev + k + 1.
@@ -172,6 +173,12 @@ struct cgs_session_s {
   uint64_t seq = 0;          // sequence number of the last launched draw
   int n_active = 0;
   uint64_t last_total = 0;
+  // steps enqueued ahead of their picks (cgs_search_run): the profiled
+  // configuration passes between steps in device memory (two words used
+  // alternately), the results land in a ring of pinned slots
+  uint32_t *d_prof = nullptr;     // [2]
+  DrawResult *h_ring = nullptr;   // pinned, mapped, [kResultRing]
+  DrawResult *d_ring = nullptr;
 };
 
 // ------------------------------------------------------------------ misc
@@ -1588,8 +1595,10 @@ void destroy_session(cgs_session s) {
   dfree(s->d_nb_bsum);
   dfree(s->d_nb_stats);
   dfree(s->d_nb_acc);
+  dfree(s->d_prof);
   if (s->h_res) (void)hipHostFree(s->h_res);
   if (s->h_acc) (void)hipHostFree(s->h_acc);
+  if (s->h_ring) (void)hipHostFree(s->h_ring);
   for (hipEvent_t ev : s->t_ev)
     if (ev) (void)hipEventDestroy(ev);
   destroy_space(s->space);
@@ -1716,38 +1725,43 @@ hipError_t launch_pending_nb(cgs_session s, bool do_draw, uint64_t u64) {
   return hipSuccess;
 }
 
-hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
-  if (s->pending_nb) return launch_pending_nb(s, do_draw, u64);
+// Enqueues one full step: score pass, weight pass, and either its first
+// draw (do_draw; result in d_res under sequence number seq) or just the
+// marking of its profiled configuration.  The profile is `prof` or, with
+// d_prof_in, the word the previous step's draw left in device memory
+// (`scored` then tells whether the step has counters to score); with
+// d_prof_out the draw leaves its pick there.  Advances the accumulator set.
+hipError_t launch_full_step(cgs_session s, cgs_model m, const ActiveCounters &act, uint32_t prof,
+                            const uint32_t *d_prof_in, uint32_t *d_prof_out, bool scored,
+                            bool do_draw, uint64_t u64, DrawResult *d_res, uint64_t seq) {
   cgs_space sp = s->space;
-  cgs_model m = s->pending_model;
   const uint32_t nv = (uint32_t)sp->n_valid;
   StepAcc *acc = s->d_acc + s->parity * kAccSlots;
   StepAcc *acc_next = s->d_acc + (s->parity ^ 1) * kAccSlots;
-  const uint32_t prof = s->pending_profile;
   const bool timed = s->params.timing > 0 && s->n_launched % (uint64_t)s->params.timing == 0;
   hipError_t e = hipSuccess;
   TimedSpan *span = nullptr;
   if (timed) {
     // kind 5: a score pass that reads no prediction (no profile or no active
     // counter, e.g. the uniform start), kept out of the score-pass totals
-    const bool scored = prof < nv && s->pending_act.n > 0;
     const int kinds[3] = {scored ? 0 : 5, 1, do_draw ? 2 : 3};
     e = begin_span(s, 3, kinds, &span);
     s->t_step = (int32_t)(s->t_spans.size() - 1);
   }
   if (e == hipSuccess)
-    e = launch_score_pass(m->d_P, m->stride, prof, s->pending_act, s->d_explored, nv, s->d_s, acc,
-                          sp->stream);
+    e = launch_score_pass(m->d_P, m->stride, prof, act, s->d_explored, nv, s->d_s, acc,
+                          sp->stream, d_prof_in);
   if (e == hipSuccess && timed) e = mark_span(s, span, 0);
   if (e == hipSuccess)
     e = launch_weight_pass(s->d_s, s->d_explored, nv, prof, acc, acc_next, s->params.gamma,
-                           s->params.w_min, s->block_log2, s->d_bsum, s->n_blocks, sp->stream);
+                           s->params.w_min, s->block_log2, s->d_bsum, s->n_blocks, sp->stream,
+                           d_prof_in);
   if (e == hipSuccess && timed) e = mark_span(s, span, 1);
   if (e == hipSuccess) {
     if (do_draw)
       e = launch_draw(s->d_s, s->d_explored, nv, prof, true, acc, s->params.gamma, s->params.w_min,
-                      s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, s->d_res, ++s->seq,
-                      sp->stream);
+                      s->block_log2, s->d_bsum, s->n_blocks, u64, sp->d_idx, d_res, seq,
+                      sp->stream, d_prof_in, d_prof_out);
     else
       e = launch_mark_one(s->d_explored, prof, nv, sp->stream);
   }
@@ -1759,6 +1773,17 @@ hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
   s->last_nb = false;
   s->cur_acc = s->parity;
   s->parity ^= 1;
+  return hipSuccess;
+}
+
+hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64) {
+  if (s->pending_nb) return launch_pending_nb(s, do_draw, u64);
+  const uint32_t prof = s->pending_profile;
+  const bool scored = prof < (uint32_t)s->space->n_valid && s->pending_act.n > 0;
+  const uint64_t seq = do_draw ? ++s->seq : s->seq;
+  const hipError_t e = launch_full_step(s, s->pending_model, s->pending_act, prof, nullptr,
+                                        nullptr, scored, do_draw, u64, s->d_res, seq);
+  if (e != hipSuccess) return e;
   s->pending = false;
   return hipSuccess;
 }
@@ -1819,6 +1844,14 @@ extern "C" cgs_status cgs_session_create(cgs_space sp, const cgs_params *params,
   }
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void **>(&s->h_acc), kAccSlots * sizeof(StepAcc), 0);
+  if (e == hipSuccess) e = dalloc(&s->d_prof, 2);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void **>(&s->h_ring), kResultRing * sizeof(DrawResult),
+                      hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) {
+    std::memset(s->h_ring, 0, kResultRing * sizeof(DrawResult));
+    e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->d_ring), s->h_ring, 0);
+  }
   if (e == hipSuccess && p.timing > 0) {
     s->t_ev.assign(kTimeEvents, nullptr);
     s->t_spans.reserve(kTimeEvents / 2);
@@ -1983,8 +2016,13 @@ extern "C" cgs_status cgs_search_step(cgs_session s, cgs_model m, uint64_t profi
 }
 
 // n_steps steps of the counter-guided search, each the work of one
-// cgs_search_step with measured counters plus one cgs_sample_next, run from
-// host code without returning to the caller in between.
+// cgs_search_step with measured counters plus one cgs_sample_next, with
+// the same results.  Every step's counter changes come from the measured
+// counters alone, so the expert system runs for all steps first and the
+// steps are enqueued ahead of their picks (up to kResultRing - 1 ahead of
+// the last pick read): step k reads its profiled configuration from the
+// device word the draw of step k - 1 wrote, and its draw's result lands in
+// ring slot k.  The host reads the picks in order as they are published.
 extern "C" cgs_status cgs_search_run(cgs_session s, cgs_model m, int n_steps,
                                      const double *measured, const cgs_expert_params *expert,
                                      const uint64_t *u64, uint64_t *raw_out, uint64_t *valid_out,
@@ -1996,24 +2034,63 @@ extern "C" cgs_status cgs_search_run(cgs_session s, cgs_model m, int n_steps,
     raw_out[i] = CGS_NO_PROFILE;
     if (valid_out) valid_out[i] = CGS_NO_PROFILE;
   }
-  cgs_status st = cgs_search_step(s, m, CGS_NO_PROFILE, nullptr, nullptr, nullptr);
-  uint64_t raw = 0, valid = 0;
-  if (st == CGS_OK) st = cgs_sample_next(s, u64[0], &raw, &valid);
+  cgs_space sp = s->space;
+  if (m->space != sp) return fail(CGS_EINVAL, "model and session belong to different spaces");
+  if (sp->n_valid == 0) return fail(CGS_EEMPTY, "the space has no valid configuration");
+  std::vector<ActiveCounters> acts((size_t)n_steps + 1);
+  cgs_status st = step_counters(m, true, nullptr, nullptr, nullptr, &acts[0]);
+  for (int i = 0; i < n_steps && st == CGS_OK; ++i)
+    st = step_counters(m, false, nullptr, measured + (size_t)i * 24, expert + i, &acts[i + 1]);
   if (st != CGS_OK) return st;
-  raw_out[0] = raw;
-  if (valid_out) valid_out[0] = valid;
-  for (int i = 0; i < n_steps; ++i) {
-    const auto t0 = std::chrono::steady_clock::now();
-    st = cgs_search_step(s, m, raw, nullptr, measured + (size_t)i * 24, expert + i);
-    if (st == CGS_OK) st = cgs_sample_next(s, u64[i + 1], &raw, &valid);
-    if (st != CGS_OK) return st;
-    if (step_us)
-      step_us[i] =
-          std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-    raw_out[i + 1] = raw;
-    if (valid_out) valid_out[i + 1] = valid;
+  st = flush_pending(s);
+  if (st != CGS_OK) return st;
+  const uint64_t seq0 = s->seq;
+  // step k: profile from d_prof[k & 1] (none for the start), pick to
+  // d_prof[(k + 1) & 1], result in ring slot k % kResultRing
+  auto launch = [&](int k) {
+    const uint32_t *in = k == 0 ? nullptr : s->d_prof + (k & 1);
+    return launch_full_step(s, m, acts[k], kNoProfile, in, s->d_prof + ((k + 1) & 1),
+                            k > 0 && acts[k].n > 0, true, u64[k], s->d_ring + k % kResultRing,
+                            seq0 + (uint64_t)k + 1);
+  };
+  // leaves the session as after the last launched step: no further draw
+  // is pending, the stream has finished everything this call enqueued
+  int launched = 0;
+  auto finish = [&](cgs_status r) {
+    s->seq = seq0 + (uint64_t)launched;
+    s->stepped = s->stepped || launched > 0;
+    const hipError_t e = hipStreamSynchronize(sp->stream);
+    if (r == CGS_OK && e != hipSuccess)
+      return fail(CGS_EDEVICE, "search run: %s", hipGetErrorString(e));
+    return r;
+  };
+  auto t_prev = std::chrono::steady_clock::now();
+  for (int k = 0; k <= n_steps; ++k) {
+    while (launched <= n_steps && launched < k + (int)kResultRing - 1) {
+      const hipError_t e = launch(launched);
+      if (e != hipSuccess)
+        return finish(fail(CGS_EDEVICE, "search run step %d: %s", launched, hipGetErrorString(e)));
+      ++launched;
+    }
+    const DrawResult *slot = s->h_ring + k % kResultRing;
+    const cgs_status ws = wait_draw(s, slot, seq0 + (uint64_t)k + 1);
+    if (ws != CGS_OK) return finish(ws);
+    const auto t = std::chrono::steady_clock::now();
+    DrawResult r;
+    std::memcpy(&r, const_cast<const DrawResult *>(static_cast<volatile const DrawResult *>(slot)),
+                sizeof r);
+    s->last_total = r.total;
+    s->n_active = acts[k].n;
+    if (r.total == 0) return finish(fail(CGS_EEMPTY, "no unexplored valid configuration is left"));
+    if (r.valid == kNoPick)
+      return finish(fail(CGS_EDEVICE, "draw found no configuration although Q = %llu",
+                         (unsigned long long)r.total));
+    raw_out[k] = r.raw;
+    if (valid_out) valid_out[k] = r.valid;
+    if (k > 0 && step_us) step_us[k - 1] = std::chrono::duration<double, std::micro>(t - t_prev).count();
+    t_prev = t;
   }
-  return CGS_OK;
+  return finish(CGS_OK);
 }
 
 extern "C" void cgs_default_online_opts(cgs_online_opts *o) {

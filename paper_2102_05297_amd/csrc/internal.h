@@ -194,19 +194,27 @@ hipError_t launch_sq_diff(const float *Pa, const float *Pb, uint64_t stride_a, u
                           int n_counters, const uint32_t *sample, uint32_t n, double *partial,
                           uint32_t grid, hipStream_t stream);
 hipError_t launch_reset_acc(StepAcc *d_acc, int n, hipStream_t stream);
+// The step's kernels take the profiled configuration's valid index either
+// as `profile` or, when d_prof is given, from device memory (the previous
+// draw's d_prof_out), so steps can be enqueued before the pick they profile
+// is known on the host.
 hipError_t launch_score_pass(const float *d_P, uint64_t stride, uint32_t profile,
                              const ActiveCounters &act, const uint32_t *d_explored,
-                             uint32_t n_valid, float *d_s, StepAcc *d_acc, hipStream_t stream);
+                             uint32_t n_valid, float *d_s, StepAcc *d_acc, hipStream_t stream,
+                             const uint32_t *d_prof = nullptr);
 hipError_t launch_weight_pass(const float *d_s, const uint32_t *d_explored, uint32_t n_valid,
                               uint32_t profile, const StepAcc *d_acc, StepAcc *d_acc_next,
                               float gamma, float w_min, int block_log2, uint64_t *d_bsum,
-                              uint32_t n_blocks, hipStream_t stream);
-// The draw stores its result, then `seq` with a system-scope release.
+                              uint32_t n_blocks, hipStream_t stream,
+                              const uint32_t *d_prof = nullptr);
+// The draw stores its result, then `seq` with a system-scope release; with
+// d_prof_out also the pick's valid index (kNoProfile without a pick).
 hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid, uint32_t profile,
                        bool mark_profile, const StepAcc *d_acc, float gamma, float w_min,
                        int block_log2, uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64,
                        const uint32_t *d_idx, DrawResult *d_res, uint64_t seq,
-                       hipStream_t stream);
+                       hipStream_t stream, const uint32_t *d_prof = nullptr,
+                       uint32_t *d_prof_out = nullptr);
 hipError_t launch_mark_one(uint32_t *d_explored, uint32_t l, uint32_t n_valid, hipStream_t stream);
 // Neighbourhood-restricted step: score the candidates (tmp arrays indexed by
 // candidate, accumulators in nb_acc), then compact, weigh and block-sum them.

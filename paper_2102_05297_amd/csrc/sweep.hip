@@ -165,10 +165,14 @@ __device__ __forceinline__ void flush_acc(uint32_t kmin, uint32_t kmax, uint32_t
 
 // Scores 4 configurations per thread over tiles of 4 * kScoreThreads
 // configurations, grid-stride, so few workgroups update the accumulators.
+// With prof_dev, the profiled configuration is read from device memory
+// (written there by the previous step's draw) instead of `profile`.
 __global__ __launch_bounds__(kScoreThreads) void score_pass(
-    const float *__restrict__ P, uint64_t stride, uint32_t profile, ActiveCounters act,
+    const float *__restrict__ P, uint64_t stride, uint32_t profile,
+    const uint32_t *__restrict__ prof_dev, ActiveCounters act,
     const uint32_t *__restrict__ explored, uint32_t n_valid, float *__restrict__ s_out,
     StepAcc *__restrict__ acc) {
+  if (prof_dev) profile = *prof_dev;
   uint32_t kmin = 0xffffffffu, kmax = 0u, cnt = 0u;
   const int n = profile < n_valid ? act.n : 0;
   const uint32_t n_tiles = (n_valid + 4u * kScoreThreads - 1) / (4u * kScoreThreads);
@@ -311,7 +315,8 @@ constexpr uint32_t kKeepWeights = 8; // weights per thread kept in registers
 template <int NT, typename W>
 __device__ void draw_body(W &wsrc, int block_log2, uint64_t *__restrict__ bsum,
                           uint32_t n_blocks, uint64_t u64, const uint32_t *__restrict__ idx,
-                          DrawResult *__restrict__ res, uint64_t seq) {
+                          DrawResult *__restrict__ res, uint64_t seq,
+                          uint32_t *__restrict__ prof_out = nullptr) {
   __shared__ uint64_t scratch[NT / kWave];
   __shared__ StepAccSums sums;
   __shared__ uint32_t found_block;
@@ -338,7 +343,10 @@ __device__ void draw_body(W &wsrc, int block_log2, uint64_t *__restrict__ bsum,
   const uint64_t pre = block_excl_scan<NT>(mine, scratch, Q); // barriers publish sums
   wsrc.stage_read(&sums);
   if (Q == 0) {
-    if (tid == 0) publish(res, kNoPick, kNoPick, 0, 0, seq);
+    if (tid == 0) {
+      if (prof_out) *prof_out = kNoProfile;
+      publish(res, kNoPick, kNoPick, 0, 0, seq);
+    }
     return;
   }
   const uint64_t r = __umul64hi(u64, Q);
@@ -408,12 +416,16 @@ __device__ void draw_body(W &wsrc, int block_log2, uint64_t *__restrict__ bsum,
       wsrc.remove(l);
       bsum[blk] -= ql;
       picked = 1;
+      if (prof_out) *prof_out = (uint32_t)wsrc.valid_of(l);
       publish(res, wsrc.valid_of(l), wsrc.raw_of(l, idx), Q, r, seq);
     }
   }
   __syncthreads();
   // no pick although Q > 0: the block sums disagree with the weights
-  if (tid == 0 && !picked) publish(res, kNoPick, kNoPick, Q, r, seq);
+  if (tid == 0 && !picked) {
+    if (prof_out) *prof_out = kNoProfile;
+    publish(res, kNoPick, kNoPick, Q, r, seq);
+  }
 }
 
 // Sum of the quantised weights of block `blk` (2^block_log2 configurations),
@@ -484,23 +496,30 @@ __device__ __forceinline__ void clear_acc(StepAcc *acc_next) {
 // One workgroup per block of 2^block_log2 configurations: block sums of q.
 __global__ __launch_bounds__(kWeightThreads) void weight_pass(
     const float *__restrict__ s, const uint32_t *__restrict__ explored, uint32_t n_valid,
-    uint32_t profile, const StepAcc *__restrict__ acc, StepAcc *__restrict__ acc_next,
-    float gamma, float w_min, int block_log2, uint64_t *__restrict__ bsum) {
+    uint32_t profile, const uint32_t *__restrict__ prof_dev, const StepAcc *__restrict__ acc,
+    StepAcc *__restrict__ acc_next, float gamma, float w_min, int block_log2,
+    uint64_t *__restrict__ bsum) {
+  if (prof_dev) profile = *prof_dev;
   if (blockIdx.x == 0) clear_acc(acc_next); // the next step's accumulators
   const uint64_t total = weight_block_sum(s, explored, n_valid, profile, acc, gamma, w_min,
                                           block_log2, blockIdx.x);
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-// One draw.  `profile` (or kNoProfile) is excluded and, when `mark_profile`,
-// marked explored once the draw is done.
+// One draw.  `profile` (or kNoProfile; read from prof_dev when given) is
+// excluded and, when `mark_profile`, marked explored once the draw is done.
+// With prof_out, the pick's valid index (kNoProfile when there is none) is
+// also stored there for the next step.
 __global__ __launch_bounds__(kDrawThreads) void draw_scores(
     const float *__restrict__ s, uint32_t *__restrict__ explored, uint32_t n_valid,
-    uint32_t profile, int mark_profile, const StepAcc *__restrict__ acc, float gamma,
-    float w_min, int block_log2, uint64_t *__restrict__ bsum, uint32_t n_blocks, uint64_t u64,
-    const uint32_t *__restrict__ idx, DrawResult *__restrict__ res, uint64_t seq) {
+    uint32_t profile, const uint32_t *__restrict__ prof_dev, int mark_profile,
+    const StepAcc *__restrict__ acc, float gamma, float w_min, int block_log2,
+    uint64_t *__restrict__ bsum, uint32_t n_blocks, uint64_t u64,
+    const uint32_t *__restrict__ idx, DrawResult *__restrict__ res, uint64_t seq,
+    uint32_t *__restrict__ prof_out) {
+  if (prof_dev) profile = *prof_dev;
   ScoreWeights w{s, explored, n_valid, profile, acc, gamma, w_min};
-  draw_body<kDrawThreads>(w, block_log2, bsum, n_blocks, u64, idx, res, seq);
+  draw_body<kDrawThreads>(w, block_log2, bsum, n_blocks, u64, idx, res, seq, prof_out);
   __syncthreads();
   if (threadIdx.x == 0 && mark_profile && profile < n_valid)
     atomicOr(&explored[profile >> 5], 1u << (profile & 31u));
@@ -786,22 +805,24 @@ hipError_t launch_reset_acc(StepAcc *d_acc, int n, hipStream_t stream) {
 
 hipError_t launch_score_pass(const float *d_P, uint64_t stride, uint32_t profile,
                              const ActiveCounters &act, const uint32_t *d_explored,
-                             uint32_t n_valid, float *d_s, StepAcc *d_acc, hipStream_t stream) {
+                             uint32_t n_valid, float *d_s, StepAcc *d_acc, hipStream_t stream,
+                             const uint32_t *d_prof) {
   const uint32_t n_tiles = (n_valid + 4u * kScoreThreads - 1) / (4u * kScoreThreads);
   const uint32_t grid = std::min<uint32_t>(n_tiles, kScoreGrid);
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL(score_pass, dim3(grid), dim3(kScoreThreads), 0, stream, d_P, stride, profile,
-                     act, d_explored, n_valid, d_s, d_acc);
+                     d_prof, act, d_explored, n_valid, d_s, d_acc);
   return hipGetLastError();
 }
 
 hipError_t launch_weight_pass(const float *d_s, const uint32_t *d_explored, uint32_t n_valid,
                               uint32_t profile, const StepAcc *d_acc, StepAcc *d_acc_next,
                               float gamma, float w_min, int block_log2, uint64_t *d_bsum,
-                              uint32_t n_blocks, hipStream_t stream) {
+                              uint32_t n_blocks, hipStream_t stream, const uint32_t *d_prof) {
   if (n_blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(weight_pass, dim3(n_blocks), dim3(kWeightThreads), 0, stream, d_s, d_explored,
-                     n_valid, profile, d_acc, d_acc_next, gamma, w_min, block_log2, d_bsum);
+                     n_valid, profile, d_prof, d_acc, d_acc_next, gamma, w_min, block_log2,
+                     d_bsum);
   return hipGetLastError();
 }
 
@@ -809,10 +830,10 @@ hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
                        bool mark_profile, const StepAcc *d_acc, float gamma, float w_min,
                        int block_log2, uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64,
                        const uint32_t *d_idx, DrawResult *d_res, uint64_t seq,
-                       hipStream_t stream) {
+                       hipStream_t stream, const uint32_t *d_prof, uint32_t *d_prof_out) {
   hipLaunchKernelGGL(draw_scores, dim3(1), dim3(kDrawThreads), 0, stream, d_s, d_explored, n_valid,
-                     profile, mark_profile ? 1 : 0, d_acc, gamma, w_min, block_log2, d_bsum,
-                     n_blocks, u64, d_idx, d_res, seq);
+                     profile, d_prof, mark_profile ? 1 : 0, d_acc, gamma, w_min, block_log2,
+                     d_bsum, n_blocks, u64, d_idx, d_res, seq, d_prof_out);
   return hipGetLastError();
 }
 
