@@ -838,7 +838,7 @@ def main() -> int:
     n_blocks = (n_valid + blk - 1) // blk
     bytes_weight = n_valid * (4 + 0.125) + 8 * n_blocks
     bytes_draw = 8 * n_blocks + blk * (4 + 0.125)
-    step_bytes = bytes_score / len(timed) + bytes_weight + bytes_draw
+    step_bytes = bytes_score / max(1, len(timed)) + bytes_weight + bytes_draw
     step_us = sum(ms[k] / max(1, launches[k]) for k in range(3)) * 1e3
     step_achieved = step_bytes / (step_us / 1e6) / 1e9 if step_us > 0 else 0.0
 
@@ -928,7 +928,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": bytes_score / len(timed),
+            "algorithmic_bytes_per_launch": bytes_score / max(1, len(timed)),
             "launches": int(launches[0]),
             "avg_us": ms[0] / max(1, launches[0]) * 1e3,
             "timing": "HIP events around every %d-th scored step's kernels" % TIMING_PERIOD,

@@ -7,7 +7,9 @@ the decision trees.  Everything is plain float64 NumPy:
   features   x_j = digit_j / 8 (digit = index of parameter j's value)
   layers     z1 = W1 x + b1, h1 = gelu(z1); z2 = W2 h1 + b2, h2 = gelu(z2);
              y = W3 h2 + b3
-  gelu       0.5 z (1 + erf(z / sqrt 2))                  (exact form)
+  gelu       z Phi(z) = 0.5 z erfc(-z / sqrt 2)           (exact form; the
+             erfc spelling of 0.5 z (1 + erf(z / sqrt 2)) keeps its
+             relative accuracy for z << 0, where 1 + erf cancels)
   loss       mean over batch and counters of (y - target)^2
   backward   hand-written chain rule (no autodiff)
   optimiser  Adam (Kingma & Ba, "Adam: a method for stochastic optimization",
@@ -24,7 +26,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
-from scipy.special import erf
+from scipy.special import erfc
 
 SQRT2 = math.sqrt(2.0)
 INV_SQRT_2PI = 1.0 / math.sqrt(2.0 * math.pi)
@@ -35,12 +37,12 @@ def features(digits: np.ndarray) -> np.ndarray:
 
 
 def gelu(z):
-    return 0.5 * z * (1.0 + erf(z / SQRT2))
+    return 0.5 * z * erfc(-z / SQRT2)
 
 
 def gelu_grad(z):
     """d/dz gelu(z) = Phi(z) + z phi(z)."""
-    return 0.5 * (1.0 + erf(z / SQRT2)) + z * INV_SQRT_2PI * np.exp(-0.5 * z * z)
+    return 0.5 * erfc(-z / SQRT2) + z * INV_SQRT_2PI * np.exp(-0.5 * z * z)
 
 
 def bf16(x) -> np.ndarray:
@@ -77,29 +79,34 @@ def forward_bf16(params, X, round_activations: bool = True):
 
 # ------------------------------------------------ bounds of a device forward
 # A forward pass with the device's precision choices (bf16 weights, inputs and
-# hidden activations, biases in float32, products summed in float32, GELU by
-# a published erfc approximation) differs from forward_bf16 by:
+# hidden activations, biases in float32, products summed in float32, GELU's
+# tail by the exponential of a fitted polynomial) differs from forward_bf16 by:
 #   * summation: any order of K float32 additions (round to nearest, or any
 #     rounding of at most one float32 ulp) errs by at most
 #     (K + 1) 2^-23 (sum |w x| + |b|), plus 2^-126 per product for a
 #     flushed subnormal;
-#   * GELU: max(z, 0) - |z| Phi(-|z|) with erfc by Abramowitz & Stegun
-#     7.1.26 (|error| <= 1.5e-7), so |z| Phi(-|z|) errs by 0.75e-7 |z|; the
-#     float32 evaluation of the tail term (reciprocal, exp2 of a rounded
-#     argument, polynomial, products) by (16 + z^2) 2^-24 relative, at most
-#     2^-24 * 3 absolute since (16 + z^2) |z| Phi(-|z|) <= 2.9; the final
-#     rounding by 2^-24 |gelu(z)|; doubled for safety;
+#   * GELU: max(z, 0) - |z| Phi(-|z|) with Phi(-x) taken as 2^p(min(x, 9)),
+#     p within TAIL_LOG2_ERR of log2 Phi(-x) on [0, 9] in its float32
+#     evaluation, and an exponential within one float32 ulp: the tail term
+#     errs by at most rho = 2^TAIL_LOG2_ERR - 1 + 2^-22 of itself for
+#     |z| <= 9 and by at most 2 (1 + rho) |z| Phi(-9) beyond; one final
+#     rounding (2^-24 |gelu(z)|); doubled for safety;
 #   * bf16 rounding of an activation: the device rounds its float32 GELU
 #     value, which lies within the two bounds above of the exact GELU of the
 #     exact pre-activation; rounding is monotone, so the device's bf16 value
 #     lies between the roundings of the interval's ends, and equals the
 #     oracle's whenever no rounding boundary falls inside the interval.
+TAIL_LOG2_ERR = 1.15e-4
+_RHO = 2.0 ** TAIL_LOG2_ERR - 1.0 + 2.0 ** -22
+_PHI9 = 0.5 * math.erfc(9.0 / SQRT2)
+
+
 def gelu_error_bound(z):
     """Bound of |device GELU(z) - gelu(z)| for float32 evaluation (above)."""
     az = np.abs(z)
-    tail = np.minimum(0.5 * az, 0.2)
-    return 2.0 * (0.75e-7 * az + 2.0 ** -24 * (16.0 + z * z) * tail
-                  + 2.0 ** -24 * np.abs(gelu(z))) + 1e-30
+    tail = az * 0.5 * erfc(az / SQRT2)
+    t = np.where(az <= 9.0, _RHO * tail, 2.0 * (1.0 + _RHO) * az * _PHI9)
+    return 2.0 * (t + 2.0 ** -24 * np.abs(gelu(z))) + 1e-30
 
 
 def _sum_bound(absW, absA, absb, K):

@@ -304,7 +304,8 @@ hipError_t launch_forest_eval(const SpaceDev *d_space, const uint32_t *d_idx, ui
   if (count == 0) return hipSuccess;
   const uint32_t n_int = (1u << depth) - 1u;
   const size_t res_lds = (size_t)n_trees * n_int * sizeof(uint16_t);
-  if (n_trees <= kResidentTrees && res_lds <= kResidentLds) {
+  const bool resident = n_trees <= kResidentTrees && res_lds <= kResidentLds;
+  if (resident) {
     // as many workgroups as fit on the device at once (LDS-bound), at most
     // one per tile
     int dev = 0, n_cu = 256;

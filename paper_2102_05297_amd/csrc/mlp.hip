@@ -15,8 +15,10 @@
 //   W2p[r][s][lane][j] = W2[32r + lane%32][kperm(s, lane/32, j)]
 //   W3p[r][s][lane][j] = W3[32r + lane%32][kperm(s, lane/32, j)]
 //   kperm(s, h, j) = 32(s/2) + 16(s%2) + 8(j/4) + 4h + (j%4)
-// GELU uses erf from Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7), far
-// below the bf16 rounding of the activations.
+// GELU's tail Phi(-|z|) is the exponential of a polynomial (gelu.h), within
+// 2^-13.6 of itself: far below the bf16 rounding of the activations.  The
+// backward pass's GELU derivative uses erf from Abramowitz & Stegun 7.1.26
+// (|error| <= 1.5e-7).
 //
 // Training runs the forward pass as one GEMM per layer (gemm_bf16 with the
 // bias and GELU in its epilogue, 32 x 32 output tiles, so a batch of a few
@@ -25,6 +27,7 @@
 #include <algorithm>
 
 #include "device_common.h"
+#include "gelu.h"
 #include "models.h"
 
 namespace cgs {
@@ -51,18 +54,12 @@ __device__ __forceinline__ void normal_cdf_pdf(float z, float &cdf, float &pdf) 
   cdf = 0.5f * (1.0f + (z >= 0.0f ? erf_abs : -erf_abs));
   pdf = e * 0.3989422804014327f;
 }
-// GELU(z) = z Phi(z) = max(z, 0) - |z| Phi(-|z|), where 2 Phi(-|z|) =
-// erfc(|z| / sqrt 2) = t P(t) exp(-z^2 / 2) with t = 1 / (1 + p |z| / sqrt 2)
-// (A&S 7.1.26; the coefficients below are P's halved).  The tail term is
-// formed directly, so negative z lose nothing to cancellation.
+// GELU(z) = max(z, 0) - |z| Phi(-|z|) with Phi(-x) = 2^p(min(x, 9)) (gelu.h):
+// nine VALU operations and one exponential.
 __device__ __forceinline__ float gelu(float z) {
   const float az = fabsf(z);
-  const float t = __builtin_amdgcn_rcpf(fmaf(az, 0.3275911f * 0.70710678118654752f, 1.0f));
-  const float e = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f); // exp(-z^2 / 2)
-  const float poly =
-      0.127414796f +
-      t * (-0.142248368f + t * (0.7107068705f + t * (-0.7265760135f + t * 0.5307027145f)));
-  return fmaf(-(az * e) * t, poly, fmaxf(z, 0.0f));
+  const float e = __builtin_amdgcn_exp2f(gelu_tail_log2(fminf(az, kGeluTailMax)));
+  return fmaf(-az, e, fmaxf(z, 0.0f));
 }
 __device__ __forceinline__ float gelu_grad(float z) {
   float c, p;
@@ -107,17 +104,31 @@ __device__ __forceinline__ void infer_features(const MlpFwdArgs &a, uint32_t fir
   }
 }
 
-// Bias + GELU of one 32x32 accumulator block, as the two bf16 B fragments of
-// the next layer's K steps 2r and 2r + 1; `b` points at bias[32 r + 4 hh].
-// LOWREG: four values at a time (fewer live temporaries).
-template <bool LOWREG = false>
-__device__ __forceinline__ void gelu_frags(const f32x16 &acc, const float *b, bf16x8 &f0,
-                                           bf16x8 &f1) {
+// The bias of one 32x32 accumulator block in the accumulator's layout (lane
+// l, register i: row 8(i/4) + 4(l/32) + i%4); `b` points at
+// bias[32 r + 4 hh].  Accumulating onto it adds the bias without a VALU
+// operation per value.
+__device__ __forceinline__ f32x16 bias_acc(const float *b) {
+  f32x16 acc;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const float4 bb = *reinterpret_cast<const float4 *>(b + 8 * q);
-    const float z[4] = {acc[4 * q] + bb.x, acc[4 * q + 1] + bb.y, acc[4 * q + 2] + bb.z,
-                        acc[4 * q + 3] + bb.w};
+    acc[4 * q] = bb.x;
+    acc[4 * q + 1] = bb.y;
+    acc[4 * q + 2] = bb.z;
+    acc[4 * q + 3] = bb.w;
+  }
+  return acc;
+}
+
+// GELU of one 32x32 accumulator block (bias included), as the two bf16 B
+// fragments of the next layer's K steps 2r and 2r + 1.  LOWREG: four values
+// at a time (fewer live temporaries).
+template <bool LOWREG = false>
+__device__ __forceinline__ void gelu_frags(const f32x16 &acc, bf16x8 &f0, bf16x8 &f1) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float z[4] = {acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const __bf16 v = (__bf16)gelu(z[t]);
@@ -130,8 +141,7 @@ __device__ __forceinline__ void gelu_frags(const f32x16 &acc, const float *b, bf
 
 template <int T, int NB3>
 __device__ __forceinline__ void infer_store(const MlpFwdArgs &a, const f32x16 (&accy)[NB3][T],
-                                            const float *b3, uint32_t first, int hh, int col,
-                                            const bool (&ok)[T]) {
+                                            uint32_t first, int hh, int col, const bool (&ok)[T]) {
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     if (!ok[t]) continue;
@@ -143,7 +153,7 @@ __device__ __forceinline__ void infer_store(const MlpFwdArgs &a, const f32x16 (&
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int c = 32 * r3 + 8 * q + 4 * hh + u;
-          if (c < a.C) a.P[(size_t)c * a.stride + i] = fmaxf(accy[r3][t][4 * q + u] + b3[c], 0.0f);
+          if (c < a.C) a.P[(size_t)c * a.stride + i] = fmaxf(accy[r3][t][4 * q + u], 0.0f);
         }
   }
 }
@@ -188,20 +198,20 @@ __device__ __forceinline__ void infer_layer1(const bf16x8 *w1, const float *bias
     for (int s = 0; s < S1; ++s) wf[s] = w1[(r * S1 + s) * 64 + lane];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      f32x16 acc = {};
+      f32x16 acc = bias_acc(bias + 32 * r + 4 * hh);
 #pragma unroll
       for (int s = 0; s < S1; ++s) acc = mfma(wf[s], xb[t][s], acc);
-      gelu_frags(acc, bias + 32 * r + 4 * hh, h1[2 * r][t], h1[2 * r + 1][t]);
+      gelu_frags(acc, h1[2 * r][t], h1[2 * r + 1][t]);
     }
     __builtin_amdgcn_sched_barrier(0); // one block's temporaries live at a time
   }
 }
 
-// Epilogue of layer-2 block r: bias + GELU, then its two K steps of layer 3.
+// Epilogue of layer-2 block r (bias included): GELU, then its two K steps
+// of layer 3.
 template <int H, int T, int NB3, bool LOWREG = false>
 __device__ __forceinline__ void infer_block_out(const f32x16 (&acc)[T], int r, const bf16x8 *w3,
-                                                const float *bias, int lane, int hh,
-                                                f32x16 (&accy)[NB3][T]) {
+                                                int lane, f32x16 (&accy)[NB3][T]) {
   constexpr int S2 = H / 16;
   bf16x8 w3f[NB3][2];
 #pragma unroll
@@ -211,7 +221,7 @@ __device__ __forceinline__ void infer_block_out(const f32x16 (&acc)[T], int r, c
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     bf16x8 f0, f1;
-    gelu_frags<LOWREG>(acc[t], bias + H + 32 * r + 4 * hh, f0, f1);
+    gelu_frags<LOWREG>(acc[t], f0, f1);
 #pragma unroll
     for (int r3 = 0; r3 < NB3; ++r3) {
       accy[r3][t] = mfma(w3f[r3][0], f0, accy[r3][t]);
@@ -269,7 +279,7 @@ mlp_infer(
 #pragma unroll
     for (int r3 = 0; r3 < NB3; ++r3)
 #pragma unroll
-      for (int t = 0; t < T; ++t) accy[r3][t] = f32x16{};
+      for (int t = 0; t < T; ++t) accy[r3][t] = bias_acc(bias + 2 * H + 32 * r3 + 4 * hh);
     if (!RESIDENT) __syncthreads(); // block 0 in the first buffer
     // with two waves per SIMD the other wave's MFMAs cover this one's epilogue
 #pragma unroll 1
@@ -283,7 +293,7 @@ mlp_infer(
       }
       f32x16 acc[T];
 #pragma unroll
-      for (int t = 0; t < T; ++t) acc[t] = f32x16{};
+      for (int t = 0; t < T; ++t) acc[t] = bias_acc(bias + H + 32 * r + 4 * hh);
 #pragma unroll
       for (int ks = 0; ks < S2; ++ks) {
         const bf16x8 wf = wr[ks * 64 + lane];
@@ -292,14 +302,14 @@ mlp_infer(
         // at most four fragments in flight ahead of their MFMAs
         if (ks % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       }
-      infer_block_out<H, T, NB3, true>(acc, r, w3, bias, lane, hh, accy);
+      infer_block_out<H, T, NB3, true>(acc, r, w3, lane, accy);
       if (more) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) w2[((r + 1) & 1) * NBLK + u * NT + tid] = st[u];
       }
       if (!RESIDENT) __syncthreads();
     }
-    infer_store<T, NB3>(a, accy, bias + 2 * H, first, hh, col, ok);
+    infer_store<T, NB3>(a, accy, first, hh, col, ok);
   }
 }
 

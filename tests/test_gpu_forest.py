@@ -55,7 +55,8 @@ def test_c1_forest_full():
 
 
 @pytest.mark.parametrize("T,D,C", [(1, 0, 3), (3, 1, 5), (4, 7, 12), (64, 4, 2), (2, 14, 7),
-                                   (5, 9, 64)])
+                                   (5, 9, 64), (1, 0, 12), (8, 10, 16), (12, 6, 32), (16, 12, 24),
+                                   (3, 5, 24), (16, 8, 32), (2, 11, 16), (7, 9, 12)])
 def test_shapes_on_c1_space(T, D, C):
     spec = synth.space_c1()
     _check_full(spec, synth.random_forest(synth.rng(50, T, D, C), spec.radix, T, D, C))
