@@ -74,7 +74,7 @@ def run_search(cgs, sp, model, U, pcs, eps, n_steps, timing):
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "score_pass_c2_traffic.md")
 VALU_PROFILE = os.path.join(ROOT, "profiles", "mlp_infer_valu.md")
 SWEEP_SOURCES = ("sweep.hip", "device_common.h", "internal.h")
-MLP_SOURCES = ("mlp.hip", "device_common.h", "internal.h")
+MLP_SOURCES = ("mlp.hip", "gelu.h", "device_common.h", "internal.h")
 # VALU issue peak with packed FP32 off: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
