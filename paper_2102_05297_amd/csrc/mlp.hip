@@ -347,9 +347,22 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const float *p) {
 // tile).  bias[N] for 2, 3, 4.
 // Output tile `tile` (row-major over 32 x 32 tiles) by one workgroup of
 // kGemmThreads; shared by the plain launch and the grouped backward launch.
-template <typename TA, typename TB, int EPI>
+// The first layer's A operand straight from the configurations: row m is
+// configuration cfg_raw[batch[m]] (cfg_raw[m] without a batch), column k its
+// parameter k's digit / 8 (0 past F); the workgroups of the first column of
+// output tiles also store the rows as bf16 into xout[m][K1] for the
+// backward pass.
+struct FeatArgs {
+  const SpaceDev *sp;
+  const uint32_t *cfg_raw;
+  const int32_t *batch;
+  int F, K1;
+  __bf16 *xout;
+};
+
+template <typename TA, typename TB, int EPI, bool FEAT = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const float *bias, const LossArgs &la,
-                                          int tile) {
+                                          int tile, const FeatArgs &fa = FeatArgs{}) {
   constexpr int NW = kGemmThreads / 64;
   __shared__ float part[NW - 1][16][64];
   const TA *A = static_cast<const TA *>(g.A);
@@ -365,11 +378,25 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const float *bias, 
       g.a_sk == 1 && g.a_sm % 8 == 0 && (reinterpret_cast<uintptr_t>(A) & 15u) == 0;
   const bool b_vec =
       g.b_sk == 1 && g.b_sn % 8 == 0 && (reinterpret_cast<uintptr_t>(B) & 15u) == 0;
+  uint64_t dlo = 0, dhi = 0; // FEAT: the digits of row m's configuration
+  if (FEAT && m < g.M && 16 * w < g.K) {
+    const uint32_t src = fa.batch ? (uint32_t)fa.batch[m] : (uint32_t)m;
+    decode_packed(fa.cfg_raw[src], fa.sp, dlo, dhi);
+  }
   for (int k0 = 16 * w; k0 < g.K; k0 += 16 * NW) {
     bf16x8 af, bf;
     const int kf = k0 + 8 * hh; // first k of this lane's fragment
     const bool full = kf + 8 <= g.K;
-    if (a_vec && full && m < g.M) {
+    if (FEAT) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = kf + j;
+        af[j] = (__bf16)((m < g.M && k < fa.F) ? (float)digit_of(dlo, dhi, (uint32_t)k) * 0.125f
+                                               : 0.0f);
+      }
+      if (n0 == 0 && m < g.M && kf < fa.K1)
+        *reinterpret_cast<bf16x8 *>(fa.xout + (size_t)m * fa.K1 + kf) = af;
+    } else if (a_vec && full && m < g.M) {
       af = load_bf16x8(A + (size_t)m * g.a_sm + kf);
     } else {
 #pragma unroll
@@ -453,6 +480,13 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const floa
   gemm_tile<TA, TB, EPI>(g, bias, la, blockIdx.x);
 }
 
+// The first hidden layer with its inputs decoded in the operand load
+// (FeatArgs): Z1 = X W1^T + b1, H1 = gelu(Z1), X stored on the side.
+__global__ __launch_bounds__(kGemmThreads) void gemm_layer1(GemmArgs g, const float *bias,
+                                                            FeatArgs fa) {
+  gemm_tile<__bf16, float, 2, true>(g, bias, LossArgs{}, blockIdx.x, fa);
+}
+
 // Column sums of src[nrows][ld] over columns [64 b, 64 b + 64) of ncols by
 // one workgroup: lanes take columns (coalesced rows), the waves split the
 // rows and meet in LDS, added in wave order.  Block 0 also forms the loss
@@ -505,21 +539,6 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bwd_group(GemmArgs g0, int 
     return;
   }
   colsum_block(cs, b - t1);
-}
-
-// Training features: X[i][k] = digit_k / 8 of configuration cfg_raw[batch[i]]
-// (bf16, K1 columns, zero past F), the inputs of the fused forward.
-__global__ __launch_bounds__(256) void mlp_features(const SpaceDev *__restrict__ sp,
-                                                    const uint32_t *__restrict__ cfg_raw,
-                                                    const int32_t *__restrict__ batch, uint32_t n,
-                                                    int F, int K1, __bf16 *__restrict__ x) {
-  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  uint64_t lo, hi;
-  decode_packed(cfg_raw[batch ? (uint32_t)batch[i] : i], sp, lo, hi);
-  for (int k = 0; k < K1; ++k)
-    x[(size_t)i * K1 + k] =
-        (__bf16)(k < F ? (float)digit_of(lo, hi, (uint32_t)k) * 0.125f : 0.0f);
 }
 
 // ------------------------------------------------------ loss, biases, Adam
@@ -729,8 +748,6 @@ hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const 
                                    const float *w3, const LossArgs *loss, hipStream_t stream) {
   if (a.n == 0) return hipSuccess;
   const int Cp = 32 * ((a.C + 31) / 32);
-  hipLaunchKernelGGL(mlp_features, dim3((a.n + 255) / 256), dim3(256), 0, stream, a.sp,
-                     a.cfg_raw, a.batch, a.n, a.F, a.K1, a.xout);
   auto gemm = [&](const GemmArgs &g, const float *bias, int epi) {
     const dim3 grid(((g.M + 31) / 32) * ((g.N + 31) / 32)), block(kGemmThreads);
     if (epi == 2)
@@ -744,8 +761,14 @@ hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const 
   };
   // Z1 = X W1^T + b1, H1 = gelu(Z1); Z2 = H1 W2^T + b2, H2 = gelu(Z2); Y = H2 W3^T + b3
   const int n = (int)a.n;
-  gemm(GemmArgs{n, a.H, a.F, a.xout, a.K1, 1, w1, 1, a.F, a.z1out, a.h1out, nullptr, a.H}, a.b1,
-       2);
+  {
+    // layer 1 decodes its inputs (the digits of the batch's configurations)
+    // in the operand load and stores them as X for the backward pass
+    const GemmArgs g1{n, a.H, a.F, nullptr, a.K1, 1, w1, 1, a.F, a.z1out, a.h1out, nullptr, a.H};
+    const dim3 grid(((g1.M + 31) / 32) * ((g1.N + 31) / 32)), block(kGemmThreads);
+    hipLaunchKernelGGL(gemm_layer1, grid, block, 0, stream, g1, a.b1,
+                       FeatArgs{a.sp, a.cfg_raw, a.batch, a.F, a.K1, a.xout});
+  }
   gemm(GemmArgs{n, a.H, a.H, a.h1out, a.H, 1, w2, 1, a.H, a.z2out, a.h2out, nullptr, a.H}, a.b2,
        2);
   gemm(GemmArgs{n, a.C, a.H, a.h2out, a.H, 1, w3, 1, a.H, a.yout, nullptr, nullptr, Cp}, a.b3, 3);
