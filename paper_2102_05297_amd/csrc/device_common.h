@@ -105,6 +105,7 @@ __device__ __forceinline__ float key_float(uint32_t k) {
 struct StepNorm {
   StepDivisor pos, neg; // s_max and -s_min
   bool fast;            // both divisors in the fast path's range
+  bool wide;            // fast, and both divisors >= kWideDivisorMin
   float gamma, w_min;
 };
 // The reciprocals are made opaque to the optimiser: it would otherwise
@@ -116,8 +117,9 @@ __device__ __forceinline__ float opaque(float x) {
 }
 __device__ __forceinline__ StepNorm step_norm(float s_min, float s_max, float gamma, float w_min) {
   StepNorm nm{step_divisor(s_max > 0.0f ? s_max : 1.0f),
-              step_divisor(s_min < 0.0f ? -s_min : 1.0f), false, gamma, w_min};
+              step_divisor(s_min < 0.0f ? -s_min : 1.0f), false, false, gamma, w_min};
   nm.fast = nm.pos.fast && nm.neg.fast;
+  nm.wide = nm.fast && nm.pos.d >= kWideDivisorMin && nm.neg.d >= kWideDivisorMin;
   nm.pos.r = opaque(nm.pos.r);
   nm.neg.r = opaque(nm.neg.r);
   return nm;
@@ -136,12 +138,18 @@ __device__ __forceinline__ StepNorm step_norm(float s_min, float s_max, float ga
 // reciprocal (stepdiv.h) wherever the fast path's operand range holds (the
 // divisors are checked once per step; |s| <= D for every unexplored
 // configuration, so only a non-zero |s| below 2^-60 leaves it) and the IEEE
-// division otherwise.
-__device__ __forceinline__ uint32_t quantized_weight(float s, bool explored, const StepNorm &nm) {
+// division otherwise.  When the step's divisors are both at least
+// kWideDivisorMin (nm.wide, kWide = true) no score needs the division: below
+// the range only 1 + s / D = 1 matters, which the sequence also gives
+// (stepdiv.h), so the per-configuration range check goes too.
+template <bool kWide>
+__device__ __forceinline__ uint32_t quantized_weight_t(float s, bool explored, const StepNorm &nm) {
   const bool pos = s > 0.0f;
   const float d = pos ? nm.pos.d : nm.neg.d;
   float t;
-  if (nm.fast) {
+  if (kWide) {
+    t = div_fast_core(s, d, pos ? nm.pos.r : nm.neg.r);
+  } else if (nm.fast) {
     t = div_fast_core(s, d, pos ? nm.pos.r : nm.neg.r); // +-0 for s == 0
     const uint32_t ab = __float_as_uint(s) & 0x7fffffffu;
     const bool slow = !explored && ab - 1u < 0x217fffffu; // 0 < |s| < 2^-60
@@ -155,6 +163,10 @@ __device__ __forceinline__ uint32_t quantized_weight(float s, bool explored, con
   const float y8 = y4 * y4;
   const float w = s > nm.gamma ? fmaxf(nm.w_min, y8) : nm.w_min;
   return explored ? 0u : (uint32_t)rintf(w * 8388608.0f);
+}
+__device__ __forceinline__ uint32_t quantized_weight(float s, bool explored, const StepNorm &nm) {
+  return nm.wide ? quantized_weight_t<true>(s, explored, nm)
+                 : quantized_weight_t<false>(s, explored, nm);
 }
 
 __device__ __forceinline__ bool explored_bit(const uint32_t *__restrict__ ex, uint32_t l) {

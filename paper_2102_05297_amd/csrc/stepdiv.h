@@ -54,6 +54,14 @@ __host__ __device__ __forceinline__ float div_fast_core(float s, float d, float 
   return fmaf(e1, r, q1);
 }
 
+// A pass whose divisor is at least 2^-34 (and in the fast range) may also
+// send numerators below the range, 0 < |s| < 2^-60, through the correction
+// sequence when only 1 + s / d is wanted: |s / d| < 2^-26, the sequence's
+// result (its intermediates may be subnormal, or flushed) stays below 2^-25
+// in magnitude as well, and 1 + t rounds to 1 for either value.  Checked on
+// the host for subnormal and tiny numerators (tests/stepdiv_check.cpp).
+constexpr float kWideDivisorMin = 0x1p-34f;
+
 // s / d through r = RN(1 / d); equal to the IEEE quotient whenever
 // div_fast_ok(s, step_divisor(d).fast).
 __host__ __device__ __forceinline__ float div_fast(float s, float d, float r) {

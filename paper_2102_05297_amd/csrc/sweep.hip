@@ -35,6 +35,7 @@
 // host polls.  Every phase issues all of its loads before the first use, so
 // a draw costs about four dependent memory round trips.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -463,25 +464,31 @@ __device__ __forceinline__ uint64_t weight_block_sum(const float *__restrict__ s
   reduce_slot_values(slot, &sums);
   __syncthreads();
   const StepNorm nm = step_norm(key_float(sums.min_key), key_float(sums.max_key), gamma, w_min);
-  uint64_t sum = 0;
-  for (uint32_t r0 = base;;) {
+  // the choice of division path is made once per block, outside the loop
+  auto weigh = [&](auto wide) {
+    uint64_t sum = 0;
+    for (uint32_t r0 = base;;) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      // no per-configuration branches: positions past the end (and the
-      // profiled configuration) count as explored and weigh 0
-      const uint32_t l0 = r0 + 4u * (threadIdx.x + k * kWeightThreads);
-      uint32_t ex4 = (ex[k] >> (l0 & 31u)) & 0xfu;
-      const uint32_t tail = end - l0;
-      if (tail < 4u) ex4 |= (0xfu << tail) & 0xfu;
-      if (profile - l0 < 4u) ex4 |= 1u << (profile - l0);
-      const float ss[4] = {sv[k].x, sv[k].y, sv[k].z, sv[k].w};
+      for (int k = 0; k < 4; ++k) {
+        // no per-configuration branches: positions past the end (and the
+        // profiled configuration) count as explored and weigh 0
+        const uint32_t l0 = r0 + 4u * (threadIdx.x + k * kWeightThreads);
+        uint32_t ex4 = (ex[k] >> (l0 & 31u)) & 0xfu;
+        const uint32_t tail = end - l0;
+        if (tail < 4u) ex4 |= (0xfu << tail) & 0xfu;
+        if (profile - l0 < 4u) ex4 |= 1u << (profile - l0);
+        const float ss[4] = {sv[k].x, sv[k].y, sv[k].z, sv[k].w};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) sum += quantized_weight(ss[e], (ex4 >> e) & 1u, nm);
+        for (int e = 0; e < 4; ++e)
+          sum += quantized_weight_t<decltype(wide)::value>(ss[e], (ex4 >> e) & 1u, nm);
+      }
+      r0 += kRound;
+      if (r0 >= end) break;
+      load_round(r0);
     }
-    r0 += kRound;
-    if (r0 >= end) break;
-    load_round(r0);
-  }
+    return sum;
+  };
+  const uint64_t sum = nm.wide ? weigh(std::true_type{}) : weigh(std::false_type{});
   return block_sum<kWeightThreads>(sum, scratch); // its barriers also retire `sums`
 }
 

@@ -3,7 +3,9 @@
 // significands while every intermediate is normal, so numerators run over
 // every significand in [1, 2) (both signs, one exponent step either way)
 // for each divisor significand given; plus operands outside the fast range,
-// zeros and non-finite values.  Prints the number of mismatches.
+// zeros and non-finite values; and 1 + s / d for numerators below the range
+// with divisors of at least kWideDivisorMin.  Prints the number of
+// mismatches.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -71,6 +73,37 @@ int main(int argc, char **argv) {
         std::printf("special mismatch s=%a d=%a\n", s, d);
       }
     }
+  // numerators below the fast range with a divisor of at least
+  // kWideDivisorMin: 1 + (the sequence's result) must equal 1 + s / d (both
+  // 1).  Every 61st float below 2^-60 (subnormals included), both signs.
+  {
+    std::vector<float> wd;
+    for (float d : {cgs::kWideDivisorMin, 0x1.fffffep-34f, 0x1.000002p-34f, 0x1.8p-20f, 1.0f,
+                    0x1.fffffep0f, 3.0f, 0x1p40f, 0x1.fffffep59f, 0x1p60f})
+      wd.push_back(d);
+    for (int i = 0; i < 22; ++i)
+      wd.push_back(std::ldexp(from_bits(0x3f800000u | (uint32_t)(g() & 0x7fffffu)),
+                              (int)(g() % 94) - 34));
+    std::vector<long> badw(nt, 0);
+    std::vector<std::thread> tw;
+    const uint32_t top = bits(0x1p-60f);
+    for (unsigned t = 0; t < nt; ++t)
+      tw.emplace_back([&, t] {
+        for (size_t i = 0; i < wd.size(); ++i) {
+          const cgs::StepDivisor v = cgs::step_divisor(wd[i]);
+          for (uint32_t b = 1 + 61 * t; b < top; b += 61 * nt)
+            for (int sg = 0; sg < 2; ++sg) {
+              const float s = sg ? -from_bits(b) : from_bits(b);
+              if (!same(1.0f + cgs::div_fast_core(s, v.d, v.r), 1.0f + s / v.d)) ++badw[t];
+            }
+        }
+      });
+    for (auto &x : tw) x.join();
+    long nw = 0;
+    for (long b : badw) nw += b;
+    std::printf("tiny numerators: divisors %zu mismatches %ld\n", wd.size(), nw);
+    total += nw;
+  }
   std::printf("divisors %zu mismatches %ld\n", divs.size(), total);
   return total != 0;
 }
