@@ -100,12 +100,18 @@ struct cgs_model_s {
   size_t n_w1p = 0, n_w2p = 0, n_w3p = 0;
   uint64_t adam_t = 0;
   int n_cu = 256;
-  // training activations for up to scratch_rows rows
+  // training step buffers for batches of up to scratch_rows rows: the
+  // weight gradients' operands [feature][rows rounded up to 32] (bf16), the
+  // per-block column sums and squared errors, and Y of the forward pass
   uint32_t scratch_rows = 0;
-  __bf16 *d_x = nullptr, *d_h1 = nullptr, *d_h2 = nullptr, *d_dyb = nullptr, *d_dz1b = nullptr,
-         *d_dz2b = nullptr;
-  float *d_z1 = nullptr, *d_z2 = nullptr, *d_y = nullptr, *d_dyf = nullptr, *d_dz1f = nullptr,
-        *d_dz2f = nullptr, *d_loss_part = nullptr;
+  __bf16 *d_xt = nullptr, *d_h1t = nullptr, *d_h2t = nullptr, *d_dyt = nullptr,
+         *d_dz2t = nullptr, *d_dz1t = nullptr;
+  float *d_bp1 = nullptr, *d_bp2 = nullptr, *d_bp3 = nullptr, *d_lossp = nullptr,
+        *d_y = nullptr;
+  // gathered features [kGatherSteps][rows rounded up to 32][K1] and targets
+  // [kGatherSteps][rows][C] of a run of steps
+  __bf16 *d_xg = nullptr;
+  float *d_tg = nullptr;
   // least-squares polynomials: descriptor and coefficients [S][T][C]
   PolyDev poly{};
   PolyDev *d_poly = nullptr;
@@ -114,6 +120,7 @@ struct cgs_model_s {
 };
 
 constexpr uint32_t kTimeEvents = 512; // event markers of 128 timed steps
+constexpr uint32_t kGatherSteps = 64;  // perceptron training steps gathered at once
 constexpr uint32_t kResultRing = 256; // draw results of steps enqueued ahead
 
 // Launches between consecutive markers t_ev[ev .. ev + n]: kernel k runs
@@ -422,19 +429,19 @@ extern "C" void cgs_space_destroy(cgs_space sp) { destroy_space(sp); }
 namespace {
 
 void free_mlp_scratch(cgs_model m) {
-  dfree(m->d_x);
-  dfree(m->d_h1);
-  dfree(m->d_h2);
-  dfree(m->d_dyb);
-  dfree(m->d_dz1b);
-  dfree(m->d_dz2b);
-  dfree(m->d_z1);
-  dfree(m->d_z2);
+  dfree(m->d_xt);
+  dfree(m->d_h1t);
+  dfree(m->d_h2t);
+  dfree(m->d_dyt);
+  dfree(m->d_dz2t);
+  dfree(m->d_dz1t);
+  dfree(m->d_bp1);
+  dfree(m->d_bp2);
+  dfree(m->d_bp3);
+  dfree(m->d_lossp);
   dfree(m->d_y);
-  dfree(m->d_dyf);
-  dfree(m->d_dz1f);
-  dfree(m->d_dz2f);
-  dfree(m->d_loss_part);
+  dfree(m->d_xg);
+  dfree(m->d_tg);
   m->scratch_rows = 0;
 }
 
@@ -1283,20 +1290,21 @@ uint64_t mlp_count(int F, int H, int C) {
 hipError_t ensure_mlp_scratch(cgs_model m, uint32_t rows) {
   if (m->scratch_rows >= rows) return hipSuccess;
   free_mlp_scratch(m);
-  const size_t H = m->sh.H, K1 = m->sh.K1, Cp = (size_t)32 * ((m->sh.C + 31) / 32);
-  hipError_t e = dalloc(&m->d_x, rows * K1);
-  if (e == hipSuccess) e = dalloc(&m->d_h1, rows * H);
-  if (e == hipSuccess) e = dalloc(&m->d_h2, rows * H);
-  if (e == hipSuccess) e = dalloc(&m->d_dyb, rows * Cp);
-  if (e == hipSuccess) e = dalloc(&m->d_dz1b, rows * H);
-  if (e == hipSuccess) e = dalloc(&m->d_dz2b, rows * H);
-  if (e == hipSuccess) e = dalloc(&m->d_z1, rows * H);
-  if (e == hipSuccess) e = dalloc(&m->d_z2, rows * H);
-  if (e == hipSuccess) e = dalloc(&m->d_y, rows * Cp);
-  if (e == hipSuccess) e = dalloc(&m->d_dyf, rows * Cp);
-  if (e == hipSuccess) e = dalloc(&m->d_dz1f, rows * H);
-  if (e == hipSuccess) e = dalloc(&m->d_dz2f, rows * H);
-  if (e == hipSuccess) e = dalloc(&m->d_loss_part, (rows + 31) / 32 * (Cp / 32)); // output tiles
+  const size_t H = m->sh.H, Cp = (size_t)32 * ((m->sh.C + 31) / 32);
+  const size_t n_pad = ((size_t)rows + 31) / 32 * 32, nblk = n_pad / 32;
+  hipError_t e = dalloc(&m->d_xt, 32 * n_pad);
+  if (e == hipSuccess) e = dalloc(&m->d_h1t, H * n_pad);
+  if (e == hipSuccess) e = dalloc(&m->d_h2t, H * n_pad);
+  if (e == hipSuccess) e = dalloc(&m->d_dyt, Cp * n_pad);
+  if (e == hipSuccess) e = dalloc(&m->d_dz2t, H * n_pad);
+  if (e == hipSuccess) e = dalloc(&m->d_dz1t, H * n_pad);
+  if (e == hipSuccess) e = dalloc(&m->d_bp1, nblk * H);
+  if (e == hipSuccess) e = dalloc(&m->d_bp2, nblk * H);
+  if (e == hipSuccess) e = dalloc(&m->d_bp3, nblk * Cp);
+  if (e == hipSuccess) e = dalloc(&m->d_lossp, nblk);
+  if (e == hipSuccess) e = dalloc(&m->d_y, n_pad * Cp);
+  if (e == hipSuccess) e = dalloc(&m->d_xg, kGatherSteps * n_pad * m->sh.K1);
+  if (e == hipSuccess) e = dalloc(&m->d_tg, kGatherSteps * (size_t)rows * m->sh.C);
   if (e != hipSuccess) {
     free_mlp_scratch(m);
     return e;
@@ -1305,59 +1313,107 @@ hipError_t ensure_mlp_scratch(cgs_model m, uint32_t rows) {
   return hipSuccess;
 }
 
-// Forward of n rows (cfg_raw[batch[i]]) storing the activations.
-hipError_t mlp_forward_rows(cgs_model m, const uint32_t *d_cfg, const int32_t *d_batch, uint32_t n,
-                            const LossArgs *loss = nullptr) {
-  MlpFwdArgs a = mlp_args(m);
-  a.cfg_raw = d_cfg;
-  a.batch = d_batch;
-  a.n = n;
-  a.xout = m->d_x;
-  a.z1out = m->d_z1;
-  a.z2out = m->d_z2;
-  a.h1out = m->d_h1;
-  a.h2out = m->d_h2;
-  a.yout = m->d_y;
-  return launch_mlp_train_forward(a, m->d_theta, m->d_theta + m->off_w2, m->d_theta + m->off_w3,
-                                  loss, m->space->stream);
+// Gathers the rows of `steps` steps of n rows (pair d_batch[s n + r], or r
+// without a batch) into m->d_xg / m->d_tg (targets when d_targets is set).
+hipError_t gather_rows(cgs_model m, const uint32_t *d_cfg, const float *d_targets,
+                       const int32_t *d_batch, uint32_t steps, uint32_t n) {
+  return launch_mlp_gather_rows(m->space->d_desc, d_cfg, d_batch, d_targets, steps, n,
+                                (n + 31) / 32 * 32, m->sh.F, m->sh.K1, m->sh.C, m->d_xg,
+                                m->d_tg, m->space->stream);
 }
 
-// Forward + loss + backward of n rows into m->d_grad; loss to *d_loss.
-hipError_t mlp_backward_rows(cgs_model m, const uint32_t *d_cfg, const float *d_targets,
-                             const int32_t *d_batch, uint32_t n, float *d_loss) {
+// Launch arguments of the row kernel for step k of the gathered run (n
+// rows); train == false: forward only, Y into m->d_y.
+TrainRowsArgs train_rows_args(cgs_model m, uint32_t k, uint32_t n, bool train) {
+  TrainRowsArgs a{};
+  const uint32_t n_pad = (n + 31) / 32 * 32;
+  a.xin = m->d_xg + (size_t)k * n_pad * m->sh.K1;
+  a.tin = train ? m->d_tg + (size_t)k * n * m->sh.C : nullptr;
+  a.train = train;
+  a.n = n;
+  a.n_pad = (n + 31) / 32 * 32;
+  a.F = m->sh.F;
+  a.H = m->sh.H;
+  a.C = m->sh.C;
+  a.K1 = m->sh.K1;
+  a.scale = 2.0f / (float)(n * (uint32_t)m->sh.C);
+  a.w1p = reinterpret_cast<const bf16x8 *>(m->d_w1p);
+  a.w2p = reinterpret_cast<const bf16x8 *>(m->d_w2p);
+  a.w3p = reinterpret_cast<const bf16x8 *>(m->d_w3p);
+  a.w2t = m->d_w2t;
+  a.w3t = m->d_w3t;
+  a.b1 = m->d_theta + m->off_b1;
+  a.b2 = m->d_theta + m->off_b2;
+  a.b3 = m->d_theta + m->off_b3;
+  a.yout = m->d_y;
+  a.xt = m->d_xt;
+  a.h1t = m->d_h1t;
+  a.h2t = m->d_h2t;
+  a.dyt = m->d_dyt;
+  a.dz2t = m->d_dz2t;
+  a.dz1t = m->d_dz1t;
+  a.bp1 = m->d_bp1;
+  a.bp2 = m->d_bp2;
+  a.bp3 = m->d_bp3;
+  a.lossp = m->d_lossp;
+  return a;
+}
+
+// Forward of n rows, Y into m->d_y ([n][Cp]).
+hipError_t mlp_forward_rows(cgs_model m, const uint32_t *d_cfg, uint32_t n) {
+  hipError_t e = gather_rows(m, d_cfg, nullptr, nullptr, 1, n);
+  if (e != hipSuccess) return e;
+  return launch_mlp_train_rows(train_rows_args(m, 0, n, false), m->space->stream);
+}
+
+// Adam settings of one step (c1, c2: this step's bias corrections).
+struct AdamStep {
+  float lr, beta1, beta2, eps, c1, c2;
+};
+
+// Forward, loss and backward of step k of the gathered run, n rows (two
+// launches): with adam == nullptr the gradient goes to m->d_grad, otherwise
+// the step is applied to the parameters; the loss goes to *d_loss.
+hipError_t mlp_step_rows(cgs_model m, uint32_t k, uint32_t n, float *d_loss,
+                         const AdamStep *adam) {
   hipStream_t st = m->space->stream;
-  const int H = m->sh.H, F = m->sh.F, C = m->sh.C, K1 = m->sh.K1, Cp = 32 * ((C + 31) / 32);
-  // the output layer's epilogue also writes dY and the squared errors per tile
-  const LossArgs loss{d_targets, d_batch, 2.0f / (float)(n * (uint32_t)C), m->d_dyf, m->d_dyb,
-                      m->d_loss_part};
-  const int n_tiles = (int)((n + 31) / 32) * ((C + 31) / 32);
-  hipError_t e = mlp_forward_rows(m, d_cfg, d_batch, n, &loss);
-  float *g = m->d_grad;
-  // three launches, one per level of the chain rule; the products of a
-  // level and the bias sums it can form are independent
-  const int nn = (int)n;
-  // dW3 = dY^T H2; dZ2 = (dY W3) * gelu'(Z2) with W3 from its transposed
-  // bf16 copy; db3 = column sums of dY
-  if (e == hipSuccess)
-    e = launch_bwd_group(
-        GemmArgs{C, H, nn, m->d_dyb, 1, Cp, m->d_h2, H, 1, g + m->off_w3, nullptr, nullptr, H}, 0,
-        GemmArgs{nn, H, C, m->d_dyb, Cp, 1, m->d_w3t, 1, Cp, m->d_dz2f, m->d_dz2b, m->d_z2, H}, 1,
-        ColSumJob{m->d_dyf, Cp, nn, C, g + m->off_b3, nullptr, 0, nullptr, 1.0f}, st);
-  // dW2 = dZ2^T H1; dZ1 = (dZ2 W2) * gelu'(Z1) with W2 transposed; db2
-  if (e == hipSuccess)
-    e = launch_bwd_group(
-        GemmArgs{H, H, nn, m->d_dz2b, 1, H, m->d_h1, H, 1, g + m->off_w2, nullptr, nullptr, H}, 0,
-        GemmArgs{nn, H, H, m->d_dz2b, H, 1, m->d_w2t, 1, H, m->d_dz1f, m->d_dz1b, m->d_z1, H}, 1,
-        ColSumJob{m->d_dz2f, H, nn, H, g + m->off_b2, nullptr, 0, nullptr, 1.0f}, st);
-  // dW1 = dZ1^T X; db1; the loss from the output tiles' partial sums
-  if (e == hipSuccess)
-    e = launch_bwd_group(
-        GemmArgs{H, F, nn, m->d_dz1b, 1, H, m->d_x, K1, 1, g, nullptr, nullptr, F}, 0, GemmArgs{},
-        0,
-        ColSumJob{m->d_dz1f, H, nn, H, g + m->off_b1, m->d_loss_part, n_tiles, d_loss,
-                  (float)(n * (uint32_t)C)},
-        st);
-  return e;
+  const TrainRowsArgs a = train_rows_args(m, k, n, true);
+  hipError_t e = launch_mlp_train_rows(a, st);
+  if (e != hipSuccess) return e;
+  GradTilesArgs g{};
+  g.sh = m->sh;
+  g.n_pad = a.n_pad;
+  g.xt = a.xt;
+  g.h1t = a.h1t;
+  g.h2t = a.h2t;
+  g.dyt = a.dyt;
+  g.dz2t = a.dz2t;
+  g.dz1t = a.dz1t;
+  g.bp1 = a.bp1;
+  g.bp2 = a.bp2;
+  g.bp3 = a.bp3;
+  g.lossp = a.lossp;
+  g.loss_out = d_loss;
+  g.loss_div = (float)(n * (uint32_t)m->sh.C);
+  g.theta = m->d_theta;
+  g.m = m->d_m;
+  g.v = m->d_v;
+  g.w1p = m->d_w1p;
+  g.w2p = m->d_w2p;
+  g.w3p = m->d_w3p;
+  g.w2t = m->d_w2t;
+  g.w3t = m->d_w3t;
+  if (adam) {
+    g.lr = adam->lr;
+    g.beta1 = adam->beta1;
+    g.beta2 = adam->beta2;
+    g.eps = adam->eps;
+    g.c1 = adam->c1;
+    g.c2 = adam->c2;
+  } else {
+    g.grad = m->d_grad;
+  }
+  return launch_mlp_grad_tiles(g, st);
 }
 
 // Uploads host pairs; returns device copies (caller frees).
@@ -1444,6 +1500,8 @@ extern "C" cgs_status cgs_model_load_mlp(cgs_space sp, const cgs_mlp_desc *desc,
   if (e == hipSuccess) e = hipMemsetAsync(m->d_v, 0, n * sizeof(float), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->d_w1p, 0, m->n_w1p * sizeof(__bf16), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->d_w3p, 0, m->n_w3p * sizeof(__bf16), st);
+  // w3t's padding columns (C .. Cp-1) are read by the backward product
+  if (e == hipSuccess) e = hipMemsetAsync(m->d_w3t, 0, m->n_w3p * sizeof(__bf16), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->d_P, 0, (size_t)C * m->stride * sizeof(float), st);
   if (e == hipSuccess)
     e = launch_pack_weights(m->sh, m->d_theta, n, m->d_w1p, m->d_w2p, m->d_w3p, m->d_w2t,
@@ -1490,15 +1548,16 @@ extern "C" cgs_status cgs_mlp_train(cgs_model m, const uint32_t *cfg, const floa
   if (e == hipSuccess && nb)
     e = hipMemcpyAsync(d_batch, batch_idx, nb * sizeof(int32_t), hipMemcpyHostToDevice, st);
   for (int s = 0; s < o->steps && e == hipSuccess; ++s) {
-    e = mlp_backward_rows(m, d_cfg, d_t, d_batch + (size_t)s * o->batch, (uint32_t)o->batch,
-                          d_loss + s);
+    const uint32_t k = (uint32_t)s % kGatherSteps;
+    if (k == 0) // the rows of the next run of steps
+      e = gather_rows(m, d_cfg, d_t, d_batch + (size_t)s * o->batch,
+                      (uint32_t)std::min<int>(kGatherSteps, o->steps - s), (uint32_t)o->batch);
     if (e != hipSuccess) break;
     m->adam_t += 1;
     const double c1 = 1.0 / (1.0 - std::pow((double)o->beta1, (double)m->adam_t));
     const double c2 = 1.0 / (1.0 - std::pow((double)o->beta2, (double)m->adam_t));
-    e = launch_adam_pack(m->sh, m->d_theta, m->d_m, m->d_v, m->d_grad, m->n_theta, o->lr,
-                         o->beta1, o->beta2, o->eps, (float)c1, (float)c2, m->d_w1p, m->d_w2p,
-                         m->d_w3p, m->d_w2t, m->d_w3t, st);
+    const AdamStep adam{o->lr, o->beta1, o->beta2, o->eps, (float)c1, (float)c2};
+    e = mlp_step_rows(m, k, (uint32_t)o->batch, d_loss + s, &adam);
   }
   if (e == hipSuccess && loss_host && o->steps > 0)
     e = hipMemcpyAsync(loss_host, d_loss, o->steps * sizeof(float), hipMemcpyDeviceToHost, st);
@@ -1524,7 +1583,8 @@ extern "C" cgs_status cgs_mlp_gradients(cgs_model m, const uint32_t *cfg, const 
   hipError_t e = ensure_mlp_scratch(m, n);
   if (e == hipSuccess) e = upload_pairs(m, cfg, targets, n, &d_cfg, &d_t);
   if (e == hipSuccess) e = dalloc(&d_loss, 1);
-  if (e == hipSuccess) e = mlp_backward_rows(m, d_cfg, d_t, nullptr, n, d_loss);
+  if (e == hipSuccess) e = gather_rows(m, d_cfg, d_t, nullptr, 1, n);
+  if (e == hipSuccess) e = mlp_step_rows(m, 0, n, d_loss, nullptr);
   float loss = 0.0f;
   if (e == hipSuccess)
     e = hipMemcpyAsync(grads, m->d_grad, m->n_theta * sizeof(float), hipMemcpyDeviceToHost, st);
@@ -1551,7 +1611,7 @@ extern "C" cgs_status cgs_mlp_forward(cgs_model m, const uint32_t *cfg, uint32_t
   std::vector<float> rows((size_t)n * Cp);
   hipError_t e = ensure_mlp_scratch(m, n);
   if (e == hipSuccess) e = upload_pairs(m, cfg, nullptr, n, &d_cfg, &d_unused);
-  if (e == hipSuccess) e = mlp_forward_rows(m, d_cfg, nullptr, n);
+  if (e == hipSuccess) e = mlp_forward_rows(m, d_cfg, n);
   if (e == hipSuccess)
     e = hipMemcpyAsync(rows.data(), m->d_y, rows.size() * sizeof(float), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -145,35 +145,16 @@ struct MlpShape {
 
 struct MlpFwdArgs {
   const SpaceDev *sp;
-  const uint32_t *idx;     // inference: valid raw indices
-  const uint32_t *cfg_raw; // training: raw indices of the pairs
-  const int32_t *batch;    // training: rows of this step (or null: 0..n-1)
+  const uint32_t *idx;     // valid raw indices
   uint32_t n;
   int F, H, C, K1, n_cu;
   const bf16x8 *w1p, *w2p, *w3p;
   const float *b1, *b2, *b3;
   float *P;
   uint64_t stride;
-  __bf16 *xout;
-  float *z1out, *z2out;
-  __bf16 *h1out, *h2out;
-  float *yout;
-};
-
-struct GemmArgs {
-  int M, N, K;
-  const void *A;
-  long a_sm, a_sk;
-  const void *B;
-  long b_sk, b_sn;
-  float *Cf;
-  __bf16 *Cb;
-  const float *Z;
-  long ldc;
 };
 
 hipError_t launch_mlp_forward(const MlpFwdArgs &a, bool train, hipStream_t stream);
-hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipStream_t stream);
 
 // ---- launchers (each enqueues on `stream`; return hipSuccess or an error)
 hipError_t launch_enumeration(const SpaceDev *d_space, uint32_t n_raw, uint32_t *d_mask,

@@ -17,13 +17,11 @@
 //   kperm(s, h, j) = 32(s/2) + 16(s%2) + 8(j/4) + 4h + (j%4)
 // GELU's tail Phi(-|z|) is the exponential of a polynomial (gelu.h), within
 // 2^-13.6 of itself: far below the bf16 rounding of the activations.  The
-// backward pass's GELU derivative uses erf from Abramowitz & Stegun 7.1.26
-// (|error| <= 1.5e-7).
+// training forward forms GELU'(z) from the same tail (within 4e-5 of it).
 //
-// Training runs the forward pass as one GEMM per layer (gemm_bf16 with the
-// bias and GELU in its epilogue, 32 x 32 output tiles, so a batch of a few
-// hundred configurations still spreads over tens of workgroups) and the
-// backward pass with the same GEMM kernel.
+// Training runs a step in two launches (the training-step section below):
+// the forward and backward chain per 32 rows of the batch, then the weight
+// gradients by 32 x 32 tiles with Adam applied where they are formed.
 #include <algorithm>
 
 #include "device_common.h"
@@ -36,24 +34,11 @@ namespace {
 
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
-constexpr int kGemmThreads = 256;
 
 __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// Phi(z) and phi(z) = exp(-z^2/2) / sqrt(2 pi); erf by A&S 7.1.26.
-__device__ __forceinline__ void normal_cdf_pdf(float z, float &cdf, float &pdf) {
-  const float x = fabsf(z) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
-  const float poly =
-      t * (0.254829592f +
-           t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-  const float e = __expf(-x * x);
-  const float erf_abs = 1.0f - poly * e;
-  cdf = 0.5f * (1.0f + (z >= 0.0f ? erf_abs : -erf_abs));
-  pdf = e * 0.3989422804014327f;
-}
 // GELU(z) = max(z, 0) - |z| Phi(-|z|) with Phi(-x) = 2^p(min(x, 9)) (gelu.h):
 // nine VALU operations and one exponential.
 __device__ __forceinline__ float gelu(float z) {
@@ -61,10 +46,17 @@ __device__ __forceinline__ float gelu(float z) {
   const float e = __builtin_amdgcn_exp2f(gelu_tail_log2(fminf(az, kGeluTailMax)));
   return fmaf(-az, e, fmaxf(z, 0.0f));
 }
-__device__ __forceinline__ float gelu_grad(float z) {
-  float c, p;
-  normal_cdf_pdf(z, c, p);
-  return c + z * p;
+// GELU(z) as above and, from the same tail, its derivative
+// GELU'(z) = Phi(z) + z phi(z), phi(z) = 2^(-z^2 / (2 ln 2)) / sqrt(2 pi):
+// the training forward keeps the derivative for the backward pass.
+__device__ __forceinline__ float gelu_with_grad(float z, float &dg) {
+  const float az = fabsf(z);
+  const float e = __builtin_amdgcn_exp2f(gelu_tail_log2(fminf(az, kGeluTailMax)));
+  const float cdf = z > 0.0f ? 1.0f - e : e;
+  const float pdf =
+      0.3989422804014327f * __builtin_amdgcn_exp2f(-0.7213475204444817f * (z * z));
+  dg = fmaf(z, pdf, cdf);
+  return fmaf(-az, e, fmaxf(z, 0.0f));
 }
 
 // ------------------------------------------------------------- inference
@@ -313,279 +305,6 @@ mlp_infer(
   }
 }
 
-// ------------------------------------------------------------------ GEMM
-// C[M][N] = sum_k A(m, k) B(k, n), bf16 operands (converted on load), fp32
-// accumulation; one 32x32 output tile per workgroup, its K range split over
-// the workgroup's waves (kGemmThreads / 64), partial tiles summed in LDS.
-// Operands are addressed with arbitrary strides so transposed products need
-// no copies.
-template <typename T> __device__ __forceinline__ __bf16 to_bf16(T v);
-template <> __device__ __forceinline__ __bf16 to_bf16<float>(float v) { return (__bf16)v; }
-template <> __device__ __forceinline__ __bf16 to_bf16<__bf16>(__bf16 v) { return v; }
-// 8 consecutive values (16-byte aligned for bf16, 32-byte for float) as bf16.
-__device__ __forceinline__ bf16x8 load_bf16x8(const __bf16 *p) {
-  return *reinterpret_cast<const bf16x8 *>(p);
-}
-__device__ __forceinline__ bf16x8 load_bf16x8(const float *p) {
-  const float4 lo = *reinterpret_cast<const float4 *>(p);
-  const float4 hi = *reinterpret_cast<const float4 *>(p + 4);
-  bf16x8 r;
-  r[0] = (__bf16)lo.x;
-  r[1] = (__bf16)lo.y;
-  r[2] = (__bf16)lo.z;
-  r[3] = (__bf16)lo.w;
-  r[4] = (__bf16)hi.x;
-  r[5] = (__bf16)hi.y;
-  r[6] = (__bf16)hi.z;
-  r[7] = (__bf16)hi.w;
-  return r;
-}
-
-// EPI 0: C = A B; 1: dZ = (A B) * gelu'(Z) (fp32 and bf16); 2: Z = A B + bias
-// (fp32) and H = gelu(Z) (bf16); 3: Y = A B + bias (fp32); 4: as 3, plus the
-// training loss terms of LossArgs (dY and one sum of squared errors per
-// tile).  bias[N] for 2, 3, 4.
-// Output tile `tile` (row-major over 32 x 32 tiles) by one workgroup of
-// kGemmThreads; shared by the plain launch and the grouped backward launch.
-// The first layer's A operand straight from the configurations: row m is
-// configuration cfg_raw[batch[m]] (cfg_raw[m] without a batch), column k its
-// parameter k's digit / 8 (0 past F); the workgroups of the first column of
-// output tiles also store the rows as bf16 into xout[m][K1] for the
-// backward pass.
-struct FeatArgs {
-  const SpaceDev *sp;
-  const uint32_t *cfg_raw;
-  const int32_t *batch;
-  int F, K1;
-  __bf16 *xout;
-};
-
-template <typename TA, typename TB, int EPI, bool FEAT = false>
-__device__ __forceinline__ void gemm_tile(const GemmArgs &g, const float *bias, const LossArgs &la,
-                                          int tile, const FeatArgs &fa = FeatArgs{}) {
-  constexpr int NW = kGemmThreads / 64;
-  __shared__ float part[NW - 1][16][64];
-  const TA *A = static_cast<const TA *>(g.A);
-  const TB *B = static_cast<const TB *>(g.B);
-  const int tiles_n = (g.N + 31) / 32;
-  const int m0 = (tile / tiles_n) * 32, n0 = (tile % tiles_n) * 32;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hh = lane >> 5, c = lane & 31;
-  const int m = m0 + c, n = n0 + c;
-  f32x16 acc = {};
-  // unit stride along K (and 8-element aligned rows): a fragment's 8 values
-  // are one contiguous, 16-byte aligned run, loaded as vectors
-  const bool a_vec =
-      g.a_sk == 1 && g.a_sm % 8 == 0 && (reinterpret_cast<uintptr_t>(A) & 15u) == 0;
-  const bool b_vec =
-      g.b_sk == 1 && g.b_sn % 8 == 0 && (reinterpret_cast<uintptr_t>(B) & 15u) == 0;
-  uint64_t dlo = 0, dhi = 0; // FEAT: the digits of row m's configuration
-  if (FEAT && m < g.M && 16 * w < g.K) {
-    const uint32_t src = fa.batch ? (uint32_t)fa.batch[m] : (uint32_t)m;
-    decode_packed(fa.cfg_raw[src], fa.sp, dlo, dhi);
-  }
-  for (int k0 = 16 * w; k0 < g.K; k0 += 16 * NW) {
-    bf16x8 af, bf;
-    const int kf = k0 + 8 * hh; // first k of this lane's fragment
-    const bool full = kf + 8 <= g.K;
-    if (FEAT) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = kf + j;
-        af[j] = (__bf16)((m < g.M && k < fa.F) ? (float)digit_of(dlo, dhi, (uint32_t)k) * 0.125f
-                                               : 0.0f);
-      }
-      if (n0 == 0 && m < g.M && kf < fa.K1)
-        *reinterpret_cast<bf16x8 *>(fa.xout + (size_t)m * fa.K1 + kf) = af;
-    } else if (a_vec && full && m < g.M) {
-      af = load_bf16x8(A + (size_t)m * g.a_sm + kf);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = kf + j;
-        af[j] = (m < g.M && k < g.K) ? to_bf16(A[(size_t)m * g.a_sm + (size_t)k * g.a_sk])
-                                     : (__bf16)0.0f;
-      }
-    }
-    if (b_vec && full && n < g.N) {
-      bf = load_bf16x8(B + (size_t)n * g.b_sn + kf);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = kf + j;
-        bf[j] = (n < g.N && k < g.K) ? to_bf16(B[(size_t)k * g.b_sk + (size_t)n * g.b_sn])
-                                     : (__bf16)0.0f;
-      }
-    }
-    acc = mfma(af, bf, acc);
-  }
-  if (w > 0) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) part[w - 1][i][lane] = acc[i];
-  }
-  __syncthreads();
-  if (w != 0) return;
-  float sq = 0.0f; // EPI 4: this lane's squared errors
-  float tv[16];    // EPI 4: the targets of this lane's 16 outputs
-  if (EPI == 4) {
-    // every target load issued before the first dY store (the stores could
-    // alias them); rows and columns past the end read row 0, column 0
-    int src[16];
-    const int cl = n0 + c < g.N ? n0 + c : 0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int row = m0 + 8 * (i / 4) + 4 * hh + (i % 4);
-      const int r = row < g.M ? row : 0;
-      src[i] = la.batch ? la.batch[r] : r;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) tv[i] = la.targets[(size_t)src[i] * g.N + cl];
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-#pragma unroll
-    for (int q = 0; q < NW - 1; ++q) acc[i] += part[q][i][lane];
-    const int row = m0 + 8 * (i / 4) + 4 * hh + (i % 4), cl = n0 + c;
-    if (row >= g.M || cl >= g.N) continue;
-    const size_t o = (size_t)row * g.ldc + cl;
-    if (EPI == 0) {
-      g.Cf[o] = acc[i];
-    } else if (EPI == 1) { // dZ = dH * gelu'(Z)
-      const float v = acc[i] * gelu_grad(g.Z[o]);
-      g.Cf[o] = v;
-      g.Cb[o] = (__bf16)v;
-    } else if (EPI == 2) { // Z = W x + b, H = gelu(Z)
-      const float v = acc[i] + bias[cl];
-      g.Cf[o] = v;
-      g.Cb[o] = (__bf16)gelu(v);
-    } else if (EPI == 3) { // Y = W h + b
-      g.Cf[o] = acc[i] + bias[cl];
-    } else { // Y, then d = Y - T and dY = scale * d
-      const float y = acc[i] + bias[cl];
-      g.Cf[o] = y;
-      const float d = y - tv[i];
-      sq += d * d;
-      la.dyf[o] = la.scale * d;
-      la.dyb[o] = (__bf16)(la.scale * d);
-    }
-  }
-  if (EPI == 4) {
-    sq = wave_sum(sq);
-    if (lane == 0) la.partial[tile] = sq;
-  }
-}
-
-template <typename TA, typename TB, int EPI>
-__global__ __launch_bounds__(kGemmThreads) void gemm_bf16(GemmArgs g, const float *bias,
-                                                          LossArgs la) {
-  gemm_tile<TA, TB, EPI>(g, bias, la, blockIdx.x);
-}
-
-// The first hidden layer with its inputs decoded in the operand load
-// (FeatArgs): Z1 = X W1^T + b1, H1 = gelu(Z1), X stored on the side.
-__global__ __launch_bounds__(kGemmThreads) void gemm_layer1(GemmArgs g, const float *bias,
-                                                            FeatArgs fa) {
-  gemm_tile<__bf16, float, 2, true>(g, bias, LossArgs{}, blockIdx.x, fa);
-}
-
-// Column sums of src[nrows][ld] over columns [64 b, 64 b + 64) of ncols by
-// one workgroup: lanes take columns (coalesced rows), the waves split the
-// rows and meet in LDS, added in wave order.  Block 0 also forms the loss
-// from the per-tile partials, in tile order.
-__device__ __forceinline__ void colsum_block(const ColSumJob &cs, int b) {
-  constexpr int NW = kGemmThreads / 64;
-  __shared__ float part[NW][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (b == 0 && threadIdx.x == 0 && cs.loss_out) {
-    float t = 0.0f;
-    for (int k = 0; k < cs.n_partial; ++k) t += cs.partial[k];
-    *cs.loss_out = t / cs.loss_div;
-  }
-  const int col = b * 64 + lane;
-  float sum = 0.0f;
-  if (col < cs.ncols) {
-#pragma unroll 4
-    for (int r = w; r < cs.nrows; r += NW) sum += cs.src[(size_t)r * cs.ld + col];
-  }
-  part[w][lane] = sum;
-  __syncthreads();
-  if (w == 0 && col < cs.ncols) {
-    float t = 0.0f;
-#pragma unroll
-    for (int k = 0; k < NW; ++k) t += part[k][lane];
-    cs.dst[col] = t;
-  }
-}
-
-__device__ __forceinline__ int gemm_tiles(const GemmArgs &g) {
-  return g.M > 0 && g.N > 0 ? ((g.M + 31) / 32) * ((g.N + 31) / 32) : 0;
-}
-
-// One level of the backward pass in one launch: two independent bf16 x bf16
-// products (epilogue 0: plain, 1: times gelu'(Z)) and one set of bias
-// gradients, each workgroup working on one of them.
-__global__ __launch_bounds__(kGemmThreads) void gemm_bwd_group(GemmArgs g0, int epi0, GemmArgs g1,
-                                                               int epi1, ColSumJob cs) {
-  int b = blockIdx.x;
-  const int t0 = gemm_tiles(g0), t1 = gemm_tiles(g1);
-  if (b < t0) {
-    if (epi0) gemm_tile<__bf16, __bf16, 1>(g0, nullptr, LossArgs{}, b);
-    else gemm_tile<__bf16, __bf16, 0>(g0, nullptr, LossArgs{}, b);
-    return;
-  }
-  b -= t0;
-  if (b < t1) {
-    if (epi1) gemm_tile<__bf16, __bf16, 1>(g1, nullptr, LossArgs{}, b);
-    else gemm_tile<__bf16, __bf16, 0>(g1, nullptr, LossArgs{}, b);
-    return;
-  }
-  colsum_block(cs, b - t1);
-}
-
-// ------------------------------------------------------ loss, biases, Adam
-// (dY and the squared errors come from the output layer's GEMM epilogue.)
-
-// Bias gradients: column sums over the batch.  A workgroup takes 64
-// consecutive columns (lane = column, coalesced rows); its 16 waves split the
-// rows and their partial sums meet in LDS.
-constexpr int kBiasWaves = 16;
-__global__ __launch_bounds__(kBiasWaves * 64) void bias_grads(
-    const float *__restrict__ dz1, const float *__restrict__ dz2, const float *__restrict__ dyf,
-    int n, int H, int C, int Cp, float *__restrict__ gb1, float *__restrict__ gb2,
-    float *__restrict__ gb3, const float *__restrict__ partial, int n_partial,
-    float *__restrict__ loss_out) {
-  __shared__ float part[kBiasWaves][64];
-  if (blockIdx.x == 0 && threadIdx.x == 0) { // the loss, tile partials in order
-    float t = 0.0f;
-    for (int k = 0; k < n_partial; ++k) t += partial[k];
-    *loss_out = t / (float)(n * C);
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + lane;
-  const float *src = nullptr;
-  float *dst = nullptr;
-  int ld = 0, col = 0;
-  if (c < H) {
-    src = dz1, dst = gb1, ld = H, col = c;
-  } else if (c < 2 * H) {
-    src = dz2, dst = gb2, ld = H, col = c - H;
-  } else if (c < 2 * H + C) {
-    src = dyf, dst = gb3, ld = Cp, col = c - 2 * H;
-  }
-  float sum = 0.0f;
-  if (src) {
-#pragma unroll 4
-    for (int b = w; b < n; b += kBiasWaves) sum += src[(size_t)b * ld + col];
-  }
-  part[w][lane] = sum;
-  __syncthreads();
-  if (w == 0 && src) {
-    float t = 0.0f;
-#pragma unroll
-    for (int k = 0; k < kBiasWaves; ++k) t += part[k][lane];
-    dst[col] = t;
-  }
-}
-
 // Position of master parameter p in the packed bf16 weight arrays, or -1
 // for biases.  which: 1, 2, 3 = W1p, W2p, W3p.
 __device__ __forceinline__ long packed_position(const MlpShape &sh, size_t p, int &which) {
@@ -657,24 +376,429 @@ __global__ __launch_bounds__(256) void pack_weights(MlpShape sh, const float *__
   pack_transposed(sh, p, th, w2t, w3t);
 }
 
-// Adam (Kingma & Ba, Algorithm 1); c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t).
-__global__ __launch_bounds__(256) void adam_pack(MlpShape sh, float *__restrict__ theta,
-                                                 float *__restrict__ m, float *__restrict__ v,
-                                                 const float *__restrict__ grad, size_t n,
-                                                 float lr, float b1, float b2, float eps, float c1,
-                                                 float c2, __bf16 *w1p, __bf16 *w2p,
-                                                 __bf16 *w3p, __bf16 *w2t, __bf16 *w3t) {
-  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= n) return;
-  const float g = grad[p];
-  const float mm = b1 * m[p] + (1.0f - b1) * g;
-  const float vv = b2 * v[p] + (1.0f - b2) * g * g;
-  m[p] = mm;
-  v[p] = vv;
-  const float th = theta[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
-  theta[p] = th;
-  pack_one(sh, p, th, w1p, w2p, w3p);
-  pack_transposed(sh, p, th, w2t, w3t);
+// ------------------------------------------------------------ training step
+// One Adam step is two launches.
+//  mlp_train_rows: one workgroup of kTrainWaves waves per 32 rows of the
+//    batch.  Z = A W^T + b by 32 x 32 output tiles (standard orientation:
+//    the activations are the MFMA A operand, read from LDS, and the weights
+//    the B operand, read as the packed fragments of the inference path), a
+//    tile per wave and layer, the activations exchanged through LDS; then
+//    the loss terms and dY = scale (Y - T), and the backward chain
+//    dZ2 = (dY W3) * gelu'(Z2), dZ1 = (dZ2 W2) * gelu'(Z1) with W3 and W2
+//    from their transposed bf16 copies.  Every product of the chain is local
+//    to the rows; each wave keeps the pre-activations of its own tiles in
+//    registers for the derivatives.  It stores the operands of the weight
+//    gradients transposed (feature-major, the batch contiguous, so the next
+//    launch reads them as vector fragments), the column sums of dY, dZ2 and
+//    dZ1 over its rows, and its sum of squared errors.
+//  mlp_grad_tiles: one workgroup per 32 x 32 tile of dW2 = dZ2^T H1,
+//    dW1 = dZ1^T X and dW3 = dY^T H2 (the batch as the reduction dimension,
+//    split over the waves and added in wave order) and one per 256 biases
+//    (block sums in block order; the first also forms the loss); each stores
+//    its gradients or applies Adam to its parameters and rewrites their bf16
+//    copies.
+// Rows past the batch carry X = 0 and dY = 0, so they add nothing.
+constexpr int kTrainWaves = 8;
+constexpr int kGradThreads = 256;
+
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+typedef __attribute__((ext_vector_type(2))) uint32_t u32x2;
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+// A operand (row = lane % 32) from an LDS activation array with row stride
+// ld: 8 consecutive features from k.
+__device__ __forceinline__ bf16x8 act_frag(const __bf16 *base, int ld, int row, int k) {
+  return *reinterpret_cast<const bf16x8 *>(base + row * ld + k);
+}
+// The same in the packed weights' K order: slot j of lane half hh at step s
+// holds feature 16 s + 8 (j / 4) + 4 hh + (j % 4) (the file header's kperm).
+__device__ __forceinline__ bf16x8 act_frag_perm(const __bf16 *base, int ld, int row, int s,
+                                                int hh) {
+  const __bf16 *p = base + row * ld + 16 * s + 4 * hh;
+  const u32x2 lo = *reinterpret_cast<const u32x2 *>(p);
+  const u32x2 hi = *reinterpret_cast<const u32x2 *>(p + 8);
+  const u32x4 u = {lo.x, lo.y, hi.x, hi.y};
+  return __builtin_bit_cast(bf16x8, u);
+}
+__device__ __forceinline__ bf16x8 frag_at(const __bf16 *p) {
+  return *reinterpret_cast<const bf16x8 *>(p);
+}
+
+// One lane's accumulator column (rows 8 (i / 4) + 4 hh + (i % 4), column
+// col) as bf16: into the LDS array (row stride ld; none when lds is null)
+// and transposed into dst[col][m0 + row] (row length n_pad, 4 rows a store).
+__device__ __forceinline__ void store_act(const float (&v)[16], __bf16 *lds, int ld, int col,
+                                          __bf16 *dst, uint32_t n_pad, uint32_t m0, int hh) {
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    bf16x4 b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      b[e] = (__bf16)v[4 * g + e];
+      if (lds) lds[(8 * g + 4 * hh + e) * ld + col] = b[e];
+    }
+    *reinterpret_cast<bf16x4 *>(dst + (size_t)col * n_pad + m0 + 8 * g + 4 * hh) = b;
+  }
+}
+
+template <int H, int NB3, int S1> struct TrainShape {
+  static constexpr int NT = H / 32;                                // tiles of a hidden layer
+  static constexpr int TPW = (NT + kTrainWaves - 1) / kTrainWaves; // tiles per wave
+  static constexpr int K1 = 16 * S1, CP = 32 * NB3;
+  // LDS row strides (bf16), padded by 16 bytes so that the 32 rows of a
+  // fragment load start in different banks
+  static constexpr int LX = K1 + 8, LH = H + 8, LY = CP + 8;
+  static constexpr size_t lds = (size_t)32 * (LX + 2 * LH + LY) * sizeof(__bf16) + 16;
+};
+
+// Rows of `steps` training steps of n rows each (step s, row r: pair
+// batch[s n + r], or pair r without a batch): features digit / 8 as bf16,
+// xg[s][n_pad][K1] (zeros past F and for rows n .. n_pad-1), and with
+// targets set their targets tg[s][n][C].  One thread per row.
+__global__ __launch_bounds__(256) void mlp_gather_rows(const SpaceDev *__restrict__ sp,
+                                                       const uint32_t *__restrict__ cfg_raw,
+                                                       const int32_t *__restrict__ batch,
+                                                       const float *__restrict__ targets,
+                                                       uint32_t steps, uint32_t n, uint32_t n_pad,
+                                                       int F, int K1, int C, __bf16 *xg,
+                                                       float *tg) {
+  const uint64_t id = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= (uint64_t)steps * n_pad) return;
+  const uint32_t s = (uint32_t)(id / n_pad), r = (uint32_t)(id % n_pad);
+  __bf16 *x = xg + id * K1;
+  if (r >= n) {
+    for (int k = 0; k < K1; ++k) x[k] = (__bf16)0.0f;
+    return;
+  }
+  const uint64_t row = (uint64_t)s * n + r;
+  const uint32_t src = batch ? (uint32_t)batch[row] : r;
+  uint64_t dlo = 0, dhi = 0;
+  decode_packed(cfg_raw[src], sp, dlo, dhi);
+  for (int k = 0; k < K1; ++k)
+    x[k] = (__bf16)(k < F ? (float)digit_of(dlo, dhi, (uint32_t)k) * 0.125f : 0.0f);
+  if (targets)
+    for (int c = 0; c < C; ++c) tg[row * C + c] = targets[(size_t)src * C + c];
+}
+
+template <int H, int NB3, int S1>
+__global__ __launch_bounds__(kTrainWaves * 64) void mlp_train_rows(TrainRowsArgs a) {
+  using TS = TrainShape<H, NB3, S1>;
+  constexpr int NT = TS::NT, TPW = TS::TPW, K1 = TS::K1, CP = TS::CP, S2 = H / 16;
+  constexpr int SB = S2 < 8 ? S2 : 8; // K steps whose weight fragments are loaded together
+  constexpr int LX = TS::LX, LH = TS::LH, LY = TS::LY;
+  extern __shared__ __align__(16) unsigned char train_lds[];
+  __bf16 *xs = reinterpret_cast<__bf16 *>(train_lds);
+  __bf16 *h1s = xs + 32 * LX;
+  __bf16 *h2s = h1s + 32 * LH; // H2, then dZ2
+  __bf16 *dys = h2s + 32 * LH;
+  float *lred = reinterpret_cast<float *>(dys + 32 * LY);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hh = lane >> 5, c = lane & 31;
+  const uint32_t blk = blockIdx.x, m0 = 32u * blk;
+  const bool train = a.train;
+
+  // the output waves' targets, requested before anything else
+  float tv[16];
+  if (train && w < NB3) {
+    const int col = 32 * w + c;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t m = m0 + 8 * (i / 4) + 4 * hh + (i % 4);
+      tv[i] = (m < a.n && col < a.C) ? a.tin[(size_t)m * a.C + col] : 0.0f;
+    }
+  }
+  // the block's features (gathered rows, zeros past n)
+  if (tid < 32 * K1 / 8) {
+    const int row = tid / (K1 / 8), seg = tid % (K1 / 8);
+    *reinterpret_cast<bf16x8 *>(xs + row * LX + 8 * seg) =
+        frag_at(a.xin + (size_t)(m0 + row) * K1 + 8 * seg);
+  }
+  __syncthreads();
+  if (tid < 256) { // X^T for dW1: 32 feature rows, zeros past K1
+    const int k = tid >> 3, seg = tid & 7;
+    bf16x4 b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) b[e] = k < K1 ? xs[(4 * seg + e) * LX + k] : (__bf16)0.0f;
+    *reinterpret_cast<bf16x4 *>(a.xt + (size_t)k * a.n_pad + m0 + 4 * seg) = b;
+  }
+
+  // B fragments of the three H-deep products: W2p and W3p (packed, K order
+  // of the file header) and rows of W2^T (natural order)
+  auto frag_w2p = [&](int t, int s) { return a.w2p[((size_t)t * S2 + s) * 64 + lane]; };
+  auto frag_w3p = [&](int t, int s) { return a.w3p[((size_t)t * S2 + s) * 64 + lane]; };
+  auto frag_w2t = [&](int t, int s) {
+    return frag_at(a.w2t + (size_t)(32 * t + c) * H + 16 * s + 8 * hh);
+  };
+  // With one tile per wave and at most 16 K steps (H <= 256) every product's
+  // B fragments are requested one phase ahead into pf[] (W2p at the start,
+  // then W3p or W2^T while the previous product finishes); otherwise they are
+  // loaded SB at a time.
+  constexpr bool PRE = TPW == 1 && S2 <= 16;
+  bf16x8 pf[PRE ? S2 : 1];
+  auto product = [&](f32x16 acc, auto afrag, auto bfrag) {
+    if constexpr (PRE) {
+#pragma unroll
+      for (int s = 0; s < S2; ++s) acc = mfma(afrag(s), pf[s], acc);
+    } else {
+#pragma unroll
+      for (int s0 = 0; s0 < S2; s0 += SB) {
+        bf16x8 bfr[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) bfr[u] = bfrag(s0 + u);
+#pragma unroll
+        for (int u = 0; u < SB; ++u) acc = mfma(afrag(s0 + u), bfr[u], acc);
+      }
+    }
+    return acc;
+  };
+  if constexpr (PRE) {
+    if (w < NT) {
+#pragma unroll
+      for (int s = 0; s < S2; ++s) pf[s] = frag_w2p(w, s);
+    }
+  }
+  // W3^T fragments of the dY W3 product, also requested now
+  bf16x8 w3f[TPW][CP / 16];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = w + kTrainWaves * q;
+    if (t >= NT || !train) break;
+#pragma unroll
+    for (int s = 0; s < CP / 16; ++s)
+      w3f[q][s] = frag_at(a.w3t + (size_t)(32 * t + c) * CP + 16 * s + 8 * hh);
+  }
+
+  f32x16 g1[TPW], g2[TPW]; // GELU'(Z1), GELU'(Z2) of the wave's tiles
+  float v[16];
+  // Z1 = X W1^T + b1, H1 = gelu(Z1)
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = w + kTrainWaves * q;
+    if (t >= NT) break;
+    f32x16 acc;
+    const float bv = a.b1[32 * t + c];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = bv;
+#pragma unroll
+    for (int s = 0; s < S1; ++s)
+      acc = mfma(act_frag(xs, LX, c, 16 * s + 8 * hh), a.w1p[(t * S1 + s) * 64 + lane], acc);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      float dg;
+      v[i] = gelu_with_grad(acc[i], dg);
+      g1[q][i] = dg;
+    }
+    store_act(v, h1s, LH, 32 * t + c, a.h1t, a.n_pad, m0, hh);
+  }
+  __syncthreads();
+  // Z2 = H1 W2^T + b2, H2 = gelu(Z2)
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = w + kTrainWaves * q;
+    if (t >= NT) break;
+    f32x16 acc;
+    const float bv = a.b2[32 * t + c];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = bv;
+    acc = product(
+        acc, [&](int s) { return act_frag_perm(h1s, LH, c, s, hh); },
+        [&](int s) { return frag_w2p(t, s); });
+    if constexpr (PRE) { // the next product's fragments
+      if (w < NB3) {
+#pragma unroll
+        for (int s = 0; s < S2; ++s) pf[s] = frag_w3p(w, s);
+      } else if (train) {
+#pragma unroll
+        for (int s = 0; s < S2; ++s) pf[s] = frag_w2t(t, s);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      float dg;
+      v[i] = gelu_with_grad(acc[i], dg);
+      g2[q][i] = dg;
+    }
+    store_act(v, h2s, LH, 32 * t + c, a.h2t, a.n_pad, m0, hh);
+  }
+  __syncthreads();
+  // Y = H2 W3^T + b3 on waves 0 .. NB3-1; training: dY, squared errors
+  if (w < NB3) {
+    const int col = 32 * w + c;
+    f32x16 acc;
+    const float bv = col < a.C ? a.b3[col] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = bv;
+    acc = product(
+        acc, [&](int s) { return act_frag_perm(h2s, LH, c, s, hh); },
+        [&](int s) { return frag_w3p(w, s); });
+    if constexpr (PRE) {
+      if (train && w < NT) {
+#pragma unroll
+        for (int s = 0; s < S2; ++s) pf[s] = frag_w2t(w, s);
+      }
+    }
+    if (!train) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const uint32_t m = m0 + 8 * (i / 4) + 4 * hh + (i % 4);
+        if (m < a.n) a.yout[(size_t)m * CP + col] = acc[i];
+      }
+    } else {
+      float sq = 0.0f, ds = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const uint32_t m = m0 + 8 * (i / 4) + 4 * hh + (i % 4);
+        const float d = (m < a.n && col < a.C) ? acc[i] - tv[i] : 0.0f;
+        sq += d * d;
+        v[i] = a.scale * d;
+        ds += v[i];
+      }
+      store_act(v, dys, LY, col, a.dyt, a.n_pad, m0, hh);
+      ds += __shfl_xor(ds, 32);
+      if (hh == 0) a.bp3[(size_t)blk * CP + col] = ds;
+      sq = wave_sum(sq);
+      if (lane == 0) lred[w] = sq;
+    }
+  }
+  if (!train) return; // uniform over the workgroup
+  __syncthreads();
+  if (tid == 0) a.lossp[blk] = NB3 == 2 ? lred[0] + lred[1] : lred[0];
+  // dZ2 = (dY W3) * gelu'(Z2), into the H2 array
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = w + kTrainWaves * q;
+    if (t >= NT) break;
+    f32x16 acc = {};
+#pragma unroll
+    for (int s = 0; s < CP / 16; ++s)
+      acc = mfma(act_frag(dys, LY, c, 16 * s + 8 * hh), w3f[q][s], acc);
+    float bs = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      v[i] = acc[i] * g2[q][i];
+      bs += v[i];
+    }
+    store_act(v, h2s, LH, 32 * t + c, a.dz2t, a.n_pad, m0, hh);
+    bs += __shfl_xor(bs, 32);
+    if (hh == 0) a.bp2[(size_t)blk * H + 32 * t + c] = bs;
+  }
+  __syncthreads();
+  // dZ1 = (dZ2 W2) * gelu'(Z1)
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = w + kTrainWaves * q;
+    if (t >= NT) break;
+    f32x16 acc = {};
+    acc = product(
+        acc, [&](int s) { return act_frag(h2s, LH, c, 16 * s + 8 * hh); },
+        [&](int s) { return frag_w2t(t, s); });
+    float bs = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      v[i] = acc[i] * g1[q][i];
+      bs += v[i];
+    }
+    store_act(v, nullptr, 0, 32 * t + c, a.dz1t, a.n_pad, m0, hh);
+    bs += __shfl_xor(bs, 32);
+    if (hh == 0) a.bp1[(size_t)blk * H + 32 * t + c] = bs;
+  }
+}
+
+// Gradient g of master parameter p: stored (gradient mode), or one Adam step
+// (Kingma & Ba, Algorithm 1; c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t))
+// followed by the bf16 copies of the new value.
+__device__ __forceinline__ void apply_grad(const GradTilesArgs &g, size_t p, float gv) {
+  if (g.grad) {
+    g.grad[p] = gv;
+    return;
+  }
+  const float mm = g.beta1 * g.m[p] + (1.0f - g.beta1) * gv;
+  const float vv = g.beta2 * g.v[p] + (1.0f - g.beta2) * gv * gv;
+  g.m[p] = mm;
+  g.v[p] = vv;
+  const float th = g.theta[p] - g.lr * (mm * g.c1) / (sqrtf(vv * g.c2) + g.eps);
+  g.theta[p] = th;
+  pack_one(g.sh, p, th, g.w1p, g.w2p, g.w3p);
+  pack_transposed(g.sh, p, th, g.w2t, g.w3t);
+}
+
+__global__ __launch_bounds__(kGradThreads) void mlp_grad_tiles(GradTilesArgs g) {
+  constexpr int NW = kGradThreads / 64;
+  __shared__ float part[NW][16][64];
+  const int H = g.sh.H, F = g.sh.F, C = g.sh.C, NT = H / 32, NB3 = (C + 31) / 32;
+  const size_t off_b1 = (size_t)H * F, off_w2 = off_b1 + H, off_b2 = off_w2 + (size_t)H * H;
+  const size_t off_w3 = off_b2 + H, off_b3 = off_w3 + (size_t)C * H;
+  const int T2 = NT * NT, T1 = NT, T3 = NB3 * NT;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hh = lane >> 5, c = lane & 31;
+  int j = blockIdx.x;
+  if (j >= T2 + T1 + T3) { // biases, one per thread: the row blocks' column sums in block order
+    const int Cp = 32 * NB3, nblk = (int)(g.n_pad / 32);
+    const int first = j - (T2 + T1 + T3);
+    const int idx = first * kGradThreads + tid;
+    if (idx < 2 * H + C) {
+      const float *src;
+      int ld, col;
+      size_t p;
+      if (idx < H) {
+        src = g.bp1, ld = H, col = idx, p = off_b1 + col;
+      } else if (idx < 2 * H) {
+        src = g.bp2, ld = H, col = idx - H, p = off_b2 + col;
+      } else {
+        src = g.bp3, ld = Cp, col = idx - 2 * H, p = off_b3 + col;
+      }
+      float s = 0.0f;
+#pragma unroll 8
+      for (int b = 0; b < nblk; ++b) s += src[(size_t)b * ld + col];
+      apply_grad(g, p, s);
+    }
+    if (first == 0 && tid == 0 && g.loss_out) {
+      float t = 0.0f;
+#pragma unroll 8
+      for (int b = 0; b < nblk; ++b) t += g.lossp[b];
+      *g.loss_out = t / g.loss_div;
+    }
+    return;
+  }
+  // tile: rows r0.. of the A operand (dZ^T), rows c0.. of the B operand
+  const __bf16 *A, *B;
+  int kind, r0, c0;
+  if (j < T2) {
+    kind = 2, r0 = 32 * (j / NT), c0 = 32 * (j % NT), A = g.dz2t, B = g.h1t;
+  } else if ((j -= T2) < T1) {
+    kind = 1, r0 = 32 * j, c0 = 0, A = g.dz1t, B = g.xt;
+  } else {
+    j -= T1;
+    kind = 3, r0 = 32 * (j / NT), c0 = 32 * (j % NT), A = g.dyt, B = g.h2t;
+  }
+  const __bf16 *pa = A + (size_t)(r0 + c) * g.n_pad + 8 * hh;
+  const __bf16 *pb = B + (size_t)(c0 + c) * g.n_pad + 8 * hh;
+  f32x16 acc = {};
+  constexpr int KB = 4; // K steps of a wave whose fragments are loaded together
+  for (uint32_t k0 = 16 * w; k0 < g.n_pad; k0 += KB * 16 * NW) {
+    bf16x8 fa[KB], fb[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const uint32_t k = k0 + u * 16 * NW;
+      fa[u] = k < g.n_pad ? frag_at(pa + k) : bf16x8{};
+      fb[u] = k < g.n_pad ? frag_at(pb + k) : bf16x8{};
+    }
+#pragma unroll
+    for (int u = 0; u < KB; ++u) acc = mfma(fa[u], fb[u], acc);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) part[w][i][lane] = acc[i];
+  __syncthreads();
+  // wave w finishes rows 8 w + 4 hh + e (registers 4 w + e) of the tile
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = 4 * w + e;
+    float gv = part[0][i][lane];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) gv += part[q][i][lane];
+    const int row = r0 + 8 * w + 4 * hh + e, col = c0 + c;
+    if (kind == 2) apply_grad(g, off_w2 + (size_t)row * H + col, gv);
+    else if (kind == 1 && col < F) apply_grad(g, (size_t)row * F + col, gv);
+    else if (kind == 3 && row < C) apply_grad(g, off_w3 + (size_t)row * H + col, gv);
+  }
 }
 
 template <typename K>
@@ -718,7 +842,7 @@ template <int H> hipError_t launch_infer_nb(const MlpFwdArgs &a, hipStream_t s) 
 
 template <int H, int NB3, int S1>
 hipError_t launch_fwd_h(const MlpFwdArgs &a, bool train, hipStream_t stream) {
-  // the training forward is launch_mlp_train_forward (one GEMM per layer)
+  // the training forward is part of launch_mlp_train_rows
   if (train) return hipErrorInvalidValue;
   return launch_infer_h<H, NB3, S1>(a, stream);
 }
@@ -744,71 +868,63 @@ hipError_t launch_mlp_forward(const MlpFwdArgs &a, bool train, hipStream_t strea
   }
 }
 
-hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const float *w2,
-                                   const float *w3, const LossArgs *loss, hipStream_t stream) {
-  if (a.n == 0) return hipSuccess;
-  const int Cp = 32 * ((a.C + 31) / 32);
-  auto gemm = [&](const GemmArgs &g, const float *bias, int epi) {
-    const dim3 grid(((g.M + 31) / 32) * ((g.N + 31) / 32)), block(kGemmThreads);
-    if (epi == 2)
-      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 2>), grid, block, 0, stream, g, bias,
-                         LossArgs{});
-    else if (loss == nullptr)
-      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 3>), grid, block, 0, stream, g, bias,
-                         LossArgs{});
-    else
-      hipLaunchKernelGGL((gemm_bf16<__bf16, float, 4>), grid, block, 0, stream, g, bias, *loss);
-  };
-  // Z1 = X W1^T + b1, H1 = gelu(Z1); Z2 = H1 W2^T + b2, H2 = gelu(Z2); Y = H2 W3^T + b3
-  const int n = (int)a.n;
-  {
-    // layer 1 decodes its inputs (the digits of the batch's configurations)
-    // in the operand load and stores them as X for the backward pass
-    const GemmArgs g1{n, a.H, a.F, nullptr, a.K1, 1, w1, 1, a.F, a.z1out, a.h1out, nullptr, a.H};
-    const dim3 grid(((g1.M + 31) / 32) * ((g1.N + 31) / 32)), block(kGemmThreads);
-    hipLaunchKernelGGL(gemm_layer1, grid, block, 0, stream, g1, a.b1,
-                       FeatArgs{a.sp, a.cfg_raw, a.batch, a.F, a.K1, a.xout});
+namespace {
+
+template <int H, int NB3, int S1>
+hipError_t launch_train_rows_h(const TrainRowsArgs &a, hipStream_t stream) {
+  using TS = TrainShape<H, NB3, S1>;
+  const auto kernel = mlp_train_rows<H, NB3, S1>;
+  if constexpr (TS::lds > 64 * 1024) {
+    static const hipError_t set = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)TS::lds);
+    if (set != hipSuccess) return set;
   }
-  gemm(GemmArgs{n, a.H, a.H, a.h1out, a.H, 1, w2, 1, a.H, a.z2out, a.h2out, nullptr, a.H}, a.b2,
-       2);
-  gemm(GemmArgs{n, a.C, a.H, a.h2out, a.H, 1, w3, 1, a.H, a.yout, nullptr, nullptr, Cp}, a.b3, 3);
+  hipLaunchKernelGGL(kernel, dim3(a.n_pad / 32), dim3(kTrainWaves * 64), TS::lds, stream, a);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(const GemmArgs &g, int a_bf16, int b_bf16, int epi, hipStream_t stream) {
-  const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
-  if (tiles == 0) return hipSuccess;
-  const dim3 grid(tiles), block(kGemmThreads);
-#define GEMM_CASE(TA, TB, E)                                                                   \
-  hipLaunchKernelGGL((gemm_bf16<TA, TB, E>), grid, block, 0, stream, g, nullptr, LossArgs{})
-  if (a_bf16 && b_bf16 && epi == 0) GEMM_CASE(__bf16, __bf16, 0);
-  else if (a_bf16 && !b_bf16 && epi == 1) GEMM_CASE(__bf16, float, 1);
-  else if (a_bf16 && !b_bf16 && epi == 0) GEMM_CASE(__bf16, float, 0);
-  else if (a_bf16 && b_bf16 && epi == 1) GEMM_CASE(__bf16, __bf16, 1);
-  else return hipErrorInvalidValue;
-#undef GEMM_CASE
+template <int H> hipError_t launch_train_rows_nb(const TrainRowsArgs &a, hipStream_t s) {
+  const int nb3 = (a.C + 31) / 32, s1 = a.K1 / 16;
+  if (nb3 == 1 && s1 == 1) return launch_train_rows_h<H, 1, 1>(a, s);
+  if (nb3 == 1 && s1 == 2) return launch_train_rows_h<H, 1, 2>(a, s);
+  if (nb3 == 2 && s1 == 1) return launch_train_rows_h<H, 2, 1>(a, s);
+  if (nb3 == 2 && s1 == 2) return launch_train_rows_h<H, 2, 2>(a, s);
+  return hipErrorInvalidValue;
+}
+
+} // namespace
+
+hipError_t launch_mlp_train_rows(const TrainRowsArgs &a, hipStream_t stream) {
+  if (a.n == 0) return hipSuccess;
+  if (a.n_pad % 32 != 0 || a.n_pad < a.n) return hipErrorInvalidValue;
+  switch (a.H) {
+  case 64: return launch_train_rows_nb<64>(a, stream);
+  case 128: return launch_train_rows_nb<128>(a, stream);
+  case 256: return launch_train_rows_nb<256>(a, stream);
+  case 512: return launch_train_rows_nb<512>(a, stream);
+  default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_mlp_gather_rows(const SpaceDev *sp, const uint32_t *cfg_raw,
+                                  const int32_t *batch, const float *targets, uint32_t steps,
+                                  uint32_t n, uint32_t n_pad, int F, int K1, int C, __bf16 *xg,
+                                  float *tg, hipStream_t stream) {
+  const uint64_t threads = (uint64_t)steps * n_pad;
+  if (threads == 0) return hipSuccess;
+  if (n_pad < n || (K1 != 16 && K1 != 32)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mlp_gather_rows, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                     stream, sp, cfg_raw, batch, targets, steps, n, n_pad, F, K1, C, xg, tg);
   return hipGetLastError();
 }
 
-hipError_t launch_bwd_group(const GemmArgs &g0, int epi0, const GemmArgs &g1, int epi1,
-                            const ColSumJob &cs, hipStream_t stream) {
-  auto tiles = [](const GemmArgs &g) {
-    return g.M > 0 && g.N > 0 ? ((g.M + 31) / 32) * ((g.N + 31) / 32) : 0;
-  };
-  const int blocks = tiles(g0) + tiles(g1) + (cs.ncols + 63) / 64;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(gemm_bwd_group, dim3(blocks), dim3(kGemmThreads), 0, stream, g0, epi0, g1,
-                     epi1, cs);
-  return hipGetLastError();
-}
-
-hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dyf, int n, int H,
-                             int C, int Cp, float *gb1, float *gb2, float *gb3,
-                             const float *partial, int n_partial, float *loss_out,
-                             hipStream_t stream) {
-  const int total = 2 * H + C;
-  hipLaunchKernelGGL(bias_grads, dim3((total + 63) / 64), dim3(kBiasWaves * 64), 0, stream, dz1,
-                     dz2, dyf, n, H, C, Cp, gb1, gb2, gb3, partial, n_partial, loss_out);
+hipError_t launch_mlp_grad_tiles(const GradTilesArgs &g, hipStream_t stream) {
+  const int NT = g.sh.H / 32, NB3 = (g.sh.C + 31) / 32;
+  if (g.n_pad == 0 || g.n_pad % 32 != 0 || NB3 < 1 || NB3 > 2 || g.sh.K1 > 32)
+    return hipErrorInvalidValue;
+  const int blocks = NT * NT + NT + NB3 * NT + (2 * g.sh.H + g.sh.C + kGradThreads - 1) / kGradThreads;
+  hipLaunchKernelGGL(mlp_grad_tiles, dim3(blocks), dim3(kGradThreads), 0, stream, g);
   return hipGetLastError();
 }
 
@@ -817,15 +933,6 @@ hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n,
                                hipStream_t stream) {
   hipLaunchKernelGGL(pack_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh,
                      theta, n, w1p, w2p, w3p, w2t, w3t);
-  return hipGetLastError();
-}
-
-hipError_t launch_adam_pack(const MlpShape &sh, float *theta, float *m, float *v,
-                            const float *grad, size_t n, float lr, float b1, float b2, float eps,
-                            float c1, float c2, __bf16 *w1p, __bf16 *w2p, __bf16 *w3p,
-                            __bf16 *w2t, __bf16 *w3t, hipStream_t stream) {
-  hipLaunchKernelGGL(adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh, theta,
-                     m, v, grad, n, lr, b1, b2, eps, c1, c2, w1p, w2p, w3p, w2t, w3t);
   return hipGetLastError();
 }
 

@@ -12,47 +12,57 @@ namespace cgs {
 hipError_t launch_rows_to_columns(const float *d_src, uint32_t n, int C, float *d_P,
                                   uint64_t stride, hipStream_t stream);
 
-// The perceptron's training forward pass (features, then one GEMM per layer
-// with the bias and GELU in its epilogue) into a.xout, z1out, h1out, z2out,
-// h2out, yout; w1, w2, w3: the fp32 master weights ([H][F], [H][H], [C][H]).
-// With `loss` set (training), the output layer's epilogue also forms the
-// error d = Y - T against the targets and writes dY = scale * d (fp32 dyf and
-// bf16 dyb, [n][Cp] like Y, padding columns untouched) and, per 32 x 32
-// output tile, the sum of d^2 into partial[tile] (ceil(n/32) * ceil(C/32)
-// tiles, row-major over the tiles).
-struct LossArgs {
-  const float *targets; // [rows][C]; output row i takes target row batch[i] (or i)
-  const int32_t *batch;
-  float scale;          // 2 / (n C)
-  float *dyf;
-  __bf16 *dyb;
-  float *partial;
+// One training step of the perceptron in two launches (mlp.hip), after
+// launch_mlp_gather_rows has gathered the rows of a run of steps.
+// launch_mlp_train_rows: per 32 rows of the batch, the forward pass, the
+// loss terms (dY = scale (Y - T)) and the backward chain to dZ1; it writes
+// the weight gradients' operands transposed, [feature][n_pad] bf16 (xt: 32
+// feature rows, zero past F; h1t, h2t, dz2t, dz1t: H rows; dyt: Cp rows),
+// the column sums of dY, dZ2 and dZ1 over each block of 32 rows
+// (bp3[blk][Cp], bp2[blk][H], bp1[blk][H]) and each block's sum of squared
+// errors (lossp[blk]).  Without train only the forward pass runs and Y goes
+// to yout[n][Cp].  Rows past n are zeros.
+struct TrainRowsArgs {
+  const __bf16 *xin;        // the step's features [n_pad][K1] (launch_mlp_gather_rows)
+  const float *tin;         // the step's targets [n][C], or null (forward only)
+  bool train;               // tin set
+  uint32_t n, n_pad;        // rows; a multiple of 32 >= n
+  int F, H, C, K1;
+  float scale;              // 2 / (n C)
+  const bf16x8 *w1p, *w2p, *w3p;
+  const __bf16 *w2t, *w3t;
+  const float *b1, *b2, *b3;
+  float *yout;
+  __bf16 *xt, *h1t, *h2t, *dyt, *dz2t, *dz1t;
+  float *bp1, *bp2, *bp3, *lossp;
 };
-hipError_t launch_mlp_train_forward(const MlpFwdArgs &a, const float *w1, const float *w2,
-                                   const float *w3, const LossArgs *loss, hipStream_t stream);
-// Column sums dst[c] = sum over rows r < nrows of src[r * ld + c], c < ncols,
-// in row order split over the waves of a workgroup; with loss_out set, also
-// *loss_out = (partial[0] + ... + partial[n_partial - 1]) / loss_div.
-struct ColSumJob {
-  const float *src;
-  int ld, nrows, ncols;
-  float *dst;
-  const float *partial;
-  int n_partial;
+hipError_t launch_mlp_train_rows(const TrainRowsArgs &a, hipStream_t stream);
+// The features (and targets) of `steps` steps of n rows: step s, row r is
+// pair batch[s n + r] (pair r when batch is null); xg[s][n_pad][K1] bf16,
+// zero rows past n; tg[s][n][C] when targets is set.
+hipError_t launch_mlp_gather_rows(const SpaceDev *sp, const uint32_t *cfg_raw,
+                                  const int32_t *batch, const float *targets, uint32_t steps,
+                                  uint32_t n, uint32_t n_pad, int F, int K1, int C, __bf16 *xg,
+                                  float *tg, hipStream_t stream);
+// launch_mlp_grad_tiles: the weight gradients dW2 = dZ2^T H1, dW1 = dZ1^T X,
+// dW3 = dY^T H2 by 32 x 32 tiles and the bias gradients (the blocks' column
+// sums added in block order) from launch_mlp_train_rows's outputs; with grad
+// set they are stored there (the layout of theta), otherwise one Adam step
+// updates theta, m, v and the packed bf16 copies.  loss_out (if set) gets
+// (lossp[0] + ... ) / loss_div.
+struct GradTilesArgs {
+  MlpShape sh;
+  uint32_t n_pad;
+  const __bf16 *xt, *h1t, *h2t, *dyt, *dz2t, *dz1t;
+  const float *bp1, *bp2, *bp3, *lossp;
   float *loss_out;
   float loss_div;
+  float *grad;
+  float *theta, *m, *v;
+  float lr, beta1, beta2, eps, c1, c2;
+  __bf16 *w1p, *w2p, *w3p, *w2t, *w3t;
 };
-// One level of the backward pass as one launch: products g0 and g1 (bf16
-// operands; epilogue 0: C = A B; 1: dZ = (A B) * gelu'(Z), fp32 and bf16)
-// and the column sums cs; an empty product has M = 0, no sums ncols = 0.
-hipError_t launch_bwd_group(const GemmArgs &g0, int epi0, const GemmArgs &g1, int epi1,
-                            const ColSumJob &cs, hipStream_t stream);
-// Bias gradients (column sums of dZ1, dZ2 [n][H] and dY [n][Cp]) and the
-// mean squared error: loss_out = (partial[0] + ... + partial[n_partial - 1]) / (n C).
-hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dyf, int n, int H,
-                             int C, int Cp, float *gb1, float *gb2, float *gb3,
-                             const float *partial, int n_partial, float *loss_out,
-                             hipStream_t stream);
+hipError_t launch_mlp_grad_tiles(const GradTilesArgs &g, hipStream_t stream);
 // The bf16 weights from the fp32 masters theta[n]: the inference fragments
 // w1p, w2p, w3p, and the transposed copies w2t[k][o] = W2[o][k] ([H][H]) and
 // w3t[k][c] = W3[c][k] ([H][Cp], Cp = C rounded up to 32) that the backward
@@ -60,12 +70,6 @@ hipError_t launch_bias_grads(const float *dz1, const float *dz2, const float *dy
 hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
                                __bf16 *w2p, __bf16 *w3p, __bf16 *w2t, __bf16 *w3t,
                                hipStream_t stream);
-// One Adam step on theta (moments m, v; c1, c2 the bias corrections of this
-// step), then the same packing of the updated weights.
-hipError_t launch_adam_pack(const MlpShape &sh, float *theta, float *m, float *v,
-                            const float *grad, size_t n, float lr, float b1, float b2, float eps,
-                            float c1, float c2, __bf16 *w1p, __bf16 *w2p, __bf16 *w3p,
-                            __bf16 *w2t, __bf16 *w3t, hipStream_t stream);
 
 // ---- regression-tree fitting (Sect. 3.4.2)
 FastDiv make_fastdiv(uint32_t d);
