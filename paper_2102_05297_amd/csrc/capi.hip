@@ -97,6 +97,7 @@ struct cgs_model_s {
   float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr, *d_grad = nullptr;
   __bf16 *d_w1p = nullptr, *d_w2p = nullptr, *d_w3p = nullptr;
   __bf16 *d_w2t = nullptr, *d_w3t = nullptr; // [H][H], [H][Cp]: backward operands
+  __bf16 *d_w1n = nullptr, *d_w2n = nullptr, *d_w3n = nullptr; // row-major, training forward
   size_t n_w1p = 0, n_w2p = 0, n_w3p = 0;
   uint64_t adam_t = 0;
   int n_cu = 256;
@@ -460,12 +461,20 @@ void destroy_model(cgs_model m) {
   dfree(m->d_w3p);
   dfree(m->d_w2t);
   dfree(m->d_w3t);
+  dfree(m->d_w1n);
+  dfree(m->d_w2n);
+  dfree(m->d_w3n);
   dfree(m->d_poly);
   dfree(m->d_beta64);
   dfree(m->d_beta32);
   free_mlp_scratch(m);
   destroy_space(m->space);
   delete m;
+}
+
+MlpCopies mlp_copies(cgs_model m) {
+  return MlpCopies{m->d_w1p, m->d_w2p, m->d_w3p, m->d_w2t, m->d_w3t,
+                   m->d_w1n, m->d_w2n, m->d_w3n};
 }
 
 MlpFwdArgs mlp_args(cgs_model m) {
@@ -1291,7 +1300,7 @@ hipError_t ensure_mlp_scratch(cgs_model m, uint32_t rows) {
   if (m->scratch_rows >= rows) return hipSuccess;
   free_mlp_scratch(m);
   const size_t H = m->sh.H, Cp = (size_t)32 * ((m->sh.C + 31) / 32);
-  const size_t n_pad = ((size_t)rows + 31) / 32 * 32, nblk = n_pad / 32;
+  const size_t n_pad = ((size_t)rows + 31) / 32 * 32, nblk = n_pad / 16; // 16-row blocks
   hipError_t e = dalloc(&m->d_xt, 32 * n_pad);
   if (e == hipSuccess) e = dalloc(&m->d_h1t, H * n_pad);
   if (e == hipSuccess) e = dalloc(&m->d_h2t, H * n_pad);
@@ -1332,14 +1341,13 @@ TrainRowsArgs train_rows_args(cgs_model m, uint32_t k, uint32_t n, bool train) {
   a.train = train;
   a.n = n;
   a.n_pad = (n + 31) / 32 * 32;
-  a.F = m->sh.F;
   a.H = m->sh.H;
   a.C = m->sh.C;
   a.K1 = m->sh.K1;
   a.scale = 2.0f / (float)(n * (uint32_t)m->sh.C);
-  a.w1p = reinterpret_cast<const bf16x8 *>(m->d_w1p);
-  a.w2p = reinterpret_cast<const bf16x8 *>(m->d_w2p);
-  a.w3p = reinterpret_cast<const bf16x8 *>(m->d_w3p);
+  a.w1n = m->d_w1n;
+  a.w2n = m->d_w2n;
+  a.w3n = m->d_w3n;
   a.w2t = m->d_w2t;
   a.w3t = m->d_w3t;
   a.b1 = m->d_theta + m->off_b1;
@@ -1398,11 +1406,7 @@ hipError_t mlp_step_rows(cgs_model m, uint32_t k, uint32_t n, float *d_loss,
   g.theta = m->d_theta;
   g.m = m->d_m;
   g.v = m->d_v;
-  g.w1p = m->d_w1p;
-  g.w2p = m->d_w2p;
-  g.w3p = m->d_w3p;
-  g.w2t = m->d_w2t;
-  g.w3t = m->d_w3t;
+  g.cp = mlp_copies(m);
   if (adam) {
     g.lr = adam->lr;
     g.beta1 = adam->beta1;
@@ -1493,6 +1497,9 @@ extern "C" cgs_status cgs_model_load_mlp(cgs_space sp, const cgs_mlp_desc *desc,
   if (e == hipSuccess) e = dalloc(&m->d_w3p, m->n_w3p);
   if (e == hipSuccess) e = dalloc(&m->d_w2t, m->n_w2p);
   if (e == hipSuccess) e = dalloc(&m->d_w3t, m->n_w3p);
+  if (e == hipSuccess) e = dalloc(&m->d_w1n, H * 32);
+  if (e == hipSuccess) e = dalloc(&m->d_w2n, m->n_w2p);
+  if (e == hipSuccess) e = dalloc(&m->d_w3n, m->n_w3p);
   if (e == hipSuccess) e = dalloc(&m->d_P, (size_t)C * m->stride);
   if (e == hipSuccess)
     e = hipMemcpyAsync(m->d_theta, params, n * sizeof(float), hipMemcpyHostToDevice, st);
@@ -1500,12 +1507,14 @@ extern "C" cgs_status cgs_model_load_mlp(cgs_space sp, const cgs_mlp_desc *desc,
   if (e == hipSuccess) e = hipMemsetAsync(m->d_v, 0, n * sizeof(float), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->d_w1p, 0, m->n_w1p * sizeof(__bf16), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->d_w3p, 0, m->n_w3p * sizeof(__bf16), st);
-  // w3t's padding columns (C .. Cp-1) are read by the backward product
+  // the padding of w3t (columns C .. Cp-1), w1n (features F .. 31) and w3n
+  // (rows C .. Cp-1) is read by the training products
   if (e == hipSuccess) e = hipMemsetAsync(m->d_w3t, 0, m->n_w3p * sizeof(__bf16), st);
+  if (e == hipSuccess) e = hipMemsetAsync(m->d_w1n, 0, H * 32 * sizeof(__bf16), st);
+  if (e == hipSuccess) e = hipMemsetAsync(m->d_w3n, 0, m->n_w3p * sizeof(__bf16), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->d_P, 0, (size_t)C * m->stride * sizeof(float), st);
   if (e == hipSuccess)
-    e = launch_pack_weights(m->sh, m->d_theta, n, m->d_w1p, m->d_w2p, m->d_w3p, m->d_w2t,
-                            m->d_w3t, st);
+    e = launch_pack_weights(m->sh, m->d_theta, n, mlp_copies(m), st);
   if (e != hipSuccess) {
     destroy_model(m);
     return fail(e == hipErrorOutOfMemory ? CGS_ENOMEM : CGS_EDEVICE, "perceptron buffers: %s",

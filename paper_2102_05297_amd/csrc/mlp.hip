@@ -366,31 +366,48 @@ __device__ __forceinline__ void pack_transposed(const MlpShape &sh, size_t p, fl
   }
 }
 
+// Row-major copies for the training kernel's B operands: w1n[o][32] (features
+// padded to 32), w2n[o][k] = W2[o][k], w3n[c][k] = W3[c][k] ([Cp][H]).
+__device__ __forceinline__ void pack_natural(const MlpShape &sh, size_t p, float v, __bf16 *w1n,
+                                             __bf16 *w2n, __bf16 *w3n) {
+  const size_t H = sh.H, F = sh.F, first_w2 = H * F + H, first_w3 = first_w2 + H * H + H;
+  if (p < H * F) {
+    w1n[(p / F) * 32 + p % F] = (__bf16)v;
+  } else if (p >= first_w2 && p < first_w2 + H * H) {
+    w2n[p - first_w2] = (__bf16)v;
+  } else if (p >= first_w3 && p < first_w3 + (size_t)sh.C * H) {
+    w3n[p - first_w3] = (__bf16)v;
+  }
+}
+
+__device__ __forceinline__ void pack_all(const MlpShape &sh, size_t p, float v, const MlpCopies &cp) {
+  pack_one(sh, p, v, cp.w1p, cp.w2p, cp.w3p);
+  pack_transposed(sh, p, v, cp.w2t, cp.w3t);
+  pack_natural(sh, p, v, cp.w1n, cp.w2n, cp.w3n);
+}
+
 __global__ __launch_bounds__(256) void pack_weights(MlpShape sh, const float *__restrict__ theta,
-                                                    size_t n, __bf16 *w1p, __bf16 *w2p,
-                                                    __bf16 *w3p, __bf16 *w2t, __bf16 *w3t) {
+                                                    size_t n, MlpCopies cp) {
   const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
-  const float th = theta[p];
-  pack_one(sh, p, th, w1p, w2p, w3p);
-  pack_transposed(sh, p, th, w2t, w3t);
+  pack_all(sh, p, theta[p], cp);
 }
 
 // ------------------------------------------------------------ training step
 // One Adam step is two launches.
-//  mlp_train_rows: one workgroup of kTrainWaves waves per 32 rows of the
-//    batch.  Z = A W^T + b by 32 x 32 output tiles (standard orientation:
-//    the activations are the MFMA A operand, read from LDS, and the weights
-//    the B operand, read as the packed fragments of the inference path), a
-//    tile per wave and layer, the activations exchanged through LDS; then
-//    the loss terms and dY = scale (Y - T), and the backward chain
+//  mlp_train_rows: one workgroup per 16 rows of the batch, one wave per
+//    16-column output tile of a hidden layer (two for H = 512).
+//    Z = A W^T + b on v_mfma_f32_16x16x32_bf16 with the activations as the
+//    A operand, read from LDS, and the weights as the B operand, read from
+//    row-major bf16 copies; the activations pass between layers through LDS.
+//    Then the loss terms and dY = scale (Y - T), and the backward chain
 //    dZ2 = (dY W3) * gelu'(Z2), dZ1 = (dZ2 W2) * gelu'(Z1) with W3 and W2
 //    from their transposed bf16 copies.  Every product of the chain is local
-//    to the rows; each wave keeps the pre-activations of its own tiles in
-//    registers for the derivatives.  It stores the operands of the weight
-//    gradients transposed (feature-major, the batch contiguous, so the next
-//    launch reads them as vector fragments), the column sums of dY, dZ2 and
-//    dZ1 over its rows, and its sum of squared errors.
+//    to the rows; each wave keeps GELU' of its own tiles in registers from
+//    the forward pass.  It stores the operands of the weight gradients
+//    transposed (feature-major, the batch contiguous, so the next launch
+//    reads them as vector fragments), the column sums of dY, dZ2 and dZ1
+//    over its rows, and its sum of squared errors.
 //  mlp_grad_tiles: one workgroup per 32 x 32 tile of dW2 = dZ2^T H1,
 //    dW1 = dZ1^T X and dW3 = dY^T H2 (the batch as the reduction dimension,
 //    split over the waves and added in wave order) and one per 256 biases
@@ -398,57 +415,56 @@ __global__ __launch_bounds__(256) void pack_weights(MlpShape sh, const float *__
 //    its gradients or applies Adam to its parameters and rewrites their bf16
 //    copies.
 // Rows past the batch carry X = 0 and dY = 0, so they add nothing.
-constexpr int kTrainWaves = 8;
+// Layout of v_mfma_f32_16x16x32_bf16 (checked on the GPU with an in-bounds
+// probe): lane l holds A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16]
+// for j = 0..7, and D[4 (l / 16) + r][l % 16] for r = 0..3.
 constexpr int kGradThreads = 256;
 
+typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
-typedef __attribute__((ext_vector_type(2))) uint32_t u32x2;
-typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
 
-// A operand (row = lane % 32) from an LDS activation array with row stride
-// ld: 8 consecutive features from k.
-__device__ __forceinline__ bf16x8 act_frag(const __bf16 *base, int ld, int row, int k) {
-  return *reinterpret_cast<const bf16x8 *>(base + row * ld + k);
+__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
-// The same in the packed weights' K order: slot j of lane half hh at step s
-// holds feature 16 s + 8 (j / 4) + 4 hh + (j % 4) (the file header's kperm).
-__device__ __forceinline__ bf16x8 act_frag_perm(const __bf16 *base, int ld, int row, int s,
-                                                int hh) {
-  const __bf16 *p = base + row * ld + 16 * s + 4 * hh;
-  const u32x2 lo = *reinterpret_cast<const u32x2 *>(p);
-  const u32x2 hi = *reinterpret_cast<const u32x2 *>(p + 8);
-  const u32x4 u = {lo.x, lo.y, hi.x, hi.y};
-  return __builtin_bit_cast(bf16x8, u);
-}
+
 __device__ __forceinline__ bf16x8 frag_at(const __bf16 *p) {
   return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-// One lane's accumulator column (rows 8 (i / 4) + 4 hh + (i % 4), column
-// col) as bf16: into the LDS array (row stride ld; none when lds is null)
-// and transposed into dst[col][m0 + row] (row length n_pad, 4 rows a store).
-__device__ __forceinline__ void store_act(const float (&v)[16], __bf16 *lds, int ld, int col,
-                                          __bf16 *dst, uint32_t n_pad, uint32_t m0, int hh) {
+// One lane's 4 accumulator values (rows 4 kg + r of column col) as bf16:
+// into the LDS array (row stride ld; none when lds is null) and transposed
+// into dst[col][m0 + 4 kg .. + 3] (row length n_pad), one 8-byte store.
+__device__ __forceinline__ void store_act4(const float (&v)[4], __bf16 *lds, int ld, int col,
+                                           __bf16 *dst, uint32_t n_pad, uint32_t m0, int kg) {
+  bf16x4 b;
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    bf16x4 b;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      b[e] = (__bf16)v[4 * g + e];
-      if (lds) lds[(8 * g + 4 * hh + e) * ld + col] = b[e];
-    }
-    *reinterpret_cast<bf16x4 *>(dst + (size_t)col * n_pad + m0 + 8 * g + 4 * hh) = b;
+  for (int r = 0; r < 4; ++r) {
+    b[r] = (__bf16)v[r];
+    if (lds) lds[(4 * kg + r) * ld + col] = b[r];
   }
+  *reinterpret_cast<bf16x4 *>(dst + (size_t)col * n_pad + m0 + 4 * kg) = b;
 }
 
-template <int H, int NB3, int S1> struct TrainShape {
-  static constexpr int NT = H / 32;                                // tiles of a hidden layer
-  static constexpr int TPW = (NT + kTrainWaves - 1) / kTrainWaves; // tiles per wave
-  static constexpr int K1 = 16 * S1, CP = 32 * NB3;
-  // LDS row strides (bf16), padded by 16 bytes so that the 32 rows of a
-  // fragment load start in different banks
-  static constexpr int LX = K1 + 8, LH = H + 8, LY = CP + 8;
-  static constexpr size_t lds = (size_t)32 * (LX + 2 * LH + LY) * sizeof(__bf16) + 16;
+// Sum over the 16 rows of a tile column: the lane's 4 values, then the 4
+// lane groups; the result is in every lane of the column.
+__device__ __forceinline__ float column_sum16(float s) {
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  return s;
+}
+
+template <int H> constexpr int train_waves() { return H / 16 < 16 ? H / 16 : 16; }
+
+template <int H, int NB3> struct TrainShape {
+  static constexpr int NT = H / 16;                  // 16-column tiles of a hidden layer
+  static constexpr int NW = train_waves<H>();        // waves
+  static constexpr int TPW = NT / NW;                // tiles per wave
+  static constexpr int CP = 32 * NB3, NT3 = CP / 16; // output columns and tiles
+  static constexpr int KS = H / 32;                  // K steps of an H-deep product
+  // LDS row strides (bf16), padded by 16 bytes so that the 16 rows of a
+  // fragment load start in different banks; features padded to 32
+  static constexpr int LX = 32 + 8, LH = H + 8, LY = CP + 8;
+  static constexpr size_t lds = (size_t)16 * (LX + 2 * LH + LY) * sizeof(__bf16) + 16 * sizeof(float);
 };
 
 // Rows of `steps` training steps of n rows each (step s, row r: pair
@@ -480,226 +496,172 @@ __global__ __launch_bounds__(256) void mlp_gather_rows(const SpaceDev *__restric
     for (int c = 0; c < C; ++c) tg[row * C + c] = targets[(size_t)src * C + c];
 }
 
-template <int H, int NB3, int S1>
-__global__ __launch_bounds__(kTrainWaves * 64) void mlp_train_rows(TrainRowsArgs a) {
-  using TS = TrainShape<H, NB3, S1>;
-  constexpr int NT = TS::NT, TPW = TS::TPW, K1 = TS::K1, CP = TS::CP, S2 = H / 16;
-  constexpr int SB = S2 < 8 ? S2 : 8; // K steps whose weight fragments are loaded together
+template <int H, int NB3>
+__global__ __launch_bounds__(train_waves<H>() * 64) void mlp_train_rows(TrainRowsArgs a) {
+  using TS = TrainShape<H, NB3>;
+  constexpr int NW = TS::NW, TPW = TS::TPW, CP = TS::CP, NT3 = TS::NT3, KS = TS::KS;
+  constexpr int SB = KS < 8 ? KS : 8; // K steps whose weight fragments are loaded together
   constexpr int LX = TS::LX, LH = TS::LH, LY = TS::LY;
+  static_assert(NT3 <= NW, "one output tile per wave");
   extern __shared__ __align__(16) unsigned char train_lds[];
   __bf16 *xs = reinterpret_cast<__bf16 *>(train_lds);
-  __bf16 *h1s = xs + 32 * LX;
-  __bf16 *h2s = h1s + 32 * LH; // H2, then dZ2
-  __bf16 *dys = h2s + 32 * LH;
-  float *lred = reinterpret_cast<float *>(dys + 32 * LY);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hh = lane >> 5, c = lane & 31;
-  const uint32_t blk = blockIdx.x, m0 = 32u * blk;
+  __bf16 *h1s = xs + 16 * LX;
+  __bf16 *h2s = h1s + 16 * LH; // H2, then dZ2
+  __bf16 *dys = h2s + 16 * LH;
+  float *lred = reinterpret_cast<float *>(dys + 16 * LY);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, kg = lane >> 4, r16 = lane & 15;
+  const uint32_t blk = blockIdx.x, m0 = 16u * blk;
   const bool train = a.train;
 
   // the output waves' targets, requested before anything else
-  float tv[16];
-  if (train && w < NB3) {
-    const int col = 32 * w + c;
+  float tv[4];
+  if (train && w < NT3) {
+    const int col = 16 * w + r16;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const uint32_t m = m0 + 8 * (i / 4) + 4 * hh + (i % 4);
-      tv[i] = (m < a.n && col < a.C) ? a.tin[(size_t)m * a.C + col] : 0.0f;
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t m = m0 + 4 * kg + r;
+      tv[r] = (m < a.n && col < a.C) ? a.tin[(size_t)m * a.C + col] : 0.0f;
     }
   }
-  // the block's features (gathered rows, zeros past n)
-  if (tid < 32 * K1 / 8) {
-    const int row = tid / (K1 / 8), seg = tid % (K1 / 8);
-    *reinterpret_cast<bf16x8 *>(xs + row * LX + 8 * seg) =
-        frag_at(a.xin + (size_t)(m0 + row) * K1 + 8 * seg);
+  // the block's features: 16 gathered rows, padded to 32 with zeros
+  if (tid < 64) {
+    const int row = tid >> 2, seg = tid & 3;
+    const bf16x8 x = 8 * seg < a.K1 ? frag_at(a.xin + (size_t)(m0 + row) * a.K1 + 8 * seg)
+                                    : bf16x8{};
+    *reinterpret_cast<bf16x8 *>(xs + row * LX + 8 * seg) = x;
   }
   __syncthreads();
-  if (tid < 256) { // X^T for dW1: 32 feature rows, zeros past K1
-    const int k = tid >> 3, seg = tid & 7;
+  if (tid < 128) { // X^T for dW1: 32 feature rows, zeros past K1
+    const int k = tid >> 2, seg = tid & 3;
     bf16x4 b;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) b[e] = k < K1 ? xs[(4 * seg + e) * LX + k] : (__bf16)0.0f;
+    for (int e = 0; e < 4; ++e) b[e] = xs[(4 * seg + e) * LX + k];
     *reinterpret_cast<bf16x4 *>(a.xt + (size_t)k * a.n_pad + m0 + 4 * seg) = b;
   }
 
-  // B fragments of the three H-deep products: W2p and W3p (packed, K order
-  // of the file header) and rows of W2^T (natural order)
-  auto frag_w2p = [&](int t, int s) { return a.w2p[((size_t)t * S2 + s) * 64 + lane]; };
-  auto frag_w3p = [&](int t, int s) { return a.w3p[((size_t)t * S2 + s) * 64 + lane]; };
-  auto frag_w2t = [&](int t, int s) {
-    return frag_at(a.w2t + (size_t)(32 * t + c) * H + 16 * s + 8 * hh);
-  };
-  // With one tile per wave and at most 16 K steps (H <= 256) every product's
-  // B fragments are requested one phase ahead into pf[] (W2p at the start,
-  // then W3p or W2^T while the previous product finishes); otherwise they are
-  // loaded SB at a time.
-  constexpr bool PRE = TPW == 1 && S2 <= 16;
-  bf16x8 pf[PRE ? S2 : 1];
-  auto product = [&](f32x16 acc, auto afrag, auto bfrag) {
-    if constexpr (PRE) {
+  f32x4 g1[TPW], g2[TPW]; // GELU'(Z1), GELU'(Z2) of the wave's tiles
+  float v[4];
+  // acc += the H-deep product of the LDS activations (row stride LH) with
+  // the weight rows wr (K contiguous), SB fragments in flight at a time
+  auto product = [&](f32x4 acc, const __bf16 *act, const __bf16 *wr) {
 #pragma unroll
-      for (int s = 0; s < S2; ++s) acc = mfma(afrag(s), pf[s], acc);
-    } else {
+    for (int s0 = 0; s0 < KS; s0 += SB) {
+      bf16x8 bfr[SB];
 #pragma unroll
-      for (int s0 = 0; s0 < S2; s0 += SB) {
-        bf16x8 bfr[SB];
+      for (int u = 0; u < SB; ++u) bfr[u] = frag_at(wr + 32 * (s0 + u));
 #pragma unroll
-        for (int u = 0; u < SB; ++u) bfr[u] = bfrag(s0 + u);
-#pragma unroll
-        for (int u = 0; u < SB; ++u) acc = mfma(afrag(s0 + u), bfr[u], acc);
-      }
+      for (int u = 0; u < SB; ++u)
+        acc = mfma16(frag_at(act + r16 * LH + 32 * (s0 + u) + 8 * kg), bfr[u], acc);
     }
     return acc;
   };
-  if constexpr (PRE) {
-    if (w < NT) {
-#pragma unroll
-      for (int s = 0; s < S2; ++s) pf[s] = frag_w2p(w, s);
-    }
-  }
-  // W3^T fragments of the dY W3 product, also requested now
-  bf16x8 w3f[TPW][CP / 16];
-#pragma unroll
-  for (int q = 0; q < TPW; ++q) {
-    const int t = w + kTrainWaves * q;
-    if (t >= NT || !train) break;
-#pragma unroll
-    for (int s = 0; s < CP / 16; ++s)
-      w3f[q][s] = frag_at(a.w3t + (size_t)(32 * t + c) * CP + 16 * s + 8 * hh);
-  }
-
-  f32x16 g1[TPW], g2[TPW]; // GELU'(Z1), GELU'(Z2) of the wave's tiles
-  float v[16];
   // Z1 = X W1^T + b1, H1 = gelu(Z1)
-#pragma unroll
+#pragma unroll 1
   for (int q = 0; q < TPW; ++q) {
-    const int t = w + kTrainWaves * q;
-    if (t >= NT) break;
-    f32x16 acc;
-    const float bv = a.b1[32 * t + c];
+    const int col = 16 * (w + NW * q) + r16;
+    const float bv = a.b1[col];
+    f32x4 acc = {bv, bv, bv, bv};
+    acc = mfma16(frag_at(xs + r16 * LX + 8 * kg), frag_at(a.w1n + (size_t)col * 32 + 8 * kg),
+                 acc);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = bv;
-#pragma unroll
-    for (int s = 0; s < S1; ++s)
-      acc = mfma(act_frag(xs, LX, c, 16 * s + 8 * hh), a.w1p[(t * S1 + s) * 64 + lane], acc);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int r = 0; r < 4; ++r) {
       float dg;
-      v[i] = gelu_with_grad(acc[i], dg);
-      g1[q][i] = dg;
+      v[r] = gelu_with_grad(acc[r], dg);
+      g1[q][r] = dg;
     }
-    store_act(v, h1s, LH, 32 * t + c, a.h1t, a.n_pad, m0, hh);
+    store_act4(v, h1s, LH, col, a.h1t, a.n_pad, m0, kg);
   }
   __syncthreads();
   // Z2 = H1 W2^T + b2, H2 = gelu(Z2)
-#pragma unroll
+#pragma unroll 1
   for (int q = 0; q < TPW; ++q) {
-    const int t = w + kTrainWaves * q;
-    if (t >= NT) break;
-    f32x16 acc;
-    const float bv = a.b2[32 * t + c];
+    const int col = 16 * (w + NW * q) + r16;
+    const float bv = a.b2[col];
+    f32x4 acc = {bv, bv, bv, bv};
+    acc = product(acc, h1s, a.w2n + (size_t)col * H + 8 * kg);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = bv;
-    acc = product(
-        acc, [&](int s) { return act_frag_perm(h1s, LH, c, s, hh); },
-        [&](int s) { return frag_w2p(t, s); });
-    if constexpr (PRE) { // the next product's fragments
-      if (w < NB3) {
-#pragma unroll
-        for (int s = 0; s < S2; ++s) pf[s] = frag_w3p(w, s);
-      } else if (train) {
-#pragma unroll
-        for (int s = 0; s < S2; ++s) pf[s] = frag_w2t(t, s);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int r = 0; r < 4; ++r) {
       float dg;
-      v[i] = gelu_with_grad(acc[i], dg);
-      g2[q][i] = dg;
+      v[r] = gelu_with_grad(acc[r], dg);
+      g2[q][r] = dg;
     }
-    store_act(v, h2s, LH, 32 * t + c, a.h2t, a.n_pad, m0, hh);
+    store_act4(v, h2s, LH, col, a.h2t, a.n_pad, m0, kg);
   }
   __syncthreads();
-  // Y = H2 W3^T + b3 on waves 0 .. NB3-1; training: dY, squared errors
-  if (w < NB3) {
-    const int col = 32 * w + c;
-    f32x16 acc;
+  // Y = H2 W3^T + b3 on waves 0 .. NT3-1; training: dY, squared errors
+  if (w < NT3) {
+    const int col = 16 * w + r16;
     const float bv = col < a.C ? a.b3[col] : 0.0f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = bv;
-    acc = product(
-        acc, [&](int s) { return act_frag_perm(h2s, LH, c, s, hh); },
-        [&](int s) { return frag_w3p(w, s); });
-    if constexpr (PRE) {
-      if (train && w < NT) {
-#pragma unroll
-        for (int s = 0; s < S2; ++s) pf[s] = frag_w2t(w, s);
-      }
-    }
+    f32x4 acc = {bv, bv, bv, bv};
+    acc = product(acc, h2s, a.w3n + (size_t)col * H + 8 * kg);
     if (!train) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const uint32_t m = m0 + 8 * (i / 4) + 4 * hh + (i % 4);
-        if (m < a.n) a.yout[(size_t)m * CP + col] = acc[i];
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t m = m0 + 4 * kg + r;
+        if (m < a.n) a.yout[(size_t)m * CP + col] = acc[r];
       }
     } else {
       float sq = 0.0f, ds = 0.0f;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const uint32_t m = m0 + 8 * (i / 4) + 4 * hh + (i % 4);
-        const float d = (m < a.n && col < a.C) ? acc[i] - tv[i] : 0.0f;
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t m = m0 + 4 * kg + r;
+        const float d = (m < a.n && col < a.C) ? acc[r] - tv[r] : 0.0f;
         sq += d * d;
-        v[i] = a.scale * d;
-        ds += v[i];
+        v[r] = a.scale * d;
+        ds += v[r];
       }
-      store_act(v, dys, LY, col, a.dyt, a.n_pad, m0, hh);
-      ds += __shfl_xor(ds, 32);
-      if (hh == 0) a.bp3[(size_t)blk * CP + col] = ds;
+      store_act4(v, dys, LY, col, a.dyt, a.n_pad, m0, kg);
+      ds = column_sum16(ds);
+      if (kg == 0) a.bp3[(size_t)blk * CP + col] = ds;
       sq = wave_sum(sq);
       if (lane == 0) lred[w] = sq;
     }
   }
   if (!train) return; // uniform over the workgroup
   __syncthreads();
-  if (tid == 0) a.lossp[blk] = NB3 == 2 ? lred[0] + lred[1] : lred[0];
+  if (tid == 0) {
+    float t = lred[0];
+#pragma unroll
+    for (int i = 1; i < NT3; ++i) t += lred[i];
+    a.lossp[blk] = t;
+  }
   // dZ2 = (dY W3) * gelu'(Z2), into the H2 array
-#pragma unroll
+#pragma unroll 1
   for (int q = 0; q < TPW; ++q) {
-    const int t = w + kTrainWaves * q;
-    if (t >= NT) break;
-    f32x16 acc = {};
+    const int col = 16 * (w + NW * q) + r16;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 w3f[CP / 32];
 #pragma unroll
-    for (int s = 0; s < CP / 16; ++s)
-      acc = mfma(act_frag(dys, LY, c, 16 * s + 8 * hh), w3f[q][s], acc);
+    for (int s = 0; s < CP / 32; ++s) w3f[s] = frag_at(a.w3t + (size_t)col * CP + 32 * s + 8 * kg);
+#pragma unroll
+    for (int s = 0; s < CP / 32; ++s)
+      acc = mfma16(frag_at(dys + r16 * LY + 32 * s + 8 * kg), w3f[s], acc);
     float bs = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      v[i] = acc[i] * g2[q][i];
-      bs += v[i];
+    for (int r = 0; r < 4; ++r) {
+      v[r] = acc[r] * g2[q][r];
+      bs += v[r];
     }
-    store_act(v, h2s, LH, 32 * t + c, a.dz2t, a.n_pad, m0, hh);
-    bs += __shfl_xor(bs, 32);
-    if (hh == 0) a.bp2[(size_t)blk * H + 32 * t + c] = bs;
+    store_act4(v, h2s, LH, col, a.dz2t, a.n_pad, m0, kg);
+    bs = column_sum16(bs);
+    if (kg == 0) a.bp2[(size_t)blk * H + col] = bs;
   }
   __syncthreads();
   // dZ1 = (dZ2 W2) * gelu'(Z1)
-#pragma unroll
+#pragma unroll 1
   for (int q = 0; q < TPW; ++q) {
-    const int t = w + kTrainWaves * q;
-    if (t >= NT) break;
-    f32x16 acc = {};
-    acc = product(
-        acc, [&](int s) { return act_frag(h2s, LH, c, 16 * s + 8 * hh); },
-        [&](int s) { return frag_w2t(t, s); });
+    const int col = 16 * (w + NW * q) + r16;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = product(acc, h2s, a.w2t + (size_t)col * H + 8 * kg);
     float bs = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      v[i] = acc[i] * g1[q][i];
-      bs += v[i];
+    for (int r = 0; r < 4; ++r) {
+      v[r] = acc[r] * g1[q][r];
+      bs += v[r];
     }
-    store_act(v, nullptr, 0, 32 * t + c, a.dz1t, a.n_pad, m0, hh);
-    bs += __shfl_xor(bs, 32);
-    if (hh == 0) a.bp1[(size_t)blk * H + 32 * t + c] = bs;
+    store_act4(v, nullptr, 0, col, a.dz1t, a.n_pad, m0, kg);
+    bs = column_sum16(bs);
+    if (kg == 0) a.bp1[(size_t)blk * H + col] = bs;
   }
 }
 
@@ -717,8 +679,7 @@ __device__ __forceinline__ void apply_grad(const GradTilesArgs &g, size_t p, flo
   g.v[p] = vv;
   const float th = g.theta[p] - g.lr * (mm * g.c1) / (sqrtf(vv * g.c2) + g.eps);
   g.theta[p] = th;
-  pack_one(g.sh, p, th, g.w1p, g.w2p, g.w3p);
-  pack_transposed(g.sh, p, th, g.w2t, g.w3t);
+  pack_all(g.sh, p, th, g.cp);
 }
 
 __global__ __launch_bounds__(kGradThreads) void mlp_grad_tiles(GradTilesArgs g) {
@@ -731,7 +692,7 @@ __global__ __launch_bounds__(kGradThreads) void mlp_grad_tiles(GradTilesArgs g) 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hh = lane >> 5, c = lane & 31;
   int j = blockIdx.x;
   if (j >= T2 + T1 + T3) { // biases, one per thread: the row blocks' column sums in block order
-    const int Cp = 32 * NB3, nblk = (int)(g.n_pad / 32);
+    const int Cp = 32 * NB3, nblk = (int)(g.n_pad / 16); // the row kernel's blocks
     const int first = j - (T2 + T1 + T3);
     const int idx = first * kGradThreads + tid;
     if (idx < 2 * H + C) {
@@ -870,26 +831,19 @@ hipError_t launch_mlp_forward(const MlpFwdArgs &a, bool train, hipStream_t strea
 
 namespace {
 
-template <int H, int NB3, int S1>
+template <int H, int NB3>
 hipError_t launch_train_rows_h(const TrainRowsArgs &a, hipStream_t stream) {
-  using TS = TrainShape<H, NB3, S1>;
-  const auto kernel = mlp_train_rows<H, NB3, S1>;
-  if constexpr (TS::lds > 64 * 1024) {
-    static const hipError_t set = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)TS::lds);
-    if (set != hipSuccess) return set;
-  }
-  hipLaunchKernelGGL(kernel, dim3(a.n_pad / 32), dim3(kTrainWaves * 64), TS::lds, stream, a);
+  using TS = TrainShape<H, NB3>;
+  static_assert(TS::lds <= 64 * 1024, "static launch size");
+  hipLaunchKernelGGL((mlp_train_rows<H, NB3>), dim3(a.n_pad / 16), dim3(TS::NW * 64), TS::lds,
+                     stream, a);
   return hipGetLastError();
 }
 
 template <int H> hipError_t launch_train_rows_nb(const TrainRowsArgs &a, hipStream_t s) {
-  const int nb3 = (a.C + 31) / 32, s1 = a.K1 / 16;
-  if (nb3 == 1 && s1 == 1) return launch_train_rows_h<H, 1, 1>(a, s);
-  if (nb3 == 1 && s1 == 2) return launch_train_rows_h<H, 1, 2>(a, s);
-  if (nb3 == 2 && s1 == 1) return launch_train_rows_h<H, 2, 1>(a, s);
-  if (nb3 == 2 && s1 == 2) return launch_train_rows_h<H, 2, 2>(a, s);
+  const int nb3 = (a.C + 31) / 32;
+  if (nb3 == 1) return launch_train_rows_h<H, 1>(a, s);
+  if (nb3 == 2) return launch_train_rows_h<H, 2>(a, s);
   return hipErrorInvalidValue;
 }
 
@@ -928,11 +882,10 @@ hipError_t launch_mlp_grad_tiles(const GradTilesArgs &g, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
-                               __bf16 *w2p, __bf16 *w3p, __bf16 *w2t, __bf16 *w3t,
-                               hipStream_t stream) {
+hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n,
+                               const MlpCopies &cp, hipStream_t stream) {
   hipLaunchKernelGGL(pack_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh,
-                     theta, n, w1p, w2p, w3p, w2t, w3t);
+                     theta, n, cp);
   return hipGetLastError();
 }
 

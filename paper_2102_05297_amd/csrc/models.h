@@ -12,13 +12,24 @@ namespace cgs {
 hipError_t launch_rows_to_columns(const float *d_src, uint32_t n, int C, float *d_P,
                                   uint64_t stride, hipStream_t stream);
 
+// The bf16 copies of the perceptron's weights, rewritten from the fp32
+// masters at creation and by every Adam step (mlp.hip):
+//   w1p, w2p, w3p: the inference kernel's packed A fragments (32x32x16);
+//   w2t [H][H], w3t [H][Cp]: W2^T and W3^T row-major (the backward B operands);
+//   w1n [H][32], w2n [H][H], w3n [Cp][H]: W1, W2, W3 row-major (the training
+//   forward's B operands; W1's rows padded to 32 features, W3 to Cp rows).
+// Padding is never written: the caller zeroes w1p, w3p, w3t, w1n and w3n.
+struct MlpCopies {
+  __bf16 *w1p, *w2p, *w3p, *w2t, *w3t, *w1n, *w2n, *w3n;
+};
+
 // One training step of the perceptron in two launches (mlp.hip), after
 // launch_mlp_gather_rows has gathered the rows of a run of steps.
-// launch_mlp_train_rows: per 32 rows of the batch, the forward pass, the
+// launch_mlp_train_rows: per 16 rows of the batch, the forward pass, the
 // loss terms (dY = scale (Y - T)) and the backward chain to dZ1; it writes
 // the weight gradients' operands transposed, [feature][n_pad] bf16 (xt: 32
 // feature rows, zero past F; h1t, h2t, dz2t, dz1t: H rows; dyt: Cp rows),
-// the column sums of dY, dZ2 and dZ1 over each block of 32 rows
+// the column sums of dY, dZ2 and dZ1 over each block of 16 rows
 // (bp3[blk][Cp], bp2[blk][H], bp1[blk][H]) and each block's sum of squared
 // errors (lossp[blk]).  Without train only the forward pass runs and Y goes
 // to yout[n][Cp].  Rows past n are zeros.
@@ -27,10 +38,9 @@ struct TrainRowsArgs {
   const float *tin;         // the step's targets [n][C], or null (forward only)
   bool train;               // tin set
   uint32_t n, n_pad;        // rows; a multiple of 32 >= n
-  int F, H, C, K1;
+  int H, C, K1;
   float scale;              // 2 / (n C)
-  const bf16x8 *w1p, *w2p, *w3p;
-  const __bf16 *w2t, *w3t;
+  const __bf16 *w1n, *w2n, *w3n, *w2t, *w3t;
   const float *b1, *b2, *b3;
   float *yout;
   __bf16 *xt, *h1t, *h2t, *dyt, *dz2t, *dz1t;
@@ -48,7 +58,7 @@ hipError_t launch_mlp_gather_rows(const SpaceDev *sp, const uint32_t *cfg_raw,
 // dW3 = dY^T H2 by 32 x 32 tiles and the bias gradients (the blocks' column
 // sums added in block order) from launch_mlp_train_rows's outputs; with grad
 // set they are stored there (the layout of theta), otherwise one Adam step
-// updates theta, m, v and the packed bf16 copies.  loss_out (if set) gets
+// updates theta, m, v and every bf16 copy.  loss_out (if set) gets
 // (lossp[0] + ... ) / loss_div.
 struct GradTilesArgs {
   MlpShape sh;
@@ -60,16 +70,12 @@ struct GradTilesArgs {
   float *grad;
   float *theta, *m, *v;
   float lr, beta1, beta2, eps, c1, c2;
-  __bf16 *w1p, *w2p, *w3p, *w2t, *w3t;
+  MlpCopies cp;
 };
 hipError_t launch_mlp_grad_tiles(const GradTilesArgs &g, hipStream_t stream);
-// The bf16 weights from the fp32 masters theta[n]: the inference fragments
-// w1p, w2p, w3p, and the transposed copies w2t[k][o] = W2[o][k] ([H][H]) and
-// w3t[k][c] = W3[c][k] ([H][Cp], Cp = C rounded up to 32) that the backward
-// products read.
-hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n, __bf16 *w1p,
-                               __bf16 *w2p, __bf16 *w3p, __bf16 *w2t, __bf16 *w3t,
-                               hipStream_t stream);
+// Every bf16 copy (MlpCopies) from the fp32 masters theta[n].
+hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n,
+                               const MlpCopies &cp, hipStream_t stream);
 
 // ---- regression-tree fitting (Sect. 3.4.2)
 FastDiv make_fastdiv(uint32_t d);
