@@ -39,24 +39,33 @@ __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+// min(|z|, 9) and max(z, 0) for finite z, each one v_med3_f32: written as
+// fminf / fmaxf they would first canonicalise z (an accumulator value the
+// compiler cannot prove canonical), one more instruction each.
+__device__ __forceinline__ float tail_arg(float az) {
+  return __builtin_amdgcn_fmed3f(az, 0.0f, kGeluTailMax);
+}
+__device__ __forceinline__ float relu(float z) {
+  return __builtin_amdgcn_fmed3f(z, 0.0f, 3.40282347e38f);
+}
 // GELU(z) = max(z, 0) - |z| Phi(-|z|) with Phi(-x) = 2^p(min(x, 9)) (gelu.h):
-// nine VALU operations and one exponential.
+// ten VALU operations and one exponential.
 __device__ __forceinline__ float gelu(float z) {
   const float az = fabsf(z);
-  const float e = __builtin_amdgcn_exp2f(gelu_tail_log2(fminf(az, kGeluTailMax)));
-  return fmaf(-az, e, fmaxf(z, 0.0f));
+  const float e = __builtin_amdgcn_exp2f(gelu_tail_log2(tail_arg(az)));
+  return fmaf(-az, e, relu(z));
 }
 // GELU(z) as above and, from the same tail, its derivative
 // GELU'(z) = Phi(z) + z phi(z), phi(z) = 2^(-z^2 / (2 ln 2)) / sqrt(2 pi):
 // the training forward keeps the derivative for the backward pass.
 __device__ __forceinline__ float gelu_with_grad(float z, float &dg) {
   const float az = fabsf(z);
-  const float e = __builtin_amdgcn_exp2f(gelu_tail_log2(fminf(az, kGeluTailMax)));
+  const float e = __builtin_amdgcn_exp2f(gelu_tail_log2(tail_arg(az)));
   const float cdf = z > 0.0f ? 1.0f - e : e;
   const float pdf =
       0.3989422804014327f * __builtin_amdgcn_exp2f(-0.7213475204444817f * (z * z));
   dg = fmaf(z, pdf, cdf);
-  return fmaf(-az, e, fmaxf(z, 0.0f));
+  return fmaf(-az, e, relu(z));
 }
 
 // ------------------------------------------------------------- inference
@@ -350,33 +359,45 @@ __device__ __forceinline__ void pack_one(const MlpShape &sh, size_t p, float v, 
   else if (which == 3) w3p[pos] = (__bf16)v;
 }
 
-// Transposed bf16 copies of W2 and W3, K-contiguous for the backward
-// products dH = dZ W (so their weight fragments are vector loads):
-// w2t[k][o] = W2[o][k] (row length H), w3t[k][c] = W3[c][k] (row length Cp,
-// the padding never read).
+// The training kernel's B operands in the fragment order of
+// v_mfma_f32_16x16x32_bf16: element (row n, k) of a matrix whose K length is
+// KD (a multiple of 32) sits at [n / 16][k / 32][16 ((k % 32) / 8) + n % 16]
+// [k % 8], so the fragment of output tile n / 16 at K step k / 32 is 64
+// lanes x 16 contiguous bytes, one load per wave.
+__device__ __forceinline__ size_t frag16_pos(size_t n, size_t k, size_t KD) {
+  return (((n >> 4) * (KD >> 5) + (k >> 5)) * 64 + 16 * ((k & 31) >> 3) + (n & 15)) * 8 +
+         (k & 7);
+}
+
+// Transposed copies for the backward products dH = dZ W: w2t holds W2^T
+// (row k, K index o: W2[o][k], K length H), w3t holds W3^T (row k, K index
+// c: W3[c][k], K length Cp; c >= C stays zero).
 __device__ __forceinline__ void pack_transposed(const MlpShape &sh, size_t p, float v,
                                                 __bf16 *w2t, __bf16 *w3t) {
   const size_t H = sh.H, first_w2 = H * sh.F + H, first_w3 = first_w2 + H * H + H;
   if (p >= first_w2 && p < first_w2 + H * H) {
-    const size_t q = p - first_w2;
-    w2t[(q % H) * H + q / H] = (__bf16)v;
+    const size_t q = p - first_w2; // W2[q / H][q % H]
+    w2t[frag16_pos(q % H, q / H, H)] = (__bf16)v;
   } else if (p >= first_w3 && p < first_w3 + (size_t)sh.C * H) {
-    const size_t q = p - first_w3, Cp = 32 * (((size_t)sh.C + 31) / 32);
-    w3t[(q % H) * Cp + q / H] = (__bf16)v;
+    const size_t q = p - first_w3, Cp = 32 * (((size_t)sh.C + 31) / 32); // W3[q / H][q % H]
+    w3t[frag16_pos(q % H, q / H, Cp)] = (__bf16)v;
   }
 }
 
-// Row-major copies for the training kernel's B operands: w1n[o][32] (features
-// padded to 32), w2n[o][k] = W2[o][k], w3n[c][k] = W3[c][k] ([Cp][H]).
+// Copies for the forward products: w1n holds W1 (row o, K index f, K length
+// 32: features past F stay zero), w2n holds W2 (K length H), w3n holds W3
+// (rows Cp, rows past C stay zero).
 __device__ __forceinline__ void pack_natural(const MlpShape &sh, size_t p, float v, __bf16 *w1n,
                                              __bf16 *w2n, __bf16 *w3n) {
   const size_t H = sh.H, F = sh.F, first_w2 = H * F + H, first_w3 = first_w2 + H * H + H;
   if (p < H * F) {
-    w1n[(p / F) * 32 + p % F] = (__bf16)v;
+    w1n[frag16_pos(p / F, p % F, 32)] = (__bf16)v;
   } else if (p >= first_w2 && p < first_w2 + H * H) {
-    w2n[p - first_w2] = (__bf16)v;
+    const size_t q = p - first_w2;
+    w2n[frag16_pos(q / H, q % H, H)] = (__bf16)v;
   } else if (p >= first_w3 && p < first_w3 + (size_t)sh.C * H) {
-    w3n[p - first_w3] = (__bf16)v;
+    const size_t q = p - first_w3;
+    w3n[frag16_pos(q / H, q % H, H)] = (__bf16)v;
   }
 }
 
@@ -399,7 +420,9 @@ __global__ __launch_bounds__(256) void pack_weights(MlpShape sh, const float *__
 //    16-column output tile of a hidden layer (two for H = 512).
 //    Z = A W^T + b on v_mfma_f32_16x16x32_bf16 with the activations as the
 //    A operand, read from LDS, and the weights as the B operand, read from
-//    row-major bf16 copies; the activations pass between layers through LDS.
+//    bf16 copies in the MFMA's fragment order (frag16_pos: one contiguous
+//    1 KB load per wave and K step); the activations pass between layers
+//    through LDS.
 //    Then the loss terms and dY = scale (Y - T), and the backward chain
 //    dZ2 = (dY W3) * gelu'(Z2), dZ1 = (dZ2 W2) * gelu'(Z1) with W3 and W2
 //    from their transposed bf16 copies.  Every product of the chain is local
@@ -542,13 +565,17 @@ __global__ __launch_bounds__(train_waves<H>() * 64) void mlp_train_rows(TrainRow
   f32x4 g1[TPW], g2[TPW]; // GELU'(Z1), GELU'(Z2) of the wave's tiles
   float v[4];
   // acc += the H-deep product of the LDS activations (row stride LH) with
-  // the weight rows wr (K contiguous), SB fragments in flight at a time
+  // output tile t of a weight copy in fragment order (frag16_pos, K length
+  // H), SB fragments in flight at a time
+  auto tile_frags = [&](const __bf16 *wc, int t, int ks) {
+    return wc + ((size_t)t * ks * 64 + lane) * 8;
+  };
   auto product = [&](f32x4 acc, const __bf16 *act, const __bf16 *wr) {
 #pragma unroll
     for (int s0 = 0; s0 < KS; s0 += SB) {
       bf16x8 bfr[SB];
 #pragma unroll
-      for (int u = 0; u < SB; ++u) bfr[u] = frag_at(wr + 32 * (s0 + u));
+      for (int u = 0; u < SB; ++u) bfr[u] = frag_at(wr + 512 * (s0 + u));
 #pragma unroll
       for (int u = 0; u < SB; ++u)
         acc = mfma16(frag_at(act + r16 * LH + 32 * (s0 + u) + 8 * kg), bfr[u], acc);
@@ -561,7 +588,7 @@ __global__ __launch_bounds__(train_waves<H>() * 64) void mlp_train_rows(TrainRow
     const int col = 16 * (w + NW * q) + r16;
     const float bv = a.b1[col];
     f32x4 acc = {bv, bv, bv, bv};
-    acc = mfma16(frag_at(xs + r16 * LX + 8 * kg), frag_at(a.w1n + (size_t)col * 32 + 8 * kg),
+    acc = mfma16(frag_at(xs + r16 * LX + 8 * kg), frag_at(tile_frags(a.w1n, w + NW * q, 1)),
                  acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -578,7 +605,7 @@ __global__ __launch_bounds__(train_waves<H>() * 64) void mlp_train_rows(TrainRow
     const int col = 16 * (w + NW * q) + r16;
     const float bv = a.b2[col];
     f32x4 acc = {bv, bv, bv, bv};
-    acc = product(acc, h1s, a.w2n + (size_t)col * H + 8 * kg);
+    acc = product(acc, h1s, tile_frags(a.w2n, w + NW * q, KS));
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       float dg;
@@ -593,7 +620,7 @@ __global__ __launch_bounds__(train_waves<H>() * 64) void mlp_train_rows(TrainRow
     const int col = 16 * w + r16;
     const float bv = col < a.C ? a.b3[col] : 0.0f;
     f32x4 acc = {bv, bv, bv, bv};
-    acc = product(acc, h2s, a.w3n + (size_t)col * H + 8 * kg);
+    acc = product(acc, h2s, tile_frags(a.w3n, w, KS));
     if (!train) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -632,7 +659,7 @@ __global__ __launch_bounds__(train_waves<H>() * 64) void mlp_train_rows(TrainRow
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     bf16x8 w3f[CP / 32];
 #pragma unroll
-    for (int s = 0; s < CP / 32; ++s) w3f[s] = frag_at(a.w3t + (size_t)col * CP + 32 * s + 8 * kg);
+    for (int s = 0; s < CP / 32; ++s) w3f[s] = frag_at(tile_frags(a.w3t, w + NW * q, CP / 32) + 512 * s);
 #pragma unroll
     for (int s = 0; s < CP / 32; ++s)
       acc = mfma16(frag_at(dys + r16 * LY + 32 * s + 8 * kg), w3f[s], acc);
@@ -652,7 +679,7 @@ __global__ __launch_bounds__(train_waves<H>() * 64) void mlp_train_rows(TrainRow
   for (int q = 0; q < TPW; ++q) {
     const int col = 16 * (w + NW * q) + r16;
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    acc = product(acc, h2s, a.w2t + (size_t)col * H + 8 * kg);
+    acc = product(acc, h2s, tile_frags(a.w2t, w + NW * q, KS));
     float bs = 0.0f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

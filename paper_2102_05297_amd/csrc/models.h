@@ -15,9 +15,10 @@ hipError_t launch_rows_to_columns(const float *d_src, uint32_t n, int C, float *
 // The bf16 copies of the perceptron's weights, rewritten from the fp32
 // masters at creation and by every Adam step (mlp.hip):
 //   w1p, w2p, w3p: the inference kernel's packed A fragments (32x32x16);
-//   w2t [H][H], w3t [H][Cp]: W2^T and W3^T row-major (the backward B operands);
-//   w1n [H][32], w2n [H][H], w3n [Cp][H]: W1, W2, W3 row-major (the training
-//   forward's B operands; W1's rows padded to 32 features, W3 to Cp rows).
+//   w2t (H x H), w3t (H x Cp): W2^T and W3^T, the training backward's B
+//   operands; w1n (H x 32), w2n (H x H), w3n (Cp x H): W1, W2, W3, the
+//   training forward's B operands (W1's rows padded to 32 features, W3 to Cp
+//   rows); all five in the 16x16x32 MFMA fragment order of mlp.hip.
 // Padding is never written: the caller zeroes w1p, w3p, w3t, w1n and w3n.
 struct MlpCopies {
   __bf16 *w1p, *w2p, *w3p, *w2t, *w3t, *w1n, *w2n, *w3n;
