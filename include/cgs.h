@@ -515,6 +515,11 @@ cgs_status cgs_search_run(cgs_session session, cgs_model model, int n_steps,
  *   step_us_host[n_steps], retrain_ms_host[W - 1] (may be NULL): wall times
  *                   of each step with its draw, and of each retraining with
  *                   its RMSE check
+ * A retrained surrogate is evaluated over every valid configuration only
+ * when its window scores with it: its RMSE comes from the validation
+ * configurations alone (the same values a full evaluation gives them), and
+ * the full evaluation follows when the RMSE passes, and once before the
+ * call returns, so the model's predictions are current afterwards.
  * tree: any model (normally a forest); mlp: a perceptron with the same
  * counters on the same space; the session should be fresh.  Returns the
  * first failing call's status (CGS_EEMPTY when the space runs out). */

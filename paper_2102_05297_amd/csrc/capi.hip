@@ -86,6 +86,9 @@ struct cgs_model_s {
   float *d_P = nullptr; // predictions [C][stride] of every valid configuration
   uint64_t stride = 0;
   float eval_ms = 0.0f;
+  // d_P lags the parameters (a perceptron retrained inside cgs_online_run
+  // whose predictions are not needed yet); never true outside that call
+  bool p_stale = false;
   // forest
   int n_trees = 0, depth = 0;
   uint16_t *d_nodes = nullptr;
@@ -1529,9 +1532,12 @@ extern "C" cgs_status cgs_model_load_mlp(cgs_space sp, const cgs_mlp_desc *desc,
   return CGS_OK;
 }
 
-extern "C" cgs_status cgs_mlp_train(cgs_model m, const uint32_t *cfg, const float *targets,
-                                    uint64_t n, const int32_t *batch_idx,
-                                    const cgs_train_opts *o, float *loss_host) {
+// The Adam steps of cgs_mlp_train; with evaluate, the predictions of every
+// valid configuration are refreshed after them, otherwise they are marked
+// stale (cgs_online_run refreshes them when they are used).
+cgs_status mlp_train_run(cgs_model m, const uint32_t *cfg, const float *targets, uint64_t n,
+                         const int32_t *batch_idx, const cgs_train_opts *o, float *loss_host,
+                         bool evaluate) {
   if (!m || !cfg || !targets || !batch_idx || !o) return fail(CGS_EINVAL, "NULL argument");
   if (m->kind != 1) return fail(CGS_EINVAL, "not a perceptron model");
   if (n == 0 || n > 0xffffffffull) return fail(CGS_ERANGE, "need 1 .. 2^32-1 pairs");
@@ -1576,7 +1582,18 @@ extern "C" cgs_status cgs_mlp_train(cgs_model m, const uint32_t *cfg, const floa
   dfree(d_batch);
   dfree(d_loss);
   if (e != hipSuccess) return fail(CGS_EDEVICE, "training: %s", hipGetErrorString(e));
+  if (!evaluate) {
+    m->p_stale = true;
+    return CGS_OK;
+  }
+  m->p_stale = false;
   return evaluate_model(m);
+}
+
+extern "C" cgs_status cgs_mlp_train(cgs_model m, const uint32_t *cfg, const float *targets,
+                                    uint64_t n, const int32_t *batch_idx,
+                                    const cgs_train_opts *o, float *loss_host) {
+  return mlp_train_run(m, cfg, targets, n, batch_idx, o, loss_host, true);
 }
 
 extern "C" cgs_status cgs_mlp_gradients(cgs_model m, const uint32_t *cfg, const float *targets,
@@ -2175,6 +2192,62 @@ extern "C" void cgs_default_online_opts(cgs_online_opts *o) {
   o->threshold = 0.05;
 }
 
+// cgs_model_rmse(mlp, tree, sample) for a perceptron whose full-space
+// predictions are stale: the inference kernel evaluates only the sampled
+// configurations (each configuration's result does not depend on which
+// others share its launch, so these are the values a full evaluation
+// would give) and the same sums are formed in the same order.
+cgs_status mlp_sample_rmse(cgs_model mlp, cgs_model tree, const uint32_t *sample, uint64_t n,
+                           double *rmse) {
+  cgs_space sp = mlp->space;
+  if (n == 0 || n > 0xffffffffull) return fail(CGS_ERANGE, "need 1 .. 2^32-1 samples");
+  std::vector<uint32_t> raw(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    if (sample[i] >= sp->n_valid)
+      return fail(CGS_EINVAL, "sample %llu outside the valid list", (unsigned long long)i);
+    raw[i] = sp->h_idx[sample[i]];
+  }
+  const int C = mlp->n_counters;
+  const uint64_t stride = (n + 63) & ~(uint64_t)63;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 1024);
+  uint32_t *d_s = nullptr, *d_raw = nullptr;
+  float *d_p = nullptr;
+  double *d_part = nullptr;
+  std::vector<double> part(grid);
+  hipError_t e = dalloc(&d_s, n);
+  if (e == hipSuccess) e = dalloc(&d_raw, n);
+  if (e == hipSuccess) e = dalloc(&d_p, (size_t)C * stride);
+  if (e == hipSuccess) e = dalloc(&d_part, grid);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_s, sample, n * sizeof(uint32_t), hipMemcpyHostToDevice, sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_raw, raw.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, sp->stream);
+  if (e == hipSuccess) {
+    MlpFwdArgs a = mlp_args(mlp);
+    a.idx = d_raw;
+    a.n = (uint32_t)n;
+    a.P = d_p;
+    a.stride = stride;
+    e = launch_mlp_forward(a, false, sp->stream);
+  }
+  if (e == hipSuccess)
+    e = launch_sq_diff_dense(d_p, tree->d_P, stride, tree->stride, C, d_s, (uint32_t)n, d_part,
+                             grid, sp->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(part.data(), d_part, grid * sizeof(double), hipMemcpyDeviceToHost,
+                       sp->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sp->stream);
+  dfree(d_s);
+  dfree(d_raw);
+  dfree(d_p);
+  dfree(d_part);
+  if (e != hipSuccess) return fail(CGS_EDEVICE, "rmse: %s", hipGetErrorString(e));
+  double sum = 0.0;
+  for (double v : part) sum += v;
+  *rmse = std::sqrt(sum / ((double)n * C));
+  return CGS_OK;
+}
+
 // The online policy around the library's own calls: per window one
 // cgs_model_rmse (and, after the first window, one cgs_mlp_train), per step
 // one cgs_search_step and one cgs_sample_next.  Targets of the collected pairs
@@ -2232,16 +2305,32 @@ extern "C" cgs_status cgs_online_run(cgs_session s, cgs_model tree, cgs_model ml
     fresh_step.clear();
     return CGS_OK;
   };
+  // The surrogate's full-space predictions are refreshed only for windows
+  // that score with it (and once before returning): a retrained network that
+  // fails the RMSE check is never evaluated beyond the validation sample.
+  auto rmse_of_mlp = [&](double *r) {
+    return mlp->p_stale ? mlp_sample_rmse(mlp, tree, val_sample, n_val, r)
+                        : cgs_model_rmse(mlp, tree, val_sample, n_val, r);
+  };
+  auto refresh = [&]() -> cgs_status {
+    if (!mlp->p_stale) return CGS_OK;
+    mlp->p_stale = false;
+    return evaluate_model(mlp);
+  };
+  auto done = [&](cgs_status st) {
+    const cgs_status r = refresh();
+    return st != CGS_OK ? st : r;
+  };
   double rmse = 0.0;
-  cgs_status st = cgs_model_rmse(mlp, tree, val_sample, n_val, &rmse);
-  if (st != CGS_OK) return st;
+  cgs_status st = rmse_of_mlp(&rmse);
+  if (st != CGS_OK) return done(st);
   bool use_mlp = rmse <= opts->threshold;
   window_rmse[0] = rmse;
   window_mlp[0] = use_mlp;
   st = cgs_search_step(s, tree, CGS_NO_PROFILE, nullptr, nullptr, nullptr);
   uint64_t raw = 0, valid = 0;
   if (st == CGS_OK) st = cgs_sample_next(s, u64[0], &raw, &valid);
-  if (st != CGS_OK) return st;
+  if (st != CGS_OK) return done(st);
   raw_out[0] = raw;
   if (valid_out) valid_out[0] = valid;
   cfg.push_back((uint32_t)raw);
@@ -2252,7 +2341,7 @@ extern "C" cgs_status cgs_online_run(cgs_session s, cgs_model tree, cgs_model ml
       const int w = i / W;
       const auto t0 = std::chrono::steady_clock::now();
       st = gather_fresh();
-      if (st != CGS_OK) return st;
+      if (st != CGS_OK) return done(st);
       if (opts->train_steps > 0) {
         // row of each batch entry: floor(u * n_pairs / 2^64), one u per entry
         const uint64_t np = cfg.size(), per = (uint64_t)opts->train_steps * opts->batch;
@@ -2262,14 +2351,16 @@ extern "C" cgs_status cgs_online_run(cgs_session s, cgs_model tree, cgs_model ml
           rows[k] = (int32_t)(((unsigned __int128)u[k] * np) >> 64);
         const cgs_train_opts to{opts->lr,    opts->beta1, opts->beta2,
                                 opts->eps,   opts->batch, opts->train_steps};
-        st = cgs_mlp_train(mlp, cfg.data(), tgt.data(), np, rows.data(), &to, nullptr);
-        if (st != CGS_OK) return st;
+        st = mlp_train_run(mlp, cfg.data(), tgt.data(), np, rows.data(), &to, nullptr, false);
+        if (st != CGS_OK) return done(st);
       }
-      st = cgs_model_rmse(mlp, tree, val_sample, n_val, &rmse);
-      if (st != CGS_OK) return st;
+      st = rmse_of_mlp(&rmse);
+      if (st != CGS_OK) return done(st);
       use_mlp = rmse <= opts->threshold;
       window_rmse[w] = rmse;
       window_mlp[w] = use_mlp;
+      if (use_mlp) st = refresh();
+      if (st != CGS_OK) return done(st);
       if (retrain_ms)
         retrain_ms[w - 1] =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -2278,7 +2369,7 @@ extern "C" cgs_status cgs_online_run(cgs_session s, cgs_model tree, cgs_model ml
     st = cgs_search_step(s, use_mlp ? mlp : tree, raw, delta + (size_t)(i - 1) * C, nullptr,
                          nullptr);
     if (st == CGS_OK) st = cgs_sample_next(s, u64[i], &raw, &valid);
-    if (st != CGS_OK) return st;
+    if (st != CGS_OK) return done(st);
     if (step_us)
       step_us[i - 1] =
           std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
@@ -2288,7 +2379,7 @@ extern "C" cgs_status cgs_online_run(cgs_session s, cgs_model tree, cgs_model ml
     fresh.push_back((uint32_t)valid);
     fresh_step.push_back(i);
   }
-  return CGS_OK;
+  return done(CGS_OK);
 }
 
 extern "C" cgs_status cgs_search_step_neighbourhood(cgs_session s, cgs_model m,

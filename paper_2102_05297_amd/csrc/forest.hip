@@ -239,7 +239,9 @@ __global__ __launch_bounds__(kResidentThreads) void forest_eval_resident(
 }
 
 // Partial sums of squared prediction differences over sampled valid
-// configurations: one double per workgroup.
+// configurations: one double per workgroup.  DENSE_A: Pa holds the sampled
+// configurations' predictions in sample order (column i for sample i).
+template <bool DENSE_A>
 __global__ __launch_bounds__(256) void sq_diff(const float *__restrict__ Pa,
                                                const float *__restrict__ Pb, uint64_t stride_a,
                                                uint64_t stride_b, int n_counters,
@@ -250,7 +252,8 @@ __global__ __launch_bounds__(256) void sq_diff(const float *__restrict__ Pa,
   for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const uint32_t l = sample[i];
     for (int c = 0; c < n_counters; ++c) {
-      const double d = (double)Pa[(size_t)c * stride_a + l] - (double)Pb[(size_t)c * stride_b + l];
+      const double d = (double)Pa[(size_t)c * stride_a + (DENSE_A ? i : l)] -
+                       (double)Pb[(size_t)c * stride_b + l];
       acc += d * d;
     }
   }
@@ -287,7 +290,15 @@ hipError_t launch_gather_rows(const float *P, uint64_t stride, int n_counters,
 hipError_t launch_sq_diff(const float *Pa, const float *Pb, uint64_t stride_a, uint64_t stride_b,
                           int n_counters, const uint32_t *sample, uint32_t n, double *partial,
                           uint32_t grid, hipStream_t stream) {
-  hipLaunchKernelGGL(sq_diff, dim3(grid), dim3(256), 0, stream, Pa, Pb, stride_a, stride_b,
+  hipLaunchKernelGGL(sq_diff<false>, dim3(grid), dim3(256), 0, stream, Pa, Pb, stride_a, stride_b,
+                     n_counters, sample, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_sq_diff_dense(const float *Pa, const float *Pb, uint64_t stride_a,
+                                uint64_t stride_b, int n_counters, const uint32_t *sample,
+                                uint32_t n, double *partial, uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(sq_diff<true>, dim3(grid), dim3(256), 0, stream, Pa, Pb, stride_a, stride_b,
                      n_counters, sample, n, partial);
   return hipGetLastError();
 }

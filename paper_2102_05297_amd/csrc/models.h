@@ -74,6 +74,11 @@ struct GradTilesArgs {
   MlpCopies cp;
 };
 hipError_t launch_mlp_grad_tiles(const GradTilesArgs &g, hipStream_t stream);
+// launch_sq_diff with Pa holding the sampled configurations' predictions
+// in sample order: Pa[c * stride_a + i] against Pb[c * stride_b + sample[i]].
+hipError_t launch_sq_diff_dense(const float *Pa, const float *Pb, uint64_t stride_a,
+                                uint64_t stride_b, int n_counters, const uint32_t *sample,
+                                uint32_t n, double *partial, uint32_t grid, hipStream_t stream);
 // Every bf16 copy (MlpCopies) from the fp32 masters theta[n].
 hipError_t launch_pack_weights(const MlpShape &sh, const float *theta, size_t n,
                                const MlpCopies &cp, hipStream_t stream);

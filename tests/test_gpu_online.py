@@ -106,8 +106,10 @@ def test_run_equals_the_calls_one_by_one():
     mlp2 = m.MLPModel(sp, [init.w[0], init.b[0], init.w[1], init.b[1], init.w[2], init.b[2]])
     sess = m.Session(sp)
     pairs_c, pairs_t = list(cfg), [row for row in tgt]
-    use = tree.rmse(mlp2, val) <= opts.threshold
+    r = tree.rmse(mlp2, val)
+    use = r <= opts.threshold
     windows = [use]
+    rmses = [r]
     sess.search_step(tree, m.NO_PROFILE)
     raw, l = sess.sample_next(int(U[0]))
     picks = [l]
@@ -121,8 +123,10 @@ def test_run_equals_the_calls_one_by_one():
             rows = np.array([(int(x) * len(pairs_c)) >> 64 for x in u], np.int32)
             mlp2.train(np.array(pairs_c, np.uint32), np.array(pairs_t, np.float32),
                        rows.reshape(opts.train_steps, opts.batch), lr=opts.lr)
-            use = tree.rmse(mlp2, val) <= opts.threshold
+            r = tree.rmse(mlp2, val)
+            use = r <= opts.threshold
             windows.append(use)
+            rmses.append(r)
         sess.search_step(mlp2 if use else tree, raw, delta=deltas[i - 1])
         raw, l = sess.sample_next(int(U[i]))
         picks.append(l)
@@ -130,7 +134,29 @@ def test_run_equals_the_calls_one_by_one():
         pairs_t.append(tree.gather_predictions([l])[0] + noise[i])
     assert log["picks"] == picks
     assert [w["model"] == "mlp" for w in log["windows"]] == windows
+    # a retrained network's RMSE comes from its validation configurations
+    # alone inside the run: the same sums as cgs_model_rmse on a full
+    # evaluation
+    assert [w["rmse"] for w in log["windows"]] == rmses
     assert (mlp.copy_params() == mlp2.copy_params()).all()
+
+
+def test_predictions_are_current_after_the_run():
+    """Every window falls back to the tree, so no retrained network is
+    evaluated beyond the validation configurations during the run; the run
+    evaluates the final one before returning: its predictions equal a fresh
+    evaluation, and the last window's RMSE is cgs_model_rmse on them."""
+    m = cgs()
+    n = 40
+    spec, forest, sp, tree, mlp, _, deltas, U, noise, cfg, tgt, val = _setup(m, n)
+    opts = m.cgs_default_online_opts(retrain_every=20, threshold=1e-9, train_steps=20, batch=32)
+    log = m.Session(sp).online_run(tree, mlp, deltas, U, noise, cfg, tgt, val,
+                                   _batch_u64(n, opts), opts)
+    assert [w["model"] for w in log["windows"]] == ["tree"] * 3
+    after = mlp.copy_predictions()
+    mlp.refresh()
+    assert (mlp.copy_predictions() == after).all()
+    assert log["windows"][-1]["rmse"] == tree.rmse(mlp, val)
 
 
 def test_surrogate_step_on_the_large_network_shape():
