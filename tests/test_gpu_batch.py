@@ -29,13 +29,14 @@ def _inputs(n_sess, n_steps, seed):
         synth.uniforms_u64(g, (n_steps + 1) * n_sess).reshape(n_steps + 1, n_sess)
 
 
-@pytest.mark.parametrize("use_graph", [1, 0])
-def test_batch_equals_single_sessions(use_graph):
+# (graph replay, score-pass variant: counter rows in flight x waves per SIMD)
+@pytest.mark.parametrize("use_graph,variant", [(1, 0), (0, 0), (1, 2), (0, 4)])
+def test_batch_equals_single_sessions(use_graph, variant):
     m = cgs()
     ids = SESSIONS
     _, spaces, models, sess_b = _build(m, ids)
     _, _, models_s, sess_s = _build(m, ids)
-    sched = m.cgs_batch_schedule(512, 256, use_graph, 0)
+    sched = m.cgs_batch_schedule(512, 256, use_graph, variant)
     batch = m.Batch(sess_b, models, sched)
     D, U = _inputs(len(ids), 6, 1)
     prof_b = [m.NO_PROFILE] * len(ids)
