@@ -85,11 +85,12 @@ def forward_bf16(params, X, round_activations: bool = True):
 #     rounding of at most one float32 ulp) errs by at most
 #     (K + 1) 2^-23 (sum |w x| + |b|), plus 2^-126 per product for a
 #     flushed subnormal;
-#   * GELU: max(z, 0) - |z| Phi(-|z|) with Phi(-x) taken as 2^p(min(x, 9)),
-#     p within TAIL_LOG2_ERR of log2 Phi(-x) on [0, 9] in its float32
-#     evaluation, and an exponential within one float32 ulp: the tail term
-#     errs by at most rho = 2^TAIL_LOG2_ERR - 1 + 2^-22 of itself for
-#     |z| <= 9 and by at most 2 (1 + rho) |z| Phi(-9) beyond; one final
+#   * GELU: max(z, 0) - |z| Phi(-|z|) with Phi(-x) taken as
+#     2^p(min(x, GELU_TAIL_MAX)), p within TAIL_LOG2_ERR of log2 Phi(-x) on
+#     [0, GELU_TAIL_MAX] in its float32 evaluation, and an exponential within
+#     one float32 ulp: the tail term errs by at most
+#     rho = 2^TAIL_LOG2_ERR - 1 + 2^-22 of itself for |z| <= GELU_TAIL_MAX
+#     and by at most 2 (1 + rho) |z| Phi(-GELU_TAIL_MAX) beyond; one final
 #     rounding (2^-24 |gelu(z)|); doubled for safety;
 #   * bf16 rounding of an activation: the device rounds its float32 GELU
 #     value, which lies within the two bounds above of the exact GELU of the
@@ -97,15 +98,16 @@ def forward_bf16(params, X, round_activations: bool = True):
 #     lies between the roundings of the interval's ends, and equals the
 #     oracle's whenever no rounding boundary falls inside the interval.
 TAIL_LOG2_ERR = 1.15e-4
+GELU_TAIL_MAX = 6.0
 _RHO = 2.0 ** TAIL_LOG2_ERR - 1.0 + 2.0 ** -22
-_PHI9 = 0.5 * math.erfc(9.0 / SQRT2)
+_PHI_CUT = 0.5 * math.erfc(GELU_TAIL_MAX / SQRT2)
 
 
 def gelu_error_bound(z):
     """Bound of |device GELU(z) - gelu(z)| for float32 evaluation (above)."""
     az = np.abs(z)
     tail = az * 0.5 * erfc(az / SQRT2)
-    t = np.where(az <= 9.0, _RHO * tail, 2.0 * (1.0 + _RHO) * az * _PHI9)
+    t = np.where(az <= GELU_TAIL_MAX, _RHO * tail, 2.0 * (1.0 + _RHO) * az * _PHI_CUT)
     return 2.0 * (t + 2.0 ** -24 * np.abs(gelu(z))) + 1e-30
 
 

@@ -39,7 +39,7 @@ __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// min(|z|, 9) and max(z, 0) for finite z, each one v_med3_f32: written as
+// min(|z|, 6) and max(z, 0) for finite z, each one v_med3_f32: written as
 // fminf / fmaxf they would first canonicalise z (an accumulator value the
 // compiler cannot prove canonical), one more instruction each.
 __device__ __forceinline__ float tail_arg(float az) {

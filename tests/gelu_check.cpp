@@ -1,12 +1,13 @@
 // Host check of the perceptron's GELU tail polynomial
 // (paper_2102_05297_amd/csrc/gelu.h) against a long double reference:
-//   1. |p(x) - log2 Phi(-x)| over every 16th float32 x in [0, 9] (and every
-//      float below 2^-10), p evaluated in float32 as the kernels do;
-//   2. the whole GELU, max(z, 0) - |z| 2^p(min(|z|, 9)), with the host's
+//   1. |p(x) - log2 Phi(-x)| over every 16th float32 x in [0, X] (and every
+//      float below 2^-10), X = kGeluTailMax, p evaluated in float32 as the
+//      kernels do;
+//   2. the whole GELU, max(z, 0) - |z| 2^p(min(|z|, X)), with the host's
 //      float32 exp2 (within one ulp, as the device's exponential), against
 //      z Phi(z) for every 64th float32 z in [-30, 30]: the error must stay
-//      within rho |z| Phi(-|z|) + 2^-24 |GELU(z)| (|z| <= 9) and
-//      2 (1 + rho) |z| Phi(-9) + 2^-24 |GELU(z)| (|z| > 9), where
+//      within rho |z| Phi(-|z|) + 2^-24 |GELU(z)| (|z| <= X) and
+//      2 (1 + rho) |z| Phi(-X) + 2^-24 |GELU(z)| (|z| > X), where
 //      rho = 2^delta - 1 + 2^-22 and delta is the bound of part 1.
 // Prints the largest errors; exits non-zero when a bound fails.
 #include <cmath>
@@ -53,7 +54,7 @@ int main() {
   for (double w : worst1) e1 = std::max(e1, w);
   // part 2: the whole GELU against its bound
   const double rho = std::exp2(delta) - 1.0 + 0x1p-22;
-  const long double phi9 = phi_neg(9.0L);
+  const long double phi_cut = phi_neg((long double)cgs::kGeluTailMax);
   std::vector<double> worst2(nt, 0.0);
   std::vector<long> bad(nt, 0);
   const uint32_t zmax = bits(30.0f);
@@ -70,7 +71,7 @@ int main() {
           const long double exact = (z > 0 ? (long double)z : 0.0L) - tail;
           const long double err = fabsl((long double)g - exact);
           const long double bound =
-              (az <= cgs::kGeluTailMax ? rho * tail : 2.0L * (1.0L + rho) * az * phi9) +
+              (az <= cgs::kGeluTailMax ? rho * tail : 2.0L * (1.0L + rho) * az * phi_cut) +
               0x1p-24L * fabsl(exact) + 1e-45L;
           if (err > bound) ++bad[t];
           const double rel = (double)(err / bound);

@@ -1,6 +1,6 @@
 """Host check of the perceptron kernels' GELU (paper_2102_05297_amd/csrc/gelu.h,
 tests/gelu_check.cpp): its tail polynomial stays within the oracle's
-TAIL_LOG2_ERR of log2 Phi(-x) on [0, 9] in float32 evaluation, and the whole
+TAIL_LOG2_ERR of log2 Phi(-x) on [0, 6] in float32 evaluation, and the whole
 GELU within the oracle's per-value bound, against a long double
 reference."""
 import os

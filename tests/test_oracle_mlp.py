@@ -111,7 +111,8 @@ def test_bf16_forward_reduces_to_plain_forward():
 # A float32 model of the device's arithmetic, written from its published
 # description (not from the kernels): products of bf16 values summed in
 # float32 in a random order, the bias added in float32, GELU as max(z, 0)
-# minus |z| 2^p with p anywhere within the tail bound of log2 Phi(-min(|z|, 9))
+# minus |z| 2^p with p anywhere within the tail bound of
+# log2 Phi(-min(|z|, GELU_TAIL_MAX))
 # (the kernels' fitted polynomial stays within it), the exponential
 # perturbed by up to 2 ulps, the subtraction rounded once (a fused
 # multiply-add), then rounded to bf16.
@@ -127,7 +128,7 @@ def _ulps(g, v, k=2):
 def _gelu_f32(g, z):
     z = np.asarray(z, np.float32)
     az = np.abs(z).astype(np.float64)
-    lp = np.log2(0.5 * erfc(np.minimum(az, 9.0) / np.sqrt(2.0)))
+    lp = np.log2(0.5 * erfc(np.minimum(az, M.GELU_TAIL_MAX) / np.sqrt(2.0)))
     p = (lp + g.uniform(-1.0, 1.0, np.shape(z)) * M.TAIL_LOG2_ERR).astype(np.float32)
     e = _ulps(g, np.exp2(p.astype(np.float64)).astype(np.float32)).astype(np.float64)
     return (np.maximum(z, np.float32(0)).astype(np.float64) - az * e).astype(np.float32)
