@@ -615,7 +615,8 @@ cgs_status cgs_batch_step_time(cgs_batch batch, float *ms);
  * runs after a warm-up; score records with every counter active; no draw,
  * the explored sets are untouched; the sessions' last-step results become
  * unavailable until their next step): every score-pass variant at grid
- * sizes 128..8192, then the weight-pass grid, then graph replay against
+ * sizes 128..8192 below the number of tiles and at one workgroup per tile,
+ * then the weight-pass grid over blocks likewise, then graph replay against
  * plain launches of the step.  cache_path (may be NULL): a text file of
  * "<shape key> -> score_grid weight_grid use_graph variant" lines, read
  * first and appended to. */

@@ -2958,13 +2958,21 @@ extern "C" cgs_status cgs_batch_autotune(cgs_batch b, const char *cache_path,
     med = t[3];
     return hipSuccess;
   };
+  // grid sizes: powers of two up to the work items, and one workgroup per
+  // item (no striding)
   const int cand[] = {128, 256, 512, 1024, 2048, 4096, 8192};
+  auto grids = [&](uint32_t items) {
+    std::vector<int> gs;
+    for (int g : cand)
+      if ((uint32_t)g < items || g == cand[0]) gs.push_back(g);
+    if (items > (uint32_t)cand[0]) gs.push_back((int)std::min<uint32_t>(items, 1u << 20));
+    return gs;
+  };
   cgs_batch_schedule best = default_schedule(b);
   float best_s = 1e30f, best_w = 1e30f;
   // score pass: every variant at every grid size
   for (int v = 0; v < kBatchScoreVariants; ++v) {
-    for (int g : cand) {
-      if ((uint32_t)g > std::max<uint32_t>(b->total_tiles, 1) && g != cand[0]) break;
+    for (int g : grids(b->total_tiles)) {
       float t = 0.0f;
       HIP_TRY(time_runs(
           [&] {
@@ -2979,8 +2987,7 @@ extern "C" cgs_status cgs_batch_autotune(cgs_batch b, const char *cache_path,
       }
     }
   }
-  for (int g : cand) {
-    if ((uint32_t)g > std::max<uint32_t>(b->total_blocks, 1) && g != cand[0]) break;
+  for (int g : grids(b->total_blocks)) {
     float t = 0.0f;
     HIP_TRY(time_runs(
         [&] {
