@@ -695,7 +695,39 @@ __global__ __launch_bounds__(train_waves<H>() * 64) void mlp_train_rows(TrainRow
 // Gradient g of master parameter p: stored (gradient mode), or one Adam step
 // (Kingma & Ba, Algorithm 1; c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t))
 // followed by the bf16 copies of the new value.
-__device__ __forceinline__ void apply_grad(const GradTilesArgs &g, size_t p, float gv) {
+// The bf16 copies of weight (o, k) of layer `kind` (1: W1[o][k], k < F;
+// 2: W2[o][k]; 3: W3[o][k], o < C) in every layout pack_all writes, with the
+// row and column known: the same positions, no divisions.
+__device__ __forceinline__ void pack_weight(const MlpShape &sh, int kind, int o, int k, float v,
+                                            const MlpCopies &cp) {
+  const __bf16 b = (__bf16)v;
+  const int H = sh.H;
+  if (kind == 1) {
+    const int S1 = sh.K1 / 16;
+    const int lane = 32 * ((k & 15) >> 3) + (o & 31);
+    cp.w1p[(((size_t)(o >> 5) * S1 + (k >> 4)) * 64 + lane) * 8 + (k & 7)] = b;
+    cp.w1n[frag16_pos(o, k, 32)] = b;
+    return;
+  }
+  const int rem = k & 15;
+  const int lane = 32 * ((rem & 7) >> 2) + (o & 31), j = 4 * (rem >> 3) + (rem & 3);
+  const size_t pp =
+      (((size_t)(o >> 5) * (H / 16) + 2 * (k >> 5) + ((k & 31) >> 4)) * 64 + lane) * 8 + j;
+  if (kind == 2) {
+    cp.w2p[pp] = b;
+    cp.w2t[frag16_pos(k, o, H)] = b;
+    cp.w2n[frag16_pos(o, k, H)] = b;
+  } else {
+    cp.w3p[pp] = b;
+    cp.w3t[frag16_pos(k, o, 32 * (((size_t)sh.C + 31) / 32))] = b;
+    cp.w3n[frag16_pos(o, k, H)] = b;
+  }
+}
+
+// Adam on parameter p (or its gradient stored, in gradient mode); a weight
+// (kind 1..3 at row o, column k) also rewrites its bf16 copies.
+__device__ __forceinline__ void apply_grad(const GradTilesArgs &g, size_t p, float gv, int kind,
+                                           int o, int k) {
   if (g.grad) {
     g.grad[p] = gv;
     return;
@@ -706,7 +738,7 @@ __device__ __forceinline__ void apply_grad(const GradTilesArgs &g, size_t p, flo
   g.v[p] = vv;
   const float th = g.theta[p] - g.lr * (mm * g.c1) / (sqrtf(vv * g.c2) + g.eps);
   g.theta[p] = th;
-  pack_all(g.sh, p, th, g.cp);
+  if (kind) pack_weight(g.sh, kind, o, k, th, g.cp);
 }
 
 __global__ __launch_bounds__(kGradThreads) void mlp_grad_tiles(GradTilesArgs g) {
@@ -736,7 +768,7 @@ __global__ __launch_bounds__(kGradThreads) void mlp_grad_tiles(GradTilesArgs g) 
       float s = 0.0f;
 #pragma unroll 8
       for (int b = 0; b < nblk; ++b) s += src[(size_t)b * ld + col];
-      apply_grad(g, p, s);
+      apply_grad(g, p, s, 0, 0, 0); // biases have no bf16 copies
     }
     if (first == 0 && tid == 0 && g.loss_out) {
       float t = 0.0f;
@@ -783,9 +815,9 @@ __global__ __launch_bounds__(kGradThreads) void mlp_grad_tiles(GradTilesArgs g) 
 #pragma unroll
     for (int q = 1; q < NW; ++q) gv += part[q][i][lane];
     const int row = r0 + 8 * w + 4 * hh + e, col = c0 + c;
-    if (kind == 2) apply_grad(g, off_w2 + (size_t)row * H + col, gv);
-    else if (kind == 1 && col < F) apply_grad(g, (size_t)row * F + col, gv);
-    else if (kind == 3 && row < C) apply_grad(g, off_w3 + (size_t)row * H + col, gv);
+    if (kind == 2) apply_grad(g, off_w2 + (size_t)row * H + col, gv, 2, row, col);
+    else if (kind == 1 && col < F) apply_grad(g, (size_t)row * F + col, gv, 1, row, col);
+    else if (kind == 3 && row < C) apply_grad(g, off_w3 + (size_t)row * H + col, gv, 3, row, col);
   }
 }
 
