@@ -369,22 +369,22 @@ __global__ __launch_bounds__(kEvalThreads) void poly_eval(const PolyDev *__restr
   for (uint32_t e = t; e < CGS_MAX_PARAMS * CGS_MAX_RADIX; e += kEvalThreads) xv[e] = pd->xv32[e];
   for (uint32_t e = t; e < T; e += kEvalThreads) terms[e] = pd->terms[e];
   __syncthreads();
-  for (uint32_t l = part * kEvalThreads + t; l < nv; l += per_group * kEvalThreads) {
-    uint64_t lo, hi;
-    decode_packed(idx[l], sp, lo, hi);
-    const uint32_t s = subspace_of(pd, lo, hi);
-    if (s < g0 || s >= g1) continue;
+  // product of the features of term d for the configuration with digits lo, hi
+  auto feature = [&](uint32_t d, uint64_t lo, uint64_t hi) {
+    float f = 1.0f;
+    for (uint32_t q = 0; q < term_count(d); ++q) {
+      const uint32_t j = term_var(d, q);
+      f *= xv[j * CGS_MAX_RADIX + digit_of(lo, hi, j)];
+    }
+    return f;
+  };
+  auto one = [&](uint32_t l, uint64_t lo, uint64_t hi, uint32_t s) {
     const float *bs = lds + (uint64_t)(s - g0) * T * CB;
     float acc[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
     for (uint32_t k = 0; k < T; ++k) {
-      const uint32_t d = terms[k];
-      float f = 1.0f;
-      for (uint32_t q = 0; q < term_count(d); ++q) {
-        const uint32_t j = term_var(d, q);
-        f *= xv[j * CGS_MAX_RADIX + digit_of(lo, hi, j)];
-      }
+      const float f = feature(terms[k], lo, hi);
       const float4 *bk = reinterpret_cast<const float4 *>(bs + k * CB);
 #pragma unroll
       for (int c4 = 0; c4 < CB / 4; ++c4) {
@@ -398,6 +398,61 @@ __global__ __launch_bounds__(kEvalThreads) void poly_eval(const PolyDev *__restr
 #pragma unroll
     for (int c = 0; c < CB; ++c)
       if ((uint32_t)c < C) P[(uint64_t)c * stride + l] = fmaxf(acc[c], 0.0f); // counters >= 0
+  };
+  if constexpr (CB > 32) { // two accumulator sets would not fit in registers
+    for (uint32_t l = part * kEvalThreads + t; l < nv; l += per_group * kEvalThreads) {
+      uint64_t lo, hi;
+      decode_packed(idx[l], sp, lo, hi);
+      const uint32_t s = subspace_of(pd, lo, hi);
+      if (s >= g0 && s < g1) one(l, lo, hi, s);
+    }
+    return;
+  }
+  // two consecutive configurations per thread: when they share a subspace
+  // (consecutive ones mostly do) each coefficient read from LDS serves both
+  for (uint32_t l0 = 2 * (part * kEvalThreads + t); l0 < nv;
+       l0 += 2 * per_group * kEvalThreads) {
+    const uint32_t l1 = l0 + 1;
+    uint64_t lo0, hi0, lo1 = 0, hi1 = 0;
+    decode_packed(idx[l0], sp, lo0, hi0);
+    const uint32_t s0 = subspace_of(pd, lo0, hi0);
+    uint32_t s1 = ~0u;
+    if (l1 < nv) {
+      decode_packed(idx[l1], sp, lo1, hi1);
+      s1 = subspace_of(pd, lo1, hi1);
+    }
+    const bool in0 = s0 >= g0 && s0 < g1, in1 = s1 >= g0 && s1 < g1;
+    if (in0 && in1 && s0 == s1) {
+      const float *bs = lds + (uint64_t)(s0 - g0) * T * CB;
+      float a0[CB], a1[CB];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) a0[c] = a1[c] = 0.0f;
+      for (uint32_t k = 0; k < T; ++k) {
+        const uint32_t d = terms[k];
+        const float f0 = feature(d, lo0, hi0), f1 = feature(d, lo1, hi1);
+        const float4 *bk = reinterpret_cast<const float4 *>(bs + k * CB);
+#pragma unroll
+        for (int c4 = 0; c4 < CB / 4; ++c4) {
+          const float4 b = bk[c4];
+          a0[4 * c4] += f0 * b.x;
+          a0[4 * c4 + 1] += f0 * b.y;
+          a0[4 * c4 + 2] += f0 * b.z;
+          a0[4 * c4 + 3] += f0 * b.w;
+          a1[4 * c4] += f1 * b.x;
+          a1[4 * c4 + 1] += f1 * b.y;
+          a1[4 * c4 + 2] += f1 * b.z;
+          a1[4 * c4 + 3] += f1 * b.w;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+        if ((uint32_t)c < C)
+          *reinterpret_cast<float2 *>(P + (uint64_t)c * stride + l0) =
+              make_float2(fmaxf(a0[c], 0.0f), fmaxf(a1[c], 0.0f)); // counters >= 0
+    } else {
+      if (in0) one(l0, lo0, hi0, s0);
+      if (in1) one(l1, lo1, hi1, s1);
+    }
   }
 }
 
