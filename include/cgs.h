@@ -318,7 +318,11 @@ cgs_status cgs_model_load_predictions(cgs_space space, int n_counters, const flo
  *   *n_tests, *tests_to_well    tests made; position (1-based) of the first
  *                               well-performing test, 0 if none
  * The model must predict the 24 counters; the session should be fresh.
- * CGS_ERANGE when the random numbers run out. */
+ * CGS_ERANGE when the random numbers run out.  An iteration's draws (up to
+ * 33) are made in one go, since they depend only on the step's weights and
+ * the random numbers: the tests are those of drawing one at a time, but
+ * draws after the test that ends the run are made too, so the session's
+ * explored set may then hold up to draws - 1 configurations more. */
 typedef struct {
   int32_t draws;          /* runs without counters per profiled run (n), 5 by default */
   int32_t stop_at_well;   /* 1: stop at the first well-performing test */

@@ -1066,6 +1066,60 @@ extern "C" void cgs_default_tuning_opts(cgs_tuning_opts *out) {
   out->well_factor = 1.1;
 }
 
+namespace {
+
+hipError_t launch_pending(cgs_session s, bool do_draw, uint64_t u64);
+cgs_status wait_draw(cgs_session s, const DrawResult *res, uint64_t seq);
+
+// The next n draws of a full step (1 <= n <= kMaxDrawSeries + 1) with
+// uniforms u64[0..n): the first as cgs_sample_next makes it (launching a
+// recorded step), the others in one draw_many launch, all enqueued before
+// the host waits; each removes its pick before the next, so the picks are
+// those of n cgs_sample_next calls.  valid[0..*made) receives the picks;
+// *made < n when a draw found nothing to draw (Q == 0; the later ones find
+// nothing either).
+cgs_status draw_series(cgs_session s, int n, const uint64_t *u64, uint64_t *valid, int *made) {
+  cgs_space sp = s->space;
+  *made = 0;
+  if (s->pending) {
+    HIP_TRY(launch_pending(s, true, u64[0]));
+  } else {
+    HIP_TRY(launch_draw(s->d_s, s->d_explored, (uint32_t)sp->n_valid, kNoProfile, false,
+                        s->d_acc + s->cur_acc * kAccSlots, s->params.gamma, s->params.w_min,
+                        s->block_log2, s->d_bsum, s->n_blocks, u64[0], sp->d_idx, s->d_res,
+                        ++s->seq, sp->stream));
+  }
+  const uint64_t seq_first = s->seq;
+  if (n > 1) {
+    DrawSeries ser{};
+    ser.n = n - 1;
+    for (int i = 1; i < n; ++i) ser.u64[i - 1] = u64[i];
+    HIP_TRY(launch_draw_many(s->d_s, s->d_explored, (uint32_t)sp->n_valid,
+                             s->d_acc + s->cur_acc * kAccSlots, s->params.gamma, s->params.w_min,
+                             s->block_log2, s->d_bsum, s->n_blocks, ser, sp->d_idx, s->d_ring,
+                             seq_first + 1, sp->stream));
+    s->seq += (uint64_t)(n - 1);
+  }
+  for (int i = 0; i < n; ++i) {
+    const DrawResult *slot = i == 0 ? s->h_res : s->h_ring + (i - 1);
+    const cgs_status ws = wait_draw(s, slot, seq_first + (uint64_t)i);
+    if (ws != CGS_OK) return ws;
+    DrawResult r;
+    std::memcpy(&r, const_cast<const DrawResult *>(static_cast<volatile const DrawResult *>(slot)),
+                sizeof r);
+    s->last_total = r.total;
+    if (r.total == 0) return CGS_OK;
+    if (r.valid == kNoPick)
+      return fail(CGS_EDEVICE, "draw found no configuration although Q = %llu",
+                  (unsigned long long)r.total);
+    valid[i] = r.valid;
+    *made = i + 1;
+  }
+  return CGS_OK;
+}
+
+} // namespace
+
 extern "C" cgs_status cgs_tuning_run(cgs_session s, cgs_model m, const float *runtime,
                                      const double *counters, const cgs_expert_params *expert,
                                      const uint64_t *uniforms, uint64_t n_uniforms,
@@ -1113,23 +1167,42 @@ extern "C" cgs_status cgs_tuning_run(cgs_session s, cgs_model m, const float *ru
     if (st != CGS_OK) break;
     float best = INFINITY;
     bool next = false, stop = false;
-    for (int k = 0; k < opts->draws; ++k) {
-      uint64_t l = 0;
-      st = draw(&l);
-      if (st == CGS_EEMPTY) {
-        st = CGS_OK;
-        break;
-      }
-      if (st != CGS_OK) break;
-      if (test(l, false)) {
-        stop = true;
-        break;
-      }
+    auto consider = [&](uint64_t l) {
+      if (test(l, false)) return stop = true;
       if (runtime[l] <= best) {
         best = runtime[l];
         c = l;
         next = true;
       }
+      return false;
+    };
+    if (opts->draws <= kMaxDrawSeries + 1 && !s->pending_nb && (s->pending || !s->last_nb)) {
+      // the step's draws in one go: they depend on its weights and the
+      // uniforms only, the tests decide where the run stops
+      const int want = (int)std::min<uint64_t>((uint64_t)opts->draws, n_uniforms - u);
+      uint64_t picks[kMaxDrawSeries + 1];
+      int made = 0;
+      if (want > 0) st = draw_series(s, want, uniforms + u, picks, &made);
+      u += (uint64_t)std::max(want, 0);
+      if (st != CGS_OK) break;
+      for (int k = 0; k < made && !stop; ++k) consider(picks[k]);
+      if (!stop && made == want && want < opts->draws) {
+        st = fail(CGS_ERANGE, "the run needs more than %llu random numbers",
+                  (unsigned long long)n_uniforms);
+        break;
+      }
+    } else {
+      for (int k = 0; k < opts->draws; ++k) {
+        uint64_t l = 0;
+        st = draw(&l);
+        if (st == CGS_EEMPTY) {
+          st = CGS_OK;
+          break;
+        }
+        if (st != CGS_OK) break;
+        if (consider(l)) break;
+      }
+      if (st != CGS_OK) break;
     }
     if (stop || !next) break;
   }

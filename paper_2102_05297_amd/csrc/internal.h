@@ -190,6 +190,18 @@ hipError_t launch_weight_pass(const float *d_s, const uint32_t *d_explored, uint
                               const uint32_t *d_prof = nullptr);
 // The draw stores its result, then `seq` with a system-scope release; with
 // d_prof_out also the pick's valid index (kNoProfile without a pick).
+// Up to kMaxDrawSeries further draws of one step in one launch (draw_many).
+constexpr int kMaxDrawSeries = 32;
+struct DrawSeries {
+  int32_t n;
+  int32_t pad;
+  uint64_t u64[kMaxDrawSeries];
+};
+hipError_t launch_draw_many(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
+                            const StepAcc *d_acc, float gamma, float w_min, int block_log2,
+                            uint64_t *d_bsum, uint32_t n_blocks, const DrawSeries &series,
+                            const uint32_t *d_idx, DrawResult *d_res, uint64_t seq0,
+                            hipStream_t stream);
 hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid, uint32_t profile,
                        bool mark_profile, const StepAcc *d_acc, float gamma, float w_min,
                        int block_log2, uint64_t *d_bsum, uint32_t n_blocks, uint64_t u64,

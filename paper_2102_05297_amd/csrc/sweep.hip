@@ -532,6 +532,23 @@ __global__ __launch_bounds__(kDrawThreads) void draw_scores(
     atomicOr(&explored[profile >> 5], 1u << (profile & 31u));
 }
 
+// Further draws of one step (after its first), made one after another by
+// one workgroup, each removing its pick before the next exactly as separate
+// launches of draw_scores would: draw i uses u64[i] and publishes into
+// res[i] under sequence number seq0 + i.
+__global__ __launch_bounds__(kDrawThreads) void draw_many(
+    const float *__restrict__ s, uint32_t *__restrict__ explored, uint32_t n_valid,
+    const StepAcc *__restrict__ acc, float gamma, float w_min, int block_log2,
+    uint64_t *__restrict__ bsum, uint32_t n_blocks, DrawSeries series,
+    const uint32_t *__restrict__ idx, DrawResult *__restrict__ res, uint64_t seq0) {
+  for (int i = 0; i < series.n; ++i) {
+    ScoreWeights w{s, explored, n_valid, kNoProfile, acc, gamma, w_min};
+    draw_body<kDrawThreads>(w, block_log2, bsum, n_blocks, series.u64[i], idx, res + i,
+                            seq0 + (uint64_t)i);
+    __syncthreads(); // the pick's removal is seen by the next draw
+  }
+}
+
 // ------------------------------------------------------------ batched
 // Score tiles of every session, grid-stride over the concatenated tile list;
 // a workgroup flushes its accumulators whenever the session changes.
@@ -841,6 +858,18 @@ hipError_t launch_draw(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
   hipLaunchKernelGGL(draw_scores, dim3(1), dim3(kDrawThreads), 0, stream, d_s, d_explored, n_valid,
                      profile, d_prof, mark_profile ? 1 : 0, d_acc, gamma, w_min, block_log2,
                      d_bsum, n_blocks, u64, d_idx, d_res, seq, d_prof_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_draw_many(const float *d_s, uint32_t *d_explored, uint32_t n_valid,
+                            const StepAcc *d_acc, float gamma, float w_min, int block_log2,
+                            uint64_t *d_bsum, uint32_t n_blocks, const DrawSeries &series,
+                            const uint32_t *d_idx, DrawResult *d_res, uint64_t seq0,
+                            hipStream_t stream) {
+  if (series.n < 1 || series.n > kMaxDrawSeries) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(draw_many, dim3(1), dim3(kDrawThreads), 0, stream, d_s, d_explored, n_valid,
+                     d_acc, gamma, w_min, block_log2, d_bsum, n_blocks, series, d_idx, d_res,
+                     seq0);
   return hipGetLastError();
 }
 
