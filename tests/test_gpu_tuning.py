@@ -54,7 +54,9 @@ def test_c1_runs_equal_the_oracle(seed):
     assert ref.tests_to_well > 0
 
 
-@pytest.mark.parametrize("seed,draws", [(0, 5), (1, 3), (2, 1)])
+# an iteration's draws go out together (up to 33: the first with the step,
+# the rest in one launch); 40 takes the one-at-a-time path
+@pytest.mark.parametrize("seed,draws", [(0, 5), (1, 3), (2, 1), (3, 33), (4, 40)])
 def test_small_space_runs_to_exhaustion(seed, draws):
     radix = [3, 4, 2, 5, 3]
     values = [[1, 2, 4], [1, 2, 4, 8], [0, 1], [1, 2, 4, 8, 16], [1, 2, 4]]
